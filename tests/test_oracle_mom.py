@@ -1,0 +1,154 @@
+"""Oracle pins for the dense Galerkin operators and solves (Sec. III-A to III-C):
+symmetry (reciprocity), Mie series, null field, Schur vs block solve, optical
+theorem and power balance."""
+import numpy as np
+import pytest
+
+from workloads import icosphere
+from oracle.rwg import RWGMesh
+from oracle import physics as ph, mie, mom
+from oracle.solve import DenseProblem
+from oracle.farfield import rcs, directions, far_field
+
+F_SPHERE = 150e6
+
+
+def _problem(cache, level, eps_r, sigma):
+    key = ("sphere", level, eps_r, sigma)
+    if key not in cache:
+        m = RWGMesh([icosphere(level)])
+        cache[key] = DenseProblem(m, F_SPHERE, [(eps_r, 1.0, sigma)])
+    return cache[key]
+
+
+def _solve(dp):
+    e = dp.rhs((0.0, 0.0, 1.0), (1.0, 0.0, 0.0))
+    return dp.solve_block(e)
+
+
+def _rcs_error(dp, u, v, eps_t_rel):
+    th = np.linspace(0.02, np.pi - 0.02, 41)
+    err2 = ref2 = 0.0
+    for phi in (0.0, np.pi / 2):
+        r = rcs(dp.mesh, dp.k0, dp.eta0, u, v, directions(th, phi + 0 * th))
+        mr = mie.bistatic_rcs(dp.k0, 1.0, eps_t_rel, th, phi + 0 * th)
+        err2 += np.sum((r - mr) ** 2); ref2 += np.sum(mr ** 2)
+    return np.sqrt(err2 / ref2)
+
+
+def test_operator_symmetry(dense_cache):
+    """L^T = L, K^T = K, X^T = -X (reciprocity of G, Sec. IV eq. Grecip)."""
+    dp = _problem(dense_cache, 2, 4.0, 0.0)
+    # tolerances at the quadrature convergence level of the oracle (~1e-6 L, ~1e-5 K)
+    for M, tol in ((dp.L0, 1e-6), (dp.Li, 1e-6), (dp.K0, 2e-5), (dp.Ki, 2e-5)):
+        assert np.abs(M - M.T).max() <= tol * np.abs(M).max()
+    assert np.abs(dp.X + dp.X.T).max() <= 1e-14 * np.abs(dp.X).max()
+
+
+def test_coplanar_self_blocks_of_K_vanish():
+    m = RWGMesh([icosphere(1)])
+    T = len(m.tri)
+    _, _, K = mom.pair_blocks(m, 1.0 - 0.2j, np.arange(T), np.arange(T))
+    assert np.abs(K).max() < 1e-15
+
+
+def test_low_frequency_limit():
+    """For k -> 0, G = 1/(4 pi R) - j k/(4 pi) + O(k^2 R), so
+    Im A_mn -> -(k/4 pi) (int f_m).(int f_n) with the closed form
+    int_{T+-} f_n = +-(l/2)(centroid - free vertex), and Im Phi_mn -> 0
+    (int div f_n = 0)."""
+    m = RWGMesh([icosphere(1)])
+    k = 1e-4
+    A, P, _ = mom.dense_operators(m, k)
+    F = (0.5 * m.length[:, None] * (m.centroid[m.tp] - m.verts[m.tp, m.ep])
+         - 0.5 * m.length[:, None] * (m.centroid[m.tm] - m.verts[m.tm, m.em]))
+    ref = -(k / (4 * np.pi)) * F @ F.T
+    assert np.abs(A.imag - ref).max() < 1e-6 * np.abs(ref).max()
+    assert np.abs(P.imag).max() < 1e-6 * np.abs(P.real).max() * k
+
+
+def test_quadrature_converged(dense_cache):
+    m = RWGMesh([icosphere(1)])
+    k = 3.0 - 0.5j
+    A, P, K = mom.dense_operators(m, k)
+    A2, P2, K2 = mom.dense_operators(m, k, rules=dict(touch_out=14, touch_in=10, close_out=10,
+                                                      close_in=10, far_out=7, far_in=7))
+    # coarse mesh (|k| h ~ 2): self terms limit convergence to ~1e-5
+    assert np.abs(A - A2).max() < 2e-5 * np.abs(A2).max()
+    assert np.abs(P - P2).max() < 3e-5 * np.abs(P2).max()
+    assert np.abs(K - K2).max() < 1e-4 * np.abs(K2).max()
+
+
+def test_mie_dielectric_converges(dense_cache):
+    """Bistatic RCS of the eps_r = 4 sphere (k0 a = 3.14) against the Mie
+    series: error falls with refinement, < 10 % at 320 triangles."""
+    errs = []
+    for lvl in (1, 2):
+        dp = _problem(dense_cache, lvl, 4.0, 0.0)
+        u, v = _solve(dp)
+        errs.append(_rcs_error(dp, u, v, 4.0))
+    assert errs[1] < 0.6 * errs[0]
+    assert errs[1] < 0.10
+
+
+def test_mie_lossy_sphere(dense_cache):
+    sigma = 0.02
+    dp = _problem(dense_cache, 2, 4.0, sigma)
+    u, v = _solve(dp)
+    et = ph.eps_tilde(F_SPHERE, 4.0, sigma) / ph.EPS0
+    assert _rcs_error(dp, u, v, et) < 0.10
+
+
+def test_mie_cfg_sphere_1280(dense_cache):
+    """The 1,280-triangle sphere at 150 MHz, eps_r = 4: RCS within 3 % of Mie."""
+    dp = _problem(dense_cache, 3, 4.0, 0.0)
+    u, v = _solve(dp)
+    assert _rcs_error(dp, u, v, 4.0) < 0.03
+
+
+def test_schur_equals_block(dense_cache):
+    dp = _problem(dense_cache, 2, 4.0, 0.02)
+    e = dp.rhs((0.0, 0.0, 1.0), (1.0, 0.0, 0.0))
+    u, v = dp.solve_block(e)
+    u2, v2 = dp.solve_gibc(e)
+    assert np.abs(u - u2).max() < 1e-10 * np.abs(u).max()
+    assert np.abs(v - v2).max() < 1e-10 * np.abs(v).max()
+
+
+def test_null_field(dense_cache):
+    """eps_r = 1, sigma = 0: the object is background, nothing scatters."""
+    dp = _problem(dense_cache, 2, 1.0, 0.0)
+    u, v = _solve(dp)
+    th = np.linspace(0.02, np.pi - 0.02, 19)
+    F = far_field(dp.mesh, dp.k0, dp.eta0, u, v, directions(th, 0 * th))
+    dp4 = _problem(dense_cache, 2, 4.0, 0.0)
+    u4, v4 = _solve(dp4)
+    F4 = far_field(dp4.mesh, dp4.k0, dp4.eta0, u4, v4, directions(th, 0 * th))
+    assert np.abs(F).max() < 3e-3 * np.abs(F4).max()
+
+
+def _cross_sections(dp, u, v):
+    th = np.linspace(0.0, np.pi, 121)
+    phis = np.linspace(0.0, 2 * np.pi, 24, endpoint=False)
+    tot = 0.0
+    for phi in phis:
+        r = rcs(dp.mesh, dp.k0, dp.eta0, u, v, directions(th, phi + 0 * th))
+        tot += np.trapezoid(r * np.sin(th), th)
+    csca = tot * (2 * np.pi / len(phis)) / (4 * np.pi)
+    Ff = far_field(dp.mesh, dp.k0, dp.eta0, u, v, np.array([[0.0, 0.0, 1.0]]))[0]
+    # forward-scattering theorem for exp(+j w t): C_ext = -(4 pi/k0) Im(e* . F(khat))
+    cext = -(4 * np.pi / dp.k0.real) * np.imag(Ff[0])
+    return cext, csca
+
+
+def test_power_balance(dense_cache):
+    """Optical theorem: C_ext = C_sca for a lossless sphere; C_ext > C_sca
+    (absorption) for a lossy one, both close to Mie."""
+    dp = _problem(dense_cache, 2, 4.0, 0.0)
+    ce, cs = _cross_sections(dp, *_solve(dp))
+    assert abs(ce - cs) < 0.02 * cs
+    dpl = _problem(dense_cache, 2, 4.0, 0.02)
+    ce2, cs2 = _cross_sections(dpl, *_solve(dpl))
+    me, ms = mie.cross_sections(dpl.k0, 1.0, ph.eps_tilde(F_SPHERE, 4.0, 0.02) / ph.EPS0)
+    assert ce2 - cs2 > 0.1 * (me - ms)
+    assert abs((ce2 - cs2) - (me - ms)) < 0.1 * (me - ms)
