@@ -1,0 +1,201 @@
+/* sie.h - C ABI of the MI355X (gfx950) implementation of the AIM-accelerated
+ * GIBC surface-integral-equation method of Sharma & Triverio, "An Accelerated
+ * Surface Integral Equation Method for the Electromagnetic Modeling of
+ * Dielectric and Lossy Objects of Arbitrary Conductivity" (arXiv:2003.11679).
+ *
+ * Conventions (all entry points)
+ *   - Time dependence e^{+j omega t}; SI units.
+ *   - Complex numbers are interleaved (re, im) pairs: sie_c128 on the host,
+ *     complex64 (float re, im) or complex128 (double re, im) on the device.
+ *   - Meshes: closed, oriented triangle surfaces; triangles counter-clockwise
+ *     seen from outside (right-hand normal = outward normal n_i, Sec. II).
+ *     0-based vertex indices.  A mesh that is not a closed consistently
+ *     oriented 2-manifold is rejected with SIE_EMESH.
+ *   - Unknowns: RWG coefficients (Sec. III-A) of u = n_i x H and v = n_i x E
+ *     on each object.  RWG n is the interior edge {a, b}, a < b, in
+ *     concatenated vertex numbering, sorted by (a, b); T+ is the triangle whose
+ *     counter-clockwise order runs a -> b.  Objects are numbered in the order
+ *     they are added and their RWG functions are contiguous in that order.
+ *   - Media: medium -1 is the background (exterior problem, wavenumber k0);
+ *     medium i >= 0 is the interior of object i (wavenumber k_i, eq. kin).
+ *   - Ownership: host arrays passed in are read during the call and copied;
+ *     host arrays passed out are written by the call and owned by the caller.
+ *     Device pointers (hot-path calls) belong to the caller; the library never
+ *     frees them and never synchronises the stream it is given except where
+ *     stated.  Handles belong to the caller, who destroys them.
+ *   - Errors: every call returns an sie_status; on failure nothing is thrown
+ *     across the ABI, outputs are left unspecified and sie_last_error() holds a
+ *     message (thread-local, valid until the next call on that thread).
+ *   - Threads: one sie_problem is used by one host thread at a time.
+ */
+#ifndef SIE_H
+#define SIE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sie_ctx sie_ctx;
+typedef struct sie_problem sie_problem;
+
+typedef struct { double re, im; } sie_c128;
+
+typedef enum {
+    SIE_OK = 0,
+    SIE_EINVAL = -1,     /* bad argument */
+    SIE_ENOMEM = -2,     /* device or host allocation failed */
+    SIE_EMESH = -3,      /* mesh not closed / not oriented / degenerate */
+    SIE_EGRID = -4,      /* grid too small to hold the stencils */
+    SIE_ENOCONV = -5,    /* iterative solve hit its iteration cap; best iterate kept */
+    SIE_EDEVICE = -6,    /* HIP runtime error */
+    SIE_ESTATE = -7      /* call out of order (e.g. matvec before setup) */
+} sie_status;
+
+typedef enum {
+    SIE_FP64 = 0,        /* complex128 everywhere */
+    SIE_FP32 = 1         /* complex64 projection / FFT / interpolation / SpMV;
+                            solves refine in FP64 (Sec. V tolerances) */
+} sie_precision;
+
+/* Operators of one medium (Sec. III-A, eq. opL, opK; AIM form eq. AIM_Lin,
+ * AIM_Kin):  A_mn = <f_m, G f_n>,  PHI_mn = <div f_m, G div f_n>,
+ * L = A - k^-2 PHI,  K_mn = <f_m, PV grad G x f_n>.  X_mn = <n x f_m, f_n>
+ * (the identity operator written I-cross in Sec. III-A) is medium-free. */
+typedef enum {
+    SIE_OP_L = 0,
+    SIE_OP_K = 1,
+    SIE_OP_X = 2
+} sie_op;
+
+/* Quadrature orders (points per axis of the product rules) used for the
+ * near-region direct integrals (Sec. III-D-1: near entries by direct
+ * integration).  Pairs are classified as self / edge-adjacent /
+ * vertex-adjacent ("touch"), close (centroid distance < 2.5 x longest edge)
+ * and far; zeros select the defaults. */
+typedef struct {
+    int32_t touch_out, touch_in, close_out, close_in, far_out, far_in;
+} sie_quad_params;
+
+typedef struct {
+    double tol;          /* relative residual of the outer (GIBC) system, default 1e-6 */
+    double inner_tol;    /* nested solve (eq. nest2) tolerance, default 1e-8 (FP64) */
+    int32_t restart;     /* GMRES restart length, default 30 */
+    int32_t max_iter;    /* outer iteration cap, default 800 (Sec. V-A) */
+    int32_t inner_max_iter; /* nested iteration cap, default 800 */
+    int32_t max_refine;  /* FP64 refinement sweeps for SIE_FP32, default 10 */
+} sie_solver_opts;
+
+typedef struct {
+    int32_t outer_iters;     /* total outer GMRES iterations (all sweeps) */
+    int32_t inner_iters;     /* total nested GMRES iterations */
+    int32_t inner_iters_max; /* largest nested count in one outer iteration */
+    int32_t refine_sweeps;
+    int32_t matvecs;         /* operator applications in SIE-matvec units */
+    double residual;         /* final relative residual of the FP64 GIBC system */
+    double t_solve_s;
+} sie_report;
+
+/* ---- context --------------------------------------------------------- */
+
+/* Binds HIP device `device`.  Returns SIE_EDEVICE if it does not exist. */
+sie_status sie_ctx_create(int device, sie_ctx **out);
+void sie_ctx_destroy(sie_ctx *ctx);
+const char *sie_last_error(void);
+
+/* ---- problem definition (Sec. II: objects with (eps_i, mu_i, sigma_i) in a
+ * homogeneous background; Sec. III-A: triangle meshes) ------------------- */
+
+sie_status sie_problem_create(sie_ctx *ctx, double freq_hz, double bg_eps_r, double bg_mu_r,
+                              sie_problem **out);
+/* xyz: [nv][3] float64 metres; tri: [nt][3] int32.  eps_r, mu_r relative;
+ * sigma in S/m.  Writes the object index to *obj_id (may be NULL). */
+sie_status sie_problem_add_object(sie_problem *p, const double *xyz, int64_t nv,
+                                  const int32_t *tri, int64_t nt, double eps_r, double mu_r,
+                                  double sigma, int32_t *obj_id);
+/* Grid of medium `medium` (Sec. III-D-1: one Cartesian grid per object plus
+ * one global exterior grid, eq. AIM_Lin): n points per axis (isotropic
+ * spacing h = largest bounding-box extent / (n - 3)), Chebyshev near radius
+ * in cells (5 = a near region 11 points across).  With `share` != 0 an
+ * interior medium reuses the exterior grid (single-object problems).
+ * Defaults: exterior n from the lambda_r/20 rule of Sec. IV, capped at 256;
+ * interiors share the exterior grid when there is one object. */
+sie_status sie_problem_set_grid(sie_problem *p, int32_t medium, int32_t n, int32_t near_radius,
+                                int32_t share);
+sie_status sie_problem_set_quadrature(sie_problem *p, const sie_quad_params *q);
+/* Builds RWG topology, grids, stencils and projection moments, near lists,
+ * precorrected near-field matrices (FP64 direct integrals on the device) and
+ * Green's spectra for every medium.  Synchronous. */
+sie_status sie_problem_setup(sie_problem *p);
+void sie_problem_destroy(sie_problem *p);
+
+/* ---- queries --------------------------------------------------------- */
+
+int64_t sie_problem_num_rwg(const sie_problem *p);      /* all objects; -1 before setup */
+int64_t sie_problem_num_tri(const sie_problem *p);
+/* RWG records (host arrays): edge_v [E][2] (a < b), tpm [E][2] (T+, T-). */
+sie_status sie_get_rwg(const sie_problem *p, int32_t *edge_v, int32_t *tpm);
+/* Grid of a medium: origin [3], h, n [3] (full grid), lo [3] and nl [3]
+ * (live box of stencil nodes), m [3] (FFT lengths, powers of two >= 2 nl - 1). */
+sie_status sie_get_grid(const sie_problem *p, int32_t medium, double *origin, double *h,
+                        int32_t *n, int32_t *lo, int32_t *nl, int32_t *m);
+/* Stencil centre (integer grid index, 3 per triangle) of every triangle of the
+ * medium's grid, in the grid's triangle order (all triangles of the objects the
+ * grid covers, ascending).  out: [nt_grid][3]; *nt_grid receives the count. */
+sie_status sie_get_stencils(const sie_problem *p, int32_t medium, int32_t *out, int64_t *nt_grid);
+/* Near-field CSR of a medium (RWG rows/cols of the medium's objects, global
+ * numbering): row_ptr [E+1] int64, cols [nnz] int32.  With row_ptr == NULL
+ * only *nnz is written. */
+sie_status sie_get_near_pattern(const sie_problem *p, int32_t medium, int64_t *row_ptr,
+                                int32_t *cols, int64_t *nnz);
+/* Precorrected near-field values (L or K, eq. LinNRP/KinNRP) in FP64, in the
+ * CSR order of sie_get_near_pattern: out [nnz]. */
+sie_status sie_get_near_values(const sie_problem *p, int32_t medium, sie_op op, sie_c128 *out);
+/* Wavenumber of a medium (eq. kin, principal branch, Im k <= 0). */
+sie_status sie_get_wavenumber(const sie_problem *p, int32_t medium, sie_c128 *k);
+
+/* ---- hot path (device pointers, caller's stream, no host synchronisation) */
+
+/* y = Op_medium x for nrhs right-hand sides stored [nrhs][E] contiguous
+ * (E = sie_problem_num_rwg), complex64 for SIE_FP32 and complex128 for
+ * SIE_FP64.  Op = L or K: AIM product near + W G P (eq. AIM_Lin / AIM_Kin);
+ * rows and columns outside the medium's objects are zero.  Op = X: medium
+ * ignored. */
+sie_status sie_matvec(sie_problem *p, int32_t medium, sie_op op, sie_precision prec, int32_t nrhs,
+                      const void *x_dev, void *y_dev, void *stream);
+/* The four stages of one L-type product, exposed for stage-level checks:
+ * grid sources [4][nl_z][nl_y][nl_x] (J_x, J_y, J_z, charge; x fastest) from
+ * RWG coefficients (projection P, P_phi); the zero-padded FFT convolution of
+ * nfields such grids with G (kind 0) on the live box; interpolation W back to
+ * RWG (vector fields minus k^-2 times the scalar field). */
+sie_status sie_project(sie_problem *p, int32_t medium, sie_precision prec, const void *x_dev,
+                       void *grid_dev, void *stream);
+sie_status sie_convolve(sie_problem *p, int32_t medium, sie_precision prec, int32_t nfields,
+                        const void *grid_in_dev, void *grid_out_dev, void *stream);
+sie_status sie_interpolate(sie_problem *p, int32_t medium, sie_precision prec,
+                           const void *grid_dev, void *y_dev, void *stream);
+
+/* ---- solve (Sec. III-C: GIBC with AIM-accelerated nested interior solves,
+ * eq. GIBCsys, nest02, nest2) --------------------------------------------- */
+
+/* Plane waves (Sec. II): E_inc = e0 exp(-j k0 khat . r); khat [nrhs][3] unit,
+ * e0 [nrhs][3] complex (V/m). */
+sie_status sie_set_planewaves(sie_problem *p, int32_t nrhs, const double *khat, const sie_c128 *e0);
+/* Solves the GIBC system for every plane wave.  opts may be NULL (defaults);
+ * report may be NULL.  Synchronous.  SIE_ENOCONV: cap reached, best iterate
+ * kept and readable. */
+sie_status sie_solve(sie_problem *p, sie_precision prec, const sie_solver_opts *opts,
+                     sie_report *report);
+/* Currents of right-hand side `rhs` (host arrays [E]). */
+sie_status sie_get_currents(const sie_problem *p, int32_t rhs, sie_c128 *u, sie_c128 *v);
+/* Scattered far-field amplitude F (E_s ~ F exp(-j k0 r)/r) of right-hand side
+ * `rhs` in the directions rhat [ndir][3]: F [ndir][3] (host). */
+sie_status sie_far_field(const sie_problem *p, int32_t rhs, int64_t ndir, const double *rhat,
+                         sie_c128 *F);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SIE_H */

@@ -1,0 +1,255 @@
+// C ABI (include/sie.h): argument checking, error capture, dispatch.
+#include <cmath>
+#include <cstring>
+
+#include "problem.h"
+
+using namespace sie;
+
+static thread_local std::string g_err;
+
+static sie_status fail(sie_status s, const std::string &m) {
+    g_err = m;
+    return s;
+}
+
+template <typename F>
+static sie_status guard(F &&f) {
+    try {
+        g_err.clear();
+        f();
+        return SIE_OK;
+    } catch (const Error &e) {
+        return fail(e.code, e.what());
+    } catch (const std::bad_alloc &) {
+        return fail(SIE_ENOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(SIE_EINVAL, e.what());
+    }
+}
+
+extern "C" {
+
+const char *sie_last_error(void) { return g_err.c_str(); }
+
+sie_status sie_ctx_create(int device, sie_ctx **out) {
+    return guard([&] {
+        SIE_CHECK(out, SIE_EINVAL, "out is NULL");
+        int n = 0;
+        SIE_HIP(hipGetDeviceCount(&n));
+        SIE_CHECK(device >= 0 && device < n, SIE_EDEVICE, "no HIP device " + std::to_string(device));
+        SIE_HIP(hipSetDevice(device));
+        auto *c = new sie_ctx;
+        c->device = device;
+        *out = c;
+    });
+}
+
+void sie_ctx_destroy(sie_ctx *ctx) { delete ctx; }
+
+sie_status sie_problem_create(sie_ctx *ctx, double freq_hz, double bg_eps_r, double bg_mu_r, sie_problem **out) {
+    return guard([&] {
+        SIE_CHECK(ctx && out, SIE_EINVAL, "NULL argument");
+        SIE_CHECK(freq_hz > 0 && std::isfinite(freq_hz), SIE_EINVAL, "frequency must be positive");
+        SIE_CHECK(bg_eps_r > 0 && bg_mu_r > 0, SIE_EINVAL, "background must be lossless with positive eps, mu");
+        auto *p = new sie_problem;
+        p->ctx = ctx;
+        p->freq = freq_hz;
+        p->bg_eps_r = bg_eps_r;
+        p->bg_mu_r = bg_mu_r;
+        *out = p;
+    });
+}
+
+sie_status sie_problem_add_object(sie_problem *p, const double *xyz, int64_t nv, const int32_t *tri, int64_t nt,
+                                  double eps_r, double mu_r, double sigma, int32_t *obj_id) {
+    return guard([&] {
+        SIE_CHECK(p && xyz && tri, SIE_EINVAL, "NULL argument");
+        SIE_CHECK(!p->is_setup, SIE_ESTATE, "problem already set up");
+        SIE_CHECK(nv >= 4 && nt >= 4, SIE_EMESH, "a closed surface needs at least 4 vertices and 4 triangles");
+        SIE_CHECK(eps_r > 0 && mu_r > 0 && sigma >= 0, SIE_EINVAL, "material needs eps_r > 0, mu_r > 0, sigma >= 0");
+        for (int64_t i = 0; i < 3 * nv; ++i) SIE_CHECK(std::isfinite(xyz[i]), SIE_EMESH, "non-finite vertex");
+        ObjIn o;
+        o.xyz.assign(xyz, xyz + 3 * nv);
+        o.tri.assign(tri, tri + 3 * nt);
+        o.eps_r = eps_r; o.mu_r = mu_r; o.sigma = sigma;
+        p->objs.push_back(std::move(o));
+        p->obj_req.push_back(GridReq());
+        if (obj_id) *obj_id = (int32_t)p->objs.size() - 1;
+    });
+}
+
+sie_status sie_problem_set_grid(sie_problem *p, int32_t medium, int32_t n, int32_t near_radius, int32_t share) {
+    return guard([&] {
+        SIE_CHECK(p, SIE_EINVAL, "NULL problem");
+        SIE_CHECK(!p->is_setup, SIE_ESTATE, "problem already set up");
+        SIE_CHECK(n == 0 || (n >= 5 && n <= 1024), SIE_EINVAL, "grid points per axis must be 0 or in [5, 1024]");
+        SIE_CHECK(near_radius >= 1 && near_radius <= 12, SIE_EINVAL, "near radius must be in [1, 12]");
+        GridReq r;
+        r.n = n; r.R = near_radius; r.share = share ? 1 : 0;
+        if (medium == -1) { r.share = -1; p->ext_req = r; return; }
+        SIE_CHECK(medium >= 0 && medium < (int)p->objs.size(), SIE_EINVAL, "medium out of range");
+        p->obj_req[medium] = r;
+    });
+}
+
+sie_status sie_problem_set_quadrature(sie_problem *p, const sie_quad_params *q) {
+    return guard([&] {
+        SIE_CHECK(p && q, SIE_EINVAL, "NULL argument");
+        SIE_CHECK(!p->is_setup, SIE_ESTATE, "problem already set up");
+        p->quad = *q;
+    });
+}
+
+sie_status sie_problem_setup(sie_problem *p) {
+    return guard([&] {
+        SIE_CHECK(p, SIE_EINVAL, "NULL problem");
+        SIE_CHECK(!p->is_setup, SIE_ESTATE, "problem already set up");
+        problem_setup(p);
+    });
+}
+
+void sie_problem_destroy(sie_problem *p) {
+    if (!p) return;
+    if (p->solve) solver_destroy(p->solve);
+    delete p;
+}
+
+int64_t sie_problem_num_rwg(const sie_problem *p) { return p && p->is_setup ? p->mesh.nrwg : -1; }
+int64_t sie_problem_num_tri(const sie_problem *p) { return p && p->is_setup ? p->mesh.nt() : -1; }
+
+sie_status sie_get_rwg(const sie_problem *p, int32_t *edge_v, int32_t *tpm) {
+    return guard([&] {
+        SIE_CHECK(p && p->is_setup, SIE_ESTATE, "problem not set up");
+        if (edge_v) std::memcpy(edge_v, p->mesh.edge_v.data(), p->mesh.edge_v.size() * sizeof(int32_t));
+        if (tpm) std::memcpy(tpm, p->mesh.tpm.data(), p->mesh.tpm.size() * sizeof(int32_t));
+    });
+}
+
+sie_status sie_get_grid(const sie_problem *p, int32_t medium, double *origin, double *h, int32_t *n, int32_t *lo,
+                        int32_t *nl, int32_t *m) {
+    return guard([&] {
+        SIE_CHECK(p && p->is_setup, SIE_ESTATE, "problem not set up");
+        const Grid &g = *p->medium(medium).grid;
+        for (int c = 0; c < 3; ++c) {
+            if (origin) origin[c] = g.origin[c];
+            if (n) n[c] = g.n[c];
+            if (lo) lo[c] = g.lo[c];
+            if (nl) nl[c] = g.nl[c];
+            if (m) m[c] = g.m[c];
+        }
+        if (h) *h = g.h;
+    });
+}
+
+sie_status sie_get_stencils(const sie_problem *p, int32_t medium, int32_t *out, int64_t *nt_grid) {
+    return guard([&] {
+        SIE_CHECK(p && p->is_setup, SIE_ESTATE, "problem not set up");
+        const Grid &g = *p->medium(medium).grid;
+        const int64_t ntg = (int64_t)g.tris.size();
+        if (nt_grid) *nt_grid = ntg;
+        if (!out) return;
+        // ascending global triangle order
+        std::vector<std::pair<int32_t, int64_t>> ord(ntg);
+        for (int64_t i = 0; i < ntg; ++i) ord[i] = {g.tris[i], i};
+        std::sort(ord.begin(), ord.end());
+        for (int64_t j = 0; j < ntg; ++j)
+            for (int c = 0; c < 3; ++c) out[3 * j + c] = g.centre[3 * ord[j].second + c];
+    });
+}
+
+sie_status sie_get_near_pattern(const sie_problem *p, int32_t medium, int64_t *row_ptr, int32_t *cols, int64_t *nnz) {
+    return guard([&] {
+        SIE_CHECK(p && p->is_setup, SIE_ESTATE, "problem not set up");
+        const Grid &g = *p->medium(medium).grid;
+        if (nnz) *nnz = g.nnz;
+        if (!row_ptr) return;
+        const int64_t E = p->mesh.nrwg;
+        std::vector<int64_t> rp = g.d_row_ptr.download(g.rwg1 - g.rwg0 + 1);
+        for (int64_t r = 0; r <= E; ++r) {
+            if (r <= g.rwg0) row_ptr[r] = 0;
+            else if (r >= g.rwg1) row_ptr[r] = g.nnz;
+            else row_ptr[r] = rp[r - g.rwg0];
+        }
+        if (cols && g.nnz) {
+            std::vector<int32_t> c = g.d_cols.download(g.nnz);
+            std::memcpy(cols, c.data(), g.nnz * sizeof(int32_t));
+        }
+    });
+}
+
+sie_status sie_get_near_values(const sie_problem *p, int32_t medium, sie_op op, sie_c128 *out) {
+    return guard([&] {
+        SIE_CHECK(p && p->is_setup, SIE_ESTATE, "problem not set up");
+        SIE_CHECK(op == SIE_OP_L || op == SIE_OP_K, SIE_EINVAL, "near values exist for L and K");
+        const Medium &md = p->medium(medium);
+        const int64_t nnz = md.grid->nnz;
+        std::vector<c128> v = (op == SIE_OP_L ? md.d_nL64 : md.d_nK64).download(nnz);
+        std::memcpy(out, v.data(), nnz * sizeof(c128));
+    });
+}
+
+sie_status sie_get_wavenumber(const sie_problem *p, int32_t medium, sie_c128 *k) {
+    return guard([&] {
+        SIE_CHECK(p && p->is_setup && k, SIE_ESTATE, "problem not set up");
+        const c128 v = p->medium(medium).k;
+        k->re = v.re; k->im = v.im;
+    });
+}
+
+sie_status sie_matvec(sie_problem *p, int32_t medium, sie_op op, sie_precision prec, int32_t nrhs, const void *x_dev,
+                      void *y_dev, void *stream) {
+    return guard([&] {
+        SIE_CHECK(p && p->is_setup, SIE_ESTATE, "problem not set up");
+        SIE_CHECK(x_dev && y_dev && nrhs >= 1, SIE_EINVAL, "bad vectors");
+        SIE_CHECK(x_dev != y_dev, SIE_EINVAL, "x and y must not alias");
+        SIE_CHECK(op == SIE_OP_L || op == SIE_OP_K || op == SIE_OP_X, SIE_EINVAL, "unknown operator");
+        Medium &md = p->medium(op == SIE_OP_X ? -1 : medium);
+        hipStream_t st = (hipStream_t)stream;
+        if (prec == SIE_FP64)
+            matvec<double>(p, md, op, nrhs, (const c128 *)x_dev, (c128 *)y_dev, st);
+        else if (prec == SIE_FP32)
+            matvec<float>(p, md, op, nrhs, (const c64 *)x_dev, (c64 *)y_dev, st);
+        else
+            throw Error(SIE_EINVAL, "unknown precision");
+    });
+}
+
+sie_status sie_project(sie_problem *p, int32_t medium, sie_precision prec, const void *x_dev, void *grid_dev,
+                       void *stream) {
+    return guard([&] {
+        SIE_CHECK(p && p->is_setup, SIE_ESTATE, "problem not set up");
+        SIE_CHECK(x_dev && grid_dev, SIE_EINVAL, "NULL pointer");
+        Medium &md = p->medium(medium);
+        if (prec == SIE_FP64) stage_project<double>(p, md, (const c128 *)x_dev, (c128 *)grid_dev, (hipStream_t)stream);
+        else stage_project<float>(p, md, (const c64 *)x_dev, (c64 *)grid_dev, (hipStream_t)stream);
+    });
+}
+
+sie_status sie_convolve(sie_problem *p, int32_t medium, sie_precision prec, int32_t nfields, const void *in_dev,
+                        void *out_dev, void *stream) {
+    return guard([&] {
+        SIE_CHECK(p && p->is_setup, SIE_ESTATE, "problem not set up");
+        SIE_CHECK(in_dev && out_dev, SIE_EINVAL, "NULL pointer");
+        Medium &md = p->medium(medium);
+        if (prec == SIE_FP64)
+            stage_convolve<double>(p, md, nfields, (const c128 *)in_dev, (c128 *)out_dev, (hipStream_t)stream);
+        else
+            stage_convolve<float>(p, md, nfields, (const c64 *)in_dev, (c64 *)out_dev, (hipStream_t)stream);
+    });
+}
+
+sie_status sie_interpolate(sie_problem *p, int32_t medium, sie_precision prec, const void *grid_dev, void *y_dev,
+                           void *stream) {
+    return guard([&] {
+        SIE_CHECK(p && p->is_setup, SIE_ESTATE, "problem not set up");
+        SIE_CHECK(grid_dev && y_dev, SIE_EINVAL, "NULL pointer");
+        Medium &md = p->medium(medium);
+        if (prec == SIE_FP64)
+            stage_interpolate<double>(p, md, (const c128 *)grid_dev, (c128 *)y_dev, (hipStream_t)stream);
+        else
+            stage_interpolate<float>(p, md, (const c64 *)grid_dev, (c64 *)y_dev, (hipStream_t)stream);
+    });
+}
+
+}  // extern "C"

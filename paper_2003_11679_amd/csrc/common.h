@@ -1,0 +1,217 @@
+// Internal declarations of the SIE library (host C++ and HIP kernels).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/sie.h"
+
+namespace sie {
+
+// ---------------------------------------------------------------- complex
+template <typename T>
+struct cx {
+    T re, im;
+    __host__ __device__ cx() : re(0), im(0) {}
+    __host__ __device__ cx(T r, T i = 0) : re(r), im(i) {}
+    template <typename U>
+    __host__ __device__ explicit cx(const cx<U> &o) : re(T(o.re)), im(T(o.im)) {}
+};
+template <typename T> __host__ __device__ inline cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T> __host__ __device__ inline cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T> __host__ __device__ inline cx<T> operator-(cx<T> a) { return {-a.re, -a.im}; }
+template <typename T> __host__ __device__ inline cx<T> operator*(cx<T> a, cx<T> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T> __host__ __device__ inline cx<T> operator*(T s, cx<T> a) { return {s * a.re, s * a.im}; }
+template <typename T> __host__ __device__ inline cx<T> operator*(cx<T> a, T s) { return {s * a.re, s * a.im}; }
+template <typename T> __host__ __device__ inline cx<T> &operator+=(cx<T> &a, cx<T> b) { a.re += b.re; a.im += b.im; return a; }
+template <typename T> __host__ __device__ inline cx<T> &operator-=(cx<T> &a, cx<T> b) { a.re -= b.re; a.im -= b.im; return a; }
+template <typename T> __host__ __device__ inline cx<T> conj(cx<T> a) { return {a.re, -a.im}; }
+template <typename T> __host__ __device__ inline T norm2(cx<T> a) { return a.re * a.re + a.im * a.im; }
+template <typename T> __host__ __device__ inline cx<T> cdiv(cx<T> a, cx<T> b) {
+    T d = b.re * b.re + b.im * b.im;
+    return {(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
+}
+using c64 = cx<float>;
+using c128 = cx<double>;
+
+// ---------------------------------------------------------------- errors
+struct Error : std::runtime_error {
+    sie_status code;
+    Error(sie_status c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define SIE_HIP(expr)                                                                         \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            throw ::sie::Error(SIE_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define SIE_CHECK(cond, code, msg)                                            \
+    do {                                                                      \
+        if (!(cond)) throw ::sie::Error(code, msg);                           \
+    } while (0)
+
+// ---------------------------------------------------------------- device buffer
+template <typename T>
+struct DBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    DBuf() = default;
+    explicit DBuf(size_t count) { alloc(count); }
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    DBuf(DBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DBuf &operator=(DBuf &&o) noexcept {
+        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        return *this;
+    }
+    ~DBuf() { release(); }
+    void alloc(size_t count) {
+        release();
+        n = count;
+        if (count) {
+            hipError_t e = hipMalloc(&p, count * sizeof(T));
+            if (e != hipSuccess) {
+                p = nullptr; n = 0;
+                throw Error(SIE_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+            }
+        }
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr; n = 0;
+    }
+    void upload(const T *h, size_t count) {
+        if (count > n) alloc(count);
+        if (count) SIE_HIP(hipMemcpy(p, h, count * sizeof(T), hipMemcpyHostToDevice));
+    }
+    void upload(const std::vector<T> &v) { upload(v.data(), v.size()); }
+    std::vector<T> download(size_t count) const {
+        std::vector<T> h(count);
+        if (count) SIE_HIP(hipMemcpy(h.data(), p, count * sizeof(T), hipMemcpyDeviceToHost));
+        return h;
+    }
+    std::vector<T> download() const { return download(n); }
+    size_t bytes() const { return n * sizeof(T); }
+};
+
+// ---------------------------------------------------------------- mesh (host)
+struct Mesh {
+    // concatenated objects
+    std::vector<double> xyz;        // [nv][3]
+    std::vector<int32_t> tri;       // [nt][3]
+    std::vector<int32_t> tri_obj;   // [nt]
+    int nobj = 0;
+    // geometry
+    std::vector<double> area;       // [nt]
+    std::vector<double> normal;     // [nt][3]
+    std::vector<double> centroid;   // [nt][3], ((v0 + v1) + v2) / 3
+    // RWG topology
+    int64_t nrwg = 0;
+    std::vector<int32_t> edge_v;    // [E][2] a < b
+    std::vector<int32_t> tpm;       // [E][2] T+, T-
+    std::vector<int32_t> epm;       // [E][2] local edge index in T+, T-
+    std::vector<double> len;        // [E]
+    std::vector<int32_t> tri_rwg;   // [nt][3]
+    std::vector<double> tri_sign;   // [nt][3]
+    std::vector<int64_t> obj_rwg0;  // [nobj + 1] first RWG of each object
+    int64_t nt() const { return (int64_t)tri.size() / 3; }
+    int64_t nv() const { return (int64_t)xyz.size() / 3; }
+};
+void build_topology(Mesh &m);   // throws Error(SIE_EMESH)
+
+// ---------------------------------------------------------------- quadrature (host)
+struct Rule {
+    std::vector<double> bary;   // [q][3]
+    std::vector<double> w;      // [q], sum = 1
+    int size() const { return (int)w.size(); }
+};
+void gauss_legendre01(int n, std::vector<double> &x, std::vector<double> &w);
+Rule rule_collapsed(int n);
+Rule rule_self(int n);
+Rule rule_edge(int n, int opp);
+Rule rule_vertex(int n, int vtx);
+
+enum PairKind { KIND_SELF = 0, KIND_EDGE = 1, KIND_VERTEX = 2, KIND_CLOSE = 3, KIND_FAR = 4 };
+constexpr double CLOSE_FACTOR = 2.5;
+
+// ---------------------------------------------------------------- grid + operators
+template <typename T>
+struct Work {       // per-medium, per-precision scratch for matvecs
+    DBuf<cx<T>> grid;     // [F][nl_z][nl_y][nl_x] sources then potentials
+    DBuf<cx<T>> bufA;     // [F][nl_z][nl_y][m_x]
+    DBuf<cx<T>> bufB;     // [F][nl_z][m_y][m_x]
+    DBuf<cx<T>> trisrc;   // [ntg][4]  per-triangle projection coefficients
+    DBuf<cx<T>> tripot;   // [ntg][5]  per-triangle interpolation partials
+    int cap_rhs = 0;
+};
+
+struct Grid {
+    double origin[3] = {0, 0, 0};
+    double h = 0;
+    int n[3] = {0, 0, 0};      // full grid
+    int lo[3] = {0, 0, 0};     // live box origin (node index)
+    int nl[3] = {0, 0, 0};     // live box extent
+    int m[3] = {0, 0, 0};      // FFT lengths (powers of two >= 2 nl - 1)
+    int near_radius = 5;
+    std::vector<int32_t> tris; // triangles (global ids) on this grid, ascending
+    std::vector<int32_t> objs; // objects covered
+    std::vector<int32_t> centre;  // [ntg][3] stencil centres (host copy)
+    // device data
+    DBuf<int32_t> d_tris;      // [ntg] global triangle id
+    DBuf<int32_t> d_centre;    // [ntg][3]
+    DBuf<double> d_mom64;      // [ntg][27][4] (M0, M1x, M1y, M1z)
+    DBuf<float> d_mom32;
+    DBuf<double> d_tri64;      // [ntg][3 edges][4]: coef c_e = s l/(2A), q_e (free vertex - centre)
+    DBuf<float> d_tri32;
+    // projection as a gather: node -> list of (local triangle, stencil slot)
+    DBuf<int32_t> d_node_ptr;  // [nlive + 1]
+    DBuf<int32_t> d_node_ent;  // [27 ntg]  (tl << 5) | slot
+    // near triangle pairs (local indices), CSR over row triangle
+    DBuf<int64_t> d_pair_ptr;  // [ntg + 1]
+    DBuf<int32_t> d_pair_s;    // [npairs]
+    int64_t npairs = 0;
+    // RWG near pattern (global RWG rows of the grid's objects)
+    int64_t rwg0 = 0, rwg1 = 0; // RWG range [rwg0, rwg1)
+    DBuf<int64_t> d_row_ptr;   // [nrow + 1] (row r = RWG rwg0 + r)
+    DBuf<int32_t> d_cols;      // [nnz] global RWG column
+    int64_t nnz = 0;
+    int64_t max_row = 0;
+    DBuf<int32_t> d_trirwg;    // [ntg][3] global RWG of each local triangle edge
+    DBuf<int32_t> d_rwgloc;    // [nrow][2] (local triangle << 2) | local edge, for T+ and T-
+    DBuf<int32_t> d_glob2loc;  // [nt] local index or -1
+    std::vector<int32_t> glob2loc;
+    std::vector<double> tri_coef;  // host copy of d_tri64
+    Work<double> w64;
+    Work<float> w32;
+    int64_t nlive() const { return (int64_t)nl[0] * nl[1] * nl[2]; }
+    int64_t mvol() const { return (int64_t)m[0] * m[1] * m[2]; }
+    int64_t oct() const { return (int64_t)(m[0] / 2 + 1) * (m[1] / 2 + 1) * (m[2] / 2 + 1); }
+};
+
+struct Medium;
+template <typename T> Work<T> &work_of(Grid &g);
+
+struct Medium {
+    int id = -1;               // -1 exterior, else object index
+    Grid *grid = nullptr;
+    c128 k;                    // wavenumber
+    c128 eps, mu;              // complex permittivity, permeability (absolute)
+    // spectra (octant-folded, 1/(mx my mz) folded in): G, dG/dx, dG/dy, dG/dz
+    DBuf<c128> d_spec64;       // [4][oct]
+    DBuf<c64> d_spec32;
+    // precorrected near values (CSR of the grid pattern)
+    DBuf<c128> d_nL64, d_nK64;
+    DBuf<c64> d_nL32, d_nK32;
+};
+
+}  // namespace sie

@@ -1,0 +1,144 @@
+// Vector kernels of the Krylov solvers: conversions, axpby, batched dot
+// products with FP64 accumulation (Gram-Schmidt), basis updates.
+#include "problem.h"
+
+namespace sie {
+
+template <typename Ti, typename To>
+__global__ void k_convert(const cx<Ti> *__restrict__ in, cx<To> *__restrict__ out, int64_t n) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) out[i] = cx<To>((To)in[i].re, (To)in[i].im);
+}
+template <typename Ti, typename To>
+void launch_convert(const cx<Ti> *in, cx<To> *out, int64_t n, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL((k_convert<Ti, To>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, out, n);
+    SIE_HIP(hipGetLastError());
+}
+
+template <typename T>
+__global__ void k_axpby(int64_t n, c128 a, const cx<T> *__restrict__ x, c128 b, cx<T> *__restrict__ y) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const cx<T> aa((T)a.re, (T)a.im), bb((T)b.re, (T)b.im);
+    y[i] = aa * x[i] + bb * y[i];
+}
+template <typename T> void launch_axpby(int64_t n, c128 a, const cx<T> *x, c128 b, cx<T> *y, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_axpby<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, a, x, b, y);
+    SIE_HIP(hipGetLastError());
+}
+
+template <typename T>
+__global__ void k_scale_into(int64_t n, c128 a, const cx<T> *__restrict__ x, cx<T> *__restrict__ y) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    y[i] = cx<T>((T)a.re, (T)a.im) * x[i];
+}
+template <typename T> void launch_scale_into(int64_t n, c128 a, const cx<T> *x, cx<T> *y, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_scale_into<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, a, x, y);
+    SIE_HIP(hipGetLastError());
+}
+
+// partial dots: block (b, j) sums conj(V[j][i]) w[i] over a strided slice
+template <typename T>
+__global__ void k_dots_part(int64_t n, const cx<T> *__restrict__ V, int64_t ldv, const cx<T> *__restrict__ w,
+                            c128 *__restrict__ part, int nb) {
+    __shared__ double sre[256], sim[256];
+    const int j = blockIdx.y;
+    const cx<T> *v = V + j * ldv;
+    double re = 0, im = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double ar = v[i].re, ai = v[i].im, br = w[i].re, bi = w[i].im;
+        re += ar * br + ai * bi;
+        im += ar * bi - ai * br;
+    }
+    sre[threadIdx.x] = re; sim[threadIdx.x] = im;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) { sre[threadIdx.x] += sre[threadIdx.x + s]; sim[threadIdx.x] += sim[threadIdx.x + s]; }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(int64_t)j * nb + blockIdx.x] = c128(sre[0], sim[0]);
+}
+
+__global__ void k_dots_final(int J, const c128 *__restrict__ part, int nb, c128 *__restrict__ h) {
+    __shared__ double sre[256], sim[256];
+    const int j = blockIdx.x;
+    double re = 0, im = 0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) { re += part[(int64_t)j * nb + b].re; im += part[(int64_t)j * nb + b].im; }
+    sre[threadIdx.x] = re; sim[threadIdx.x] = im;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) { sre[threadIdx.x] += sre[threadIdx.x + s]; sim[threadIdx.x] += sim[threadIdx.x + s]; }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) h[j] = c128(sre[0], sim[0]);
+}
+
+template <typename T>
+void launch_dots(int64_t n, int J, const cx<T> *V, int64_t ldv, const cx<T> *w, c128 *part, int nb, c128 *h,
+                 hipStream_t st) {
+    if (J <= 0) return;
+    hipLaunchKernelGGL(k_dots_part<T>, dim3(nb, J), dim3(256), 0, st, n, V, ldv, w, part, nb);
+    SIE_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_dots_final, dim3(J), dim3(256), 0, st, J, part, nb, h);
+    SIE_HIP(hipGetLastError());
+}
+
+template <typename T, int SGN>
+__global__ void k_gemv(int64_t n, int J, const cx<T> *__restrict__ V, int64_t ldv, const c128 *__restrict__ h,
+                       cx<T> *__restrict__ w) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double re = 0, im = 0;
+    for (int j = 0; j < J; ++j) {
+        const cx<T> v = V[j * ldv + i];
+        const c128 c = h[j];
+        re += v.re * c.re - v.im * c.im;
+        im += v.re * c.im + v.im * c.re;
+    }
+    w[i] = cx<T>((T)(w[i].re + SGN * re), (T)(w[i].im + SGN * im));
+}
+template <typename T>
+void launch_gemv_sub(int64_t n, int J, const cx<T> *V, int64_t ldv, const c128 *h, cx<T> *w, hipStream_t st) {
+    if (J <= 0 || n <= 0) return;
+    hipLaunchKernelGGL((k_gemv<T, -1>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, J, V, ldv, h, w);
+    SIE_HIP(hipGetLastError());
+}
+template <typename T>
+void launch_gemv_add(int64_t n, int J, const cx<T> *V, int64_t ldv, const c128 *h, cx<T> *w, hipStream_t st) {
+    if (J <= 0 || n <= 0) return;
+    hipLaunchKernelGGL((k_gemv<T, 1>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, J, V, ldv, h, w);
+    SIE_HIP(hipGetLastError());
+}
+
+template <typename T>
+__global__ void k_diag_mul(int64_t n, const c128 *__restrict__ d, const cx<T> *__restrict__ x, cx<T> *__restrict__ y) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const cx<T> dd((T)d[i].re, (T)d[i].im);
+    y[i] = dd * x[i];
+}
+template <typename T> void launch_diag_mul(int64_t n, const c128 *d, const cx<T> *x, cx<T> *y, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_diag_mul<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, d, x, y);
+    SIE_HIP(hipGetLastError());
+}
+
+template void launch_convert<double, float>(const c128 *, c64 *, int64_t, hipStream_t);
+template void launch_convert<float, double>(const c64 *, c128 *, int64_t, hipStream_t);
+template void launch_convert<double, double>(const c128 *, c128 *, int64_t, hipStream_t);
+#define SIE_INST_B(T)                                                                                          \
+    template void launch_axpby<T>(int64_t, c128, const cx<T> *, c128, cx<T> *, hipStream_t);                  \
+    template void launch_scale_into<T>(int64_t, c128, const cx<T> *, cx<T> *, hipStream_t);                   \
+    template void launch_dots<T>(int64_t, int, const cx<T> *, int64_t, const cx<T> *, c128 *, int, c128 *,     \
+                                 hipStream_t);                                                                \
+    template void launch_gemv_sub<T>(int64_t, int, const cx<T> *, int64_t, const c128 *, cx<T> *, hipStream_t); \
+    template void launch_gemv_add<T>(int64_t, int, const cx<T> *, int64_t, const c128 *, cx<T> *, hipStream_t); \
+    template void launch_diag_mul<T>(int64_t, const c128 *, const cx<T> *, cx<T> *, hipStream_t);
+SIE_INST_B(float)
+SIE_INST_B(double)
+
+}  // namespace sie

@@ -1,0 +1,284 @@
+// Grid-side stages of the AIM product (Sec. III-D-1, eq. AIM_Lin / AIM_Kin):
+// stencil assignment, projection moments, projection P / P_phi (a gather over
+// per-node source lists, so results do not depend on thread scheduling),
+// interpolation W = P^T and the near-field CSR product that also adds the
+// interpolated far part.
+//
+// Projection weights of RWG n on triangle t at stencil node a (27 nodes,
+// tensor Lagrange polynomials l_a of the 3-point stencil, moment matching up
+// to degree 2 per axis):
+//   P_n(a)     = c_e (M1_t[a] - q_e M0_t[a]),   P_phi,n(a) = 2 c_e M0_t[a]
+//   M0_t[a] = int_t l_a dS,  M1_t[a] = int_t l_a (r - r_c) dS,
+//   c_e = +-l/(2A),  q_e = (vertex opposite edge e) - r_c,  r_c = stencil centre.
+#include "common.h"
+#include "kernels.h"
+
+namespace sie {
+
+__global__ void k_stencil_assign(const double *__restrict__ centroids, const int32_t *__restrict__ tris,
+                                 int64_t ntg, double ox, double oy, double oz, double h, int nx, int ny,
+                                 int nz, int32_t *__restrict__ centre, int32_t *__restrict__ raw) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= ntg) return;
+    const int64_t t = tris[i];
+    const double o[3] = {ox, oy, oz};
+    const int n[3] = {nx, ny, nz};
+    for (int c = 0; c < 3; ++c) {
+        // IEEE subtraction, division, addition; no contraction possible
+        double q = (centroids[3 * t + c] - o[c]) / h;
+        double f = floor(q + 0.5);
+        int v = (int)f;
+        raw[3 * i + c] = v;
+        centre[3 * i + c] = v < 1 ? 1 : (v > n[c] - 2 ? n[c] - 2 : v);
+    }
+}
+
+void launch_stencil_assign(const double *centroids, const int32_t *tris, int64_t ntg, const double origin[3],
+                           double h, const int n[3], int32_t *centre_out, int32_t *raw_out, hipStream_t st) {
+    if (ntg == 0) return;
+    hipLaunchKernelGGL(k_stencil_assign, dim3((unsigned)((ntg + 255) / 256)), dim3(256), 0, st, centroids, tris,
+                       ntg, origin[0], origin[1], origin[2], h, n[0], n[1], n[2], centre_out, raw_out);
+    SIE_HIP(hipGetLastError());
+}
+
+// One thread per triangle: 27 x (M0, M1) by a quadrature rule exact for the
+// degree-7 integrands (rule: [nq][4] = bary0, bary1, bary2, weight).
+__global__ void k_moments(const double *__restrict__ xyz, const int32_t *__restrict__ tri,
+                          const int32_t *__restrict__ tris, const int32_t *__restrict__ centre, int64_t ntg,
+                          double ox, double oy, double oz, double h, const double *__restrict__ rule, int nq,
+                          double *__restrict__ mom64, float *__restrict__ mom32) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= ntg) return;
+    const int64_t t = tris[i];
+    double v[3][3];
+    for (int k = 0; k < 3; ++k)
+        for (int c = 0; c < 3; ++c) v[k][c] = xyz[3 * (int64_t)tri[3 * t + k] + c];
+    const double rc[3] = {ox + h * centre[3 * i], oy + h * centre[3 * i + 1], oz + h * centre[3 * i + 2]};
+    double e1[3], e2[3];
+    for (int c = 0; c < 3; ++c) { e1[c] = v[1][c] - v[0][c]; e2[c] = v[2][c] - v[0][c]; }
+    double cr0 = e1[1] * e2[2] - e1[2] * e2[1], cr1 = e1[2] * e2[0] - e1[0] * e2[2], cr2 = e1[0] * e2[1] - e1[1] * e2[0];
+    const double A = 0.5 * sqrt(cr0 * cr0 + cr1 * cr1 + cr2 * cr2);
+    double M[27][4];
+    for (int a = 0; a < 27; ++a) M[a][0] = M[a][1] = M[a][2] = M[a][3] = 0.0;
+    for (int q = 0; q < nq; ++q) {
+        const double b0 = rule[4 * q], b1 = rule[4 * q + 1], b2 = rule[4 * q + 2], w = rule[4 * q + 3] * A;
+        double d[3], l[3][3];
+        for (int c = 0; c < 3; ++c) {
+            d[c] = b0 * v[0][c] + b1 * v[1][c] + b2 * v[2][c] - rc[c];
+            const double xi = d[c] / h;
+            l[c][0] = 0.5 * xi * (xi - 1.0);
+            l[c][1] = 1.0 - xi * xi;
+            l[c][2] = 0.5 * xi * (xi + 1.0);
+        }
+        for (int cz = 0; cz < 3; ++cz)
+            for (int cy = 0; cy < 3; ++cy)
+                for (int cx_ = 0; cx_ < 3; ++cx_) {
+                    const int a = (cz * 3 + cy) * 3 + cx_;
+                    const double wl = w * l[0][cx_] * l[1][cy] * l[2][cz];
+                    M[a][0] += wl;
+                    M[a][1] += wl * d[0];
+                    M[a][2] += wl * d[1];
+                    M[a][3] += wl * d[2];
+                }
+    }
+    for (int a = 0; a < 27; ++a)
+        for (int c = 0; c < 4; ++c) {
+            mom64[(i * 27 + a) * 4 + c] = M[a][c];
+            mom32[(i * 27 + a) * 4 + c] = (float)M[a][c];
+        }
+}
+
+void launch_moments(const double *xyz, const int32_t *tri, const int32_t *tris, const int32_t *centre,
+                    int64_t ntg, const double origin[3], double h, const double *rule, int nq,
+                    double *mom64, float *mom32, hipStream_t st) {
+    if (ntg == 0) return;
+    hipLaunchKernelGGL(k_moments, dim3((unsigned)((ntg + 127) / 128)), dim3(128), 0, st, xyz, tri, tris, centre,
+                       ntg, origin[0], origin[1], origin[2], h, rule, nq, mom64, mom32);
+    SIE_HIP(hipGetLastError());
+}
+
+// Per-triangle projection coefficients: alpha = sum_e x_e c_e and
+// beta = sum_e x_e c_e q_e (trisrc[t] = alpha, beta_x, beta_y, beta_z).
+template <typename T>
+__global__ void k_tri_sources(int64_t ntg, const int32_t *__restrict__ tri_rwg, const T *__restrict__ coef,
+                              const cx<T> *__restrict__ x, cx<T> *__restrict__ src) {
+    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= ntg) return;
+    cx<T> a, bx, by, bz;
+    for (int e = 0; e < 3; ++e) {
+        const cx<T> xv = x[tri_rwg[3 * t + e]];
+        const T *c = coef + (t * 3 + e) * 4;
+        const cx<T> cxv = c[0] * xv;
+        a += cxv;
+        bx += c[1] * cxv; by += c[2] * cxv; bz += c[3] * cxv;
+    }
+    src[4 * t] = a; src[4 * t + 1] = bx; src[4 * t + 2] = by; src[4 * t + 3] = bz;
+}
+
+template <typename T>
+void launch_tri_sources(const Grid &g, const int32_t *tri_rwg_loc, const T *tri_coef, const cx<T> *x,
+                        cx<T> *trisrc, hipStream_t st) {
+    int64_t ntg = (int64_t)g.tris.size();
+    if (!ntg) return;
+    hipLaunchKernelGGL(k_tri_sources<T>, dim3((unsigned)((ntg + 255) / 256)), dim3(256), 0, st, ntg, tri_rwg_loc,
+                       tri_coef, x, trisrc);
+    SIE_HIP(hipGetLastError());
+}
+
+// Gather projection: one thread per live node.  grid [F][nlive] with
+// J_c = sum (alpha M1_c - beta_c M0) and (F == 4) Q = sum 2 alpha M0.
+template <typename T>
+__global__ void k_project(int64_t nlive, const int32_t *__restrict__ node_ptr, const int32_t *__restrict__ ent,
+                          const T *__restrict__ mom, const cx<T> *__restrict__ src, cx<T> *__restrict__ grid,
+                          int nf) {
+    int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (v >= nlive) return;
+    cx<T> jx, jy, jz, q;
+    for (int k = node_ptr[v]; k < node_ptr[v + 1]; ++k) {
+        const int32_t e = ent[k];
+        const int64_t t = e >> 5;
+        const int a = e & 31;
+        const T *m = mom + (t * 27 + a) * 4;
+        const cx<T> al = src[4 * t], bx = src[4 * t + 1], by = src[4 * t + 2], bz = src[4 * t + 3];
+        jx += m[1] * al - m[0] * bx;
+        jy += m[2] * al - m[0] * by;
+        jz += m[3] * al - m[0] * bz;
+        q += m[0] * al;
+    }
+    grid[v] = jx; grid[nlive + v] = jy; grid[2 * nlive + v] = jz;
+    if (nf == 4) grid[3 * nlive + v] = T(2) * q;
+}
+
+template <typename T>
+void launch_project(const Grid &g, const T *mom, const cx<T> *trisrc, cx<T> *grid, int nfields, hipStream_t st) {
+    const int64_t nlive = g.nlive();
+    hipLaunchKernelGGL(k_project<T>, dim3((unsigned)((nlive + 255) / 256)), dim3(256), 0, st, nlive,
+                       g.d_node_ptr.p, g.d_node_ent.p, mom, trisrc, grid, nfields);
+    SIE_HIP(hipGetLastError());
+}
+
+// Interpolation partials per triangle: psi = sum_a M1[a] . F_vec(a),
+// chi = sum_a M0[a] F_vec(a), zeta = sum_a M0[a] F_scal(a) (F == 4).
+template <typename T>
+__global__ void k_interp(int64_t ntg, const int32_t *__restrict__ centre, int lox, int loy, int loz, int nlx,
+                         int nly, int64_t nlive, const T *__restrict__ mom, const cx<T> *__restrict__ pot, int nf,
+                         cx<T> *__restrict__ out) {
+    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= ntg) return;
+    const int cxi = centre[3 * t] - lox, cyi = centre[3 * t + 1] - loy, czi = centre[3 * t + 2] - loz;
+    cx<T> psi, chx, chy, chz, zeta;
+    for (int dz = 0; dz < 3; ++dz)
+        for (int dy = 0; dy < 3; ++dy)
+            for (int dx = 0; dx < 3; ++dx) {
+                const int a = (dz * 3 + dy) * 3 + dx;
+                const int64_t v = ((int64_t)(czi + dz - 1) * nly + (cyi + dy - 1)) * nlx + (cxi + dx - 1);
+                const T *m = mom + (t * 27 + a) * 4;
+                const cx<T> fx = pot[v], fy = pot[nlive + v], fz = pot[2 * nlive + v];
+                psi += m[1] * fx + m[2] * fy + m[3] * fz;
+                chx += m[0] * fx; chy += m[0] * fy; chz += m[0] * fz;
+                if (nf == 4) zeta += m[0] * pot[3 * nlive + v];
+            }
+    cx<T> *o = out + 5 * t;
+    o[0] = psi; o[1] = chx; o[2] = chy; o[3] = chz; o[4] = zeta;
+}
+
+template <typename T>
+void launch_interp(const Grid &g, const T *mom, const cx<T> *pot, int nfields, cx<T> *tripot, hipStream_t st) {
+    int64_t ntg = (int64_t)g.tris.size();
+    if (!ntg) return;
+    hipLaunchKernelGGL(k_interp<T>, dim3((unsigned)((ntg + 255) / 256)), dim3(256), 0, st, ntg, g.d_centre.p,
+                       g.lo[0], g.lo[1], g.lo[2], g.nl[0], g.nl[1], g.nlive(), mom, pot, nfields, tripot);
+    SIE_HIP(hipGetLastError());
+}
+
+template <typename T>
+__device__ inline cx<T> wave_sum(cx<T> v) {
+    for (int off = 32; off > 0; off >>= 1) {
+        v.re += __shfl_xor(v.re, off, 64);
+        v.im += __shfl_xor(v.im, off, 64);
+    }
+    return v;
+}
+
+// One wavefront per row.  Far part of row n from its two triangles:
+// c_e (psi - q_e . chi) + kscal c_e zeta   (kscal = -2 k^-2 for L, 0 for K).
+template <typename T>
+__global__ void k_spmv_far(int64_t E, int64_t rwg0, int64_t rwg1, const int64_t *__restrict__ row_ptr,
+                           const int32_t *__restrict__ cols, const cx<T> *__restrict__ vals,
+                           const int32_t *__restrict__ rwg_loc, const T *__restrict__ coef,
+                           const cx<T> *__restrict__ tripot, cx<T> kscal, const cx<T> *__restrict__ x,
+                           cx<T> *__restrict__ y, int use_far) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (row >= E) return;
+    if (row < rwg0 || row >= rwg1) {
+        if (lane == 0) y[row] = cx<T>();
+        return;
+    }
+    const int64_t r = row - rwg0;
+    cx<T> acc;
+    if (vals) {
+        const int64_t b = row_ptr[r], e = row_ptr[r + 1];
+        for (int64_t j = b + lane; j < e; j += 64) acc += vals[j] * x[cols[j]];
+        acc = wave_sum(acc);
+    }
+    if (lane == 0) {
+        if (use_far) {
+            for (int s = 0; s < 2; ++s) {
+                const int32_t lc = rwg_loc[2 * r + s];
+                const int64_t t = lc >> 2;
+                const int ed = lc & 3;
+                const T *c = coef + (t * 3 + ed) * 4;
+                const cx<T> *p = tripot + 5 * t;
+                cx<T> v = p[0] - (c[1] * p[1] + c[2] * p[2] + c[3] * p[3]);
+                v += kscal * p[4];
+                acc += c[0] * v;
+            }
+        }
+        y[row] = acc;
+    }
+}
+
+template <typename T>
+void launch_spmv_far(const Grid &g, int64_t E, const int32_t *rwg_loc, const T *tri_coef, const cx<T> *tripot,
+                     cx<T> kscal, const cx<T> *vals, const cx<T> *x, cx<T> *y, bool use_far, hipStream_t st) {
+    if (E == 0) return;
+    const int rows_per_block = 4;
+    hipLaunchKernelGGL(k_spmv_far<T>, dim3((unsigned)((E + rows_per_block - 1) / rows_per_block)), dim3(256), 0, st,
+                       E, g.rwg0, g.rwg1, g.d_row_ptr.p, g.d_cols.p, vals, rwg_loc, tri_coef, tripot, kscal, x, y,
+                       use_far ? 1 : 0);
+    SIE_HIP(hipGetLastError());
+}
+
+// y = X x for the sparse X (real values, <= 5 per row, CSR int32).
+template <typename T>
+__global__ void k_x_apply(int64_t E, const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                          const T *__restrict__ val, const cx<T> *__restrict__ x, cx<T> *__restrict__ y) {
+    int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= E) return;
+    cx<T> acc;
+    for (int j = ptr[r]; j < ptr[r + 1]; ++j) acc += val[j] * x[col[j]];
+    y[r] = acc;
+}
+
+template <typename T>
+void launch_x_apply(int64_t E, const int32_t *xptr, const int32_t *xcol, const T *xval, const cx<T> *x, cx<T> *y,
+                    hipStream_t st) {
+    if (E == 0) return;
+    hipLaunchKernelGGL(k_x_apply<T>, dim3((unsigned)((E + 255) / 256)), dim3(256), 0, st, E, xptr, xcol, xval, x, y);
+    SIE_HIP(hipGetLastError());
+}
+
+#define SIE_INST(T)                                                                                           \
+    template void launch_tri_sources<T>(const Grid &, const int32_t *, const T *, const cx<T> *, cx<T> *,      \
+                                        hipStream_t);                                                          \
+    template void launch_project<T>(const Grid &, const T *, const cx<T> *, cx<T> *, int, hipStream_t);         \
+    template void launch_interp<T>(const Grid &, const T *, const cx<T> *, int, cx<T> *, hipStream_t);          \
+    template void launch_spmv_far<T>(const Grid &, int64_t, const int32_t *, const T *, const cx<T> *, cx<T>,   \
+                                     const cx<T> *, const cx<T> *, cx<T> *, bool, hipStream_t);                 \
+    template void launch_x_apply<T>(int64_t, const int32_t *, const int32_t *, const T *, const cx<T> *, cx<T> *, \
+                                    hipStream_t);
+SIE_INST(float)
+SIE_INST(double)
+
+}  // namespace sie

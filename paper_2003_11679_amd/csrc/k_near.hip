@@ -1,0 +1,537 @@
+// Near region of the AIM (Sec. III-D-1): triangle pairs whose stencil
+// centres are within R cells (Chebyshev), their direct Galerkin integrals in
+// FP64 (near entries "computed accurately with direct integration") minus the
+// grid's own contribution (precorrection, eq. LinNRP / KinNRP), assembled per
+// RWG pair into one CSR pattern; and the grid Green's function samples and
+// spectra used by the convolution.
+//
+// Direct integrals of a pair (t, s), observation r on t, source r' on s:
+//   S(r) = int_s G,  V(r) = int_s G r',  Gv(r) = int_s grad_r G
+// with G = exp(-jkR)/(4 pi R) split into 1/(4 pi R), integrated in closed form
+// (Wilton et al. 1984; Graglia 1993), plus a bounded remainder integrated by
+// quadrature.  With f_e = c_e (r - p_e) on t and f_f = c_f (r' - p_f) on s and
+// W the outer weights:
+//   A[e][f]   = c_e c_f [sum W r.V - p_f . sum W S r - p_e . sum W V + p_e.p_f sum W S]
+//   Phi[e][f] = 4 c_e c_f sum W S
+//   K[e][f]   = c_e c_f [(p_f - p_e) . sum W (Gv x r) + (sum W Gv) . (p_f x p_e)]
+// (the K inner integral reduces to Gv x (r - p_f) because grad_r G is parallel
+// to r - r').
+#include "common.h"
+#include "kernels.h"
+
+namespace sie {
+
+// ----------------------------------------------------------------- near pairs
+__global__ void k_near_count(const int32_t *__restrict__ centre, int64_t ntg, const int32_t *__restrict__ cell_ptr,
+                             int lox, int loy, int loz, int nlx, int nly, int nlz, int R,
+                             int64_t *__restrict__ count) {
+    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= ntg) return;
+    const int cx_ = centre[3 * t] - lox, cy = centre[3 * t + 1] - loy, cz = centre[3 * t + 2] - loz;
+    const int x0 = max(cx_ - R, 0), x1 = min(cx_ + R, nlx - 1);
+    int64_t n = 0;
+    for (int z = max(cz - R, 0); z <= min(cz + R, nlz - 1); ++z)
+        for (int y = max(cy - R, 0); y <= min(cy + R, nly - 1); ++y) {
+            const int64_t base = ((int64_t)z * nly + y) * nlx;
+            n += cell_ptr[base + x1 + 1] - cell_ptr[base + x0];
+        }
+    count[t] = n;
+}
+
+__global__ void k_near_emit(const int32_t *__restrict__ centre, int64_t ntg, const int32_t *__restrict__ cell_ptr,
+                            int lox, int loy, int loz, int nlx, int nly, int nlz, int R,
+                            const int64_t *__restrict__ pair_ptr, int32_t *__restrict__ pair_s) {
+    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= ntg) return;
+    const int cx_ = centre[3 * t] - lox, cy = centre[3 * t + 1] - loy, cz = centre[3 * t + 2] - loz;
+    const int x0 = max(cx_ - R, 0), x1 = min(cx_ + R, nlx - 1);
+    int64_t o = pair_ptr[t];
+    for (int z = max(cz - R, 0); z <= min(cz + R, nlz - 1); ++z)
+        for (int y = max(cy - R, 0); y <= min(cy + R, nly - 1); ++y) {
+            const int64_t base = ((int64_t)z * nly + y) * nlx;
+            for (int32_t s = cell_ptr[base + x0]; s < cell_ptr[base + x1 + 1]; ++s) pair_s[o++] = s;
+        }
+}
+
+void launch_near_count(const int32_t *centre, int64_t ntg, const int32_t *cell_ptr, const int32_t *,
+                       const int lo[3], const int nl[3], int R, int64_t *count, hipStream_t st) {
+    if (!ntg) return;
+    hipLaunchKernelGGL(k_near_count, dim3((unsigned)((ntg + 255) / 256)), dim3(256), 0, st, centre, ntg, cell_ptr,
+                       lo[0], lo[1], lo[2], nl[0], nl[1], nl[2], R, count);
+    SIE_HIP(hipGetLastError());
+}
+
+void launch_near_emit(const int32_t *centre, int64_t ntg, const int32_t *cell_ptr, const int32_t *,
+                      const int lo[3], const int nl[3], int R, const int64_t *pair_ptr, int32_t *pair_s,
+                      hipStream_t st) {
+    if (!ntg) return;
+    hipLaunchKernelGGL(k_near_emit, dim3((unsigned)((ntg + 255) / 256)), dim3(256), 0, st, centre, ntg, cell_ptr,
+                       lo[0], lo[1], lo[2], nl[0], nl[1], nl[2], R, pair_ptr, pair_s);
+    SIE_HIP(hipGetLastError());
+}
+
+// ----------------------------------------------------------------- RWG pattern
+// One block per RWG row: mark the columns of all near pairs of the row's two
+// triangles in an LDS bitmap over the grid's RWG range, then count (pass 0)
+// or write them in ascending order (pass 1).
+__global__ void k_rwg_pattern(int64_t nrow, int64_t rwg0, int64_t nbits, const int32_t *__restrict__ rwg_loc,
+                              const int64_t *__restrict__ pair_ptr, const int32_t *__restrict__ pair_s,
+                              const int32_t *__restrict__ tris, const int32_t *__restrict__ tri_rwg,
+                              int64_t *__restrict__ row_len, const int64_t *__restrict__ row_ptr,
+                              int32_t *__restrict__ cols, int pass) {
+    extern __shared__ unsigned int bits[];
+    __shared__ int64_t part[256];
+    const int64_t r = blockIdx.x;
+    if (r >= nrow) return;
+    const int nw = (int)((nbits + 31) / 32);
+    for (int i = threadIdx.x; i < nw; i += blockDim.x) bits[i] = 0u;
+    __syncthreads();
+    for (int side = 0; side < 2; ++side) {
+        const int64_t tl = rwg_loc[2 * r + side] >> 2;
+        for (int64_t k = pair_ptr[tl] + threadIdx.x; k < pair_ptr[tl + 1]; k += blockDim.x) {
+            const int64_t g = tris[pair_s[k]];
+            for (int e = 0; e < 3; ++e) {
+                const int64_t b = (int64_t)tri_rwg[3 * g + e] - rwg0;
+                atomicOr(&bits[b >> 5], 1u << (b & 31));
+            }
+        }
+    }
+    __syncthreads();
+    // each thread owns a contiguous chunk of words
+    const int chunk = (nw + blockDim.x - 1) / blockDim.x;
+    const int w0 = threadIdx.x * chunk, w1 = min(nw, w0 + chunk);
+    int64_t mine = 0;
+    for (int w = w0; w < w1; ++w) mine += __popc(bits[w]);
+    part[threadIdx.x] = mine;
+    __syncthreads();
+    if (pass == 0) {
+        if (threadIdx.x == 0) {
+            int64_t s = 0;
+            for (int i = 0; i < (int)blockDim.x; ++i) s += part[i];
+            row_len[r] = s;
+        }
+        return;
+    }
+    // exclusive scan of part (small, serial per thread over predecessors)
+    int64_t off = 0;
+    for (int i = 0; i < (int)threadIdx.x; ++i) off += part[i];
+    int64_t o = row_ptr[r] + off;
+    for (int w = w0; w < w1; ++w) {
+        unsigned int v = bits[w];
+        while (v) {
+            const int b = __ffs(v) - 1;
+            v &= v - 1;
+            cols[o++] = (int32_t)(rwg0 + (int64_t)w * 32 + b);
+        }
+    }
+}
+
+void launch_rwg_pattern(int64_t nrow, int64_t rwg0, int64_t nbits, const int32_t *rwg_loc, const int64_t *pair_ptr,
+                         const int32_t *pair_s, const int32_t *tris, const int32_t *tri_rwg, int64_t *row_len,
+                         const int64_t *row_ptr, int32_t *cols, int pass, hipStream_t st) {
+    if (!nrow) return;
+    const size_t sh = ((nbits + 31) / 32) * sizeof(unsigned int);
+    SIE_CHECK(sh <= 96 * 1024, SIE_EINVAL, "RWG range of a grid too large for the pattern builder");
+    hipLaunchKernelGGL(k_rwg_pattern, dim3((unsigned)nrow), dim3(256), sh, st, nrow, rwg0, nbits, rwg_loc, pair_ptr,
+                       pair_s, tris, tri_rwg, row_len, row_ptr, cols, pass);
+    SIE_HIP(hipGetLastError());
+}
+
+// ----------------------------------------------------------------- direct integrals
+struct V3 { double x, y, z; };
+__device__ inline V3 operator+(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ inline V3 operator-(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ inline V3 operator*(double s, V3 a) { return {s * a.x, s * a.y, s * a.z}; }
+__device__ inline double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ inline V3 cross(V3 a, V3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+__device__ inline double len(V3 a) { return sqrt(dot(a, a)); }
+
+struct CV3 { c128 x, y, z; };
+__device__ inline CV3 cscale(c128 s, V3 a) { return {a.x * s, a.y * s, a.z * s}; }
+__device__ inline void cadd(CV3 &a, CV3 b) { a.x += b.x; a.y += b.y; a.z += b.z; }
+__device__ inline c128 cdot(V3 a, CV3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ inline CV3 ccross_cv(CV3 a, V3 b) {   // a x b
+    return {b.z * a.y - b.y * a.z, b.x * a.z - b.z * a.x, b.y * a.x - b.x * a.y};
+}
+
+// ln((R+ + l+)/(R- + l-)) free of cancellation for any foot-point position.
+__device__ inline double logratio(double lp, double lm, double Rp, double Rm, double R02) {
+    if (lm >= 0.0) return log((Rp + lp) / (Rm + lm));
+    if (lp <= 0.0) return log((Rm - lm) / (Rp - lp));
+    return log((Rp + lp) * (Rm - lm)) - log(R02);
+}
+
+struct SrcTri {
+    V3 v[3];
+    V3 n;
+    V3 lh[3], mh[3];
+    double A, e01;
+};
+
+// Static potentials of source triangle st at r: I = int 1/R,
+// Irho = int (rho' - rho)/R, gI = grad_r int 1/R; d snapped to 0 in-plane.
+__device__ inline void static_potentials(const SrcTri &st, V3 r, double &I, V3 &Irho, V3 &gI, double &d) {
+    d = dot(r - st.v[0], st.n);
+    if (fabs(d) <= 1e-10 * st.e01) d = 0.0;
+    const double ad = fabs(d);
+    double sI = 0.0, sb = 0.0;
+    Irho = {0, 0, 0};
+    gI = {0, 0, 0};
+    for (int i = 0; i < 3; ++i) {
+        const V3 a = st.v[i], b = st.v[(i + 1) % 3];
+        const V3 bm = b - r, am = a - r;
+        const double lp = dot(bm, st.lh[i]), lm = dot(am, st.lh[i]), t = dot(am, st.mh[i]);
+        const double Rp = len(bm), Rm = len(am);
+        const double R02 = t * t + d * d;
+        const bool online = R02 <= 1e-30 * (lp * lp + lm * lm + 1e-300);
+        const double f = logratio(lp, lm, Rp, Rm, R02);
+        double beta = 0.0;
+        if (!online) {
+            beta = atan2(t * lp, R02 + ad * Rp) - atan2(t * lm, R02 + ad * Rm);
+            sI += t * f;
+        }
+        sb += beta;
+        const double coef = (online ? 0.0 : R02 * f) + lp * Rp - lm * Rm;
+        Irho = Irho + (0.5 * coef) * st.mh[i];
+        gI = gI - f * st.mh[i];
+    }
+    I = sI - ad * sb;
+    const double sg = d > 0.0 ? 1.0 : (d < 0.0 ? -1.0 : 0.0);
+    gI = gI - (sg * sb) * st.n;
+}
+
+__device__ inline c128 cexp_mjk(c128 k, double R) {   // exp(-j k R)
+    const double mag = exp(k.im * R);
+    double s, c;
+    sincos(k.re * R, &s, &c);
+    return {mag * c, -mag * s};
+}
+
+__device__ inline int rule_index_outer(int kind, int loc) {
+    // 0 self, 1..3 edge(opp), 4..6 vertex(vtx), 7 close, 8 far
+    if (kind == KIND_SELF) return 0;
+    if (kind == KIND_EDGE) return 1 + loc;
+    if (kind == KIND_VERTEX) return 4 + loc;
+    return kind == KIND_CLOSE ? 7 : 8;
+}
+__device__ inline int rule_index_inner(int kind) {
+    return kind <= KIND_VERTEX ? 9 : (kind == KIND_CLOSE ? 10 : 11);
+}
+
+__global__ void __launch_bounds__(128) k_near_fill(NearFillArgs a) {
+    const int64_t ntg = a.ntg;
+    // row triangle from pair index by binary search over pair_ptr
+    const int64_t npairs = a.pair_ptr[ntg];
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= npairs) return;
+    int64_t lo = 0, hi = ntg;   // find tl with pair_ptr[tl] <= p < pair_ptr[tl+1]
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (a.pair_ptr[mid] <= p) lo = mid; else hi = mid;
+    }
+    const int64_t tl = lo, sl = a.pair_s[p];
+    const int64_t tg = a.tris[tl], sg = a.tris[sl];
+    // classification
+    int vt[3], vs[3];
+    for (int i = 0; i < 3; ++i) { vt[i] = a.tri[3 * tg + i]; vs[i] = a.tri[3 * sg + i]; }
+    int nshared = 0, shared_mask = 0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            if (vt[i] == vs[j]) { ++nshared; shared_mask |= 1 << i; }
+    const V3 o = {a.centroid[3 * tg], a.centroid[3 * tg + 1], a.centroid[3 * tg + 2]};
+    V3 pt[3], ps[3];
+    for (int i = 0; i < 3; ++i) {
+        pt[i] = V3{a.xyz[3 * (int64_t)vt[i]], a.xyz[3 * (int64_t)vt[i] + 1], a.xyz[3 * (int64_t)vt[i] + 2]} - o;
+        ps[i] = V3{a.xyz[3 * (int64_t)vs[i]], a.xyz[3 * (int64_t)vs[i] + 1], a.xyz[3 * (int64_t)vs[i] + 2]} - o;
+    }
+    int kind, loc = 0;
+    if (nshared == 3) kind = KIND_SELF;
+    else if (nshared == 2) { kind = KIND_EDGE; loc = (~shared_mask & 7) == 1 ? 0 : ((~shared_mask & 7) == 2 ? 1 : 2); }
+    else if (nshared == 1) { kind = KIND_VERTEX; loc = shared_mask == 1 ? 0 : (shared_mask == 2 ? 1 : 2); }
+    else {
+        double hmax = 0.0;
+        for (int i = 0; i < 3; ++i) {
+            hmax = fmax(hmax, len(pt[(i + 1) % 3] - pt[(i + 2) % 3]));
+            hmax = fmax(hmax, len(ps[(i + 1) % 3] - ps[(i + 2) % 3]));
+        }
+        const V3 cs = V3{a.centroid[3 * sg], a.centroid[3 * sg + 1], a.centroid[3 * sg + 2]} - o;
+        kind = len(cs) < CLOSE_FACTOR * hmax ? KIND_CLOSE : KIND_FAR;
+    }
+    if (kind < a.kind_lo || kind > a.kind_hi) return;
+
+    // source triangle geometry
+    SrcTri st;
+    for (int i = 0; i < 3; ++i) st.v[i] = ps[i];
+    {
+        const V3 e1 = ps[1] - ps[0], e2 = ps[2] - ps[0];
+        const V3 c = cross(e1, e2);
+        const double nn = len(c);
+        st.n = (1.0 / nn) * c;
+        st.A = 0.5 * nn;
+        st.e01 = len(e1);
+        for (int i = 0; i < 3; ++i) {
+            const V3 le = ps[(i + 1) % 3] - ps[i];
+            st.lh[i] = (1.0 / len(le)) * le;
+            st.mh[i] = cross(st.lh[i], st.n);
+        }
+    }
+    double At;
+    {
+        const V3 c = cross(pt[1] - pt[0], pt[2] - pt[0]);
+        At = 0.5 * len(c);
+    }
+    const c128 k = a.k;
+    const double inv4pi = 0.07957747154594767;   // 1/(4 pi)
+    const int ro = rule_index_outer(kind, loc), ri = rule_index_inner(kind);
+    const double *Ro = a.rules + 4 * a.rule_off[ro];
+    const double *Ri = a.rules + 4 * a.rule_off[ri];
+    const int no = a.rule_n[ro], ni = a.rule_n[ri];
+
+    c128 aRV, aS;
+    CV3 aV = {}, aSR = {}, aGR = {}, aG = {};
+    for (int qo = 0; qo < no; ++qo) {
+        const V3 r = Ro[4 * qo] * pt[0] + Ro[4 * qo + 1] * pt[1] + Ro[4 * qo + 2] * pt[2];
+        const double W = Ro[4 * qo + 3] * At;
+        double I0, d;
+        V3 Irho, gI;
+        static_potentials(st, r, I0, Irho, gI, d);
+        const V3 rho = r - d * st.n;
+        c128 S(I0 * inv4pi, 0.0);
+        CV3 V = {c128((Irho.x + rho.x * I0) * inv4pi), c128((Irho.y + rho.y * I0) * inv4pi),
+                 c128((Irho.z + rho.z * I0) * inv4pi)};
+        CV3 Gv = {c128(gI.x * inv4pi), c128(gI.y * inv4pi), c128(gI.z * inv4pi)};
+        for (int qi = 0; qi < ni; ++qi) {
+            const V3 rp = Ri[4 * qi] * ps[0] + Ri[4 * qi + 1] * ps[1] + Ri[4 * qi + 2] * ps[2];
+            const double wA = Ri[4 * qi + 3] * st.A;
+            const V3 df = r - rp;
+            const double R = len(df);
+            c128 rem, hg;
+            if (R == 0.0) {
+                rem = c128(k.im * inv4pi, -k.re * inv4pi);      // -j k /(4 pi)
+            } else {
+                const c128 ez = cexp_mjk(k, R);
+                const c128 z(k.im * R, -k.re * R);               // z = -j k R
+                rem = (inv4pi / R) * (ez - c128(1.0));
+                const c128 one_mz(1.0 - z.re, -z.im);
+                hg = (inv4pi / (R * R * R)) * (c128(1.0) - one_mz * ez);
+            }
+            S += wA * rem;
+            cadd(V, cscale(wA * rem, rp));
+            cadd(Gv, cscale(wA * hg, df));
+        }
+        aRV += W * cdot(r, V);
+        aS += W * S;
+        cadd(aV, CV3{W * V.x, W * V.y, W * V.z});
+        cadd(aSR, cscale(W * S, r));
+        // Gv x r
+        const CV3 gxr = ccross_cv(Gv, r);
+        cadd(aGR, CV3{W * gxr.x, W * gxr.y, W * gxr.z});
+        cadd(aG, CV3{W * Gv.x, W * Gv.y, W * Gv.z});
+    }
+
+    // precorrection: grid contribution of the pair
+    const int Wt = a.gtab_w, D = 2 * Wt + 1;
+    const int dx0 = a.centre[3 * tl] - a.centre[3 * sl];
+    const int dy0 = a.centre[3 * tl + 1] - a.centre[3 * sl + 1];
+    const int dz0 = a.centre[3 * tl + 2] - a.centre[3 * sl + 2];
+    c128 S00, S11, C11;
+    CV3 S10 = {}, S01 = {}, Vs = {}, Vt = {}, U = {};
+    const double *mt = a.mom + tl * 27 * 4;
+    const double *ms = a.mom + sl * 27 * 4;
+    for (int ia = 0; ia < 27; ++ia) {
+        const int ax = ia % 3 - 1, ay = (ia / 3) % 3 - 1, az = ia / 9 - 1;
+        const double m0t = mt[4 * ia];
+        const V3 m1t = {mt[4 * ia + 1], mt[4 * ia + 2], mt[4 * ia + 3]};
+        for (int ib = 0; ib < 27; ++ib) {
+            const int bx = ib % 3 - 1, by = (ib / 3) % 3 - 1, bz = ib / 9 - 1;
+            const int ddx = dx0 + ax - bx + Wt, ddy = dy0 + ay - by + Wt, ddz = dz0 + az - bz + Wt;
+            const c128 *gp = a.gtab + 4 * (((int64_t)ddz * D + ddy) * D + ddx);
+            const c128 G = gp[0];
+            const CV3 g = {gp[1], gp[2], gp[3]};
+            const double m0s = ms[4 * ib];
+            const V3 m1s = {ms[4 * ib + 1], ms[4 * ib + 2], ms[4 * ib + 3]};
+            const double m00 = m0t * m0s;
+            S00 += m00 * G;
+            S11 += dot(m1t, m1s) * G;
+            cadd(S10, cscale(m0s * G, m1t));
+            cadd(S01, cscale(m0t * G, m1s));
+            // g . (m1s x m1t)
+            C11 += cdot(cross(m1s, m1t), g);
+            // m0t (g x m1s)
+            const CV3 gxm1s = ccross_cv(g, m1s);
+            cadd(Vs, CV3{m0t * gxm1s.x, m0t * gxm1s.y, m0t * gxm1s.z});
+            // m0s (m1t x g) = -m0s (g x m1t)
+            const CV3 gxm1t = ccross_cv(g, m1t);
+            cadd(Vt, CV3{-m0s * gxm1t.x, -m0s * gxm1t.y, -m0s * gxm1t.z});
+            cadd(U, CV3{m00 * g.x, m00 * g.y, m00 * g.z});
+        }
+    }
+    // k^-2
+    const c128 k2 = k * k;
+    const c128 ik2 = cdiv(c128(1.0), k2);
+    const double *ct = a.tri_coef + tl * 12;
+    const double *cs = a.tri_coef + sl * 12;
+    c128 *out = a.blocks + p * 18;
+    for (int e = 0; e < 3; ++e) {
+        const double ce = ct[4 * e];
+        const V3 qe = {ct[4 * e + 1], ct[4 * e + 2], ct[4 * e + 3]};
+        const V3 pe = pt[e];
+        for (int f = 0; f < 3; ++f) {
+            const double cf = cs[4 * f];
+            const V3 qf = {cs[4 * f + 1], cs[4 * f + 2], cs[4 * f + 3]};
+            const V3 pf = ps[f];
+            const double cc = ce * cf;
+            const c128 Ad = cc * (aRV - cdot(pf, aSR) - cdot(pe, aV) + dot(pe, pf) * aS);
+            const c128 Pd = (4.0 * cc) * aS;
+            const c128 Kd = cc * (cdot(pf - pe, aGR) + cdot(cross(pf, pe), aG));
+            const c128 Ag = cc * (S11 - cdot(qf, S10) - cdot(qe, S01) + dot(qe, qf) * S00);
+            const c128 Pg = (4.0 * cc) * S00;
+            const c128 Kg = cc * (C11 - cdot(qe, Vs) - cdot(qf, Vt) + cdot(cross(qf, qe), U));
+            out[e * 3 + f] = (Ad - Ag) - ik2 * (Pd - Pg);
+            out[9 + e * 3 + f] = Kd - Kg;
+        }
+    }
+}
+
+void launch_near_fill(const NearFillArgs &a, int64_t npairs, hipStream_t st) {
+    if (!npairs) return;
+    hipLaunchKernelGGL(k_near_fill, dim3((unsigned)((npairs + 127) / 128)), dim3(128), 0, st, a);
+    SIE_HIP(hipGetLastError());
+}
+
+// Deterministic CSR assembly: entry (m, n) sums the blocks of the (at most 4)
+// near triangle pairs (T+-(m), T+-(n)).
+__device__ inline int64_t find_pair(const int64_t *pair_ptr, const int32_t *pair_s, int64_t tl, int32_t sl) {
+    int64_t lo = pair_ptr[tl], hi = pair_ptr[tl + 1];
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        const int32_t v = pair_s[mid];
+        if (v == sl) return mid;
+        if (v < sl) lo = mid + 1; else hi = mid;
+    }
+    return -1;
+}
+
+__global__ void k_near_gather(int64_t nrow, int64_t rwg0, const int64_t *__restrict__ row_ptr,
+                              const int32_t *__restrict__ cols, const int32_t *__restrict__ rwg_loc,
+                              const int32_t *__restrict__ glob2loc, const int32_t *__restrict__ tpm,
+                              const int32_t *__restrict__ epm, const int64_t *__restrict__ pair_ptr,
+                              const int32_t *__restrict__ pair_s, const c128 *__restrict__ blocks,
+                              c128 *__restrict__ nL64, c128 *__restrict__ nK64, c64 *__restrict__ nL32,
+                              c64 *__restrict__ nK32) {
+    const int64_t r = blockIdx.y;
+    if (r >= nrow) return;
+    const int64_t j = row_ptr[r] + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= row_ptr[r + 1]) return;
+    const int32_t n = cols[j];
+    c128 L, K;
+    for (int sa = 0; sa < 2; ++sa) {
+        const int32_t lc = rwg_loc[2 * r + sa];
+        const int64_t tl = lc >> 2;
+        const int ea = lc & 3;
+        for (int sb = 0; sb < 2; ++sb) {
+            const int32_t sl = glob2loc[tpm[2 * (int64_t)n + sb]];
+            if (sl < 0) continue;
+            const int eb = epm[2 * (int64_t)n + sb];
+            const int64_t q = find_pair(pair_ptr, pair_s, tl, sl);
+            if (q < 0) continue;
+            L += blocks[q * 18 + ea * 3 + eb];
+            K += blocks[q * 18 + 9 + ea * 3 + eb];
+        }
+    }
+    // row-triangle chunks are processed one after the other: accumulate
+    nL64[j] += L;
+    nK64[j] += K;
+}
+
+void launch_near_gather(int64_t nrow, int64_t rwg0, int64_t max_row, const int64_t *row_ptr, const int32_t *cols,
+                         const int32_t *rwg_loc, const int32_t *glob2loc, const int32_t *tpm, const int32_t *epm,
+                         const int64_t *pair_ptr, const int32_t *pair_s, const c128 *blocks, c128 *nL64,
+                         c128 *nK64, c64 *nL32, c64 *nK32, hipStream_t st) {
+    if (!nrow || !max_row) return;
+    SIE_CHECK(nrow < 65536LL * 1024, SIE_EINVAL, "too many rows");
+    for (int64_t r0 = 0; r0 < nrow; r0 += 65535) {
+        const int64_t nr = std::min<int64_t>(65535, nrow - r0);
+        dim3 grid((unsigned)((max_row + 255) / 256), (unsigned)nr);
+        hipLaunchKernelGGL(k_near_gather, grid, dim3(256), 0, st, nr, rwg0, row_ptr + r0, cols,
+                           rwg_loc + 2 * r0, glob2loc, tpm, epm, pair_ptr, pair_s, blocks, nL64, nK64, nL32, nK32);
+        SIE_HIP(hipGetLastError());
+    }
+}
+
+// ----------------------------------------------------------------- Green's function tables
+__device__ inline void green_at(c128 k, double h, int dx, int dy, int dz, c128 out[4]) {
+    const double rx = h * dx, ry = h * dy, rz = h * dz;
+    const double r = sqrt(rx * rx + ry * ry + rz * rz);
+    if (r == 0.0) { out[0] = out[1] = out[2] = out[3] = c128(); return; }
+    const double inv4pi = 0.07957747154594767;
+    const c128 e = cexp_mjk(k, r);
+    out[0] = (inv4pi / r) * e;
+    // grad_r G = r_vec * ( -(1 + j k r) exp(-j k r) / (4 pi r^3) )
+    const c128 onejkr(1.0 - k.im * r, k.re * r);
+    const c128 s = (-inv4pi / (r * r * r)) * (onejkr * e);
+    out[1] = rx * s; out[2] = ry * s; out[3] = rz * s;
+}
+
+__global__ void k_green_table(c128 k, double h, int W, c128 *tab) {
+    const int D = 2 * W + 1;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= (int64_t)D * D * D) return;
+    const int dx = (int)(i % D) - W, dy = (int)((i / D) % D) - W, dz = (int)(i / ((int64_t)D * D)) - W;
+    c128 g[4];
+    green_at(k, h, dx, dy, dz, g);
+    for (int c = 0; c < 4; ++c) tab[4 * i + c] = g[c];
+}
+
+void launch_green_table(c128 k, double h, int W, c128 *tab, hipStream_t st) {
+    const int64_t n = (int64_t)(2 * W + 1) * (2 * W + 1) * (2 * W + 1);
+    hipLaunchKernelGGL(k_green_table, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, k, h, W, tab);
+    SIE_HIP(hipGetLastError());
+}
+
+// Circulant embedding of G (kind 0) or dG/dx_(kind-1) on [mz][my][mx]:
+// index i maps to offset i (i < nl) or i - m (i > m - nl); other indices 0.
+__global__ void k_green_sample(c128 k, double h, int nlx, int nly, int nlz, int mx, int my, int mz, int kind,
+                               c128 *vol) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= (int64_t)mx * my * mz) return;
+    const int ix = (int)(i % mx), iy = (int)((i / mx) % my), iz = (int)(i / ((int64_t)mx * my));
+    auto off = [](int idx, int nl, int m, bool &ok) {
+        if (idx < nl) { ok = true; return idx; }
+        if (idx > m - nl) { ok = true; return idx - m; }
+        ok = false; return 0;
+    };
+    bool okx, oky, okz;
+    const int dx = off(ix, nlx, mx, okx), dy = off(iy, nly, my, oky), dz = off(iz, nlz, mz, okz);
+    c128 g[4];
+    if (okx && oky && okz) green_at(k, h, dx, dy, dz, g);
+    else g[0] = g[1] = g[2] = g[3] = c128();
+    vol[i] = g[kind];
+}
+
+void launch_green_sample(c128 k, double h, const int nl[3], const int m[3], int kind, c128 *vol, hipStream_t st) {
+    const int64_t n = (int64_t)m[0] * m[1] * m[2];
+    hipLaunchKernelGGL(k_green_sample, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, k, h, nl[0], nl[1], nl[2],
+                       m[0], m[1], m[2], kind, vol);
+    SIE_HIP(hipGetLastError());
+}
+
+__global__ void k_fold_octant(const c128 *vol, int mx, int my, int mz, double scale, c128 *s64, c64 *s32) {
+    const int ox = mx / 2 + 1, oy = my / 2 + 1, oz = mz / 2 + 1;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= (int64_t)ox * oy * oz) return;
+    const int fx = (int)(i % ox), fy = (int)((i / ox) % oy), fz = (int)(i / ((int64_t)ox * oy));
+    const c128 v = scale * vol[((int64_t)fz * my + fy) * mx + fx];
+    s64[i] = v;
+    s32[i] = c64((float)v.re, (float)v.im);
+}
+
+void launch_fold_octant(const c128 *vol, const int m[3], int kind, double scale, c128 *spec64, c64 *spec32,
+                        hipStream_t st) {
+    const int64_t oct = (int64_t)(m[0] / 2 + 1) * (m[1] / 2 + 1) * (m[2] / 2 + 1);
+    hipLaunchKernelGGL(k_fold_octant, dim3((unsigned)((oct + 255) / 256)), dim3(256), 0, st, vol, m[0], m[1], m[2],
+                       scale, spec64 + kind * oct, spec32 + kind * oct);
+    SIE_HIP(hipGetLastError());
+}
+
+}  // namespace sie

@@ -1,0 +1,67 @@
+// Launchers of the HIP kernels (definitions in k_*.hip).
+#pragma once
+#include "common.h"
+
+namespace sie {
+
+// ---- k_fft.hip
+template <typename T>
+void fft_convolve(const Grid &g, const cx<T> *spec, int nf, int mode, const cx<T> *in, cx<T> *out,
+                  cx<T> *bufA, cx<T> *bufB, hipStream_t st);
+void fft3d_full_fwd(c128 *vol, c128 *tmp, int mx, int my, int mz, hipStream_t st);
+
+// ---- k_grid.hip
+void launch_stencil_assign(const double *centroids, const int32_t *tris, int64_t ntg, const double origin[3],
+                           double h, const int n[3], int32_t *centre_out, int32_t *raw_out, hipStream_t st);
+void launch_moments(const double *xyz, const int32_t *tri, const int32_t *tris, const int32_t *centre,
+                    int64_t ntg, const double origin[3], double h, const double *rule, int nq,
+                    double *mom64, float *mom32, hipStream_t st);
+template <typename T>
+void launch_tri_sources(const Grid &g, const int32_t *tri_rwg_loc, const T *tri_coef, const cx<T> *x,
+                        cx<T> *trisrc, hipStream_t st);
+template <typename T>
+void launch_project(const Grid &g, const T *mom, const cx<T> *trisrc, cx<T> *grid, int nfields, hipStream_t st);
+template <typename T>
+void launch_interp(const Grid &g, const T *mom, const cx<T> *pot, int nfields, cx<T> *tripot, hipStream_t st);
+// y[r] = sum_j N[r,j] x[j] + sum over the row's triangles of the far part,
+// for rows r in [rwg0, rwg1); rows outside are zeroed.  kscal = -2 k^-2
+// (scalar part weight; 0 for K-type).  N may be null (far part only).
+template <typename T>
+void launch_spmv_far(const Grid &g, int64_t E, const int32_t *rwg_loc, const T *tri_coef,
+                     const cx<T> *tripot, cx<T> kscal, const cx<T> *vals, const cx<T> *x, cx<T> *y,
+                     bool use_far, hipStream_t st);
+template <typename T>
+void launch_x_apply(int64_t E, const int32_t *xptr, const int32_t *xcol, const T *xval, const cx<T> *x,
+                    cx<T> *y, hipStream_t st);
+
+// ---- k_near.hip
+void launch_near_count(const int32_t *centre, int64_t ntg, const int32_t *cell_ptr, const int32_t *cell_tri,
+                       const int lo[3], const int nl[3], int R, int64_t *count, hipStream_t st);
+void launch_near_emit(const int32_t *centre, int64_t ntg, const int32_t *cell_ptr, const int32_t *cell_tri,
+                      const int lo[3], const int nl[3], int R, const int64_t *pair_ptr, int32_t *pair_s,
+                      hipStream_t st);
+void launch_rwg_pattern(int64_t nrow, int64_t rwg0, int64_t nbits, const int32_t *rwg_loc, const int64_t *pair_ptr,
+                        const int32_t *pair_s, const int32_t *tris, const int32_t *tri_rwg, int64_t *row_len,
+                        const int64_t *row_ptr, int32_t *cols, int pass, hipStream_t st);
+
+struct NearFillArgs {
+    const double *xyz; const int32_t *tri; const int32_t *tris; const int32_t *centre;
+    const double *centroid; const double *tri_coef; const double *mom;
+    const int64_t *pair_ptr; const int32_t *pair_s; int64_t ntg;
+    const double *rules; const int *rule_off; const int *rule_n;   // packed rules
+    const c128 *gtab; int gtab_w;    // grid G / grad G table over offsets [-W, W]^3, 4 comps
+    c128 k; double h; int kind_lo, kind_hi;
+    c128 *blocks;                    // [npairs][2][3][3]: L then K
+};
+void launch_near_fill(const NearFillArgs &a, int64_t npairs, hipStream_t st);
+void launch_near_gather(int64_t nrow, int64_t rwg0, int64_t max_row, const int64_t *row_ptr, const int32_t *cols,
+                        const int32_t *rwg_loc, const int32_t *glob2loc, const int32_t *tpm, const int32_t *epm,
+                        const int64_t *pair_ptr, const int32_t *pair_s, const c128 *blocks, c128 *nL64,
+                        c128 *nK64, c64 *nL32, c64 *nK32, hipStream_t st);
+void launch_green_table(c128 k, double h, int W, c128 *tab, hipStream_t st);
+void launch_green_sample(c128 k, double h, const int nl[3], const int m[3], int kind, c128 *vol, hipStream_t st);
+void launch_fold_octant(const c128 *vol, const int m[3], int kind, double scale, c128 *spec64, c64 *spec32,
+                        hipStream_t st);
+
+
+}  // namespace sie

@@ -1,0 +1,549 @@
+// Problem setup and the AIM operator product (Sec. III-D-1).
+//
+// Readings of what the paper leaves to its references:
+//  * grid: isotropic spacing h = (largest bounding-box extent)/(n - 3), one
+//    spare node on each side, centred on the bounding box;
+//  * stencil: 3 points per axis (order n = 2, the order of Fig. R), anchored
+//    at floor((c - x0)/h + 0.5) of the triangle centroid c, clamped to
+//    [1, n - 2];
+//  * projection: Galerkin moments of the tensor Lagrange polynomials (moment
+//    matching up to degree 2 per axis), interpolation W = P^T;
+//  * grid Green's function zero at zero offset (only near pairs see it, and
+//    they are precorrected);
+//  * near region: stencil centres within R cells per axis (R = 5: a near
+//    region 11 grid points across, Sec. IV-A);
+//  * scalar potential term subtracted (L = A - k^-2 Phi, eq. AIM_Lin with the
+//    sign carried by W_phi).
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "problem.h"
+
+namespace sie {
+
+static const double C0 = 299792458.0;
+static const double MU0 = 4e-7 * 3.14159265358979323846;
+static const double EPS0 = 1.0 / (MU0 * C0 * C0);
+
+// k = sqrt(w mu (w eps - j sigma)), principal branch (Re k >= 0, Im k <= 0) (eq. kin)
+static c128 wavenumber(double w, double eps_r, double mu_r, double sigma) {
+    const double ar = w * MU0 * mu_r * w * EPS0 * eps_r, ai = -w * MU0 * mu_r * sigma;
+    const double mod = std::sqrt(std::hypot(ar, ai));
+    const double ang = 0.5 * std::atan2(ai, ar);
+    c128 k(mod * std::cos(ang), mod * std::sin(ang));
+    if (k.re < 0) k = -k;
+    return k;
+}
+
+static int next_pow2(int v) {
+    int m = 1;
+    while (m < v) m <<= 1;
+    return m;
+}
+
+static void build_grid_geometry(sie_problem *p, Grid &g, const GridReq &req, double lambda_r) {
+    const Mesh &m = p->mesh;
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    double esum = 0;
+    int64_t ecnt = 0;
+    for (int32_t t : g.tris)
+        for (int k = 0; k < 3; ++k) {
+            const double *v = &m.xyz[3 * (int64_t)m.tri[3 * (int64_t)t + k]];
+            for (int c = 0; c < 3; ++c) { lo[c] = std::min(lo[c], v[c]); hi[c] = std::max(hi[c], v[c]); }
+            const int e = m.tri_rwg[3 * (int64_t)t + k];
+            esum += m.len[e]; ecnt++;
+        }
+    double ext = std::max(hi[0] - lo[0], std::max(hi[1] - lo[1], hi[2] - lo[2]));
+    int n = req.n;
+    if (n <= 0) {
+        // lambda_r / 20 (Sec. IV), no finer than the mean edge length
+        const double mean_edge = esum / std::max<int64_t>(ecnt, 1);
+        const double hr = std::max(lambda_r / 20.0, mean_edge);
+        const double htarget = std::min(hr, std::max(mean_edge, 1e-300));
+        n = (int)std::ceil(ext / htarget) + 3;
+        n = std::max(5, std::min(n, 256));
+    }
+    SIE_CHECK(n >= 4, SIE_EGRID, "grid needs at least 4 points per axis");
+    g.h = ext / (n - 3);
+    for (int c = 0; c < 3; ++c) {
+        g.n[c] = n;
+        g.origin[c] = 0.5 * (lo[c] + hi[c]) - g.h * (n - 1) / 2.0;
+    }
+    g.near_radius = req.R;
+}
+
+// Stencil centres, live box, local (cell-sorted) triangle order, moments,
+// projection lists, near pairs and the RWG near pattern of one grid.
+static void build_grid(sie_problem *p, Grid &g) {
+    const Mesh &m = p->mesh;
+    const int64_t ntg = (int64_t)g.tris.size();
+    SIE_CHECK(ntg > 0, SIE_EINVAL, "grid without triangles");
+    // 1. stencil assignment (ascending global order)
+    {
+        DBuf<int32_t> d_t(ntg), d_c(3 * ntg), d_raw(3 * ntg);
+        d_t.upload(g.tris);
+        launch_stencil_assign(p->d_centroid.p, d_t.p, ntg, g.origin, g.h, g.n, d_c.p, d_raw.p, 0);
+        std::vector<int32_t> c = d_c.download(), raw = d_raw.download();
+        for (int64_t i = 0; i < 3 * ntg; ++i)
+            SIE_CHECK(raw[i] >= 0 && raw[i] <= g.n[i % 3] - 1, SIE_EGRID, "triangle outside its grid");
+        // 2. live box
+        int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-1, -1, -1};
+        for (int64_t i = 0; i < ntg; ++i)
+            for (int k = 0; k < 3; ++k) { lo[k] = std::min(lo[k], c[3 * i + k]); hi[k] = std::max(hi[k], c[3 * i + k]); }
+        for (int k = 0; k < 3; ++k) {
+            g.lo[k] = lo[k] - 1;
+            g.nl[k] = hi[k] - lo[k] + 3;
+            g.m[k] = std::max(2, next_pow2(2 * g.nl[k] - 1));
+        }
+        // 3. local order: sorted by live-box cell (z, y, x), then global id
+        std::vector<int64_t> key(ntg);
+        for (int64_t i = 0; i < ntg; ++i)
+            key[i] = ((int64_t)(c[3 * i + 2] - g.lo[2]) * g.nl[1] + (c[3 * i + 1] - g.lo[1])) * g.nl[0] +
+                     (c[3 * i] - g.lo[0]);
+        std::vector<int64_t> ord(ntg);
+        std::iota(ord.begin(), ord.end(), 0);
+        std::stable_sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) { return key[a] < key[b]; });
+        std::vector<int32_t> tris2(ntg), c2(3 * ntg);
+        for (int64_t i = 0; i < ntg; ++i) {
+            tris2[i] = g.tris[ord[i]];
+            for (int k = 0; k < 3; ++k) c2[3 * i + k] = c[3 * ord[i] + k];
+        }
+        g.tris = tris2;
+        g.centre = c2;
+        g.d_tris.upload(g.tris);
+        g.d_centre.upload(g.centre);
+        // cell_ptr over live cells for the near search
+        const int64_t nlive = g.nlive();
+        std::vector<int32_t> cell_ptr(nlive + 1, 0);
+        for (int64_t i = 0; i < ntg; ++i) cell_ptr[key[ord[i]] + 1]++;
+        for (int64_t v = 0; v < nlive; ++v) cell_ptr[v + 1] += cell_ptr[v];
+        // 4. near pairs
+        DBuf<int32_t> d_cell(nlive + 1);
+        d_cell.upload(cell_ptr);
+        DBuf<int64_t> d_cnt(ntg);
+        launch_near_count(g.d_centre.p, ntg, d_cell.p, nullptr, g.lo, g.nl, g.near_radius, d_cnt.p, 0);
+        std::vector<int64_t> cnt = d_cnt.download();
+        std::vector<int64_t> pptr(ntg + 1, 0);
+        for (int64_t i = 0; i < ntg; ++i) pptr[i + 1] = pptr[i] + cnt[i];
+        g.npairs = pptr[ntg];
+        g.d_pair_ptr.upload(pptr);
+        g.d_pair_s.alloc(std::max<int64_t>(g.npairs, 1));
+        launch_near_emit(g.d_centre.p, ntg, d_cell.p, nullptr, g.lo, g.nl, g.near_radius, g.d_pair_ptr.p,
+                         g.d_pair_s.p, 0);
+    }
+    // 5. per-triangle coefficients and maps
+    g.glob2loc.assign(m.nt(), -1);
+    for (int64_t i = 0; i < ntg; ++i) g.glob2loc[g.tris[i]] = (int32_t)i;
+    g.d_glob2loc.upload(g.glob2loc);
+    g.tri_coef.assign(12 * ntg, 0.0);
+    std::vector<float> coef32(12 * ntg);
+    std::vector<int32_t> trirwg(3 * ntg);
+    for (int64_t i = 0; i < ntg; ++i) {
+        const int64_t t = g.tris[i];
+        const double rc[3] = {g.origin[0] + g.h * g.centre[3 * i], g.origin[1] + g.h * g.centre[3 * i + 1],
+                              g.origin[2] + g.h * g.centre[3 * i + 2]};
+        for (int e = 0; e < 3; ++e) {
+            const int32_t n = m.tri_rwg[3 * t + e];
+            trirwg[3 * i + e] = n;
+            const double ce = m.tri_sign[3 * t + e] * m.len[n] / (2.0 * m.area[t]);
+            const double *pv = &m.xyz[3 * (int64_t)m.tri[3 * t + e]];
+            double *o = &g.tri_coef[12 * i + 4 * e];
+            o[0] = ce;
+            for (int c = 0; c < 3; ++c) o[1 + c] = pv[c] - rc[c];
+        }
+    }
+    for (int64_t i = 0; i < 12 * ntg; ++i) coef32[i] = (float)g.tri_coef[i];
+    g.d_tri64.upload(g.tri_coef);
+    g.d_tri32.upload(coef32);
+    g.d_trirwg.upload(trirwg);
+    // RWG rows of the grid's objects
+    g.rwg0 = m.obj_rwg0[*std::min_element(g.objs.begin(), g.objs.end())];
+    g.rwg1 = m.obj_rwg0[*std::max_element(g.objs.begin(), g.objs.end()) + 1];
+    const int64_t nrow = g.rwg1 - g.rwg0;
+    std::vector<int32_t> rwgloc(2 * nrow);
+    for (int64_t r = 0; r < nrow; ++r) {
+        const int64_t n = g.rwg0 + r;
+        for (int s = 0; s < 2; ++s) {
+            const int32_t tl = g.glob2loc[m.tpm[2 * n + s]];
+            SIE_CHECK(tl >= 0, SIE_EINVAL, "RWG triangle not on its grid");
+            rwgloc[2 * r + s] = (tl << 2) | m.epm[2 * n + s];
+        }
+    }
+    g.d_rwgloc.upload(rwgloc);
+    // 6. moments
+    {
+        Rule r = rule_collapsed(5);   // exact to degree 8 (integrands of degree 7)
+        std::vector<double> packed(4 * r.size());
+        for (int q = 0; q < r.size(); ++q) {
+            for (int c = 0; c < 3; ++c) packed[4 * q + c] = r.bary[3 * q + c];
+            packed[4 * q + 3] = r.w[q];
+        }
+        DBuf<double> d_rule;
+        d_rule.upload(packed);
+        g.d_mom64.alloc(27 * 4 * ntg);
+        g.d_mom32.alloc(27 * 4 * ntg);
+        launch_moments(p->d_xyz.p, p->d_tri.p, g.d_tris.p, g.d_centre.p, ntg, g.origin, g.h, d_rule.p, r.size(),
+                       g.d_mom64.p, g.d_mom32.p, 0);
+        SIE_HIP(hipDeviceSynchronize());
+    }
+    // 7. projection gather lists: node -> (local triangle, slot)
+    {
+        const int64_t nlive = g.nlive();
+        std::vector<int32_t> nptr(nlive + 1, 0), ent(27 * ntg);
+        auto node_of = [&](int64_t i, int a) {
+            const int dx = a % 3 - 1, dy = (a / 3) % 3 - 1, dz = a / 9 - 1;
+            return ((int64_t)(g.centre[3 * i + 2] + dz - g.lo[2]) * g.nl[1] + (g.centre[3 * i + 1] + dy - g.lo[1])) *
+                       g.nl[0] + (g.centre[3 * i] + dx - g.lo[0]);
+        };
+        for (int64_t i = 0; i < ntg; ++i)
+            for (int a = 0; a < 27; ++a) nptr[node_of(i, a) + 1]++;
+        for (int64_t v = 0; v < nlive; ++v) nptr[v + 1] += nptr[v];
+        std::vector<int32_t> fill(nptr.begin(), nptr.end() - 1);
+        for (int64_t i = 0; i < ntg; ++i)
+            for (int a = 0; a < 27; ++a) ent[fill[node_of(i, a)]++] = (int32_t)((i << 5) | a);
+        g.d_node_ptr.upload(nptr);
+        g.d_node_ent.upload(ent);
+    }
+    // 8. RWG near pattern
+    {
+        DBuf<int64_t> d_len(nrow), d_rp(nrow + 1);
+        launch_rwg_pattern(nrow, g.rwg0, nrow, g.d_rwgloc.p, g.d_pair_ptr.p, g.d_pair_s.p, g.d_tris.p,
+                           p->d_tri_rwg.p, d_len.p, nullptr, nullptr, 0, 0);
+        std::vector<int64_t> len = d_len.download();
+        std::vector<int64_t> rp(nrow + 1, 0);
+        g.max_row = 0;
+        for (int64_t r = 0; r < nrow; ++r) { rp[r + 1] = rp[r] + len[r]; g.max_row = std::max(g.max_row, len[r]); }
+        g.nnz = rp[nrow];
+        g.d_row_ptr.upload(rp);
+        g.d_cols.alloc(std::max<int64_t>(g.nnz, 1));
+        launch_rwg_pattern(nrow, g.rwg0, nrow, g.d_rwgloc.p, g.d_pair_ptr.p, g.d_pair_s.p, g.d_tris.p,
+                           p->d_tri_rwg.p, nullptr, g.d_row_ptr.p, g.d_cols.p, 1, 0);
+        SIE_HIP(hipDeviceSynchronize());
+    }
+}
+
+static std::vector<double> pack_rule(const Rule &r) {
+    std::vector<double> v(4 * r.size());
+    for (int q = 0; q < r.size(); ++q) {
+        for (int c = 0; c < 3; ++c) v[4 * q + c] = r.bary[3 * q + c];
+        v[4 * q + 3] = r.w[q];
+    }
+    return v;
+}
+
+// Precorrected near values and Green's spectra of one medium on its grid.
+static void build_medium(sie_problem *p, Medium &md) {
+    Grid &g = *md.grid;
+    const int64_t ntg = (int64_t)g.tris.size();
+    // rules: 0 self, 1..3 edge, 4..6 vertex, 7 close, 8 far, 9 touch inner, 10 close inner, 11 far inner
+    const sie_quad_params &q = p->quad;
+    std::vector<Rule> rules;
+    rules.push_back(rule_self(q.touch_out));
+    for (int i = 0; i < 3; ++i) rules.push_back(rule_edge(q.touch_out, i));
+    for (int i = 0; i < 3; ++i) rules.push_back(rule_vertex(q.touch_out, i));
+    rules.push_back(rule_collapsed(q.close_out));
+    rules.push_back(rule_collapsed(q.far_out));
+    rules.push_back(rule_collapsed(q.touch_in));
+    rules.push_back(rule_collapsed(q.close_in));
+    rules.push_back(rule_collapsed(q.far_in));
+    std::vector<double> packed;
+    std::vector<int> off, num;
+    for (auto &r : rules) {
+        off.push_back((int)(packed.size() / 4));
+        num.push_back(r.size());
+        auto v = pack_rule(r);
+        packed.insert(packed.end(), v.begin(), v.end());
+    }
+    DBuf<double> d_rules; d_rules.upload(packed);
+    DBuf<int> d_off; d_off.upload(off);
+    DBuf<int> d_num; d_num.upload(num);
+    const int W = g.near_radius + 2;
+    const int64_t D = 2 * W + 1;
+    DBuf<c128> d_gtab(4 * D * D * D);
+    launch_green_table(md.k, g.h, W, d_gtab.p, 0);
+
+    md.d_nL64.alloc(std::max<int64_t>(g.nnz, 1));
+    md.d_nK64.alloc(std::max<int64_t>(g.nnz, 1));
+    SIE_HIP(hipMemset(md.d_nL64.p, 0, md.d_nL64.bytes()));
+    SIE_HIP(hipMemset(md.d_nK64.p, 0, md.d_nK64.bytes()));
+    // process row triangles in chunks to bound the pair-block buffer
+    std::vector<int64_t> pptr = g.d_pair_ptr.download();
+    const int64_t max_chunk = 12000000;
+    DBuf<c128> blocks;
+    DBuf<int64_t> d_pp;
+    DBuf<int32_t> d_rwgloc_chunk;
+    const int64_t nrow = g.rwg1 - g.rwg0;
+    std::vector<int32_t> rwgloc = g.d_rwgloc.download();
+    int64_t t0 = 0;
+    while (t0 < ntg) {
+        int64_t t1 = t0 + 1;
+        while (t1 < ntg && pptr[t1 + 1] - pptr[t0] <= max_chunk) ++t1;
+        const int64_t np = pptr[t1] - pptr[t0];
+        // chunk-relative pair pointers over all rows (rows outside the chunk empty)
+        std::vector<int64_t> cp(ntg + 1);
+        for (int64_t i = 0; i <= ntg; ++i) cp[i] = std::min(std::max(pptr[i], pptr[t0]), pptr[t1]) - pptr[t0];
+        d_pp.upload(cp);
+        blocks.alloc(std::max<int64_t>(np, 1) * 18);
+        NearFillArgs a;
+        a.xyz = p->d_xyz.p; a.tri = p->d_tri.p; a.tris = g.d_tris.p; a.centre = g.d_centre.p;
+        a.centroid = p->d_centroid.p; a.tri_coef = g.d_tri64.p; a.mom = g.d_mom64.p;
+        a.pair_ptr = d_pp.p; a.pair_s = g.d_pair_s.p + pptr[t0]; a.ntg = ntg;
+        a.rules = d_rules.p; a.rule_off = d_off.p; a.rule_n = d_num.p;
+        a.gtab = d_gtab.p; a.gtab_w = W; a.k = md.k; a.h = g.h;
+        a.blocks = blocks.p;
+        for (auto kr : {std::pair<int, int>{0, 2}, {3, 3}, {4, 4}}) {
+            a.kind_lo = kr.first; a.kind_hi = kr.second;
+            launch_near_fill(a, np, 0);
+        }
+        launch_near_gather(nrow, g.rwg0, g.max_row, g.d_row_ptr.p, g.d_cols.p, g.d_rwgloc.p, g.d_glob2loc.p,
+                           p->d_tpm.p, p->d_epm.p, d_pp.p, g.d_pair_s.p + pptr[t0], blocks.p, md.d_nL64.p,
+                           md.d_nK64.p, nullptr, nullptr, 0);
+        SIE_HIP(hipDeviceSynchronize());
+        t0 = t1;
+    }
+    md.d_nL32.alloc(std::max<int64_t>(g.nnz, 1));
+    md.d_nK32.alloc(std::max<int64_t>(g.nnz, 1));
+    launch_convert<double, float>(md.d_nL64.p, md.d_nL32.p, g.nnz, 0);
+    launch_convert<double, float>(md.d_nK64.p, md.d_nK32.p, g.nnz, 0);
+    // spectra of G, dG/dx, dG/dy, dG/dz, folded to the octant, 1/(mx my mz) folded in
+    const int64_t vol = g.mvol();
+    DBuf<c128> d_vol(vol), d_tmp(vol);
+    md.d_spec64.alloc(4 * g.oct());
+    md.d_spec32.alloc(4 * g.oct());
+    const double scale = 1.0 / (double)vol;
+    for (int kind = 0; kind < 4; ++kind) {
+        launch_green_sample(md.k, g.h, g.nl, g.m, kind, d_vol.p, 0);
+        fft3d_full_fwd(d_vol.p, d_tmp.p, g.m[0], g.m[1], g.m[2], 0);
+        launch_fold_octant(d_vol.p, g.m, kind, scale, md.d_spec64.p, md.d_spec32.p, 0);
+    }
+    SIE_HIP(hipDeviceSynchronize());
+}
+
+static void build_x(sie_problem *p) {
+    const Mesh &m = p->mesh;
+    const int64_t E = m.nrwg;
+    std::vector<std::vector<std::pair<int32_t, double>>> rows(E);
+    for (int64_t t = 0; t < m.nt(); ++t) {
+        const double *nn = &m.normal[3 * t];
+        const double *c = &m.centroid[3 * t];
+        double pr[3][3], ce[3];
+        for (int e = 0; e < 3; ++e) {
+            const double *pv = &m.xyz[3 * (int64_t)m.tri[3 * t + e]];
+            for (int k = 0; k < 3; ++k) pr[e][k] = pv[k] - c[k];
+            ce[e] = m.tri_sign[3 * t + e] * m.len[m.tri_rwg[3 * t + e]] / (2.0 * m.area[t]);
+        }
+        // int_t (n x f_e) . f_f dS = c_e c_f A n . (p_e' x p_f'), p' = p - centroid
+        for (int e = 0; e < 3; ++e)
+            for (int f = 0; f < 3; ++f) {
+                const double cx_ = pr[e][1] * pr[f][2] - pr[e][2] * pr[f][1];
+                const double cy = pr[e][2] * pr[f][0] - pr[e][0] * pr[f][2];
+                const double cz = pr[e][0] * pr[f][1] - pr[e][1] * pr[f][0];
+                const double v = ce[e] * ce[f] * m.area[t] * (nn[0] * cx_ + nn[1] * cy + nn[2] * cz);
+                const int32_t a = m.tri_rwg[3 * t + e], b = m.tri_rwg[3 * t + f];
+                bool found = false;
+                for (auto &pr2 : rows[a])
+                    if (pr2.first == b) { pr2.second += v; found = true; }
+                if (!found) rows[a].push_back({b, v});
+            }
+    }
+    std::vector<int32_t> ptr(E + 1, 0), col;
+    std::vector<double> val;
+    for (int64_t r = 0; r < E; ++r) {
+        std::sort(rows[r].begin(), rows[r].end());
+        for (auto &e : rows[r]) { col.push_back(e.first); val.push_back(e.second); }
+        ptr[r + 1] = (int32_t)col.size();
+    }
+    std::vector<float> val32(val.begin(), val.end());
+    p->d_xptr.upload(ptr);
+    p->d_xcol.upload(col);
+    p->d_xval64.upload(val);
+    p->d_xval32.upload(val32);
+}
+
+template <typename T>
+static void ensure_work(Grid &g, Work<T> &w) {
+    if (w.grid.n) return;
+    const int F = 4;
+    w.grid.alloc(F * g.nlive());
+    w.bufA.alloc((size_t)F * g.nl[2] * g.nl[1] * g.m[0]);
+    w.bufB.alloc((size_t)F * g.nl[2] * g.m[1] * g.m[0]);
+    w.trisrc.alloc(4 * g.tris.size());
+    w.tripot.alloc(5 * g.tris.size());
+}
+
+template <> Work<double> &work_of<double>(Grid &g) { ensure_work(g, g.w64); return g.w64; }
+template <> Work<float> &work_of<float>(Grid &g) { ensure_work(g, g.w32); return g.w32; }
+
+template <typename T> static const T *mom_of(Grid &g);
+template <> const double *mom_of<double>(Grid &g) { return g.d_mom64.p; }
+template <> const float *mom_of<float>(Grid &g) { return g.d_mom32.p; }
+template <typename T> static const T *coef_of(Grid &g);
+template <> const double *coef_of<double>(Grid &g) { return g.d_tri64.p; }
+template <> const float *coef_of<float>(Grid &g) { return g.d_tri32.p; }
+template <typename T> static const cx<T> *spec_of(Medium &m);
+template <> const c128 *spec_of<double>(Medium &m) { return m.d_spec64.p; }
+template <> const c64 *spec_of<float>(Medium &m) { return m.d_spec32.p; }
+template <typename T> static const cx<T> *near_of(Medium &m, sie_op op);
+template <> const c128 *near_of<double>(Medium &m, sie_op op) { return op == SIE_OP_L ? m.d_nL64.p : m.d_nK64.p; }
+template <> const c64 *near_of<float>(Medium &m, sie_op op) { return op == SIE_OP_L ? m.d_nL32.p : m.d_nK32.p; }
+template <typename T> static const T *xval_of(sie_problem *p);
+template <> const double *xval_of<double>(sie_problem *p) { return p->d_xval64.p; }
+template <> const float *xval_of<float>(sie_problem *p) { return p->d_xval32.p; }
+
+template <typename T>
+void matvec(sie_problem *p, Medium &md, sie_op op, int nrhs, const cx<T> *x, cx<T> *y, hipStream_t st) {
+    const int64_t E = p->mesh.nrwg;
+    if (op == SIE_OP_X) {
+        for (int r = 0; r < nrhs; ++r)
+            launch_x_apply<T>(E, p->d_xptr.p, p->d_xcol.p, xval_of<T>(p), x + r * E, y + r * E, st);
+        return;
+    }
+    Grid &g = *md.grid;
+    Work<T> &w = work_of<T>(g);
+    const int F = op == SIE_OP_L ? 4 : 3;
+    const c128 k2 = md.k * md.k;
+    const c128 ks = op == SIE_OP_L ? cdiv(c128(-2.0), k2) : c128();
+    const cx<T> kscal((T)ks.re, (T)ks.im);
+    for (int r = 0; r < nrhs; ++r) {
+        launch_tri_sources<T>(g, g.d_trirwg.p, coef_of<T>(g), x + r * E, w.trisrc.p, st);
+        launch_project<T>(g, mom_of<T>(g), w.trisrc.p, w.grid.p, F, st);
+        fft_convolve<T>(g, spec_of<T>(md), F, op == SIE_OP_L ? 0 : 1, w.grid.p, w.grid.p, w.bufA.p, w.bufB.p, st);
+        launch_interp<T>(g, mom_of<T>(g), w.grid.p, F, w.tripot.p, st);
+        launch_spmv_far<T>(g, E, g.d_rwgloc.p, coef_of<T>(g), w.tripot.p, kscal, near_of<T>(md, op), x + r * E,
+                           y + r * E, true, st);
+    }
+}
+
+template <typename T>
+void stage_project(sie_problem *p, Medium &md, const cx<T> *x, cx<T> *grid, hipStream_t st) {
+    Grid &g = *md.grid;
+    Work<T> &w = work_of<T>(g);
+    launch_tri_sources<T>(g, g.d_trirwg.p, coef_of<T>(g), x, w.trisrc.p, st);
+    launch_project<T>(g, mom_of<T>(g), w.trisrc.p, grid, 4, st);
+}
+
+template <typename T>
+void stage_convolve(sie_problem *p, Medium &md, int nf, const cx<T> *in, cx<T> *out, hipStream_t st) {
+    Grid &g = *md.grid;
+    Work<T> &w = work_of<T>(g);
+    SIE_CHECK(nf >= 1 && nf <= 4, SIE_EINVAL, "nfields must be 1..4");
+    fft_convolve<T>(g, spec_of<T>(md), nf, 0, in, out, w.bufA.p, w.bufB.p, st);
+}
+
+template <typename T>
+void stage_interpolate(sie_problem *p, Medium &md, const cx<T> *grid, cx<T> *y, hipStream_t st) {
+    Grid &g = *md.grid;
+    Work<T> &w = work_of<T>(g);
+    const c128 ks = cdiv(c128(-2.0), md.k * md.k);
+    launch_interp<T>(g, mom_of<T>(g), grid, 4, w.tripot.p, st);
+    launch_spmv_far<T>(g, p->mesh.nrwg, g.d_rwgloc.p, coef_of<T>(g), w.tripot.p, cx<T>((T)ks.re, (T)ks.im),
+                       (const cx<T> *)nullptr, (const cx<T> *)nullptr, y, true, st);
+}
+
+#define SIE_INST_MV(T)                                                                                     \
+    template void matvec<T>(sie_problem *, Medium &, sie_op, int, const cx<T> *, cx<T> *, hipStream_t);    \
+    template void stage_project<T>(sie_problem *, Medium &, const cx<T> *, cx<T> *, hipStream_t);          \
+    template void stage_convolve<T>(sie_problem *, Medium &, int, const cx<T> *, cx<T> *, hipStream_t);    \
+    template void stage_interpolate<T>(sie_problem *, Medium &, const cx<T> *, cx<T> *, hipStream_t);
+SIE_INST_MV(float)
+SIE_INST_MV(double)
+
+void problem_setup(sie_problem *p) {
+    SIE_CHECK(!p->objs.empty(), SIE_ESTATE, "no objects");
+    SIE_HIP(hipSetDevice(p->ctx->device));
+    Mesh &m = p->mesh;
+    m = Mesh();
+    for (size_t i = 0; i < p->objs.size(); ++i) {
+        const ObjIn &o = p->objs[i];
+        const int32_t off = (int32_t)m.nv();
+        m.xyz.insert(m.xyz.end(), o.xyz.begin(), o.xyz.end());
+        for (int32_t v : o.tri) m.tri.push_back(v + off);
+        for (size_t t = 0; t < o.tri.size() / 3; ++t) m.tri_obj.push_back((int32_t)i);
+        for (int32_t v : o.tri) SIE_CHECK(v >= 0 && v < (int32_t)(o.xyz.size() / 3), SIE_EMESH, "vertex index out of range");
+    }
+    m.nobj = (int)p->objs.size();
+    build_topology(m);
+    // quadrature defaults
+    sie_quad_params &q = p->quad;
+    if (q.touch_out <= 0) q.touch_out = 6;
+    if (q.touch_in <= 0) q.touch_in = 6;
+    if (q.close_out <= 0) q.close_out = 5;
+    if (q.close_in <= 0) q.close_in = 5;
+    if (q.far_out <= 0) q.far_out = 4;
+    if (q.far_in <= 0) q.far_in = 4;
+    SIE_CHECK(q.touch_out <= 16 && q.touch_in <= 16 && q.close_out <= 16 && q.close_in <= 16 && q.far_out <= 16 &&
+                  q.far_in <= 16, SIE_EINVAL, "quadrature order above 16");
+    // device mesh arrays
+    p->d_xyz.upload(m.xyz);
+    p->d_centroid.upload(m.centroid);
+    p->d_tri.upload(m.tri);
+    p->d_tri_rwg.upload(m.tri_rwg);
+    p->d_tpm.upload(m.tpm);
+    p->d_epm.upload(m.epm);
+    build_x(p);
+    // media
+    p->w = 2.0 * 3.14159265358979323846 * p->freq;
+    const double w = p->w;
+    p->ext = Medium();
+    p->ext.id = -1;
+    p->ext.k = wavenumber(w, p->bg_eps_r, p->bg_mu_r, 0.0);
+    p->ext.eps = c128(EPS0 * p->bg_eps_r);
+    p->ext.mu = c128(MU0 * p->bg_mu_r);
+    p->ints.clear();
+    p->ints.resize(m.nobj);
+    for (int i = 0; i < m.nobj; ++i) {
+        Medium &md = p->ints[i];
+        md.id = i;
+        md.k = wavenumber(w, p->objs[i].eps_r, p->objs[i].mu_r, p->objs[i].sigma);
+        md.eps = c128(EPS0 * p->objs[i].eps_r, -p->objs[i].sigma / w);
+        md.mu = c128(MU0 * p->objs[i].mu_r);
+    }
+    // grids
+    p->grids.clear();
+    const double lam0 = 2.0 * 3.14159265358979323846 / p->ext.k.re;
+    {
+        auto g = std::make_unique<Grid>();
+        for (int64_t t = 0; t < m.nt(); ++t) g->tris.push_back((int32_t)t);
+        for (int i = 0; i < m.nobj; ++i) g->objs.push_back(i);
+        build_grid_geometry(p, *g, p->ext_req, lam0);
+        build_grid(p, *g);
+        p->ext.grid = g.get();
+        p->grids.push_back(std::move(g));
+    }
+    for (int i = 0; i < m.nobj; ++i) {
+        const GridReq &rq = p->obj_req[i];
+        const bool share = rq.share == 1 || (rq.share == -1 && m.nobj == 1);
+        if (share) {
+            SIE_CHECK(m.nobj == 1, SIE_EINVAL, "interior grids can share the exterior grid only for one object");
+            p->ints[i].grid = p->ext.grid;
+            continue;
+        }
+        auto g = std::make_unique<Grid>();
+        for (int64_t t = 0; t < m.nt(); ++t)
+            if (m.tri_obj[t] == i) g->tris.push_back((int32_t)t);
+        g->objs.push_back(i);
+        const double lam_r = 2.0 * 3.14159265358979323846 /
+                             (p->ext.k.re * std::sqrt(p->objs[i].eps_r * p->objs[i].mu_r));
+        build_grid_geometry(p, *g, rq, lam_r);
+        build_grid(p, *g);
+        p->ints[i].grid = g.get();
+        p->grids.push_back(std::move(g));
+    }
+    build_medium(p, p->ext);
+    for (int i = 0; i < m.nobj; ++i) build_medium(p, p->ints[i]);
+    p->is_setup = true;
+}
+
+}  // namespace sie
+
+sie::Medium &sie_problem::medium(int id) {
+    if (id == -1) return ext;
+    SIE_CHECK(id >= 0 && id < (int)ints.size(), SIE_EINVAL, "medium index out of range");
+    return ints[id];
+}
+const sie::Medium &sie_problem::medium(int id) const {
+    if (id == -1) return ext;
+    SIE_CHECK(id >= 0 && id < (int)ints.size(), SIE_EINVAL, "medium index out of range");
+    return ints[id];
+}

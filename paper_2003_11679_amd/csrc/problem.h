@@ -1,0 +1,87 @@
+// Problem state: mesh, grids, media (exterior and interiors), operators.
+#pragma once
+#include "common.h"
+#include "kernels.h"
+
+struct sie_ctx {
+    int device = 0;
+};
+
+namespace sie {
+
+struct ObjIn {
+    std::vector<double> xyz;
+    std::vector<int32_t> tri;
+    double eps_r = 1, mu_r = 1, sigma = 0;
+};
+
+struct GridReq {
+    int n = 0;         // 0 = rule
+    int R = 5;
+    int share = -1;    // -1 default, 0 own grid, 1 share exterior grid
+};
+
+struct SolveState;     // solver.cpp
+
+}  // namespace sie
+
+struct sie_problem {
+    sie_ctx *ctx = nullptr;
+    double freq = 0, w = 0, bg_eps_r = 1, bg_mu_r = 1;
+    std::vector<sie::ObjIn> objs;
+    sie::GridReq ext_req;
+    std::vector<sie::GridReq> obj_req;
+    sie_quad_params quad{0, 0, 0, 0, 0, 0};
+    bool is_setup = false;
+
+    sie::Mesh mesh;
+    std::vector<std::unique_ptr<sie::Grid>> grids;
+    sie::Medium ext;
+    std::vector<sie::Medium> ints;
+    // device mesh arrays
+    sie::DBuf<double> d_xyz, d_centroid;
+    sie::DBuf<int32_t> d_tri, d_tri_rwg, d_tpm, d_epm;
+    // X operator (CSR, real)
+    sie::DBuf<int32_t> d_xptr, d_xcol;
+    sie::DBuf<double> d_xval64;
+    sie::DBuf<float> d_xval32;
+    // plane waves
+    std::vector<double> khat;          // [nrhs][3]
+    std::vector<sie::c128> e0;         // [nrhs][3]
+    sie::SolveState *solve = nullptr;   // owned; freed by solver_destroy
+
+    sie::Medium &medium(int id);
+    const sie::Medium &medium(int id) const;
+};
+
+namespace sie {
+
+void problem_setup(sie_problem *p);
+template <typename T>
+void matvec(sie_problem *p, Medium &md, sie_op op, int nrhs, const cx<T> *x, cx<T> *y, hipStream_t st);
+template <typename T>
+void stage_project(sie_problem *p, Medium &md, const cx<T> *x, cx<T> *grid, hipStream_t st);
+template <typename T>
+void stage_convolve(sie_problem *p, Medium &md, int nf, const cx<T> *in, cx<T> *out, hipStream_t st);
+template <typename T>
+void stage_interpolate(sie_problem *p, Medium &md, const cx<T> *grid, cx<T> *y, hipStream_t st);
+void solver_destroy(SolveState *s);
+
+// ---- k_blas.hip
+template <typename Ti, typename To> void launch_convert(const cx<Ti> *in, cx<To> *out, int64_t n, hipStream_t st);
+template <typename T> void launch_axpby(int64_t n, c128 a, const cx<T> *x, c128 b, cx<T> *y, hipStream_t st);
+template <typename T> void launch_scale_into(int64_t n, c128 a, const cx<T> *x, cx<T> *y, hipStream_t st);
+// h[j] = sum_i conj(V[j][i]) w[i], j < J (FP64 accumulation); part: scratch [J][nb]
+template <typename T> void launch_dots(int64_t n, int J, const cx<T> *V, int64_t ldv, const cx<T> *w, c128 *part,
+                                       int nb, c128 *h, hipStream_t st);
+// w -= sum_j V[j] h[j]
+template <typename T> void launch_gemv_sub(int64_t n, int J, const cx<T> *V, int64_t ldv, const c128 *h, cx<T> *w,
+                                           hipStream_t st);
+// w += sum_j V[j] h[j]
+template <typename T> void launch_gemv_add(int64_t n, int J, const cx<T> *V, int64_t ldv, const c128 *h, cx<T> *w,
+                                           hipStream_t st);
+// y[i] = d[i] * x[i] with per-element complex d (range [i0, i1), zero elsewhere if zero_out)
+template <typename T> void launch_diag_mul(int64_t n, const c128 *d, const cx<T> *x, cx<T> *y, hipStream_t st);
+constexpr int DOT_BLOCKS = 256;
+
+}  // namespace sie

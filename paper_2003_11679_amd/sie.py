@@ -1,0 +1,299 @@
+"""ctypes binding of ``libsie.so`` (include/sie.h).
+
+Argument marshalling only: every computation runs in the HIP library.  Device
+arrays are torch tensors (complex64 / complex128 on a HIP device); the stream
+is torch's current stream unless one is given.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsie.so")
+
+SIE_OK, SIE_EINVAL, SIE_ENOMEM, SIE_EMESH, SIE_EGRID, SIE_ENOCONV, SIE_EDEVICE, SIE_ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
+FP64, FP32 = 0, 1
+OP_L, OP_K, OP_X = 0, 1, 2
+EXTERIOR = -1
+
+_STATUS = {SIE_EINVAL: "EINVAL", SIE_ENOMEM: "ENOMEM", SIE_EMESH: "EMESH", SIE_EGRID: "EGRID",
+           SIE_ENOCONV: "ENOCONV", SIE_EDEVICE: "EDEVICE", SIE_ESTATE: "ESTATE"}
+
+
+class SieError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class c128(ctypes.Structure):
+    _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double)]
+
+
+class QuadParams(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in
+                ("touch_out", "touch_in", "close_out", "close_in", "far_out", "far_in")]
+
+
+class SolverOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("inner_tol", ctypes.c_double), ("restart", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("inner_max_iter", ctypes.c_int32),
+                ("max_refine", ctypes.c_int32)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("outer_iters", ctypes.c_int32), ("inner_iters", ctypes.c_int32),
+                ("inner_iters_max", ctypes.c_int32), ("refine_sweeps", ctypes.c_int32),
+                ("matvecs", ctypes.c_int32), ("residual", ctypes.c_double), ("t_solve_s", ctypes.c_double)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+_lib = None
+_VP = ctypes.c_void_p
+_I32P = ctypes.POINTER(ctypes.c_int32)
+_I64P = ctypes.POINTER(ctypes.c_int64)
+_DP = ctypes.POINTER(ctypes.c_double)
+_CP = ctypes.POINTER(c128)
+
+# (name, restype, argtypes): every entry point declared in include/sie.h
+SIGNATURES = [
+    ("sie_ctx_create", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_VP)]),
+    ("sie_ctx_destroy", None, [_VP]),
+    ("sie_last_error", ctypes.c_char_p, []),
+    ("sie_problem_create", ctypes.c_int, [_VP, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                          ctypes.POINTER(_VP)]),
+    ("sie_problem_add_object", ctypes.c_int, [_VP, _DP, ctypes.c_int64, _I32P, ctypes.c_int64,
+                                              ctypes.c_double, ctypes.c_double, ctypes.c_double, _I32P]),
+    ("sie_problem_set_grid", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.c_int32]),
+    ("sie_problem_set_quadrature", ctypes.c_int, [_VP, ctypes.POINTER(QuadParams)]),
+    ("sie_problem_setup", ctypes.c_int, [_VP]),
+    ("sie_problem_destroy", None, [_VP]),
+    ("sie_problem_num_rwg", ctypes.c_int64, [_VP]),
+    ("sie_problem_num_tri", ctypes.c_int64, [_VP]),
+    ("sie_get_rwg", ctypes.c_int, [_VP, _I32P, _I32P]),
+    ("sie_get_grid", ctypes.c_int, [_VP, ctypes.c_int32, _DP, _DP, _I32P, _I32P, _I32P, _I32P]),
+    ("sie_get_stencils", ctypes.c_int, [_VP, ctypes.c_int32, _I32P, _I64P]),
+    ("sie_get_near_pattern", ctypes.c_int, [_VP, ctypes.c_int32, _I64P, _I32P, _I64P]),
+    ("sie_get_near_values", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int, _CP]),
+    ("sie_get_wavenumber", ctypes.c_int, [_VP, ctypes.c_int32, _CP]),
+    ("sie_matvec", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int, ctypes.c_int, ctypes.c_int32, _VP, _VP, _VP]),
+    ("sie_project", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int, _VP, _VP, _VP]),
+    ("sie_convolve", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int, ctypes.c_int32, _VP, _VP, _VP]),
+    ("sie_interpolate", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int, _VP, _VP, _VP]),
+    ("sie_set_planewaves", ctypes.c_int, [_VP, ctypes.c_int32, _DP, _CP]),
+    ("sie_solve", ctypes.c_int, [_VP, ctypes.c_int, ctypes.POINTER(SolverOpts), ctypes.POINTER(Report)]),
+    ("sie_get_currents", ctypes.c_int, [_VP, ctypes.c_int32, _CP, _CP]),
+    ("sie_far_field", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int64, _DP, _CP]),
+]
+
+
+def lib():
+    """Loads libsie.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2003_11679_amd/build.py "
+                               "(the HIP library is the only implementation)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(st):
+    if st != SIE_OK:
+        raise SieError(st, lib().sie_last_error().decode())
+    return st
+
+
+def _ptr(a, t):
+    return a.ctypes.data_as(ctypes.POINTER(t))
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(stream)
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Context:
+    def __init__(self, device=0):
+        h = _VP()
+        _check(lib().sie_ctx_create(device, ctypes.byref(h)))
+        self.h = h
+        self.device = device
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.sie_ctx_destroy(self.h)
+            self.h = None
+
+
+class Problem:
+    """One scattering problem: objects, grids, operators, solve."""
+
+    def __init__(self, freq, bg_eps_r=1.0, bg_mu_r=1.0, ctx=None, device=0):
+        self.ctx = ctx or Context(device)
+        h = _VP()
+        _check(lib().sie_problem_create(self.ctx.h, float(freq), float(bg_eps_r), float(bg_mu_r),
+                                        ctypes.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.sie_problem_destroy(self.h)
+            self.h = None
+
+    # -- definition -----------------------------------------------------------
+    def add_object(self, xyz, tri, eps_r=1.0, mu_r=1.0, sigma=0.0):
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        tri = np.ascontiguousarray(tri, dtype=np.int32)
+        oid = ctypes.c_int32()
+        _check(lib().sie_problem_add_object(self.h, _ptr(xyz, ctypes.c_double), len(xyz),
+                                            _ptr(tri, ctypes.c_int32), len(tri), float(eps_r), float(mu_r),
+                                            float(sigma), ctypes.byref(oid)))
+        return oid.value
+
+    def set_grid(self, medium, n=0, near_radius=5, share=0):
+        _check(lib().sie_problem_set_grid(self.h, medium, n, near_radius, share))
+
+    def set_quadrature(self, **orders):
+        q = QuadParams(**{k: int(v) for k, v in orders.items()})
+        _check(lib().sie_problem_set_quadrature(self.h, ctypes.byref(q)))
+
+    def setup(self):
+        _check(lib().sie_problem_setup(self.h))
+
+    # -- queries --------------------------------------------------------------
+    @property
+    def num_rwg(self):
+        return lib().sie_problem_num_rwg(self.h)
+
+    @property
+    def num_tri(self):
+        return lib().sie_problem_num_tri(self.h)
+
+    def rwg(self):
+        E = self.num_rwg
+        ev = np.empty((E, 2), np.int32); tpm = np.empty((E, 2), np.int32)
+        _check(lib().sie_get_rwg(self.h, _ptr(ev, ctypes.c_int32), _ptr(tpm, ctypes.c_int32)))
+        return ev, tpm
+
+    def grid(self, medium=EXTERIOR):
+        o = np.empty(3); h = np.empty(1)
+        n, lo, nl, m = (np.empty(3, np.int32) for _ in range(4))
+        _check(lib().sie_get_grid(self.h, medium, _ptr(o, ctypes.c_double), _ptr(h, ctypes.c_double),
+                                  _ptr(n, ctypes.c_int32), _ptr(lo, ctypes.c_int32), _ptr(nl, ctypes.c_int32),
+                                  _ptr(m, ctypes.c_int32)))
+        return {"origin": o, "h": float(h[0]), "n": n, "lo": lo, "nl": nl, "m": m}
+
+    def stencils(self, medium=EXTERIOR):
+        cnt = ctypes.c_int64()
+        _check(lib().sie_get_stencils(self.h, medium, None, ctypes.byref(cnt)))
+        out = np.empty((cnt.value, 3), np.int32)
+        _check(lib().sie_get_stencils(self.h, medium, _ptr(out, ctypes.c_int32), ctypes.byref(cnt)))
+        return out
+
+    def near_pattern(self, medium=EXTERIOR):
+        nnz = ctypes.c_int64()
+        _check(lib().sie_get_near_pattern(self.h, medium, None, None, ctypes.byref(nnz)))
+        rp = np.empty(self.num_rwg + 1, np.int64)
+        cols = np.empty(max(nnz.value, 1), np.int32)
+        _check(lib().sie_get_near_pattern(self.h, medium, _ptr(rp, ctypes.c_int64), _ptr(cols, ctypes.c_int32),
+                                          ctypes.byref(nnz)))
+        return rp, cols[:nnz.value]
+
+    def near_values(self, medium, op):
+        rp, cols = self.near_pattern(medium)
+        out = np.empty((max(len(cols), 1), 2))
+        _check(lib().sie_get_near_values(self.h, medium, op, out.ctypes.data_as(_CP)))
+        return (out[:, 0] + 1j * out[:, 1])[:len(cols)]
+
+    def wavenumber(self, medium=EXTERIOR):
+        k = c128()
+        _check(lib().sie_get_wavenumber(self.h, medium, ctypes.byref(k)))
+        return complex(k.re, k.im)
+
+    # -- hot path -------------------------------------------------------------
+    @staticmethod
+    def _prec_of(t):
+        import torch
+        if t.dtype == torch.complex128:
+            return FP64
+        if t.dtype == torch.complex64:
+            return FP32
+        raise TypeError("device vectors must be complex64 or complex128")
+
+    def matvec(self, medium, op, x, y=None, stream=None):
+        """y = Op x for x of shape [E] or [nrhs, E] on the device."""
+        import torch
+        prec = self._prec_of(x)
+        x = x.contiguous()
+        if y is None:
+            y = torch.empty_like(x)
+        nrhs = 1 if x.dim() == 1 else x.shape[0]
+        _check(lib().sie_matvec(self.h, medium, op, prec, nrhs, _VP(x.data_ptr()), _VP(y.data_ptr()),
+                                _stream(stream)))
+        return y
+
+    def project(self, medium, x, stream=None):
+        import torch
+        g = self.grid(medium)
+        nl = g["nl"]
+        out = torch.empty((4, nl[2], nl[1], nl[0]), dtype=x.dtype, device=x.device)
+        _check(lib().sie_project(self.h, medium, self._prec_of(x), _VP(x.contiguous().data_ptr()),
+                                 _VP(out.data_ptr()), _stream(stream)))
+        return out
+
+    def convolve(self, medium, grid_in, out=None, stream=None):
+        import torch
+        grid_in = grid_in.contiguous()
+        if out is None:
+            out = torch.empty_like(grid_in)
+        _check(lib().sie_convolve(self.h, medium, self._prec_of(grid_in), grid_in.shape[0],
+                                  _VP(grid_in.data_ptr()), _VP(out.data_ptr()), _stream(stream)))
+        return out
+
+    def interpolate(self, medium, grid, stream=None):
+        import torch
+        y = torch.empty(self.num_rwg, dtype=grid.dtype, device=grid.device)
+        _check(lib().sie_interpolate(self.h, medium, self._prec_of(grid), _VP(grid.contiguous().data_ptr()),
+                                     _VP(y.data_ptr()), _stream(stream)))
+        return y
+
+    # -- solve ----------------------------------------------------------------
+    def set_planewaves(self, khat, e0):
+        khat = np.ascontiguousarray(np.atleast_2d(khat), dtype=np.float64)
+        e0 = np.atleast_2d(np.asarray(e0, dtype=np.complex128))
+        ee = np.ascontiguousarray(np.stack([e0.real, e0.imag], axis=-1))
+        _check(lib().sie_set_planewaves(self.h, len(khat), _ptr(khat, ctypes.c_double), ee.ctypes.data_as(_CP)))
+
+    def solve(self, precision=FP64, **opts):
+        o = SolverOpts(**opts) if opts else None
+        r = Report()
+        st = lib().sie_solve(self.h, precision, ctypes.byref(o) if o else None, ctypes.byref(r))
+        if st not in (SIE_OK, SIE_ENOCONV):
+            _check(st)
+        d = r.as_dict()
+        d["converged"] = st == SIE_OK
+        return d
+
+    def currents(self, rhs=0):
+        E = self.num_rwg
+        u = np.empty((E, 2)); v = np.empty((E, 2))
+        _check(lib().sie_get_currents(self.h, rhs, u.ctypes.data_as(_CP), v.ctypes.data_as(_CP)))
+        return u[:, 0] + 1j * u[:, 1], v[:, 0] + 1j * v[:, 1]
+
+    def far_field(self, rhat, rhs=0):
+        rhat = np.ascontiguousarray(np.atleast_2d(rhat), dtype=np.float64)
+        out = np.empty((len(rhat), 3, 2))
+        _check(lib().sie_far_field(self.h, rhs, len(rhat), _ptr(rhat, ctypes.c_double), out.ctypes.data_as(_CP)))
+        return out[..., 0] + 1j * out[..., 1]
