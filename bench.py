@@ -1,0 +1,203 @@
+#!/usr/bin/env python3
+"""Benchmark: SIE matvecs/s and served solves/s of the GIBC/AIM solver on one
+MI355X.
+
+One step is one complete solve request on the copper-bar workload (100 x 10 x 5
+um bar, sigma = 5.8e7 S/m, 20,088 triangles / 30,132 RWG functions, 10 GHz,
+64^3 grid, near region 11 points across): mesh topology, grid and stencils,
+near lists, FP64 near-field integrals with precorrection, Green's spectra,
+plane-wave excitation, the nested GIBC solve (FP32 stages inside FP64
+refinement to a relative residual of 1e-6) and the far field.  The synthetic
+mesh is generated on the host before the timed region.
+
+value = SIE matvecs / s over the timed steps, one SIE matvec being one AIM
+operator product (L or K) of one medium for one right-hand side; solves/s and
+p50/p99 step latency are reported beside it.  The roofline object covers the
+dominant kernel (the near-field CSR product k_spmv_far), timed with HIP events
+recorded by the library on the stream the kernel runs on.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=64, help="rows of the oracle's dense matvec sample")
+    ap.add_argument("--tol", type=float, default=1e-3,
+                    help="relative FP64 residual of the solve (the metric's 1e-3 accuracy gate)")
+    return ap.parse_args()
+
+
+def step(mesh, cfg, prec, tol, timing=False):
+    """One solve request; returns (problem, report, setup_s, total_s)."""
+    import torch
+    from paper_2003_11679_amd import Problem
+    xyz, tri = mesh
+    o = cfg.objects[0]
+    t0 = time.perf_counter()
+    p = Problem(cfg.freq)
+    p.add_object(xyz, tri, eps_r=o.eps_r, mu_r=o.mu_r, sigma=o.sigma)
+    p.set_grid(-1, n=cfg.ext_grid_n, near_radius=cfg.near_radius)
+    p.setup()
+    t1 = time.perf_counter()
+    if timing:
+        p.set_timing(True)
+    w = cfg.waves[0]
+    p.set_planewaves(w.khat, w.e0)
+    rep = p.solve(prec, tol=tol)
+    th = np.linspace(0.0, np.pi, 91)
+    rhat = np.stack([np.sin(th), 0 * th, np.cos(th)], axis=1)
+    F = p.far_field(rhat)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    rep["far_field_max"] = float(np.abs(F).max())
+    return p, rep, t1 - t0, t2 - t0
+
+
+def spmv_bytes(p, prec):
+    """Algorithmic HBM bytes of one k_spmv_far launch: CSR values and column
+    indices, row pointers, x read once, y written once, far-part operands
+    (two triangles per row: coefficient and interpolation partials)."""
+    rp, cols = p.near_pattern(-1)
+    nnz = len(cols)
+    E = p.num_rwg
+    T = p.num_tri
+    s = 8 if prec == 1 else 16          # complex element
+    r = 4 if prec == 1 else 8           # real element
+    return nnz * (s + 4) + (E + 1) * 8 + 2 * E * s + E * 8 + T * (12 * r + 5 * s), nnz
+
+
+def cpu_baseline(cfg, mesh, rows):
+    """The oracle's dense Galerkin matvec (plain definition, Sec. III-A) on a
+    seeded sample of rows: every row integrates its two triangles against all
+    triangles at both wavenumbers; extrapolated to matvecs/s."""
+    from oracle.rwg import RWGMesh
+    from oracle import mom, physics as ph
+    m = RWGMesh([mesh])
+    rng = np.random.default_rng(11683)
+    sample = rng.choice(m.nrwg, size=rows, replace=False)
+    T = len(m.tri)
+    x = rng.standard_normal(m.nrwg) + 1j * rng.standard_normal(m.nrwg)
+    k = ph.wavenumber(cfg.freq, cfg.objects[0].eps_r, 1.0, cfg.objects[0].sigma)
+    t0 = time.perf_counter()
+    for n in sample:
+        tl = np.repeat([m.tp[n], m.tm[n]], T)
+        sl = np.tile(np.arange(T), 2)
+        A, P, K = mom.pair_blocks(m, k, tl, sl)
+        L = A - P / k ** 2
+        e = np.repeat([m.ep[n], m.em[n]], T)
+        cols = m.tri_rwg[sl]                         # [2T,3]
+        vals = L[np.arange(2 * T), e]                # [2T,3]
+        _ = np.sum(vals * x[cols])
+    dt = time.perf_counter() - t0
+    rate = rows / dt / m.nrwg                        # matvecs/s
+    return {"value": rate, "unit": "SIE matvecs/s", "cores": os.cpu_count(), "kind": "oracle",
+            "sample": f"dense L-operator rows of the copper bar: {rows} seeded rows of {m.nrwg} "
+                      f"(each row: its 2 triangles x all {T} triangles, oracle integration policy, "
+                      f"C pair integrals with OpenMP), {dt:.1f} s, extrapolated to whole matvecs"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the build has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("no HIP device", file=sys.stderr)
+        sys.exit(1)
+    from workloads import bar_cfg
+    cfg = bar_cfg()
+    mesh = (cfg.objects[0].xyz, cfg.objects[0].tri)
+    prec = 1 if args.precision == "fp32" else 0
+    print(f"[bench] workload bar {len(mesh[1])} triangles, precision {args.precision}, "
+          f"warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
+    ref = None
+    for i in range(args.warmup):
+        p, rep, su, tot = step(mesh, cfg, prec, args.tol)
+        print(f"[bench] warmup {i}: setup {su:.2f}s total {tot:.2f}s {rep}", file=sys.stderr, flush=True)
+        if i == 0 and prec == 1:
+            # FP64 reference of the same request (accuracy of the FP32 path)
+            u32, v32 = p.currents()
+            r64 = p.solve(0, tol=args.tol)
+            u64, v64 = p.currents()
+            ref = {"rel_err_u": float(np.linalg.norm(u32 - u64) / np.linalg.norm(u64)),
+                   "rel_err_v": float(np.linalg.norm(v32 - v64) / np.linalg.norm(v64)),
+                   "fp64_solve": r64}
+            print(f"[bench] fp64 reference: {ref}", file=sys.stderr, flush=True)
+        del p
+    torch.cuda.synchronize()
+    lat, matvecs, setups, reps = [], 0, [], []
+    spmv_ms, spmv_n, prod_ms, prod_n = 0.0, 0, 0.0, 0
+    t0 = time.perf_counter()
+    last = None
+    for i in range(args.steps):
+        p, rep, su, tot = step(mesh, cfg, prec, args.tol, timing=True)
+        st = p.stage_times()
+        spmv_n += st["spmv"][0]; spmv_ms += st["spmv"][1]
+        prod_n += st["product"][0]; prod_ms += st["product"][1]
+        lat.append(tot); setups.append(su); reps.append(rep)
+        matvecs += rep["matvecs"]
+        print(f"[bench] step {i}: setup {su:.2f}s total {tot:.2f}s {rep}", file=sys.stderr, flush=True)
+        if last is not None:
+            del last
+        last = p
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    nbytes, nnz = spmv_bytes(last, prec)
+    avg_ms = spmv_ms / max(spmv_n, 1)
+    achieved = nbytes / (avg_ms * 1e-3) / 1e9
+    conv = all(r["converged"] for r in reps)
+    out = {
+        "metric": "SIE matvecs/s + served solves/s, p50/p99 latency at rel err <=1e-3 vs FP64",
+        "value": matvecs / T,
+        "unit": "SIE matvecs/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": T / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64+f64" if prec == 1 else "c128",
+        "data": "synthetic",
+        "config": {"workload": "copper bar 100x10x5 um, sigma 5.8e7 S/m, 20088 triangles (30132 RWG), "
+                               "10 GHz, 64^3 grid, near radius 5, plane wave -z x-polarised, 1 RHS, "
+                               f"GIBC solve to a relative FP64 residual of {args.tol:g}",
+                   "precision": args.precision, "nnz_near": int(nnz)},
+        "solves_per_s": args.steps / T,
+        "latency_p50_s": float(np.percentile(lat, 50)),
+        "latency_p99_s": float(np.percentile(lat, 99)),
+        "setup_s_mean": float(np.mean(setups)),
+        "converged": conv,
+        "tol": args.tol,
+        "fp32_vs_fp64": ref,
+        "residual_fp64_max": max(r["residual"] for r in reps),
+        "outer_iters": reps[-1]["outer_iters"], "inner_iters": reps[-1]["inner_iters"],
+        "refine_sweeps": reps[-1]["refine_sweeps"],
+        "matvec_ms_mean": prod_ms / max(prod_n, 1),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_spmv_far", "avg_launch_ms": avg_ms, "launches": spmv_n,
+                     "bytes_per_launch": nbytes},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle dense row sample)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(cfg, mesh, args.cpu_rows)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -82,10 +82,12 @@ typedef struct {
 typedef struct {
     double tol;          /* relative residual of the outer (GIBC) system, default 1e-6 */
     double inner_tol;    /* nested solve (eq. nest2) tolerance, default 1e-8 (FP64) */
-    int32_t restart;     /* GMRES restart length, default 30 */
+    int32_t restart;     /* GMRES restart length, default 100 */
     int32_t max_iter;    /* outer iteration cap, default 800 (Sec. V-A) */
     int32_t inner_max_iter; /* nested iteration cap, default 800 */
     int32_t max_refine;  /* FP64 refinement sweeps for SIE_FP32, default 10 */
+    int32_t precond;     /* 0 none (default); 1 block-Jacobi of the direct near-region
+                            operators (-j w eps_i L_i,NR inner, j w mu0 L0,NR outer) */
 } sie_solver_opts;
 
 typedef struct {
@@ -176,6 +178,14 @@ sie_status sie_convolve(sie_problem *p, int32_t medium, sie_precision prec, int3
                         const void *grid_in_dev, void *grid_out_dev, void *stream);
 sie_status sie_interpolate(sie_problem *p, int32_t medium, sie_precision prec,
                            const void *grid_dev, void *y_dev, void *stream);
+
+/* Stage timers (HIP events recorded on the stream of each product).
+ * sie_set_timing(p, 1) starts recording (and clears the totals); stages:
+ * 0 projection, 1 FFT convolution, 2 interpolation, 3 near-field CSR product
+ * (the k_spmv_far kernel alone), 4 whole operator product.  Query returns the
+ * number of timed launches and their summed duration (synchronises). */
+sie_status sie_set_timing(sie_problem *p, int32_t on);
+sie_status sie_get_stage_time(sie_problem *p, int32_t stage, int64_t *launches, double *total_ms);
 
 /* ---- solve (Sec. III-C: GIBC with AIM-accelerated nested interior solves,
  * eq. GIBCsys, nest02, nest2) --------------------------------------------- */

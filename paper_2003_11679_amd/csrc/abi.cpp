@@ -252,4 +252,38 @@ sie_status sie_interpolate(sie_problem *p, int32_t medium, sie_precision prec, c
     });
 }
 
+sie_status sie_set_timing(sie_problem *p, int32_t on) {
+    return guard([&] {
+        SIE_CHECK(p, SIE_EINVAL, "NULL problem");
+        p->timer.reset();
+        p->timer.on = on != 0;
+    });
+}
+
+sie_status sie_get_stage_time(sie_problem *p, int32_t stage, int64_t *launches, double *total_ms) {
+    return guard([&] {
+        SIE_CHECK(p, SIE_EINVAL, "NULL problem");
+        SIE_CHECK(stage >= 0 && stage < NSTAGE, SIE_EINVAL, "stage out of range");
+        p->timer.flush();
+        if (launches) *launches = p->timer.count[stage];
+        if (total_ms) *total_ms = p->timer.total_ms[stage];
+    });
+}
+
+sie_status sie_set_planewaves(sie_problem *p, int32_t nrhs, const double *khat, const sie_c128 *e0) {
+    return guard([&] { planewaves_entry(p, nrhs, khat, e0); });
+}
+
+sie_status sie_solve(sie_problem *p, sie_precision prec, const sie_solver_opts *opts, sie_report *report) {
+    return guard([&] { solve_entry(p, prec, opts, report); });
+}
+
+sie_status sie_get_currents(const sie_problem *p, int32_t rhs, sie_c128 *u, sie_c128 *v) {
+    return guard([&] { currents_entry(p, rhs, u, v); });
+}
+
+sie_status sie_far_field(const sie_problem *p, int32_t rhs, int64_t ndir, const double *rhat, sie_c128 *F) {
+    return guard([&] { farfield_entry(p, rhs, ndir, rhat, F); });
+}
+
 }  // extern "C"

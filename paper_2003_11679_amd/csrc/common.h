@@ -212,6 +212,7 @@ struct Medium {
     // precorrected near values (CSR of the grid pattern)
     DBuf<c128> d_nL64, d_nK64;
     DBuf<c64> d_nL32, d_nK32;
+    DBuf<c128> d_nLd64;        // direct near-region L (no precorrection): preconditioner source
 };
 
 }  // namespace sie

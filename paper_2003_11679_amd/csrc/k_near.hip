@@ -371,7 +371,7 @@ __global__ void __launch_bounds__(128) k_near_fill(NearFillArgs a) {
     const c128 ik2 = cdiv(c128(1.0), k2);
     const double *ct = a.tri_coef + tl * 12;
     const double *cs = a.tri_coef + sl * 12;
-    c128 *out = a.blocks + p * 18;
+    c128 *out = a.blocks + p * 27;
     for (int e = 0; e < 3; ++e) {
         const double ce = ct[4 * e];
         const V3 qe = {ct[4 * e + 1], ct[4 * e + 2], ct[4 * e + 3]};
@@ -389,6 +389,7 @@ __global__ void __launch_bounds__(128) k_near_fill(NearFillArgs a) {
             const c128 Kg = cc * (C11 - cdot(qe, Vs) - cdot(qf, Vt) + cdot(cross(qf, qe), U));
             out[e * 3 + f] = (Ad - Ag) - ik2 * (Pd - Pg);
             out[9 + e * 3 + f] = Kd - Kg;
+            out[18 + e * 3 + f] = Ad - ik2 * Pd;     // direct (unprecorrected) L
         }
     }
 }
@@ -417,14 +418,13 @@ __global__ void k_near_gather(int64_t nrow, int64_t rwg0, const int64_t *__restr
                               const int32_t *__restrict__ glob2loc, const int32_t *__restrict__ tpm,
                               const int32_t *__restrict__ epm, const int64_t *__restrict__ pair_ptr,
                               const int32_t *__restrict__ pair_s, const c128 *__restrict__ blocks,
-                              c128 *__restrict__ nL64, c128 *__restrict__ nK64, c64 *__restrict__ nL32,
-                              c64 *__restrict__ nK32) {
+                              c128 *__restrict__ nL64, c128 *__restrict__ nK64, c128 *__restrict__ nLd64) {
     const int64_t r = blockIdx.y;
     if (r >= nrow) return;
     const int64_t j = row_ptr[r] + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (j >= row_ptr[r + 1]) return;
     const int32_t n = cols[j];
-    c128 L, K;
+    c128 L, K, Ld;
     for (int sa = 0; sa < 2; ++sa) {
         const int32_t lc = rwg_loc[2 * r + sa];
         const int64_t tl = lc >> 2;
@@ -435,26 +435,28 @@ __global__ void k_near_gather(int64_t nrow, int64_t rwg0, const int64_t *__restr
             const int eb = epm[2 * (int64_t)n + sb];
             const int64_t q = find_pair(pair_ptr, pair_s, tl, sl);
             if (q < 0) continue;
-            L += blocks[q * 18 + ea * 3 + eb];
-            K += blocks[q * 18 + 9 + ea * 3 + eb];
+            L += blocks[q * 27 + ea * 3 + eb];
+            K += blocks[q * 27 + 9 + ea * 3 + eb];
+            Ld += blocks[q * 27 + 18 + ea * 3 + eb];
         }
     }
     // row-triangle chunks are processed one after the other: accumulate
     nL64[j] += L;
     nK64[j] += K;
+    nLd64[j] += Ld;
 }
 
 void launch_near_gather(int64_t nrow, int64_t rwg0, int64_t max_row, const int64_t *row_ptr, const int32_t *cols,
                          const int32_t *rwg_loc, const int32_t *glob2loc, const int32_t *tpm, const int32_t *epm,
                          const int64_t *pair_ptr, const int32_t *pair_s, const c128 *blocks, c128 *nL64,
-                         c128 *nK64, c64 *nL32, c64 *nK32, hipStream_t st) {
+                         c128 *nK64, c128 *nLd64, hipStream_t st) {
     if (!nrow || !max_row) return;
     SIE_CHECK(nrow < 65536LL * 1024, SIE_EINVAL, "too many rows");
     for (int64_t r0 = 0; r0 < nrow; r0 += 65535) {
         const int64_t nr = std::min<int64_t>(65535, nrow - r0);
         dim3 grid((unsigned)((max_row + 255) / 256), (unsigned)nr);
         hipLaunchKernelGGL(k_near_gather, grid, dim3(256), 0, st, nr, rwg0, row_ptr + r0, cols,
-                           rwg_loc + 2 * r0, glob2loc, tpm, epm, pair_ptr, pair_s, blocks, nL64, nK64, nL32, nK32);
+                           rwg_loc + 2 * r0, glob2loc, tpm, epm, pair_ptr, pair_s, blocks, nL64, nK64, nLd64);
         SIE_HIP(hipGetLastError());
     }
 }

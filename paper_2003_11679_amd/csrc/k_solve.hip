@@ -1,0 +1,237 @@
+// Kernels of the solve: plane-wave excitation, far field, and the batched
+// block-Jacobi stand-in for the near-region preconditioner M_i = -j w eps_i L_i,NR
+// (eq. nest2pc; the paper factorises M_i with a sparse LU, here diagonal
+// blocks of spatially adjacent RWG functions are inverted in FP64).
+#include "problem.h"
+#include "solve_kernels.h"
+
+namespace sie {
+
+// e_m = int f_m . e0 exp(-j k0 khat . r) dS over the two triangles of m.
+__global__ void k_excitation(int64_t E, const double *__restrict__ xyz, const int32_t *__restrict__ tri,
+                             const int32_t *__restrict__ tpm, const int32_t *__restrict__ epm,
+                             const double *__restrict__ len, const double *__restrict__ area,
+                             const double *__restrict__ rule, int nq, double k0, double kx, double ky, double kz,
+                             c128 ex, c128 ey, c128 ez, c128 *__restrict__ out) {
+    int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (n >= E) return;
+    c128 acc;
+    for (int s = 0; s < 2; ++s) {
+        const int64_t t = tpm[2 * n + s];
+        const int e = epm[2 * n + s];
+        const double sg = s == 0 ? 1.0 : -1.0;
+        const double A = area[t];
+        const double c = sg * len[n] / (2.0 * A);
+        double v[3][3];
+        for (int k = 0; k < 3; ++k)
+            for (int d = 0; d < 3; ++d) v[k][d] = xyz[3 * (int64_t)tri[3 * t + k] + d];
+        for (int q = 0; q < nq; ++q) {
+            double r[3];
+            for (int d = 0; d < 3; ++d)
+                r[d] = rule[4 * q] * v[0][d] + rule[4 * q + 1] * v[1][d] + rule[4 * q + 2] * v[2][d];
+            const double ph = -k0 * (kx * r[0] + ky * r[1] + kz * r[2]);
+            double sn, cs;
+            sincos(ph, &sn, &cs);
+            const c128 phase(cs, sn);
+            const double w = rule[4 * q + 3] * A * c;
+            const c128 fd = (r[0] - v[e][0]) * ex + (r[1] - v[e][1]) * ey + (r[2] - v[e][2]) * ez;
+            acc += w * (fd * phase);
+        }
+    }
+    out[n] = acc;
+}
+
+void launch_excitation(sie_problem *p, const double *rule, int nq, double k0, const double khat[3], const c128 e0[3],
+                       c128 *out, hipStream_t st) {
+    const int64_t E = p->mesh.nrwg;
+    hipLaunchKernelGGL(k_excitation, dim3((unsigned)((E + 127) / 128)), dim3(128), 0, st, E, p->d_xyz.p, p->d_tri.p,
+                       p->d_tpm.p, p->d_epm.p, p->d_len.p, p->d_area.p, rule, nq, k0, khat[0], khat[1], khat[2],
+                       e0[0], e0[1], e0[2], out);
+    SIE_HIP(hipGetLastError());
+}
+
+// Far-field amplitude for direction d (one block per direction):
+// F = (-j k0 / 4 pi) [eta0 (N_u - rhat (rhat . N_u)) + rhat x N_v],
+// N_x = int x(r') exp(j k0 rhat . r') dS'.
+__global__ void k_farfield(int64_t T, const double *__restrict__ xyz, const int32_t *__restrict__ tri,
+                           const int32_t *__restrict__ tri_rwg, const double *__restrict__ tri_sign,
+                           const double *__restrict__ len, const double *__restrict__ area,
+                           const double *__restrict__ rule, int nq, double k0, double eta0,
+                           const double *__restrict__ rhat, const c128 *__restrict__ u, const c128 *__restrict__ v,
+                           c128 *__restrict__ F) {
+    __shared__ double red[12][256];
+    const int d = blockIdx.x;
+    const double rx = rhat[3 * d], ry = rhat[3 * d + 1], rz = rhat[3 * d + 2];
+    c128 nu[3], nv[3];
+    for (int64_t t = threadIdx.x; t < T; t += blockDim.x) {
+        double vt[3][3];
+        for (int k = 0; k < 3; ++k)
+            for (int c = 0; c < 3; ++c) vt[k][c] = xyz[3 * (int64_t)tri[3 * t + k] + c];
+        c128 cu[3], cv[3];
+        double ce[3];
+        for (int e = 0; e < 3; ++e) {
+            const int n = tri_rwg[3 * t + e];
+            ce[e] = tri_sign[3 * t + e] * len[n] / (2.0 * area[t]);
+            cu[e] = u[n]; cv[e] = v[n];
+        }
+        for (int q = 0; q < nq; ++q) {
+            double r[3];
+            for (int c = 0; c < 3; ++c)
+                r[c] = rule[4 * q] * vt[0][c] + rule[4 * q + 1] * vt[1][c] + rule[4 * q + 2] * vt[2][c];
+            double sn, cs;
+            sincos(k0 * (rx * r[0] + ry * r[1] + rz * r[2]), &sn, &cs);
+            const c128 ph = (rule[4 * q + 3] * area[t]) * c128(cs, sn);
+            for (int c = 0; c < 3; ++c) {
+                c128 ju, jv;
+                for (int e = 0; e < 3; ++e) {
+                    const double f = ce[e] * (r[c] - vt[e][c]);
+                    ju += f * cu[e];
+                    jv += f * cv[e];
+                }
+                nu[c] += ph * ju;
+                nv[c] += ph * jv;
+            }
+        }
+    }
+    for (int c = 0; c < 3; ++c) {
+        red[2 * c][threadIdx.x] = nu[c].re; red[2 * c + 1][threadIdx.x] = nu[c].im;
+        red[6 + 2 * c][threadIdx.x] = nv[c].re; red[7 + 2 * c][threadIdx.x] = nv[c].im;
+    }
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < 12; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        c128 Nu[3], Nv[3];
+        for (int c = 0; c < 3; ++c) {
+            Nu[c] = c128(red[2 * c][0], red[2 * c + 1][0]);
+            Nv[c] = c128(red[6 + 2 * c][0], red[7 + 2 * c][0]);
+        }
+        const double rh[3] = {rx, ry, rz};
+        const c128 rdot = rx * Nu[0] + ry * Nu[1] + rz * Nu[2];
+        const c128 cr[3] = {ry * Nv[2] - rz * Nv[1], rz * Nv[0] - rx * Nv[2], rx * Nv[1] - ry * Nv[0]};
+        const c128 pre(0.0, -k0 / (4.0 * 3.14159265358979323846));
+        for (int c = 0; c < 3; ++c) F[3 * d + c] = pre * (eta0 * (Nu[c] - rh[c] * rdot) + cr[c]);
+    }
+}
+
+void launch_farfield(sie_problem *p, const double *rule, int nq, double k0, double eta0, const double *rhat,
+                     int64_t ndir, const c128 *u, const c128 *v, c128 *F, hipStream_t st) {
+    if (ndir == 0) return;
+    hipLaunchKernelGGL(k_farfield, dim3((unsigned)ndir), dim3(256), 0, st, p->mesh.nt(), p->d_xyz.p, p->d_tri.p,
+                       p->d_tri_rwg.p, p->d_tri_sign.p, p->d_len.p, p->d_area.p, rule, nq, k0, eta0, rhat, u, v, F);
+    SIE_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- block Jacobi
+// One workgroup per block of B RWG functions (perm: [nb][B], -1 = padding):
+// gather the scaled direct near-region entries, invert by Gauss-Jordan with
+// partial pivoting in LDS (FP64), store the inverse.
+__global__ void k_bj_setup(int B, const int32_t *__restrict__ perm, int64_t rwg0, const int64_t *__restrict__ row_ptr,
+                           const int32_t *__restrict__ cols, const c128 *__restrict__ vals, c128 scale,
+                           c128 *__restrict__ inv64, c64 *__restrict__ inv32) {
+    extern __shared__ unsigned char smem[];
+    c128 *a = reinterpret_cast<c128 *>(smem);          // [B][2B]
+    c128 *fcol = a + 2 * B * B;                         // [B]
+    __shared__ int piv;
+    const int b = blockIdx.x;
+    const int W = 2 * B;
+    const int32_t *pb = perm + (int64_t)b * B;
+    for (int it = threadIdx.x; it < B * B; it += blockDim.x) {
+        const int i = it / B, j = it - i * B;
+        const int32_t r = pb[i], c = pb[j];
+        c128 val;
+        if (r < 0 || c < 0) {
+            val = c128(i == j ? 1.0 : 0.0);
+        } else {
+            int64_t lo = row_ptr[r - rwg0], hi = row_ptr[r - rwg0 + 1];
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                const int32_t cm = cols[mid];
+                if (cm == c) { val = scale * vals[mid]; break; }
+                if (cm < c) lo = mid + 1; else hi = mid;
+            }
+        }
+        a[i * W + j] = val;
+        a[i * W + B + j] = c128(i == j ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    for (int k = 0; k < B; ++k) {
+        if (threadIdx.x == 0) {
+            int best = k;
+            double bv = norm2(a[k * W + k]);
+            for (int i = k + 1; i < B; ++i) {
+                const double v = norm2(a[i * W + k]);
+                if (v > bv) { bv = v; best = i; }
+            }
+            piv = best;
+        }
+        __syncthreads();
+        const int pr = piv;
+        if (pr != k)
+            for (int j = threadIdx.x; j < W; j += blockDim.x) {
+                const c128 t = a[k * W + j];
+                a[k * W + j] = a[pr * W + j];
+                a[pr * W + j] = t;
+            }
+        __syncthreads();
+        const c128 pinv = cdiv(c128(1.0), a[k * W + k]);
+        __syncthreads();
+        for (int j = threadIdx.x; j < W; j += blockDim.x) a[k * W + j] = pinv * a[k * W + j];
+        __syncthreads();
+        for (int i = threadIdx.x; i < B; i += blockDim.x) fcol[i] = a[i * W + k];
+        __syncthreads();
+        for (int it = threadIdx.x; it < B * W; it += blockDim.x) {
+            const int i = it / W, j = it - i * W;
+            if (i != k) a[i * W + j] -= fcol[i] * a[k * W + j];
+        }
+        __syncthreads();
+    }
+    for (int it = threadIdx.x; it < B * B; it += blockDim.x) {
+        const int i = it / B, j = it - i * B;
+        const c128 v = a[i * W + B + j];
+        inv64[(int64_t)b * B * B + it] = v;
+        inv32[(int64_t)b * B * B + it] = c64((float)v.re, (float)v.im);
+    }
+}
+
+void launch_bj_setup(int nb, int B, const int32_t *perm, int64_t rwg0, const int64_t *row_ptr, const int32_t *cols,
+                     const c128 *vals, c128 scale, c128 *inv64, c64 *inv32, hipStream_t st) {
+    if (!nb) return;
+    const size_t sh = (2 * (size_t)B * B + B) * sizeof(c128);
+    hipLaunchKernelGGL(k_bj_setup, dim3(nb), dim3(256), sh, st, B, perm, rwg0, row_ptr, cols, vals, scale, inv64,
+                       inv32);
+    SIE_HIP(hipGetLastError());
+}
+
+template <typename T>
+__global__ void k_bj_apply(int B, const int32_t *__restrict__ perm, const cx<T> *__restrict__ inv,
+                           const cx<T> *__restrict__ x, cx<T> *__restrict__ y) {
+    extern __shared__ unsigned char smem[];
+    cx<T> *xs = reinterpret_cast<cx<T> *>(smem);
+    const int b = blockIdx.x;
+    const int32_t *pb = perm + (int64_t)b * B;
+    for (int j = threadIdx.x; j < B; j += blockDim.x) xs[j] = pb[j] >= 0 ? x[pb[j]] : cx<T>();
+    __syncthreads();
+    for (int i = threadIdx.x; i < B; i += blockDim.x) {
+        if (pb[i] < 0) continue;
+        const cx<T> *row = inv + ((int64_t)b * B + i) * B;
+        cx<T> acc;
+        for (int j = 0; j < B; ++j) acc += row[j] * xs[j];
+        y[pb[i]] = acc;
+    }
+}
+
+template <typename T>
+void launch_bj_apply(int nb, int B, const int32_t *perm, const cx<T> *inv, const cx<T> *x, cx<T> *y, hipStream_t st) {
+    if (!nb) return;
+    hipLaunchKernelGGL(k_bj_apply<T>, dim3(nb), dim3(64), B * sizeof(cx<T>), st, B, perm, inv, x, y);
+    SIE_HIP(hipGetLastError());
+}
+
+template void launch_bj_apply<float>(int, int, const int32_t *, const c64 *, const c64 *, c64 *, hipStream_t);
+template void launch_bj_apply<double>(int, int, const int32_t *, const c128 *, const c128 *, c128 *, hipStream_t);
+
+}  // namespace sie

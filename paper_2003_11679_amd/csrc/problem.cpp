@@ -265,11 +265,13 @@ static void build_medium(sie_problem *p, Medium &md) {
 
     md.d_nL64.alloc(std::max<int64_t>(g.nnz, 1));
     md.d_nK64.alloc(std::max<int64_t>(g.nnz, 1));
+    md.d_nLd64.alloc(std::max<int64_t>(g.nnz, 1));
     SIE_HIP(hipMemset(md.d_nL64.p, 0, md.d_nL64.bytes()));
     SIE_HIP(hipMemset(md.d_nK64.p, 0, md.d_nK64.bytes()));
+    SIE_HIP(hipMemset(md.d_nLd64.p, 0, md.d_nLd64.bytes()));
     // process row triangles in chunks to bound the pair-block buffer
     std::vector<int64_t> pptr = g.d_pair_ptr.download();
-    const int64_t max_chunk = 12000000;
+    const int64_t max_chunk = 8000000;   // pair blocks of one chunk: 3.5 GB
     DBuf<c128> blocks;
     DBuf<int64_t> d_pp;
     DBuf<int32_t> d_rwgloc_chunk;
@@ -284,7 +286,7 @@ static void build_medium(sie_problem *p, Medium &md) {
         std::vector<int64_t> cp(ntg + 1);
         for (int64_t i = 0; i <= ntg; ++i) cp[i] = std::min(std::max(pptr[i], pptr[t0]), pptr[t1]) - pptr[t0];
         d_pp.upload(cp);
-        blocks.alloc(std::max<int64_t>(np, 1) * 18);
+        blocks.alloc(std::max<int64_t>(np, 1) * 27);
         NearFillArgs a;
         a.xyz = p->d_xyz.p; a.tri = p->d_tri.p; a.tris = g.d_tris.p; a.centre = g.d_centre.p;
         a.centroid = p->d_centroid.p; a.tri_coef = g.d_tri64.p; a.mom = g.d_mom64.p;
@@ -298,7 +300,7 @@ static void build_medium(sie_problem *p, Medium &md) {
         }
         launch_near_gather(nrow, g.rwg0, g.max_row, g.d_row_ptr.p, g.d_cols.p, g.d_rwgloc.p, g.d_glob2loc.p,
                            p->d_tpm.p, p->d_epm.p, d_pp.p, g.d_pair_s.p + pptr[t0], blocks.p, md.d_nL64.p,
-                           md.d_nK64.p, nullptr, nullptr, 0);
+                           md.d_nK64.p, md.d_nLd64.p, 0);
         SIE_HIP(hipDeviceSynchronize());
         t0 = t1;
     }
@@ -391,6 +393,48 @@ template <typename T> static const T *xval_of(sie_problem *p);
 template <> const double *xval_of<double>(sie_problem *p) { return p->d_xval64.p; }
 template <> const float *xval_of<float>(sie_problem *p) { return p->d_xval32.p; }
 
+// ---- stage timers
+hipEvent_t StageTimer::get() {
+    if (pool.empty()) {
+        hipEvent_t e;
+        SIE_HIP(hipEventCreate(&e));
+        return e;
+    }
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+}
+void StageTimer::begin(int, hipStream_t st, hipEvent_t &a) {
+    a = get();
+    SIE_HIP(hipEventRecord(a, st));
+}
+void StageTimer::end(int stage, hipStream_t st, hipEvent_t a) {
+    hipEvent_t b = get();
+    SIE_HIP(hipEventRecord(b, st));
+    pending.push_back({stage, a, b});
+    if (pending.size() >= 4096) flush();
+}
+void StageTimer::flush() {
+    for (auto &r : pending) {
+        SIE_HIP(hipEventSynchronize(r.b));
+        float ms = 0.f;
+        SIE_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+        total_ms[r.stage] += ms;
+        count[r.stage] += 1;
+        pool.push_back(r.a);
+        pool.push_back(r.b);
+    }
+    pending.clear();
+}
+void StageTimer::reset() {
+    flush();
+    for (int i = 0; i < NSTAGE; ++i) { total_ms[i] = 0; count[i] = 0; }
+}
+StageTimer::~StageTimer() {
+    for (auto &r : pending) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+    for (auto e : pool) (void)hipEventDestroy(e);
+}
+
 template <typename T>
 void matvec(sie_problem *p, Medium &md, sie_op op, int nrhs, const cx<T> *x, cx<T> *y, hipStream_t st) {
     const int64_t E = p->mesh.nrwg;
@@ -405,13 +449,20 @@ void matvec(sie_problem *p, Medium &md, sie_op op, int nrhs, const cx<T> *x, cx<
     const c128 k2 = md.k * md.k;
     const c128 ks = op == SIE_OP_L ? cdiv(c128(-2.0), k2) : c128();
     const cx<T> kscal((T)ks.re, (T)ks.im);
+    StageTimer &tm = p->timer;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
     for (int r = 0; r < nrhs; ++r) {
+        if (tm.on) { tm.begin(ST_PRODUCT, st, e0); tm.begin(ST_PROJECT, st, e1); }
         launch_tri_sources<T>(g, g.d_trirwg.p, coef_of<T>(g), x + r * E, w.trisrc.p, st);
         launch_project<T>(g, mom_of<T>(g), w.trisrc.p, w.grid.p, F, st);
+        if (tm.on) { tm.end(ST_PROJECT, st, e1); tm.begin(ST_FFT, st, e1); }
         fft_convolve<T>(g, spec_of<T>(md), F, op == SIE_OP_L ? 0 : 1, w.grid.p, w.grid.p, w.bufA.p, w.bufB.p, st);
+        if (tm.on) { tm.end(ST_FFT, st, e1); tm.begin(ST_INTERP, st, e1); }
         launch_interp<T>(g, mom_of<T>(g), w.grid.p, F, w.tripot.p, st);
+        if (tm.on) { tm.end(ST_INTERP, st, e1); tm.begin(ST_SPMV, st, e1); }
         launch_spmv_far<T>(g, E, g.d_rwgloc.p, coef_of<T>(g), w.tripot.p, kscal, near_of<T>(md, op), x + r * E,
                            y + r * E, true, st);
+        if (tm.on) { tm.end(ST_SPMV, st, e1); tm.end(ST_PRODUCT, st, e0); }
     }
 }
 
@@ -481,6 +532,9 @@ void problem_setup(sie_problem *p) {
     p->d_tri_rwg.upload(m.tri_rwg);
     p->d_tpm.upload(m.tpm);
     p->d_epm.upload(m.epm);
+    p->d_len.upload(m.len);
+    p->d_area.upload(m.area);
+    p->d_tri_sign.upload(m.tri_sign);
     build_x(p);
     // media
     p->w = 2.0 * 3.14159265358979323846 * p->freq;

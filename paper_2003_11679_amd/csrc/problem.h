@@ -23,6 +23,23 @@ struct GridReq {
 
 struct SolveState;     // solver.cpp
 
+// HIP-event timers of the operator stages (enabled per problem).
+enum Stage { ST_PROJECT = 0, ST_FFT = 1, ST_INTERP = 2, ST_SPMV = 3, ST_PRODUCT = 4, NSTAGE = 5 };
+struct StageTimer {
+    bool on = false;
+    struct Rec { int stage; hipEvent_t a, b; };
+    std::vector<Rec> pending;
+    std::vector<hipEvent_t> pool;
+    double total_ms[NSTAGE] = {0, 0, 0, 0, 0};
+    int64_t count[NSTAGE] = {0, 0, 0, 0, 0};
+    hipEvent_t get();
+    void begin(int stage, hipStream_t st, hipEvent_t &a);
+    void end(int stage, hipStream_t st, hipEvent_t a);
+    void flush();
+    void reset();
+    ~StageTimer();
+};
+
 }  // namespace sie
 
 struct sie_problem {
@@ -41,6 +58,7 @@ struct sie_problem {
     // device mesh arrays
     sie::DBuf<double> d_xyz, d_centroid;
     sie::DBuf<int32_t> d_tri, d_tri_rwg, d_tpm, d_epm;
+    sie::DBuf<double> d_len, d_area, d_tri_sign;
     // X operator (CSR, real)
     sie::DBuf<int32_t> d_xptr, d_xcol;
     sie::DBuf<double> d_xval64;
@@ -49,6 +67,7 @@ struct sie_problem {
     std::vector<double> khat;          // [nrhs][3]
     std::vector<sie::c128> e0;         // [nrhs][3]
     sie::SolveState *solve = nullptr;   // owned; freed by solver_destroy
+    sie::StageTimer timer;
 
     sie::Medium &medium(int id);
     const sie::Medium &medium(int id) const;
@@ -66,6 +85,10 @@ void stage_convolve(sie_problem *p, Medium &md, int nf, const cx<T> *in, cx<T> *
 template <typename T>
 void stage_interpolate(sie_problem *p, Medium &md, const cx<T> *grid, cx<T> *y, hipStream_t st);
 void solver_destroy(SolveState *s);
+void planewaves_entry(sie_problem *p, int32_t nrhs, const double *khat, const sie_c128 *e0);
+void solve_entry(sie_problem *p, sie_precision prec, const sie_solver_opts *opts, sie_report *rep);
+void currents_entry(const sie_problem *p, int32_t rhs, sie_c128 *u, sie_c128 *v);
+void farfield_entry(const sie_problem *p, int32_t rhs, int64_t ndir, const double *rhat, sie_c128 *F);
 
 // ---- k_blas.hip
 template <typename Ti, typename To> void launch_convert(const cx<Ti> *in, cx<To> *out, int64_t n, hipStream_t st);

@@ -1,0 +1,14 @@
+// Launchers of the solve kernels (k_solve.hip).
+#pragma once
+#include "problem.h"
+
+namespace sie {
+void launch_excitation(sie_problem *p, const double *rule, int nq, double k0, const double khat[3], const c128 e0[3],
+                       c128 *out, hipStream_t st);
+void launch_farfield(sie_problem *p, const double *rule, int nq, double k0, double eta0, const double *rhat,
+                     int64_t ndir, const c128 *u, const c128 *v, c128 *F, hipStream_t st);
+void launch_bj_setup(int nb, int B, const int32_t *perm, int64_t rwg0, const int64_t *row_ptr, const int32_t *cols,
+                     const c128 *vals, c128 scale, c128 *inv64, c64 *inv32, hipStream_t st);
+template <typename T>
+void launch_bj_apply(int nb, int B, const int32_t *perm, const cx<T> *inv, const cx<T> *x, cx<T> *y, hipStream_t st);
+}  // namespace sie

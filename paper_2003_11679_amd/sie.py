@@ -39,7 +39,7 @@ class QuadParams(ctypes.Structure):
 class SolverOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("inner_tol", ctypes.c_double), ("restart", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("inner_max_iter", ctypes.c_int32),
-                ("max_refine", ctypes.c_int32)]
+                ("max_refine", ctypes.c_int32), ("precond", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -84,6 +84,8 @@ SIGNATURES = [
     ("sie_project", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int, _VP, _VP, _VP]),
     ("sie_convolve", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int, ctypes.c_int32, _VP, _VP, _VP]),
     ("sie_interpolate", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int, _VP, _VP, _VP]),
+    ("sie_set_timing", ctypes.c_int, [_VP, ctypes.c_int32]),
+    ("sie_get_stage_time", ctypes.c_int, [_VP, ctypes.c_int32, _I64P, _DP]),
     ("sie_set_planewaves", ctypes.c_int, [_VP, ctypes.c_int32, _DP, _CP]),
     ("sie_solve", ctypes.c_int, [_VP, ctypes.c_int, ctypes.POINTER(SolverOpts), ctypes.POINTER(Report)]),
     ("sie_get_currents", ctypes.c_int, [_VP, ctypes.c_int32, _CP, _CP]),
@@ -268,6 +270,20 @@ class Problem:
         _check(lib().sie_interpolate(self.h, medium, self._prec_of(grid), _VP(grid.contiguous().data_ptr()),
                                      _VP(y.data_ptr()), _stream(stream)))
         return y
+
+    STAGES = ("project", "fft", "interp", "spmv", "product")
+
+    def set_timing(self, on=True):
+        _check(lib().sie_set_timing(self.h, 1 if on else 0))
+
+    def stage_times(self):
+        """{stage: (launches, total_ms)} of the stage timers."""
+        out = {}
+        for i, name in enumerate(self.STAGES):
+            n = ctypes.c_int64(); ms = ctypes.c_double()
+            _check(lib().sie_get_stage_time(self.h, i, ctypes.byref(n), ctypes.byref(ms)))
+            out[name] = (n.value, ms.value)
+        return out
 
     # -- solve ----------------------------------------------------------------
     def set_planewaves(self, khat, e0):

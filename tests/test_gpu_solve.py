@@ -1,0 +1,117 @@
+"""GPU GIBC solve against the oracle: excitation and far field, residual of
+the GPU solution measured with the oracle's AIM operators, agreement with the
+dense solution and with the Mie series, FP32 + FP64 refinement vs FP64."""
+import numpy as np
+import pytest
+
+from cases import CASES, gpu_problem, oracle_aim, mesh_of
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+KHAT = (0.0, 0.0, 1.0)
+E0 = (1.0, 0.0, 0.0)
+
+
+@pytest.fixture(scope="module")
+def solved():
+    out = {}
+    for name in ("sphere2", "sphere2_lossy"):
+        print(f"[solve {name}]", flush=True)
+        p = gpu_problem(name)
+        p.set_planewaves(KHAT, E0)
+        r64 = p.solve(0)
+        u64, v64 = p.currents()
+        r32 = p.solve(1)
+        u32, v32 = p.currents()
+        out[name] = dict(p=p, r64=r64, r32=r32, u64=u64, v64=v64, u32=u32, v32=v32)
+        print(f"  fp64 {r64}\n  fp32 {r32}", flush=True)
+    return out
+
+
+def _dense(name):
+    from oracle.rwg import RWGMesh
+    from oracle.solve import DenseProblem
+    build, eps_r, sigma, freq, n, R = CASES[name]
+    m = RWGMesh([build()])
+    return DenseProblem(m, freq, [(eps_r, 1.0, sigma)])
+
+
+def test_converged(solved):
+    for name, s in solved.items():
+        assert s["r64"]["converged"] and s["r64"]["residual"] <= 1e-5, (name, s["r64"])
+        assert s["r32"]["converged"] and s["r32"]["residual"] <= 1e-5, (name, s["r32"])
+
+
+def test_fp32_refined_matches_fp64(solved):
+    for name, s in solved.items():
+        for a, b in ((s["u32"], s["u64"]), (s["v32"], s["v64"])):
+            assert np.linalg.norm(a - b) <= 2e-5 * np.linalg.norm(b), name
+
+
+def test_solution_satisfies_oracle_aim_system(solved):
+    """Block residual of the GPU solution computed with the oracle's AIM
+    operators (same approximation, independent implementation)."""
+    from oracle import physics as ph
+    from oracle.mom import excitation, x_matrix
+    for name, s in solved.items():
+        build, eps_r, sigma, freq, n, R = CASES[name]
+        ext, inn = oracle_aim(name, -1), oracle_aim(name, 0)
+        m = ext.mesh
+        w = ph.omega(freq)
+        X = x_matrix(m)
+        u, v = s["u64"], s["v64"]
+        e = excitation(m, ph.wavenumber(freq, 1.0), KHAT, E0)
+        r1 = e - (1j * w * ph.MU0 * ext.matvec(u, "L") - (ext.matvec(v, "K") - 0.5 * X @ v))
+        et = ph.eps_tilde(freq, eps_r, sigma)
+        r2 = -(-(inn.matvec(u, "K") + 0.5 * X @ u) - 1j * w * et * inn.matvec(v, "L"))
+        rel = np.sqrt(np.linalg.norm(r1) ** 2 + np.linalg.norm(r2) ** 2) / np.linalg.norm(e)
+        assert rel < 1e-5, (name, rel)
+
+
+def test_close_to_dense_solution(solved):
+    """AIM solution vs the dense (unaccelerated) oracle solution on the coarse
+    test grid (12^3, near radius 3).  The lossless eps_r = 4 sphere sits near an
+    interior cavity resonance (k_i a = 6.29), which amplifies the ~1e-3 operator
+    error of this coarse grid in the solution; the lossy sphere does not."""
+    tols = {"sphere2_lossy": 5e-3, "sphere2": 0.1}
+    for name, s in solved.items():
+        dp = _dense(name)
+        e = dp.rhs(KHAT, E0)
+        u, v = dp.solve_block(e)
+        eu = float(np.linalg.norm(s["u64"] - u) / np.linalg.norm(u))
+        ev = float(np.linalg.norm(s["v64"] - v) / np.linalg.norm(v))
+        print(f"{name}: |du|/|u| = {eu:.2e}, |dv|/|v| = {ev:.2e}")
+        assert eu < tols[name] and ev < tols[name], (name, eu, ev)
+
+
+def test_excitation_and_far_field_match_oracle(solved):
+    from oracle import physics as ph
+    from oracle.rwg import RWGMesh
+    from oracle.farfield import far_field, directions
+    s = solved["sphere2"]
+    p = s["p"]
+    m = RWGMesh([mesh_of("sphere2")])
+    k0 = ph.wavenumber(CASES["sphere2"][3], 1.0)
+    th = np.linspace(0.05, np.pi - 0.05, 9)
+    rhat = directions(th, 0.3 + 0 * th)
+    F = p.far_field(rhat)
+    Fo = far_field(m, k0, ph.ETA0, s["u32"], s["v32"], rhat)
+    assert np.abs(F - Fo).max() < 1e-10 * np.abs(Fo).max()
+
+
+def test_rcs_against_mie(solved):
+    from oracle import physics as ph, mie
+    from oracle.farfield import directions
+    s = solved["sphere2"]
+    p = s["p"]
+    build, eps_r, sigma, freq, n, R = CASES["sphere2"]
+    k0 = ph.wavenumber(freq, 1.0)
+    th = np.linspace(0.02, np.pi - 0.02, 41)
+    err2 = ref2 = 0.0
+    for phi in (0.0, np.pi / 2):
+        F = p.far_field(directions(th, phi + 0 * th))
+        r = 4 * np.pi * np.sum(np.abs(F) ** 2, axis=1)
+        mr = mie.bistatic_rcs(k0, 1.0, eps_r, th, phi + 0 * th)
+        err2 += np.sum((r - mr) ** 2); ref2 += np.sum(mr ** 2)
+    assert np.sqrt(err2 / ref2) < 0.10
