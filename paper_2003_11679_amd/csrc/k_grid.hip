@@ -125,35 +125,56 @@ void launch_tri_sources(const Grid &g, const int32_t *tri_rwg_loc, const T *tri_
     SIE_HIP(hipGetLastError());
 }
 
-// Gather projection: one thread per live node.  grid [F][nlive] with
+// Gather projection: `lpn` lanes (a power of two <= 64) per live node share
+// its entry list and reduce with lane shuffles.  grid [F][nlive] with
 // J_c = sum (alpha M1_c - beta_c M0) and (F == 4) Q = sum 2 alpha M0.
+template <typename T>
+__device__ inline T seg_sum(T v, int lpn) {
+    for (int off = lpn >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
 template <typename T>
 __global__ void k_project(int64_t nlive, const int32_t *__restrict__ node_ptr, const int32_t *__restrict__ ent,
                           const T *__restrict__ mom, const cx<T> *__restrict__ src, cx<T> *__restrict__ grid,
-                          int nf) {
-    int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (v >= nlive) return;
-    cx<T> jx, jy, jz, q;
-    for (int k = node_ptr[v]; k < node_ptr[v + 1]; ++k) {
-        const int32_t e = ent[k];
-        const int64_t t = e >> 5;
-        const int a = e & 31;
-        const T *m = mom + (t * 27 + a) * 4;
-        const cx<T> al = src[4 * t], bx = src[4 * t + 1], by = src[4 * t + 2], bz = src[4 * t + 3];
-        jx += m[1] * al - m[0] * bx;
-        jy += m[2] * al - m[0] * by;
-        jz += m[3] * al - m[0] * bz;
-        q += m[0] * al;
+                          int nf, int lpn) {
+    const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t v = gid / lpn;
+    const int sub = (int)(gid % lpn);
+    // every lane of a wave takes part in the shuffles; out-of-range nodes add zeros
+    T s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (v < nlive) {
+        for (int k = node_ptr[v] + sub; k < node_ptr[v + 1]; k += lpn) {
+            const int32_t e = ent[k];
+            const int64_t t = e >> 5;
+            const int a = e & 31;
+            const T *m = mom + (t * 27 + a) * 4;
+            const cx<T> al = src[4 * t], bx = src[4 * t + 1], by = src[4 * t + 2], bz = src[4 * t + 3];
+            s[0] += m[1] * al.re - m[0] * bx.re; s[1] += m[1] * al.im - m[0] * bx.im;
+            s[2] += m[2] * al.re - m[0] * by.re; s[3] += m[2] * al.im - m[0] * by.im;
+            s[4] += m[3] * al.re - m[0] * bz.re; s[5] += m[3] * al.im - m[0] * bz.im;
+            s[6] += m[0] * al.re; s[7] += m[0] * al.im;
+        }
     }
-    grid[v] = jx; grid[nlive + v] = jy; grid[2 * nlive + v] = jz;
-    if (nf == 4) grid[3 * nlive + v] = T(2) * q;
+    for (int i = 0; i < 8; ++i) s[i] = seg_sum(s[i], lpn);
+    if (v < nlive && sub == 0) {
+        grid[v] = cx<T>(s[0], s[1]);
+        grid[nlive + v] = cx<T>(s[2], s[3]);
+        grid[2 * nlive + v] = cx<T>(s[4], s[5]);
+        if (nf == 4) grid[3 * nlive + v] = cx<T>(T(2) * s[6], T(2) * s[7]);
+    }
 }
 
 template <typename T>
 void launch_project(const Grid &g, const T *mom, const cx<T> *trisrc, cx<T> *grid, int nfields, hipStream_t st) {
     const int64_t nlive = g.nlive();
-    hipLaunchKernelGGL(k_project<T>, dim3((unsigned)((nlive + 255) / 256)), dim3(256), 0, st, nlive,
-                       g.d_node_ptr.p, g.d_node_ent.p, mom, trisrc, grid, nfields);
+    // lanes per node: about two entries per lane on average
+    const double avg = 27.0 * (double)g.tris.size() / (double)std::max<int64_t>(nlive, 1);
+    int lpn = 1;
+    while (lpn < 64 && lpn * 2 <= avg / 2.0) lpn *= 2;
+    const int64_t threads = nlive * lpn;
+    hipLaunchKernelGGL(k_project<T>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, nlive,
+                       g.d_node_ptr.p, g.d_node_ent.p, mom, trisrc, grid, nfields, lpn);
     SIE_HIP(hipGetLastError());
 }
 
@@ -219,7 +240,27 @@ __global__ void k_spmv_far(int64_t E, int64_t rwg0, int64_t rwg1, const int64_t 
     cx<T> acc;
     if (vals) {
         const int64_t b = row_ptr[r], e = row_ptr[r + 1];
-        for (int64_t j = b + lane; j < e; j += 64) acc += vals[j] * x[cols[j]];
+        // four independent gathers in flight per lane; values and column
+        // indices are streamed once (non-temporal), x stays cache-resident
+        cx<T> a1, a2, a3;
+        int64_t j = b + lane;
+        for (; j + 192 < e; j += 256) {
+            const int32_t c0 = __builtin_nontemporal_load(cols + j);
+            const int32_t c1 = __builtin_nontemporal_load(cols + j + 64);
+            const int32_t c2 = __builtin_nontemporal_load(cols + j + 128);
+            const int32_t c3 = __builtin_nontemporal_load(cols + j + 192);
+            const T *vp = reinterpret_cast<const T *>(vals + j);
+            const cx<T> v0(__builtin_nontemporal_load(vp), __builtin_nontemporal_load(vp + 1));
+            const cx<T> v1(__builtin_nontemporal_load(vp + 128), __builtin_nontemporal_load(vp + 129));
+            const cx<T> v2(__builtin_nontemporal_load(vp + 256), __builtin_nontemporal_load(vp + 257));
+            const cx<T> v3(__builtin_nontemporal_load(vp + 384), __builtin_nontemporal_load(vp + 385));
+            acc += v0 * x[c0];
+            a1 += v1 * x[c1];
+            a2 += v2 * x[c2];
+            a3 += v3 * x[c3];
+        }
+        for (; j < e; j += 64) acc += vals[j] * x[cols[j]];
+        acc += (a1 + a2) + a3;
         acc = wave_sum(acc);
     }
     if (lane == 0) {

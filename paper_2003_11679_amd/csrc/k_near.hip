@@ -218,47 +218,49 @@ __device__ inline int rule_index_inner(int kind) {
     return kind <= KIND_VERTEX ? 9 : (kind == KIND_CLOSE ? 10 : 11);
 }
 
-__global__ void __launch_bounds__(128) k_near_fill(NearFillArgs a) {
-    const int64_t ntg = a.ntg;
-    // row triangle from pair index by binary search over pair_ptr
-    const int64_t npairs = a.pair_ptr[ntg];
-    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p >= npairs) return;
-    int64_t lo = 0, hi = ntg;   // find tl with pair_ptr[tl] <= p < pair_ptr[tl+1]
-    while (hi - lo > 1) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (a.pair_ptr[mid] <= p) lo = mid; else hi = mid;
-    }
-    const int64_t tl = lo, sl = a.pair_s[p];
-    const int64_t tg = a.tris[tl], sg = a.tris[sl];
-    // classification
+// Classification of a pair: self / edge-adjacent / vertex-adjacent by shared
+// vertices, else close (centroid distance < CLOSE_FACTOR x longest edge) or far.
+// loc: local vertex of t opposite the shared edge (edge) or shared (vertex).
+__device__ inline int classify(const NearFillArgs &a, int64_t tg, int64_t sg, int &loc) {
     int vt[3], vs[3];
     for (int i = 0; i < 3; ++i) { vt[i] = a.tri[3 * tg + i]; vs[i] = a.tri[3 * sg + i]; }
     int nshared = 0, shared_mask = 0;
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j)
             if (vt[i] == vs[j]) { ++nshared; shared_mask |= 1 << i; }
+    loc = 0;
+    if (nshared == 3) return KIND_SELF;
+    if (nshared == 2) { const int m = ~shared_mask & 7; loc = m == 1 ? 0 : (m == 2 ? 1 : 2); return KIND_EDGE; }
+    if (nshared == 1) { loc = shared_mask == 1 ? 0 : (shared_mask == 2 ? 1 : 2); return KIND_VERTEX; }
     const V3 o = {a.centroid[3 * tg], a.centroid[3 * tg + 1], a.centroid[3 * tg + 2]};
     V3 pt[3], ps[3];
     for (int i = 0; i < 3; ++i) {
         pt[i] = V3{a.xyz[3 * (int64_t)vt[i]], a.xyz[3 * (int64_t)vt[i] + 1], a.xyz[3 * (int64_t)vt[i] + 2]} - o;
         ps[i] = V3{a.xyz[3 * (int64_t)vs[i]], a.xyz[3 * (int64_t)vs[i] + 1], a.xyz[3 * (int64_t)vs[i] + 2]} - o;
     }
-    int kind, loc = 0;
-    if (nshared == 3) kind = KIND_SELF;
-    else if (nshared == 2) { kind = KIND_EDGE; loc = (~shared_mask & 7) == 1 ? 0 : ((~shared_mask & 7) == 2 ? 1 : 2); }
-    else if (nshared == 1) { kind = KIND_VERTEX; loc = shared_mask == 1 ? 0 : (shared_mask == 2 ? 1 : 2); }
-    else {
-        double hmax = 0.0;
-        for (int i = 0; i < 3; ++i) {
-            hmax = fmax(hmax, len(pt[(i + 1) % 3] - pt[(i + 2) % 3]));
-            hmax = fmax(hmax, len(ps[(i + 1) % 3] - ps[(i + 2) % 3]));
-        }
-        const V3 cs = V3{a.centroid[3 * sg], a.centroid[3 * sg + 1], a.centroid[3 * sg + 2]} - o;
-        kind = len(cs) < CLOSE_FACTOR * hmax ? KIND_CLOSE : KIND_FAR;
+    double hmax = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        hmax = fmax(hmax, len(pt[(i + 1) % 3] - pt[(i + 2) % 3]));
+        hmax = fmax(hmax, len(ps[(i + 1) % 3] - ps[(i + 2) % 3]));
     }
-    if (kind < a.kind_lo || kind > a.kind_hi) return;
+    const V3 cs = V3{a.centroid[3 * sg], a.centroid[3 * sg + 1], a.centroid[3 * sg + 2]} - o;
+    return len(cs) < CLOSE_FACTOR * hmax ? KIND_CLOSE : KIND_FAR;
+}
 
+// Direct integrals of pair (tl, sl) minus its grid contribution; writes the
+// L, K and direct-L 3x3 blocks of pair slot p.  mt: moments of tl (LDS or
+// global); gr: radial tables in LDS, gr[2 q] = G(h sqrt(q)), gr[2 q + 1] =
+// -(1 + j k r) exp(-j k r)/(4 pi r^3) at r = h sqrt(q), q = |d|^2 (0 at q = 0).
+__device__ void fill_pair(const NearFillArgs &a, int64_t tl, int64_t sl, int64_t p, int kind, int loc,
+                          const double *mt, const c128 *gr) {
+    const int64_t tg = a.tris[tl], sg = a.tris[sl];
+    const V3 o = {a.centroid[3 * tg], a.centroid[3 * tg + 1], a.centroid[3 * tg + 2]};
+    V3 pt[3], ps[3];
+    for (int i = 0; i < 3; ++i) {
+        const int64_t vt = a.tri[3 * tg + i], vs = a.tri[3 * sg + i];
+        pt[i] = V3{a.xyz[3 * vt], a.xyz[3 * vt + 1], a.xyz[3 * vt + 2]} - o;
+        ps[i] = V3{a.xyz[3 * vs], a.xyz[3 * vs + 1], a.xyz[3 * vs + 2]} - o;
+    }
     // source triangle geometry
     SrcTri st;
     for (int i = 0; i < 3; ++i) st.v[i] = ps[i];
@@ -275,11 +277,7 @@ __global__ void __launch_bounds__(128) k_near_fill(NearFillArgs a) {
             st.mh[i] = cross(st.lh[i], st.n);
         }
     }
-    double At;
-    {
-        const V3 c = cross(pt[1] - pt[0], pt[2] - pt[0]);
-        At = 0.5 * len(c);
-    }
+    const double At = 0.5 * len(cross(pt[1] - pt[0], pt[2] - pt[0]));
     const c128 k = a.k;
     const double inv4pi = 0.07957747154594767;   // 1/(4 pi)
     const int ro = rule_index_outer(kind, loc), ri = rule_index_inner(kind);
@@ -323,52 +321,46 @@ __global__ void __launch_bounds__(128) k_near_fill(NearFillArgs a) {
         aS += W * S;
         cadd(aV, CV3{W * V.x, W * V.y, W * V.z});
         cadd(aSR, cscale(W * S, r));
-        // Gv x r
-        const CV3 gxr = ccross_cv(Gv, r);
+        const CV3 gxr = ccross_cv(Gv, r);   // Gv x r
         cadd(aGR, CV3{W * gxr.x, W * gxr.y, W * gxr.z});
         cadd(aG, CV3{W * Gv.x, W * Gv.y, W * Gv.z});
     }
 
-    // precorrection: grid contribution of the pair
-    const int Wt = a.gtab_w, D = 2 * Wt + 1;
+    // precorrection: grid contribution of the pair over the 27 x 27 stencil
+    // node pairs, offsets d = (c_t + o_a) - (c_s + o_b)
     const int dx0 = a.centre[3 * tl] - a.centre[3 * sl];
     const int dy0 = a.centre[3 * tl + 1] - a.centre[3 * sl + 1];
     const int dz0 = a.centre[3 * tl + 2] - a.centre[3 * sl + 2];
+    const double h = a.h;
     c128 S00, S11, C11;
     CV3 S10 = {}, S01 = {}, Vs = {}, Vt = {}, U = {};
-    const double *mt = a.mom + tl * 27 * 4;
     const double *ms = a.mom + sl * 27 * 4;
-    for (int ia = 0; ia < 27; ++ia) {
-        const int ax = ia % 3 - 1, ay = (ia / 3) % 3 - 1, az = ia / 9 - 1;
-        const double m0t = mt[4 * ia];
-        const V3 m1t = {mt[4 * ia + 1], mt[4 * ia + 2], mt[4 * ia + 3]};
-        for (int ib = 0; ib < 27; ++ib) {
-            const int bx = ib % 3 - 1, by = (ib / 3) % 3 - 1, bz = ib / 9 - 1;
-            const int ddx = dx0 + ax - bx + Wt, ddy = dy0 + ay - by + Wt, ddz = dz0 + az - bz + Wt;
-            const c128 *gp = a.gtab + 4 * (((int64_t)ddz * D + ddy) * D + ddx);
-            const c128 G = gp[0];
-            const CV3 g = {gp[1], gp[2], gp[3]};
-            const double m0s = ms[4 * ib];
-            const V3 m1s = {ms[4 * ib + 1], ms[4 * ib + 2], ms[4 * ib + 3]};
+    for (int ib = 0; ib < 27; ++ib) {
+        const int bx = ib % 3 - 1, by = (ib / 3) % 3 - 1, bz = ib / 9 - 1;
+        const double m0s = ms[4 * ib];
+        const V3 m1s = {ms[4 * ib + 1], ms[4 * ib + 2], ms[4 * ib + 3]};
+        for (int ia = 0; ia < 27; ++ia) {
+            const int ddx = dx0 + ia % 3 - 1 - bx, ddy = dy0 + (ia / 3) % 3 - 1 - by, ddz = dz0 + ia / 9 - 1 - bz;
+            const int q = ddx * ddx + ddy * ddy + ddz * ddz;
+            const c128 G = gr[2 * q];
+            const c128 sr = gr[2 * q + 1];
+            const CV3 g = {(h * ddx) * sr, (h * ddy) * sr, (h * ddz) * sr};
+            const double m0t = mt[4 * ia];
+            const V3 m1t = {mt[4 * ia + 1], mt[4 * ia + 2], mt[4 * ia + 3]};
             const double m00 = m0t * m0s;
             S00 += m00 * G;
             S11 += dot(m1t, m1s) * G;
             cadd(S10, cscale(m0s * G, m1t));
             cadd(S01, cscale(m0t * G, m1s));
-            // g . (m1s x m1t)
-            C11 += cdot(cross(m1s, m1t), g);
-            // m0t (g x m1s)
-            const CV3 gxm1s = ccross_cv(g, m1s);
+            C11 += cdot(cross(m1s, m1t), g);                  // g . (m1s x m1t)
+            const CV3 gxm1s = ccross_cv(g, m1s);              // m0t (g x m1s)
             cadd(Vs, CV3{m0t * gxm1s.x, m0t * gxm1s.y, m0t * gxm1s.z});
-            // m0s (m1t x g) = -m0s (g x m1t)
-            const CV3 gxm1t = ccross_cv(g, m1t);
+            const CV3 gxm1t = ccross_cv(g, m1t);              // m0s (m1t x g)
             cadd(Vt, CV3{-m0s * gxm1t.x, -m0s * gxm1t.y, -m0s * gxm1t.z});
             cadd(U, CV3{m00 * g.x, m00 * g.y, m00 * g.z});
         }
     }
-    // k^-2
-    const c128 k2 = k * k;
-    const c128 ik2 = cdiv(c128(1.0), k2);
+    const c128 ik2 = cdiv(c128(1.0), k * k);
     const double *ct = a.tri_coef + tl * 12;
     const double *cs = a.tri_coef + sl * 12;
     c128 *out = a.blocks + p * 27;
@@ -394,10 +386,115 @@ __global__ void __launch_bounds__(128) k_near_fill(NearFillArgs a) {
     }
 }
 
+// Radial Green's tables for |d|^2 = 0 .. nq-1 (grid offsets in cells).
+__global__ void k_green_radial(c128 k, double h, int nq, c128 *gr) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    if (q == 0) { gr[0] = c128(); gr[1] = c128(); return; }
+    const double r = h * sqrt((double)q);
+    const double inv4pi = 0.07957747154594767;
+    const c128 e = cexp_mjk(k, r);
+    gr[2 * q] = (inv4pi / r) * e;
+    const c128 onejkr(1.0 - k.im * r, k.re * r);
+    gr[2 * q + 1] = (-inv4pi / (r * r * r)) * (onejkr * e);
+}
+
+__device__ inline void load_radial(const c128 *g, int nq, c128 *lds) {
+    for (int i = threadIdx.x; i < 2 * nq; i += blockDim.x) lds[i] = g[i];
+}
+
+// Pass 0 counts, pass 1 appends, the non-far pairs of each kind (lists[kind]).
+__global__ void k_near_classify(NearFillArgs a, int64_t ntg, int pass, unsigned long long *counts,
+                                int64_t *lists0, int64_t *lists1, int64_t *lists2, int64_t *lists3) {
+    const int64_t tl = blockIdx.x;
+    if (tl >= ntg) return;
+    const int64_t tg = a.tris[tl];
+    for (int64_t p = a.pair_ptr[tl] + threadIdx.x; p < a.pair_ptr[tl + 1]; p += blockDim.x) {
+        int loc;
+        const int kind = classify(a, tg, a.tris[a.pair_s[p]], loc);
+        if (kind == KIND_FAR) continue;
+        const unsigned long long i = atomicAdd(&counts[kind], 1ull);
+        if (pass == 1) {
+            int64_t *L = kind == 0 ? lists0 : (kind == 1 ? lists1 : (kind == 2 ? lists2 : lists3));
+            L[i] = (p << 2) | loc;
+        }
+    }
+}
+
+// Far pairs: one workgroup per row triangle; its moments and the radial
+// tables live in LDS.
+__global__ void __launch_bounds__(128) k_near_fill_far(NearFillArgs a, int64_t ntg) {
+    extern __shared__ unsigned char smem[];
+    c128 *gr = reinterpret_cast<c128 *>(smem);
+    double *mt = reinterpret_cast<double *>(gr + 2 * a.nq);
+    const int64_t tl = blockIdx.x;
+    if (tl >= ntg) return;
+    load_radial(a.gradial, a.nq, gr);
+    for (int i = threadIdx.x; i < 108; i += blockDim.x) mt[i] = a.mom[tl * 108 + i];
+    __syncthreads();
+    const int64_t tg = a.tris[tl];
+    for (int64_t p = a.pair_ptr[tl] + threadIdx.x; p < a.pair_ptr[tl + 1]; p += blockDim.x) {
+        const int64_t sl = a.pair_s[p];
+        int loc;
+        if (classify(a, tg, a.tris[sl], loc) != KIND_FAR) continue;
+        fill_pair(a, tl, sl, p, KIND_FAR, 0, mt, gr);
+    }
+}
+
+// Listed (touching / close) pairs of one kind: one thread per pair.
+__global__ void __launch_bounds__(128) k_near_fill_list(NearFillArgs a, int64_t ntg, const int64_t *list, int64_t n,
+                                                        int kind) {
+    extern __shared__ unsigned char smem[];
+    c128 *gr = reinterpret_cast<c128 *>(smem);
+    load_radial(a.gradial, a.nq, gr);
+    __syncthreads();
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t e = list[i];
+    const int64_t p = e >> 2;
+    const int loc = (int)(e & 3);
+    int64_t lo = 0, hi = ntg;   // row: pair_ptr[tl] <= p < pair_ptr[tl + 1]
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (a.pair_ptr[mid] <= p) lo = mid; else hi = mid;
+    }
+    fill_pair(a, lo, a.pair_s[p], p, kind, loc, a.mom + lo * 108, gr);
+}
+
+void launch_green_radial(c128 k, double h, int nq, c128 *gr, hipStream_t st) {
+    hipLaunchKernelGGL(k_green_radial, dim3((nq + 255) / 256), dim3(256), 0, st, k, h, nq, gr);
+    SIE_HIP(hipGetLastError());
+}
+
 void launch_near_fill(const NearFillArgs &a, int64_t npairs, hipStream_t st) {
     if (!npairs) return;
-    hipLaunchKernelGGL(k_near_fill, dim3((unsigned)((npairs + 127) / 128)), dim3(128), 0, st, a);
+    const int64_t ntg = a.ntg;
+    const size_t sh_rad = 2 * (size_t)a.nq * sizeof(c128);
+    // classify non-far pairs into per-kind lists
+    DBuf<unsigned long long> counts(4);
+    SIE_HIP(hipMemsetAsync(counts.p, 0, 4 * sizeof(unsigned long long), st));
+    hipLaunchKernelGGL(k_near_classify, dim3((unsigned)ntg), dim3(128), 0, st, a, ntg, 0, counts.p, nullptr, nullptr,
+                       nullptr, nullptr);
     SIE_HIP(hipGetLastError());
+    std::vector<unsigned long long> cnt(4);
+    SIE_HIP(hipMemcpyAsync(cnt.data(), counts.p, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    SIE_HIP(hipStreamSynchronize(st));
+    DBuf<int64_t> lists[4];
+    for (int kd = 0; kd < 4; ++kd) lists[kd].alloc(std::max<unsigned long long>(cnt[kd], 1));
+    SIE_HIP(hipMemsetAsync(counts.p, 0, 4 * sizeof(unsigned long long), st));
+    hipLaunchKernelGGL(k_near_classify, dim3((unsigned)ntg), dim3(128), 0, st, a, ntg, 1, counts.p, lists[0].p,
+                       lists[1].p, lists[2].p, lists[3].p);
+    SIE_HIP(hipGetLastError());
+    // far pairs per row triangle
+    hipLaunchKernelGGL(k_near_fill_far, dim3((unsigned)ntg), dim3(128), sh_rad + 108 * sizeof(double), st, a, ntg);
+    SIE_HIP(hipGetLastError());
+    for (int kd = 0; kd < 4; ++kd) {
+        if (!cnt[kd]) continue;
+        hipLaunchKernelGGL(k_near_fill_list, dim3((unsigned)((cnt[kd] + 127) / 128)), dim3(128), sh_rad, st, a, ntg,
+                           lists[kd].p, (int64_t)cnt[kd], kd);
+        SIE_HIP(hipGetLastError());
+    }
+    SIE_HIP(hipStreamSynchronize(st));
 }
 
 // Deterministic CSR assembly: entry (m, n) sums the blocks of the (at most 4)
@@ -473,22 +570,6 @@ __device__ inline void green_at(c128 k, double h, int dx, int dy, int dz, c128 o
     const c128 onejkr(1.0 - k.im * r, k.re * r);
     const c128 s = (-inv4pi / (r * r * r)) * (onejkr * e);
     out[1] = rx * s; out[2] = ry * s; out[3] = rz * s;
-}
-
-__global__ void k_green_table(c128 k, double h, int W, c128 *tab) {
-    const int D = 2 * W + 1;
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= (int64_t)D * D * D) return;
-    const int dx = (int)(i % D) - W, dy = (int)((i / D) % D) - W, dz = (int)(i / ((int64_t)D * D)) - W;
-    c128 g[4];
-    green_at(k, h, dx, dy, dz, g);
-    for (int c = 0; c < 4; ++c) tab[4 * i + c] = g[c];
-}
-
-void launch_green_table(c128 k, double h, int W, c128 *tab, hipStream_t st) {
-    const int64_t n = (int64_t)(2 * W + 1) * (2 * W + 1) * (2 * W + 1);
-    hipLaunchKernelGGL(k_green_table, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, k, h, W, tab);
-    SIE_HIP(hipGetLastError());
 }
 
 // Circulant embedding of G (kind 0) or dG/dx_(kind-1) on [mz][my][mx]:

@@ -49,8 +49,8 @@ struct NearFillArgs {
     const double *centroid; const double *tri_coef; const double *mom;
     const int64_t *pair_ptr; const int32_t *pair_s; int64_t ntg;
     const double *rules; const int *rule_off; const int *rule_n;   // packed rules
-    const c128 *gtab; int gtab_w;    // grid G / grad G table over offsets [-W, W]^3, 4 comps
-    c128 k; double h; int kind_lo, kind_hi;
+    const c128 *gradial; int nq;     // radial tables (G, grad G / (h d)) for |d|^2 < nq
+    c128 k; double h;
     c128 *blocks;                    // [npairs][3][3][3]: L, K (precorrected), L direct
 };
 void launch_near_fill(const NearFillArgs &a, int64_t npairs, hipStream_t st);
@@ -58,7 +58,7 @@ void launch_near_gather(int64_t nrow, int64_t rwg0, int64_t max_row, const int64
                         const int32_t *rwg_loc, const int32_t *glob2loc, const int32_t *tpm, const int32_t *epm,
                         const int64_t *pair_ptr, const int32_t *pair_s, const c128 *blocks, c128 *nL64,
                         c128 *nK64, c128 *nLd64, hipStream_t st);
-void launch_green_table(c128 k, double h, int W, c128 *tab, hipStream_t st);
+void launch_green_radial(c128 k, double h, int nq, c128 *gr, hipStream_t st);
 void launch_green_sample(c128 k, double h, const int nl[3], const int m[3], int kind, c128 *vol, hipStream_t st);
 void launch_fold_octant(const c128 *vol, const int m[3], int kind, double scale, c128 *spec64, c64 *spec32,
                         hipStream_t st);
