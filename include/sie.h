@@ -167,14 +167,16 @@ sie_status sie_get_wavenumber(const sie_problem *p, int32_t medium, sie_c128 *k)
  * ignored. */
 sie_status sie_matvec(sie_problem *p, int32_t medium, sie_op op, sie_precision prec, int32_t nrhs,
                       const void *x_dev, void *y_dev, void *stream);
-/* The four stages of one L-type product, exposed for stage-level checks:
- * grid sources [4][nl_z][nl_y][nl_x] (J_x, J_y, J_z, charge; x fastest) from
- * RWG coefficients (projection P, P_phi); the zero-padded FFT convolution of
- * nfields such grids with G (kind 0) on the live box; interpolation W back to
- * RWG (vector fields minus k^-2 times the scalar field). */
+/* The stages of one AIM product, exposed for stage-level checks: grid
+ * sources [4][nl_z][nl_y][nl_x] (J_x, J_y, J_z, charge; x fastest) from RWG
+ * coefficients (projection P, P_phi); the zero-padded FFT convolution on the
+ * live box (Sec. III-D-1), op = SIE_OP_L: each of nfields (1..4) grids with
+ * G, op = SIE_OP_K: the 3 grids (J_x, J_y, J_z) to grad G x J (nfields = 3);
+ * interpolation W back to RWG (vector fields minus k^-2 times the scalar
+ * field).  in and out may be the same buffer. */
 sie_status sie_project(sie_problem *p, int32_t medium, sie_precision prec, const void *x_dev,
                        void *grid_dev, void *stream);
-sie_status sie_convolve(sie_problem *p, int32_t medium, sie_precision prec, int32_t nfields,
+sie_status sie_convolve(sie_problem *p, int32_t medium, sie_op op, sie_precision prec, int32_t nfields,
                         const void *grid_in_dev, void *grid_out_dev, void *stream);
 sie_status sie_interpolate(sie_problem *p, int32_t medium, sie_precision prec,
                            const void *grid_dev, void *y_dev, void *stream);

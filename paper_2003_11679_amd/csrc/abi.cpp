@@ -226,16 +226,17 @@ sie_status sie_project(sie_problem *p, int32_t medium, sie_precision prec, const
     });
 }
 
-sie_status sie_convolve(sie_problem *p, int32_t medium, sie_precision prec, int32_t nfields, const void *in_dev,
-                        void *out_dev, void *stream) {
+sie_status sie_convolve(sie_problem *p, int32_t medium, sie_op op, sie_precision prec, int32_t nfields,
+                        const void *in_dev, void *out_dev, void *stream) {
     return guard([&] {
         SIE_CHECK(p && p->is_setup, SIE_ESTATE, "problem not set up");
         SIE_CHECK(in_dev && out_dev, SIE_EINVAL, "NULL pointer");
+        SIE_CHECK(op == SIE_OP_L || op == SIE_OP_K, SIE_EINVAL, "convolution op must be L (G) or K (grad G x)");
         Medium &md = p->medium(medium);
         if (prec == SIE_FP64)
-            stage_convolve<double>(p, md, nfields, (const c128 *)in_dev, (c128 *)out_dev, (hipStream_t)stream);
+            stage_convolve<double>(p, md, op, nfields, (const c128 *)in_dev, (c128 *)out_dev, (hipStream_t)stream);
         else
-            stage_convolve<float>(p, md, nfields, (const c64 *)in_dev, (c64 *)out_dev, (hipStream_t)stream);
+            stage_convolve<float>(p, md, op, nfields, (const c64 *)in_dev, (c64 *)out_dev, (hipStream_t)stream);
     });
 }
 

@@ -12,172 +12,512 @@
 //   x inverse   A -> out[F][nz][ny][nx] (keep nx)
 // Zero padding is never stored: a pass reads only the live prefix of its
 // lines and writes only what the next pass reads.
+//
+// Inside a block a tile of lines sits in LDS and is transformed by
+// radix-8 (then 4 or 2) Stockham stages whose butterflies run in
+// registers.  The line length is a template parameter, so LDS offsets fold
+// into instruction immediates; global addresses are a uniform base plus a
+// per-thread 32-bit offset plus a uniform step per register slot.
 #include "common.h"
 #include "kernels.h"
 
+#include <algorithm>
+#include <atomic>
+
 namespace sie {
 
-template <typename T> __device__ inline void sincospi_t(T x, T *s, T *c);
-template <> __device__ inline void sincospi_t<double>(double x, double *s, double *c) { sincospi(x, s, c); }
-template <> __device__ inline void sincospi_t<float>(float x, float *s, float *c) { sincospif(x, s, c); }
+// LDS tiles store element j of a line at j + j/8: one pad slot every eight
+// elements, so that the stride-R writes of the early Stockham stages fall
+// on distinct banks.  Lines are padded_pitch(L) apart.
+__device__ inline int padj(int j) { return j + (j >> 3); }
+__host__ __device__ constexpr int padded_pitch(int L) { return L + (L >> 3) + 1; }
 
-// Radix-2 Stockham transform of `nl` lines of length L held in LDS (line-major,
-// row pitch `pitch`).  Ping-pongs between a and b; returns the buffer holding
-// the result.  sign = -1 forward, +1 inverse (unscaled).
-template <typename T>
-__device__ cx<T> *lds_fft(cx<T> *a, cx<T> *b, int L, int nl, int pitch, T sign) {
-    const int half = L >> 1;
-    const int total = nl * half;
-    for (int p = 1; p < L; p <<= 1) {
-        for (int it = threadIdx.x; it < total; it += blockDim.x) {
-            const int line = it / half;
-            const int i = it - line * half;
-            const int k = i & (p - 1);
-            cx<T> u0 = a[line * pitch + i];
-            cx<T> u1 = a[line * pitch + i + half];
-            T s, c;
-            sincospi_t<T>(sign * T(k) / T(p), &s, &c);
-            cx<T> w(c, s);
-            u1 = w * u1;
-            const int j = (i << 1) - k;
-            b[line * pitch + j] = u0 + u1;
-            b[line * pitch + j + p] = u0 - u1;
-        }
-        __syncthreads();
-        cx<T> *t = a; a = b; b = t;
-    }
-    return a;
+// padj(j0 + r * S) for a compile-time stride S: separable when S is a
+// multiple of 8 (then the pad of the step is exact).
+template <int S>
+__device__ inline int padj_step(int j0, int r) {
+    if constexpr (S % 8 == 0) return padj(j0) + r * (S + S / 8);
+    else return padj(j0 + r * S);
 }
 
-// Generic pass: lines of length L along an axis with element strides
-// (s_in, s_out); the block handles `tx` lines.  Line (b, j) starts at
-// in + b*bs_in + j*js_in.  j runs over [0, nj), b over gridDim.y * (tiles).
-// contiguous: element stride 1 (x passes) -> threads walk along lines;
-// otherwise lines are adjacent in memory (js = 1) -> threads walk across lines.
+// Half twiddle table exp(-2 pi i j / L), j < L/2, built per block in LDS
+// (FP64 sincospi, rounded to T).  A stage reads only w^j1, w^2j1 and w^4j1
+// with j1 < L/(2R), so every index stays below L/2.
+__host__ __device__ constexpr int twiddle_len(int L) { return L >= 2 ? L / 2 : 1; }
+
 template <typename T>
-__global__ void k_fft_pass(const cx<T> *__restrict__ in, cx<T> *__restrict__ out, int L, int n_in,
-                           int n_out, long s_in, long s_out, long js_in, long js_out, long bs_in,
-                           long bs_out, int nj, int tx, int contiguous, T sign) {
+__device__ inline void init_twiddles(cx<T> *tw, int L) {
+    for (int j = threadIdx.x; j < twiddle_len(L); j += blockDim.x) {
+        double sn, cs;
+        sincospi(-2.0 * (double)j / (double)L, &sn, &cs);
+        tw[j] = cx<T>((T)cs, (T)sn);
+    }
+}
+
+// -i a (forward) or +i a (inverse)
+template <typename T, bool INV>
+__device__ inline cx<T> rot_mi(cx<T> a) {
+    return INV ? cx<T>(-a.im, a.re) : cx<T>(a.im, -a.re);
+}
+
+// In-register DFTs of length 2, 4, 8; forward exp(-2 pi i rq/R), inverse +.
+template <typename T>
+__device__ inline void dft2(cx<T> *u) {
+    const cx<T> a = u[0], b = u[1];
+    u[0] = a + b;
+    u[1] = a - b;
+}
+template <typename T, bool INV>
+__device__ inline void dft4(cx<T> *u) {
+    const cx<T> s02 = u[0] + u[2], d02 = u[0] - u[2], s13 = u[1] + u[3], d13 = u[1] - u[3];
+    const cx<T> jd = rot_mi<T, INV>(d13);
+    u[0] = s02 + s13;
+    u[2] = s02 - s13;
+    u[1] = d02 + jd;
+    u[3] = d02 - jd;
+}
+template <typename T, bool INV>
+__device__ inline void dft8(cx<T> *u) {
+    cx<T> e[4] = {u[0], u[2], u[4], u[6]}, o[4] = {u[1], u[3], u[5], u[7]};
+    dft4<T, INV>(e);
+    dft4<T, INV>(o);
+    const T r2 = T(0.70710678118654752440);
+    // w = exp(-+ 2 pi i / 8): w^1 = (1 -+ i)/sqrt2, w^2 = -+ i, w^3 = (-1 -+ i)/sqrt2
+    const cx<T> o1 = r2 * (o[1] + rot_mi<T, INV>(o[1]));
+    const cx<T> o2 = rot_mi<T, INV>(o[2]);
+    const cx<T> o3 = r2 * (rot_mi<T, INV>(o[3]) - o[3]);
+    u[0] = e[0] + o[0]; u[4] = e[0] - o[0];
+    u[1] = e[1] + o1;   u[5] = e[1] - o1;
+    u[2] = e[2] + o2;   u[6] = e[2] - o2;
+    u[3] = e[3] + o3;   u[7] = e[3] - o3;
+}
+template <typename T, int R, bool INV>
+__device__ inline void dftR(cx<T> *u) {
+    if constexpr (R == 2) dft2(u);
+    else if constexpr (R == 4) dft4<T, INV>(u);
+    else dft8<T, INV>(u);
+}
+
+// One radix-R Stockham stage over nl lines of length L = 2^LGL in LDS, in
+// place: each thread stages NB = VPT/R butterflies in registers between two
+// barriers (the block has NT threads and nl * L <= NT * VPT).  p = 2^LGP is
+// the product of the earlier radices; butterfly i (k = i mod p) takes
+// x[i + r L/R] times w^(r k L/(p R)) and writes its DFT_R outputs to
+// ((i - k) R + k + r p).
+// Slot b of thread t: when a line has at most NT butterflies, butterfly
+// t mod (L/R) of line t / (L/R) + b NT/(L/R) (so the twiddles are the same
+// for all b); otherwise butterfly t + (b mod BPL) NT of line b / BPL, with
+// BPL = (L/R)/NT slots per line.
+template <typename T, int R, int NT, int VPT, int LGL, int LGP, bool INV>
+__device__ inline void fft_stage(cx<T> *buf, int nl, const cx<T> *tw) {
+    constexpr int L = 1 << LGL, PITCH = padded_pitch(L);
+    constexpr int LGR = R == 8 ? 3 : (R == 4 ? 2 : 1);
+    constexpr int NB = VPT / R;
+    static_assert(NB >= 1, "too few values per thread for this radix");
+    constexpr int LGNBF = LGL - LGR;
+    constexpr int NBF = 1 << LGNBF;
+    constexpr bool WIDE = NBF > NT;
+    constexpr int BPL = WIDE ? NBF / NT : 1;
+    constexpr int DLINE = WIDE ? 0 : NT >> LGNBF;
+    constexpr int P = 1 << LGP;
+    constexpr int LGTWS = LGL - LGP - LGR;
+    const int tid = threadIdx.x;
+    auto bf_i = [&](int b) { return WIDE ? tid + (b % BPL) * NT : tid & (NBF - 1); };
+    auto bf_line = [&](int b) { return WIDE ? b / BPL : (tid >> LGNBF) + b * DLINE; };
+
+    // w^(r k L/(p R)), r = 1..R-1: powers 1, 2, 4 from the table, the
+    // others as products of those
+    auto twiddles = [&](int k, cx<T> *w) {
+        const int j1 = k << LGTWS;
+        w[1] = tw[j1];
+        if constexpr (R >= 4) {
+            w[2] = tw[2 * j1];
+            w[3] = w[1] * w[2];
+        }
+        if constexpr (R == 8) {
+            w[4] = tw[4 * j1];
+            w[5] = w[1] * w[4];
+            w[6] = w[2] * w[4];
+            w[7] = w[3] * w[4];
+        }
+        if constexpr (INV) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) w[r] = conj(w[r]);
+        }
+    };
+    constexpr bool SHARED_TW = !WIDE || P <= NT;   // k independent of b
+    cx<T> w[R];
+    if constexpr (P > 1 && SHARED_TW) twiddles(bf_i(0) & (P - 1), w);
+
+    cx<T> u[NB][R];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int i = bf_i(b), line = bf_line(b);
+        if (line < nl) {
+            const cx<T> *rd = buf + line * PITCH;
+#pragma unroll
+            for (int r = 0; r < R; ++r) u[b][r] = rd[padj_step<NBF>(i, r)];
+            if constexpr (P > 1) {
+                cx<T> wb[R];
+                if constexpr (!SHARED_TW) twiddles(i & (P - 1), wb);
+#pragma unroll
+                for (int r = 1; r < R; ++r) u[b][r] = (SHARED_TW ? w[r] : wb[r]) * u[b][r];
+            }
+            dftR<T, R, INV>(u[b]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int i = bf_i(b), line = bf_line(b);
+        if (line < nl) {
+            const int k = i & (P - 1);
+            const int j = ((i - k) << LGR) + k;
+            cx<T> *wr = buf + line * PITCH;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                int o;
+                if constexpr (P == 1 && R == 8) o = padj(j) + r;   // j = 8 i: no carry into j / 8
+                else o = padj_step<P>(j, r);
+                wr[o] = u[b][r];
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Full transform of nl lines of length 2^LGL, natural order in and out;
+// radix 8 while at least three factors of two remain, then 4 or 2.  The
+// stage sequence is fixed at compile time so that every stage's registers
+// are allocated on their own.
+template <typename T, int NT, int VPT, int LGL, bool INV, int LGP = 0>
+__device__ inline void lds_fft(cx<T> *buf, int nl, const cx<T> *tw) {
+    if constexpr (LGP < LGL) {
+        constexpr int rem = LGL - LGP;
+        constexpr int LGR = rem >= 3 ? 3 : rem;
+        fft_stage<T, 1 << LGR, NT, VPT, LGL, LGP, INV>(buf, nl, tw);
+        lds_fft<T, NT, VPT, LGL, INV, LGP + LGR>(buf, nl, tw);
+    }
+}
+
+// Generic pass: tx = 2^lgtx lines of length L = 2^LGL per block along one
+// axis.  Line (b, j) starts at in + b*bs_in + j*js_in.
+//   CONTIG: element stride 1 (x passes); threads walk along lines.
+//   otherwise adjacent lines are adjacent in memory (stride 1 between
+//   lines, s between elements) and threads walk across lines, so each row
+//   segment of the tile is one coalesced access.
+// Element q of thread t is (line0 + dline(q), pos0 + dpos(q)) with
+// dline/dpos uniform.  Zero padding beyond n_in; only n_out outputs written.
+template <typename T, int NT, int VPT, int LGL, bool CONTIG, bool INV, int MINW>
+__global__ void __launch_bounds__(NT, MINW) k_fft_pass(const cx<T> *__restrict__ in, cx<T> *__restrict__ out,
+                                                       int n_in, int n_out, int s_in, int s_out, int js_in,
+                                                       int js_out, long bs_in, long bs_out, int nj, int lgtx) {
+    constexpr int L = 1 << LGL, PITCH = padded_pitch(L);
     extern __shared__ unsigned char smem_raw[];
-    cx<T> *buf0 = reinterpret_cast<cx<T> *>(smem_raw);
-    const int pitch = L + 1;
-    cx<T> *buf1 = buf0 + tx * pitch;
-    const int j0 = blockIdx.x * tx;
-    const long b = blockIdx.y;
+    cx<T> *tw = reinterpret_cast<cx<T> *>(smem_raw);
+    cx<T> *buf = tw + twiddle_len(L);
+    const int tx = 1 << lgtx;
+    const int j0 = blockIdx.x << lgtx;
     const int nlines = min(tx, nj - j0);
-    const cx<T> *src = in + b * bs_in + (long)j0 * js_in;
-    cx<T> *dst = out + b * bs_out + (long)j0 * js_out;
-    const int total = tx * L;
-    for (int it = threadIdx.x; it < total; it += blockDim.x) {
-        int line, pos;
-        if (contiguous) { line = it / L; pos = it - line * L; }
-        else { pos = it / tx; line = it - pos * tx; }
-        cx<T> v;
-        if (line < nlines && pos < n_in) v = src[(long)line * js_in + (long)pos * s_in];
-        buf0[line * pitch + pos] = v;
+    const cx<T> *src = in + (long)blockIdx.y * bs_in + (long)j0 * (CONTIG ? js_in : 1);
+    cx<T> *dst = out + (long)blockIdx.y * bs_out + (long)j0 * (CONTIG ? js_out : 1);
+    const int tid = threadIdx.x;
+    const int line0 = CONTIG ? tid >> LGL : tid & (tx - 1);
+    const int pos0 = CONTIG ? tid & (L - 1) : tid >> lgtx;
+    auto dline = [&](int q) { return CONTIG ? (q * NT) >> LGL : 0; };
+    auto dpos = [&](int q) { return CONTIG ? (q * NT) & (L - 1) : (q * NT) >> lgtx; };
+    auto in_tile = [&](int q) { return CONTIG ? line0 + dline(q) < tx : pos0 + dpos(q) < L; };
+    const int goff_in = CONTIG ? line0 * js_in + pos0 : line0 + pos0 * s_in;
+    const int goff_out = CONTIG ? line0 * js_out + pos0 : line0 + pos0 * s_out;
+    const int loff = line0 * PITCH + padj(pos0);   // dpos(q) is a multiple of 8
+
+    cx<T> r[VPT];
+#pragma unroll
+    for (int q = 0; q < VPT; ++q) {
+        const int dl = dline(q), dp = dpos(q);
+        if (line0 + dl < nlines && pos0 + dp < n_in)
+            r[q] = src[goff_in + (CONTIG ? dl * js_in + dp : dp * s_in)];
+        else
+            r[q] = cx<T>();
     }
+    init_twiddles(tw, L);
+#pragma unroll
+    for (int q = 0; q < VPT; ++q)
+        if (in_tile(q)) buf[loff + dline(q) * PITCH + dpos(q) + dpos(q) / 8] = r[q];
     __syncthreads();
-    cx<T> *res = lds_fft<T>(buf0, buf1, L, tx, pitch, sign);
-    const int totalo = tx * n_out;
-    for (int it = threadIdx.x; it < totalo; it += blockDim.x) {
-        int line, pos;
-        if (contiguous) { line = it / n_out; pos = it - line * n_out; }
-        else { pos = it / tx; line = it - pos * tx; }
-        if (line < nlines) dst[(long)line * js_out + (long)pos * s_out] = res[line * pitch + pos];
+    lds_fft<T, NT, VPT, LGL, INV>(buf, tx, tw);
+    // gather the whole tile from LDS first, then issue the global stores
+#pragma unroll
+    for (int q = 0; q < VPT; ++q)
+        if (in_tile(q)) r[q] = buf[loff + dline(q) * PITCH + dpos(q) + dpos(q) / 8];
+#pragma unroll
+    for (int q = 0; q < VPT; ++q) {
+        const int dl = dline(q), dp = dpos(q);
+        if (line0 + dl < nlines && pos0 + dp < n_out) dst[goff_out + (CONTIG ? dl * js_out + dp : dp * s_out)] = r[q];
     }
 }
 
-// Octant lookup of a spectrum that is even (kind 0) or odd along axis
-// (kind - 1) (kinds 1..3 = dG/dx, dG/dy, dG/dz).
-template <typename T>
-__device__ inline cx<T> spec_at(const cx<T> *spec, long oct, int kind, int kx, int ky, int kz,
-                                int mx, int my, int mz) {
-    int fx = kx <= mx / 2 ? kx : mx - kx;
-    int fy = ky <= my / 2 ? ky : my - ky;
-    int fz = kz <= mz / 2 ? kz : mz - kz;
-    cx<T> v = spec[(long)kind * oct + ((long)fz * (my / 2 + 1) + fy) * (mx / 2 + 1) + fx];
-    bool neg = (kind == 1 && kx > mx / 2) || (kind == 2 && ky > my / 2) || (kind == 3 && kz > mz / 2);
-    return neg ? -v : v;
-}
-
-// Fused z pass.  buf [F][nz][my][mx]; lines along z (stride my*mx), tiles of
-// tx consecutive x.  mode 0: every field times G (scalar kernel).  mode 1:
-// the three fields (J_x, J_y, J_z) are replaced by grad G x J:
-//   psi_x = Gy Jz - Gz Jy,  psi_y = Gz Jx - Gx Jz,  psi_z = Gx Jy - Gy Jx.
-template <typename T>
-__global__ void k_fft_zpass(cx<T> *__restrict__ buf, const cx<T> *__restrict__ spec, int mx, int my,
-                            int mz, int nz, int nf, int tx, int mode) {
+// Fused z pass.  buf [F][nz][my][mx]; a block owns a tile of tx = 2^lgtx
+// consecutive x at one ky and runs its z lines (length mz = 2^LGL) field by
+// field through LDS: forward z, spectral product, inverse z, keep nz.
+// Element q of thread t is (kz, xi) = (t / tx + q NT / tx, t mod tx).
+//   MODE 0: field blockIdx.z times G (the blocks of the nf fields read the
+//           same spectrum values; the folded spectrum is small enough to
+//           stay cached between them).
+//   MODE 1: the three fields (J_x, J_y, J_z) become grad G x J,
+//           psi_x = Gy Jz - Gz Jy, psi_y = Gz Jx - Gx Jz, psi_z = Gx Jy - Gy Jx;
+//           the transformed fields are held in registers until all three
+//           are known.
+// The spectrum is stored on its (mx/2+1)(my/2+1)(mz/2+1) octant: G is even
+// along every axis, dG/dx_a odd along axis a (kinds 1..3).
+template <typename T, int NT, int VPT, int LGL, int MODE, int MINW>
+__global__ void __launch_bounds__(NT, MINW) k_fft_zpass(cx<T> *__restrict__ buf, const cx<T> *__restrict__ spec,
+                                                        int mx, int my, int nz, int lgtx) {
+    constexpr int mz = 1 << LGL, PITCH = padded_pitch(mz);
     extern __shared__ unsigned char smem_raw[];
-    const int nfb = mode == 1 ? 3 : 1;        // fields per block
-    const int pitch = mz + 1;
-    cx<T> *buf0 = reinterpret_cast<cx<T> *>(smem_raw);
-    cx<T> *buf1 = buf0 + nfb * tx * pitch;
-    const int x0 = blockIdx.x * tx;
+    cx<T> *tw = reinterpret_cast<cx<T> *>(smem_raw);
+    cx<T> *lb = tw + twiddle_len(mz);
+    const int tx = 1 << lgtx;
+    const int x0 = blockIdx.x << lgtx;
     const int ky = blockIdx.y;
-    const int f0 = mode == 1 ? 0 : blockIdx.z;
     const int nlines = min(tx, mx - x0);
-    const long plane = (long)my * mx;
+    const int plane = my * mx;
     const long fstride = (long)nz * plane;
-    const long oct = (long)(mx / 2 + 1) * (my / 2 + 1) * (mz / 2 + 1);
-    const int nl = nfb * tx;                  // LDS lines: (field, x)
-    for (int it = threadIdx.x; it < nl * mz; it += blockDim.x) {
-        int pos = it / nl, l = it - pos * nl;
-        int f = l / tx, xi = l - f * tx;
-        cx<T> v;
-        if (xi < nlines && pos < nz) v = buf[(long)(f0 + f) * fstride + pos * plane + (long)ky * mx + x0 + xi];
-        buf0[l * pitch + pos] = v;
-    }
-    __syncthreads();
-    cx<T> *res = lds_fft<T>(buf0, buf1, mz, nl, pitch, T(-1));
-    cx<T> *oth = res == buf0 ? buf1 : buf0;
-    // spectral product
-    for (int it = threadIdx.x; it < tx * mz; it += blockDim.x) {
-        int kz = it / tx, xi = it - kz * tx;
-        int kx = x0 + xi;
-        if (xi >= nlines) continue;
-        if (mode == 0) {
-            cx<T> g = spec_at<T>(spec, oct, 0, kx, ky, kz, mx, my, mz);
-            res[xi * pitch + kz] = g * res[xi * pitch + kz];
-        } else {
-            cx<T> gx = spec_at<T>(spec, oct, 1, kx, ky, kz, mx, my, mz);
-            cx<T> gy = spec_at<T>(spec, oct, 2, kx, ky, kz, mx, my, mz);
-            cx<T> gz = spec_at<T>(spec, oct, 3, kx, ky, kz, mx, my, mz);
-            cx<T> jx = res[(0 * tx + xi) * pitch + kz];
-            cx<T> jy = res[(1 * tx + xi) * pitch + kz];
-            cx<T> jz = res[(2 * tx + xi) * pitch + kz];
-            res[(0 * tx + xi) * pitch + kz] = gy * jz - gz * jy;
-            res[(1 * tx + xi) * pitch + kz] = gz * jx - gx * jz;
-            res[(2 * tx + xi) * pitch + kz] = gx * jy - gy * jx;
+    const int tid = threadIdx.x;
+    const int xi = tid & (tx - 1);
+    const int pos0 = tid >> lgtx;
+    auto dpos = [&](int q) { return (q * NT) >> lgtx; };
+    const int goff = pos0 * plane + xi;
+    const int loff = xi * PITCH + padj(pos0);
+    cx<T> *base = buf + (long)ky * mx + x0;
+    // folded spectrum coordinates of this thread's elements
+    const int kx = min(x0 + xi, mx - 1);
+    const int fx = kx <= mx / 2 ? kx : mx - kx;
+    const int fy = ky <= my / 2 ? ky : my - ky;
+    const int sx = mx / 2 + 1, sxy = sx * (my / 2 + 1);
+    const long oct = (long)sxy * (mz / 2 + 1);
+    const int soff = fy * sx + fx;
+    init_twiddles(tw, mz);
+
+    auto load_field = [&](int f) {
+        const cx<T> *fb = base + f * fstride;
+        cx<T> r[VPT];
+#pragma unroll
+        for (int q = 0; q < VPT; ++q)
+            r[q] = xi < nlines && pos0 + dpos(q) < nz ? fb[goff + dpos(q) * plane] : cx<T>();
+        __syncthreads();                      // earlier readers of lb are done
+#pragma unroll
+        for (int q = 0; q < VPT; ++q)
+            if (pos0 + dpos(q) < mz) lb[loff + dpos(q) + dpos(q) / 8] = r[q];
+        __syncthreads();
+    };
+    auto store_field = [&](int f) {
+        cx<T> *fb = base + f * fstride;
+        cx<T> r[VPT];
+#pragma unroll
+        for (int q = 0; q < VPT; ++q)
+            if (pos0 + dpos(q) < mz) r[q] = lb[loff + dpos(q) + dpos(q) / 8];
+#pragma unroll
+        for (int q = 0; q < VPT; ++q)
+            if (xi < nlines && pos0 + dpos(q) < nz) fb[goff + dpos(q) * plane] = r[q];
+    };
+    auto lds_q = [&](int q) -> cx<T> & { return lb[loff + dpos(q) + dpos(q) / 8]; };
+    // spectrum value of kind `kind` at element q (padding lanes clamp kx;
+    // their products are never stored)
+    auto spec_q = [&](int kind, int q) {
+        const int kz = min(pos0 + dpos(q), mz - 1);
+        const int fz = kz <= mz / 2 ? kz : mz - kz;
+        const cx<T> v = spec[kind * oct + fz * sxy + soff];
+        const bool neg = (kind == 1 && kx > mx / 2) || (kind == 2 && ky > my / 2) || (kind == 3 && kz > mz / 2);
+        return neg ? -v : v;
+    };
+
+    if constexpr (MODE == 0) {
+        const int f = blockIdx.z;
+        load_field(f);
+        lds_fft<T, NT, VPT, LGL, false>(lb, tx, tw);
+#pragma unroll
+        for (int q = 0; q < VPT; ++q)
+            if (pos0 + dpos(q) < mz) lds_q(q) = spec_q(0, q) * lds_q(q);
+        __syncthreads();
+        lds_fft<T, NT, VPT, LGL, true>(lb, tx, tw);
+        store_field(f);
+    } else {
+        cx<T> J[3][VPT];
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            load_field(f);
+            lds_fft<T, NT, VPT, LGL, false>(lb, tx, tw);
+#pragma unroll
+            for (int q = 0; q < VPT; ++q) J[f][q] = pos0 + dpos(q) < mz ? lds_q(q) : cx<T>();
+        }
+#pragma unroll
+        for (int q = 0; q < VPT; ++q) {
+            const cx<T> gx = spec_q(1, q), gy = spec_q(2, q), gz = spec_q(3, q);
+            const cx<T> jx = J[0][q], jy = J[1][q], jz = J[2][q];
+            J[0][q] = gy * jz - gz * jy;
+            J[1][q] = gz * jx - gx * jz;
+            J[2][q] = gx * jy - gy * jx;
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            __syncthreads();                  // earlier readers of lb are done
+#pragma unroll
+            for (int q = 0; q < VPT; ++q)
+                if (pos0 + dpos(q) < mz) lds_q(q) = J[c][q];
+            __syncthreads();
+            lds_fft<T, NT, VPT, LGL, true>(lb, tx, tw);
+            store_field(c);
         }
     }
-    __syncthreads();
-    res = lds_fft<T>(res, oth, mz, nl, pitch, T(1));
-    for (int it = threadIdx.x; it < nl * nz; it += blockDim.x) {
-        int pos = it / nl, l = it - pos * nl;
-        int f = l / tx, xi = l - f * tx;
-        if (xi < nlines) buf[(long)(f0 + f) * fstride + pos * plane + (long)ky * mx + x0 + xi] = res[l * pitch + pos];
-    }
 }
 
-static int lines_per_block(int L, size_t elem, int nf_per_block) {
-    // two LDS buffers of tx lines x (L + 1) elements within 64 KiB
-    long cap = 65536 / (2 * (long)(L + 1) * elem * nf_per_block);
+// Block shapes (threads NT, values per thread VPT; a tile holds NT * VPT
+// values).  Pass and G z-pass tiles hold up to 64 KiB of data (8192
+// complex64 or 4096 complex128) with 512 threads, so that two blocks (four
+// waves per SIMD, the launch-bounds minimum) share a CU within 128
+// registers.  The grad-G z pass keeps three transformed fields in registers
+// and runs 256 x 8, at two waves per SIMD in FP32 and one in FP64 (which
+// would spill at two).
+template <typename T> struct FftShape {
+    static constexpr int nt = 512;
+    static constexpr int vpt = sizeof(T) == 4 ? 16 : 8;
+    static constexpr int minw = 4;
+    static constexpr int grad_nt = 256;
+    static constexpr int grad_vpt = 8;
+    static constexpr int grad_minw = sizeof(T) == 4 ? 2 : 1;
+};
+
+// Shortest and longest supported transform (2^3 .. 2^10).
+constexpr int kMinLg = 3, kMaxLg = 10;
+
+// Dynamic LDS available to one block: the device limit, capped at 80 KiB so
+// that two blocks share a CU.
+static long lds_budget() {
+    static std::atomic<long> cached[64];
+    int dev = 0;
+    SIE_HIP(hipGetDevice(&dev));
+    SIE_CHECK(dev >= 0 && dev < 64, SIE_EINVAL, "device index out of range");
+    long v = cached[dev].load();
+    if (v == 0) {
+        int lim = 0;
+        SIE_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        v = std::min<long>(lim, 80 * 1024);
+        cached[dev].store(v);
+    }
+    return v;
+}
+
+static int ilog2(int v) {
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+// Lines per block (a power of two): tile within nt * vpt values, the LDS
+// budget (padded lines plus the half twiddle table), and at most nt / 8 so
+// that the per-slot step along a line in the strided layouts (nt / lines)
+// is a multiple of 8 elements, which keeps the LDS pad of that step exact.
+static int lines_per_block(int L, size_t elem, int nt, int vpt) {
+    const long tile = (long)nt * vpt;
+    SIE_CHECK(L >= (1 << kMinLg) && (L & (L - 1)) == 0 && L <= (1 << kMaxLg) && L <= tile, SIE_EGRID,
+              "FFT length must be a power of two between 8 and 1024");
+    long cap = (lds_budget() - (long)twiddle_len(L) * (long)elem) / ((long)padded_pitch(L) * (long)elem);
+    cap = std::min<long>(cap, tile / L);
+    cap = std::min<long>(cap, nt / 8);
+    SIE_CHECK(cap >= 1, SIE_EGRID, "FFT line does not fit in LDS");
     int tx = 1;
-    while (tx * 2 <= cap && tx * 2 <= 64) tx *= 2;
+    while (2 * tx <= cap) tx *= 2;
     return tx;
 }
 
-template <typename T>
-static void pass(const cx<T> *in, cx<T> *out, int L, int n_in, int n_out, long s_in, long s_out,
-                 long js_in, long js_out, long bs_in, long bs_out, int nj, long nb, bool contiguous,
-                 T sign, hipStream_t st) {
-    int tx = lines_per_block(L, sizeof(cx<T>), 1);
-    if (contiguous) tx = std::min(tx, 16);
+static size_t tile_lds(int L, int tx, size_t elem) {
+    return ((size_t)tx * padded_pitch(L) + twiddle_len(L)) * elem;
+}
+
+// 32-bit per-thread offsets: every element a block touches must lie within
+// 2^31 elements of its uniform base.
+static void check_span(long span) {
+    SIE_CHECK(span >= 0 && span < (1L << 31), SIE_EGRID, "FFT pass spans more than 2^31 elements");
+}
+
+template <typename T, int LGL, bool INV>
+static void launch_pass(const cx<T> *in, cx<T> *out, int n_in, int n_out, long s_in, long s_out, long js_in,
+                        long js_out, long bs_in, long bs_out, int nj, long nb, bool contiguous, hipStream_t st) {
+    constexpr int NT = FftShape<T>::nt, V = FftShape<T>::vpt, W = FftShape<T>::minw;
+    constexpr int L = 1 << LGL;
+    const int tx = lines_per_block(L, sizeof(cx<T>), NT, V);
+    SIE_CHECK(nb >= 1 && nb <= 65535, SIE_EGRID, "FFT batch above 65535 lines");
     dim3 grid((nj + tx - 1) / tx, (unsigned)nb);
-    size_t sh = 2 * (size_t)tx * (L + 1) * sizeof(cx<T>);
-    hipLaunchKernelGGL(k_fft_pass<T>, grid, dim3(256), sh, st, in, out, L, n_in, n_out, s_in, s_out,
-                       js_in, js_out, bs_in, bs_out, nj, tx, contiguous ? 1 : 0, sign);
+    const size_t sh = tile_lds(L, tx, sizeof(cx<T>));
+    if (contiguous) {
+        SIE_CHECK(s_in == 1 && s_out == 1, SIE_EINVAL, "contiguous FFT pass needs unit element stride");
+        check_span((long)tx * std::max(js_in, js_out) + L);
+        hipLaunchKernelGGL((k_fft_pass<T, NT, V, LGL, true, INV, W>), grid, dim3(NT), sh, st, in, out, n_in, n_out,
+                           1, 1, (int)js_in, (int)js_out, bs_in, bs_out, nj, ilog2(tx));
+    } else {
+        SIE_CHECK(js_in == 1 && js_out == 1, SIE_EINVAL, "strided FFT pass needs adjacent lines");
+        check_span((long)L * std::max(s_in, s_out) + tx);
+        hipLaunchKernelGGL((k_fft_pass<T, NT, V, LGL, false, INV, W>), grid, dim3(NT), sh, st, in, out, n_in,
+                           n_out, (int)s_in, (int)s_out, 1, 1, bs_in, bs_out, nj, ilog2(tx));
+    }
     SIE_HIP(hipGetLastError());
+}
+
+template <typename T, bool INV, int LGL = kMinLg>
+static void pass_lg(int lg, const cx<T> *in, cx<T> *out, int n_in, int n_out, long s_in, long s_out, long js_in,
+                    long js_out, long bs_in, long bs_out, int nj, long nb, bool contiguous, hipStream_t st) {
+    if constexpr (LGL <= kMaxLg) {
+        if (lg == LGL)
+            launch_pass<T, LGL, INV>(in, out, n_in, n_out, s_in, s_out, js_in, js_out, bs_in, bs_out, nj, nb,
+                                     contiguous, st);
+        else
+            pass_lg<T, INV, LGL + 1>(lg, in, out, n_in, n_out, s_in, s_out, js_in, js_out, bs_in, bs_out, nj, nb,
+                                     contiguous, st);
+    } else {
+        SIE_CHECK(false, SIE_EGRID, "FFT length must be a power of two between 8 and 1024");
+    }
+}
+
+template <typename T>
+static void pass(const cx<T> *in, cx<T> *out, int L, int n_in, int n_out, long s_in, long s_out, long js_in,
+                 long js_out, long bs_in, long bs_out, int nj, long nb, bool contiguous, bool inv, hipStream_t st) {
+    SIE_CHECK((L & (L - 1)) == 0, SIE_EGRID, "FFT length must be a power of two");
+    if (inv)
+        pass_lg<T, true>(ilog2(L), in, out, n_in, n_out, s_in, s_out, js_in, js_out, bs_in, bs_out, nj, nb,
+                         contiguous, st);
+    else
+        pass_lg<T, false>(ilog2(L), in, out, n_in, n_out, s_in, s_out, js_in, js_out, bs_in, bs_out, nj, nb,
+                          contiguous, st);
+}
+
+template <typename T, int LGL = kMinLg>
+static void zpass_lg(int lg, const Grid &g, const cx<T> *spec, int nf, int mode, cx<T> *bufB, hipStream_t st) {
+    if constexpr (LGL <= kMaxLg) {
+        if (lg != LGL) {
+            zpass_lg<T, LGL + 1>(lg, g, spec, nf, mode, bufB, st);
+            return;
+        }
+        constexpr int mz = 1 << LGL;
+        const int mx = g.m[0], my = g.m[1], nz = g.nl[2];
+        check_span((long)nz * my * mx);
+        if (mode == 0) {
+            constexpr int NT = FftShape<T>::nt, V = FftShape<T>::vpt, W = FftShape<T>::minw;
+            const int tx = lines_per_block(mz, sizeof(cx<T>), NT, V);
+            dim3 grid((mx + tx - 1) / tx, my, nf);
+            hipLaunchKernelGGL((k_fft_zpass<T, NT, V, LGL, 0, W>), grid, dim3(NT), tile_lds(mz, tx, sizeof(cx<T>)),
+                               st, bufB, spec, mx, my, nz, ilog2(tx));
+        } else {
+            constexpr int NT = FftShape<T>::grad_nt, V = FftShape<T>::grad_vpt, W = FftShape<T>::grad_minw;
+            const int tx = lines_per_block(mz, sizeof(cx<T>), NT, V);
+            dim3 grid((mx + tx - 1) / tx, my);
+            hipLaunchKernelGGL((k_fft_zpass<T, NT, V, LGL, 1, W>), grid, dim3(NT), tile_lds(mz, tx, sizeof(cx<T>)),
+                               st, bufB, spec, mx, my, nz, ilog2(tx));
+        }
+        SIE_HIP(hipGetLastError());
+    } else {
+        SIE_CHECK(false, SIE_EGRID, "FFT length must be a power of two between 8 and 1024");
+    }
 }
 
 // out may alias in.  nf fields; mode 0 (G) or 1 (grad G x, nf == 3).
@@ -187,37 +527,27 @@ void fft_convolve(const Grid &g, const cx<T> *spec, int nf, int mode, const cx<T
     const int nx = g.nl[0], ny = g.nl[1], nz = g.nl[2];
     const int mx = g.m[0], my = g.m[1], mz = g.m[2];
     SIE_CHECK(mode == 0 || nf == 3, SIE_EINVAL, "grad-G convolution needs 3 fields");
-    SIE_CHECK(mx <= 1024 && my <= 1024 && mz <= 1024, SIE_EGRID, "FFT length above 1024");
     // x forward: lines (f, z, y) contiguous; batch b = f*nz + z, j = y
-    pass<T>(in, bufA, mx, nx, mx, 1, 1, nx, mx, (long)ny * nx, (long)ny * mx, ny, (long)nf * nz, true,
-            T(-1), st);
+    pass<T>(in, bufA, mx, nx, mx, 1, 1, nx, mx, (long)ny * nx, (long)ny * mx, ny, (long)nf * nz, true, false, st);
     // y forward: lines along y, j = x (adjacent), batch b = f*nz + z
-    pass<T>(bufA, bufB, my, ny, my, mx, mx, 1, 1, (long)ny * mx, (long)my * mx, mx, (long)nf * nz, false,
-            T(-1), st);
+    pass<T>(bufA, bufB, my, ny, my, mx, mx, 1, 1, (long)ny * mx, (long)my * mx, mx, (long)nf * nz, false, false,
+            st);
     // z fused
-    {
-        int nfb = mode == 1 ? 3 : 1;
-        int tx = lines_per_block(mz, sizeof(cx<T>), nfb);
-        dim3 grid((mx + tx - 1) / tx, my, mode == 1 ? 1 : nf);
-        size_t sh = 2 * (size_t)nfb * tx * (mz + 1) * sizeof(cx<T>);
-        hipLaunchKernelGGL(k_fft_zpass<T>, grid, dim3(256), sh, st, bufB, spec, mx, my, mz, nz, nf, tx, mode);
-        SIE_HIP(hipGetLastError());
-    }
+    SIE_CHECK((mz & (mz - 1)) == 0, SIE_EGRID, "FFT length must be a power of two");
+    zpass_lg<T>(ilog2(mz), g, spec, nf, mode, bufB, st);
     // y inverse: keep ny
-    pass<T>(bufB, bufA, my, my, ny, mx, mx, 1, 1, (long)my * mx, (long)ny * mx, mx, (long)nf * nz, false,
-            T(1), st);
+    pass<T>(bufB, bufA, my, my, ny, mx, mx, 1, 1, (long)my * mx, (long)ny * mx, mx, (long)nf * nz, false, true, st);
     // x inverse: keep nx
-    pass<T>(bufA, out, mx, mx, nx, 1, 1, mx, nx, (long)ny * mx, (long)ny * nx, ny, (long)nf * nz, true,
-            T(1), st);
+    pass<T>(bufA, out, mx, mx, nx, 1, 1, mx, nx, (long)ny * mx, (long)ny * nx, ny, (long)nf * nz, true, true, st);
 }
 
 // Full (unpruned) forward 3D FFT of a [mz][my][mx] complex128 volume in place,
 // using `tmp` of the same size (spectrum construction).
 void fft3d_full_fwd(c128 *vol, c128 *tmp, int mx, int my, int mz, hipStream_t st) {
-    pass<double>(vol, tmp, mx, mx, mx, 1, 1, mx, mx, (long)my * mx, (long)my * mx, my, mz, true, -1.0, st);
-    pass<double>(tmp, vol, my, my, my, mx, mx, 1, 1, (long)my * mx, (long)my * mx, mx, mz, false, -1.0, st);
+    pass<double>(vol, tmp, mx, mx, mx, 1, 1, mx, mx, (long)my * mx, (long)my * mx, my, mz, true, false, st);
+    pass<double>(tmp, vol, my, my, my, mx, mx, 1, 1, (long)my * mx, (long)my * mx, mx, mz, false, false, st);
     // z: lines along z with stride my*mx; treat (y) as batch, j = x
-    pass<double>(vol, tmp, mz, mz, mz, (long)my * mx, (long)my * mx, 1, 1, mx, mx, mx, my, false, -1.0, st);
+    pass<double>(vol, tmp, mz, mz, mz, (long)my * mx, (long)my * mx, 1, 1, mx, mx, mx, my, false, false, st);
     SIE_HIP(hipMemcpyAsync(vol, tmp, sizeof(c128) * (size_t)mx * my * mz, hipMemcpyDeviceToDevice, st));
 }
 

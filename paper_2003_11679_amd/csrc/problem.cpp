@@ -474,11 +474,12 @@ void stage_project(sie_problem *p, Medium &md, const cx<T> *x, cx<T> *grid, hipS
 }
 
 template <typename T>
-void stage_convolve(sie_problem *p, Medium &md, int nf, const cx<T> *in, cx<T> *out, hipStream_t st) {
+void stage_convolve(sie_problem *p, Medium &md, sie_op op, int nf, const cx<T> *in, cx<T> *out, hipStream_t st) {
     Grid &g = *md.grid;
     Work<T> &w = work_of<T>(g);
-    SIE_CHECK(nf >= 1 && nf <= 4, SIE_EINVAL, "nfields must be 1..4");
-    fft_convolve<T>(g, spec_of<T>(md), nf, 0, in, out, w.bufA.p, w.bufB.p, st);
+    if (op == SIE_OP_K) SIE_CHECK(nf == 3, SIE_EINVAL, "the grad-G convolution takes 3 fields");
+    else SIE_CHECK(nf >= 1 && nf <= 4, SIE_EINVAL, "nfields must be 1..4");
+    fft_convolve<T>(g, spec_of<T>(md), nf, op == SIE_OP_K ? 1 : 0, in, out, w.bufA.p, w.bufB.p, st);
 }
 
 template <typename T>
@@ -494,7 +495,7 @@ void stage_interpolate(sie_problem *p, Medium &md, const cx<T> *grid, cx<T> *y, 
 #define SIE_INST_MV(T)                                                                                     \
     template void matvec<T>(sie_problem *, Medium &, sie_op, int, const cx<T> *, cx<T> *, hipStream_t);    \
     template void stage_project<T>(sie_problem *, Medium &, const cx<T> *, cx<T> *, hipStream_t);          \
-    template void stage_convolve<T>(sie_problem *, Medium &, int, const cx<T> *, cx<T> *, hipStream_t);    \
+    template void stage_convolve<T>(sie_problem *, Medium &, sie_op, int, const cx<T> *, cx<T> *, hipStream_t); \
     template void stage_interpolate<T>(sie_problem *, Medium &, const cx<T> *, cx<T> *, hipStream_t);
 SIE_INST_MV(float)
 SIE_INST_MV(double)

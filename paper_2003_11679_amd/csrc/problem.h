@@ -81,7 +81,7 @@ void matvec(sie_problem *p, Medium &md, sie_op op, int nrhs, const cx<T> *x, cx<
 template <typename T>
 void stage_project(sie_problem *p, Medium &md, const cx<T> *x, cx<T> *grid, hipStream_t st);
 template <typename T>
-void stage_convolve(sie_problem *p, Medium &md, int nf, const cx<T> *in, cx<T> *out, hipStream_t st);
+void stage_convolve(sie_problem *p, Medium &md, sie_op op, int nf, const cx<T> *in, cx<T> *out, hipStream_t st);
 template <typename T>
 void stage_interpolate(sie_problem *p, Medium &md, const cx<T> *grid, cx<T> *y, hipStream_t st);
 void solver_destroy(SolveState *s);

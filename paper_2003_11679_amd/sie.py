@@ -82,7 +82,7 @@ SIGNATURES = [
     ("sie_get_wavenumber", ctypes.c_int, [_VP, ctypes.c_int32, _CP]),
     ("sie_matvec", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int, ctypes.c_int, ctypes.c_int32, _VP, _VP, _VP]),
     ("sie_project", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int, _VP, _VP, _VP]),
-    ("sie_convolve", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int, ctypes.c_int32, _VP, _VP, _VP]),
+    ("sie_convolve", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int, ctypes.c_int, ctypes.c_int32, _VP, _VP, _VP]),
     ("sie_interpolate", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int, _VP, _VP, _VP]),
     ("sie_set_timing", ctypes.c_int, [_VP, ctypes.c_int32]),
     ("sie_get_stage_time", ctypes.c_int, [_VP, ctypes.c_int32, _I64P, _DP]),
@@ -255,12 +255,15 @@ class Problem:
                                  _VP(out.data_ptr()), _stream(stream)))
         return out
 
-    def convolve(self, medium, grid_in, out=None, stream=None):
+    def convolve(self, medium, grid_in, out=None, op=OP_L, stream=None):
+        """Zero-padded FFT convolution of grid_in [F][nl_z][nl_y][nl_x] on the
+        live box: op OP_L, each field with G; op OP_K, the 3 fields J to
+        grad G x J."""
         import torch
         grid_in = grid_in.contiguous()
         if out is None:
             out = torch.empty_like(grid_in)
-        _check(lib().sie_convolve(self.h, medium, self._prec_of(grid_in), grid_in.shape[0],
+        _check(lib().sie_convolve(self.h, medium, op, self._prec_of(grid_in), grid_in.shape[0],
                                   _VP(grid_in.data_ptr()), _VP(out.data_ptr()), _stream(stream)))
         return out
 
