@@ -28,16 +28,34 @@ namespace sie {
 
 // LDS tiles store element j of a line at j + j/8: one pad slot every eight
 // elements, so that the stride-R writes of the early Stockham stages fall
-// on distinct banks.  Lines are padded_pitch(L) apart.
-__device__ inline int padj(int j) { return j + (j >> 3); }
-__host__ __device__ constexpr int padded_pitch(int L) { return L + (L >> 3) + 1; }
+// on distinct banks.
+__device__ __forceinline__ int padj(int j) { return j + (j >> 3); }
 
 // padj(j0 + r * S) for a compile-time stride S: separable when S is a
 // multiple of 8 (then the pad of the step is exact).
 template <int S>
-__device__ inline int padj_step(int j0, int r) {
+__device__ __forceinline__ int padj_step(int j0, int r) {
     if constexpr (S % 8 == 0) return padj(j0) + r * (S + S / 8);
     else return padj(j0 + r * S);
+}
+
+// LDS element access through float2 / double2, so that a complex value
+// moves with one 64-bit (FP32) or 128-bit (FP64) LDS instruction.  LDS
+// tiles hold whole elements at element-aligned offsets.
+template <typename T> struct Vec2;
+template <> struct Vec2<float> { using type = float2; };
+template <> struct Vec2<double> { using type = double2; };
+template <typename T>
+__device__ __forceinline__ cx<T> lds_ld(const cx<T> *p) {
+    const typename Vec2<T>::type v = *reinterpret_cast<const typename Vec2<T>::type *>(p);
+    return cx<T>(v.x, v.y);
+}
+template <typename T>
+__device__ __forceinline__ void lds_st(cx<T> *p, cx<T> a) {
+    typename Vec2<T>::type v;
+    v.x = a.re;
+    v.y = a.im;
+    *reinterpret_cast<typename Vec2<T>::type *>(p) = v;
 }
 
 // Half twiddle table exp(-2 pi i j / L), j < L/2, built per block in LDS
@@ -46,29 +64,29 @@ __device__ inline int padj_step(int j0, int r) {
 __host__ __device__ constexpr int twiddle_len(int L) { return L >= 2 ? L / 2 : 1; }
 
 template <typename T>
-__device__ inline void init_twiddles(cx<T> *tw, int L) {
+__device__ __forceinline__ void init_twiddles(cx<T> *tw, int L) {
     for (int j = threadIdx.x; j < twiddle_len(L); j += blockDim.x) {
         double sn, cs;
         sincospi(-2.0 * (double)j / (double)L, &sn, &cs);
-        tw[j] = cx<T>((T)cs, (T)sn);
+        lds_st(tw + j, cx<T>((T)cs, (T)sn));
     }
 }
 
 // -i a (forward) or +i a (inverse)
 template <typename T, bool INV>
-__device__ inline cx<T> rot_mi(cx<T> a) {
+__device__ __forceinline__ cx<T> rot_mi(cx<T> a) {
     return INV ? cx<T>(-a.im, a.re) : cx<T>(a.im, -a.re);
 }
 
 // In-register DFTs of length 2, 4, 8; forward exp(-2 pi i rq/R), inverse +.
 template <typename T>
-__device__ inline void dft2(cx<T> *u) {
+__device__ __forceinline__ void dft2(cx<T> *u) {
     const cx<T> a = u[0], b = u[1];
     u[0] = a + b;
     u[1] = a - b;
 }
 template <typename T, bool INV>
-__device__ inline void dft4(cx<T> *u) {
+__device__ __forceinline__ void dft4(cx<T> *u) {
     const cx<T> s02 = u[0] + u[2], d02 = u[0] - u[2], s13 = u[1] + u[3], d13 = u[1] - u[3];
     const cx<T> jd = rot_mi<T, INV>(d13);
     u[0] = s02 + s13;
@@ -77,7 +95,7 @@ __device__ inline void dft4(cx<T> *u) {
     u[3] = d02 - jd;
 }
 template <typename T, bool INV>
-__device__ inline void dft8(cx<T> *u) {
+__device__ __forceinline__ void dft8(cx<T> *u) {
     cx<T> e[4] = {u[0], u[2], u[4], u[6]}, o[4] = {u[1], u[3], u[5], u[7]};
     dft4<T, INV>(e);
     dft4<T, INV>(o);
@@ -92,7 +110,7 @@ __device__ inline void dft8(cx<T> *u) {
     u[3] = e[3] + o3;   u[7] = e[3] - o3;
 }
 template <typename T, int R, bool INV>
-__device__ inline void dftR(cx<T> *u) {
+__device__ __forceinline__ void dftR(cx<T> *u) {
     if constexpr (R == 2) dft2(u);
     else if constexpr (R == 4) dft4<T, INV>(u);
     else dft8<T, INV>(u);
@@ -108,9 +126,11 @@ __device__ inline void dftR(cx<T> *u) {
 // t mod (L/R) of line t / (L/R) + b NT/(L/R) (so the twiddles are the same
 // for all b); otherwise butterfly t + (b mod BPL) NT of line b / BPL, with
 // BPL = (L/R)/NT slots per line.
-template <typename T, int R, int NT, int VPT, int LGL, int LGP, bool INV>
-__device__ inline void fft_stage(cx<T> *buf, int nl, const cx<T> *tw) {
-    constexpr int L = 1 << LGL, PITCH = padded_pitch(L);
+// ZIN (first stage only): inputs at L/2 and above are zero and not read.
+// ZOUT (last stage only): outputs at L/2 and above are not written.
+template <typename T, int R, int NT, int VPT, int LGL, int LGP, int PITCH, bool INV, bool ZIN, bool ZOUT>
+__device__ __forceinline__ void fft_stage(cx<T> *buf, int nl, const cx<T> *tw) {
+    constexpr int L = 1 << LGL;
     constexpr int LGR = R == 8 ? 3 : (R == 4 ? 2 : 1);
     constexpr int NB = VPT / R;
     static_assert(NB >= 1, "too few values per thread for this radix");
@@ -129,13 +149,13 @@ __device__ inline void fft_stage(cx<T> *buf, int nl, const cx<T> *tw) {
     // others as products of those
     auto twiddles = [&](int k, cx<T> *w) {
         const int j1 = k << LGTWS;
-        w[1] = tw[j1];
+        w[1] = lds_ld(tw + j1);
         if constexpr (R >= 4) {
-            w[2] = tw[2 * j1];
+            w[2] = lds_ld(tw + 2 * j1);
             w[3] = w[1] * w[2];
         }
         if constexpr (R == 8) {
-            w[4] = tw[4 * j1];
+            w[4] = lds_ld(tw + 4 * j1);
             w[5] = w[1] * w[4];
             w[6] = w[2] * w[4];
             w[7] = w[3] * w[4];
@@ -156,7 +176,8 @@ __device__ inline void fft_stage(cx<T> *buf, int nl, const cx<T> *tw) {
         if (line < nl) {
             const cx<T> *rd = buf + line * PITCH;
 #pragma unroll
-            for (int r = 0; r < R; ++r) u[b][r] = rd[padj_step<NBF>(i, r)];
+            for (int r = 0; r < R; ++r)
+                u[b][r] = ZIN && r >= R / 2 ? cx<T>() : lds_ld(rd + padj_step<NBF>(i, r));
             if constexpr (P > 1) {
                 cx<T> wb[R];
                 if constexpr (!SHARED_TW) twiddles(i & (P - 1), wb);
@@ -175,58 +196,110 @@ __device__ inline void fft_stage(cx<T> *buf, int nl, const cx<T> *tw) {
             const int j = ((i - k) << LGR) + k;
             cx<T> *wr = buf + line * PITCH;
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
+            for (int r = 0; r < (ZOUT ? R / 2 : R); ++r) {
                 int o;
                 if constexpr (P == 1 && R == 8) o = padj(j) + r;   // j = 8 i: no carry into j / 8
                 else o = padj_step<P>(j, r);
-                wr[o] = u[b][r];
+                lds_st(wr + o, u[b][r]);
             }
         }
     }
     __syncthreads();
 }
 
-// Full transform of nl lines of length 2^LGL, natural order in and out;
-// radix 8 while at least three factors of two remain, then 4 or 2.  The
-// stage sequence is fixed at compile time so that every stage's registers
-// are allocated on their own.
-template <typename T, int NT, int VPT, int LGL, bool INV, int LGP = 0>
-__device__ inline void lds_fft(cx<T> *buf, int nl, const cx<T> *tw) {
+// Full transform of nl lines of length 2^LGL (lines PITCH apart), natural
+// order in and out; radix 8 while at least three factors of two remain,
+// then 4 or 2.  The stage sequence is fixed at compile time so that every
+// stage's registers are allocated on their own.  ZIN: the upper half of
+// every input line is zero (zero-padded forward transform); ZOUT: only the
+// lower half of the output is used (pruned inverse transform).
+template <typename T, int NT, int VPT, int LGL, int PITCH, bool INV, bool ZIN, bool ZOUT, int LGP = 0>
+__device__ __forceinline__ void lds_fft(cx<T> *buf, int nl, const cx<T> *tw) {
     if constexpr (LGP < LGL) {
         constexpr int rem = LGL - LGP;
         constexpr int LGR = rem >= 3 ? 3 : rem;
-        fft_stage<T, 1 << LGR, NT, VPT, LGL, LGP, INV>(buf, nl, tw);
-        lds_fft<T, NT, VPT, LGL, INV, LGP + LGR>(buf, nl, tw);
+        constexpr bool LAST = LGP + LGR == LGL;
+        fft_stage<T, 1 << LGR, NT, VPT, LGL, LGP, PITCH, INV, ZIN && LGP == 0, ZOUT && LAST>(buf, nl, tw);
+        lds_fft<T, NT, VPT, LGL, PITCH, INV, false, ZOUT, LGP + LGR>(buf, nl, tw);
     }
 }
 
-// Generic pass: tx = 2^lgtx lines of length L = 2^LGL per block along one
-// axis.  Line (b, j) starts at in + b*bs_in + j*js_in.
+// Tile shape of a block: TX = 2^LGTX lines of length L = 2^LGL, PITCH
+// elements apart, plus the half twiddle table.  TX is the largest power of
+// two with TX * L <= NT * VPT, TX <= NT / 8 (so that the per-slot step along
+// a line in the across-lines layouts is a multiple of 8 elements and keeps
+// the LDS pad of that step exact) and the tile within kLdsBudget.  PITCH is
+// the padded length rounded up so that the TX lines of one row segment fall
+// on distinct bank slots of a kBankRow-byte LDS row.
+constexpr long kLdsBudget = 80 * 1024;
+constexpr int kBankRow = 128;
+
+template <typename T, int NT, int VPT, int LGL>
+struct Tile {
+    static constexpr int L = 1 << LGL;
+    static constexpr int ESZ = 2 * sizeof(T);
+    static constexpr int E = kBankRow / ESZ;          // elements per bank row
+    static constexpr int base_pitch(int tx) {
+        const int b = L + L / 8, c = tx >= E ? 1 : E / tx;
+        return b + ((c - b) % E + E) % E;
+    }
+    static constexpr int lines() {
+        int tx = 1;
+        while (2 * tx * L <= NT * VPT && 2 * tx <= NT / 8 &&
+               (long)(2 * tx * base_pitch(2 * tx) + twiddle_len(L)) * ESZ <= kLdsBudget)
+            tx *= 2;
+        return tx;
+    }
+    static constexpr int TX = lines();
+    static constexpr int LGTX = TX <= 1 ? 0 : (TX <= 2 ? 1 : (TX <= 4 ? 2 : (TX <= 8 ? 3 : (TX <= 16 ? 4 : (TX <= 32 ? 5 : 6)))));
+    static constexpr int PITCH = base_pitch(TX);
+    static constexpr size_t BYTES = (size_t)(TX * PITCH + twiddle_len(L)) * ESZ;
+    static_assert((1 << LGTX) == TX, "tile lines must be a power of two <= 64");
+    static_assert(TX * L <= NT * VPT, "tile larger than the block's register slots");
+    static_assert(L <= NT * VPT, "line longer than the block's register slots");
+};
+
+// Generic pass: TX lines of length L = 2^LGL per block along one axis
+// (tile shape Tile<T, NT, VPT, LGL>).  Line (b, j) starts at
+// in + b*bs_in + j*js_in.
 //   CONTIG: element stride 1 (x passes); threads walk along lines.
 //   otherwise adjacent lines are adjacent in memory (stride 1 between
 //   lines, s between elements) and threads walk across lines, so each row
 //   segment of the tile is one coalesced access.
 // Element q of thread t is (line0 + dline(q), pos0 + dpos(q)) with
-// dline/dpos uniform.  Zero padding beyond n_in; only n_out outputs written.
-template <typename T, int NT, int VPT, int LGL, bool CONTIG, bool INV, int MINW>
+// dline/dpos compile-time.  Zero padding beyond n_in; only n_out outputs
+// written.  PRUNE: forward passes have n_in <= L/2, inverse passes
+// n_out <= L/2 (zero-padded convolution), and the transforms skip the
+// zero inputs / unused outputs.
+template <typename T, int NT, int VPT, int LGL, bool CONTIG, bool INV, bool PRUNE, int MINW>
 __global__ void __launch_bounds__(NT, MINW) k_fft_pass(const cx<T> *__restrict__ in, cx<T> *__restrict__ out,
                                                        int n_in, int n_out, int s_in, int s_out, int js_in,
-                                                       int js_out, long bs_in, long bs_out, int nj, int lgtx) {
-    constexpr int L = 1 << LGL, PITCH = padded_pitch(L);
-    extern __shared__ unsigned char smem_raw[];
+                                                       int js_out, long bs_in, long bs_out, int nj) {
+    using TS = Tile<T, NT, VPT, LGL>;
+    constexpr int L = 1 << LGL, PITCH = TS::PITCH, TX = TS::TX, LGTX = TS::LGTX;
+    constexpr bool ZIN = PRUNE && !INV, ZOUT = PRUNE && INV;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T> *tw = reinterpret_cast<cx<T> *>(smem_raw);
     cx<T> *buf = tw + twiddle_len(L);
-    const int tx = 1 << lgtx;
-    const int j0 = blockIdx.x << lgtx;
-    const int nlines = min(tx, nj - j0);
+    const int j0 = blockIdx.x * TX;
+    const int nlines = min(TX, nj - j0);
     const cx<T> *src = in + (long)blockIdx.y * bs_in + (long)j0 * (CONTIG ? js_in : 1);
     cx<T> *dst = out + (long)blockIdx.y * bs_out + (long)j0 * (CONTIG ? js_out : 1);
     const int tid = threadIdx.x;
-    const int line0 = CONTIG ? tid >> LGL : tid & (tx - 1);
-    const int pos0 = CONTIG ? tid & (L - 1) : tid >> lgtx;
+    const int line0 = CONTIG ? tid >> LGL : tid & (TX - 1);
+    const int pos0 = CONTIG ? tid & (L - 1) : tid >> LGTX;
     auto dline = [&](int q) { return CONTIG ? (q * NT) >> LGL : 0; };
-    auto dpos = [&](int q) { return CONTIG ? (q * NT) & (L - 1) : (q * NT) >> lgtx; };
-    auto in_tile = [&](int q) { return CONTIG ? line0 + dline(q) < tx : pos0 + dpos(q) < L; };
+    auto dpos = [&](int q) { return CONTIG ? (q * NT) & (L - 1) : (q * NT) >> LGTX; };
+    // LDS slots the transform reads: the whole tile, or its lower half
+    // when the upper half of every line is known to be zero
+    auto lds_in = [&](int q) {
+        return CONTIG ? line0 + dline(q) < TX && (!ZIN || pos0 + dpos(q) < L / 2)
+                      : pos0 + dpos(q) < (ZIN ? L / 2 : L);
+    };
+    auto lds_out = [&](int q) {
+        return CONTIG ? line0 + dline(q) < TX && (!ZOUT || pos0 + dpos(q) < L / 2)
+                      : pos0 + dpos(q) < (ZOUT ? L / 2 : L);
+    };
     const int goff_in = CONTIG ? line0 * js_in + pos0 : line0 + pos0 * s_in;
     const int goff_out = CONTIG ? line0 * js_out + pos0 : line0 + pos0 * s_out;
     const int loff = line0 * PITCH + padj(pos0);   // dpos(q) is a multiple of 8
@@ -243,13 +316,13 @@ __global__ void __launch_bounds__(NT, MINW) k_fft_pass(const cx<T> *__restrict__
     init_twiddles(tw, L);
 #pragma unroll
     for (int q = 0; q < VPT; ++q)
-        if (in_tile(q)) buf[loff + dline(q) * PITCH + dpos(q) + dpos(q) / 8] = r[q];
+        if (lds_in(q)) lds_st(buf + loff + dline(q) * PITCH + dpos(q) + dpos(q) / 8, r[q]);
     __syncthreads();
-    lds_fft<T, NT, VPT, LGL, INV>(buf, tx, tw);
+    lds_fft<T, NT, VPT, LGL, PITCH, INV, ZIN, ZOUT>(buf, TX, tw);
     // gather the whole tile from LDS first, then issue the global stores
 #pragma unroll
     for (int q = 0; q < VPT; ++q)
-        if (in_tile(q)) r[q] = buf[loff + dline(q) * PITCH + dpos(q) + dpos(q) / 8];
+        if (lds_out(q)) r[q] = lds_ld(buf + loff + dline(q) * PITCH + dpos(q) + dpos(q) / 8);
 #pragma unroll
     for (int q = 0; q < VPT; ++q) {
         const int dl = dline(q), dp = dpos(q);
@@ -257,13 +330,14 @@ __global__ void __launch_bounds__(NT, MINW) k_fft_pass(const cx<T> *__restrict__
     }
 }
 
-// Fused z pass.  buf [F][nz][my][mx]; a block owns a tile of tx = 2^lgtx
-// consecutive x at one ky and runs its z lines (length mz = 2^LGL) field by
-// field through LDS: forward z, spectral product, inverse z, keep nz.
+// Fused z pass.  buf [F][nz][my][mx]; a block owns a tile of tx (Tile
+// shape) consecutive x at one ky and runs its z lines (length mz = 2^LGL,
+// nz <= mz/2 live) field by field through LDS: forward z (pruned input),
+// spectral product, inverse z (pruned output, keep nz).
 // Element q of thread t is (kz, xi) = (t / tx + q NT / tx, t mod tx).
-//   MODE 0: field blockIdx.z times G (the blocks of the nf fields read the
-//           same spectrum values; the folded spectrum is small enough to
-//           stay cached between them).
+//   MODE 0: each of the nf fields times G; the block handles rows ky and
+//           my - ky (ky <= my/2), which see the same G values, and reads
+//           those once into registers for both rows and every field.
 //   MODE 1: the three fields (J_x, J_y, J_z) become grad G x J,
 //           psi_x = Gy Jz - Gz Jy, psi_y = Gz Jx - Gx Jz, psi_z = Gx Jy - Gy Jx;
 //           the transformed fields are held in registers until all three
@@ -272,14 +346,17 @@ __global__ void __launch_bounds__(NT, MINW) k_fft_pass(const cx<T> *__restrict__
 // along every axis, dG/dx_a odd along axis a (kinds 1..3).
 template <typename T, int NT, int VPT, int LGL, int MODE, int MINW>
 __global__ void __launch_bounds__(NT, MINW) k_fft_zpass(cx<T> *__restrict__ buf, const cx<T> *__restrict__ spec,
-                                                        int mx, int my, int nz, int lgtx) {
-    constexpr int mz = 1 << LGL, PITCH = padded_pitch(mz);
-    extern __shared__ unsigned char smem_raw[];
+                                                        int mx, int my, int nz, int nf) {
+    using TS = Tile<T, NT, VPT, LGL>;
+    constexpr int mz = 1 << LGL, PITCH = TS::PITCH, tx = TS::TX, lgtx = TS::LGTX;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T> *tw = reinterpret_cast<cx<T> *>(smem_raw);
     cx<T> *lb = tw + twiddle_len(mz);
-    const int tx = 1 << lgtx;
-    const int x0 = blockIdx.x << lgtx;
+    const int x0 = blockIdx.x * tx;
+    // MODE 0 pairs row ky with its mirror my - ky (same G values);
+    // MODE 1 takes one row (dG/dy changes sign across the mirror)
     const int ky = blockIdx.y;
+    const int nrows = MODE == 0 && ky > 0 && 2 * ky < my ? 2 : 1;
     const int nlines = min(tx, mx - x0);
     const int plane = my * mx;
     const long fstride = (long)nz * plane;
@@ -289,7 +366,7 @@ __global__ void __launch_bounds__(NT, MINW) k_fft_zpass(cx<T> *__restrict__ buf,
     auto dpos = [&](int q) { return (q * NT) >> lgtx; };
     const int goff = pos0 * plane + xi;
     const int loff = xi * PITCH + padj(pos0);
-    cx<T> *base = buf + (long)ky * mx + x0;
+    auto row_base = [&](int row) { return buf + (long)(row == 0 ? ky : my - ky) * mx + x0; };
     // folded spectrum coordinates of this thread's elements
     const int kx = min(x0 + xi, mx - 1);
     const int fx = kx <= mx / 2 ? kx : mx - kx;
@@ -299,8 +376,8 @@ __global__ void __launch_bounds__(NT, MINW) k_fft_zpass(cx<T> *__restrict__ buf,
     const int soff = fy * sx + fx;
     init_twiddles(tw, mz);
 
-    auto load_field = [&](int f) {
-        const cx<T> *fb = base + f * fstride;
+    auto load_field = [&](int f, int row) {
+        const cx<T> *fb = row_base(row) + f * fstride;
         cx<T> r[VPT];
 #pragma unroll
         for (int q = 0; q < VPT; ++q)
@@ -308,20 +385,20 @@ __global__ void __launch_bounds__(NT, MINW) k_fft_zpass(cx<T> *__restrict__ buf,
         __syncthreads();                      // earlier readers of lb are done
 #pragma unroll
         for (int q = 0; q < VPT; ++q)
-            if (pos0 + dpos(q) < mz) lb[loff + dpos(q) + dpos(q) / 8] = r[q];
+            if (pos0 + dpos(q) < mz / 2) lds_st(lb + loff + dpos(q) + dpos(q) / 8, r[q]);
         __syncthreads();
     };
-    auto store_field = [&](int f) {
-        cx<T> *fb = base + f * fstride;
+    auto store_field = [&](int f, int row) {
+        cx<T> *fb = row_base(row) + f * fstride;
         cx<T> r[VPT];
 #pragma unroll
         for (int q = 0; q < VPT; ++q)
-            if (pos0 + dpos(q) < mz) r[q] = lb[loff + dpos(q) + dpos(q) / 8];
+            if (pos0 + dpos(q) < mz / 2) r[q] = lds_ld(lb + loff + dpos(q) + dpos(q) / 8);
 #pragma unroll
         for (int q = 0; q < VPT; ++q)
             if (xi < nlines && pos0 + dpos(q) < nz) fb[goff + dpos(q) * plane] = r[q];
     };
-    auto lds_q = [&](int q) -> cx<T> & { return lb[loff + dpos(q) + dpos(q) / 8]; };
+    auto lds_q = [&](int q) { return lb + loff + dpos(q) + dpos(q) / 8; };
     // spectrum value of kind `kind` at element q (padding lanes clamp kx;
     // their products are never stored)
     auto spec_q = [&](int kind, int q) {
@@ -333,23 +410,28 @@ __global__ void __launch_bounds__(NT, MINW) k_fft_zpass(cx<T> *__restrict__ buf,
     };
 
     if constexpr (MODE == 0) {
-        const int f = blockIdx.z;
-        load_field(f);
-        lds_fft<T, NT, VPT, LGL, false>(lb, tx, tw);
+        cx<T> g[VPT];
 #pragma unroll
-        for (int q = 0; q < VPT; ++q)
-            if (pos0 + dpos(q) < mz) lds_q(q) = spec_q(0, q) * lds_q(q);
-        __syncthreads();
-        lds_fft<T, NT, VPT, LGL, true>(lb, tx, tw);
-        store_field(f);
+        for (int q = 0; q < VPT; ++q) g[q] = spec_q(0, q);
+        for (int t = 0; t < nrows * nf; ++t) {
+            const int row = t / nf, f = t - row * nf;
+            load_field(f, row);
+            lds_fft<T, NT, VPT, LGL, PITCH, false, true, false>(lb, tx, tw);
+#pragma unroll
+            for (int q = 0; q < VPT; ++q)
+                if (pos0 + dpos(q) < mz) lds_st(lds_q(q), g[q] * lds_ld(lds_q(q)));
+            __syncthreads();
+            lds_fft<T, NT, VPT, LGL, PITCH, true, false, true>(lb, tx, tw);
+            store_field(f, row);
+        }
     } else {
         cx<T> J[3][VPT];
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
-            load_field(f);
-            lds_fft<T, NT, VPT, LGL, false>(lb, tx, tw);
+            load_field(f, 0);
+            lds_fft<T, NT, VPT, LGL, PITCH, false, true, false>(lb, tx, tw);
 #pragma unroll
-            for (int q = 0; q < VPT; ++q) J[f][q] = pos0 + dpos(q) < mz ? lds_q(q) : cx<T>();
+            for (int q = 0; q < VPT; ++q) J[f][q] = pos0 + dpos(q) < mz ? lds_ld(lds_q(q)) : cx<T>();
         }
 #pragma unroll
         for (int q = 0; q < VPT; ++q) {
@@ -364,10 +446,10 @@ __global__ void __launch_bounds__(NT, MINW) k_fft_zpass(cx<T> *__restrict__ buf,
             __syncthreads();                  // earlier readers of lb are done
 #pragma unroll
             for (int q = 0; q < VPT; ++q)
-                if (pos0 + dpos(q) < mz) lds_q(q) = J[c][q];
+                if (pos0 + dpos(q) < mz) lds_st(lds_q(q), J[c][q]);
             __syncthreads();
-            lds_fft<T, NT, VPT, LGL, true>(lb, tx, tw);
-            store_field(c);
+            lds_fft<T, NT, VPT, LGL, PITCH, true, false, true>(lb, tx, tw);
+            store_field(c, 0);
         }
     }
 }
@@ -391,9 +473,8 @@ template <typename T> struct FftShape {
 // Shortest and longest supported transform (2^3 .. 2^10).
 constexpr int kMinLg = 3, kMaxLg = 10;
 
-// Dynamic LDS available to one block: the device limit, capped at 80 KiB so
-// that two blocks share a CU.
-static long lds_budget() {
+// Dynamic LDS available to one block on the current device.
+static long lds_limit() {
     static std::atomic<long> cached[64];
     int dev = 0;
     SIE_HIP(hipGetDevice(&dev));
@@ -402,7 +483,7 @@ static long lds_budget() {
     if (v == 0) {
         int lim = 0;
         SIE_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-        v = std::min<long>(lim, 80 * 1024);
+        v = lim;
         cached[dev].store(v);
     }
     return v;
@@ -414,81 +495,69 @@ static int ilog2(int v) {
     return l;
 }
 
-// Lines per block (a power of two): tile within nt * vpt values, the LDS
-// budget (padded lines plus the half twiddle table), and at most nt / 8 so
-// that the per-slot step along a line in the strided layouts (nt / lines)
-// is a multiple of 8 elements, which keeps the LDS pad of that step exact.
-static int lines_per_block(int L, size_t elem, int nt, int vpt) {
-    const long tile = (long)nt * vpt;
-    SIE_CHECK(L >= (1 << kMinLg) && (L & (L - 1)) == 0 && L <= (1 << kMaxLg) && L <= tile, SIE_EGRID,
-              "FFT length must be a power of two between 8 and 1024");
-    long cap = (lds_budget() - (long)twiddle_len(L) * (long)elem) / ((long)padded_pitch(L) * (long)elem);
-    cap = std::min<long>(cap, tile / L);
-    cap = std::min<long>(cap, nt / 8);
-    SIE_CHECK(cap >= 1, SIE_EGRID, "FFT line does not fit in LDS");
-    int tx = 1;
-    while (2 * tx <= cap) tx *= 2;
-    return tx;
-}
-
-static size_t tile_lds(int L, int tx, size_t elem) {
-    return ((size_t)tx * padded_pitch(L) + twiddle_len(L)) * elem;
-}
-
 // 32-bit per-thread offsets: every element a block touches must lie within
 // 2^31 elements of its uniform base.
 static void check_span(long span) {
     SIE_CHECK(span >= 0 && span < (1L << 31), SIE_EGRID, "FFT pass spans more than 2^31 elements");
 }
 
-template <typename T, int LGL, bool INV>
+template <typename TS>
+static void check_tile() {
+    SIE_CHECK((long)TS::BYTES <= lds_limit(), SIE_EDEVICE, "FFT tile needs more LDS than the device offers");
+}
+
+template <typename T, int LGL, bool INV, bool PRUNE>
 static void launch_pass(const cx<T> *in, cx<T> *out, int n_in, int n_out, long s_in, long s_out, long js_in,
                         long js_out, long bs_in, long bs_out, int nj, long nb, bool contiguous, hipStream_t st) {
     constexpr int NT = FftShape<T>::nt, V = FftShape<T>::vpt, W = FftShape<T>::minw;
+    using TS = Tile<T, NT, V, LGL>;
     constexpr int L = 1 << LGL;
-    const int tx = lines_per_block(L, sizeof(cx<T>), NT, V);
+    check_tile<TS>();
     SIE_CHECK(nb >= 1 && nb <= 65535, SIE_EGRID, "FFT batch above 65535 lines");
-    dim3 grid((nj + tx - 1) / tx, (unsigned)nb);
-    const size_t sh = tile_lds(L, tx, sizeof(cx<T>));
+    SIE_CHECK(n_in >= 0 && n_in <= L && n_out >= 0 && n_out <= L, SIE_EINVAL, "FFT line extents exceed the length");
+    if (PRUNE) SIE_CHECK(INV ? n_out <= L / 2 : n_in <= L / 2, SIE_EINVAL, "pruned FFT needs a half-length live line");
+    dim3 grid((nj + TS::TX - 1) / TS::TX, (unsigned)nb);
     if (contiguous) {
         SIE_CHECK(s_in == 1 && s_out == 1, SIE_EINVAL, "contiguous FFT pass needs unit element stride");
-        check_span((long)tx * std::max(js_in, js_out) + L);
-        hipLaunchKernelGGL((k_fft_pass<T, NT, V, LGL, true, INV, W>), grid, dim3(NT), sh, st, in, out, n_in, n_out,
-                           1, 1, (int)js_in, (int)js_out, bs_in, bs_out, nj, ilog2(tx));
+        check_span((long)TS::TX * std::max(js_in, js_out) + L);
+        hipLaunchKernelGGL((k_fft_pass<T, NT, V, LGL, true, INV, PRUNE, W>), grid, dim3(NT), TS::BYTES, st, in, out,
+                           n_in, n_out, 1, 1, (int)js_in, (int)js_out, bs_in, bs_out, nj);
     } else {
         SIE_CHECK(js_in == 1 && js_out == 1, SIE_EINVAL, "strided FFT pass needs adjacent lines");
-        check_span((long)L * std::max(s_in, s_out) + tx);
-        hipLaunchKernelGGL((k_fft_pass<T, NT, V, LGL, false, INV, W>), grid, dim3(NT), sh, st, in, out, n_in,
-                           n_out, (int)s_in, (int)s_out, 1, 1, bs_in, bs_out, nj, ilog2(tx));
+        check_span((long)L * std::max(s_in, s_out) + TS::TX);
+        hipLaunchKernelGGL((k_fft_pass<T, NT, V, LGL, false, INV, PRUNE, W>), grid, dim3(NT), TS::BYTES, st, in,
+                           out, n_in, n_out, (int)s_in, (int)s_out, 1, 1, bs_in, bs_out, nj);
     }
     SIE_HIP(hipGetLastError());
 }
 
-template <typename T, bool INV, int LGL = kMinLg>
+template <typename T, bool INV, bool PRUNE, int LGL = kMinLg>
 static void pass_lg(int lg, const cx<T> *in, cx<T> *out, int n_in, int n_out, long s_in, long s_out, long js_in,
                     long js_out, long bs_in, long bs_out, int nj, long nb, bool contiguous, hipStream_t st) {
     if constexpr (LGL <= kMaxLg) {
         if (lg == LGL)
-            launch_pass<T, LGL, INV>(in, out, n_in, n_out, s_in, s_out, js_in, js_out, bs_in, bs_out, nj, nb,
-                                     contiguous, st);
+            launch_pass<T, LGL, INV, PRUNE>(in, out, n_in, n_out, s_in, s_out, js_in, js_out, bs_in, bs_out, nj,
+                                            nb, contiguous, st);
         else
-            pass_lg<T, INV, LGL + 1>(lg, in, out, n_in, n_out, s_in, s_out, js_in, js_out, bs_in, bs_out, nj, nb,
-                                     contiguous, st);
+            pass_lg<T, INV, PRUNE, LGL + 1>(lg, in, out, n_in, n_out, s_in, s_out, js_in, js_out, bs_in, bs_out,
+                                            nj, nb, contiguous, st);
     } else {
         SIE_CHECK(false, SIE_EGRID, "FFT length must be a power of two between 8 and 1024");
     }
 }
 
+// One pass of the zero-padded convolution (pruned: forward passes read a
+// half-length live prefix, inverse passes keep one).
 template <typename T>
 static void pass(const cx<T> *in, cx<T> *out, int L, int n_in, int n_out, long s_in, long s_out, long js_in,
                  long js_out, long bs_in, long bs_out, int nj, long nb, bool contiguous, bool inv, hipStream_t st) {
     SIE_CHECK((L & (L - 1)) == 0, SIE_EGRID, "FFT length must be a power of two");
     if (inv)
-        pass_lg<T, true>(ilog2(L), in, out, n_in, n_out, s_in, s_out, js_in, js_out, bs_in, bs_out, nj, nb,
-                         contiguous, st);
+        pass_lg<T, true, true>(ilog2(L), in, out, n_in, n_out, s_in, s_out, js_in, js_out, bs_in, bs_out, nj, nb,
+                               contiguous, st);
     else
-        pass_lg<T, false>(ilog2(L), in, out, n_in, n_out, s_in, s_out, js_in, js_out, bs_in, bs_out, nj, nb,
-                          contiguous, st);
+        pass_lg<T, false, true>(ilog2(L), in, out, n_in, n_out, s_in, s_out, js_in, js_out, bs_in, bs_out, nj, nb,
+                                contiguous, st);
 }
 
 template <typename T, int LGL = kMinLg>
@@ -501,18 +570,21 @@ static void zpass_lg(int lg, const Grid &g, const cx<T> *spec, int nf, int mode,
         constexpr int mz = 1 << LGL;
         const int mx = g.m[0], my = g.m[1], nz = g.nl[2];
         check_span((long)nz * my * mx);
+        SIE_CHECK(nz <= mz / 2, SIE_EGRID, "z live extent above half the FFT length");
         if (mode == 0) {
             constexpr int NT = FftShape<T>::nt, V = FftShape<T>::vpt, W = FftShape<T>::minw;
-            const int tx = lines_per_block(mz, sizeof(cx<T>), NT, V);
-            dim3 grid((mx + tx - 1) / tx, my, nf);
-            hipLaunchKernelGGL((k_fft_zpass<T, NT, V, LGL, 0, W>), grid, dim3(NT), tile_lds(mz, tx, sizeof(cx<T>)),
-                               st, bufB, spec, mx, my, nz, ilog2(tx));
+            using TS = Tile<T, NT, V, LGL>;
+            check_tile<TS>();
+            dim3 grid((mx + TS::TX - 1) / TS::TX, my / 2 + 1);
+            hipLaunchKernelGGL((k_fft_zpass<T, NT, V, LGL, 0, W>), grid, dim3(NT), TS::BYTES, st, bufB, spec, mx, my,
+                               nz, nf);
         } else {
             constexpr int NT = FftShape<T>::grad_nt, V = FftShape<T>::grad_vpt, W = FftShape<T>::grad_minw;
-            const int tx = lines_per_block(mz, sizeof(cx<T>), NT, V);
-            dim3 grid((mx + tx - 1) / tx, my);
-            hipLaunchKernelGGL((k_fft_zpass<T, NT, V, LGL, 1, W>), grid, dim3(NT), tile_lds(mz, tx, sizeof(cx<T>)),
-                               st, bufB, spec, mx, my, nz, ilog2(tx));
+            using TS = Tile<T, NT, V, LGL>;
+            check_tile<TS>();
+            dim3 grid((mx + TS::TX - 1) / TS::TX, my);
+            hipLaunchKernelGGL((k_fft_zpass<T, NT, V, LGL, 1, W>), grid, dim3(NT), TS::BYTES, st, bufB, spec, mx, my,
+                               nz, 3);
         }
         SIE_HIP(hipGetLastError());
     } else {
@@ -544,10 +616,14 @@ void fft_convolve(const Grid &g, const cx<T> *spec, int nf, int mode, const cx<T
 // Full (unpruned) forward 3D FFT of a [mz][my][mx] complex128 volume in place,
 // using `tmp` of the same size (spectrum construction).
 void fft3d_full_fwd(c128 *vol, c128 *tmp, int mx, int my, int mz, hipStream_t st) {
-    pass<double>(vol, tmp, mx, mx, mx, 1, 1, mx, mx, (long)my * mx, (long)my * mx, my, mz, true, false, st);
-    pass<double>(tmp, vol, my, my, my, mx, mx, 1, 1, (long)my * mx, (long)my * mx, mx, mz, false, false, st);
+    auto full = [&](const c128 *in, c128 *out, int L, long s, long js, long bs, int nj, long nb, bool contiguous) {
+        SIE_CHECK((L & (L - 1)) == 0, SIE_EGRID, "FFT length must be a power of two");
+        pass_lg<double, false, false>(ilog2(L), in, out, L, L, s, s, js, js, bs, bs, nj, nb, contiguous, st);
+    };
+    full(vol, tmp, mx, 1, mx, (long)my * mx, my, mz, true);
+    full(tmp, vol, my, mx, 1, (long)my * mx, mx, mz, false);
     // z: lines along z with stride my*mx; treat (y) as batch, j = x
-    pass<double>(vol, tmp, mz, mz, mz, (long)my * mx, (long)my * mx, 1, 1, mx, mx, mx, my, false, false, st);
+    full(vol, tmp, mz, (long)my * mx, 1, mx, mx, my, false);
     SIE_HIP(hipMemcpyAsync(vol, tmp, sizeof(c128) * (size_t)mx * my * mz, hipMemcpyDeviceToDevice, st));
 }
 
