@@ -6,9 +6,11 @@ One step is one complete solve request on the copper-bar workload (100 x 10 x 5
 um bar, sigma = 5.8e7 S/m, 20,088 triangles / 30,132 RWG functions, 10 GHz,
 64^3 grid, near region 11 points across): mesh topology, grid and stencils,
 near lists, FP64 near-field integrals with precorrection, Green's spectra,
-plane-wave excitation, the nested GIBC solve (FP32 stages inside FP64
-refinement to the relative FP64 residual given by --tol, default 1e-3, the
-metric's accuracy gate) and the far field.  The synthetic
+plane-wave excitation, the nested GIBC solve (FP32 interior stages inside
+FP64 refinement to the relative FP64 block residual given by --tol, default
+1e-6; interior block-Jacobi preconditioner, restart 200) and the far field.
+The FP32 currents are compared with an FP64 solve of the same request during
+warmup (relative error gate 1e-3).  The synthetic
 mesh is generated on the host before the timed region.
 
 value = SIE matvecs / s over the timed steps, one SIE matvec being one AIM
@@ -41,9 +43,15 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=64, help="rows of the oracle's dense matvec sample")
     ap.add_argument("--workload", choices=["bar", "fft"], default="bar",
                     help="bar: solve requests (default); fft: 4-field 256^3 convolution microbenchmark")
-    ap.add_argument("--tol", type=float, default=1e-3,
-                    help="relative FP64 residual of the solve (the metric's 1e-3 accuracy gate)")
+    ap.add_argument("--tol", type=float, default=1e-6,
+                    help="relative FP64 block residual of every solve")
+    ap.add_argument("--restart", type=int, default=200)
+    ap.add_argument("--precond", type=int, default=1,
+                    help="block-Jacobi bit mask: 1 nested interior solve, 2 outer solve")
     return ap.parse_args()
+
+
+SOLVE_OPTS = {}
 
 
 def step(mesh, cfg, prec, tol, timing=False):
@@ -62,7 +70,7 @@ def step(mesh, cfg, prec, tol, timing=False):
         p.set_timing(True)
     w = cfg.waves[0]
     p.set_planewaves(w.khat, w.e0)
-    rep = p.solve(prec, tol=tol)
+    rep = p.solve(prec, tol=tol, **SOLVE_OPTS)
     th = np.linspace(0.0, np.pi, 91)
     rhat = np.stack([np.sin(th), 0 * th, np.cos(th)], axis=1)
     F = p.far_field(rhat)
@@ -183,6 +191,7 @@ def main():
     cfg = bar_cfg()
     mesh = (cfg.objects[0].xyz, cfg.objects[0].tri)
     prec = 1 if args.precision == "fp32" else 0
+    SOLVE_OPTS.update(restart=args.restart, precond=args.precond)
     print(f"[bench] workload bar {len(mesh[1])} triangles, precision {args.precision}, "
           f"warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
     ref = None
@@ -192,7 +201,7 @@ def main():
         if i == 0 and prec == 1:
             # FP64 reference of the same request (accuracy of the FP32 path)
             u32, v32 = p.currents()
-            r64 = p.solve(0, tol=args.tol)
+            r64 = p.solve(0, tol=args.tol, **SOLVE_OPTS)
             u64, v64 = p.currents()
             ref = {"rel_err_u": float(np.linalg.norm(u32 - u64) / np.linalg.norm(u64)),
                    "rel_err_v": float(np.linalg.norm(v32 - v64) / np.linalg.norm(v64)),

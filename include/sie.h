@@ -82,12 +82,14 @@ typedef struct {
 typedef struct {
     double tol;          /* relative residual of the outer (GIBC) system, default 1e-6 */
     double inner_tol;    /* nested solve (eq. nest2) tolerance, default 1e-8 (FP64) */
-    int32_t restart;     /* GMRES restart length, default 100 */
+    int32_t restart;     /* GMRES restart length, default 100, at most 1000 */
     int32_t max_iter;    /* outer iteration cap, default 800 (Sec. V-A) */
     int32_t inner_max_iter; /* nested iteration cap, default 800 */
     int32_t max_refine;  /* FP64 refinement sweeps for SIE_FP32, default 10 */
-    int32_t precond;     /* 0 none (default); 1 block-Jacobi of the direct near-region
-                            operators (-j w eps_i L_i,NR inner, j w mu0 L0,NR outer) */
+    int32_t precond;     /* bit mask of block-Jacobi preconditioners built from the
+                            direct near-region operators: 1 the nested interior
+                            solve (-j w eps_i L_i,NR), 2 the outer solve
+                            (j w mu0 L0,NR); 0 none (default) */
 } sie_solver_opts;
 
 typedef struct {

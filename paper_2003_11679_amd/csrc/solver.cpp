@@ -68,6 +68,10 @@ struct Gmres {
     // Solves A x = b (x holds the initial guess).  Returns iterations; *relres
     // receives the final relative residual estimate.
     const char *tag = "gmres";
+    // Stagnation window: a cycle that gains under 1 % over this many
+    // iterations hands back to the caller (the precision floor of an FP32
+    // correction); 0 disables it.
+    int stag_window = 25;
     int solve(const Op &A, const Op &M, const cx<T> *b, cx<T> *x, double tol, int maxit, double *relres,
               hipStream_t st, int *napply = nullptr) {
         static const bool trace = std::getenv("SIE_TRACE") != nullptr;
@@ -131,9 +135,9 @@ struct Gmres {
                 res = std::sqrt(norm2(g[j + 1])) / bn;
                 if (trace) std::fprintf(stderr, "[%s] it %d res %.3e\n", tag, it + 1, res);
                 hist.push_back(res);
-                // stagnation: under 1 % progress over the last 25 iterations
-                // (the precision floor of an FP32 sweep); hand back to the caller
-                if (hist.size() > 25 && res > 0.99 * hist[hist.size() - 26]) stagnated = true;
+                if (stag_window > 0 && (int)hist.size() > stag_window &&
+                    res > 0.99 * hist[hist.size() - 1 - stag_window])
+                    stagnated = true;
                 if (hn > 0.0 && hn > 1e-300) launch_scale_into<T>(n, c128(1.0 / hn), w.p, V.p + (size_t)(j + 1) * n, st);
                 if (res <= tol || hn <= 1e-14 * beta || stagnated) { ++j; ++it; break; }
             }
@@ -301,13 +305,13 @@ struct Ops {
         mv(p->ext, SIE_OP_X, x, t[4]);
         launch_axpby<T>(E, c128(0.5 * sgn), t[4], c128(1.0), y, st);
     }
-    bool use_bj = false;
+    bool use_bj_in = false, use_bj_out = false;
     void prec_inner(const cx<T> *x, cx<T> *y) {
-        if (use_bj) launch_bj_apply<T>(s.pin.nb, s.pin.B, s.pin.perm.p, bj_inv<T>(s.pin), x, y, st);
+        if (use_bj_in) launch_bj_apply<T>(s.pin.nb, s.pin.B, s.pin.perm.p, bj_inv<T>(s.pin), x, y, st);
         else SIE_HIP(hipMemcpyAsync(y, x, E * sizeof(cx<T>), hipMemcpyDeviceToDevice, st));
     }
     void prec_outer(const cx<T> *x, cx<T> *y) {
-        if (use_bj) launch_bj_apply<T>(s.pout.nb, s.pout.B, s.pout.perm.p, bj_inv<T>(s.pout), x, y, st);
+        if (use_bj_out) launch_bj_apply<T>(s.pout.nb, s.pout.B, s.pout.perm.p, bj_inv<T>(s.pout), x, y, st);
         else SIE_HIP(hipMemcpyAsync(y, x, E * sizeof(cx<T>), hipMemcpyDeviceToDevice, st));
     }
     // Mixed precision: an FP64 operator set may delegate the interior work
@@ -394,14 +398,15 @@ static void solve_all(sie_problem *p, sie_precision prec, const sie_solver_opts 
     SolveState &s = *p->solve;
     const int64_t E = s.E;
     hipStream_t st = 0;
-    if (o.precond == 1) build_preconditioners(p, s);
+    if (o.precond != 0) build_preconditioners(p, s);
     s.matvecs = s.inner_iters = s.inner_max = 0;
     int outer_total = 0, sweeps_total = 0;
     double worst = 0.0;
     bool all_conv = true;
     const auto t0 = std::chrono::steady_clock::now();
     Ops<double> o64(p, s, st, o.inner_tol, o.inner_max_iter, o.restart);
-    o64.use_bj = o.precond == 1;
+    o64.use_bj_in = (o.precond & 1) != 0;
+    o64.use_bj_out = (o.precond & 2) != 0;
     for (int r = 0; r < s.nrhs; ++r) {
         c128 *e = s.e.p + r * E, *u = s.u.p + r * E, *v = s.v.p + r * E;
         double res = 1.0;
@@ -413,10 +418,10 @@ static void solve_all(sie_problem *p, sie_precision prec, const sie_solver_opts 
         std::unique_ptr<Ops<float>> o32;
         if (prec == SIE_FP32) {
             o32.reset(new Ops<float>(p, s, st, std::max(o.inner_tol, 1e-5), o.inner_max_iter, o.restart));
-            o32->use_bj = o.precond == 1;
+            o32->use_bj_in = o64.use_bj_in;
+            o32->use_bj_out = o64.use_bj_out;
             o64.lo = o32.get();
         }
-        const double sweep_tol = prec == SIE_FP32 ? std::max(1e-5, o.tol) : o.tol;
         SIE_HIP(hipMemsetAsync(u, 0, E * sizeof(c128), st));
         SIE_HIP(hipMemsetAsync(v, 0, E * sizeof(c128), st));
         DBuf<c128> r1(E), r2(E), du(E), dv(E), sv(E);
@@ -433,6 +438,14 @@ static void solve_all(sie_problem *p, sie_precision prec, const sie_solver_opts 
             o64.KpX(false, -1.0, sv.p, o64.t[3]);
             launch_axpby<double>(E, c128(1.0), o64.t[3], c128(1.0), r1.p, st);
             SIE_HIP(hipMemsetAsync(du.p, 0, E * sizeof(c128), st));
+            // FP64: run through the plateaus of the low-frequency EFIE; FP32:
+            // hand back when a correction stalls for longer than a plateau
+            s.go64.stag_window = prec == SIE_FP32 ? 100 : 0;
+            // relative tolerance of the correction solve: what is left to the
+            // target, but at most three digits per FP32 sweep (its interior
+            // products carry FP32 rounding)
+            const double need = o.tol / res;
+            const double sweep_tol = prec == SIE_FP32 ? std::max(need, 1e-3) : need;
             double rr;
             outer_total += s.go64.solve([&](const c128 *x, c128 *y) { o64.gibc(x, y); },
                                         [&](const c128 *x, c128 *y) { o64.prec_outer(x, y); }, r1.p, du.p,
@@ -516,8 +529,8 @@ void solve_entry(sie_problem *p, sie_precision prec, const sie_solver_opts *opts
         if (opts->max_refine > 0) o.max_refine = opts->max_refine;
         o.precond = opts->precond;
     }
-    SIE_CHECK(o.precond == 0 || o.precond == 1, SIE_EINVAL, "unknown preconditioner");
-    SIE_CHECK(o.restart <= 200, SIE_EINVAL, "restart above 200");
+    SIE_CHECK(o.precond >= 0 && o.precond <= 3, SIE_EINVAL, "unknown preconditioner");
+    SIE_CHECK(o.restart <= 1000, SIE_EINVAL, "restart above 1000");
     solve_all(p, prec, o, rep);
 }
 
