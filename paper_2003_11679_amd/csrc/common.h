@@ -147,12 +147,13 @@ constexpr double CLOSE_FACTOR = 2.5;
 // ---------------------------------------------------------------- grid + operators
 template <typename T>
 struct Work {       // per-medium, per-precision scratch for matvecs
-    DBuf<cx<T>> grid;     // [F][nl_z][nl_y][nl_x] sources then potentials
-    DBuf<cx<T>> bufA;     // [F][nl_z][nl_y][m_x]
-    DBuf<cx<T>> bufB;     // [F][nl_z][m_y][m_x]
-    DBuf<cx<T>> trisrc;   // [ntg][4]  per-triangle projection coefficients
+    DBuf<cx<T>> grid;     // [rhs][F][nl_z][nl_y][nl_x] sources then potentials
+    DBuf<cx<T>> bufA;     // [rhs][F][nl_z][nl_y][m_x]
+    DBuf<cx<T>> bufB;     // [rhs][F][nl_z][m_y][m_x]
+    DBuf<cx<T>> trisrc;   // [rhs][ntg][4]  per-triangle projection coefficients
     DBuf<cx<T>> tripot;   // [ntg][5]  per-triangle interpolation partials
-    int cap_rhs = 0;
+    DBuf<cx<T>> xt;       // [E][nrhs] right-hand sides of a batched product
+    int cap_rhs = 0;      // right-hand sides the buffers above hold
 };
 
 struct Grid {

@@ -41,57 +41,74 @@ template <typename T> void launch_scale_into(int64_t n, c128 a, const cx<T> *x, 
     SIE_HIP(hipGetLastError());
 }
 
-// partial dots: block (b, j) sums conj(V[j][i]) w[i] over a strided slice
+// Batched dot products of ns systems stored [ns][n] inside every vector:
+// h[s * hstride + j] = sum_i conj(V_j[s][i]) w[s][i], j < J, where V_j starts
+// at V + j * ldv.  Partial sums per block (b, j, s), then a final reduction;
+// FP64 accumulation.
 template <typename T>
 __global__ void k_dots_part(int64_t n, const cx<T> *__restrict__ V, int64_t ldv, const cx<T> *__restrict__ w,
                             c128 *__restrict__ part, int nb) {
     __shared__ double sre[256], sim[256];
-    const int j = blockIdx.y;
-    const cx<T> *v = V + j * ldv;
+    const int j = blockIdx.y, s = blockIdx.z, J = gridDim.y;
+    const cx<T> *v = V + j * ldv + s * n;
+    const cx<T> *ws = w + s * n;
     double re = 0, im = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const double ar = v[i].re, ai = v[i].im, br = w[i].re, bi = w[i].im;
+        const double ar = v[i].re, ai = v[i].im, br = ws[i].re, bi = ws[i].im;
         re += ar * br + ai * bi;
         im += ar * bi - ai * br;
     }
     sre[threadIdx.x] = re; sim[threadIdx.x] = im;
     __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) { sre[threadIdx.x] += sre[threadIdx.x + s]; sim[threadIdx.x] += sim[threadIdx.x + s]; }
+    for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) { sre[threadIdx.x] += sre[threadIdx.x + k]; sim[threadIdx.x] += sim[threadIdx.x + k]; }
         __syncthreads();
     }
-    if (threadIdx.x == 0) part[(int64_t)j * nb + blockIdx.x] = c128(sre[0], sim[0]);
+    if (threadIdx.x == 0) part[((int64_t)s * J + j) * nb + blockIdx.x] = c128(sre[0], sim[0]);
 }
 
-__global__ void k_dots_final(int J, const c128 *__restrict__ part, int nb, c128 *__restrict__ h) {
+__global__ void k_dots_final(int J, const c128 *__restrict__ part, int nb, c128 *__restrict__ h, int hstride) {
     __shared__ double sre[256], sim[256];
-    const int j = blockIdx.x;
+    const int j = blockIdx.x, s = blockIdx.y;
+    const c128 *ps = part + ((int64_t)s * J + j) * nb;
     double re = 0, im = 0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) { re += part[(int64_t)j * nb + b].re; im += part[(int64_t)j * nb + b].im; }
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) { re += ps[b].re; im += ps[b].im; }
     sre[threadIdx.x] = re; sim[threadIdx.x] = im;
     __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) { sre[threadIdx.x] += sre[threadIdx.x + s]; sim[threadIdx.x] += sim[threadIdx.x + s]; }
+    for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) { sre[threadIdx.x] += sre[threadIdx.x + k]; sim[threadIdx.x] += sim[threadIdx.x + k]; }
         __syncthreads();
     }
-    if (threadIdx.x == 0) h[j] = c128(sre[0], sim[0]);
+    if (threadIdx.x == 0) h[(int64_t)s * hstride + j] = c128(sre[0], sim[0]);
+}
+
+// part holds ns * J * nb partial sums.
+template <typename T>
+void launch_dots_sys(int64_t n, int J, const cx<T> *V, int64_t ldv, int ns, const cx<T> *w, c128 *part, int nb,
+                     c128 *h, int hstride, hipStream_t st) {
+    if (J <= 0 || ns <= 0) return;
+    hipLaunchKernelGGL(k_dots_part<T>, dim3(nb, J, ns), dim3(256), 0, st, n, V, ldv, w, part, nb);
+    SIE_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_dots_final, dim3(J, ns), dim3(256), 0, st, J, part, nb, h, hstride);
+    SIE_HIP(hipGetLastError());
 }
 
 template <typename T>
 void launch_dots(int64_t n, int J, const cx<T> *V, int64_t ldv, const cx<T> *w, c128 *part, int nb, c128 *h,
                  hipStream_t st) {
-    if (J <= 0) return;
-    hipLaunchKernelGGL(k_dots_part<T>, dim3(nb, J), dim3(256), 0, st, n, V, ldv, w, part, nb);
-    SIE_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_dots_final, dim3(J), dim3(256), 0, st, J, part, nb, h);
-    SIE_HIP(hipGetLastError());
+    launch_dots_sys<T>(n, J, V, ldv, 1, w, part, nb, h, J, st);
 }
 
+// w[s] += SGN sum_j V_j[s] h[s * hstride + j]
 template <typename T, int SGN>
 __global__ void k_gemv(int64_t n, int J, const cx<T> *__restrict__ V, int64_t ldv, const c128 *__restrict__ h,
-                       cx<T> *__restrict__ w) {
+                       int hstride, cx<T> *__restrict__ w) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const int s = blockIdx.y;
+    V += s * n;
+    h += (int64_t)s * hstride;
+    w += s * n;
     double re = 0, im = 0;
     for (int j = 0; j < J; ++j) {
         const cx<T> v = V[j * ldv + i];
@@ -102,15 +119,36 @@ __global__ void k_gemv(int64_t n, int J, const cx<T> *__restrict__ V, int64_t ld
     w[i] = cx<T>((T)(w[i].re + SGN * re), (T)(w[i].im + SGN * im));
 }
 template <typename T>
-void launch_gemv_sub(int64_t n, int J, const cx<T> *V, int64_t ldv, const c128 *h, cx<T> *w, hipStream_t st) {
-    if (J <= 0 || n <= 0) return;
-    hipLaunchKernelGGL((k_gemv<T, -1>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, J, V, ldv, h, w);
+void launch_gemv_sys(int64_t n, int J, const cx<T> *V, int64_t ldv, int ns, const c128 *h, int hstride, cx<T> *w,
+                     bool add, hipStream_t st) {
+    if (J <= 0 || n <= 0 || ns <= 0) return;
+    const dim3 grid((unsigned)((n + 255) / 256), (unsigned)ns);
+    if (add) hipLaunchKernelGGL((k_gemv<T, 1>), grid, dim3(256), 0, st, n, J, V, ldv, h, hstride, w);
+    else hipLaunchKernelGGL((k_gemv<T, -1>), grid, dim3(256), 0, st, n, J, V, ldv, h, hstride, w);
     SIE_HIP(hipGetLastError());
 }
 template <typename T>
+void launch_gemv_sub(int64_t n, int J, const cx<T> *V, int64_t ldv, const c128 *h, cx<T> *w, hipStream_t st) {
+    launch_gemv_sys<T>(n, J, V, ldv, 1, h, J, w, false, st);
+}
+template <typename T>
 void launch_gemv_add(int64_t n, int J, const cx<T> *V, int64_t ldv, const c128 *h, cx<T> *w, hipStream_t st) {
-    if (J <= 0 || n <= 0) return;
-    hipLaunchKernelGGL((k_gemv<T, 1>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, J, V, ldv, h, w);
+    launch_gemv_sys<T>(n, J, V, ldv, 1, h, J, w, true, st);
+}
+
+// y[s] = c[s] x[s] for ns systems [ns][n] (c on the device)
+template <typename T>
+__global__ void k_scale_sys(int64_t n, const c128 *__restrict__ c, const cx<T> *__restrict__ x, cx<T> *__restrict__ y) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int s = blockIdx.y;
+    const cx<T> cc((T)c[s].re, (T)c[s].im);
+    y[s * n + i] = cc * x[s * n + i];
+}
+template <typename T>
+void launch_scale_sys(int64_t n, int ns, const c128 *c, const cx<T> *x, cx<T> *y, hipStream_t st) {
+    if (n <= 0 || ns <= 0) return;
+    hipLaunchKernelGGL(k_scale_sys<T>, dim3((unsigned)((n + 255) / 256), (unsigned)ns), dim3(256), 0, st, n, c, x, y);
     SIE_HIP(hipGetLastError());
 }
 
@@ -137,6 +175,11 @@ template void launch_convert<double, double>(const c128 *, c128 *, int64_t, hipS
                                  hipStream_t);                                                                \
     template void launch_gemv_sub<T>(int64_t, int, const cx<T> *, int64_t, const c128 *, cx<T> *, hipStream_t); \
     template void launch_gemv_add<T>(int64_t, int, const cx<T> *, int64_t, const c128 *, cx<T> *, hipStream_t); \
+    template void launch_dots_sys<T>(int64_t, int, const cx<T> *, int64_t, int, const cx<T> *, c128 *, int, c128 *, \
+                                     int, hipStream_t);                                                       \
+    template void launch_gemv_sys<T>(int64_t, int, const cx<T> *, int64_t, int, const c128 *, int, cx<T> *, bool, \
+                                     hipStream_t);                                                            \
+    template void launch_scale_sys<T>(int64_t, int, const c128 *, const cx<T> *, cx<T> *, hipStream_t);       \
     template void launch_diag_mul<T>(int64_t, const c128 *, const cx<T> *, cx<T> *, hipStream_t);
 SIE_INST_B(float)
 SIE_INST_B(double)

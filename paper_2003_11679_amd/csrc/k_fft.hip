@@ -335,15 +335,17 @@ __global__ void __launch_bounds__(NT, MINW) k_fft_pass(const cx<T> *__restrict__
 // nz <= mz/2 live) field by field through LDS: forward z (pruned input),
 // spectral product, inverse z (pruned output, keep nz).
 // Element q of thread t is (kz, xi) = (t / tx + q NT / tx, t mod tx).
-//   MODE 0: each of the nf fields times G; the block handles rows ky and
-//           my - ky (ky <= my/2), which see the same G values, and reads
-//           those once into registers for both rows and every field.
-//   MODE 1: the three fields (J_x, J_y, J_z) become grad G x J,
+//   MODE 0: each field times G; a block takes up to kZFields fields
+//           (blockIdx.z chunk) of rows ky and my - ky (ky <= my/2), which
+//           see the same G values, and reads those once into registers.
+//   MODE 1: the fields (J_x, J_y, J_z) of triple blockIdx.z become grad G x J,
 //           psi_x = Gy Jz - Gz Jy, psi_y = Gz Jx - Gx Jz, psi_z = Gx Jy - Gy Jx;
 //           the transformed fields are held in registers until all three
 //           are known.
 // The spectrum is stored on its (mx/2+1)(my/2+1)(mz/2+1) octant: G is even
 // along every axis, dG/dx_a odd along axis a (kinds 1..3).
+constexpr int kZFields = 4;   // fields per G z-pass block
+
 template <typename T, int NT, int VPT, int LGL, int MODE, int MINW>
 __global__ void __launch_bounds__(NT, MINW) k_fft_zpass(cx<T> *__restrict__ buf, const cx<T> *__restrict__ spec,
                                                         int mx, int my, int nz, int nf) {
@@ -413,8 +415,9 @@ __global__ void __launch_bounds__(NT, MINW) k_fft_zpass(cx<T> *__restrict__ buf,
         cx<T> g[VPT];
 #pragma unroll
         for (int q = 0; q < VPT; ++q) g[q] = spec_q(0, q);
-        for (int t = 0; t < nrows * nf; ++t) {
-            const int row = t / nf, f = t - row * nf;
+        const int fb = blockIdx.z * kZFields, nfb = min(kZFields, nf - fb);
+        for (int t = 0; t < nrows * nfb; ++t) {
+            const int row = t / nfb, f = fb + t - row * nfb;
             load_field(f, row);
             lds_fft<T, NT, VPT, LGL, PITCH, false, true, false>(lb, tx, tw);
 #pragma unroll
@@ -426,9 +429,10 @@ __global__ void __launch_bounds__(NT, MINW) k_fft_zpass(cx<T> *__restrict__ buf,
         }
     } else {
         cx<T> J[3][VPT];
+        const int f0 = 3 * blockIdx.z;            // the block's (J_x, J_y, J_z) triple
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
-            load_field(f, 0);
+            load_field(f0 + f, 0);
             lds_fft<T, NT, VPT, LGL, PITCH, false, true, false>(lb, tx, tw);
 #pragma unroll
             for (int q = 0; q < VPT; ++q) J[f][q] = pos0 + dpos(q) < mz ? lds_ld(lds_q(q)) : cx<T>();
@@ -449,7 +453,7 @@ __global__ void __launch_bounds__(NT, MINW) k_fft_zpass(cx<T> *__restrict__ buf,
                 if (pos0 + dpos(q) < mz) lds_st(lds_q(q), J[c][q]);
             __syncthreads();
             lds_fft<T, NT, VPT, LGL, PITCH, true, false, true>(lb, tx, tw);
-            store_field(c, 0);
+            store_field(f0 + c, 0);
         }
     }
 }
@@ -575,16 +579,16 @@ static void zpass_lg(int lg, const Grid &g, const cx<T> *spec, int nf, int mode,
             constexpr int NT = FftShape<T>::nt, V = FftShape<T>::vpt, W = FftShape<T>::minw;
             using TS = Tile<T, NT, V, LGL>;
             check_tile<TS>();
-            dim3 grid((mx + TS::TX - 1) / TS::TX, my / 2 + 1);
+            dim3 grid((mx + TS::TX - 1) / TS::TX, my / 2 + 1, (nf + kZFields - 1) / kZFields);
             hipLaunchKernelGGL((k_fft_zpass<T, NT, V, LGL, 0, W>), grid, dim3(NT), TS::BYTES, st, bufB, spec, mx, my,
                                nz, nf);
         } else {
             constexpr int NT = FftShape<T>::grad_nt, V = FftShape<T>::grad_vpt, W = FftShape<T>::grad_minw;
             using TS = Tile<T, NT, V, LGL>;
             check_tile<TS>();
-            dim3 grid((mx + TS::TX - 1) / TS::TX, my);
+            dim3 grid((mx + TS::TX - 1) / TS::TX, my, nf / 3);
             hipLaunchKernelGGL((k_fft_zpass<T, NT, V, LGL, 1, W>), grid, dim3(NT), TS::BYTES, st, bufB, spec, mx, my,
-                               nz, 3);
+                               nz, nf);
         }
         SIE_HIP(hipGetLastError());
     } else {
@@ -592,13 +596,12 @@ static void zpass_lg(int lg, const Grid &g, const cx<T> *spec, int nf, int mode,
     }
 }
 
-// out may alias in.  nf fields; mode 0 (G) or 1 (grad G x, nf == 3).
+// One chunk of fields through the five passes (nf * nz <= 65535).
 template <typename T>
-void fft_convolve(const Grid &g, const cx<T> *spec, int nf, int mode, const cx<T> *in, cx<T> *out,
-                  cx<T> *bufA, cx<T> *bufB, hipStream_t st) {
+static void convolve_chunk(const Grid &g, const cx<T> *spec, int nf, int mode, const cx<T> *in, cx<T> *out,
+                           cx<T> *bufA, cx<T> *bufB, hipStream_t st) {
     const int nx = g.nl[0], ny = g.nl[1], nz = g.nl[2];
     const int mx = g.m[0], my = g.m[1], mz = g.m[2];
-    SIE_CHECK(mode == 0 || nf == 3, SIE_EINVAL, "grad-G convolution needs 3 fields");
     // x forward: lines (f, z, y) contiguous; batch b = f*nz + z, j = y
     pass<T>(in, bufA, mx, nx, mx, 1, 1, nx, mx, (long)ny * nx, (long)ny * mx, ny, (long)nf * nz, true, false, st);
     // y forward: lines along y, j = x (adjacent), batch b = f*nz + z
@@ -611,6 +614,25 @@ void fft_convolve(const Grid &g, const cx<T> *spec, int nf, int mode, const cx<T
     pass<T>(bufB, bufA, my, my, ny, mx, mx, 1, 1, (long)my * mx, (long)ny * mx, mx, (long)nf * nz, false, true, st);
     // x inverse: keep nx
     pass<T>(bufA, out, mx, mx, nx, 1, 1, mx, nx, (long)ny * mx, (long)ny * nx, ny, (long)nf * nz, true, true, st);
+}
+
+// out may alias in.  nf fields [nf][nl_z][nl_y][nl_x]: mode 0 each with G;
+// mode 1 consecutive triples (J_x, J_y, J_z) to grad G x J (nf % 3 == 0).
+// bufA / bufB hold nf fields of their pass layouts.
+template <typename T>
+void fft_convolve(const Grid &g, const cx<T> *spec, int nf, int mode, const cx<T> *in, cx<T> *out,
+                  cx<T> *bufA, cx<T> *bufB, hipStream_t st) {
+    SIE_CHECK(nf >= 1 && (mode == 0 || nf % 3 == 0), SIE_EINVAL, "grad-G convolution needs field triples");
+    const int nx = g.nl[0], ny = g.nl[1], nz = g.nl[2];
+    const int mx = g.m[0], my = g.m[1];
+    const int group = mode == 1 ? 3 : 1;
+    const int chunk = std::max(group, (65535 / nz) / group * group);
+    SIE_CHECK((long)chunk * nz <= 65535, SIE_EGRID, "live box too deep for one FFT batch");
+    const long flive = (long)nx * ny * nz, fa = (long)nz * ny * mx, fb = (long)nz * my * mx;
+    for (int f0 = 0; f0 < nf; f0 += chunk) {
+        const int c = std::min(chunk, nf - f0);
+        convolve_chunk<T>(g, spec, c, mode, in + f0 * flive, out + f0 * flive, bufA + f0 * fa, bufB + f0 * fb, st);
+    }
 }
 
 // Full (unpruned) forward 3D FFT of a [mz][my][mx] complex128 volume in place,

@@ -101,9 +101,11 @@ void launch_moments(const double *xyz, const int32_t *tri, const int32_t *tris, 
 // beta = sum_e x_e c_e q_e (trisrc[t] = alpha, beta_x, beta_y, beta_z).
 template <typename T>
 __global__ void k_tri_sources(int64_t ntg, const int32_t *__restrict__ tri_rwg, const T *__restrict__ coef,
-                              const cx<T> *__restrict__ x, cx<T> *__restrict__ src) {
+                              const cx<T> *__restrict__ x, int64_t ldx, cx<T> *__restrict__ src) {
     int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= ntg) return;
+    x += blockIdx.y * ldx;                 // right-hand side blockIdx.y
+    src += blockIdx.y * 4 * ntg;
     cx<T> a, bx, by, bz;
     for (int e = 0; e < 3; ++e) {
         const cx<T> xv = x[tri_rwg[3 * t + e]];
@@ -117,11 +119,12 @@ __global__ void k_tri_sources(int64_t ntg, const int32_t *__restrict__ tri_rwg, 
 
 template <typename T>
 void launch_tri_sources(const Grid &g, const int32_t *tri_rwg_loc, const T *tri_coef, const cx<T> *x,
-                        cx<T> *trisrc, hipStream_t st) {
+                        int64_t ldx, int nrhs, cx<T> *trisrc, hipStream_t st) {
     int64_t ntg = (int64_t)g.tris.size();
-    if (!ntg) return;
-    hipLaunchKernelGGL(k_tri_sources<T>, dim3((unsigned)((ntg + 255) / 256)), dim3(256), 0, st, ntg, tri_rwg_loc,
-                       tri_coef, x, trisrc);
+    if (!ntg || nrhs < 1) return;
+    SIE_CHECK(nrhs <= 65535, SIE_EINVAL, "too many right-hand sides");
+    hipLaunchKernelGGL(k_tri_sources<T>, dim3((unsigned)((ntg + 255) / 256), (unsigned)nrhs), dim3(256), 0, st, ntg,
+                       tri_rwg_loc, tri_coef, x, ldx, trisrc);
     SIE_HIP(hipGetLastError());
 }
 
@@ -137,9 +140,11 @@ __device__ inline T seg_sum(T v, int lpn) {
 template <typename T>
 __global__ void k_project(int64_t nlive, const int32_t *__restrict__ node_ptr, const int32_t *__restrict__ ent,
                           const T *__restrict__ mom, const cx<T> *__restrict__ src, cx<T> *__restrict__ grid,
-                          int nf, int lpn) {
+                          int nf, int lpn, int64_t ntg) {
     const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t v = gid / lpn;
+    src += blockIdx.y * 4 * ntg;           // right-hand side blockIdx.y
+    grid += blockIdx.y * nf * nlive;
     const int sub = (int)(gid % lpn);
     // every lane of a wave takes part in the shuffles; out-of-range nodes add zeros
     T s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -166,15 +171,19 @@ __global__ void k_project(int64_t nlive, const int32_t *__restrict__ node_ptr, c
 }
 
 template <typename T>
-void launch_project(const Grid &g, const T *mom, const cx<T> *trisrc, cx<T> *grid, int nfields, hipStream_t st) {
+void launch_project(const Grid &g, const T *mom, const cx<T> *trisrc, cx<T> *grid, int nfields, int nrhs,
+                    hipStream_t st) {
     const int64_t nlive = g.nlive();
+    if (nrhs < 1) return;
+    SIE_CHECK(nrhs <= 65535, SIE_EINVAL, "too many right-hand sides");
     // lanes per node: about two entries per lane on average
     const double avg = 27.0 * (double)g.tris.size() / (double)std::max<int64_t>(nlive, 1);
     int lpn = 1;
     while (lpn < 64 && lpn * 2 <= avg / 2.0) lpn *= 2;
     const int64_t threads = nlive * lpn;
-    hipLaunchKernelGGL(k_project<T>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, nlive,
-                       g.d_node_ptr.p, g.d_node_ent.p, mom, trisrc, grid, nfields, lpn);
+    hipLaunchKernelGGL(k_project<T>, dim3((unsigned)((threads + 255) / 256), (unsigned)nrhs), dim3(256), 0, st,
+                       nlive, g.d_node_ptr.p, g.d_node_ent.p, mom, trisrc, grid, nfields, lpn,
+                       (int64_t)g.tris.size());
     SIE_HIP(hipGetLastError());
 }
 
@@ -186,6 +195,8 @@ __global__ void k_interp(int64_t ntg, const int32_t *__restrict__ centre, int lo
                          cx<T> *__restrict__ out) {
     int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= ntg) return;
+    pot += blockIdx.y * nf * nlive;        // right-hand side blockIdx.y
+    out += blockIdx.y * 5 * ntg;
     const int cxi = centre[3 * t] - lox, cyi = centre[3 * t + 1] - loy, czi = centre[3 * t + 2] - loz;
     cx<T> psi, chx, chy, chz, zeta;
     for (int dz = 0; dz < 3; ++dz)
@@ -204,10 +215,13 @@ __global__ void k_interp(int64_t ntg, const int32_t *__restrict__ centre, int lo
 }
 
 template <typename T>
-void launch_interp(const Grid &g, const T *mom, const cx<T> *pot, int nfields, cx<T> *tripot, hipStream_t st) {
+void launch_interp(const Grid &g, const T *mom, const cx<T> *pot, int nfields, int nrhs, cx<T> *tripot,
+                   hipStream_t st) {
     int64_t ntg = (int64_t)g.tris.size();
-    if (!ntg) return;
-    hipLaunchKernelGGL(k_interp<T>, dim3((unsigned)((ntg + 255) / 256)), dim3(256), 0, st, ntg, g.d_centre.p,
+    if (!ntg || nrhs < 1) return;
+    SIE_CHECK(nrhs <= 65535, SIE_EINVAL, "too many right-hand sides");
+    hipLaunchKernelGGL(k_interp<T>, dim3((unsigned)((ntg + 255) / 256), (unsigned)nrhs), dim3(256), 0, st, ntg,
+                       g.d_centre.p,
                        g.lo[0], g.lo[1], g.lo[2], g.nl[0], g.nl[1], g.nlive(), mom, pot, nfields, tripot);
     SIE_HIP(hipGetLastError());
 }
@@ -291,6 +305,105 @@ void launch_spmv_far(const Grid &g, int64_t E, const int32_t *rwg_loc, const T *
     SIE_HIP(hipGetLastError());
 }
 
+// Right-hand-side transpose x [nrhs][E] -> xt [E][nrhs] through a 32 x 32
+// LDS tile, so that the batched near-field product reads the nrhs values of
+// one column as one contiguous row.
+template <typename T>
+__global__ void k_rhs_transpose(int64_t E, int nrhs, const cx<T> *__restrict__ x, cx<T> *__restrict__ xt) {
+    __shared__ T tre[32][33], tim[32][33];
+    const int64_t e0 = blockIdx.x * 32LL;
+    const int r0 = blockIdx.y * 32;
+    for (int i = threadIdx.y; i < 32; i += 8) {
+        const int r = r0 + i;
+        const int64_t e = e0 + threadIdx.x;
+        if (r < nrhs && e < E) {
+            const cx<T> v = x[r * E + e];
+            tre[i][threadIdx.x] = v.re;
+            tim[i][threadIdx.x] = v.im;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.y; i < 32; i += 8) {
+        const int64_t e = e0 + i;
+        const int r = r0 + threadIdx.x;
+        if (r < nrhs && e < E) xt[e * nrhs + r] = cx<T>(tre[threadIdx.x][i], tim[threadIdx.x][i]);
+    }
+}
+
+// Batched near-field product plus far part for nrhs right-hand sides:
+// y[r][row] = sum_j N[row][j] xt[j][r] + c_e (psi - q_e . chi) + kscal c_e zeta
+// (tripot of right-hand side r).  One 64-lane block per row, lane = right-
+// hand side (grid.y slices of 64): the row's column indices and values are
+// wave-uniform (scalar loads, read once for all right-hand sides), the x
+// values of a column are one contiguous row of xt.
+template <typename T>
+__global__ void __launch_bounds__(64) k_spmm_far(int64_t E, int64_t rwg0, int64_t rwg1, int nrhs,
+                                                 const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ cols,
+                                                 const cx<T> *__restrict__ vals, const int32_t *__restrict__ rwg_loc,
+                                                 const T *__restrict__ coef, const cx<T> *__restrict__ tripot,
+                                                 int64_t ntg, cx<T> kscal, const cx<T> *__restrict__ xt,
+                                                 cx<T> *__restrict__ y) {
+    const int64_t row = blockIdx.x;
+    const int r = blockIdx.y * 64 + threadIdx.x;
+    const bool act = r < nrhs;
+    if (row < rwg0 || row >= rwg1) {
+        if (act) y[r * E + row] = cx<T>();
+        return;
+    }
+    const int64_t rr = row - rwg0;
+    cx<T> acc;
+    if (vals) {
+        const int64_t b = row_ptr[rr], e = row_ptr[rr + 1];
+        const cx<T> *xr = xt + (act ? r : 0);
+        cx<T> a1, a2, a3;
+        int64_t j = b;
+        for (; j + 3 < e; j += 4) {
+            const int32_t c0 = cols[j], c1 = cols[j + 1], c2 = cols[j + 2], c3 = cols[j + 3];
+            const cx<T> v0 = vals[j], v1 = vals[j + 1], v2 = vals[j + 2], v3 = vals[j + 3];
+            acc += v0 * xr[(int64_t)c0 * nrhs];
+            a1 += v1 * xr[(int64_t)c1 * nrhs];
+            a2 += v2 * xr[(int64_t)c2 * nrhs];
+            a3 += v3 * xr[(int64_t)c3 * nrhs];
+        }
+        for (; j < e; ++j) acc += vals[j] * xr[(int64_t)cols[j] * nrhs];
+        acc += (a1 + a2) + a3;
+    }
+    if (!act) return;
+    if (tripot) {
+        const cx<T> *tp = tripot + (int64_t)r * 5 * ntg;
+        for (int s = 0; s < 2; ++s) {
+            const int32_t lc = rwg_loc[2 * rr + s];
+            const int64_t t = lc >> 2;
+            const int ed = lc & 3;
+            const T *c = coef + (t * 3 + ed) * 4;
+            const cx<T> *q = tp + 5 * t;
+            cx<T> v = q[0] - (c[1] * q[1] + c[2] * q[2] + c[3] * q[3]);
+            v += kscal * q[4];
+            acc += c[0] * v;
+        }
+    }
+    y[r * E + row] = acc;
+}
+
+// xt: scratch of E * nrhs values; x, y: [nrhs][E].
+template <typename T>
+void launch_spmm_far(const Grid &g, int64_t E, int nrhs, const int32_t *rwg_loc, const T *tri_coef,
+                     const cx<T> *tripot, cx<T> kscal, const cx<T> *vals, const cx<T> *x, cx<T> *xt, cx<T> *y,
+                     hipStream_t st) {
+    if (E == 0 || nrhs < 1) return;
+    SIE_CHECK(nrhs <= 65535 * 64, SIE_EINVAL, "too many right-hand sides");
+    SIE_CHECK(E <= 0x7fffffffLL, SIE_EINVAL, "too many RWG functions for one launch");
+    if (vals) {
+        hipLaunchKernelGGL(k_rhs_transpose<T>, dim3((unsigned)((E + 31) / 32), (unsigned)((nrhs + 31) / 32)),
+                           dim3(32, 8), 0, st, E, nrhs, x, xt);
+        SIE_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_spmm_far<T>, dim3((unsigned)E, (unsigned)((nrhs + 63) / 64)), dim3(64), 0, st, E, g.rwg0,
+                       g.rwg1, nrhs, g.d_row_ptr.p, g.d_cols.p, vals, rwg_loc, tri_coef, tripot,
+                       (int64_t)g.tris.size(), kscal, xt, y);
+    SIE_HIP(hipGetLastError());
+}
+
 // y = X x for the sparse X (real values, <= 5 per row, CSR int32).
 template <typename T>
 __global__ void k_x_apply(int64_t E, const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
@@ -311,10 +424,12 @@ void launch_x_apply(int64_t E, const int32_t *xptr, const int32_t *xcol, const T
 }
 
 #define SIE_INST(T)                                                                                           \
-    template void launch_tri_sources<T>(const Grid &, const int32_t *, const T *, const cx<T> *, cx<T> *,      \
-                                        hipStream_t);                                                          \
-    template void launch_project<T>(const Grid &, const T *, const cx<T> *, cx<T> *, int, hipStream_t);         \
-    template void launch_interp<T>(const Grid &, const T *, const cx<T> *, int, cx<T> *, hipStream_t);          \
+    template void launch_tri_sources<T>(const Grid &, const int32_t *, const T *, const cx<T> *, int64_t, int,  \
+                                        cx<T> *, hipStream_t);                                                 \
+    template void launch_project<T>(const Grid &, const T *, const cx<T> *, cx<T> *, int, int, hipStream_t);    \
+    template void launch_interp<T>(const Grid &, const T *, const cx<T> *, int, int, cx<T> *, hipStream_t);     \
+    template void launch_spmm_far<T>(const Grid &, int64_t, int, const int32_t *, const T *, const cx<T> *,     \
+                                     cx<T>, const cx<T> *, const cx<T> *, cx<T> *, cx<T> *, hipStream_t);       \
     template void launch_spmv_far<T>(const Grid &, int64_t, const int32_t *, const T *, const cx<T> *, cx<T>,   \
                                      const cx<T> *, const cx<T> *, cx<T> *, bool, hipStream_t);                 \
     template void launch_x_apply<T>(int64_t, const int32_t *, const int32_t *, const T *, const cx<T> *, cx<T> *, \

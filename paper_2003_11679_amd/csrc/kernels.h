@@ -18,11 +18,13 @@ void launch_moments(const double *xyz, const int32_t *tri, const int32_t *tris, 
                     double *mom64, float *mom32, hipStream_t st);
 template <typename T>
 void launch_tri_sources(const Grid &g, const int32_t *tri_rwg_loc, const T *tri_coef, const cx<T> *x,
-                        cx<T> *trisrc, hipStream_t st);
+                        int64_t ldx, int nrhs, cx<T> *trisrc, hipStream_t st);
 template <typename T>
-void launch_project(const Grid &g, const T *mom, const cx<T> *trisrc, cx<T> *grid, int nfields, hipStream_t st);
+void launch_project(const Grid &g, const T *mom, const cx<T> *trisrc, cx<T> *grid, int nfields, int nrhs,
+                    hipStream_t st);
 template <typename T>
-void launch_interp(const Grid &g, const T *mom, const cx<T> *pot, int nfields, cx<T> *tripot, hipStream_t st);
+void launch_interp(const Grid &g, const T *mom, const cx<T> *pot, int nfields, int nrhs, cx<T> *tripot,
+                   hipStream_t st);
 // y[r] = sum_j N[r,j] x[j] + sum over the row's triangles of the far part,
 // for rows r in [rwg0, rwg1); rows outside are zeroed.  kscal = -2 k^-2
 // (scalar part weight; 0 for K-type).  N may be null (far part only).
@@ -30,6 +32,10 @@ template <typename T>
 void launch_spmv_far(const Grid &g, int64_t E, const int32_t *rwg_loc, const T *tri_coef,
                      const cx<T> *tripot, cx<T> kscal, const cx<T> *vals, const cx<T> *x, cx<T> *y,
                      bool use_far, hipStream_t st);
+template <typename T>
+void launch_spmm_far(const Grid &g, int64_t E, int nrhs, const int32_t *rwg_loc, const T *tri_coef,
+                     const cx<T> *tripot, cx<T> kscal, const cx<T> *vals, const cx<T> *x, cx<T> *xt, cx<T> *y,
+                     hipStream_t st);
 template <typename T>
 void launch_x_apply(int64_t E, const int32_t *xptr, const int32_t *xcol, const T *xval, const cx<T> *x,
                     cx<T> *y, hipStream_t st);

@@ -362,19 +362,27 @@ static void build_x(sie_problem *p) {
     p->d_xval32.upload(val32);
 }
 
+// Scratch for products of up to nrhs right-hand sides (grown on demand; E is
+// the number of RWG functions, for the transposed right-hand sides).
 template <typename T>
-static void ensure_work(Grid &g, Work<T> &w) {
-    if (w.grid.n) return;
-    const int F = 4;
-    w.grid.alloc(F * g.nlive());
-    w.bufA.alloc((size_t)F * g.nl[2] * g.nl[1] * g.m[0]);
-    w.bufB.alloc((size_t)F * g.nl[2] * g.m[1] * g.m[0]);
-    w.trisrc.alloc(4 * g.tris.size());
-    w.tripot.alloc(5 * g.tris.size());
+static void ensure_work(Grid &g, Work<T> &w, int nrhs, int64_t E) {
+    if (w.cap_rhs < nrhs) {
+        const size_t F = 4, R = (size_t)nrhs;
+        w.grid.alloc(R * F * g.nlive());
+        w.bufA.alloc(R * F * g.nl[2] * g.nl[1] * g.m[0]);
+        w.bufB.alloc(R * F * g.nl[2] * g.m[1] * g.m[0]);
+        w.trisrc.alloc(R * 4 * g.tris.size());
+        w.tripot.alloc(R * 5 * g.tris.size());
+        w.cap_rhs = nrhs;
+    }
+    if (nrhs > 1 && w.xt.n < (size_t)nrhs * E) w.xt.alloc((size_t)nrhs * E);
 }
 
-template <> Work<double> &work_of<double>(Grid &g) { ensure_work(g, g.w64); return g.w64; }
-template <> Work<float> &work_of<float>(Grid &g) { ensure_work(g, g.w32); return g.w32; }
+template <> Work<double> &work_of<double>(Grid &g) { ensure_work(g, g.w64, 1, 0); return g.w64; }
+template <> Work<float> &work_of<float>(Grid &g) { ensure_work(g, g.w32, 1, 0); return g.w32; }
+template <typename T> static Work<T> &work_rhs(Grid &g, int nrhs, int64_t E);
+template <> Work<double> &work_rhs<double>(Grid &g, int nrhs, int64_t E) { ensure_work(g, g.w64, nrhs, E); return g.w64; }
+template <> Work<float> &work_rhs<float>(Grid &g, int nrhs, int64_t E) { ensure_work(g, g.w32, nrhs, E); return g.w32; }
 
 template <typename T> static const T *mom_of(Grid &g);
 template <> const double *mom_of<double>(Grid &g) { return g.d_mom64.p; }
@@ -450,14 +458,32 @@ void matvec(sie_problem *p, Medium &md, sie_op op, int nrhs, const cx<T> *x, cx<
     const cx<T> kscal((T)ks.re, (T)ks.im);
     StageTimer &tm = p->timer;
     hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (nrhs > 1) {
+        // batched: every stage takes all right-hand sides at once; the
+        // near-field values are streamed once for the whole batch
+        Work<T> &wb = work_rhs<T>(g, nrhs, E);
+        if (tm.on) { tm.begin(ST_PRODUCT, st, e0); tm.begin(ST_PROJECT, st, e1); }
+        launch_tri_sources<T>(g, g.d_trirwg.p, coef_of<T>(g), x, E, nrhs, wb.trisrc.p, st);
+        launch_project<T>(g, mom_of<T>(g), wb.trisrc.p, wb.grid.p, F, nrhs, st);
+        if (tm.on) { tm.end(ST_PROJECT, st, e1); tm.begin(ST_FFT, st, e1); }
+        fft_convolve<T>(g, spec_of<T>(md), F * nrhs, op == SIE_OP_L ? 0 : 1, wb.grid.p, wb.grid.p, wb.bufA.p,
+                        wb.bufB.p, st);
+        if (tm.on) { tm.end(ST_FFT, st, e1); tm.begin(ST_INTERP, st, e1); }
+        launch_interp<T>(g, mom_of<T>(g), wb.grid.p, F, nrhs, wb.tripot.p, st);
+        if (tm.on) { tm.end(ST_INTERP, st, e1); tm.begin(ST_SPMV, st, e1); }
+        launch_spmm_far<T>(g, E, nrhs, g.d_rwgloc.p, coef_of<T>(g), wb.tripot.p, kscal, near_of<T>(md, op), x,
+                           wb.xt.p, y, st);
+        if (tm.on) { tm.end(ST_SPMV, st, e1); tm.end(ST_PRODUCT, st, e0); }
+        return;
+    }
     for (int r = 0; r < nrhs; ++r) {
         if (tm.on) { tm.begin(ST_PRODUCT, st, e0); tm.begin(ST_PROJECT, st, e1); }
-        launch_tri_sources<T>(g, g.d_trirwg.p, coef_of<T>(g), x + r * E, w.trisrc.p, st);
-        launch_project<T>(g, mom_of<T>(g), w.trisrc.p, w.grid.p, F, st);
+        launch_tri_sources<T>(g, g.d_trirwg.p, coef_of<T>(g), x + r * E, E, 1, w.trisrc.p, st);
+        launch_project<T>(g, mom_of<T>(g), w.trisrc.p, w.grid.p, F, 1, st);
         if (tm.on) { tm.end(ST_PROJECT, st, e1); tm.begin(ST_FFT, st, e1); }
         fft_convolve<T>(g, spec_of<T>(md), F, op == SIE_OP_L ? 0 : 1, w.grid.p, w.grid.p, w.bufA.p, w.bufB.p, st);
         if (tm.on) { tm.end(ST_FFT, st, e1); tm.begin(ST_INTERP, st, e1); }
-        launch_interp<T>(g, mom_of<T>(g), w.grid.p, F, w.tripot.p, st);
+        launch_interp<T>(g, mom_of<T>(g), w.grid.p, F, 1, w.tripot.p, st);
         if (tm.on) { tm.end(ST_INTERP, st, e1); tm.begin(ST_SPMV, st, e1); }
         launch_spmv_far<T>(g, E, g.d_rwgloc.p, coef_of<T>(g), w.tripot.p, kscal, near_of<T>(md, op), x + r * E,
                            y + r * E, true, st);
@@ -469,8 +495,8 @@ template <typename T>
 void stage_project(sie_problem *p, Medium &md, const cx<T> *x, cx<T> *grid, hipStream_t st) {
     Grid &g = *md.grid;
     Work<T> &w = work_of<T>(g);
-    launch_tri_sources<T>(g, g.d_trirwg.p, coef_of<T>(g), x, w.trisrc.p, st);
-    launch_project<T>(g, mom_of<T>(g), w.trisrc.p, grid, 4, st);
+    launch_tri_sources<T>(g, g.d_trirwg.p, coef_of<T>(g), x, p->mesh.nrwg, 1, w.trisrc.p, st);
+    launch_project<T>(g, mom_of<T>(g), w.trisrc.p, grid, 4, 1, st);
 }
 
 template <typename T>
@@ -487,7 +513,7 @@ void stage_interpolate(sie_problem *p, Medium &md, const cx<T> *grid, cx<T> *y, 
     Grid &g = *md.grid;
     Work<T> &w = work_of<T>(g);
     const c128 ks = cdiv(c128(-2.0), md.k * md.k);
-    launch_interp<T>(g, mom_of<T>(g), grid, 4, w.tripot.p, st);
+    launch_interp<T>(g, mom_of<T>(g), grid, 4, 1, w.tripot.p, st);
     launch_spmv_far<T>(g, p->mesh.nrwg, g.d_rwgloc.p, coef_of<T>(g), w.tripot.p, cx<T>((T)ks.re, (T)ks.im),
                        (const cx<T> *)nullptr, (const cx<T> *)nullptr, y, true, st);
 }

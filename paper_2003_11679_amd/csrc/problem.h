@@ -103,6 +103,15 @@ template <typename T> void launch_gemv_sub(int64_t n, int J, const cx<T> *V, int
 // w += sum_j V[j] h[j]
 template <typename T> void launch_gemv_add(int64_t n, int J, const cx<T> *V, int64_t ldv, const c128 *h, cx<T> *w,
                                            hipStream_t st);
+// Batched forms for ns systems stored [ns][n] inside every vector (Krylov
+// vector j at V + j * ldv): dots into h[s * hstride + j], w[s] -+= V[s] h[s],
+// y[s] = c[s] x[s].
+template <typename T> void launch_dots_sys(int64_t n, int J, const cx<T> *V, int64_t ldv, int ns, const cx<T> *w,
+                                           c128 *part, int nb, c128 *h, int hstride, hipStream_t st);
+template <typename T> void launch_gemv_sys(int64_t n, int J, const cx<T> *V, int64_t ldv, int ns, const c128 *h,
+                                           int hstride, cx<T> *w, bool add, hipStream_t st);
+template <typename T> void launch_scale_sys(int64_t n, int ns, const c128 *c, const cx<T> *x, cx<T> *y,
+                                            hipStream_t st);
 // y[i] = d[i] * x[i] with per-element complex d (range [i0, i1), zero elsewhere if zero_out)
 template <typename T> void launch_diag_mul(int64_t n, const c128 *d, const cx<T> *x, cx<T> *y, hipStream_t st);
 constexpr int DOT_BLOCKS = 256;

@@ -13,6 +13,12 @@
 // Gram-Schmidt applied twice with FP64 dot products, Givens rotations and the
 // triangular solve in FP64 on the host) drives both levels.
 //
+// Several right-hand sides are solved together: the Krylov solvers iterate
+// them in lock step (one Hessenberg matrix per right-hand side) and every
+// operator product takes the whole batch, so the near-field values are
+// streamed once per batch (SpMM) and the FFTs run over all fields of all
+// right-hand sides.
+//
 // Precision: SIE_FP64 runs every stage in complex128.  SIE_FP32 runs the
 // interior work (K_i products and the nested L_i solves, which dominate the
 // operator count) in complex64 inside FP64 iterative refinement: the residual
@@ -37,129 +43,189 @@ namespace sie {
 static const double PI = 3.14159265358979323846;
 
 // ---------------------------------------------------------------- GMRES
+// nb independent systems with the same operator iterate in lock step: every
+// vector holds the nb systems [nb][n], one operator application serves all
+// of them, and each keeps its own Hessenberg matrix, rotations, tolerance
+// and convergence state.  A system that has converged (or stalled) in a
+// cycle stops extending its basis; its next basis vectors are zero, so the
+// shared products carry zeros for it.
 template <typename T>
 struct Gmres {
-    int64_t n = 0;
-    int m = 0;
-    DBuf<cx<T>> V, Zb, w, r;
-    DBuf<c128> part, hd;
+    int64_t n = 0;                  // length of one system
+    int nb = 0;                     // systems
+    int m = 0;                      // restart length
+    int dblk = 1;                   // dot-product blocks per system
+    DBuf<cx<T>> V, Zb, w, r;        // V: (m+1) x [nb][n], Zb: m x [nb][n], w, r: [nb][n]
+    DBuf<c128> part, hd, cd;
     using Op = std::function<void(const cx<T> *, cx<T> *)>;
-
-    void init(int64_t n_, int m_) {
-        if (n == n_ && m == m_) return;
-        n = n_; m = m_;
-        V.alloc((size_t)(m + 1) * n);
-        Zb.alloc((size_t)m * n);
-        w.alloc(n);
-        r.alloc(n);
-        part.alloc((size_t)(m + 1) * DOT_BLOCKS);
-        hd.alloc(m + 1);
-    }
-
-    std::vector<c128> dots(int J, const cx<T> *Vp, const cx<T> *x, hipStream_t st) {
-        launch_dots<T>(n, J, Vp, n, x, part.p, DOT_BLOCKS, hd.p, st);
-        std::vector<c128> h(J);
-        SIE_HIP(hipMemcpyAsync(h.data(), hd.p, J * sizeof(c128), hipMemcpyDeviceToHost, st));
-        SIE_HIP(hipStreamSynchronize(st));
-        return h;
-    }
-    double norm(const cx<T> *x, hipStream_t st) { return std::sqrt(std::max(0.0, dots(1, x, x, st)[0].re)); }
-
-    // Solves A x = b (x holds the initial guess).  Returns iterations; *relres
-    // receives the final relative residual estimate.
     const char *tag = "gmres";
-    // Stagnation window: a cycle that gains under 1 % over this many
+    // Stagnation window: a system that gains under 1 % over this many
     // iterations hands back to the caller (the precision floor of an FP32
     // correction); 0 disables it.
     int stag_window = 25;
-    int solve(const Op &A, const Op &M, const cx<T> *b, cx<T> *x, double tol, int maxit, double *relres,
-              hipStream_t st, int *napply = nullptr) {
+
+    void init(int64_t n_, int nb_, int m_) {
+        if (n == n_ && nb == nb_ && m == m_) return;
+        n = n_; nb = nb_; m = m_;
+        const size_t blk = (size_t)nb * n;
+        V.alloc((size_t)(m + 1) * blk);
+        Zb.alloc((size_t)m * blk);
+        w.alloc(blk);
+        r.alloc(blk);
+        dblk = (int)std::min<int64_t>(DOT_BLOCKS, std::max<int64_t>(4, (n + 4095) / 4096));
+        part.alloc((size_t)nb * (m + 1) * dblk);
+        hd.alloc((size_t)nb * (m + 1));
+        cd.alloc(nb);
+    }
+    // h[s][j] = V_j[s]^H x[s], j < J (V_j at Vp + j * nb * n)
+    std::vector<c128> dots(int J, const cx<T> *Vp, const cx<T> *x, hipStream_t st) {
+        launch_dots_sys<T>(n, J, Vp, (int64_t)nb * n, nb, x, part.p, dblk, hd.p, m + 1, st);
+        std::vector<c128> h((size_t)nb * (m + 1));
+        SIE_HIP(hipMemcpyAsync(h.data(), hd.p, h.size() * sizeof(c128), hipMemcpyDeviceToHost, st));
+        SIE_HIP(hipStreamSynchronize(st));
+        return h;
+    }
+    std::vector<double> norms(const cx<T> *x, hipStream_t st) {
+        std::vector<c128> h = dots(1, x, x, st);
+        std::vector<double> out(nb);
+        for (int k = 0; k < nb; ++k) out[k] = std::sqrt(std::max(0.0, h[(size_t)k * (m + 1)].re));
+        return out;
+    }
+    void scale(const std::vector<c128> &c, const cx<T> *x, cx<T> *y, hipStream_t st) {
+        SIE_HIP(hipMemcpyAsync(cd.p, c.data(), nb * sizeof(c128), hipMemcpyHostToDevice, st));
+        launch_scale_sys<T>(n, nb, cd.p, x, y, st);
+    }
+
+    // Solves A x = b for the nb systems (x holds the initial guesses), each
+    // to its own relative tolerance tol[k].  Returns the iterations of the
+    // longest system; relres[k] receives the final relative residuals.
+    int solve(const Op &A, const Op &M, const cx<T> *b, cx<T> *x, const std::vector<double> &tol, int maxit,
+              std::vector<double> *relres, hipStream_t st, int *napply = nullptr) {
         static const bool trace = std::getenv("SIE_TRACE") != nullptr;
-        const double bn = norm(b, st);
-        if (bn == 0.0) {
-            SIE_HIP(hipMemsetAsync(x, 0, n * sizeof(cx<T>), st));
-            if (relres) *relres = 0.0;
-            return 0;
+        const std::vector<double> bn = norms(b, st);
+        std::vector<char> fin(nb, 0);
+        std::vector<double> res(nb, 0.0);
+        std::vector<c128> zero(nb, c128());
+        for (int k = 0; k < nb; ++k)
+            if (bn[k] == 0.0) fin[k] = 1;
+        {   // systems with a zero right-hand side: x = 0
+            std::vector<c128> keep(nb);
+            for (int k = 0; k < nb; ++k) keep[k] = c128(fin[k] ? 0.0 : 1.0);
+            scale(keep, x, x, st);
         }
+        const size_t mm = (size_t)(m + 1) * m;
+        std::vector<c128> H((size_t)nb * mm), g((size_t)nb * (m + 1)), sn((size_t)nb * m);
+        std::vector<double> cs((size_t)nb * m);
+        std::vector<std::vector<double>> hist(nb);
+        std::vector<char> stag(nb, 0);
         int it = 0;
-        double res = 1.0;
-        bool stagnated = false;
-        std::vector<double> hist;
-        std::vector<c128> H((size_t)(m + 1) * m), g(m + 1), sn(m);
-        std::vector<double> cs(m);
         while (true) {
             // r = b - A x
             A(x, r.p);
             if (napply) ++*napply;
-            launch_axpby<T>(n, c128(1.0), b, c128(-1.0), r.p, st);
-            const double beta = norm(r.p, st);
-            res = beta / bn;
-            if (trace) std::fprintf(stderr, "[%s] restart at it %d true res %.3e\n", tag, it, res);
-            if (res <= tol || it >= maxit) break;
-            launch_scale_into<T>(n, c128(1.0 / beta), r.p, V.p, st);
-            std::fill(g.begin(), g.end(), c128());
-            g[0] = c128(beta);
+            launch_axpby<T>((int64_t)nb * n, c128(1.0), b, c128(-1.0), r.p, st);
+            const std::vector<double> beta = norms(r.p, st);
+            bool all = true;
+            for (int k = 0; k < nb; ++k) {
+                if (bn[k] > 0.0) res[k] = beta[k] / bn[k];
+                if (!fin[k] && (res[k] <= tol[k] || stag[k])) fin[k] = 1;
+                all = all && fin[k];
+            }
+            if (trace) std::fprintf(stderr, "[%s] restart at it %d true res %.3e\n", tag, it, res[0]);
+            if (all || it >= maxit) break;
+            std::vector<c128> c0(nb);
+            std::vector<char> act(nb, 0);
+            std::vector<int> kb(nb, 0);
+            for (int k = 0; k < nb; ++k) {
+                act[k] = !fin[k];
+                c0[k] = act[k] ? c128(1.0 / beta[k]) : c128();
+                std::fill(g.begin() + (size_t)k * (m + 1), g.begin() + (size_t)(k + 1) * (m + 1), c128());
+                g[(size_t)k * (m + 1)] = c128(beta[k]);
+            }
+            scale(c0, r.p, V.p, st);
+            const int64_t blk = (int64_t)nb * n;
             int j = 0;
             for (; j < m && it < maxit; ++j, ++it) {
-                cx<T> *vj = V.p + (size_t)j * n, *zj = Zb.p + (size_t)j * n;
+                cx<T> *vj = V.p + (size_t)j * blk, *zj = Zb.p + (size_t)j * blk;
                 M(vj, zj);
                 A(zj, w.p);
                 if (napply) ++*napply;
+                // classical Gram-Schmidt, twice
                 std::vector<c128> h = dots(j + 1, V.p, w.p, st);
-                launch_gemv_sub<T>(n, j + 1, V.p, n, hd.p, w.p, st);
+                launch_gemv_sys<T>(n, j + 1, V.p, blk, nb, hd.p, m + 1, w.p, false, st);
                 std::vector<c128> h2 = dots(j + 1, V.p, w.p, st);
-                launch_gemv_sub<T>(n, j + 1, V.p, n, hd.p, w.p, st);
-                for (int i = 0; i <= j; ++i) h[i] += h2[i];
-                const double hn = norm(w.p, st);
-                // Givens
-                for (int i = 0; i < j; ++i) {
-                    const c128 a = h[i], bb = h[i + 1];
-                    h[i] = cs[i] * a + sn[i] * bb;
-                    h[i + 1] = cs[i] * bb - conj(sn[i]) * a;
-                }
-                {
-                    const c128 a = h[j];
-                    const double aa = std::sqrt(norm2(a));
-                    const double t = std::hypot(aa, hn);
-                    if (aa == 0.0) { cs[j] = 0.0; sn[j] = c128(1.0); h[j] = c128(t); }
-                    else {
-                        const c128 ph = (1.0 / aa) * a;
-                        cs[j] = aa / t;
-                        sn[j] = (hn / t) * ph;
-                        h[j] = t * ph;
+                launch_gemv_sys<T>(n, j + 1, V.p, blk, nb, hd.p, m + 1, w.p, false, st);
+                const std::vector<double> hn = norms(w.p, st);
+                std::vector<c128> cn(nb);
+                bool any = false;
+                for (int k = 0; k < nb; ++k) {
+                    if (!act[k]) continue;
+                    c128 *hk = h.data() + (size_t)k * (m + 1);
+                    const c128 *h2k = h2.data() + (size_t)k * (m + 1);
+                    for (int i = 0; i <= j; ++i) hk[i] += h2k[i];
+                    c128 *gk = g.data() + (size_t)k * (m + 1);
+                    double *csk = cs.data() + (size_t)k * m;
+                    c128 *snk = sn.data() + (size_t)k * m;
+                    for (int i = 0; i < j; ++i) {
+                        const c128 a = hk[i], bb = hk[i + 1];
+                        hk[i] = csk[i] * a + snk[i] * bb;
+                        hk[i + 1] = csk[i] * bb - conj(snk[i]) * a;
                     }
-                    g[j + 1] = -(conj(sn[j]) * g[j]);
-                    g[j] = cs[j] * g[j];
+                    {
+                        const c128 a = hk[j];
+                        const double aa = std::sqrt(norm2(a));
+                        const double t = std::hypot(aa, hn[k]);
+                        if (aa == 0.0) { csk[j] = 0.0; snk[j] = c128(1.0); hk[j] = c128(t); }
+                        else {
+                            const c128 ph = (1.0 / aa) * a;
+                            csk[j] = aa / t;
+                            snk[j] = (hn[k] / t) * ph;
+                            hk[j] = t * ph;
+                        }
+                        gk[j + 1] = -(conj(snk[j]) * gk[j]);
+                        gk[j] = csk[j] * gk[j];
+                    }
+                    c128 *Hk = H.data() + (size_t)k * mm;
+                    for (int i = 0; i <= j; ++i) Hk[(size_t)i * m + j] = hk[i];
+                    res[k] = std::sqrt(norm2(gk[j + 1])) / bn[k];
+                    kb[k] = j + 1;
+                    auto &hs = hist[k];
+                    hs.push_back(res[k]);
+                    if (stag_window > 0 && (int)hs.size() > stag_window &&
+                        res[k] > 0.99 * hs[hs.size() - 1 - stag_window])
+                        stag[k] = 1;
+                    if (res[k] <= tol[k] || hn[k] <= 1e-14 * beta[k] || stag[k]) act[k] = 0;
+                    if (act[k] && hn[k] > 1e-300) cn[k] = c128(1.0 / hn[k]);
+                    any = any || act[k];
                 }
-                for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h[i];
-                res = std::sqrt(norm2(g[j + 1])) / bn;
-                if (trace) std::fprintf(stderr, "[%s] it %d res %.3e\n", tag, it + 1, res);
-                hist.push_back(res);
-                if (stag_window > 0 && (int)hist.size() > stag_window &&
-                    res > 0.99 * hist[hist.size() - 1 - stag_window])
-                    stagnated = true;
-                if (hn > 0.0 && hn > 1e-300) launch_scale_into<T>(n, c128(1.0 / hn), w.p, V.p + (size_t)(j + 1) * n, st);
-                if (res <= tol || hn <= 1e-14 * beta || stagnated) { ++j; ++it; break; }
+                if (trace) std::fprintf(stderr, "[%s] it %d res %.3e\n", tag, it + 1, res[0]);
+                scale(cn, w.p, V.p + (size_t)(j + 1) * blk, st);
+                if (!any) { ++j; ++it; break; }
             }
-            // y = H^-1 g ; x += Zb y
-            const int k = j;
-            std::vector<c128> y(k);
-            for (int i = k - 1; i >= 0; --i) {
-                c128 s = g[i];
-                for (int l = i + 1; l < k; ++l) s -= H[(size_t)i * m + l] * y[l];
-                y[i] = cdiv(s, H[(size_t)i * m + i]);
+            // y_k = H_k^-1 g_k ; x_k += Zb_k y_k
+            std::vector<c128> y((size_t)nb * (m + 1));
+            int kmax = 0;
+            for (int k = 0; k < nb; ++k) {
+                const int kk = kb[k];
+                kmax = std::max(kmax, kk);
+                const c128 *Hk = H.data() + (size_t)k * mm;
+                const c128 *gk = g.data() + (size_t)k * (m + 1);
+                c128 *yk = y.data() + (size_t)k * (m + 1);
+                for (int i = kk - 1; i >= 0; --i) {
+                    c128 sacc = gk[i];
+                    for (int l = i + 1; l < kk; ++l) sacc -= Hk[(size_t)i * m + l] * yk[l];
+                    yk[i] = cdiv(sacc, Hk[(size_t)i * m + i]);
+                }
             }
-            SIE_HIP(hipMemcpyAsync(hd.p, y.data(), k * sizeof(c128), hipMemcpyHostToDevice, st));
-            launch_gemv_add<T>(n, k, Zb.p, n, hd.p, x, st);
-            if (stagnated) {
-                A(x, r.p);
-                launch_axpby<T>(n, c128(1.0), b, c128(-1.0), r.p, st);
-                res = norm(r.p, st) / bn;
-                break;
+            if (kmax > 0) {
+                SIE_HIP(hipMemcpyAsync(hd.p, y.data(), y.size() * sizeof(c128), hipMemcpyHostToDevice, st));
+                launch_gemv_sys<T>(n, kmax, Zb.p, blk, nb, hd.p, m + 1, x, true, st);
             }
         }
         if (relres) *relres = res;
-        return it;
+        int itmax = 0;
+        for (int k = 0; k < nb; ++k) itmax = std::max(itmax, (int)hist[k].size());
+        return itmax;
     }
 };
 
@@ -247,33 +313,37 @@ template <typename T> static Gmres<T> &inner_of(SolveState &s);
 template <> Gmres<double> &inner_of<double>(SolveState &s) { return s.gi64; }
 template <> Gmres<float> &inner_of<float>(SolveState &s) { return s.gi32; }
 
+// Operator set for nb right-hand sides at once: every vector is [nb][E].
 template <typename T>
 struct Ops {
     sie_problem *p;
     SolveState &s;
     hipStream_t st;
     int64_t E;
+    int nb;
+    int64_t NE;                    // nb * E
     cx<T> *t[6];
     double inner_tol;
     int inner_max_iter;
     int restart;
 
-    Ops(sie_problem *p_, SolveState &s_, hipStream_t st_, double itol, int imax, int rs)
-        : p(p_), s(s_), st(st_), E(p_->mesh.nrwg), inner_tol(itol), inner_max_iter(imax), restart(rs) {
+    Ops(sie_problem *p_, SolveState &s_, hipStream_t st_, double itol, int imax, int rs, int nb_)
+        : p(p_), s(s_), st(st_), E(p_->mesh.nrwg), nb(nb_), NE((int64_t)nb_ * p_->mesh.nrwg), inner_tol(itol),
+          inner_max_iter(imax), restart(rs) {
         DBuf<cx<T>> *tb = tmp_of<T>(s);
         for (int i = 0; i < 6; ++i) {
-            if (tb[i].n != (size_t)E) tb[i].alloc(E);
+            if (tb[i].n != (size_t)NE) tb[i].alloc(NE);
             t[i] = tb[i].p;
         }
-        inner_of<T>(s).init(E, restart);
-        outer_of<T>(s).init(E, restart);
+        inner_of<T>(s).init(E, nb, restart);
+        outer_of<T>(s).init(E, nb, restart);
         inner_of<T>(s).tag = sizeof(T) == 8 ? "inner64" : "inner32";
         outer_of<T>(s).tag = sizeof(T) == 8 ? "outer64" : "outer32";
     }
 
     void mv(Medium &md, sie_op op, const cx<T> *x, cx<T> *y) {
-        matvec<T>(p, md, op, 1, x, y, st);
-        if (op != SIE_OP_X) s.matvecs++;
+        matvec<T>(p, md, op, nb, x, y, st);
+        if (op != SIE_OP_X) s.matvecs += nb;
     }
     // y = sum_i (-j w eps~_i) L_i x   (block diagonal over objects)
     void Lhat(const cx<T> *x, cx<T> *y) {
@@ -282,10 +352,10 @@ struct Ops {
             const c128 sc = c128(0.0, -p->w) * md.eps;
             if (i == 0) {
                 mv(md, SIE_OP_L, x, y);
-                launch_scale_into<T>(E, sc, y, y, st);
+                launch_scale_into<T>(NE, sc, y, y, st);
             } else {
                 mv(md, SIE_OP_L, x, t[5]);
-                launch_axpby<T>(E, sc, t[5], c128(1.0), y, st);
+                launch_axpby<T>(NE, sc, t[5], c128(1.0), y, st);
             }
         }
     }
@@ -296,35 +366,35 @@ struct Ops {
                 if (i == 0) mv(p->ints[i], SIE_OP_K, x, y);
                 else {
                     mv(p->ints[i], SIE_OP_K, x, t[5]);
-                    launch_axpby<T>(E, c128(1.0), t[5], c128(1.0), y, st);
+                    launch_axpby<T>(NE, c128(1.0), t[5], c128(1.0), y, st);
                 }
             }
         } else {
             mv(p->ext, SIE_OP_K, x, y);
         }
         mv(p->ext, SIE_OP_X, x, t[4]);
-        launch_axpby<T>(E, c128(0.5 * sgn), t[4], c128(1.0), y, st);
+        launch_axpby<T>(NE, c128(0.5 * sgn), t[4], c128(1.0), y, st);
     }
     bool use_bj_in = false, use_bj_out = false;
-    void prec_inner(const cx<T> *x, cx<T> *y) {
-        if (use_bj_in) launch_bj_apply<T>(s.pin.nb, s.pin.B, s.pin.perm.p, bj_inv<T>(s.pin), x, y, st);
-        else SIE_HIP(hipMemcpyAsync(y, x, E * sizeof(cx<T>), hipMemcpyDeviceToDevice, st));
+    void bj(bool on, const BlockJacobi &b, const cx<T> *x, cx<T> *y) {
+        if (!on) {
+            SIE_HIP(hipMemcpyAsync(y, x, NE * sizeof(cx<T>), hipMemcpyDeviceToDevice, st));
+            return;
+        }
+        for (int k = 0; k < nb; ++k) launch_bj_apply<T>(b.nb, b.B, b.perm.p, bj_inv<T>(b), x + k * E, y + k * E, st);
     }
-    void prec_outer(const cx<T> *x, cx<T> *y) {
-        if (use_bj_out) launch_bj_apply<T>(s.pout.nb, s.pout.B, s.pout.perm.p, bj_inv<T>(s.pout), x, y, st);
-        else SIE_HIP(hipMemcpyAsync(y, x, E * sizeof(cx<T>), hipMemcpyDeviceToDevice, st));
-    }
+    void prec_inner(const cx<T> *x, cx<T> *y) { bj(use_bj_in, s.pin, x, y); }
+    void prec_outer(const cx<T> *x, cx<T> *y) { bj(use_bj_out, s.pout, x, y); }
     // Mixed precision: an FP64 operator set may delegate the interior work
     // (K_i products and the nested L_i solves) to an FP32 one.
     Ops<float> *lo = nullptr;
     // v = Lhat^-1 a (nested solve, eq. nest2)
     void inner_solve(const cx<T> *a, cx<T> *v);
     void inner_solve_native(const cx<T> *a, cx<T> *v) {
-        SIE_HIP(hipMemsetAsync(v, 0, E * sizeof(cx<T>), st));
-        double rr;
+        SIE_HIP(hipMemsetAsync(v, 0, NE * sizeof(cx<T>), st));
         int it = inner_of<T>(s).solve([&](const cx<T> *x, cx<T> *y) { Lhat(x, y); },
-                                      [&](const cx<T> *x, cx<T> *y) { prec_inner(x, y); }, a, v, inner_tol,
-                                      inner_max_iter, &rr, st);
+                                      [&](const cx<T> *x, cx<T> *y) { prec_inner(x, y); }, a, v,
+                                      std::vector<double>(nb, inner_tol), inner_max_iter, nullptr, st);
         s.inner_iters += it;
         s.inner_max = std::max(s.inner_max, it);
     }
@@ -339,7 +409,7 @@ struct Ops {
         Z(u, t[1]);
         KpX(false, -1.0, t[1], t[2]);
         mv(p->ext, SIE_OP_L, u, y);
-        launch_axpby<T>(E, c128(-1.0), t[2], c128(0.0, p->w) * p->ext.mu, y, st);
+        launch_axpby<T>(NE, c128(-1.0), t[2], c128(0.0, p->w) * p->ext.mu, y, st);
     }
 };
 
@@ -348,35 +418,39 @@ template <> void Ops<float>::Z(const c64 *u, c64 *v) { Z_native(u, v); }
 template <> void Ops<double>::inner_solve(const c128 *a, c128 *v) {
     if (!lo) { inner_solve_native(a, v); return; }
     c64 *a32 = lo->t[1], *v32 = lo->t[2];
-    launch_convert<double, float>(a, a32, E, st);
+    launch_convert<double, float>(a, a32, NE, st);
     lo->inner_solve_native(a32, v32);
-    launch_convert<float, double>(v32, v, E, st);
+    launch_convert<float, double>(v32, v, NE, st);
 }
 template <> void Ops<double>::Z(const c128 *u, c128 *v) {
     if (!lo) { Z_native(u, v); return; }
     c64 *u32 = lo->t[1], *v32 = lo->t[2];
-    launch_convert<double, float>(u, u32, E, st);
+    launch_convert<double, float>(u, u32, NE, st);
     lo->Z_native(u32, v32);
-    launch_convert<float, double>(v32, v, E, st);
+    launch_convert<float, double>(v32, v, NE, st);
 }
 
-// FP64 residual of the block equations: r1 = e - [j w mu0 L0 u - (K0 - X/2) v],
-// r2 = -[-(K_i + X/2) u + Lhat v]; returns ||r|| / ||e||.
-static double block_residual(Ops<double> &o, const c128 *e, const c128 *u, const c128 *v, c128 *r1, c128 *r2) {
-    const int64_t E = o.E;
+// FP64 residual of the block equations for the nb systems of o:
+// r1 = e - [j w mu0 L0 u - (K0 - X/2) v], r2 = -[-(K_i + X/2) u + Lhat v];
+// returns ||r_k|| / ||e_k|| per system.
+static std::vector<double> block_residual(Ops<double> &o, const c128 *e, const c128 *u, const c128 *v, c128 *r1,
+                                          c128 *r2) {
+    const int64_t NE = o.NE;
     hipStream_t st = o.st;
     // r1
     o.KpX(false, -1.0, v, o.t[2]);
     o.mv(o.p->ext, SIE_OP_L, u, r1);
-    launch_axpby<double>(E, c128(-1.0), o.t[2], c128(0.0, o.p->w) * o.p->ext.mu, r1, st);   // A1 x
-    launch_axpby<double>(E, c128(1.0), e, c128(-1.0), r1, st);                              // e - A1 x
+    launch_axpby<double>(NE, c128(-1.0), o.t[2], c128(0.0, o.p->w) * o.p->ext.mu, r1, st);   // A1 x
+    launch_axpby<double>(NE, c128(1.0), e, c128(-1.0), r1, st);                              // e - A1 x
     // r2 = (K_i + X/2) u - Lhat v
     o.KpX(true, +1.0, u, r2);
     o.Lhat(v, o.t[3]);
-    launch_axpby<double>(E, c128(-1.0), o.t[3], c128(1.0), r2, st);
+    launch_axpby<double>(NE, c128(-1.0), o.t[3], c128(1.0), r2, st);
     Gmres<double> &g = o.s.go64;
-    const double n1 = g.norm(r1, st), n2 = g.norm(r2, st), ne = g.norm(e, st);
-    return std::sqrt(n1 * n1 + n2 * n2) / ne;
+    const std::vector<double> n1 = g.norms(r1, st), n2 = g.norms(r2, st), ne = g.norms(e, st);
+    std::vector<double> out(o.nb);
+    for (int k = 0; k < o.nb; ++k) out[k] = ne[k] > 0.0 ? std::sqrt(n1[k] * n1[k] + n2[k] * n2[k]) / ne[k] : 0.0;
+    return out;
 }
 
 static void build_preconditioners(sie_problem *p, SolveState &s) {
@@ -394,6 +468,10 @@ static void build_preconditioners(sie_problem *p, SolveState &s) {
     s.pre_built = true;
 }
 
+// Krylov storage of one batch of right-hand sides is kept within this many
+// bytes (outer and nested bases, FP64 plus the FP32 nested copy).
+constexpr double kKrylovBudget = 24e9;
+
 static void solve_all(sie_problem *p, sie_precision prec, const sie_solver_opts &o, sie_report *rep) {
     SolveState &s = *p->solve;
     const int64_t E = s.E;
@@ -404,12 +482,18 @@ static void solve_all(sie_problem *p, sie_precision prec, const sie_solver_opts 
     double worst = 0.0;
     bool all_conv = true;
     const auto t0 = std::chrono::steady_clock::now();
-    Ops<double> o64(p, s, st, o.inner_tol, o.inner_max_iter, o.restart);
-    o64.use_bj_in = (o.precond & 1) != 0;
-    o64.use_bj_out = (o.precond & 2) != 0;
-    for (int r = 0; r < s.nrhs; ++r) {
-        c128 *e = s.e.p + r * E, *u = s.u.p + r * E, *v = s.v.p + r * E;
-        double res = 1.0;
+    // right-hand sides per batch: all of them, unless the Krylov bases
+    // (2 restart + 1 vectors per level, FP64 outer + nested, FP32 nested)
+    // would exceed the budget
+    const double per_rhs = (double)E * (2.0 * o.restart + 1.0) * (16.0 + 16.0 + 8.0);
+    const int nb = (int)std::max(1.0, std::min((double)s.nrhs, std::floor(kKrylovBudget / per_rhs)));
+    for (int r0 = 0; r0 < s.nrhs; r0 += nb) {
+        const int cnt = std::min(nb, s.nrhs - r0);
+        Ops<double> o64(p, s, st, o.inner_tol, o.inner_max_iter, o.restart, cnt);
+        o64.use_bj_in = (o.precond & 1) != 0;
+        o64.use_bj_out = (o.precond & 2) != 0;
+        c128 *e = s.e.p + r0 * E, *u = s.u.p + r0 * E, *v = s.v.p + r0 * E;
+        const int64_t NE = (int64_t)cnt * E;
         // Refinement sweeps: residual of the block equations in FP64, correction
         // from the nested GIBC solve.  SIE_FP32 delegates the interior work to
         // complex64 (the exterior products and outer Krylov vectors stay FP64:
@@ -417,49 +501,66 @@ static void solve_all(sie_problem *p, sie_precision prec, const sie_solver_opts 
         // below its scalar potential and does not survive FP32).
         std::unique_ptr<Ops<float>> o32;
         if (prec == SIE_FP32) {
-            o32.reset(new Ops<float>(p, s, st, std::max(o.inner_tol, 1e-5), o.inner_max_iter, o.restart));
+            o32.reset(new Ops<float>(p, s, st, std::max(o.inner_tol, 1e-5), o.inner_max_iter, o.restart, cnt));
             o32->use_bj_in = o64.use_bj_in;
             o32->use_bj_out = o64.use_bj_out;
             o64.lo = o32.get();
         }
-        SIE_HIP(hipMemsetAsync(u, 0, E * sizeof(c128), st));
-        SIE_HIP(hipMemsetAsync(v, 0, E * sizeof(c128), st));
-        DBuf<c128> r1(E), r2(E), du(E), dv(E), sv(E);
-        double prev = 2.0;
+        SIE_HIP(hipMemsetAsync(u, 0, NE * sizeof(c128), st));
+        SIE_HIP(hipMemsetAsync(v, 0, NE * sizeof(c128), st));
+        DBuf<c128> r1(NE), r2(NE), du(NE), dv(NE), sv(NE);
+        std::vector<double> prev(cnt, 2.0), res(cnt, 1.0);
+        std::vector<char> done(cnt, 0);
         for (int sw = 0; sw <= o.max_refine; ++sw) {
             res = block_residual(o64, e, u, v, r1.p, r2.p);
-            // stop at the tolerance, at the sweep cap, or when a sweep no longer
-            // halves the residual (the outer system itself has stagnated)
-            if (res <= o.tol || sw == o.max_refine || res > 0.5 * prev) break;
-            prev = res;
+            // a system stops at the tolerance, at the sweep cap, or when a
+            // sweep no longer halves its residual (its outer system has
+            // stagnated)
+            bool all = true;
+            std::vector<c128> keep(cnt);
+            for (int k = 0; k < cnt; ++k) {
+                if (!done[k] && (res[k] <= o.tol || sw == o.max_refine || res[k] > 0.5 * prev[k])) done[k] = 1;
+                prev[k] = res[k];
+                keep[k] = c128(done[k] ? 0.0 : 1.0);
+                all = all && done[k];
+            }
+            if (all) break;
             ++sweeps_total;
+            // finished systems take a zero correction
+            Gmres<double> &g = s.go64;
+            g.scale(keep, r1.p, r1.p, st);
+            g.scale(keep, r2.p, r2.p, st);
             // s = Lhat^-1 r2 ; r1' = r1 + (K0 - X/2) s
             o64.inner_solve(r2.p, sv.p);
             o64.KpX(false, -1.0, sv.p, o64.t[3]);
-            launch_axpby<double>(E, c128(1.0), o64.t[3], c128(1.0), r1.p, st);
-            SIE_HIP(hipMemsetAsync(du.p, 0, E * sizeof(c128), st));
+            launch_axpby<double>(NE, c128(1.0), o64.t[3], c128(1.0), r1.p, st);
+            SIE_HIP(hipMemsetAsync(du.p, 0, NE * sizeof(c128), st));
             // FP64: run through the plateaus of the low-frequency EFIE; FP32:
             // hand back when a correction stalls for longer than a plateau
-            s.go64.stag_window = prec == SIE_FP32 ? 100 : 0;
-            // relative tolerance of the correction solve: what is left to the
+            g.stag_window = prec == SIE_FP32 ? 100 : 0;
+            // relative tolerance of each correction solve: what is left to the
             // target, but at most three digits per FP32 sweep (its interior
             // products carry FP32 rounding)
-            const double need = o.tol / res;
-            const double sweep_tol = prec == SIE_FP32 ? std::max(need, 1e-3) : need;
-            double rr;
-            outer_total += s.go64.solve([&](const c128 *x, c128 *y) { o64.gibc(x, y); },
-                                        [&](const c128 *x, c128 *y) { o64.prec_outer(x, y); }, r1.p, du.p,
-                                        sweep_tol, o.max_iter, &rr, st);
+            std::vector<double> stol(cnt);
+            for (int k = 0; k < cnt; ++k) {
+                const double need = res[k] > 0.0 ? o.tol / res[k] : 1.0;
+                stol[k] = prec == SIE_FP32 ? std::max(need, 1e-3) : need;
+            }
+            outer_total += g.solve([&](const c128 *x, c128 *y) { o64.gibc(x, y); },
+                                   [&](const c128 *x, c128 *y) { o64.prec_outer(x, y); }, r1.p, du.p, stol,
+                                   o.max_iter, nullptr, st);
             // dv = Lhat^-1 (r2 + (K_i + X/2) du)
             o64.KpX(true, +1.0, du.p, o64.t[3]);
-            launch_axpby<double>(E, c128(1.0), r2.p, c128(1.0), o64.t[3], st);
+            launch_axpby<double>(NE, c128(1.0), r2.p, c128(1.0), o64.t[3], st);
             o64.inner_solve(o64.t[3], dv.p);
-            launch_axpby<double>(E, c128(1.0), du.p, c128(1.0), u, st);
-            launch_axpby<double>(E, c128(1.0), dv.p, c128(1.0), v, st);
+            launch_axpby<double>(NE, c128(1.0), du.p, c128(1.0), u, st);
+            launch_axpby<double>(NE, c128(1.0), dv.p, c128(1.0), v, st);
         }
         o64.lo = nullptr;
-        worst = std::max(worst, res);
-        if (!(res <= o.tol)) all_conv = false;
+        for (int k = 0; k < cnt; ++k) {
+            worst = std::max(worst, res[k]);
+            if (!(res[k] <= o.tol)) all_conv = false;
+        }
     }
     SIE_HIP(hipStreamSynchronize(st));
     const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
