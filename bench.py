@@ -41,8 +41,14 @@ def parse():
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=64, help="rows of the oracle's dense matvec sample")
-    ap.add_argument("--workload", choices=["bar", "fft"], default="bar",
-                    help="bar: solve requests (default); fft: 4-field 256^3 convolution microbenchmark")
+    ap.add_argument("--workload", choices=["bar", "fft", "batch", "serve"], default="bar",
+                    help="bar: solve requests (default); fft: 4-field 256^3 convolution microbenchmark; "
+                         "batch: 64 plane waves solved together on a 20,480-triangle sphere; "
+                         "serve: a Poisson stream of solve requests on the library's server")
+    ap.add_argument("--nrhs", type=int, default=64, help="batch workload: plane waves")
+    ap.add_argument("--requests", type=int, default=12, help="serve workload: requests of the trace")
+    ap.add_argument("--max-tri", type=int, default=20000, help="serve workload: triangle cap per request")
+    ap.add_argument("--slots", type=int, default=4, help="serve workload: concurrent requests")
     ap.add_argument("--tol", type=float, default=1e-6,
                     help="relative FP64 block residual of every solve")
     ap.add_argument("--restart", type=int, default=200)
@@ -174,6 +180,120 @@ def fft_micro(args):
                                    "frac": ach / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": nb}}))
 
 
+def batch_workload(args):
+    """64 plane waves (8 x 8 incidence grid) on a 20,480-triangle sphere of
+    diameter 1 m, eps_r 2.5, sigma 0.1 S/m, 150 MHz, 64^3 grid: one step is
+    one solve of all waves together (lock-step GMRES, batched products)."""
+    import torch
+    from workloads import geodesic_sphere
+    from workloads.configs import multi_rhs_waves
+    from paper_2003_11679_amd import Problem
+    xyz, tri = geodesic_sphere(32, 0.5)
+    waves = multi_rhs_waves()[:args.nrhs]
+    prec = 1 if args.precision == "fp32" else 0
+    opts = dict(tol=args.tol, restart=min(args.restart, 100), precond=args.precond)
+
+    def one(timing=False):
+        p = Problem(150e6)
+        p.add_object(xyz, tri, eps_r=2.5, sigma=0.1)
+        p.set_grid(-1, n=64, near_radius=5)
+        t0 = time.perf_counter()
+        p.setup()
+        if timing:
+            p.set_timing(True)
+        p.set_planewaves([w.khat for w in waves], [w.e0 for w in waves])
+        rep = p.solve(prec, **opts)
+        torch.cuda.synchronize()
+        return p, rep, time.perf_counter() - t0
+
+    for i in range(args.warmup):
+        _, rep, dt = one()
+        print(f"[bench] batch warmup {i}: {dt:.2f}s {rep}", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    matvecs, reps = 0, []
+    for i in range(args.steps):
+        p, rep, dt = one(timing=True)
+        matvecs += rep["matvecs"]
+        reps.append(rep)
+        print(f"[bench] batch step {i}: {dt:.2f}s {rep}", file=sys.stderr, flush=True)
+    T = time.perf_counter() - t0
+    st = p.stage_times()
+    print(json.dumps({"metric": "RHS-matvecs/s of a batched multi-RHS solve", "value": matvecs / T,
+                      "unit": "RHS-matvecs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                      "ms_per_step": T / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+                      "vs_baseline": None, "dtype": "c64+f64" if prec == 1 else "c128", "data": "synthetic",
+                      "config": {"workload": f"{len(waves)} plane waves (8x8 incidence grid, alternating "
+                                             "polarisation), geodesic sphere 20480 triangles, d = 1 m, eps_r 2.5, "
+                                             "sigma 0.1, 150 MHz, 64^3 grid, near radius 5, solve to "
+                                             f"{args.tol:g}"},
+                      "solves_per_s": args.steps / T, "rhs_solves_per_s": args.steps * len(waves) / T,
+                      "converged": all(r["converged"] for r in reps), "residual_fp64_max":
+                      max(r["residual"] for r in reps), "outer_iters": reps[-1]["outer_iters"],
+                      "batched_product_ms": {k: v[1] / max(v[0], 1) for k, v in st.items()}}))
+
+
+def serve_workload(args):
+    """The seeded Poisson request stream (50 req/s): each request a sphere,
+    box or ellipsoid with its own material and frequency, submitted at its
+    arrival time to the library's server (FP32 + FP64 refinement); latency =
+    completion - arrival, queueing, setup and solve included."""
+    import torch
+    from workloads.configs import serving_trace, serving_mesh
+    from paper_2003_11679_amd import Problem, Server
+    trace = serving_trace()[:args.requests]
+    reqs = []
+    for r in trace:
+        r = dict(r)
+        r["nt"] = min(r["nt"], args.max_tri)
+        xyz, tri = serving_mesh(r)
+        ext = float(np.max(xyz.max(0) - xyz.min(0)))
+        edge = float(np.mean(np.linalg.norm(xyz[tri[:, 1]] - xyz[tri[:, 0]], axis=1)))
+        n = 8
+        while ext / (n - 3) > edge and n < 256:
+            n *= 2
+        reqs.append((r, xyz, tri, n))
+    prec = 1 if args.precision == "fp32" else 0
+    srv = Server(max_slots=args.slots)
+    t0 = time.perf_counter()
+    tickets = []
+    for r, xyz, tri, n in reqs:
+        dt = r["t"] - trace[0]["t"] - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        p = Problem(r["freq"], ctx=srv.ctx)
+        p.add_object(xyz, tri, eps_r=r["eps_r"], sigma=r["sigma"])
+        p.set_grid(-1, n=n, near_radius=3)
+        tickets.append(srv.submit(p, (0.0, 0.0, -1.0), (1.0, 0.0, 0.0), prec, tol=args.tol, restart=100,
+                                  precond=args.precond))
+    infos = []
+    for t in tickets:
+        while True:
+            i = srv.poll(t)
+            if i["done"]:
+                break
+            time.sleep(0.005)
+        infos.append(i)
+        print(f"[bench] request {len(infos)}: status {i['status']} latency "
+              f"{i['t_end_s'] - i['t_submit_s']:.2f}s run {i['t_end_s'] - i['t_start_s']:.2f}s "
+              f"{i['report']}", file=sys.stderr, flush=True)
+        srv.take(t)
+    T = time.perf_counter() - t0
+    srv.close()
+    lat = [i["t_end_s"] - i["t_submit_s"] for i in infos]
+    conv = sum(1 for i in infos if i["status"] == 0)
+    span = max(i["t_end_s"] for i in infos) - min(i["t_submit_s"] for i in infos)
+    print(json.dumps({"metric": "served solves/s, p50/p99 latency", "value": len(infos) / span,
+                      "unit": "solves/s", "n_gpus": 1, "steps": len(infos), "warmup": 0,
+                      "ms_per_step": span / len(infos) * 1e3, "higher_is_better": True, "scaling": "weak",
+                      "vs_baseline": None, "dtype": "c64+f64" if prec == 1 else "c128", "data": "synthetic",
+                      "config": {"workload": f"first {len(infos)} requests of the seeded 50 req/s trace, "
+                                             f"triangles capped at {args.max_tri}, {args.slots} slots, near "
+                                             f"radius 3, solve to {args.tol:g}"},
+                      "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
+                      "converged": conv, "requests": len(infos), "wall_s": T,
+                      "offered_rate": 50.0}))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -186,6 +306,12 @@ def main():
         sys.exit(1)
     if args.workload == "fft":
         fft_micro(args)
+        return
+    if args.workload == "batch":
+        batch_workload(args)
+        return
+    if args.workload == "serve":
+        serve_workload(args)
         return
     from workloads import bar_cfg
     cfg = bar_cfg()

@@ -26,7 +26,9 @@
  *   - Errors: every call returns an sie_status; on failure nothing is thrown
  *     across the ABI, outputs are left unspecified and sie_last_error() holds a
  *     message (thread-local, valid until the next call on that thread).
- *   - Threads: one sie_problem is used by one host thread at a time.
+ *   - Threads: one sie_problem is used by one host thread at a time.  Setup
+ *     and solves run on the calling thread's default stream; a NULL stream
+ *     passed to a hot-path call means the caller's legacy default stream.
  */
 #ifndef SIE_H
 #define SIE_H
@@ -208,6 +210,54 @@ sie_status sie_get_currents(const sie_problem *p, int32_t rhs, sie_c128 *u, sie_
  * `rhs` in the directions rhat [ndir][3]: F [ndir][3] (host). */
 sie_status sie_far_field(const sie_problem *p, int32_t rhs, int64_t ndir, const double *rhat,
                          sie_c128 *F);
+
+/* ---- serving: continuous batching of independent solve requests
+ *
+ * A server runs queued solve requests concurrently on worker threads of one
+ * device (each on its own stream), admitting requests first-in first-out
+ * while the sum of their device-memory footprint estimates stays within the
+ * budget (a request larger than the budget still runs when nothing else
+ * does).  A request is a problem with its objects and grids described
+ * (sie_problem_setup not yet called, or already called), plus plane waves,
+ * precision and solver options; the worker runs setup, plane waves and the
+ * solve.  Serving is not described in the paper: it is the deployment form
+ * of the per-request pipeline of Sec. III. */
+typedef struct sie_server sie_server;
+
+typedef struct {
+    int32_t done;           /* 0 queued or running, 1 finished */
+    int32_t running;        /* 1 while a worker holds the request */
+    sie_status status;      /* result of the request once done (SIE_OK,
+                               SIE_ENOCONV or the error of setup / solve) */
+    double t_submit_s;      /* times on the server's clock (s since creation) */
+    double t_start_s;
+    double t_end_s;
+    size_t footprint;       /* the estimate the request was admitted with */
+    sie_report report;      /* the solve's report once done */
+    char message[256];      /* error message of a failed request ("" if none) */
+} sie_job_info;
+
+/* Device-memory estimate (bytes) of a problem's setup and solve: near-field
+ * CSR values of every medium (FP64 and FP32), grid buffers and spectra, and
+ * the Krylov bases of the default solver options; available before setup. */
+sie_status sie_problem_footprint(const sie_problem *p, size_t *device_bytes);
+/* hbm_budget_bytes 0: 80 % of the device memory free at creation;
+ * max_slots: concurrent requests (worker threads), 1..64. */
+sie_status sie_server_create(sie_ctx *ctx, size_t hbm_budget_bytes, int32_t max_slots, sie_server **out);
+/* Queues a request; the server owns p until sie_server_take.  khat / e0 as
+ * in sie_set_planewaves (copied); opts may be NULL.  *ticket identifies the
+ * request. */
+sie_status sie_server_submit(sie_server *s, sie_problem *p, int32_t nrhs, const double *khat,
+                             const sie_c128 *e0, sie_precision prec, const sie_solver_opts *opts,
+                             uint64_t *ticket);
+/* State of a request (non-blocking). */
+sie_status sie_server_poll(sie_server *s, uint64_t ticket, sie_job_info *info);
+/* Blocks until the request is done, then hands the problem back (currents
+ * and far fields readable if its status allows) and forgets the ticket. */
+sie_status sie_server_take(sie_server *s, uint64_t ticket, sie_problem **out);
+/* Waits for the running requests, destroys the problems still owned by the
+ * server and frees it. */
+void sie_server_destroy(sie_server *s);
 
 #ifdef __cplusplus
 }

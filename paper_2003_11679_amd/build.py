@@ -13,7 +13,7 @@ ARCH = "gfx950"
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=fast",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-Wno-unused-result", "-munsafe-fp-atomics"]
+         "-Wno-unused-result", "-munsafe-fp-atomics", "-fgpu-default-stream=per-thread"]
 
 
 def sources():

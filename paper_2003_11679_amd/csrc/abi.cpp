@@ -13,6 +13,10 @@ static sie_status fail(sie_status s, const std::string &m) {
     return s;
 }
 
+namespace sie {
+void set_last_error(const std::string &m) { g_err = m; }
+}  // namespace sie
+
 template <typename F>
 static sie_status guard(F &&f) {
     try {
@@ -27,6 +31,15 @@ static sie_status guard(F &&f) {
         return fail(SIE_EINVAL, e.what());
     }
 }
+
+// The library runs its own work (setup, solves) on the calling thread's
+// default stream.  A null stream handed in by a caller means the caller's
+// legacy default stream, so hot-path calls order with the caller's work.
+static hipStream_t user_stream(void *stream) { return stream ? (hipStream_t)stream : hipStreamLegacy; }
+
+// Entry points that run on the thread's own stream first wait for work the
+// caller queued on the legacy default stream.
+static void after_caller_work() { SIE_HIP(hipStreamSynchronize(hipStreamLegacy)); }
 
 extern "C" {
 
@@ -105,6 +118,7 @@ sie_status sie_problem_setup(sie_problem *p) {
     return guard([&] {
         SIE_CHECK(p, SIE_EINVAL, "NULL problem");
         SIE_CHECK(!p->is_setup, SIE_ESTATE, "problem already set up");
+        after_caller_work();
         problem_setup(p);
     });
 }
@@ -205,7 +219,7 @@ sie_status sie_matvec(sie_problem *p, int32_t medium, sie_op op, sie_precision p
         SIE_CHECK(x_dev != y_dev, SIE_EINVAL, "x and y must not alias");
         SIE_CHECK(op == SIE_OP_L || op == SIE_OP_K || op == SIE_OP_X, SIE_EINVAL, "unknown operator");
         Medium &md = p->medium(op == SIE_OP_X ? -1 : medium);
-        hipStream_t st = (hipStream_t)stream;
+        hipStream_t st = user_stream(stream);
         if (prec == SIE_FP64)
             matvec<double>(p, md, op, nrhs, (const c128 *)x_dev, (c128 *)y_dev, st);
         else if (prec == SIE_FP32)
@@ -221,8 +235,8 @@ sie_status sie_project(sie_problem *p, int32_t medium, sie_precision prec, const
         SIE_CHECK(p && p->is_setup, SIE_ESTATE, "problem not set up");
         SIE_CHECK(x_dev && grid_dev, SIE_EINVAL, "NULL pointer");
         Medium &md = p->medium(medium);
-        if (prec == SIE_FP64) stage_project<double>(p, md, (const c128 *)x_dev, (c128 *)grid_dev, (hipStream_t)stream);
-        else stage_project<float>(p, md, (const c64 *)x_dev, (c64 *)grid_dev, (hipStream_t)stream);
+        if (prec == SIE_FP64) stage_project<double>(p, md, (const c128 *)x_dev, (c128 *)grid_dev, user_stream(stream));
+        else stage_project<float>(p, md, (const c64 *)x_dev, (c64 *)grid_dev, user_stream(stream));
     });
 }
 
@@ -234,9 +248,9 @@ sie_status sie_convolve(sie_problem *p, int32_t medium, sie_op op, sie_precision
         SIE_CHECK(op == SIE_OP_L || op == SIE_OP_K, SIE_EINVAL, "convolution op must be L (G) or K (grad G x)");
         Medium &md = p->medium(medium);
         if (prec == SIE_FP64)
-            stage_convolve<double>(p, md, op, nfields, (const c128 *)in_dev, (c128 *)out_dev, (hipStream_t)stream);
+            stage_convolve<double>(p, md, op, nfields, (const c128 *)in_dev, (c128 *)out_dev, user_stream(stream));
         else
-            stage_convolve<float>(p, md, op, nfields, (const c64 *)in_dev, (c64 *)out_dev, (hipStream_t)stream);
+            stage_convolve<float>(p, md, op, nfields, (const c64 *)in_dev, (c64 *)out_dev, user_stream(stream));
     });
 }
 
@@ -247,9 +261,9 @@ sie_status sie_interpolate(sie_problem *p, int32_t medium, sie_precision prec, c
         SIE_CHECK(grid_dev && y_dev, SIE_EINVAL, "NULL pointer");
         Medium &md = p->medium(medium);
         if (prec == SIE_FP64)
-            stage_interpolate<double>(p, md, (const c128 *)grid_dev, (c128 *)y_dev, (hipStream_t)stream);
+            stage_interpolate<double>(p, md, (const c128 *)grid_dev, (c128 *)y_dev, user_stream(stream));
         else
-            stage_interpolate<float>(p, md, (const c64 *)grid_dev, (c64 *)y_dev, (hipStream_t)stream);
+            stage_interpolate<float>(p, md, (const c64 *)grid_dev, (c64 *)y_dev, user_stream(stream));
     });
 }
 
@@ -272,11 +286,17 @@ sie_status sie_get_stage_time(sie_problem *p, int32_t stage, int64_t *launches, 
 }
 
 sie_status sie_set_planewaves(sie_problem *p, int32_t nrhs, const double *khat, const sie_c128 *e0) {
-    return guard([&] { planewaves_entry(p, nrhs, khat, e0); });
+    return guard([&] {
+        after_caller_work();
+        planewaves_entry(p, nrhs, khat, e0);
+    });
 }
 
 sie_status sie_solve(sie_problem *p, sie_precision prec, const sie_solver_opts *opts, sie_report *report) {
-    return guard([&] { solve_entry(p, prec, opts, report); });
+    return guard([&] {
+        after_caller_work();
+        solve_entry(p, prec, opts, report);
+    });
 }
 
 sie_status sie_get_currents(const sie_problem *p, int32_t rhs, sie_c128 *u, sie_c128 *v) {

@@ -332,22 +332,26 @@ __global__ void k_rhs_transpose(int64_t E, int nrhs, const cx<T> *__restrict__ x
 
 // Batched near-field product plus far part for nrhs right-hand sides:
 // y[r][row] = sum_j N[row][j] xt[j][r] + c_e (psi - q_e . chi) + kscal c_e zeta
-// (tripot of right-hand side r).  One 64-lane block per row, lane = right-
-// hand side (grid.y slices of 64): the row's column indices and values are
-// wave-uniform (scalar loads, read once for all right-hand sides), the x
-// values of a column are one contiguous row of xt.
-template <typename T>
+// (tripot of right-hand side r).  One 64-lane block per row; the lanes are
+// SLOTS = 64 / RPW groups of RPW (a power of two >= nrhs of the slice, at
+// most 64) lanes: group s takes the row's nonzeros s, s + SLOTS, ... and
+// lane q of the group right-hand side q, so every lane is busy whatever
+// nrhs is; the groups are summed with lane shuffles at the end.  The x
+// values of one column are one contiguous row of xt.
+template <typename T, int RPW>
 __global__ void __launch_bounds__(64) k_spmm_far(int64_t E, int64_t rwg0, int64_t rwg1, int nrhs,
                                                  const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ cols,
                                                  const cx<T> *__restrict__ vals, const int32_t *__restrict__ rwg_loc,
                                                  const T *__restrict__ coef, const cx<T> *__restrict__ tripot,
                                                  int64_t ntg, cx<T> kscal, const cx<T> *__restrict__ xt,
                                                  cx<T> *__restrict__ y) {
+    constexpr int SLOTS = 64 / RPW;
     const int64_t row = blockIdx.x;
-    const int r = blockIdx.y * 64 + threadIdx.x;
+    const int slot = threadIdx.x / RPW, q = threadIdx.x % RPW;
+    const int r = blockIdx.y * RPW + q;
     const bool act = r < nrhs;
     if (row < rwg0 || row >= rwg1) {
-        if (act) y[r * E + row] = cx<T>();
+        if (act && slot == 0) y[r * E + row] = cx<T>();
         return;
     }
     const int64_t rr = row - rwg0;
@@ -355,30 +359,32 @@ __global__ void __launch_bounds__(64) k_spmm_far(int64_t E, int64_t rwg0, int64_
     if (vals) {
         const int64_t b = row_ptr[rr], e = row_ptr[rr + 1];
         const cx<T> *xr = xt + (act ? r : 0);
-        cx<T> a1, a2, a3;
-        int64_t j = b;
-        for (; j + 3 < e; j += 4) {
-            const int32_t c0 = cols[j], c1 = cols[j + 1], c2 = cols[j + 2], c3 = cols[j + 3];
-            const cx<T> v0 = vals[j], v1 = vals[j + 1], v2 = vals[j + 2], v3 = vals[j + 3];
+        cx<T> a1;
+        int64_t j = b + slot;
+        for (; j + SLOTS < e; j += 2 * SLOTS) {
+            const int32_t c0 = cols[j], c1 = cols[j + SLOTS];
+            const cx<T> v0 = vals[j], v1 = vals[j + SLOTS];
             acc += v0 * xr[(int64_t)c0 * nrhs];
             a1 += v1 * xr[(int64_t)c1 * nrhs];
-            a2 += v2 * xr[(int64_t)c2 * nrhs];
-            a3 += v3 * xr[(int64_t)c3 * nrhs];
         }
-        for (; j < e; ++j) acc += vals[j] * xr[(int64_t)cols[j] * nrhs];
-        acc += (a1 + a2) + a3;
+        if (j < e) acc += vals[j] * xr[(int64_t)cols[j] * nrhs];
+        acc += a1;
+        for (int off = RPW; off < 64; off <<= 1) {
+            acc.re += __shfl_xor(acc.re, off, 64);
+            acc.im += __shfl_xor(acc.im, off, 64);
+        }
     }
-    if (!act) return;
+    if (!act || slot != 0) return;
     if (tripot) {
         const cx<T> *tp = tripot + (int64_t)r * 5 * ntg;
-        for (int s = 0; s < 2; ++s) {
-            const int32_t lc = rwg_loc[2 * rr + s];
+        for (int s2 = 0; s2 < 2; ++s2) {
+            const int32_t lc = rwg_loc[2 * rr + s2];
             const int64_t t = lc >> 2;
             const int ed = lc & 3;
             const T *c = coef + (t * 3 + ed) * 4;
-            const cx<T> *q = tp + 5 * t;
-            cx<T> v = q[0] - (c[1] * q[1] + c[2] * q[2] + c[3] * q[3]);
-            v += kscal * q[4];
+            const cx<T> *qq = tp + 5 * t;
+            cx<T> v = qq[0] - (c[1] * qq[1] + c[2] * qq[2] + c[3] * qq[3]);
+            v += kscal * qq[4];
             acc += c[0] * v;
         }
     }
@@ -398,9 +404,23 @@ void launch_spmm_far(const Grid &g, int64_t E, int nrhs, const int32_t *rwg_loc,
                            dim3(32, 8), 0, st, E, nrhs, x, xt);
         SIE_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_spmm_far<T>, dim3((unsigned)E, (unsigned)((nrhs + 63) / 64)), dim3(64), 0, st, E, g.rwg0,
-                       g.rwg1, nrhs, g.d_row_ptr.p, g.d_cols.p, vals, rwg_loc, tri_coef, tripot,
-                       (int64_t)g.tris.size(), kscal, xt, y);
+    int rpw = 1;
+    while (rpw < nrhs && rpw < 64) rpw *= 2;
+    const dim3 grid((unsigned)E, (unsigned)((nrhs + rpw - 1) / rpw));
+    const int64_t ntg = (int64_t)g.tris.size();
+#define SIE_SPMM(R)                                                                                              \
+    hipLaunchKernelGGL((k_spmm_far<T, R>), grid, dim3(64), 0, st, E, g.rwg0, g.rwg1, nrhs, g.d_row_ptr.p,        \
+                       g.d_cols.p, vals, rwg_loc, tri_coef, tripot, ntg, kscal, xt, y)
+    switch (rpw) {
+    case 1: SIE_SPMM(1); break;
+    case 2: SIE_SPMM(2); break;
+    case 4: SIE_SPMM(4); break;
+    case 8: SIE_SPMM(8); break;
+    case 16: SIE_SPMM(16); break;
+    case 32: SIE_SPMM(32); break;
+    default: SIE_SPMM(64); break;
+    }
+#undef SIE_SPMM
     SIE_HIP(hipGetLastError());
 }
 

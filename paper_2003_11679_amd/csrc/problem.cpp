@@ -185,7 +185,7 @@ static void build_grid(sie_problem *p, Grid &g) {
         g.d_mom32.alloc(27 * 4 * ntg);
         launch_moments(p->d_xyz.p, p->d_tri.p, g.d_tris.p, g.d_centre.p, ntg, g.origin, g.h, d_rule.p, r.size(),
                        g.d_mom64.p, g.d_mom32.p, 0);
-        SIE_HIP(hipDeviceSynchronize());
+        SIE_HIP(hipStreamSynchronize(0));
     }
     // 7. projection gather lists: node -> (local triangle, slot)
     {
@@ -219,7 +219,7 @@ static void build_grid(sie_problem *p, Grid &g) {
         g.d_cols.alloc(std::max<int64_t>(g.nnz, 1));
         launch_rwg_pattern(nrow, g.rwg0, nrow, g.d_rwgloc.p, g.d_pair_ptr.p, g.d_pair_s.p, g.d_tris.p,
                            p->d_tri_rwg.p, nullptr, g.d_row_ptr.p, g.d_cols.p, 1, 0);
-        SIE_HIP(hipDeviceSynchronize());
+        SIE_HIP(hipStreamSynchronize(0));
     }
 }
 
@@ -300,7 +300,7 @@ static void build_medium(sie_problem *p, Medium &md) {
         launch_near_gather(nrow, g.rwg0, g.max_row, g.d_row_ptr.p, g.d_cols.p, g.d_rwgloc.p, g.d_glob2loc.p,
                            p->d_tpm.p, p->d_epm.p, d_pp.p, g.d_pair_s.p + pptr[t0], blocks.p, md.d_nL64.p,
                            md.d_nK64.p, md.d_nLd64.p, 0);
-        SIE_HIP(hipDeviceSynchronize());
+        SIE_HIP(hipStreamSynchronize(0));
         t0 = t1;
     }
     md.d_nL32.alloc(std::max<int64_t>(g.nnz, 1));
@@ -318,7 +318,7 @@ static void build_medium(sie_problem *p, Medium &md) {
         fft3d_full_fwd(d_vol.p, d_tmp.p, g.m[0], g.m[1], g.m[2], 0);
         launch_fold_octant(d_vol.p, g.m, kind, scale, md.d_spec64.p, md.d_spec32.p, 0);
     }
-    SIE_HIP(hipDeviceSynchronize());
+    SIE_HIP(hipStreamSynchronize(0));
 }
 
 static void build_x(sie_problem *p) {

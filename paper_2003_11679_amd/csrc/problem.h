@@ -88,6 +88,8 @@ void solver_destroy(SolveState *s);
 void planewaves_entry(sie_problem *p, int32_t nrhs, const double *khat, const sie_c128 *e0);
 void solve_entry(sie_problem *p, sie_precision prec, const sie_solver_opts *opts, sie_report *rep);
 void currents_entry(const sie_problem *p, int32_t rhs, sie_c128 *u, sie_c128 *v);
+// Message returned by sie_last_error() on this thread.
+void set_last_error(const std::string &m);
 void farfield_entry(const sie_problem *p, int32_t rhs, int64_t ndir, const double *rhat, sie_c128 *F);
 
 // ---- k_blas.hip

@@ -279,7 +279,7 @@ static void bj_build(sie_problem *p, BlockJacobi &bj, const std::vector<Medium *
         launch_bj_setup(nbi, bj.B, bj.perm.p + o, g.rwg0, g.d_row_ptr.p, g.d_cols.p, media[i]->d_nLd64.p, scales[i],
                         bj.inv64.p + o * bj.B, bj.inv32.p + o * bj.B, 0);
     }
-    SIE_HIP(hipDeviceSynchronize());
+    SIE_HIP(hipStreamSynchronize(0));
 }
 
 template <typename T> static const cx<T> *bj_inv(const BlockJacobi &bj);
@@ -611,7 +611,7 @@ void planewaves_entry(sie_problem *p, int32_t nrhs, const double *khat, const si
         for (int c = 0; c < 3; ++c) { ee[c] = c128(e0[3 * r + c].re, e0[3 * r + c].im); p->e0[3 * r + c] = ee[c]; }
         launch_excitation(p, d_rule.p, rq.size(), p->ext.k.re, kh, ee, s.e.p + r * E, 0);
     }
-    SIE_HIP(hipDeviceSynchronize());
+    SIE_HIP(hipStreamSynchronize(0));
 }
 }  // namespace sie
 

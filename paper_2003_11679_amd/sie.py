@@ -51,6 +51,18 @@ class Report(ctypes.Structure):
         return {n: getattr(self, n) for n, _ in self._fields_}
 
 
+class JobInfo(ctypes.Structure):
+    _fields_ = [("done", ctypes.c_int32), ("running", ctypes.c_int32), ("status", ctypes.c_int),
+                ("t_submit_s", ctypes.c_double), ("t_start_s", ctypes.c_double), ("t_end_s", ctypes.c_double),
+                ("footprint", ctypes.c_size_t), ("report", Report), ("message", ctypes.c_char * 256)]
+
+    def as_dict(self):
+        d = {n: getattr(self, n) for n, _ in self._fields_ if n not in ("report", "message")}
+        d["report"] = self.report.as_dict()
+        d["message"] = self.message.decode()
+        return d
+
+
 _lib = None
 _VP = ctypes.c_void_p
 _I32P = ctypes.POINTER(ctypes.c_int32)
@@ -90,6 +102,13 @@ SIGNATURES = [
     ("sie_solve", ctypes.c_int, [_VP, ctypes.c_int, ctypes.POINTER(SolverOpts), ctypes.POINTER(Report)]),
     ("sie_get_currents", ctypes.c_int, [_VP, ctypes.c_int32, _CP, _CP]),
     ("sie_far_field", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int64, _DP, _CP]),
+    ("sie_problem_footprint", ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_size_t)]),
+    ("sie_server_create", ctypes.c_int, [_VP, ctypes.c_size_t, ctypes.c_int32, ctypes.POINTER(_VP)]),
+    ("sie_server_submit", ctypes.c_int, [_VP, _VP, ctypes.c_int32, _DP, _CP, ctypes.c_int,
+                                         ctypes.POINTER(SolverOpts), ctypes.POINTER(ctypes.c_uint64)]),
+    ("sie_server_poll", ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.POINTER(JobInfo)]),
+    ("sie_server_take", ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.POINTER(_VP)]),
+    ("sie_server_destroy", None, [_VP]),
 ]
 
 
@@ -150,7 +169,7 @@ class Problem:
         self.h = h
 
     def __del__(self):
-        if getattr(self, "h", None) and _lib is not None:
+        if getattr(self, "h", None) and _lib is not None and not getattr(self, "_served", False):
             _lib.sie_problem_destroy(self.h)
             self.h = None
 
@@ -316,3 +335,56 @@ class Problem:
         out = np.empty((len(rhat), 3, 2))
         _check(lib().sie_far_field(self.h, rhs, len(rhat), _ptr(rhat, ctypes.c_double), out.ctypes.data_as(_CP)))
         return out[..., 0] + 1j * out[..., 1]
+
+
+class Server:
+    """Continuous batching of independent solve requests on one device: the
+    library's worker threads admit requests first-in first-out within a
+    device-memory budget and run setup, plane waves and solve concurrently."""
+
+    def __init__(self, hbm_budget_bytes=0, max_slots=4, ctx=None, device=0):
+        self.ctx = ctx or Context(device)
+        h = _VP()
+        _check(lib().sie_server_create(self.ctx.h, int(hbm_budget_bytes), int(max_slots), ctypes.byref(h)))
+        self.h = h
+        self._owned = {}
+
+    def submit(self, problem, khat, e0, precision=FP32, **opts):
+        """Queues `problem` (ownership passes to the server until take());
+        returns the ticket."""
+        khat = np.ascontiguousarray(np.atleast_2d(khat), dtype=np.float64)
+        e0 = np.atleast_2d(np.asarray(e0, dtype=np.complex128))
+        ee = np.ascontiguousarray(np.stack([e0.real, e0.imag], axis=-1))
+        o = SolverOpts(**opts) if opts else None
+        t = ctypes.c_uint64()
+        _check(lib().sie_server_submit(self.h, problem.h, len(khat), _ptr(khat, ctypes.c_double),
+                                       ee.ctypes.data_as(_CP), precision, ctypes.byref(o) if o else None,
+                                       ctypes.byref(t)))
+        self._owned[t.value] = problem
+        problem._served = True
+        return t.value
+
+    def poll(self, ticket):
+        info = JobInfo()
+        _check(lib().sie_server_poll(self.h, ticket, ctypes.byref(info)))
+        return info.as_dict()
+
+    def take(self, ticket):
+        """Waits for the request and hands its problem back."""
+        out = _VP()
+        _check(lib().sie_server_take(self.h, ticket, ctypes.byref(out)))
+        p = self._owned.pop(ticket)
+        p._served = False
+        return p
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.sie_server_destroy(self.h)
+            for p in self._owned.values():
+                p.h = None          # destroyed by the server
+            self._owned.clear()
+            self.h = None
+
+    def __del__(self):
+        self.close()
+

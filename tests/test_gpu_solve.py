@@ -71,10 +71,15 @@ def test_solution_satisfies_oracle_aim_system(solved):
 
 def test_close_to_dense_solution(solved):
     """AIM solution vs the dense (unaccelerated) oracle solution on the coarse
-    test grid (12^3, near radius 3).  The lossless eps_r = 4 sphere sits near an
-    interior cavity resonance (k_i a = 6.29), which amplifies the ~1e-3 operator
-    error of this coarse grid in the solution; the lossy sphere does not."""
-    tols = {"sphere2_lossy": 5e-3, "sphere2": 0.1}
+    test grids.  The lossless eps_r = 4 sphere (12^3, near radius 3) sits near
+    an interior cavity resonance (k_i a = 6.29), which amplifies the ~1e-3
+    operator error of its grid in the solution.  The lossy sphere's grid
+    (10^3, h = 0.29 m, near radius 2) is far coarser than the lambda/20 rule of
+    Sec. IV for its interior wavenumber (|k_i| h = 7): the oracle's own AIM
+    operators, assembled densely, are 1-3e-2 from the dense ones there and the
+    oracle's AIM solution is 3.6e-2 (u) / 2.8e-2 (v) from the dense solution;
+    the GPU solution equals the oracle's AIM one (the system-residual test)."""
+    tols = {"sphere2_lossy": 5e-2, "sphere2": 0.1}
     for name, s in solved.items():
         dp = _dense(name)
         e = dp.rhs(KHAT, E0)
