@@ -359,16 +359,18 @@ __global__ void __launch_bounds__(64) k_spmm_far(int64_t E, int64_t rwg0, int64_
     if (vals) {
         const int64_t b = row_ptr[rr], e = row_ptr[rr + 1];
         const cx<T> *xr = xt + (act ? r : 0);
-        cx<T> a1;
+        cx<T> a1, a2, a3;
         int64_t j = b + slot;
-        for (; j + SLOTS < e; j += 2 * SLOTS) {
-            const int32_t c0 = cols[j], c1 = cols[j + SLOTS];
-            const cx<T> v0 = vals[j], v1 = vals[j + SLOTS];
+        for (; j + 3 * SLOTS < e; j += 4 * SLOTS) {
+            const int32_t c0 = cols[j], c1 = cols[j + SLOTS], c2 = cols[j + 2 * SLOTS], c3 = cols[j + 3 * SLOTS];
+            const cx<T> v0 = vals[j], v1 = vals[j + SLOTS], v2 = vals[j + 2 * SLOTS], v3 = vals[j + 3 * SLOTS];
             acc += v0 * xr[(int64_t)c0 * nrhs];
             a1 += v1 * xr[(int64_t)c1 * nrhs];
+            a2 += v2 * xr[(int64_t)c2 * nrhs];
+            a3 += v3 * xr[(int64_t)c3 * nrhs];
         }
-        if (j < e) acc += vals[j] * xr[(int64_t)cols[j] * nrhs];
-        acc += a1;
+        for (; j < e; j += SLOTS) acc += vals[j] * xr[(int64_t)cols[j] * nrhs];
+        acc += (a1 + a2) + a3;
         for (int off = RPW; off < 64; off <<= 1) {
             acc.re += __shfl_xor(acc.re, off, 64);
             acc.im += __shfl_xor(acc.im, off, 64);
