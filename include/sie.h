@@ -88,10 +88,20 @@ typedef struct {
     int32_t max_iter;    /* outer iteration cap, default 800 (Sec. V-A) */
     int32_t inner_max_iter; /* nested iteration cap, default 800 */
     int32_t max_refine;  /* FP64 refinement sweeps for SIE_FP32, default 10 */
-    int32_t precond;     /* bit mask of block-Jacobi preconditioners built from the
-                            direct near-region operators: 1 the nested interior
-                            solve (-j w eps_i L_i,NR), 2 the outer solve
-                            (j w mu0 L0,NR); 0 none (default) */
+    int32_t precond;     /* bit mask of preconditioners built from the direct
+                            near-region operators (eq. nest2pc): 1 block-Jacobi
+                            of -j w eps_i L_i,NR in the nested interior solves,
+                            2 block-Jacobi of j w mu0 L0,NR in the outer solve,
+                            4 the nested near-region preconditioner M_i applied
+                            as restricted additive Schwarz over clusters of
+                            C^3 grid cells with O cells of overlap (dense FP64
+                            inverses of M_i on each extended cluster; O spans
+                            about three mesh edges, C = 2 O, smaller when an
+                            extended cluster would exceed 2048 functions);
+                            only media whose field decays within the near
+                            region (five skin depths within R grid spacings)
+                            get it, the others run unpreconditioned.  1 and 4
+                            exclude each other (SIE_EINVAL); 0 none (default) */
 } sie_solver_opts;
 
 typedef struct {
@@ -185,10 +195,24 @@ sie_status sie_convolve(sie_problem *p, int32_t medium, sie_op op, sie_precision
 sie_status sie_interpolate(sie_problem *p, int32_t medium, sie_precision prec,
                            const void *grid_dev, void *y_dev, void *stream);
 
+/* Nested-solve preconditioner (eq. nest2pc, M_i = -j w eps_i L_i,NR of every
+ * object's interior medium), applied to nrhs vectors [nrhs][E] on the
+ * caller's stream: precond = 1 block-Jacobi, 4 restricted additive Schwarz
+ * over grid-cell clusters (see sie_solver_opts.precond; rows of media
+ * without clusters are copied).  Built on first use (host-synchronous); the
+ * same structure serves later solves.  x and y must not alias; complex64 for
+ * SIE_FP32, complex128 for SIE_FP64.  SIE_ESTATE before setup. */
+sie_status sie_nested_precond(sie_problem *p, int32_t precond, sie_precision prec, int32_t nrhs,
+                              const void *x_dev, void *y_dev, void *stream);
+/* Clusters of the built Schwarz preconditioner (-1 if not built); *owned
+ * (nullable) receives the number of RWG rows they own. */
+int32_t sie_nested_precond_clusters(const sie_problem *p, int64_t *owned);
+
 /* Stage timers (HIP events recorded on the stream of each product).
  * sie_set_timing(p, 1) starts recording (and clears the totals); stages:
  * 0 projection, 1 FFT convolution, 2 interpolation, 3 near-field CSR product
- * (the k_spmv_far kernel alone), 4 whole operator product.  Query returns the
+ * (the k_spmv_far kernel alone), 4 whole operator product, 5 the FP64
+ * near-field CSR products alone (also counted in 3).  Query returns the
  * number of timed launches and their summed duration (synchronises). */
 sie_status sie_set_timing(sie_problem *p, int32_t on);
 sie_status sie_get_stage_time(sie_problem *p, int32_t stage, int64_t *launches, double *total_ms);

@@ -165,7 +165,7 @@ class AIMOperator:
 
     def _near_matrices(self, rules, chunk=2000):
         E = self.mesh.nrwg
-        rows, cols, va, vp, vk = [], [], [], [], []
+        rows, cols, va, vp, vk, vd = [], [], [], [], [], []
         self.direct_blocks = []
         for c0 in range(0, len(self.near_t), chunk):
             tl = self.near_t[c0:c0 + chunk]; sl = self.near_s[c0:c0 + chunk]
@@ -175,10 +175,14 @@ class AIMOperator:
             rows.append(np.broadcast_to(rm[:, :, None], (len(tl), 3, 3)).ravel())
             cols.append(np.broadcast_to(rn[:, None, :], (len(tl), 3, 3)).ravel())
             va.append((Ad - Ag).ravel()); vp.append((Pd - Pg).ravel()); vk.append((Kd - Kg).ravel())
+            vd.append((Ad - Pd / (self.k * self.k)).ravel())
         rows = np.concatenate(rows); cols = np.concatenate(cols)
         mk = lambda v: sp.coo_matrix((np.concatenate(v), (rows, cols)), shape=(E, E)).tocsr()
         self.NA, self.NP, self.NK = mk(va), mk(vp), mk(vk)
-        for M in (self.NA, self.NP, self.NK):
+        # direct near-region L (no precorrection): L_NR of the paper's
+        # near-region preconditioner (eq. nest2pc)
+        self.NLd = mk(vd)
+        for M in (self.NA, self.NP, self.NK, self.NLd):
             M.sum_duplicates()
 
     # -- grid stages ---------------------------------------------------------

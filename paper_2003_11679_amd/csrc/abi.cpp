@@ -229,6 +229,19 @@ sie_status sie_matvec(sie_problem *p, int32_t medium, sie_op op, sie_precision p
     });
 }
 
+sie_status sie_nested_precond(sie_problem *p, int32_t precond, sie_precision prec, int32_t nrhs, const void *x_dev,
+                              void *y_dev, void *stream) {
+    return guard([&] {
+        SIE_CHECK(p, SIE_EINVAL, "NULL problem");
+        nested_precond_entry(p, precond, prec, nrhs, x_dev, y_dev, user_stream(stream));
+    });
+}
+
+int32_t sie_nested_precond_clusters(const sie_problem *p, int64_t *owned) {
+    if (!p) return -1;
+    return nested_precond_clusters(p, owned);
+}
+
 sie_status sie_project(sie_problem *p, int32_t medium, sie_precision prec, const void *x_dev, void *grid_dev,
                        void *stream) {
     return guard([&] {

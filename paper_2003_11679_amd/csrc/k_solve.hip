@@ -235,3 +235,205 @@ template void launch_bj_apply<float>(int, int, const int32_t *, const c64 *, con
 template void launch_bj_apply<double>(int, int, const int32_t *, const c128 *, const c128 *, c128 *, hipStream_t);
 
 }  // namespace sie
+
+namespace sie {
+
+// ---------------------------------------------------------------- Schwarz clusters
+// Restricted additive Schwarz form of the near-region preconditioner
+// M_i = -j w eps_i L_i,NR (eq. nest2pc): the RWG functions are grouped into
+// clusters of grid cells; cluster c owns its RWG functions and extends over
+// the cells around it (ext).  M_i restricted to ext x ext is inverted, and the
+// rows of the inverse that belong to the owned functions are kept:
+//     y[own] = (M_ext^-1)[own, :] x[ext].
+// Setup solves M_ext^T Y = E_own (E_own: unit columns at the owned
+// positions) by Gauss-Jordan elimination with partial pivoting in FP64; the
+// augmented matrix [M_ext^T | E_own] (n x (n + n_own), row-major) lives in a
+// global workspace, one workgroup per cluster.
+
+__global__ __launch_bounds__(512) void k_ras_gather(int c0, const int64_t *__restrict__ ext_off,
+                                                    const int32_t *__restrict__ ext,
+                                                    const int32_t *__restrict__ own_off,
+                                                    const int32_t *__restrict__ own_pos,
+                                                    const int64_t *__restrict__ ws_off, int64_t rwg0,
+                                                    const int64_t *__restrict__ row_ptr,
+                                                    const int32_t *__restrict__ cols, const c128 *__restrict__ vals,
+                                                    c128 scale, c128 *__restrict__ ws) {
+    __shared__ int32_t xs[kRasMax];
+    const int c = c0 + blockIdx.x;
+    const int64_t e0 = ext_off[c];
+    const int n = (int)(ext_off[c + 1] - e0);
+    const int o0 = own_off[c];
+    const int no = own_off[c + 1] - o0;
+    const int64_t W = n + no;
+    c128 *B = ws + (ws_off[c] - ws_off[c0]);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) xs[i] = ext[e0 + i];
+    for (int64_t t = threadIdx.x; t < (int64_t)n * W; t += blockDim.x) B[t] = c128();
+    __syncthreads();
+    for (int q = threadIdx.x; q < no; q += blockDim.x) B[(int64_t)own_pos[o0 + q] * W + n + q] = c128(1.0);
+    // row i of M_ext (RWG xs[i]) is column i of B: one wave per row, lanes
+    // over its near-field nonzeros, columns located in the sorted ext list
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int i = wv; i < n; i += nw) {
+        const int64_t r = (int64_t)xs[i] - rwg0;
+        const int64_t lo = row_ptr[r], hi = row_ptr[r + 1];
+        for (int64_t t = lo + lane; t < hi; t += 64) {
+            const int32_t col = cols[t];
+            int a = 0, b = n;
+            while (a < b) {
+                const int mid = (a + b) >> 1;
+                if (xs[mid] < col) a = mid + 1; else b = mid;
+            }
+            if (a < n && xs[a] == col) B[(int64_t)a * W + i] = scale * vals[t];
+        }
+    }
+}
+
+__global__ __launch_bounds__(512) void k_ras_invert(int c0, const int64_t *__restrict__ ext_off,
+                                                    const int32_t *__restrict__ own_off,
+                                                    const int64_t *__restrict__ ws_off,
+                                                    const int64_t *__restrict__ m_off, c128 *__restrict__ ws,
+                                                    c128 *__restrict__ m64, c64 *__restrict__ m32,
+                                                    int *__restrict__ fail) {
+    __shared__ __align__(16) double lds[2 * (3 * kRasMax + 1)];
+    c128 *prow = reinterpret_cast<c128 *>(lds);          // [2 kRasMax] scaled pivot row
+    c128 *fcol = prow + 2 * kRasMax;                     // [kRasMax] column k
+    c128 *pinv = fcol + kRasMax;                         // 1 / pivot
+    __shared__ double rv[8];
+    __shared__ int ri[8];
+    __shared__ int piv;
+    const int c = c0 + blockIdx.x;
+    const int n = (int)(ext_off[c + 1] - ext_off[c]);
+    const int no = own_off[c + 1] - own_off[c];
+    const int W = n + no;
+    c128 *B = ws + (ws_off[c] - ws_off[c0]);
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+    for (int k = 0; k < n; ++k) {
+        // pivot: largest |B[i][k]|, i >= k (lowest index among equals)
+        double best = -1.0;
+        int bi = n;
+        for (int i = k + tid; i < n; i += blockDim.x) {
+            const double v = norm2(B[(int64_t)i * W + k]);
+            if (v > best) { best = v; bi = i; }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ov = __shfl_down(best, off);
+            const int oi = __shfl_down(bi, off);
+            if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+        }
+        if (lane == 0) { rv[wv] = best; ri[wv] = bi; }
+        __syncthreads();
+        if (tid == 0) {
+            double b = rv[0];
+            int p = ri[0];
+            for (int w = 1; w < nw; ++w)
+                if (rv[w] > b || (rv[w] == b && ri[w] < p)) { b = rv[w]; p = ri[w]; }
+            piv = p;
+            if (!(b > 0.0)) *fail = 1;
+        }
+        __syncthreads();
+        const int pr = piv;
+        if (pr != k)
+            for (int j = k + tid; j < W; j += blockDim.x) {
+                const c128 t = B[(int64_t)k * W + j];
+                B[(int64_t)k * W + j] = B[(int64_t)pr * W + j];
+                B[(int64_t)pr * W + j] = t;
+            }
+        __syncthreads();
+        if (tid == 0) {
+            const c128 d = B[(int64_t)k * W + k];
+            *pinv = norm2(d) > 0.0 ? cdiv(c128(1.0), d) : c128();
+        }
+        __syncthreads();
+        const c128 s = *pinv;
+        for (int j = k + 1 + tid; j < W; j += blockDim.x) {
+            const c128 v = s * B[(int64_t)k * W + j];
+            prow[j] = v;
+            B[(int64_t)k * W + j] = v;
+        }
+        for (int i = tid; i < n; i += blockDim.x) fcol[i] = i == k ? c128() : B[(int64_t)i * W + k];
+        __syncthreads();
+        // eliminate column k from every other row: one wave per row segment
+        for (int i = wv; i < n; i += nw) {
+            if (i == k) continue;
+            const c128 f = fcol[i];
+            c128 *row = B + (int64_t)i * W;
+            for (int j = k + 1 + lane; j < W; j += 64) row[j] -= f * prow[j];
+        }
+        __syncthreads();
+    }
+    // Y = right block (n x no); row q of the kept inverse is column q of Y
+    const int64_t mo = m_off[c];
+    for (int64_t t = tid; t < (int64_t)no * n; t += blockDim.x) {
+        const int q = (int)(t / n), j = (int)(t - (int64_t)q * n);
+        const c128 v = B[(int64_t)j * W + n + q];
+        m64[mo + t] = v;
+        m32[mo + t] = c64((float)v.re, (float)v.im);
+    }
+}
+
+void launch_ras_setup(int c0, int cnt, const int64_t *ext_off, const int32_t *ext, const int32_t *own_off,
+                      const int32_t *own_pos, const int64_t *ws_off, const int64_t *m_off, int64_t rwg0,
+                      const int64_t *row_ptr, const int32_t *cols, const c128 *vals, c128 scale, c128 *ws,
+                      c128 *m64, c64 *m32, int *fail, hipStream_t st) {
+    if (cnt <= 0) return;
+    hipLaunchKernelGGL(k_ras_gather, dim3(cnt), dim3(512), 0, st, c0, ext_off, ext, own_off, own_pos, ws_off, rwg0,
+                       row_ptr, cols, vals, scale, ws);
+    SIE_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_ras_invert, dim3(cnt), dim3(512), 0, st, c0, ext_off, own_off, ws_off, m_off, ws, m64, m32,
+                       fail);
+    SIE_HIP(hipGetLastError());
+}
+
+// y[own] = M_own x[ext] for every cluster and every right-hand side
+// (blockIdx.y; vectors ld apart): x[ext] staged in LDS, one wave per owned row.
+template <typename T>
+__global__ __launch_bounds__(256) void k_ras_apply(const int64_t *__restrict__ ext_off, const int32_t *__restrict__ ext,
+                                                   const int32_t *__restrict__ own_off, const int32_t *__restrict__ own,
+                                                   const int64_t *__restrict__ m_off, const cx<T> *__restrict__ M,
+                                                   const cx<T> *__restrict__ x, cx<T> *__restrict__ y, int64_t ld) {
+    __shared__ __align__(16) T lds[2 * kRasMax];
+    cx<T> *xs = reinterpret_cast<cx<T> *>(lds);
+    const int c = blockIdx.x;
+    x += blockIdx.y * ld;
+    y += blockIdx.y * ld;
+    const int64_t e0 = ext_off[c];
+    const int n = (int)(ext_off[c + 1] - e0);
+    const int o0 = own_off[c];
+    const int no = own_off[c + 1] - o0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) xs[i] = x[ext[e0 + i]];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const cx<T> *Mc = M + m_off[c];
+    for (int q = wv; q < no; q += nw) {
+        const cx<T> *row = Mc + (int64_t)q * n;
+        T re = 0, im = 0;
+        for (int j = lane; j < n; j += 64) {
+            const cx<T> a = row[j], b = xs[j];
+            re += a.re * b.re - a.im * b.im;
+            im += a.re * b.im + a.im * b.re;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            re += __shfl_down(re, off);
+            im += __shfl_down(im, off);
+        }
+        if (lane == 0) y[own[o0 + q]] = cx<T>(re, im);
+    }
+}
+
+template <typename T>
+void launch_ras_apply(int nc, const int64_t *ext_off, const int32_t *ext, const int32_t *own_off, const int32_t *own,
+                      const int64_t *m_off, const cx<T> *M, const cx<T> *x, cx<T> *y, int64_t ld, int nrhs,
+                      hipStream_t st) {
+    if (nc <= 0 || nrhs <= 0) return;
+    hipLaunchKernelGGL(k_ras_apply<T>, dim3(nc, nrhs), dim3(256), 0, st, ext_off, ext, own_off, own, m_off, M, x, y,
+                       ld);
+    SIE_HIP(hipGetLastError());
+}
+
+template void launch_ras_apply<float>(int, const int64_t *, const int32_t *, const int32_t *, const int32_t *,
+                                      const int64_t *, const c64 *, const c64 *, c64 *, int64_t, int, hipStream_t);
+template void launch_ras_apply<double>(int, const int64_t *, const int32_t *, const int32_t *, const int32_t *,
+                                       const int64_t *, const c128 *, const c128 *, c128 *, int64_t, int,
+                                       hipStream_t);
+
+}  // namespace sie

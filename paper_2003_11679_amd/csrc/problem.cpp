@@ -415,10 +415,10 @@ void StageTimer::begin(int, hipStream_t st, hipEvent_t &a) {
     a = get();
     SIE_HIP(hipEventRecord(a, st));
 }
-void StageTimer::end(int stage, hipStream_t st, hipEvent_t a) {
+void StageTimer::end(int stage, hipStream_t st, hipEvent_t a, int extra) {
     hipEvent_t b = get();
     SIE_HIP(hipEventRecord(b, st));
-    pending.push_back({stage, a, b});
+    pending.push_back({stage, extra, a, b});
     if (pending.size() >= 4096) flush();
 }
 void StageTimer::flush() {
@@ -428,6 +428,10 @@ void StageTimer::flush() {
         SIE_HIP(hipEventElapsedTime(&ms, r.a, r.b));
         total_ms[r.stage] += ms;
         count[r.stage] += 1;
+        if (r.extra >= 0) {
+            total_ms[r.extra] += ms;
+            count[r.extra] += 1;
+        }
         pool.push_back(r.a);
         pool.push_back(r.b);
     }
@@ -473,7 +477,7 @@ void matvec(sie_problem *p, Medium &md, sie_op op, int nrhs, const cx<T> *x, cx<
         if (tm.on) { tm.end(ST_INTERP, st, e1); tm.begin(ST_SPMV, st, e1); }
         launch_spmm_far<T>(g, E, nrhs, g.d_rwgloc.p, coef_of<T>(g), wb.tripot.p, kscal, near_of<T>(md, op), x,
                            wb.xt.p, y, st);
-        if (tm.on) { tm.end(ST_SPMV, st, e1); tm.end(ST_PRODUCT, st, e0); }
+        if (tm.on) { tm.end(ST_SPMV, st, e1, sizeof(T) == 8 ? ST_SPMV64 : -1); tm.end(ST_PRODUCT, st, e0); }
         return;
     }
     for (int r = 0; r < nrhs; ++r) {
@@ -487,7 +491,7 @@ void matvec(sie_problem *p, Medium &md, sie_op op, int nrhs, const cx<T> *x, cx<
         if (tm.on) { tm.end(ST_INTERP, st, e1); tm.begin(ST_SPMV, st, e1); }
         launch_spmv_far<T>(g, E, g.d_rwgloc.p, coef_of<T>(g), w.tripot.p, kscal, near_of<T>(md, op), x + r * E,
                            y + r * E, true, st);
-        if (tm.on) { tm.end(ST_SPMV, st, e1); tm.end(ST_PRODUCT, st, e0); }
+        if (tm.on) { tm.end(ST_SPMV, st, e1, sizeof(T) == 8 ? ST_SPMV64 : -1); tm.end(ST_PRODUCT, st, e0); }
     }
 }
 

@@ -24,17 +24,19 @@ struct GridReq {
 struct SolveState;     // solver.cpp
 
 // HIP-event timers of the operator stages (enabled per problem).
-enum Stage { ST_PROJECT = 0, ST_FFT = 1, ST_INTERP = 2, ST_SPMV = 3, ST_PRODUCT = 4, NSTAGE = 5 };
+// ST_SPMV64 counts the FP64 near-field products a second time (they are in
+// ST_SPMV as well).
+enum Stage { ST_PROJECT = 0, ST_FFT = 1, ST_INTERP = 2, ST_SPMV = 3, ST_PRODUCT = 4, ST_SPMV64 = 5, NSTAGE = 6 };
 struct StageTimer {
     bool on = false;
-    struct Rec { int stage; hipEvent_t a, b; };
+    struct Rec { int stage, extra; hipEvent_t a, b; };
     std::vector<Rec> pending;
     std::vector<hipEvent_t> pool;
-    double total_ms[NSTAGE] = {0, 0, 0, 0, 0};
-    int64_t count[NSTAGE] = {0, 0, 0, 0, 0};
+    double total_ms[NSTAGE] = {0, 0, 0, 0, 0, 0};
+    int64_t count[NSTAGE] = {0, 0, 0, 0, 0, 0};
     hipEvent_t get();
     void begin(int stage, hipStream_t st, hipEvent_t &a);
-    void end(int stage, hipStream_t st, hipEvent_t a);
+    void end(int stage, hipStream_t st, hipEvent_t a, int extra = -1);
     void flush();
     void reset();
     ~StageTimer();
@@ -87,6 +89,9 @@ void stage_interpolate(sie_problem *p, Medium &md, const cx<T> *grid, cx<T> *y, 
 void solver_destroy(SolveState *s);
 void planewaves_entry(sie_problem *p, int32_t nrhs, const double *khat, const sie_c128 *e0);
 void solve_entry(sie_problem *p, sie_precision prec, const sie_solver_opts *opts, sie_report *rep);
+void nested_precond_entry(sie_problem *p, int precond, sie_precision prec, int nrhs, const void *x, void *y,
+                          hipStream_t st);
+int nested_precond_clusters(const sie_problem *p, int64_t *owned);
 void currents_entry(const sie_problem *p, int32_t rhs, sie_c128 *u, sie_c128 *v);
 // Message returned by sie_last_error() on this thread.
 void set_last_error(const std::string &m);

@@ -11,4 +11,15 @@ void launch_bj_setup(int nb, int B, const int32_t *perm, int64_t rwg0, const int
                      const c128 *vals, c128 scale, c128 *inv64, c64 *inv32, hipStream_t st);
 template <typename T>
 void launch_bj_apply(int nb, int B, const int32_t *perm, const cx<T> *inv, const cx<T> *x, cx<T> *y, hipStream_t st);
+// Schwarz clusters of the near-region preconditioner: largest extended
+// cluster (RWG functions) the kernels take.
+constexpr int kRasMax = 2048;
+void launch_ras_setup(int c0, int cnt, const int64_t *ext_off, const int32_t *ext, const int32_t *own_off,
+                      const int32_t *own_pos, const int64_t *ws_off, const int64_t *m_off, int64_t rwg0,
+                      const int64_t *row_ptr, const int32_t *cols, const c128 *vals, c128 scale, c128 *ws,
+                      c128 *m64, c64 *m32, int *fail, hipStream_t st);
+template <typename T>
+void launch_ras_apply(int nc, const int64_t *ext_off, const int32_t *ext, const int32_t *own_off, const int32_t *own,
+                      const int64_t *m_off, const cx<T> *M, const cx<T> *x, cx<T> *y, int64_t ld, int nrhs,
+                      hipStream_t st);
 }  // namespace sie

@@ -33,7 +33,9 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <numeric>
+#include <unordered_map>
 
 #include "problem.h"
 #include "solve_kernels.h"
@@ -286,6 +288,153 @@ template <typename T> static const cx<T> *bj_inv(const BlockJacobi &bj);
 template <> const c128 *bj_inv<double>(const BlockJacobi &bj) { return bj.inv64.p; }
 template <> const c64 *bj_inv<float>(const BlockJacobi &bj) { return bj.inv32.p; }
 
+// Restricted additive Schwarz form of the near-region preconditioner
+// M_i = -j w eps_i L_i,NR (eq. nest2pc): clusters of C^3 grid cells own their
+// RWG functions (cell of the stencil centre of T+) and extend O cells beyond
+// on every side; each cluster keeps the owned rows of the inverse of M_i
+// restricted to its extended set.  The overlap spans about three mesh edges
+// (O = max(1, round(3 l / h)) for mean RWG edge l and grid spacing h) and
+// C = 2 O; clusters shrink when an extended one would exceed kRasMax.
+struct Schwarz {
+    int nc = 0;
+    bool covers_all = false;       // every RWG row is owned by some cluster
+    int64_t owned = 0;
+    DBuf<int64_t> ext_off, m_off;  // [nc + 1]
+    DBuf<int32_t> ext, own_off, own;
+    DBuf<c128> m64;
+    DBuf<c64> m32;
+};
+
+// Setup workspace (augmented cluster matrices in FP64) per launch.
+constexpr double kSchwarzWorkspace = 2e9;
+
+// The near-region operator carries the interior medium's interaction when
+// the field decays within the near region: five skin depths fit within
+// R grid spacings.  For low-loss media the near-region inverse is a poor
+// approximation of the operator's inverse and the nested solve runs
+// unpreconditioned.
+static bool near_region_dominates(const Medium &md) {
+    const double a = std::fabs(md.k.im);
+    return a > 0.0 && 5.0 / a <= md.grid->near_radius * md.grid->h;
+}
+
+struct ClusterLists {
+    std::vector<int64_t> ext_off{0}, m_off{0}, ws_off{0};
+    std::vector<int32_t> ext, own_off{0}, own, own_pos;
+};
+
+// Clusters of one medium over its RWG rows [r0, r1); false if an extended
+// cluster would exceed kRasMax functions at this cluster size.
+static bool cluster_medium(sie_problem *p, const Medium &md, int64_t r0, int64_t r1, int C, int O,
+                           ClusterLists &L) {
+    const Grid &g = *md.grid;
+    auto cell = [&](int64_t r, int d) { return g.centre[3 * (size_t)g.glob2loc[p->mesh.tpm[2 * r]] + d]; };
+    auto lin = [&](int64_t x, int64_t y, int64_t z) { return (z * g.n[1] + y) * g.n[0] + x; };
+    std::unordered_map<int64_t, std::vector<int32_t>> bucket;
+    std::map<int64_t, std::vector<int32_t>> clusters;   // ordered: deterministic numbering
+    for (int64_t r = r0; r < r1; ++r) {
+        const int x = cell(r, 0), y = cell(r, 1), z = cell(r, 2);
+        bucket[lin(x, y, z)].push_back((int32_t)r);
+        clusters[lin(x / C, y / C, z / C)].push_back((int32_t)r);
+    }
+    ClusterLists M = L;
+    for (const auto &kv : clusters) {
+        const std::vector<int32_t> &ow = kv.second;
+        const int bx = cell(ow[0], 0) / C * C, by = cell(ow[0], 1) / C * C, bz = cell(ow[0], 2) / C * C;
+        std::vector<int32_t> ex;
+        for (int z = bz - O; z <= bz + C - 1 + O; ++z)
+            for (int y = by - O; y <= by + C - 1 + O; ++y)
+                for (int x = bx - O; x <= bx + C - 1 + O; ++x) {
+                    if (x < 0 || y < 0 || z < 0 || x >= g.n[0] || y >= g.n[1] || z >= g.n[2]) continue;
+                    auto it = bucket.find(lin(x, y, z));
+                    if (it != bucket.end()) ex.insert(ex.end(), it->second.begin(), it->second.end());
+                }
+        std::sort(ex.begin(), ex.end());
+        if (ex.size() > (size_t)kRasMax) return false;
+        const int64_t n = (int64_t)ex.size(), no = (int64_t)ow.size();
+        for (int32_t r : ow) {
+            M.own.push_back(r);
+            M.own_pos.push_back((int32_t)(std::lower_bound(ex.begin(), ex.end(), r) - ex.begin()));
+        }
+        M.ext.insert(M.ext.end(), ex.begin(), ex.end());
+        M.ext_off.push_back((int64_t)M.ext.size());
+        M.own_off.push_back((int32_t)M.own.size());
+        M.m_off.push_back(M.m_off.back() + no * n);
+        M.ws_off.push_back(M.ws_off.back() + n * (n + no));
+    }
+    L = std::move(M);
+    return true;
+}
+
+static void schwarz_build(sie_problem *p, Schwarz &sw, const std::vector<Medium *> &media,
+                          const std::vector<std::pair<int64_t, int64_t>> &ranges, const std::vector<c128> &scales) {
+    ClusterLists L;
+    std::vector<int> first, used;
+    int64_t total = 0;
+    for (size_t i = 0; i < media.size(); ++i) {
+        total += ranges[i].second - ranges[i].first;
+        first.push_back((int)L.own_off.size() - 1);
+        used.push_back(0);
+        if (!near_region_dominates(*media[i])) continue;
+        const int64_t r0 = ranges[i].first, r1 = ranges[i].second;
+        double l = 0.0;
+        for (int64_t r = r0; r < r1; ++r) l += p->mesh.len[r];
+        l /= (double)std::max<int64_t>(r1 - r0, 1);
+        const int O0 = std::max(1, (int)std::lround(3.0 * l / media[i]->grid->h));
+        for (int O = O0; O >= 1 && !used.back(); --O)
+            for (int C = 2 * O; C >= 1 && !used.back(); --C)
+                if (cluster_medium(p, *media[i], r0, r1, C, O, L)) used.back() = 1;
+    }
+    first.push_back((int)L.own_off.size() - 1);
+    sw.nc = (int)L.own_off.size() - 1;
+    sw.owned = (int64_t)L.own.size();
+    sw.covers_all = sw.owned == total;
+    if (sw.nc == 0) return;
+    sw.ext_off.upload(L.ext_off);
+    sw.ext.upload(L.ext);
+    sw.own_off.upload(L.own_off);
+    sw.own.upload(L.own);
+    sw.m_off.upload(L.m_off);
+    sw.m64.alloc((size_t)L.m_off.back());
+    sw.m32.alloc((size_t)L.m_off.back());
+    DBuf<int32_t> own_pos;
+    own_pos.upload(L.own_pos);
+    DBuf<int64_t> ws_off;
+    ws_off.upload(L.ws_off);
+    // batches of clusters within the workspace budget (at least one cluster)
+    std::vector<std::pair<int, int>> batches;
+    size_t ws_max = 0;
+    for (size_t i = 0; i < media.size(); ++i) {
+        for (int a = first[i]; a < first[i + 1];) {
+            int b = a + 1;
+            while (b < first[i + 1] && (double)(L.ws_off[b + 1] - L.ws_off[a]) * sizeof(c128) <= kSchwarzWorkspace) ++b;
+            batches.push_back({a, b});
+            ws_max = std::max(ws_max, (size_t)(L.ws_off[b] - L.ws_off[a]));
+            a = b;
+        }
+    }
+    DBuf<c128> ws(ws_max);
+    DBuf<int> fail(1);
+    SIE_HIP(hipMemsetAsync(fail.p, 0, sizeof(int), 0));
+    for (size_t i = 0; i < media.size(); ++i) {
+        const Grid &g = *media[i]->grid;
+        for (const auto &bt : batches) {
+            if (bt.first < first[i] || bt.first >= first[i + 1]) continue;
+            launch_ras_setup(bt.first, bt.second - bt.first, sw.ext_off.p, sw.ext.p, sw.own_off.p, own_pos.p,
+                             ws_off.p, sw.m_off.p, g.rwg0, g.d_row_ptr.p, g.d_cols.p, media[i]->d_nLd64.p,
+                             scales[i], ws.p, sw.m64.p, sw.m32.p, fail.p, 0);
+        }
+    }
+    int bad = 0;
+    SIE_HIP(hipMemcpyAsync(&bad, fail.p, sizeof(int), hipMemcpyDeviceToHost, 0));
+    SIE_HIP(hipStreamSynchronize(0));
+    SIE_CHECK(!bad, SIE_EINVAL, "near-region preconditioner: singular cluster matrix");
+}
+
+template <typename T> static const cx<T> *ras_m(const Schwarz &w);
+template <> const c128 *ras_m<double>(const Schwarz &w) { return w.m64.p; }
+template <> const c64 *ras_m<float>(const Schwarz &w) { return w.m32.p; }
+
 // ---------------------------------------------------------------- solve state
 struct SolveState {
     int nrhs = 0;
@@ -294,6 +443,8 @@ struct SolveState {
     bool solved = false;
     BlockJacobi pin, pout;         // inner (interior L-hat) and outer (exterior) preconditioners
     bool pre_built = false;
+    Schwarz sin;                   // near-region Schwarz preconditioner of the nested solves
+    bool sin_built = false;
     Gmres<double> go64, gi64;
     Gmres<float> go32, gi32;
     DBuf<c128> t64[6];
@@ -383,7 +534,16 @@ struct Ops {
         }
         for (int k = 0; k < nb; ++k) launch_bj_apply<T>(b.nb, b.B, b.perm.p, bj_inv<T>(b), x + k * E, y + k * E, st);
     }
-    void prec_inner(const cx<T> *x, cx<T> *y) { bj(use_bj_in, s.pin, x, y); }
+    bool use_ras_in = false;
+    void prec_inner(const cx<T> *x, cx<T> *y) {
+        if (!use_ras_in) {
+            bj(use_bj_in, s.pin, x, y);
+            return;
+        }
+        const Schwarz &w = s.sin;
+        if (!w.covers_all) SIE_HIP(hipMemcpyAsync(y, x, NE * sizeof(cx<T>), hipMemcpyDeviceToDevice, st));
+        launch_ras_apply<T>(w.nc, w.ext_off.p, w.ext.p, w.own_off.p, w.own.p, w.m_off.p, ras_m<T>(w), x, y, E, nb, st);
+    }
     void prec_outer(const cx<T> *x, cx<T> *y) { bj(use_bj_out, s.pout, x, y); }
     // Mixed precision: an FP64 operator set may delegate the interior work
     // (K_i products and the nested L_i solves) to an FP32 one.
@@ -453,8 +613,9 @@ static std::vector<double> block_residual(Ops<double> &o, const c128 *e, const c
     return out;
 }
 
-static void build_preconditioners(sie_problem *p, SolveState &s) {
-    if (s.pre_built) return;
+// precond bits: 1 block-Jacobi in the nested solves, 2 block-Jacobi in the
+// outer solve, 4 near-region Schwarz clusters in the nested solves.
+static void build_preconditioners(sie_problem *p, SolveState &s, int precond) {
     std::vector<Medium *> mi;
     std::vector<std::pair<int64_t, int64_t>> ri;
     std::vector<c128> si;
@@ -463,9 +624,15 @@ static void build_preconditioners(sie_problem *p, SolveState &s) {
         ri.push_back({p->mesh.obj_rwg0[i], p->mesh.obj_rwg0[i + 1]});
         si.push_back(c128(0.0, -p->w) * p->ints[i].eps);
     }
-    bj_build(p, s.pin, mi, ri, si);
-    bj_build(p, s.pout, {&p->ext}, {{0, p->mesh.nrwg}}, {c128(0.0, p->w) * p->ext.mu});
-    s.pre_built = true;
+    if ((precond & 3) && !s.pre_built) {
+        bj_build(p, s.pin, mi, ri, si);
+        bj_build(p, s.pout, {&p->ext}, {{0, p->mesh.nrwg}}, {c128(0.0, p->w) * p->ext.mu});
+        s.pre_built = true;
+    }
+    if ((precond & 4) && !s.sin_built) {
+        schwarz_build(p, s.sin, mi, ri, si);
+        s.sin_built = true;
+    }
 }
 
 // Krylov storage of one batch of right-hand sides is kept within this many
@@ -476,7 +643,7 @@ static void solve_all(sie_problem *p, sie_precision prec, const sie_solver_opts 
     SolveState &s = *p->solve;
     const int64_t E = s.E;
     hipStream_t st = 0;
-    if (o.precond != 0) build_preconditioners(p, s);
+    if (o.precond != 0) build_preconditioners(p, s, o.precond);
     s.matvecs = s.inner_iters = s.inner_max = 0;
     int outer_total = 0, sweeps_total = 0;
     double worst = 0.0;
@@ -492,6 +659,7 @@ static void solve_all(sie_problem *p, sie_precision prec, const sie_solver_opts 
         Ops<double> o64(p, s, st, o.inner_tol, o.inner_max_iter, o.restart, cnt);
         o64.use_bj_in = (o.precond & 1) != 0;
         o64.use_bj_out = (o.precond & 2) != 0;
+        o64.use_ras_in = (o.precond & 4) != 0 && s.sin.nc > 0;
         c128 *e = s.e.p + r0 * E, *u = s.u.p + r0 * E, *v = s.v.p + r0 * E;
         const int64_t NE = (int64_t)cnt * E;
         // Refinement sweeps: residual of the block equations in FP64, correction
@@ -504,6 +672,7 @@ static void solve_all(sie_problem *p, sie_precision prec, const sie_solver_opts 
             o32.reset(new Ops<float>(p, s, st, std::max(o.inner_tol, 1e-5), o.inner_max_iter, o.restart, cnt));
             o32->use_bj_in = o64.use_bj_in;
             o32->use_bj_out = o64.use_bj_out;
+            o32->use_ras_in = o64.use_ras_in;
             o64.lo = o32.get();
         }
         SIE_HIP(hipMemsetAsync(u, 0, NE * sizeof(c128), st));
@@ -580,6 +749,45 @@ static void solve_all(sie_problem *p, sie_precision prec, const sie_solver_opts 
 }  // namespace sie
 
 namespace sie {
+template <typename T>
+static void nested_precond_apply(sie_problem *p, SolveState &s, int precond, int nrhs, const cx<T> *x, cx<T> *y,
+                                 hipStream_t st) {
+    const int64_t E = p->mesh.nrwg;
+    if (precond == 4) {
+        const Schwarz &w = s.sin;
+        if (!w.covers_all)
+            SIE_HIP(hipMemcpyAsync(y, x, (size_t)nrhs * E * sizeof(cx<T>), hipMemcpyDeviceToDevice, st));
+        launch_ras_apply<T>(w.nc, w.ext_off.p, w.ext.p, w.own_off.p, w.own.p, w.m_off.p, ras_m<T>(w), x, y, E, nrhs,
+                            st);
+    } else {
+        for (int k = 0; k < nrhs; ++k)
+            launch_bj_apply<T>(s.pin.nb, s.pin.B, s.pin.perm.p, bj_inv<T>(s.pin), x + k * E, y + k * E, st);
+    }
+}
+
+void nested_precond_entry(sie_problem *p, int precond, sie_precision prec, int nrhs, const void *x, void *y,
+                          hipStream_t st) {
+    SIE_CHECK(p && p->is_setup, SIE_ESTATE, "problem not set up");
+    SIE_CHECK(precond == 1 || precond == 4, SIE_EINVAL,
+              "nested preconditioner must be 1 (block-Jacobi) or 4 (Schwarz clusters)");
+    SIE_CHECK(x && y && nrhs >= 1, SIE_EINVAL, "bad vectors");
+    SIE_CHECK(x != y, SIE_EINVAL, "x and y must not alias");
+    SIE_CHECK(prec == SIE_FP64 || prec == SIE_FP32, SIE_EINVAL, "unknown precision");
+    if (!p->solve) p->solve = new SolveState;
+    SolveState &s = *p->solve;
+    build_preconditioners(p, s, precond);
+    if (prec == SIE_FP64)
+        nested_precond_apply<double>(p, s, precond, nrhs, (const c128 *)x, (c128 *)y, st);
+    else
+        nested_precond_apply<float>(p, s, precond, nrhs, (const c64 *)x, (c64 *)y, st);
+}
+
+int nested_precond_clusters(const sie_problem *p, int64_t *owned) {
+    if (!p->solve || !p->solve->sin_built) return -1;
+    if (owned) *owned = p->solve->sin.owned;
+    return p->solve->sin.nc;
+}
+
 void planewaves_entry(sie_problem *p, int32_t nrhs, const double *khat, const sie_c128 *e0) {
     SIE_CHECK(p && p->is_setup, SIE_ESTATE, "problem not set up");
     SIE_CHECK(nrhs >= 1 && khat && e0, SIE_EINVAL, "bad plane waves");
@@ -630,7 +838,8 @@ void solve_entry(sie_problem *p, sie_precision prec, const sie_solver_opts *opts
         if (opts->max_refine > 0) o.max_refine = opts->max_refine;
         o.precond = opts->precond;
     }
-    SIE_CHECK(o.precond >= 0 && o.precond <= 3, SIE_EINVAL, "unknown preconditioner");
+    SIE_CHECK(o.precond >= 0 && o.precond <= 7, SIE_EINVAL, "unknown preconditioner");
+    SIE_CHECK((o.precond & 5) != 5, SIE_EINVAL, "nested block-Jacobi (1) and nested Schwarz clusters (4) exclude each other");
     SIE_CHECK(o.restart <= 1000, SIE_EINVAL, "restart above 1000");
     solve_all(p, prec, o, rep);
 }

@@ -96,6 +96,8 @@ SIGNATURES = [
     ("sie_project", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int, _VP, _VP, _VP]),
     ("sie_convolve", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int, ctypes.c_int, ctypes.c_int32, _VP, _VP, _VP]),
     ("sie_interpolate", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int, _VP, _VP, _VP]),
+    ("sie_nested_precond", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int, ctypes.c_int32, _VP, _VP, _VP]),
+    ("sie_nested_precond_clusters", ctypes.c_int32, [_VP, _I64P]),
     ("sie_set_timing", ctypes.c_int, [_VP, ctypes.c_int32]),
     ("sie_get_stage_time", ctypes.c_int, [_VP, ctypes.c_int32, _I64P, _DP]),
     ("sie_set_planewaves", ctypes.c_int, [_VP, ctypes.c_int32, _DP, _CP]),
@@ -265,6 +267,26 @@ class Problem:
                                 _stream(stream)))
         return y
 
+    def nested_precond(self, precond, x, y=None, stream=None):
+        """y = nested-solve preconditioner (1 block-Jacobi, 4 Schwarz
+        clusters) applied to x of shape [E] or [nrhs, E] on the device."""
+        import torch
+        prec = self._prec_of(x)
+        x = x.contiguous()
+        if y is None:
+            y = torch.empty_like(x)
+        nrhs = 1 if x.dim() == 1 else x.shape[0]
+        _check(lib().sie_nested_precond(self.h, precond, prec, nrhs, _VP(x.data_ptr()), _VP(y.data_ptr()),
+                                        _stream(stream)))
+        return y
+
+    def nested_precond_clusters(self):
+        """(clusters, owned RWG rows) of the built Schwarz preconditioner,
+        (-1, 0) before it is built."""
+        owned = ctypes.c_int64(0)
+        n = lib().sie_nested_precond_clusters(self.h, ctypes.byref(owned))
+        return int(n), int(owned.value)
+
     def project(self, medium, x, stream=None):
         import torch
         g = self.grid(medium)
@@ -293,7 +315,7 @@ class Problem:
                                      _VP(y.data_ptr()), _stream(stream)))
         return y
 
-    STAGES = ("project", "fft", "interp", "spmv", "product")
+    STAGES = ("project", "fft", "interp", "spmv", "product", "spmv64")
 
     def set_timing(self, on=True):
         _check(lib().sie_set_timing(self.h, 1 if on else 0))

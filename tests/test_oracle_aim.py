@@ -111,3 +111,34 @@ def test_independent_of_grid_G0():
     y0 = AIMOperator(m, g, K_TEST, near_radius=2).matvec(x, "L")
     y1 = AIMOperator(m, g, K_TEST, near_radius=2, g0=123.0 - 45.0j).matvec(x, "L")
     assert np.abs(y0 - y1).max() < 1e-11 * np.abs(y0).max()
+
+
+def test_direct_near_region_equals_dense_when_every_pair_is_near(sphere2):
+    """The direct near-region L (source of the nested preconditioner,
+    eq. nest2pc) is the dense L when the near region covers the object."""
+    m, dense = sphere2
+    op = AIMOperator(m, Grid.enclosing(m.xyz, 6), K_TEST, near_radius=10)
+    N = op.NLd.toarray()
+    assert np.abs(N - dense["L"]).max() < 1e-12 * np.abs(dense["L"]).max()
+
+
+def test_direct_near_region_pattern_and_symmetry(sphere2):
+    """Entries only where a triangle pair of the two RWG functions is near;
+    symmetric up to quadrature (reciprocity); equal to the dense L on pairs
+    whose every triangle pair is near."""
+    m, dense = sphere2
+    R = 2
+    op = AIMOperator(m, Grid.enclosing(m.xyz, 12), K_TEST, near_radius=R)
+    N = op.NLd.toarray()
+    c = op.centres
+    d = np.abs(c[:, None, :] - c[None, :, :]).max(axis=2)
+    tp, tm = m.tp, m.tm
+    any_near = np.zeros_like(N, bool); all_near = np.ones_like(N, bool)
+    for a in (tp, tm):
+        for b in (tp, tm):
+            near = d[a][:, b] <= R
+            any_near |= near; all_near &= near
+    assert not np.any(N[~any_near])
+    assert np.abs(N - N.T).max() < 1e-6 * np.abs(N).max()
+    L = dense["L"]
+    assert np.abs(N[all_near] - L[all_near]).max() < 1e-12 * np.abs(L).max()
