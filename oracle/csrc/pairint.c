@@ -14,6 +14,17 @@
  * the caller's quadrature rule.  Using grad G x (r' - p) = grad G x (r - p)
  * (grad_r G is parallel to r - r'), the K inner integral needs only
  * int_s grad_r G dS'.
+ *
+ * Strongly lossy media (|Im k| l > 2 on the source triangle's longest edge l,
+ * |Im k| >= 0.38 |k|) make G decay within a small fraction of a triangle; the
+ * extracted static part and the quadrature of the remainder then cancel to a
+ * result far below either, and the remainder rule fails.  Touching and close
+ * pairs there take polar_pot: polar coordinates around the projection of the
+ * observation point, the radial integral of G in closed form, the radial
+ * integrals of G r' and of the gradient remainder by Gauss-Legendre on
+ * intervals graded in units of 1/|k| (cut at 64/|k|, with the closed-form
+ * static tail of the gradient beyond), and composite Gauss-Legendre in the
+ * angle, broken where the distance to the edge crosses a radial breakpoint.
  */
 #include <math.h>
 #include <complex.h>
@@ -81,6 +92,139 @@ static void static_pot(const double v[3][3], const double n[3], const double r[3
     for (int c = 0; c < 3; ++c) gI[c] -= sg * sb * n[c];
 }
 
+/* Radial breakpoints of the strong-loss scheme in units of 1/|k|; the last
+ * one is the cut. */
+static const double POLAR_B[] = {0.25, 0.5, 1.0, 2.0, 3.0, 4.0, 6.0, 8.0, 12.0, 16.0, 24.0, 32.0, 48.0, 64.0};
+#define POLAR_NB 14
+#define POLAR_NG 8
+
+/* Gauss-Legendre on [a, b] of the radial integrands at height d:
+ * fV = exp(-jkR) rp^2 / (4 pi R)      (vector potential, r' - rho0 part)
+ * fT = [1 - (1 + jkR) exp(-jkR)] rp^2 / (4 pi R^3)   (gradient remainder). */
+static void radial_gl(cplx k, double d, double a, double b, const double *gx, const double *gw,
+                      cplx *IV, cplx *IT) {
+    const double h = 0.5 * (b - a), c = 0.5 * (b + a);
+    for (int g = 0; g < POLAR_NG; ++g) {
+        const double rp = c + h * gx[g];
+        const double R = sqrt(rp * rp + d * d);
+        const cplx e = cexp(-JJ * k * R);
+        const double w = h * gw[g] * rp * rp / (4.0 * PI_ * R);
+        *IV += w * e;
+        *IT += w * (1.0 - (1.0 + JJ * k * R) * e) / (R * R);
+    }
+}
+
+/* S = int G, V = int G r', Gv = int grad_r G over triangle v at r, for
+ * strongly lossy media (see the header).  With rho0 the projection of r on
+ * the plane, d the height, and the triangle split into the signed triangles
+ * (rho0, edge) swept by the angle theta (direction u(theta), edge distance
+ * rho(theta), Re = sqrt(rho^2 + d^2)):
+ *   S   = sum int dtheta [exp(-jk|d|) - exp(-jk Re)] / (4 pi jk)
+ *   V   = rho0 S + sum int dtheta u IV(rho),  IV = int_0^rho G rp^2 drp
+ *   Gv.n = sum int dtheta [d exp(-jk Re)/Re - sign(d) exp(-jk|d|)] / (4 pi)
+ *   Gv_t = -sum int dtheta u J(rho),  J = int_0^rho g rp^2 drp, g R^3 = -(1 + jkR) exp(-jkR)/(4 pi)
+ * J splits into -(ln(rho + Re) - rho/Re)/(4 pi) plus the integral IT of the
+ * remainder g + 1/(4 pi R^3); the theta-independent rest (ln|d|/(4 pi),
+ * divergent in the plane) drops out since sum int u dtheta = 0 for points
+ * off the triangle's boundary.  Beyond the cut IV and J are constant and
+ * their angular integrals are closed-form. */
+static void polar_pot(const double v[3][3], const double n[3], const double r[3], cplx k,
+                      const double *gx, const double *gw, cplx *S, cplx V[3], cplx Gv[3]) {
+    const double inv4pi = 1.0 / (4.0 * PI_);
+    double tmp[3];
+    sub3(r, v[0], tmp);
+    double d = dot3(tmp, n);
+    double e01[3]; sub3(v[1], v[0], e01);
+    if (fabs(d) <= 1e-10 * norm3(e01)) d = 0.0;
+    const double ad = fabs(d), sgd = (d > 0.0) ? 1.0 : ((d < 0.0) ? -1.0 : 0.0);
+    const double rho0[3] = { r[0] - d * n[0], r[1] - d * n[1], r[2] - d * n[2] };
+    const double u = 1.0 / cabs(k);
+    double b[POLAR_NB];
+    cplx CV[POLAR_NB], CT[POLAR_NB];
+    {
+        cplx iv = 0.0, it = 0.0;
+        double lo = 0.0;
+        for (int j = 0; j < POLAR_NB; ++j) {
+            b[j] = POLAR_B[j] * u;
+            radial_gl(k, d, lo, b[j], gx, gw, &iv, &it);
+            CV[j] = iv; CT[j] = it;
+            lo = b[j];
+        }
+    }
+    const double rc = b[POLAR_NB - 1], Rc = sqrt(rc * rc + d * d);
+    const cplx Vc = CV[POLAR_NB - 1];
+    const cplx Jc = CT[POLAR_NB - 1] - inv4pi * (log(rc + Rc) - rc / Rc);
+    const cplx ekd = cexp(-JJ * k * ad);
+    cplx sumS = 0.0, sumN = 0.0, UV[3] = {0.0, 0.0, 0.0}, UJ[3] = {0.0, 0.0, 0.0};
+    double tot = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        const double *a = v[i], *bb = v[(i + 1) % 3];
+        double le[3], lh[3], mh[3], am[3], bm[3];
+        sub3(bb, a, le);
+        const double ll = norm3(le);
+        lh[0] = le[0] / ll; lh[1] = le[1] / ll; lh[2] = le[2] / ll;
+        cross3(lh, n, mh);
+        sub3(a, rho0, am); sub3(bb, rho0, bm);
+        const double t = dot3(am, mh), sa = dot3(am, lh), sb = dot3(bm, lh);
+        if (fabs(t) <= 1e-12 * ll) continue;
+        const double at = fabs(t), sg = t > 0.0 ? 1.0 : -1.0;
+        const double tha = atan(sa / at), thb = atan(sb / at);
+        tot += sg * (thb - tha);
+        double bp[2 * POLAR_NB + 2];
+        int nbp = 0;
+        bp[nbp++] = tha;
+        for (int j = 0; j < POLAR_NB; ++j) {
+            if (b[j] <= at) continue;
+            const double ph = acos(at / b[j]);
+            if (-ph > tha && -ph < thb) bp[nbp++] = -ph;
+            if (ph > tha && ph < thb) bp[nbp++] = ph;
+        }
+        bp[nbp++] = thb;
+        for (int x = 1; x < nbp; ++x)          /* insertion sort */
+            for (int y = x; y > 0 && bp[y - 1] > bp[y]; --y) { double q = bp[y]; bp[y] = bp[y - 1]; bp[y - 1] = q; }
+        for (int q = 0; q + 1 < nbp; ++q) {
+            const double t1 = bp[q], t2 = bp[q + 1];
+            const double h = 0.5 * (t2 - t1), c = 0.5 * (t2 + t1);
+            if (h <= 0.0) continue;
+            if (at / cos(c) >= rc) {
+                /* beyond the cut: sg int u dtheta times the constants */
+                for (int m = 0; m < 3; ++m) {
+                    const double U = sg * (sg * (sin(t2) - sin(t1)) * mh[m] - (cos(t2) - cos(t1)) * lh[m]);
+                    UV[m] += U * Vc;
+                    UJ[m] += U * Jc;
+                }
+                continue;
+            }
+            for (int g = 0; g < POLAR_NG; ++g) {
+                const double th = c + h * gx[g];
+                const double wt = sg * h * gw[g];
+                const double ct = cos(th), st = sin(th);
+                const double rho = at / ct, Re = sqrt(rho * rho + d * d);
+                double uh[3];
+                for (int m = 0; m < 3; ++m) uh[m] = sg * ct * mh[m] + st * lh[m];
+                int j = -1;
+                while (j + 1 < POLAR_NB && b[j + 1] <= rho) ++j;
+                cplx IV = j >= 0 ? CV[j] : 0.0, IT = j >= 0 ? CT[j] : 0.0;
+                radial_gl(k, d, j >= 0 ? b[j] : 0.0, rho, gx, gw, &IV, &IT);
+                const cplx J = IT - inv4pi * (log(rho + Re) - rho / Re);
+                const cplx eR = cexp(-JJ * k * Re);
+                sumS += wt * eR;
+                sumN += wt * d * eR / Re;
+                for (int m = 0; m < 3; ++m) {
+                    UV[m] += wt * uh[m] * IV;
+                    UJ[m] += wt * uh[m] * J;
+                }
+            }
+        }
+    }
+    *S = (ekd * tot - sumS) * inv4pi / (JJ * k);
+    const cplx nrm = inv4pi * (sumN - sgd * ekd * tot);
+    for (int m = 0; m < 3; ++m) {
+        V[m] = rho0[m] * (*S) + UV[m];
+        Gv[m] = n[m] * nrm - UJ[m];
+    }
+}
+
 /* Exported for the oracle's own tests. */
 void oracle_static_pot(const double *v9, const double *r, double *out7) {
     double v[3][3]; memcpy(v, v9, sizeof(v));
@@ -90,15 +234,34 @@ void oracle_static_pot(const double *v9, const double *r, double *out7) {
     static_pot(v, n, r, &out7[0], &out7[1], &out7[4]);
 }
 
+/* Exported for the oracle's own tests: out14 = S, V[3], Gv[3] (re, im). */
+void oracle_polar_pot(const double *v9, const double *r, double kr, double ki, const double *gx,
+                      const double *gw, double *out14) {
+    double v[3][3]; memcpy(v, v9, sizeof(v));
+    double e1[3], e2[3], n[3];
+    sub3(v[1], v[0], e1); sub3(v[2], v[0], e2); cross3(e1, e2, n);
+    double nn = norm3(n); n[0] /= nn; n[1] /= nn; n[2] /= nn;
+    cplx S, V[3], Gv[3];
+    polar_pot(v, n, r, kr + JJ * ki, gx, gw, &S, V, Gv);
+    out14[0] = creal(S); out14[1] = cimag(S);
+    for (int m = 0; m < 3; ++m) {
+        out14[2 + 2 * m] = creal(V[m]); out14[3 + 2 * m] = cimag(V[m]);
+        out14[8 + 2 * m] = creal(Gv[m]); out14[9 + 2 * m] = cimag(Gv[m]);
+    }
+}
+
 /* verts [T][3][3], area [T], sgn [T][3], len [T][3]
  * pairs tl[P], sl[P]; k = kr + j ki
- * outer rule (no, bo[no][3], wo[no]); inner rule (ni, bi[ni][3], wi[ni])
+ * outer rule (no, bo[no][3], wo[no]); inner rule (ni, bi[ni][3], wi[ni]);
+ * polar != 0: the strong-loss inner scheme (polar_pot, Gauss-Legendre nodes
+ * gx, weights gw on [-1, 1], POLAR_NG of each) instead of the inner rule
  * outputs (interleaved complex) A, Phi, K: [P][3][3][2] */
 void oracle_pair_blocks(const double *verts, const double *area, const double *sgn,
                         const double *len, long long P, const long long *tl, const long long *sl,
                         double kr, double ki,
                         int no, const double *bo, const double *wo,
                         int ni, const double *bi, const double *wi,
+                        int polar, const double *gx, const double *gw,
                         double *Aout, double *Pout, double *Kout) {
     const cplx k = kr + JJ * ki;
     const double inv4pi = 1.0 / (4.0 * PI_);
@@ -128,14 +291,17 @@ void oracle_pair_blocks(const double *verts, const double *area, const double *s
             for (int c = 0; c < 3; ++c)
                 r[c] = bo[3*qo] * tv[0][c] + bo[3*qo+1] * tv[1][c] + bo[3*qo+2] * tv[2][c];
             const double W = wo[qo] * At;
+            cplx S, V[3], Gv[3];
+            if (polar) {
+                polar_pot(sv, ns, r, k, gx, gw, &S, V, Gv);
+            } else {
             double I0, Irho[3], gI[3];
             static_pot(sv, ns, r, &I0, Irho, gI);
             double tmp[3]; sub3(r, sv[0], tmp);
             double d = dot3(tmp, ns);
             if (fabs(d) <= 1e-10 * norm3(e1)) d = 0.0;
             double rho[3] = { r[0] - d * ns[0], r[1] - d * ns[1], r[2] - d * ns[2] };
-            cplx S = I0 * inv4pi;
-            cplx V[3], Gv[3];
+            S = I0 * inv4pi;
             for (int c = 0; c < 3; ++c) {
                 V[c] = (Irho[c] + rho[c] * I0) * inv4pi;
                 Gv[c] = gI[c] * inv4pi;
@@ -159,6 +325,7 @@ void oracle_pair_blocks(const double *verts, const double *area, const double *s
                     V[c] += wA * rem * ip[qi][c];
                     Gv[c] += wA * hg * df[c];
                 }
+            }
             }
             for (int e = 0; e < 3; ++e) {
                 double fe[3];

@@ -168,6 +168,23 @@ def inner_rule(kind, rules):
     return collapsed_gauss(rules["far_in"])
 
 
+# Strong loss: G decays within a fraction of a triangle and the static
+# extraction cancels to far below its parts.  Touching and close pairs whose
+# source triangle's longest edge l has |Im k| l > POLAR_KL, in media with
+# |Im k| >= POLAR_LOSS |k|, take the polar inner scheme (oracle/csrc/pairint.c).
+POLAR_KL = 2.0
+POLAR_LOSS = 0.38
+
+
+def polar_pairs(mesh, k, sl, kind):
+    """Boolean [P]: pairs integrated with the strong-loss inner scheme."""
+    k = complex(k)
+    if abs(k.imag) < POLAR_LOSS * abs(k):
+        return np.zeros(len(sl), bool)
+    lmax = mesh.tri_len[np.asarray(sl)].max(axis=1)
+    return (kind <= KIND_CLOSE) & (abs(k.imag) * lmax > POLAR_KL)
+
+
 def pair_blocks(mesh, k, tl, sl, rules=None):
     """Local (A, Phi, K) blocks [P,3,3] with the oracle's integration policy
     (plain-C core)."""
@@ -177,17 +194,19 @@ def pair_blocks(mesh, k, tl, sl, rules=None):
         r.update(rules)
     tl = np.asarray(tl, dtype=np.int64); sl = np.asarray(sl, dtype=np.int64)
     kind, local = classify_pairs(mesh, tl, sl)
+    pol = polar_pairs(mesh, k, sl, kind)
     P = len(tl)
     A = np.empty((P, 3, 3), np.complex128); Ph = np.empty_like(A); K = np.empty_like(A)
     for kd in range(5):
         for lc in (range(3) if kd in (KIND_EDGE, KIND_VERTEX) else (0,)):
             sel = (kind == kd) if kd not in (KIND_EDGE, KIND_VERTEX) else ((kind == kd) & (local == lc))
-            idx = np.nonzero(sel)[0]
-            if len(idx) == 0:
-                continue
-            a, p, kk = pair_blocks_c(mesh, k, tl[idx], sl[idx], outer_rule(kd, lc, r),
-                                     inner_rule(kd, r))
-            A[idx] = a; Ph[idx] = p; K[idx] = kk
+            for pl in (False, True):
+                idx = np.nonzero(sel & (pol == pl))[0]
+                if len(idx) == 0:
+                    continue
+                a, p, kk = pair_blocks_c(mesh, k, tl[idx], sl[idx], outer_rule(kd, lc, r),
+                                         inner_rule(kd, r), polar=pl)
+                A[idx] = a; Ph[idx] = p; K[idx] = kk
     return A, Ph, K
 
 
