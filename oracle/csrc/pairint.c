@@ -18,8 +18,9 @@
  * Strongly lossy media (|Im k| l > 2 on the source triangle's longest edge l,
  * |Im k| >= 0.38 |k|) make G decay within a small fraction of a triangle; the
  * extracted static part and the quadrature of the remainder then cancel to a
- * result far below either, and the remainder rule fails.  Touching and close
- * pairs there take polar_pot: polar coordinates around the projection of the
+ * result far below either, and the remainder rule fails (distant pairs keep
+ * its quadrature error in place of an exponentially small value).  All pairs
+ * there take polar_pot: polar coordinates around the projection of the
  * observation point, the radial integral of G in closed form, the radial
  * integrals of G r' and of the gradient remainder by Gauss-Legendre on
  * intervals graded in units of 1/|k| (cut at 64/|k|, with the closed-form
@@ -123,11 +124,13 @@ static void radial_gl(cplx k, double d, double a, double b, const double *gx, co
  *   V   = rho0 S + sum int dtheta u IV(rho),  IV = int_0^rho G rp^2 drp
  *   Gv.n = sum int dtheta [d exp(-jk Re)/Re - sign(d) exp(-jk|d|)] / (4 pi)
  *   Gv_t = -sum int dtheta u J(rho),  J = int_0^rho g rp^2 drp, g R^3 = -(1 + jkR) exp(-jkR)/(4 pi)
- * J splits into -(ln(rho + Re) - rho/Re)/(4 pi) plus the integral IT of the
- * remainder g + 1/(4 pi R^3); the theta-independent rest (ln|d|/(4 pi),
- * divergent in the plane) drops out since sum int u dtheta = 0 for points
- * off the triangle's boundary.  Beyond the cut IV and J are constant and
- * their angular integrals are closed-form. */
+ * J splits into -(ln(rho + Re) - rho/Re - ln|d|)/(4 pi) plus the integral
+ * IT of the remainder g + 1/(4 pi R^3).  In the plane (d = 0) the ln|d| term
+ * diverges; it is theta-independent and drops out there, since the signed
+ * sum of int u dtheta vanishes for in-plane points, which never lie on the
+ * triangle's boundary (off the plane they may: points of a face at right
+ * angles project onto the shared edge, so the term is kept).  Beyond the
+ * cut IV and J are constant and their angular integrals are closed-form. */
 static void polar_pot(const double v[3][3], const double n[3], const double r[3], cplx k,
                       const double *gx, const double *gw, cplx *S, cplx V[3], cplx Gv[3]) {
     const double inv4pi = 1.0 / (4.0 * PI_);
@@ -153,7 +156,8 @@ static void polar_pot(const double v[3][3], const double n[3], const double r[3]
     }
     const double rc = b[POLAR_NB - 1], Rc = sqrt(rc * rc + d * d);
     const cplx Vc = CV[POLAR_NB - 1];
-    const cplx Jc = CT[POLAR_NB - 1] - inv4pi * (log(rc + Rc) - rc / Rc);
+    const double gref = ad > 0.0 ? log(ad) : 0.0;
+    const cplx Jc = CT[POLAR_NB - 1] - inv4pi * (log(rc + Rc) - rc / Rc - gref);
     const cplx ekd = cexp(-JJ * k * ad);
     cplx sumS = 0.0, sumN = 0.0, UV[3] = {0.0, 0.0, 0.0}, UJ[3] = {0.0, 0.0, 0.0};
     double tot = 0.0;
@@ -206,7 +210,7 @@ static void polar_pot(const double v[3][3], const double n[3], const double r[3]
                 while (j + 1 < POLAR_NB && b[j + 1] <= rho) ++j;
                 cplx IV = j >= 0 ? CV[j] : 0.0, IT = j >= 0 ? CT[j] : 0.0;
                 radial_gl(k, d, j >= 0 ? b[j] : 0.0, rho, gx, gw, &IV, &IT);
-                const cplx J = IT - inv4pi * (log(rho + Re) - rho / Re);
+                const cplx J = IT - inv4pi * (log(rho + Re) - rho / Re - gref);
                 const cplx eR = cexp(-JJ * k * Re);
                 sumS += wt * eR;
                 sumN += wt * d * eR / Re;

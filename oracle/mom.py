@@ -169,20 +169,22 @@ def inner_rule(kind, rules):
 
 
 # Strong loss: G decays within a fraction of a triangle and the static
-# extraction cancels to far below its parts.  Touching and close pairs whose
-# source triangle's longest edge l has |Im k| l > POLAR_KL, in media with
-# |Im k| >= POLAR_LOSS |k|, take the polar inner scheme (oracle/csrc/pairint.c).
+# extraction cancels to far below its parts (for distant pairs the true value
+# is exponentially small and the extraction leaves its quadrature error).
+# Pairs whose source triangle's longest edge l has |Im k| l > POLAR_KL, in
+# media with |Im k| >= POLAR_LOSS |k|, take the polar inner scheme
+# (oracle/csrc/pairint.c), whatever their kind.
 POLAR_KL = 2.0
 POLAR_LOSS = 0.38
 
 
-def polar_pairs(mesh, k, sl, kind):
+def polar_pairs(mesh, k, sl, kind=None):
     """Boolean [P]: pairs integrated with the strong-loss inner scheme."""
     k = complex(k)
     if abs(k.imag) < POLAR_LOSS * abs(k):
         return np.zeros(len(sl), bool)
     lmax = mesh.tri_len[np.asarray(sl)].max(axis=1)
-    return (kind <= KIND_CLOSE) & (abs(k.imag) * lmax > POLAR_KL)
+    return abs(k.imag) * lmax > POLAR_KL
 
 
 def pair_blocks(mesh, k, tl, sl, rules=None):

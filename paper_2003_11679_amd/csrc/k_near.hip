@@ -207,6 +207,139 @@ __device__ inline c128 cexp_mjk(c128 k, double R) {   // exp(-j k R)
     return {mag * c, -mag * s};
 }
 
+// ---------------------------------------------------------------- strong loss
+// When the medium's field decays within a small fraction of a triangle
+// (|Im k| l > 2 for the source triangle's longest edge l, |Im k| >= 0.38 |k|),
+// the static extraction cancels to far below its parts and the remainder
+// rule fails (distant pairs keep its quadrature error in place of an
+// exponentially small value).  Every pair then integrates in polar coordinates
+// about the projection rho0 of the observation point: the triangle is the
+// signed sum of the triangles (rho0, edge), swept by the angle theta with
+// direction u(theta), edge distance rho(theta), Re = sqrt(rho^2 + d^2):
+//   S    = sum int dtheta [exp(-jk|d|) - exp(-jk Re)] / (4 pi jk)
+//   V    = rho0 S + sum int dtheta u IV(rho),   IV = int_0^rho G rp^2 drp
+//   Gv.n = sum int dtheta [d exp(-jk Re)/Re - sign(d) exp(-jk|d|)] / (4 pi)
+//   Gv_t = -sum int dtheta u J(rho),  J = IT - (ln(rho + Re) - rho/Re - ln|d|)/(4 pi)
+// with IT the radial integral of the gradient kernel's remainder
+// [1 - (1 + jkR) exp(-jkR)] rp^2/(4 pi R^3).  In the plane (d = 0) the ln|d|
+// term diverges and drops out: it is theta-independent and the signed sum of
+// int u dtheta vanishes for in-plane points, which never lie on the
+// triangle's boundary (off the plane they can: points of a face at right
+// angles project onto the shared edge, so there it is kept).  The
+// radial integrals use Gauss-Legendre on intervals graded in 1/|k| up to the
+// cut 64/|k|, beyond which IV and J are constant and their angular integrals
+// closed-form; the angle uses composite Gauss-Legendre, broken where rho
+// crosses a radial breakpoint.
+constexpr int kPolarNB = 14, kPolarNG = 8;
+__constant__ double kPolarB[kPolarNB] = {0.25, 0.5, 1.0, 2.0, 3.0, 4.0, 6.0, 8.0, 12.0, 16.0, 24.0, 32.0, 48.0, 64.0};
+constexpr double kPolarKL = 2.0, kPolarLoss = 0.38;
+
+__device__ inline void polar_radial(c128 k, double d, double lo, double hi, const double *gx, const double *gw,
+                                    c128 &IV, c128 &IT) {
+    const double h = 0.5 * (hi - lo), c = 0.5 * (hi + lo);
+    for (int g = 0; g < kPolarNG; ++g) {
+        const double rp = c + h * gx[g];
+        const double R = sqrt(rp * rp + d * d);
+        const c128 e = cexp_mjk(k, R);
+        const double w = h * gw[g] * rp * rp / (4.0 * M_PI * R);
+        IV += w * e;
+        const c128 opjkR(1.0 - k.im * R, k.re * R);          // 1 + j k R
+        IT += (w / (R * R)) * (c128(1.0) - opjkR * e);
+    }
+}
+
+__device__ void polar_potentials(const SrcTri &st, V3 r, c128 k, const double *gl, c128 &S, CV3 &V, CV3 &Gv) {
+    const double *gx = gl, *gw = gl + kPolarNG;
+    const double inv4pi = 1.0 / (4.0 * M_PI);
+    double d = dot(r - st.v[0], st.n);
+    if (fabs(d) <= 1e-10 * st.e01) d = 0.0;
+    const double ad = fabs(d), sgd = d > 0.0 ? 1.0 : (d < 0.0 ? -1.0 : 0.0);
+    const V3 rho0 = r - d * st.n;
+    const double u = 1.0 / hypot(k.re, k.im);
+    double b[kPolarNB];
+    c128 CV[kPolarNB], CT[kPolarNB];
+    {
+        c128 iv, it;
+        double lo = 0.0;
+        for (int j = 0; j < kPolarNB; ++j) {
+            b[j] = kPolarB[j] * u;
+            polar_radial(k, d, lo, b[j], gx, gw, iv, it);
+            CV[j] = iv;
+            CT[j] = it;
+            lo = b[j];
+        }
+    }
+    const double rc = b[kPolarNB - 1], Rc = sqrt(rc * rc + d * d);
+    const c128 Vc = CV[kPolarNB - 1];
+    const double gref = ad > 0.0 ? log(ad) : 0.0;
+    const c128 Jc = CT[kPolarNB - 1] - c128(inv4pi * (log(rc + Rc) - rc / Rc - gref));
+    const c128 ekd = cexp_mjk(k, ad);
+    c128 sumS, sumN;
+    CV3 UV = {}, UJ = {};
+    double tot = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        const V3 a = st.v[i], bb = st.v[(i + 1) % 3];
+        const double ll = len(bb - a);
+        const V3 lh = st.lh[i], mh = st.mh[i];
+        const V3 am = a - rho0, bm = bb - rho0;
+        const double t = dot(am, mh), sa = dot(am, lh), sb = dot(bm, lh);
+        if (fabs(t) <= 1e-12 * ll) continue;
+        const double at = fabs(t), sg = t > 0.0 ? 1.0 : -1.0;
+        const double tha = atan(sa / at), thb = atan(sb / at);
+        tot += sg * (thb - tha);
+        double bp[2 * kPolarNB + 2];
+        int nbp = 0;
+        bp[nbp++] = tha;
+        for (int j = 0; j < kPolarNB; ++j) {
+            if (b[j] <= at) continue;
+            const double ph = acos(at / b[j]);
+            if (-ph > tha && -ph < thb) bp[nbp++] = -ph;
+            if (ph > tha && ph < thb) bp[nbp++] = ph;
+        }
+        bp[nbp++] = thb;
+        for (int x = 1; x < nbp; ++x)
+            for (int y = x; y > 0 && bp[y - 1] > bp[y]; --y) {
+                const double q = bp[y];
+                bp[y] = bp[y - 1];
+                bp[y - 1] = q;
+            }
+        for (int q = 0; q + 1 < nbp; ++q) {
+            const double t1 = bp[q], t2 = bp[q + 1];
+            const double h = 0.5 * (t2 - t1), c = 0.5 * (t2 + t1);
+            if (h <= 0.0) continue;
+            if (at / cos(c) >= rc) {
+                const V3 U = sg * ((sg * (sin(t2) - sin(t1))) * mh - (cos(t2) - cos(t1)) * lh);
+                cadd(UV, cscale(Vc, U));
+                cadd(UJ, cscale(Jc, U));
+                continue;
+            }
+            for (int g = 0; g < kPolarNG; ++g) {
+                const double th = c + h * gx[g];
+                const double wt = sg * h * gw[g];
+                const double ct = cos(th), sn = sin(th);
+                const double rho = at / ct, Re = sqrt(rho * rho + d * d);
+                const V3 uh = (sg * ct) * mh + sn * lh;
+                int j = -1;
+                while (j + 1 < kPolarNB && b[j + 1] <= rho) ++j;
+                c128 IV = j >= 0 ? CV[j] : c128(), IT = j >= 0 ? CT[j] : c128();
+                polar_radial(k, d, j >= 0 ? b[j] : 0.0, rho, gx, gw, IV, IT);
+                const c128 J = IT - c128(inv4pi * (log(rho + Re) - rho / Re - gref));
+                const c128 eR = cexp_mjk(k, Re);
+                sumS += wt * eR;
+                sumN += (wt * d / Re) * eR;
+                cadd(UV, cscale(wt * IV, uh));
+                cadd(UJ, cscale(wt * J, uh));
+            }
+        }
+    }
+    const c128 ijk = cdiv(c128(1.0), c128(-k.im, k.re));   // 1/(j k)
+    S = (tot * ekd - sumS) * inv4pi * ijk;
+    const c128 nrm = inv4pi * (sumN - (sgd * tot) * ekd);
+    const CV3 sr = cscale(S, rho0), nn = cscale(nrm, st.n);
+    V = {sr.x + UV.x, sr.y + UV.y, sr.z + UV.z};
+    Gv = {nn.x - UJ.x, nn.y - UJ.y, nn.z - UJ.z};
+}
+
 __device__ inline int rule_index_outer(int kind, int loc) {
     // 0 self, 1..3 edge(opp), 4..6 vertex(vtx), 7 close, 8 far
     if (kind == KIND_SELF) return 0;
@@ -284,20 +417,28 @@ __device__ void fill_pair(const NearFillArgs &a, int64_t tl, int64_t sl, int64_t
     const double *Ro = a.rules + 4 * a.rule_off[ro];
     const double *Ri = a.rules + 4 * a.rule_off[ri];
     const int no = a.rule_n[ro], ni = a.rule_n[ri];
+    double lmax = 0.0;
+    for (int i = 0; i < 3; ++i) lmax = fmax(lmax, len(ps[(i + 1) % 3] - ps[i]));
+    const bool polar = a.polar && fabs(k.im) * lmax > kPolarKL;
 
     c128 aRV, aS;
     CV3 aV = {}, aSR = {}, aGR = {}, aG = {};
     for (int qo = 0; qo < no; ++qo) {
         const V3 r = Ro[4 * qo] * pt[0] + Ro[4 * qo + 1] * pt[1] + Ro[4 * qo + 2] * pt[2];
         const double W = Ro[4 * qo + 3] * At;
+        c128 S;
+        CV3 V, Gv;
+        if (polar) {
+            polar_potentials(st, r, k, a.polar_gl, S, V, Gv);
+        } else {
         double I0, d;
         V3 Irho, gI;
         static_potentials(st, r, I0, Irho, gI, d);
         const V3 rho = r - d * st.n;
-        c128 S(I0 * inv4pi, 0.0);
-        CV3 V = {c128((Irho.x + rho.x * I0) * inv4pi), c128((Irho.y + rho.y * I0) * inv4pi),
-                 c128((Irho.z + rho.z * I0) * inv4pi)};
-        CV3 Gv = {c128(gI.x * inv4pi), c128(gI.y * inv4pi), c128(gI.z * inv4pi)};
+        S = c128(I0 * inv4pi, 0.0);
+        V = {c128((Irho.x + rho.x * I0) * inv4pi), c128((Irho.y + rho.y * I0) * inv4pi),
+             c128((Irho.z + rho.z * I0) * inv4pi)};
+        Gv = {c128(gI.x * inv4pi), c128(gI.y * inv4pi), c128(gI.z * inv4pi)};
         for (int qi = 0; qi < ni; ++qi) {
             const V3 rp = Ri[4 * qi] * ps[0] + Ri[4 * qi + 1] * ps[1] + Ri[4 * qi + 2] * ps[2];
             const double wA = Ri[4 * qi + 3] * st.A;
@@ -316,6 +457,7 @@ __device__ void fill_pair(const NearFillArgs &a, int64_t tl, int64_t sl, int64_t
             S += wA * rem;
             cadd(V, cscale(wA * rem, rp));
             cadd(Gv, cscale(wA * hg, df));
+        }
         }
         aRV += W * cdot(r, V);
         aS += W * S;

@@ -58,6 +58,8 @@ struct NearFillArgs {
     const c128 *gradial; int nq;     // radial tables (G, grad G / (h d)) for |d|^2 < nq
     c128 k; double h;
     c128 *blocks;                    // [npairs][3][3][3]: L, K (precorrected), L direct
+    int polar;                       // medium lossy enough for the strong-loss inner scheme
+    const double *polar_gl;          // its Gauss-Legendre nodes [8] and weights [8] on [-1, 1]
 };
 void launch_near_fill(const NearFillArgs &a, int64_t npairs, hipStream_t st);
 void launch_near_gather(int64_t nrow, int64_t rwg0, int64_t max_row, const int64_t *row_ptr, const int32_t *cols,

@@ -264,6 +264,14 @@ static void build_medium(sie_problem *p, Medium &md) {
     const int nq = 3 * W * W + 1;
     DBuf<c128> d_grad(2 * nq);
     launch_green_radial(md.k, g.h, nq, d_grad.p, 0);
+    // strong-loss inner scheme: 8-point Gauss-Legendre on [-1, 1]
+    std::vector<double> glx, glw, gl;
+    gauss_legendre01(8, glx, glw);
+    for (double x : glx) gl.push_back(2.0 * x - 1.0);
+    for (double w : glw) gl.push_back(2.0 * w);
+    DBuf<double> d_gl;
+    d_gl.upload(gl);
+    const int polar = std::fabs(md.k.im) >= 0.38 * std::hypot(md.k.re, md.k.im) ? 1 : 0;
 
     md.d_nL64.alloc(std::max<int64_t>(g.nnz, 1));
     md.d_nK64.alloc(std::max<int64_t>(g.nnz, 1));
@@ -296,6 +304,8 @@ static void build_medium(sie_problem *p, Medium &md) {
         a.rules = d_rules.p; a.rule_off = d_off.p; a.rule_n = d_num.p;
         a.gradial = d_grad.p; a.nq = nq; a.k = md.k; a.h = g.h;
         a.blocks = blocks.p;
+        a.polar = polar;
+        a.polar_gl = d_gl.p;
         launch_near_fill(a, np, 0);
         launch_near_gather(nrow, g.rwg0, g.max_row, g.d_row_ptr.p, g.d_cols.p, g.d_rwgloc.p, g.d_glob2loc.p,
                            p->d_tpm.p, p->d_epm.p, d_pp.p, g.d_pair_s.p + pptr[t0], blocks.p, md.d_nL64.p,

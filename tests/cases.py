@@ -13,6 +13,9 @@ CASES = {
     "sphere2": (lambda: icosphere(2), 4.0, 0.0, 150e6, 12, 3),
     "sphere2_lossy": (lambda: icosphere(2), 4.0, 0.5, 150e6, 10, 2),
     "bar_small": (lambda: box_mesh((100e-6, 10e-6, 5e-6), (30, 3, 2)), 1.0, 5.8e7, 10e9, 20, 3),
+    # good conductor on a coarse mesh: skin depth 5 um, edges 0.5 mm
+    # (|Im k_i| l ~ 140, strong-loss inner integration)
+    "box_cond": (lambda: box_mesh((3e-3, 2e-3, 2e-3), (6, 4, 4)), 1.0, 1e7, 1e9, 12, 3),
 }
 
 

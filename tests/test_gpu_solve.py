@@ -16,7 +16,7 @@ E0 = (1.0, 0.0, 0.0)
 @pytest.fixture(scope="module")
 def solved():
     out = {}
-    for name in ("sphere2", "sphere2_lossy"):
+    for name in ("sphere2", "sphere2_lossy", "box_cond"):
         print(f"[solve {name}]", flush=True)
         p = gpu_problem(name)
         p.set_planewaves(KHAT, E0)
@@ -44,9 +44,28 @@ def test_converged(solved):
 
 
 def test_fp32_refined_matches_fp64(solved):
+    """The spheres' systems are well conditioned: currents agree to 2e-5.  The
+    conducting box is electrically tiny (k0 l = 0.06), its exterior EFIE
+    conditioning (~1e8) turns the 1e-6 residual into ~1e-3 current
+    differences along near-null directions that do not radiate; there the far
+    field is compared tightly."""
+    th = np.linspace(0.0, np.pi, 13)
+    rhat = np.stack([np.sin(th), 0 * th, np.cos(th)], axis=1)
     for name, s in solved.items():
+        tol = 1e-3 if name == "box_cond" else 2e-5
         for a, b in ((s["u32"], s["u64"]), (s["v32"], s["v64"])):
-            assert np.linalg.norm(a - b) <= 2e-5 * np.linalg.norm(b), name
+            err = np.linalg.norm(a - b) / np.linalg.norm(b)
+            print(f"{name}: fp32 vs fp64 currents {err:.2e}")
+            assert err <= tol, (name, err)
+        if name == "box_cond":
+            p = s["p"]
+            u, v = p.currents()
+            f32 = p.far_field(rhat)
+            p.solve(0)
+            f64 = p.far_field(rhat)
+            err = np.abs(f32 - f64).max() / np.abs(f64).max()
+            print(f"{name}: fp32 vs fp64 far field {err:.2e}")
+            assert err < 1e-5, (name, err)
 
 
 def test_solution_satisfies_oracle_aim_system(solved):
@@ -78,8 +97,11 @@ def test_close_to_dense_solution(solved):
     Sec. IV for its interior wavenumber (|k_i| h = 7): the oracle's own AIM
     operators, assembled densely, are 1-3e-2 from the dense ones there and the
     oracle's AIM solution is 3.6e-2 (u) / 2.8e-2 (v) from the dense solution;
-    the GPU solution equals the oracle's AIM one (the system-residual test)."""
-    tols = {"sphere2_lossy": 5e-2, "sphere2": 0.1}
+    the GPU solution equals the oracle's AIM one (the system-residual test).
+    The conducting box (skin depth 1e-2 of an edge) has an essentially local
+    interior operator; its AIM solution is 1.2e-3 (u) / 3.0e-3 (v) from the
+    dense one with the oracle's own operators."""
+    tols = {"sphere2_lossy": 5e-2, "sphere2": 0.1, "box_cond": 1e-2}
     for name, s in solved.items():
         dp = _dense(name)
         e = dp.rhs(KHAT, E0)

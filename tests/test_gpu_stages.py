@@ -18,7 +18,7 @@ def _rel(a, b):
     return np.abs(a - b).max() / np.abs(b).max()
 
 
-@pytest.fixture(scope="module", params=["sphere2", "bar_small"])
+@pytest.fixture(scope="module", params=["sphere2", "bar_small", "box_cond"])
 def case(request):
     name = request.param
     print(f"[case {name}]", flush=True)
