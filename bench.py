@@ -99,15 +99,21 @@ def step(mesh, cfg, prec, tol, timing=False):
 
 def spmv_bytes(p, prec):
     """Algorithmic HBM bytes of one k_spmv_far launch: CSR values and column
-    indices, row pointers, x read once, y written once, far-part operands
+    indices in the stored form (16-bit offsets from each row's first column
+    plus that base when every row spans fewer than 65536 columns, else 32-bit
+    indices), row pointers, x read once, y written once, far-part operands
     (two triangles per row: coefficient and interpolation partials)."""
     rp, cols = p.near_pattern(-1)
     nnz = len(cols)
     E = p.num_rwg
     T = p.num_tri
+    nrow = len(rp) - 1
     s = 8 if prec == 1 else 16          # complex element
     r = 4 if prec == 1 else 8           # real element
-    return nnz * (s + 4) + (E + 1) * 8 + 2 * E * s + E * 8 + T * (12 * r + 5 * s), nnz
+    full = rp[1:] > rp[:-1]
+    span = cols[rp[1:][full] - 1] - cols[rp[:-1][full]] if full.any() else np.zeros(1)
+    idx = nnz * 2 + nrow * 4 if span.max() < 65536 else nnz * 4
+    return nnz * s + idx + (E + 1) * 8 + 2 * E * s + E * 8 + T * (12 * r + 5 * s), nnz
 
 
 def cpu_baseline(cfg, mesh, rows):

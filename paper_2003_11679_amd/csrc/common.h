@@ -185,6 +185,12 @@ struct Grid {
     int64_t rwg0 = 0, rwg1 = 0; // RWG range [rwg0, rwg1)
     DBuf<int64_t> d_row_ptr;   // [nrow + 1] (row r = RWG rwg0 + r)
     DBuf<int32_t> d_cols;      // [nnz] global RWG column
+    // the same columns as 16-bit offsets from the row's first column, when
+    // every row spans fewer than 65536 columns (the products then stream
+    // 2 bytes per index instead of 4)
+    bool cols16 = false;
+    DBuf<uint16_t> d_cols16;   // [nnz]
+    DBuf<int32_t> d_row_base;  // [nrow]
     int64_t nnz = 0;
     int64_t max_row = 0;
     DBuf<int32_t> d_trirwg;    // [ntg][3] global RWG of each local triangle edge

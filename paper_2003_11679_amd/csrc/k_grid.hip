@@ -237,9 +237,34 @@ __device__ inline cx<T> wave_sum(cx<T> v) {
 
 // One wavefront per row.  Far part of row n from its two triangles:
 // c_e (psi - q_e . chi) + kscal c_e zeta   (kscal = -2 k^-2 for L, 0 for K).
-template <typename T>
+// Row base (first column) and 16-bit column offsets: one wave per row.
+__global__ void k_cols16(int64_t nrow, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ cols,
+                         int32_t *__restrict__ row_base, uint16_t *__restrict__ cols16, int *__restrict__ wide) {
+    const int lane = threadIdx.x & 63;
+    const int64_t r = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (r >= nrow) return;
+    const int64_t b = row_ptr[r], e = row_ptr[r + 1];
+    const int32_t base = e > b ? cols[b] : 0;
+    if (lane == 0) row_base[r] = base;
+    if (e > b && cols[e - 1] - base > 65535) {      // columns ascend within a row
+        if (lane == 0) atomicMax(wide, 1);
+        return;
+    }
+    for (int64_t j = b + lane; j < e; j += 64) cols16[j] = (uint16_t)(cols[j] - base);
+}
+
+void launch_cols16(int64_t nrow, const int64_t *row_ptr, const int32_t *cols, int32_t *row_base, uint16_t *cols16,
+                   int *wide, hipStream_t st) {
+    if (nrow <= 0) return;
+    hipLaunchKernelGGL(k_cols16, dim3((unsigned)((nrow + 3) / 4)), dim3(256), 0, st, nrow, row_ptr, cols, row_base,
+                       cols16, wide);
+    SIE_HIP(hipGetLastError());
+}
+
+template <typename T, bool C16>
 __global__ void k_spmv_far(int64_t E, int64_t rwg0, int64_t rwg1, const int64_t *__restrict__ row_ptr,
-                           const int32_t *__restrict__ cols, const cx<T> *__restrict__ vals,
+                           const int32_t *__restrict__ cols, const uint16_t *__restrict__ cols16,
+                           const int32_t *__restrict__ row_base, const cx<T> *__restrict__ vals,
                            const int32_t *__restrict__ rwg_loc, const T *__restrict__ coef,
                            const cx<T> *__restrict__ tripot, cx<T> kscal, const cx<T> *__restrict__ x,
                            cx<T> *__restrict__ y, int use_far) {
@@ -255,14 +280,20 @@ __global__ void k_spmv_far(int64_t E, int64_t rwg0, int64_t rwg1, const int64_t 
     if (vals) {
         const int64_t b = row_ptr[r], e = row_ptr[r + 1];
         // four independent gathers in flight per lane; values and column
-        // indices are streamed once (non-temporal), x stays cache-resident
+        // indices are streamed once (non-temporal), x stays cache-resident;
+        // C16: columns as 16-bit offsets from the row's first column
+        const int32_t base = C16 ? row_base[r] : 0;
+        auto col = [&](int64_t jj) -> int32_t {
+            if constexpr (C16) return base + (int32_t)__builtin_nontemporal_load(cols16 + jj);
+            else return __builtin_nontemporal_load(cols + jj);
+        };
         cx<T> a1, a2, a3;
         int64_t j = b + lane;
         for (; j + 192 < e; j += 256) {
-            const int32_t c0 = __builtin_nontemporal_load(cols + j);
-            const int32_t c1 = __builtin_nontemporal_load(cols + j + 64);
-            const int32_t c2 = __builtin_nontemporal_load(cols + j + 128);
-            const int32_t c3 = __builtin_nontemporal_load(cols + j + 192);
+            const int32_t c0 = col(j);
+            const int32_t c1 = col(j + 64);
+            const int32_t c2 = col(j + 128);
+            const int32_t c3 = col(j + 192);
             const T *vp = reinterpret_cast<const T *>(vals + j);
             const cx<T> v0(__builtin_nontemporal_load(vp), __builtin_nontemporal_load(vp + 1));
             const cx<T> v1(__builtin_nontemporal_load(vp + 128), __builtin_nontemporal_load(vp + 129));
@@ -273,7 +304,7 @@ __global__ void k_spmv_far(int64_t E, int64_t rwg0, int64_t rwg1, const int64_t 
             a2 += v2 * x[c2];
             a3 += v3 * x[c3];
         }
-        for (; j < e; j += 64) acc += vals[j] * x[cols[j]];
+        for (; j < e; j += 64) acc += vals[j] * x[col(j)];
         acc += (a1 + a2) + a3;
         acc = wave_sum(acc);
     }
@@ -299,9 +330,15 @@ void launch_spmv_far(const Grid &g, int64_t E, const int32_t *rwg_loc, const T *
                      cx<T> kscal, const cx<T> *vals, const cx<T> *x, cx<T> *y, bool use_far, hipStream_t st) {
     if (E == 0) return;
     const int rows_per_block = 4;
-    hipLaunchKernelGGL(k_spmv_far<T>, dim3((unsigned)((E + rows_per_block - 1) / rows_per_block)), dim3(256), 0, st,
-                       E, g.rwg0, g.rwg1, g.d_row_ptr.p, g.d_cols.p, vals, rwg_loc, tri_coef, tripot, kscal, x, y,
-                       use_far ? 1 : 0);
+    const dim3 grid((unsigned)((E + rows_per_block - 1) / rows_per_block));
+    if (g.cols16)
+        hipLaunchKernelGGL((k_spmv_far<T, true>), grid, dim3(256), 0, st, E, g.rwg0, g.rwg1, g.d_row_ptr.p, g.d_cols.p,
+                           g.d_cols16.p, g.d_row_base.p, vals, rwg_loc, tri_coef, tripot, kscal, x, y,
+                           use_far ? 1 : 0);
+    else
+        hipLaunchKernelGGL((k_spmv_far<T, false>), grid, dim3(256), 0, st, E, g.rwg0, g.rwg1, g.d_row_ptr.p,
+                           g.d_cols.p, g.d_cols16.p, g.d_row_base.p, vals, rwg_loc, tri_coef, tripot, kscal, x, y,
+                           use_far ? 1 : 0);
     SIE_HIP(hipGetLastError());
 }
 
@@ -338,9 +375,11 @@ __global__ void k_rhs_transpose(int64_t E, int nrhs, const cx<T> *__restrict__ x
 // lane q of the group right-hand side q, so every lane is busy whatever
 // nrhs is; the groups are summed with lane shuffles at the end.  The x
 // values of one column are one contiguous row of xt.
-template <typename T, int RPW>
+template <typename T, int RPW, bool C16>
 __global__ void __launch_bounds__(64) k_spmm_far(int64_t E, int64_t rwg0, int64_t rwg1, int nrhs,
                                                  const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ cols,
+                                                 const uint16_t *__restrict__ cols16,
+                                                 const int32_t *__restrict__ row_base,
                                                  const cx<T> *__restrict__ vals, const int32_t *__restrict__ rwg_loc,
                                                  const T *__restrict__ coef, const cx<T> *__restrict__ tripot,
                                                  int64_t ntg, cx<T> kscal, const cx<T> *__restrict__ xt,
@@ -359,17 +398,22 @@ __global__ void __launch_bounds__(64) k_spmm_far(int64_t E, int64_t rwg0, int64_
     if (vals) {
         const int64_t b = row_ptr[rr], e = row_ptr[rr + 1];
         const cx<T> *xr = xt + (act ? r : 0);
+        const int32_t base = C16 ? row_base[rr] : 0;
+        auto col = [&](int64_t jj) -> int32_t {
+            if constexpr (C16) return base + (int32_t)cols16[jj];
+            else return cols[jj];
+        };
         cx<T> a1, a2, a3;
         int64_t j = b + slot;
         for (; j + 3 * SLOTS < e; j += 4 * SLOTS) {
-            const int32_t c0 = cols[j], c1 = cols[j + SLOTS], c2 = cols[j + 2 * SLOTS], c3 = cols[j + 3 * SLOTS];
+            const int32_t c0 = col(j), c1 = col(j + SLOTS), c2 = col(j + 2 * SLOTS), c3 = col(j + 3 * SLOTS);
             const cx<T> v0 = vals[j], v1 = vals[j + SLOTS], v2 = vals[j + 2 * SLOTS], v3 = vals[j + 3 * SLOTS];
             acc += v0 * xr[(int64_t)c0 * nrhs];
             a1 += v1 * xr[(int64_t)c1 * nrhs];
             a2 += v2 * xr[(int64_t)c2 * nrhs];
             a3 += v3 * xr[(int64_t)c3 * nrhs];
         }
-        for (; j < e; j += SLOTS) acc += vals[j] * xr[(int64_t)cols[j] * nrhs];
+        for (; j < e; j += SLOTS) acc += vals[j] * xr[(int64_t)col(j) * nrhs];
         acc += (a1 + a2) + a3;
         for (int off = RPW; off < 64; off <<= 1) {
             acc.re += __shfl_xor(acc.re, off, 64);
@@ -411,8 +455,14 @@ void launch_spmm_far(const Grid &g, int64_t E, int nrhs, const int32_t *rwg_loc,
     const dim3 grid((unsigned)E, (unsigned)((nrhs + rpw - 1) / rpw));
     const int64_t ntg = (int64_t)g.tris.size();
 #define SIE_SPMM(R)                                                                                              \
-    hipLaunchKernelGGL((k_spmm_far<T, R>), grid, dim3(64), 0, st, E, g.rwg0, g.rwg1, nrhs, g.d_row_ptr.p,        \
-                       g.d_cols.p, vals, rwg_loc, tri_coef, tripot, ntg, kscal, xt, y)
+    if (g.cols16)                                                                                                \
+        hipLaunchKernelGGL((k_spmm_far<T, R, true>), grid, dim3(64), 0, st, E, g.rwg0, g.rwg1, nrhs,             \
+                           g.d_row_ptr.p, g.d_cols.p, g.d_cols16.p, g.d_row_base.p, vals, rwg_loc, tri_coef,     \
+                           tripot, ntg, kscal, xt, y);                                                           \
+    else                                                                                                         \
+        hipLaunchKernelGGL((k_spmm_far<T, R, false>), grid, dim3(64), 0, st, E, g.rwg0, g.rwg1, nrhs,            \
+                           g.d_row_ptr.p, g.d_cols.p, g.d_cols16.p, g.d_row_base.p, vals, rwg_loc, tri_coef,     \
+                           tripot, ntg, kscal, xt, y)
     switch (rpw) {
     case 1: SIE_SPMM(1); break;
     case 2: SIE_SPMM(2); break;

@@ -288,7 +288,7 @@ __global__ __launch_bounds__(512) void k_ras_gather(int c0, const int64_t *__res
     }
 }
 
-__global__ __launch_bounds__(512) void k_ras_invert(int c0, const int64_t *__restrict__ ext_off,
+__global__ __launch_bounds__(1024) void k_ras_invert(int c0, const int64_t *__restrict__ ext_off,
                                                     const int32_t *__restrict__ own_off,
                                                     const int64_t *__restrict__ ws_off,
                                                     const int64_t *__restrict__ m_off, c128 *__restrict__ ws,
@@ -298,8 +298,8 @@ __global__ __launch_bounds__(512) void k_ras_invert(int c0, const int64_t *__res
     c128 *prow = reinterpret_cast<c128 *>(lds);          // [2 kRasMax] scaled pivot row
     c128 *fcol = prow + 2 * kRasMax;                     // [kRasMax] column k
     c128 *pinv = fcol + kRasMax;                         // 1 / pivot
-    __shared__ double rv[8];
-    __shared__ int ri[8];
+    __shared__ double rv[16];
+    __shared__ int ri[16];
     __shared__ int piv;
     const int c = c0 + blockIdx.x;
     const int n = (int)(ext_off[c + 1] - ext_off[c]);
@@ -379,13 +379,16 @@ void launch_ras_setup(int c0, int cnt, const int64_t *ext_off, const int32_t *ex
     hipLaunchKernelGGL(k_ras_gather, dim3(cnt), dim3(512), 0, st, c0, ext_off, ext, own_off, own_pos, ws_off, rwg0,
                        row_ptr, cols, vals, scale, ws);
     SIE_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_ras_invert, dim3(cnt), dim3(512), 0, st, c0, ext_off, own_off, ws_off, m_off, ws, m64, m32,
+    hipLaunchKernelGGL(k_ras_invert, dim3(cnt), dim3(1024), 0, st, c0, ext_off, own_off, ws_off, m_off, ws, m64, m32,
                        fail);
     SIE_HIP(hipGetLastError());
 }
 
-// y[own] = M_own x[ext] for every cluster and every right-hand side
-// (blockIdx.y; vectors ld apart): x[ext] staged in LDS, one wave per owned row.
+// y[own] = M_own x[ext] for every cluster and every right-hand side: one
+// workgroup per (cluster, kRasRows owned rows, right-hand side), x[ext]
+// staged in LDS, one wave per owned row (lanes over the extended set).
+constexpr int kRasRows = 16;
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_ras_apply(const int64_t *__restrict__ ext_off, const int32_t *__restrict__ ext,
                                                    const int32_t *__restrict__ own_off, const int32_t *__restrict__ own,
@@ -394,24 +397,37 @@ __global__ __launch_bounds__(256) void k_ras_apply(const int64_t *__restrict__ e
     __shared__ __align__(16) T lds[2 * kRasMax];
     cx<T> *xs = reinterpret_cast<cx<T> *>(lds);
     const int c = blockIdx.x;
-    x += blockIdx.y * ld;
-    y += blockIdx.y * ld;
-    const int64_t e0 = ext_off[c];
-    const int n = (int)(ext_off[c + 1] - e0);
     const int o0 = own_off[c];
     const int no = own_off[c + 1] - o0;
+    const int q0 = blockIdx.y * kRasRows;
+    if (q0 >= no) return;                      // uniform over the workgroup
+    x += blockIdx.z * ld;
+    y += blockIdx.z * ld;
+    const int64_t e0 = ext_off[c];
+    const int n = (int)(ext_off[c + 1] - e0);
     for (int i = threadIdx.x; i < n; i += blockDim.x) xs[i] = x[ext[e0 + i]];
     __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const cx<T> *Mc = M + m_off[c];
-    for (int q = wv; q < no; q += nw) {
+    const int q1 = min(no, q0 + kRasRows);
+    for (int q = q0 + wv; q < q1; q += nw) {
         const cx<T> *row = Mc + (int64_t)q * n;
-        T re = 0, im = 0;
-        for (int j = lane; j < n; j += 64) {
+        T re = 0, im = 0, re2 = 0, im2 = 0;
+        int j = lane;
+        for (; j + 64 < n; j += 128) {
+            const cx<T> a = row[j], b = xs[j], a2 = row[j + 64], b2 = xs[j + 64];
+            re += a.re * b.re - a.im * b.im;
+            im += a.re * b.im + a.im * b.re;
+            re2 += a2.re * b2.re - a2.im * b2.im;
+            im2 += a2.re * b2.im + a2.im * b2.re;
+        }
+        if (j < n) {
             const cx<T> a = row[j], b = xs[j];
             re += a.re * b.re - a.im * b.im;
             im += a.re * b.im + a.im * b.re;
         }
+        re += re2;
+        im += im2;
         for (int off = 32; off > 0; off >>= 1) {
             re += __shfl_down(re, off);
             im += __shfl_down(im, off);
@@ -421,19 +437,21 @@ __global__ __launch_bounds__(256) void k_ras_apply(const int64_t *__restrict__ e
 }
 
 template <typename T>
-void launch_ras_apply(int nc, const int64_t *ext_off, const int32_t *ext, const int32_t *own_off, const int32_t *own,
-                      const int64_t *m_off, const cx<T> *M, const cx<T> *x, cx<T> *y, int64_t ld, int nrhs,
-                      hipStream_t st) {
-    if (nc <= 0 || nrhs <= 0) return;
-    hipLaunchKernelGGL(k_ras_apply<T>, dim3(nc, nrhs), dim3(256), 0, st, ext_off, ext, own_off, own, m_off, M, x, y,
-                       ld);
+void launch_ras_apply(int nc, int max_own, const int64_t *ext_off, const int32_t *ext, const int32_t *own_off,
+                      const int32_t *own, const int64_t *m_off, const cx<T> *M, const cx<T> *x, cx<T> *y, int64_t ld,
+                      int nrhs, hipStream_t st) {
+    if (nc <= 0 || nrhs <= 0 || max_own <= 0) return;
+    SIE_CHECK(nrhs <= 65535, SIE_EINVAL, "too many right-hand sides for one preconditioner launch");
+    const dim3 grid((unsigned)nc, (unsigned)((max_own + kRasRows - 1) / kRasRows), (unsigned)nrhs);
+    hipLaunchKernelGGL(k_ras_apply<T>, grid, dim3(256), 0, st, ext_off, ext, own_off, own, m_off, M, x, y, ld);
     SIE_HIP(hipGetLastError());
 }
 
-template void launch_ras_apply<float>(int, const int64_t *, const int32_t *, const int32_t *, const int32_t *,
-                                      const int64_t *, const c64 *, const c64 *, c64 *, int64_t, int, hipStream_t);
-template void launch_ras_apply<double>(int, const int64_t *, const int32_t *, const int32_t *, const int32_t *,
-                                       const int64_t *, const c128 *, const c128 *, c128 *, int64_t, int,
-                                       hipStream_t);
+template void launch_ras_apply<float>(int, int, const int64_t *, const int32_t *, const int32_t *,
+                                      const int32_t *, const int64_t *, const c64 *, const c64 *, c64 *, int64_t,
+                                      int, hipStream_t);
+template void launch_ras_apply<double>(int, int, const int64_t *, const int32_t *, const int32_t *,
+                                       const int32_t *, const int64_t *, const c128 *, const c128 *, c128 *,
+                                       int64_t, int, hipStream_t);
 
 }  // namespace sie

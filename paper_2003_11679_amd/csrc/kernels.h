@@ -46,6 +46,10 @@ void launch_near_count(const int32_t *centre, int64_t ntg, const int32_t *cell_p
 void launch_near_emit(const int32_t *centre, int64_t ntg, const int32_t *cell_ptr, const int32_t *cell_tri,
                       const int lo[3], const int nl[3], int R, const int64_t *pair_ptr, int32_t *pair_s,
                       hipStream_t st);
+// 16-bit column offsets from each row's first column; *wide is set when a
+// row spans 65536 columns or more (the offsets are then unusable).
+void launch_cols16(int64_t nrow, const int64_t *row_ptr, const int32_t *cols, int32_t *row_base, uint16_t *cols16,
+                   int *wide, hipStream_t st);
 void launch_rwg_pattern(int64_t nrow, int64_t rwg0, int64_t nbits, const int32_t *rwg_loc, const int64_t *pair_ptr,
                         const int32_t *pair_s, const int32_t *tris, const int32_t *tri_rwg, int64_t *row_len,
                         const int64_t *row_ptr, int32_t *cols, int pass, hipStream_t st);

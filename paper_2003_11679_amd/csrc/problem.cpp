@@ -219,7 +219,20 @@ static void build_grid(sie_problem *p, Grid &g) {
         g.d_cols.alloc(std::max<int64_t>(g.nnz, 1));
         launch_rwg_pattern(nrow, g.rwg0, nrow, g.d_rwgloc.p, g.d_pair_ptr.p, g.d_pair_s.p, g.d_tris.p,
                            p->d_tri_rwg.p, nullptr, g.d_row_ptr.p, g.d_cols.p, 1, 0);
+        // 16-bit column offsets for the near-field products
+        g.d_row_base.alloc(std::max<int64_t>(nrow, 1));
+        g.d_cols16.alloc(std::max<int64_t>(g.nnz, 1));
+        DBuf<int> wide(1);
+        SIE_HIP(hipMemsetAsync(wide.p, 0, sizeof(int), 0));
+        launch_cols16(nrow, g.d_row_ptr.p, g.d_cols.p, g.d_row_base.p, g.d_cols16.p, wide.p, 0);
+        int w = 0;
+        SIE_HIP(hipMemcpyAsync(&w, wide.p, sizeof(int), hipMemcpyDeviceToHost, 0));
         SIE_HIP(hipStreamSynchronize(0));
+        g.cols16 = w == 0;
+        if (!g.cols16) {
+            g.d_cols16 = DBuf<uint16_t>();
+            g.d_row_base = DBuf<int32_t>();
+        }
     }
 }
 

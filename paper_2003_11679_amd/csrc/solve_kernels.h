@@ -19,7 +19,7 @@ void launch_ras_setup(int c0, int cnt, const int64_t *ext_off, const int32_t *ex
                       const int64_t *row_ptr, const int32_t *cols, const c128 *vals, c128 scale, c128 *ws,
                       c128 *m64, c64 *m32, int *fail, hipStream_t st);
 template <typename T>
-void launch_ras_apply(int nc, const int64_t *ext_off, const int32_t *ext, const int32_t *own_off, const int32_t *own,
-                      const int64_t *m_off, const cx<T> *M, const cx<T> *x, cx<T> *y, int64_t ld, int nrhs,
-                      hipStream_t st);
+void launch_ras_apply(int nc, int max_own, const int64_t *ext_off, const int32_t *ext, const int32_t *own_off,
+                      const int32_t *own, const int64_t *m_off, const cx<T> *M, const cx<T> *x, cx<T> *y, int64_t ld,
+                      int nrhs, hipStream_t st);
 }  // namespace sie

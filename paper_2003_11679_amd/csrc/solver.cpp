@@ -297,6 +297,7 @@ template <> const c64 *bj_inv<float>(const BlockJacobi &bj) { return bj.inv32.p;
 // C = 2 O; clusters shrink when an extended one would exceed kRasMax.
 struct Schwarz {
     int nc = 0;
+    int max_own = 0;               // largest owned set of one cluster
     bool covers_all = false;       // every RWG row is owned by some cluster
     int64_t owned = 0;
     DBuf<int64_t> ext_off, m_off;  // [nc + 1]
@@ -388,6 +389,7 @@ static void schwarz_build(sie_problem *p, Schwarz &sw, const std::vector<Medium 
     first.push_back((int)L.own_off.size() - 1);
     sw.nc = (int)L.own_off.size() - 1;
     sw.owned = (int64_t)L.own.size();
+    for (int c = 0; c < sw.nc; ++c) sw.max_own = std::max(sw.max_own, L.own_off[c + 1] - L.own_off[c]);
     sw.covers_all = sw.owned == total;
     if (sw.nc == 0) return;
     sw.ext_off.upload(L.ext_off);
@@ -542,7 +544,7 @@ struct Ops {
         }
         const Schwarz &w = s.sin;
         if (!w.covers_all) SIE_HIP(hipMemcpyAsync(y, x, NE * sizeof(cx<T>), hipMemcpyDeviceToDevice, st));
-        launch_ras_apply<T>(w.nc, w.ext_off.p, w.ext.p, w.own_off.p, w.own.p, w.m_off.p, ras_m<T>(w), x, y, E, nb, st);
+        launch_ras_apply<T>(w.nc, w.max_own, w.ext_off.p, w.ext.p, w.own_off.p, w.own.p, w.m_off.p, ras_m<T>(w), x, y, E, nb, st);
     }
     void prec_outer(const cx<T> *x, cx<T> *y) { bj(use_bj_out, s.pout, x, y); }
     // Mixed precision: an FP64 operator set may delegate the interior work
@@ -757,7 +759,7 @@ static void nested_precond_apply(sie_problem *p, SolveState &s, int precond, int
         const Schwarz &w = s.sin;
         if (!w.covers_all)
             SIE_HIP(hipMemcpyAsync(y, x, (size_t)nrhs * E * sizeof(cx<T>), hipMemcpyDeviceToDevice, st));
-        launch_ras_apply<T>(w.nc, w.ext_off.p, w.ext.p, w.own_off.p, w.own.p, w.m_off.p, ras_m<T>(w), x, y, E, nrhs,
+        launch_ras_apply<T>(w.nc, w.max_own, w.ext_off.p, w.ext.p, w.own_off.p, w.own.p, w.m_off.p, ras_m<T>(w), x, y, E, nrhs,
                             st);
     } else {
         for (int k = 0; k < nrhs; ++k)
