@@ -51,6 +51,28 @@ static const double PI = 3.14159265358979323846;
 // and convergence state.  A system that has converged (or stalled) in a
 // cycle stops extending its basis; its next basis vectors are zero, so the
 // shared products carry zeros for it.
+// Page-locked host buffer (device-to-host results read after one stream
+// synchronisation; host-to-device coefficients copied without staging).
+struct PinnedC128 {
+    c128 *p = nullptr;
+    size_t n = 0;
+    void alloc(size_t k) {
+        if (k <= n) return;
+        release();
+        SIE_HIP(hipHostMalloc((void **)&p, k * sizeof(c128), hipHostMallocDefault));
+        n = k;
+    }
+    void release() {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    PinnedC128() = default;
+    PinnedC128(const PinnedC128 &) = delete;
+    PinnedC128 &operator=(const PinnedC128 &) = delete;
+    ~PinnedC128() { release(); }
+};
+
 template <typename T>
 struct Gmres {
     int64_t n = 0;                  // length of one system
@@ -59,6 +81,9 @@ struct Gmres {
     int dblk = 1;                   // dot-product blocks per system
     DBuf<cx<T>> V, Zb, w, r;        // V: (m+1) x [nb][n], Zb: m x [nb][n], w, r: [nb][n]
     DBuf<c128> part, hd, cd;
+    PinnedC128 hh;                  // 3 slots of [nb][m + 1] dot results
+    PinnedC128 hc;                  // [nb] scaling coefficients
+    hipEvent_t hc_done = nullptr;   // last copy out of hc
     using Op = std::function<void(const cx<T> *, cx<T> *)>;
     const char *tag = "gmres";
     // Stagnation window: a system that gains under 1 % over this many
@@ -78,6 +103,23 @@ struct Gmres {
         part.alloc((size_t)nb * (m + 1) * dblk);
         hd.alloc((size_t)nb * (m + 1));
         cd.alloc(nb);
+        hh.alloc(3 * (size_t)nb * (m + 1));
+        hc.alloc(nb);
+        if (!hc_done) SIE_HIP(hipEventCreateWithFlags(&hc_done, hipEventDisableTiming));
+    }
+    Gmres() = default;
+    Gmres(const Gmres &) = delete;
+    Gmres &operator=(const Gmres &) = delete;
+    ~Gmres() {
+        if (hc_done) (void)hipEventDestroy(hc_done);
+    }
+    // Launches h[s][j] = V_j[s]^H x[s], j < J, and its copy into host slot
+    // `slot`; readable after the next synchronisation of st.
+    const c128 *dots_async(int J, const cx<T> *Vp, const cx<T> *x, int slot, hipStream_t st) {
+        launch_dots_sys<T>(n, J, Vp, (int64_t)nb * n, nb, x, part.p, dblk, hd.p, m + 1, st);
+        c128 *h = hh.p + (size_t)slot * nb * (m + 1);
+        SIE_HIP(hipMemcpyAsync(h, hd.p, (size_t)nb * (m + 1) * sizeof(c128), hipMemcpyDeviceToHost, st));
+        return h;
     }
     // h[s][j] = V_j[s]^H x[s], j < J (V_j at Vp + j * nb * n)
     std::vector<c128> dots(int J, const cx<T> *Vp, const cx<T> *x, hipStream_t st) {
@@ -94,7 +136,10 @@ struct Gmres {
         return out;
     }
     void scale(const std::vector<c128> &c, const cx<T> *x, cx<T> *y, hipStream_t st) {
-        SIE_HIP(hipMemcpyAsync(cd.p, c.data(), nb * sizeof(c128), hipMemcpyHostToDevice, st));
+        SIE_HIP(hipEventSynchronize(hc_done));     // hc no longer being copied
+        std::copy(c.begin(), c.end(), hc.p);
+        SIE_HIP(hipMemcpyAsync(cd.p, hc.p, nb * sizeof(c128), hipMemcpyHostToDevice, st));
+        SIE_HIP(hipEventRecord(hc_done, st));
         launch_scale_sys<T>(n, nb, cd.p, x, y, st);
     }
 
@@ -152,18 +197,25 @@ struct Gmres {
                 M(vj, zj);
                 A(zj, w.p);
                 if (napply) ++*napply;
-                // classical Gram-Schmidt, twice
-                std::vector<c128> h = dots(j + 1, V.p, w.p, st);
+                // classical Gram-Schmidt, twice (the projections use the
+                // device copies of the coefficients; the host reads all
+                // three results after one synchronisation)
+                const c128 *hp1 = dots_async(j + 1, V.p, w.p, 0, st);
                 launch_gemv_sys<T>(n, j + 1, V.p, blk, nb, hd.p, m + 1, w.p, false, st);
-                std::vector<c128> h2 = dots(j + 1, V.p, w.p, st);
+                const c128 *hp2 = dots_async(j + 1, V.p, w.p, 1, st);
                 launch_gemv_sys<T>(n, j + 1, V.p, blk, nb, hd.p, m + 1, w.p, false, st);
-                const std::vector<double> hn = norms(w.p, st);
+                const c128 *hp3 = dots_async(1, w.p, w.p, 2, st);
+                SIE_HIP(hipStreamSynchronize(st));
+                std::vector<c128> h(hp1, hp1 + (size_t)nb * (m + 1));
+                const c128 *h2 = hp2;
+                std::vector<double> hn(nb);
+                for (int k = 0; k < nb; ++k) hn[k] = std::sqrt(std::max(0.0, hp3[(size_t)k * (m + 1)].re));
                 std::vector<c128> cn(nb);
                 bool any = false;
                 for (int k = 0; k < nb; ++k) {
                     if (!act[k]) continue;
                     c128 *hk = h.data() + (size_t)k * (m + 1);
-                    const c128 *h2k = h2.data() + (size_t)k * (m + 1);
+                    const c128 *h2k = h2 + (size_t)k * (m + 1);
                     for (int i = 0; i <= j; ++i) hk[i] += h2k[i];
                     c128 *gk = g.data() + (size_t)k * (m + 1);
                     double *csk = cs.data() + (size_t)k * m;
