@@ -285,18 +285,24 @@ def serve_workload(args):
         tickets.append(srv.submit(p, (0.0, 0.0, -1.0), (1.0, 0.0, 0.0), prec, tol=args.tol, restart=100,
                                   precond=args.precond, max_iter=args.max_iter,
                                   inner_max_iter=args.inner_max_iter))
-    infos = []
-    for t in tickets:
-        while True:
-            i = srv.poll(t)
+    # requests are reported as they start and as they finish (completion order)
+    infos = [None] * len(tickets)
+    started = [False] * len(tickets)
+    left = set(range(len(tickets)))
+    while left:
+        for q in sorted(left):
+            i = srv.poll(tickets[q])
+            if i["running"] and not started[q]:
+                started[q] = True
+                print(f"[bench] request {q + 1}: started", file=sys.stderr, flush=True)
             if i["done"]:
-                break
-            time.sleep(0.005)
-        infos.append(i)
-        print(f"[bench] request {len(infos)}: status {i['status']} latency "
-              f"{i['t_end_s'] - i['t_submit_s']:.2f}s run {i['t_end_s'] - i['t_start_s']:.2f}s "
-              f"{i['report']}", file=sys.stderr, flush=True)
-        srv.take(t)
+                infos[q] = i
+                left.discard(q)
+                print(f"[bench] request {q + 1}: status {i['status']} latency "
+                      f"{i['t_end_s'] - i['t_submit_s']:.2f}s run {i['t_end_s'] - i['t_start_s']:.2f}s "
+                      f"{i['report']}", file=sys.stderr, flush=True)
+                srv.take(tickets[q])
+        time.sleep(0.005)
     T = time.perf_counter() - t0
     srv.close()
     lat = [i["t_end_s"] - i["t_submit_s"] for i in infos]

@@ -84,7 +84,9 @@ typedef struct {
 typedef struct {
     double tol;          /* relative residual of the outer (GIBC) system, default 1e-6 */
     double inner_tol;    /* nested solve (eq. nest2) tolerance, default 1e-8 (FP64) */
-    int32_t restart;     /* GMRES restart length, default 100, at most 1000 */
+    int32_t restart;     /* GMRES restart length, default 100, at most 1000; the
+                            nested solves restart after max(restart,
+                            min(inner_max_iter, 300)) iterations */
     int32_t max_iter;    /* outer iteration cap, default 800 (Sec. V-A) */
     int32_t inner_max_iter; /* nested iteration cap, default 800 */
     int32_t max_refine;  /* FP64 refinement sweeps for SIE_FP32, default 10 */

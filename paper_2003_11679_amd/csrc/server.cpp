@@ -43,8 +43,9 @@ double now_s(std::chrono::steady_clock::time_point t0) {
 // Device bytes of one problem, estimated from its description: near-field
 // CSR of every medium (FP64 L, K and direct L, FP32 L and K, column index;
 // rows times an estimate of the RWG functions within the near region),
-// grid buffers and spectra, and the Krylov bases of the solve.
-size_t estimate_footprint(const sie_problem *p, int restart) {
+// grid buffers and spectra, and the Krylov bases of the solve (outer
+// dimension `restart`, nested max(restart, min(inner_max_iter, 300))).
+size_t estimate_footprint(const sie_problem *p, int restart, int inner_max_iter) {
     int64_t T = 0;
     for (const auto &o : p->objs) T += (int64_t)o.tri.size() / 3;
     const double E = 1.5 * (double)T;
@@ -65,7 +66,8 @@ size_t estimate_footprint(const sie_problem *p, int restart) {
         const double rows = p->objs.empty() ? 0.0 : 1.5 * (double)p->objs[i].tri.size() / 3.0;
         b += grid_bytes(p->obj_req[i].n, p->obj_req[i].R, rows);
     }
-    b += E * (2.0 * restart + 1.0) * (16.0 + 16.0 + 8.0);   // outer + nested bases (FP64, FP32 nested)
+    const int mi = std::max(restart, std::min(inner_max_iter, 300));
+    b += E * ((2.0 * restart + 1.0) + (2.0 * mi + 1.0)) * (16.0 + 8.0);   // outer and nested bases, FP64 + FP32
     b += E * 64.0 * 16.0;                                     // vectors of the solve
     return (size_t)b;
 }
@@ -159,7 +161,7 @@ sie_status sie_problem_footprint(const sie_problem *p, size_t *device_bytes) {
     return sguard([&] {
         SIE_CHECK(p && device_bytes, SIE_EINVAL, "NULL argument");
         SIE_CHECK(!p->objs.empty(), SIE_ESTATE, "no objects");
-        *device_bytes = estimate_footprint(p, 100);
+        *device_bytes = estimate_footprint(p, 100, 800);
     });
 }
 
@@ -196,7 +198,8 @@ sie_status sie_server_submit(sie_server *s, sie_problem *p, int32_t nrhs, const 
         j->e0.assign(e0, e0 + 3 * (size_t)nrhs);
         j->prec = prec;
         if (opts) { j->opts = *opts; j->has_opts = true; }
-        j->info.footprint = estimate_footprint(p, opts && opts->restart > 0 ? opts->restart : 100);
+        j->info.footprint = estimate_footprint(p, opts && opts->restart > 0 ? opts->restart : 100,
+                                               opts && opts->inner_max_iter > 0 ? opts->inner_max_iter : 800);
         j->info.status = SIE_OK;
         {
             std::lock_guard<std::mutex> lk(s->mu);

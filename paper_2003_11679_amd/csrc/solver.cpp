@@ -518,6 +518,13 @@ template <typename T> static Gmres<T> &inner_of(SolveState &s);
 template <> Gmres<double> &inner_of<double>(SolveState &s) { return s.gi64; }
 template <> Gmres<float> &inner_of<float>(SolveState &s) { return s.gi32; }
 
+// Krylov dimension of the nested solves: the interior EFIE of a low-loss
+// dielectric on a fine mesh needs a few hundred iterations, which restarts
+// every `restart` iterations would multiply; restart only beyond 300.
+static int nested_dim(int restart, int inner_max_iter) {
+    return std::max(restart, std::min(inner_max_iter, 300));
+}
+
 // Operator set for nb right-hand sides at once: every vector is [nb][E].
 template <typename T>
 struct Ops {
@@ -540,7 +547,7 @@ struct Ops {
             if (tb[i].n != (size_t)NE) tb[i].alloc(NE);
             t[i] = tb[i].p;
         }
-        inner_of<T>(s).init(E, nb, restart);
+        inner_of<T>(s).init(E, nb, nested_dim(restart, imax));
         outer_of<T>(s).init(E, nb, restart);
         inner_of<T>(s).tag = sizeof(T) == 8 ? "inner64" : "inner32";
         outer_of<T>(s).tag = sizeof(T) == 8 ? "outer64" : "outer32";
@@ -704,9 +711,10 @@ static void solve_all(sie_problem *p, sie_precision prec, const sie_solver_opts 
     bool all_conv = true;
     const auto t0 = std::chrono::steady_clock::now();
     // right-hand sides per batch: all of them, unless the Krylov bases
-    // (2 restart + 1 vectors per level, FP64 outer + nested, FP32 nested)
-    // would exceed the budget
-    const double per_rhs = (double)E * (2.0 * o.restart + 1.0) * (16.0 + 16.0 + 8.0);
+    // (2 m + 1 vectors per level: FP64 and FP32 outer with m = restart, FP64
+    // and FP32 nested with the nested dimension) would exceed the budget
+    const int mi = nested_dim(o.restart, o.inner_max_iter);
+    const double per_rhs = (double)E * ((2.0 * o.restart + 1.0) * (16.0 + 8.0) + (2.0 * mi + 1.0) * (16.0 + 8.0));
     const int nb = (int)std::max(1.0, std::min((double)s.nrhs, std::floor(kKrylovBudget / per_rhs)));
     for (int r0 = 0; r0 < s.nrhs; r0 += nb) {
         const int cnt = std::min(nb, s.nrhs - r0);
