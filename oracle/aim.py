@@ -115,7 +115,7 @@ def grad_green_grid(k, h, d):
 class AIMOperator:
     """AIM approximations of A, Phi and K at one wavenumber on one grid."""
 
-    def __init__(self, mesh, grid, k, near_radius=5, tris=None, rules=None, g0=0.0):
+    def __init__(self, mesh, grid, k, near_radius=5, tris=None, rules=None, g0=0.0, near=True):
         self.mesh, self.grid, self.k, self.R = mesh, grid, complex(k), int(near_radius)
         self.g0 = g0                      # grid G at zero offset (result must not depend on it)
         T = len(mesh.tri)
@@ -126,8 +126,10 @@ class AIMOperator:
         self.nodes = node_index(grid, self.centres)
         if np.any(self.nodes < 0) or np.any(self.nodes >= grid.n):
             raise ValueError("stencil outside grid")
-        self.near_t, self.near_s = self.near_pairs()
-        self._near_matrices(rules)
+        self.rules = rules
+        if near:        # near=False: grid stages only (near rows on demand, near_rows)
+            self.near_t, self.near_s = self.near_pairs()
+            self._near_matrices(rules)
 
     # -- near region -------------------------------------------------------
     def near_pairs(self):
@@ -135,6 +137,44 @@ class AIMOperator:
         d = np.abs(c[:, None, :] - c[None, :, :]).max(axis=2)
         ti, si = np.nonzero(d <= self.R)
         return self.tris[ti], self.tris[si]
+
+    def near_rows(self, rows):
+        """Precorrected near-region L and K (and direct L) of the given RWG rows
+        only, for meshes too large for the full near matrices: for each row,
+        its two triangles against every triangle of the grid within the near
+        radius.  Returns {row: (cols ascending, L, K, L direct)}."""
+        m = self.mesh
+        k2 = self.k * self.k
+        tset = np.unique(np.concatenate([m.tp[rows], m.tm[rows]]))
+        c = self.centres
+        tl, sl = [], []
+        for t in tset:
+            d = np.abs(c[self.tris] - c[t]).max(axis=1)
+            ss = self.tris[d <= self.R]
+            tl.append(np.full(len(ss), t)); sl.append(ss)
+        tl = np.concatenate(tl); sl = np.concatenate(sl)
+        Ad, Pd, Kd = pair_blocks(m, self.k, tl, sl, self.rules)
+        Ag = np.empty_like(Ad); Pg = np.empty_like(Pd); Kg = np.empty_like(Kd)
+        for c0 in range(0, len(tl), 2000):
+            Ag[c0:c0 + 2000], Pg[c0:c0 + 2000], Kg[c0:c0 + 2000] = self.grid_blocks(tl[c0:c0 + 2000],
+                                                                                 sl[c0:c0 + 2000])
+        Lp = (Ad - Ag) - (Pd - Pg) / k2
+        Kp = Kd - Kg
+        Ld = Ad - Pd / k2
+        out = {}
+        for r in rows:
+            acc = {}
+            for t, e in ((m.tp[r], m.ep[r]), (m.tm[r], m.em[r])):
+                sel = np.nonzero(tl == t)[0]
+                for pi in sel:
+                    for f in range(3):
+                        n = m.tri_rwg[sl[pi], f]
+                        a = acc.setdefault(n, np.zeros(3, np.complex128))
+                        a += (Lp[pi, e, f], Kp[pi, e, f], Ld[pi, e, f])
+            cols = np.array(sorted(acc))
+            vals = np.array([acc[n] for n in cols])
+            out[int(r)] = (cols, vals[:, 0], vals[:, 1], vals[:, 2])
+        return out
 
     def _offset_tables(self):
         """G and grad G on all node offsets a near pair can produce."""
@@ -219,7 +259,13 @@ class AIMOperator:
 
     def kernel_fft(self, kind):
         """Circulant embedding (2N per axis) of G or dG/dx_c on the offsets
-        -(N-1)..(N-1), transformed: [2Nz, 2Ny, 2Nx]."""
+        -(N-1)..(N-1), transformed: [2Nz, 2Ny, 2Nx] (kept per kind)."""
+        cache = self.__dict__.setdefault("_kfft", {})
+        if kind not in cache:
+            cache[kind] = self._kernel_fft(kind)
+        return cache[kind]
+
+    def _kernel_fft(self, kind):
         n = self.grid.n
         m = 2 * n
         ax = [np.concatenate([np.arange(0, n[i]), [0], np.arange(-(n[i] - 1), 0)]) for i in range(3)]

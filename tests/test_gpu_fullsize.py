@@ -1,0 +1,220 @@
+"""Parity at the full sizes of the two large configurations, in the launch
+configuration the bench times (default quadrature, FP64 and FP32 products):
+
+* copper bar, 20,088 triangles, 64^3 grid, near radius 5;
+* 8 x 8 array of lossy cubes, 196,608 triangles, 256^3 exterior grid and one
+  16^3 grid per cube.
+
+Checked against the oracle: every triangle's stencil centre (bit-exact); the
+near-field rows (pattern and FP64 L, K values) of a seeded sample of rows,
+integrated by the oracle for those rows only; for the bar, the whole FP64 L
+and K products on the sampled rows (the oracle's near rows plus its own
+projection, FFT convolution and interpolation on the full grid).  For the
+cube array, whose 512^3 convolution the oracle does not run here, the full
+products are checked for reciprocity (x^T L y = y^T L x, W = P^T and a
+symmetric G) and FP32 against FP64."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+# the library's default quadrature orders
+DEFAULT_QUAD = dict(touch_out=6, touch_in=6, close_out=5, close_in=5, far_out=3, far_in=3)
+
+
+def _problem(cfg):
+    from paper_2003_11679_amd import Problem
+    p = Problem(cfg.freq)
+    for ob in cfg.objects:
+        p.add_object(ob.xyz, ob.tri, eps_r=ob.eps_r, sigma=ob.sigma)
+    p.set_grid(-1, n=cfg.ext_grid_n, near_radius=cfg.near_radius)
+    if not cfg.shared_grid:
+        for i, ob in enumerate(cfg.objects):
+            p.set_grid(i, n=ob.grid_n, near_radius=cfg.near_radius)
+    p.setup()
+    return p
+
+
+def _mesh(cfg):
+    from oracle.rwg import RWGMesh
+    return RWGMesh([(ob.xyz, ob.tri) for ob in cfg.objects])
+
+
+@pytest.fixture(scope="module")
+def bar():
+    from workloads import bar_cfg
+    print("[fullsize bar]", flush=True)
+    cfg = bar_cfg()
+    return cfg, _problem(cfg), _mesh(cfg)
+
+
+@pytest.fixture(scope="module")
+def cubes():
+    from workloads import cube_array_cfg
+    print("[fullsize cube array]", flush=True)
+    cfg = cube_array_cfg()
+    return cfg, _problem(cfg), _mesh(cfg)
+
+
+def _oracle(cfg, m, medium):
+    from oracle.aim import Grid, AIMOperator
+    from oracle import physics as ph
+    if medium == -1:
+        grid = Grid.enclosing(m.xyz, cfg.ext_grid_n)
+        return AIMOperator(m, grid, ph.wavenumber(cfg.freq, 1.0), near_radius=cfg.near_radius,
+                           rules=DEFAULT_QUAD, near=False)
+    ob = cfg.objects[medium]
+    k = ph.wavenumber(cfg.freq, ob.eps_r, 1.0, ob.sigma)
+    if cfg.shared_grid:
+        grid = Grid.enclosing(m.xyz, cfg.ext_grid_n)
+        tris = None
+    else:
+        grid = Grid.enclosing(np.asarray(ob.xyz, float), ob.grid_n)
+        tris = np.nonzero(m.tri_obj == medium)[0]
+    return AIMOperator(m, grid, k, near_radius=cfg.near_radius, tris=tris, rules=DEFAULT_QUAD, near=False)
+
+
+def _check_rows(p, op, medium, rows):
+    rp, cols = p.near_pattern(medium)
+    vL = p.near_values(medium, 0)
+    vK = p.near_values(medium, 1)
+    ref = op.near_rows(rows)
+    # errors relative to the largest value over the sampled rows (K rows of
+    # coplanar neighbourhoods are zero up to rounding)
+    eL = eK = sL = sK = 0.0
+    for r in rows:                     # row_ptr is global: empty outside the medium
+        c, lv, kv, _ = ref[int(r)]
+        a, b = rp[r], rp[r + 1]
+        assert np.array_equal(cols[a:b], c), r
+        eL = max(eL, np.abs(vL[a:b] - lv).max()); sL = max(sL, np.abs(lv).max())
+        eK = max(eK, np.abs(vK[a:b] - kv).max()); sK = max(sK, np.abs(kv).max())
+    assert eL < 1e-10 * sL, eL / sL
+    assert eK < 1e-10 * sK, eK / sK
+
+
+def test_bar_stencils_bit_exact(bar):
+    cfg, p, m = bar
+    from oracle.aim import Grid, stencil_centres
+    g = Grid.enclosing(m.xyz, cfg.ext_grid_n)
+    gg = p.grid(-1)
+    assert np.array_equal(gg["origin"], g.origin) and gg["h"] == g.h
+    assert np.array_equal(p.stencils(-1), stencil_centres(g, m.centroid))
+
+
+@pytest.mark.parametrize("medium", [-1, 0])
+def test_bar_near_rows(bar, medium):
+    cfg, p, m = bar
+    rows = np.sort(np.random.default_rng(11690 + medium).choice(m.nrwg, size=12, replace=False))
+    _check_rows(p, _oracle(cfg, m, medium), medium, rows)
+
+
+@pytest.mark.parametrize("medium", [-1, 0])
+def test_bar_products_on_sampled_rows(bar, medium):
+    """Whole FP64 products of the full bar on sampled rows: near rows plus the
+    oracle's grid stages on the full 64^3 grid."""
+    cfg, p, m = bar
+    op = _oracle(cfg, m, medium)
+    rng = np.random.default_rng(11691)
+    x = rng.standard_normal(m.nrwg) + 1j * rng.standard_normal(m.nrwg)
+    rows = np.sort(rng.choice(m.nrwg, size=12, replace=False))
+    near = op.near_rows(rows)
+    xd = torch.from_numpy(x).to("cuda")
+    far_L = op.far_part(x, "A") - op.far_part(x, "P") / op.k ** 2
+    far_K = op.far_part(x, "K")
+    for code, far, j in ((0, far_L, 1), (1, far_K, 2)):
+        y = p.matvec(medium, code, xd).cpu().numpy()
+        ref = np.array([near[int(r)][j] @ x[near[int(r)][0]] for r in rows]) + far[rows]
+        err = np.abs(y[rows] - ref).max() / np.abs(ref).max()
+        assert err < 1e-9, (code, err)
+
+
+def test_cube_array_stencils_and_interior_grids(cubes):
+    cfg, p, m = cubes
+    from oracle.aim import Grid, stencil_centres
+    g = Grid.enclosing(m.xyz, cfg.ext_grid_n)
+    gg = p.grid(-1)
+    assert np.array_equal(gg["origin"], g.origin) and gg["h"] == g.h
+    assert np.array_equal(p.stencils(-1), stencil_centres(g, m.centroid))
+    for i in (0, 27, 63):
+        ob = cfg.objects[i]
+        gi = Grid.enclosing(np.asarray(ob.xyz, float), ob.grid_n)
+        pg = p.grid(i)
+        assert np.array_equal(pg["origin"], gi.origin) and pg["h"] == gi.h, i
+        tri = np.nonzero(m.tri_obj == i)[0]
+        assert np.array_equal(p.stencils(i), stencil_centres(gi, m.centroid[tri])), i
+
+
+@pytest.mark.parametrize("medium", [-1, 0, 63])
+def test_cube_array_near_rows(cubes, medium):
+    cfg, p, m = cubes
+    if medium == -1:
+        pool = np.arange(m.nrwg)
+    else:
+        pool = np.arange(*m.obj_rwg_range(medium))
+    rows = np.sort(np.random.default_rng(11692 + medium).choice(pool, size=8, replace=False))
+    _check_rows(p, _oracle(cfg, m, medium), medium, rows)
+
+
+@pytest.mark.parametrize("medium", [-1, 5])
+def test_cube_array_reciprocity_and_fp32(cubes, medium):
+    cfg, p, m = cubes
+    rng = np.random.default_rng(11693)
+    x = torch.from_numpy(rng.standard_normal(m.nrwg) + 1j * rng.standard_normal(m.nrwg)).to("cuda")
+    y = torch.from_numpy(rng.standard_normal(m.nrwg) + 1j * rng.standard_normal(m.nrwg)).to("cuda")
+    for code, tol in ((0, 1e-5), (1, 1e-3)):
+        Lx = p.matvec(medium, code, x)
+        Ly = p.matvec(medium, code, y)
+        a = torch.dot(y, Lx).item()
+        b = torch.dot(x, Ly).item()
+        assert abs(a - b) < tol * abs(a), (code, abs(a - b) / abs(a))
+        L32 = p.matvec(medium, code, x.to(torch.complex64)).to(torch.complex128)
+        e32 = (torch.linalg.norm(L32 - Lx) / torch.linalg.norm(Lx)).item()
+        assert e32 < 2e-6, (code, e32)
+
+
+def test_sphere_config_solve():
+    """The 1,280-triangle dielectric sphere (eps_r = 4, 150 MHz, 16^3 grid,
+    near radius 5) solved in FP64 to 1e-6: the solution satisfies the oracle's
+    AIM block system, and its bistatic RCS follows the Mie series (the dense
+    method of moments on this mesh is 2.1 % from Mie)."""
+    from workloads import sphere_cfg
+    from oracle import physics as ph, mie
+    from oracle.aim import Grid, AIMOperator
+    from oracle.mom import excitation, x_matrix
+    from oracle.farfield import directions
+    cfg = sphere_cfg()
+    print("[fullsize sphere]", flush=True)
+    p = _problem(cfg)
+    wave = cfg.waves[0]
+    p.set_planewaves(wave.khat, wave.e0)
+    rep = p.solve(0, tol=1e-6, restart=200)
+    print(f"  {rep}", flush=True)
+    assert rep["converged"] and rep["residual"] <= 1e-6, rep
+    u, v = p.currents()
+    m = _mesh(cfg)
+    ob = cfg.objects[0]
+    g = Grid.enclosing(m.xyz, cfg.ext_grid_n)
+    ext = AIMOperator(m, g, ph.wavenumber(cfg.freq, 1.0), near_radius=cfg.near_radius, rules=DEFAULT_QUAD)
+    inn = AIMOperator(m, g, ph.wavenumber(cfg.freq, ob.eps_r, 1.0, ob.sigma), near_radius=cfg.near_radius,
+                      rules=DEFAULT_QUAD)
+    w = ph.omega(cfg.freq)
+    X = x_matrix(m)
+    e = excitation(m, ph.wavenumber(cfg.freq, 1.0), wave.khat, wave.e0)
+    r1 = e - (1j * w * ph.MU0 * ext.matvec(u, "L") - (ext.matvec(v, "K") - 0.5 * X @ v))
+    et = ph.eps_tilde(cfg.freq, ob.eps_r, ob.sigma)
+    r2 = -(-(inn.matvec(u, "K") + 0.5 * X @ u) - 1j * w * et * inn.matvec(v, "L"))
+    rel = np.sqrt(np.linalg.norm(r1) ** 2 + np.linalg.norm(r2) ** 2) / np.linalg.norm(e)
+    assert rel < 1e-5, rel
+    k0 = ph.wavenumber(cfg.freq, 1.0)
+    th = np.linspace(0.02, np.pi - 0.02, 41)
+    err2 = ref2 = 0.0
+    for phi in (0.0, np.pi / 2):
+        F = p.far_field(directions(th, phi + 0 * th))
+        r = 4 * np.pi * np.sum(np.abs(F) ** 2, axis=1)
+        mr = mie.bistatic_rcs(k0, 1.0, ob.eps_r, th, phi + 0 * th)
+        err2 += np.sum((r - mr) ** 2); ref2 += np.sum(mr ** 2)
+    err = np.sqrt(err2 / ref2)
+    print(f"  rcs vs Mie {err:.3e}, oracle AIM block residual {rel:.2e}", flush=True)
+    assert err < 0.05, err

@@ -142,3 +142,24 @@ def test_direct_near_region_pattern_and_symmetry(sphere2):
     assert np.abs(N - N.T).max() < 1e-6 * np.abs(N).max()
     L = dense["L"]
     assert np.abs(N[all_near] - L[all_near]).max() < 1e-12 * np.abs(L).max()
+
+
+def test_near_rows_equal_full_near_matrices():
+    """Row-sampled near values (for meshes too large for the full matrices)
+    reproduce the rows of the full near-region matrices."""
+    m = RWGMesh([icosphere(2)])
+    g = Grid.enclosing(m.xyz, 10)
+    full = AIMOperator(m, g, K_TEST, near_radius=2)
+    part = AIMOperator(m, g, K_TEST, near_radius=2, near=False)
+    rows = np.random.default_rng(5).choice(m.nrwg, size=12, replace=False)
+    got = part.near_rows(rows)
+    L = full.near_L().tocsr(); K = full.NK.tocsr(); Ld = full.NLd.tocsr()
+    for r in rows:
+        cols, lv, kv, ldv = got[int(r)]
+        for M, v in ((L, lv), (K, kv), (Ld, ldv)):
+            row = M.getrow(r)
+            row.sort_indices()
+            nz = np.abs(row.toarray()[0]) > 0
+            assert set(np.nonzero(nz)[0]) <= set(cols)
+            assert np.abs(row.toarray()[0][cols] - v).max() <= 1e-14 * np.abs(M.data).max()
+        assert np.array_equal(cols, np.sort(L.getrow(r).indices))
