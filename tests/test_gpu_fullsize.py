@@ -218,3 +218,37 @@ def test_sphere_config_solve():
     err = np.sqrt(err2 / ref2)
     print(f"  rcs vs Mie {err:.3e}, oracle AIM block residual {rel:.2e}", flush=True)
     assert err < 0.05, err
+
+
+@pytest.mark.parametrize("which", ["sphere5120", "bar4824"])
+def test_batching_config_products(which):
+    """Batching configuration meshes (sphere of 5,120 triangles at 150 MHz,
+    eps_r 2.5, sigma 0.1 S/m; copper bar of 4,824 triangles at 10 GHz), grid by
+    the mean-edge rule: the 64-RHS batched products (SpMM near field, batched
+    grid stages) equal 64 single products, L and K, exterior and interior."""
+    from workloads.configs import batching_meshes
+    from paper_2003_11679_amd import Problem
+    spheres, bars = batching_meshes()
+    xyz, tri = dict(spheres + bars)[which]
+    freq, eps_r, sigma = (150e6, 2.5, 0.1) if which.startswith("sphere") else (10e9, 1.0, 5.8e7)
+    ext = float(np.max(xyz.max(0) - xyz.min(0)))
+    edge = float(np.mean(np.linalg.norm(xyz[tri[:, 1]] - xyz[tri[:, 0]], axis=1)))
+    n = 8
+    while ext / (n - 3) > edge and n < 256:
+        n *= 2
+    print(f"[batching {which}] grid {n}", flush=True)
+    p = Problem(freq)
+    p.add_object(xyz, tri, eps_r=eps_r, sigma=sigma)
+    p.set_grid(-1, n=n, near_radius=5)
+    p.setup()
+    E = p.num_rwg
+    rng = np.random.default_rng(11694)
+    X = rng.standard_normal((64, E)) + 1j * rng.standard_normal((64, E))
+    for medium in (-1, 0):
+        for code in (0, 1):
+            for dtype, tol in ((torch.complex128, 1e-12), (torch.complex64, 2e-5)):
+                xd = torch.from_numpy(X).to("cuda", dtype)
+                got = p.matvec(medium, code, xd).cpu().numpy()
+                ref = np.stack([p.matvec(medium, code, xd[r]).cpu().numpy() for r in range(64)])
+                err = np.abs(got - ref).max() / np.abs(ref).max()
+                assert err < tol, (medium, code, dtype, err)
