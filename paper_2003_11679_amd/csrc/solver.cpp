@@ -35,6 +35,7 @@
 #include <functional>
 #include <map>
 #include <numeric>
+#include <type_traits>
 #include <unordered_map>
 
 #include "problem.h"
@@ -626,13 +627,35 @@ struct Ops {
         inner_solve_native(t[0], v);
     }
     // y = j w mu0 L0 u - (K0 - X/2) Z u
+    void gibc_mixed(const cx<T> *u, cx<T> *y);
     void gibc(const cx<T> *u, cx<T> *y) {
+        if constexpr (std::is_same<T, double>::value) {
+            if (lo) {
+                gibc_mixed(u, y);
+                return;
+            }
+        }
         Z(u, t[1]);
         KpX(false, -1.0, t[1], t[2]);
         mv(p->ext, SIE_OP_L, u, y);
         launch_axpby<T>(NE, c128(-1.0), t[2], c128(0.0, p->w) * p->ext.mu, y, st);
     }
 };
+
+// Mixed precision: v = Z u comes out of the FP32 nested solve, and
+// (K0 - X/2) v is applied to it in FP32 as well (K0 has no cancellation
+// between terms of different order in k0 h); j w mu0 L0 u stays FP64 (its
+// vector potential is ~(k0 h)^2 below its scalar potential at low frequency).
+template <> void Ops<float>::gibc_mixed(const c64 *, c64 *) {}
+template <> void Ops<double>::gibc_mixed(const c128 *u, c128 *y) {
+    c64 *u32 = lo->t[1], *v32 = lo->t[2], *k32 = lo->t[3];
+    launch_convert<double, float>(u, u32, NE, st);
+    lo->Z_native(u32, v32);
+    lo->KpX(false, -1.0, v32, k32);
+    launch_convert<float, double>(k32, t[2], NE, st);
+    mv(p->ext, SIE_OP_L, u, y);
+    launch_axpby<double>(NE, c128(-1.0), t[2], c128(0.0, p->w) * p->ext.mu, y, st);
+}
 
 template <> void Ops<float>::inner_solve(const c64 *a, c64 *v) { inner_solve_native(a, v); }
 template <> void Ops<float>::Z(const c64 *u, c64 *v) { Z_native(u, v); }
