@@ -147,8 +147,14 @@ struct Gmres {
     // Solves A x = b for the nb systems (x holds the initial guesses), each
     // to its own relative tolerance tol[k].  Returns the iterations of the
     // longest system; relres[k] receives the final relative residuals.
+    // x_zero: the guesses are zero (the first residual is b, no product).
+    // trust_estimate: return when every system's Arnoldi residual estimate
+    // meets its tolerance (or it stagnated) instead of confirming it with a
+    // true residual; for solves inside an outer iteration whose own residual
+    // is checked.
     int solve(const Op &A, const Op &M, const cx<T> *b, cx<T> *x, const std::vector<double> &tol, int maxit,
-              std::vector<double> *relres, hipStream_t st, int *napply = nullptr) {
+              std::vector<double> *relres, hipStream_t st, int *napply = nullptr, bool x_zero = false,
+              bool trust_estimate = false) {
         static const bool trace = std::getenv("SIE_TRACE") != nullptr;
         const std::vector<double> bn = norms(b, st);
         std::vector<char> fin(nb, 0);
@@ -167,11 +173,17 @@ struct Gmres {
         std::vector<std::vector<double>> hist(nb);
         std::vector<char> stag(nb, 0);
         int it = 0;
+        bool first = true;
         while (true) {
             // r = b - A x
-            A(x, r.p);
-            if (napply) ++*napply;
-            launch_axpby<T>((int64_t)nb * n, c128(1.0), b, c128(-1.0), r.p, st);
+            if (first && x_zero) {
+                SIE_HIP(hipMemcpyAsync(r.p, b, (size_t)nb * n * sizeof(cx<T>), hipMemcpyDeviceToDevice, st));
+            } else {
+                A(x, r.p);
+                if (napply) ++*napply;
+                launch_axpby<T>((int64_t)nb * n, c128(1.0), b, c128(-1.0), r.p, st);
+            }
+            first = false;
             const std::vector<double> beta = norms(r.p, st);
             bool all = true;
             for (int k = 0; k < nb; ++k) {
@@ -275,6 +287,15 @@ struct Gmres {
             if (kmax > 0) {
                 SIE_HIP(hipMemcpyAsync(hd.p, y.data(), y.size() * sizeof(c128), hipMemcpyHostToDevice, st));
                 launch_gemv_sys<T>(n, kmax, Zb.p, blk, nb, hd.p, m + 1, x, true, st);
+            }
+            if (trust_estimate) {
+                bool done = true;
+                for (int k = 0; k < nb; ++k)
+                    if (!fin[k] && !(res[k] <= tol[k] || stag[k])) done = false;
+                if (done || it >= maxit) {
+                    SIE_HIP(hipStreamSynchronize(st));   // y is host memory
+                    break;
+                }
             }
         }
         if (relres) *relres = res;
@@ -616,7 +637,8 @@ struct Ops {
         SIE_HIP(hipMemsetAsync(v, 0, NE * sizeof(cx<T>), st));
         int it = inner_of<T>(s).solve([&](const cx<T> *x, cx<T> *y) { Lhat(x, y); },
                                       [&](const cx<T> *x, cx<T> *y) { prec_inner(x, y); }, a, v,
-                                      std::vector<double>(nb, inner_tol), inner_max_iter, nullptr, st);
+                                      std::vector<double>(nb, inner_tol), inner_max_iter, nullptr, st, nullptr,
+                                      true, true);
         s.inner_iters += it;
         s.inner_max = std::max(s.inner_max, it);
     }
