@@ -476,11 +476,17 @@ __device__ void fill_pair(const NearFillArgs &a, int64_t tl, int64_t sl, int64_t
     const double h = a.h;
     c128 S00, S11, C11;
     CV3 S10 = {}, S01 = {}, Vs = {}, Vt = {}, U = {};
+    // The sums over node pairs factor through the source node b: for each b
+    // the test-node sums Gb0 = sum_a m0t G, Gb1 = sum_a m1t G,
+    // gb0 = sum_a m0t g and gb1x = sum_a g x m1t, then
+    //   S00 += m0s Gb0, S01 += m1s Gb0, S10 += m0s Gb1, S11 += m1s . Gb1,
+    //   U += m0s gb0, Vs += gb0 x m1s, Vt -= m0s gb1x, C11 -= m1s . gb1x
+    // (g . (m1s x m1t) = -m1s . (g x m1t)).
     const double *ms = a.mom + sl * 27 * 4;
     for (int ib = 0; ib < 27; ++ib) {
         const int bx = ib % 3 - 1, by = (ib / 3) % 3 - 1, bz = ib / 9 - 1;
-        const double m0s = ms[4 * ib];
-        const V3 m1s = {ms[4 * ib + 1], ms[4 * ib + 2], ms[4 * ib + 3]};
+        c128 Gb0;
+        CV3 Gb1 = {}, gb0 = {}, gb1x = {};
         for (int ia = 0; ia < 27; ++ia) {
             const int ddx = dx0 + ia % 3 - 1 - bx, ddy = dy0 + (ia / 3) % 3 - 1 - by, ddz = dz0 + ia / 9 - 1 - bz;
             const int q = ddx * ddx + ddy * ddy + ddz * ddz;
@@ -489,18 +495,21 @@ __device__ void fill_pair(const NearFillArgs &a, int64_t tl, int64_t sl, int64_t
             const CV3 g = {(h * ddx) * sr, (h * ddy) * sr, (h * ddz) * sr};
             const double m0t = mt[4 * ia];
             const V3 m1t = {mt[4 * ia + 1], mt[4 * ia + 2], mt[4 * ia + 3]};
-            const double m00 = m0t * m0s;
-            S00 += m00 * G;
-            S11 += dot(m1t, m1s) * G;
-            cadd(S10, cscale(m0s * G, m1t));
-            cadd(S01, cscale(m0t * G, m1s));
-            C11 += cdot(cross(m1s, m1t), g);                  // g . (m1s x m1t)
-            const CV3 gxm1s = ccross_cv(g, m1s);              // m0t (g x m1s)
-            cadd(Vs, CV3{m0t * gxm1s.x, m0t * gxm1s.y, m0t * gxm1s.z});
-            const CV3 gxm1t = ccross_cv(g, m1t);              // m0s (m1t x g)
-            cadd(Vt, CV3{-m0s * gxm1t.x, -m0s * gxm1t.y, -m0s * gxm1t.z});
-            cadd(U, CV3{m00 * g.x, m00 * g.y, m00 * g.z});
+            Gb0 += m0t * G;
+            cadd(Gb1, cscale(G, m1t));
+            cadd(gb0, CV3{m0t * g.x, m0t * g.y, m0t * g.z});
+            cadd(gb1x, ccross_cv(g, m1t));
         }
+        const double m0s = ms[4 * ib];
+        const V3 m1s = {ms[4 * ib + 1], ms[4 * ib + 2], ms[4 * ib + 3]};
+        S00 += m0s * Gb0;
+        cadd(S01, cscale(Gb0, m1s));
+        cadd(S10, CV3{m0s * Gb1.x, m0s * Gb1.y, m0s * Gb1.z});
+        S11 += cdot(m1s, Gb1);
+        cadd(U, CV3{m0s * gb0.x, m0s * gb0.y, m0s * gb0.z});
+        cadd(Vs, ccross_cv(gb0, m1s));
+        cadd(Vt, CV3{-m0s * gb1x.x, -m0s * gb1x.y, -m0s * gb1x.z});
+        C11 += -cdot(m1s, gb1x);
     }
     const c128 ik2 = cdiv(c128(1.0), k * k);
     const double *ct = a.tri_coef + tl * 12;
