@@ -824,7 +824,7 @@ static void solve_all(sie_problem *p, sie_precision prec, const sie_solver_opts 
             }
             outer_total += g.solve([&](const c128 *x, c128 *y) { o64.gibc(x, y); },
                                    [&](const c128 *x, c128 *y) { o64.prec_outer(x, y); }, r1.p, du.p, stol,
-                                   o.max_iter, nullptr, st);
+                                   o.max_iter, nullptr, st, nullptr, true);
             // dv = Lhat^-1 (r2 + (K_i + X/2) du)
             o64.KpX(true, +1.0, du.p, o64.t[3]);
             launch_axpby<double>(NE, c128(1.0), r2.p, c128(1.0), o64.t[3], st);
