@@ -9,7 +9,7 @@ near lists, FP64 near-field integrals with precorrection, Green's spectra,
 plane-wave excitation, the nested GIBC solve (FP32 interior stages inside
 FP64 refinement to the relative FP64 block residual given by --tol, default
 1e-7; the nested solves preconditioned by the near-region operator in
-restricted additive Schwarz form, restart 200) and the far field.
+restricted additive Schwarz form, outer restart 1000) and the far field.
 The FP32 currents are compared with an FP64 solve of the same request during
 warmup (relative error gate 1e-3).  The synthetic
 mesh is generated on the host before the timed region.
@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=64, help="rows of the oracle's dense matvec sample")
     ap.add_argument("--workload", choices=["bar", "fft", "batch", "serve", "counters"], default="bar",
                     help="bar: solve requests (default); fft: 4-field 256^3 convolution microbenchmark; "
-                         "batch: 64 plane waves solved together on a 20,480-triangle sphere; "
+                         "batch: 64 plane waves solved together on a 4,824-triangle copper bar; "
                          "serve: a Poisson stream of solve requests on the library's server; "
                          "counters: launches for HBM counter runs (1 GiB copy + copper-bar near-field products)")
     ap.add_argument("--nrhs", type=int, default=64, help="batch workload: plane waves")
@@ -58,13 +58,17 @@ def parse():
                     help="relative FP64 block residual of every solve; default 1e-7 for the bar (its EFIE "
                          "conditioning turns a 1e-6 residual into ~1e-3 in the currents; 1e-7 keeps FP32 "
                          "within 1e-3 of FP64), 1e-6 for the batch and serve workloads")
-    ap.add_argument("--restart", type=int, default=200)
+    ap.add_argument("--restart", type=int, default=None,
+                    help="outer GMRES restart length; default 1000 for the bar (its low-frequency EFIE "
+                         "converges in a staircase that restarts would lengthen), 200 for the batch workload")
     ap.add_argument("--precond", type=int, default=4,
                     help="preconditioner bit mask: 1 nested block-Jacobi, 2 outer block-Jacobi, 4 nested "
                          "near-region preconditioner in Schwarz form (conductive media)")
     a = ap.parse_args()
     if a.tol is None:
         a.tol = 1e-7 if a.workload == "bar" else 1e-6
+    if a.restart is None:
+        a.restart = 1000 if a.workload == "bar" else 200
     return a
 
 
