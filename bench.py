@@ -88,7 +88,7 @@ def step(mesh, cfg, prec, tol, timing=False):
     p.setup()
     t1 = time.perf_counter()
     if timing:
-        p.set_timing(True)
+        p.set_timing(2)   # the near-field CSR product alone: two events per product
     w = cfg.waves[0]
     p.set_planewaves(w.khat, w.e0)
     rep = p.solve(prec, tol=tol, **SOLVE_OPTS)
@@ -422,7 +422,7 @@ def main():
         del p
     torch.cuda.synchronize()
     lat, matvecs, setups, reps = [], 0, [], []
-    spmv_ms, spmv_n, prod_ms, prod_n, s64_ms, s64_n = 0.0, 0, 0.0, 0, 0.0, 0
+    spmv_ms, spmv_n, s64_ms, s64_n = 0.0, 0, 0.0, 0
     t0 = time.perf_counter()
     last = None
     for i in range(args.steps):
@@ -430,7 +430,6 @@ def main():
         st = p.stage_times()
         spmv_n += st["spmv"][0]; spmv_ms += st["spmv"][1]
         s64_n += st["spmv64"][0]; s64_ms += st["spmv64"][1]
-        prod_n += st["product"][0]; prod_ms += st["product"][1]
         lat.append(tot); setups.append(su); reps.append(rep)
         matvecs += rep["matvecs"]
         print(f"[bench] step {i}: setup {su:.2f}s total {tot:.2f}s {rep}", file=sys.stderr, flush=True)
@@ -471,7 +470,6 @@ def main():
         "residual_fp64_max": max(r["residual"] for r in reps),
         "outer_iters": reps[-1]["outer_iters"], "inner_iters": reps[-1]["inner_iters"],
         "refine_sweeps": reps[-1]["refine_sweeps"],
-        "matvec_ms_mean": prod_ms / max(prod_n, 1),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": spmv_traffic() if prec == 1 else None,

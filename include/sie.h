@@ -211,7 +211,9 @@ sie_status sie_nested_precond(sie_problem *p, int32_t precond, sie_precision pre
 int32_t sie_nested_precond_clusters(const sie_problem *p, int64_t *owned);
 
 /* Stage timers (HIP events recorded on the stream of each product).
- * sie_set_timing(p, 1) starts recording (and clears the totals); stages:
+ * sie_set_timing(p, 1) starts recording every stage, sie_set_timing(p, 2)
+ * the near-field CSR product alone (stages 3 and 5: two events per product
+ * instead of ten), 0 stops; each call clears the totals.  Stages:
  * 0 projection, 1 FFT convolution, 2 interpolation, 3 near-field CSR product
  * (the k_spmv_far kernel alone), 4 whole operator product, 5 the FP64
  * near-field CSR products alone (also counted in 3).  Query returns the

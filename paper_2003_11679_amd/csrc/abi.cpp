@@ -283,8 +283,9 @@ sie_status sie_interpolate(sie_problem *p, int32_t medium, sie_precision prec, c
 sie_status sie_set_timing(sie_problem *p, int32_t on) {
     return guard([&] {
         SIE_CHECK(p, SIE_EINVAL, "NULL problem");
+        SIE_CHECK(on >= 0 && on <= 2, SIE_EINVAL, "timing mode must be 0, 1 or 2");
         p->timer.reset();
-        p->timer.on = on != 0;
+        p->timer.on = on;
     });
 }
 

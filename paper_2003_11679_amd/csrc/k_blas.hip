@@ -152,6 +152,45 @@ void launch_scale_sys(int64_t n, int ns, const c128 *c, const cx<T> *x, cx<T> *y
     SIE_HIP(hipGetLastError());
 }
 
+// y[s] = c.v[s] x[s] with the coefficients passed by value (no copy to the
+// device ahead of the launch)
+template <typename T>
+__global__ void k_scale_val(int64_t n, ScaleArg c, const cx<T> *__restrict__ x, cx<T> *__restrict__ y) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int s = blockIdx.y;
+    const cx<T> cc((T)c.v[s].re, (T)c.v[s].im);
+    y[s * n + i] = cc * x[s * n + i];
+}
+template <typename T>
+void launch_scale_val(int64_t n, int ns, const ScaleArg &c, const cx<T> *x, cx<T> *y, hipStream_t st) {
+    if (n <= 0 || ns <= 0) return;
+    SIE_CHECK(ns <= kScaleArg, SIE_EINVAL, "too many systems for by-value coefficients");
+    hipLaunchKernelGGL(k_scale_val<T>, dim3((unsigned)((n + 255) / 256), (unsigned)ns), dim3(256), 0, st, n, c, x, y);
+    SIE_HIP(hipGetLastError());
+}
+
+// y[s] = x[s] / sqrt(Re d[s * dstride]) for a squared norm d on the device;
+// zero where that norm is zero
+template <typename T>
+__global__ void k_scale_rnorm(int64_t n, const c128 *__restrict__ d, int dstride, const cx<T> *__restrict__ x,
+                              cx<T> *__restrict__ y) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int s = blockIdx.y;
+    const double q = d[(int64_t)s * dstride].re;
+    const T c = q > 0.0 ? (T)(1.0 / sqrt(q)) : (T)0;
+    const cx<T> v = x[s * n + i];
+    y[s * n + i] = cx<T>(c * v.re, c * v.im);
+}
+template <typename T>
+void launch_scale_rnorm(int64_t n, int ns, const c128 *d, int dstride, const cx<T> *x, cx<T> *y, hipStream_t st) {
+    if (n <= 0 || ns <= 0) return;
+    hipLaunchKernelGGL(k_scale_rnorm<T>, dim3((unsigned)((n + 255) / 256), (unsigned)ns), dim3(256), 0, st, n, d,
+                       dstride, x, y);
+    SIE_HIP(hipGetLastError());
+}
+
 template <typename T>
 __global__ void k_diag_mul(int64_t n, const c128 *__restrict__ d, const cx<T> *__restrict__ x, cx<T> *__restrict__ y) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -180,6 +219,8 @@ template void launch_convert<double, double>(const c128 *, c128 *, int64_t, hipS
     template void launch_gemv_sys<T>(int64_t, int, const cx<T> *, int64_t, int, const c128 *, int, cx<T> *, bool, \
                                      hipStream_t);                                                            \
     template void launch_scale_sys<T>(int64_t, int, const c128 *, const cx<T> *, cx<T> *, hipStream_t);       \
+    template void launch_scale_val<T>(int64_t, int, const ScaleArg &, const cx<T> *, cx<T> *, hipStream_t);   \
+    template void launch_scale_rnorm<T>(int64_t, int, const c128 *, int, const cx<T> *, cx<T> *, hipStream_t); \
     template void launch_diag_mul<T>(int64_t, const c128 *, const cx<T> *, cx<T> *, hipStream_t);
 SIE_INST_B(float)
 SIE_INST_B(double)

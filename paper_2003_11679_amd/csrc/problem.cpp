@@ -484,37 +484,42 @@ void matvec(sie_problem *p, Medium &md, sie_op op, int nrhs, const cx<T> *x, cx<
     const c128 ks = op == SIE_OP_L ? cdiv(c128(-2.0), k2) : c128();
     const cx<T> kscal((T)ks.re, (T)ks.im);
     StageTimer &tm = p->timer;
+    const bool all = tm.on == 1;   // every stage; otherwise the near-field CSR product only
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (nrhs > 1) {
         // batched: every stage takes all right-hand sides at once; the
         // near-field values are streamed once for the whole batch
         Work<T> &wb = work_rhs<T>(g, nrhs, E);
-        if (tm.on) { tm.begin(ST_PRODUCT, st, e0); tm.begin(ST_PROJECT, st, e1); }
+        if (all) { tm.begin(ST_PRODUCT, st, e0); tm.begin(ST_PROJECT, st, e1); }
         launch_tri_sources<T>(g, g.d_trirwg.p, coef_of<T>(g), x, E, nrhs, wb.trisrc.p, st);
         launch_project<T>(g, mom_of<T>(g), wb.trisrc.p, wb.grid.p, F, nrhs, st);
-        if (tm.on) { tm.end(ST_PROJECT, st, e1); tm.begin(ST_FFT, st, e1); }
+        if (all) { tm.end(ST_PROJECT, st, e1); tm.begin(ST_FFT, st, e1); }
         fft_convolve<T>(g, spec_of<T>(md), F * nrhs, op == SIE_OP_L ? 0 : 1, wb.grid.p, wb.grid.p, wb.bufA.p,
                         wb.bufB.p, st);
-        if (tm.on) { tm.end(ST_FFT, st, e1); tm.begin(ST_INTERP, st, e1); }
+        if (all) { tm.end(ST_FFT, st, e1); tm.begin(ST_INTERP, st, e1); }
         launch_interp<T>(g, mom_of<T>(g), wb.grid.p, F, nrhs, wb.tripot.p, st);
-        if (tm.on) { tm.end(ST_INTERP, st, e1); tm.begin(ST_SPMV, st, e1); }
+        if (all) tm.end(ST_INTERP, st, e1);
+        if (tm.on) tm.begin(ST_SPMV, st, e1);
         launch_spmm_far<T>(g, E, nrhs, g.d_rwgloc.p, coef_of<T>(g), wb.tripot.p, kscal, near_of<T>(md, op), x,
                            wb.xt.p, y, st);
-        if (tm.on) { tm.end(ST_SPMV, st, e1, sizeof(T) == 8 ? ST_SPMV64 : -1); tm.end(ST_PRODUCT, st, e0); }
+        if (tm.on) tm.end(ST_SPMV, st, e1, sizeof(T) == 8 ? ST_SPMV64 : -1);
+        if (all) tm.end(ST_PRODUCT, st, e0);
         return;
     }
     for (int r = 0; r < nrhs; ++r) {
-        if (tm.on) { tm.begin(ST_PRODUCT, st, e0); tm.begin(ST_PROJECT, st, e1); }
+        if (all) { tm.begin(ST_PRODUCT, st, e0); tm.begin(ST_PROJECT, st, e1); }
         launch_tri_sources<T>(g, g.d_trirwg.p, coef_of<T>(g), x + r * E, E, 1, w.trisrc.p, st);
         launch_project<T>(g, mom_of<T>(g), w.trisrc.p, w.grid.p, F, 1, st);
-        if (tm.on) { tm.end(ST_PROJECT, st, e1); tm.begin(ST_FFT, st, e1); }
+        if (all) { tm.end(ST_PROJECT, st, e1); tm.begin(ST_FFT, st, e1); }
         fft_convolve<T>(g, spec_of<T>(md), F, op == SIE_OP_L ? 0 : 1, w.grid.p, w.grid.p, w.bufA.p, w.bufB.p, st);
-        if (tm.on) { tm.end(ST_FFT, st, e1); tm.begin(ST_INTERP, st, e1); }
+        if (all) { tm.end(ST_FFT, st, e1); tm.begin(ST_INTERP, st, e1); }
         launch_interp<T>(g, mom_of<T>(g), w.grid.p, F, 1, w.tripot.p, st);
-        if (tm.on) { tm.end(ST_INTERP, st, e1); tm.begin(ST_SPMV, st, e1); }
+        if (all) tm.end(ST_INTERP, st, e1);
+        if (tm.on) tm.begin(ST_SPMV, st, e1);
         launch_spmv_far<T>(g, E, g.d_rwgloc.p, coef_of<T>(g), w.tripot.p, kscal, near_of<T>(md, op), x + r * E,
                            y + r * E, true, st);
-        if (tm.on) { tm.end(ST_SPMV, st, e1, sizeof(T) == 8 ? ST_SPMV64 : -1); tm.end(ST_PRODUCT, st, e0); }
+        if (tm.on) tm.end(ST_SPMV, st, e1, sizeof(T) == 8 ? ST_SPMV64 : -1);
+        if (all) tm.end(ST_PRODUCT, st, e0);
     }
 }
 

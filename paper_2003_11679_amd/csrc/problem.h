@@ -28,7 +28,7 @@ struct SolveState;     // solver.cpp
 // ST_SPMV as well).
 enum Stage { ST_PROJECT = 0, ST_FFT = 1, ST_INTERP = 2, ST_SPMV = 3, ST_PRODUCT = 4, ST_SPMV64 = 5, NSTAGE = 6 };
 struct StageTimer {
-    bool on = false;
+    int on = 0;   // 0 off, 1 every stage, 2 the near-field CSR product alone
     struct Rec { int stage, extra; hipEvent_t a, b; };
     std::vector<Rec> pending;
     std::vector<hipEvent_t> pool;
@@ -119,6 +119,15 @@ template <typename T> void launch_gemv_sys(int64_t n, int J, const cx<T> *V, int
                                            int hstride, cx<T> *w, bool add, hipStream_t st);
 template <typename T> void launch_scale_sys(int64_t n, int ns, const c128 *c, const cx<T> *x, cx<T> *y,
                                             hipStream_t st);
+// y[s] = c.v[s] x[s], coefficients passed by value (ns <= kScaleArg)
+constexpr int kScaleArg = 64;
+struct ScaleArg { c128 v[kScaleArg]; };
+template <typename T> void launch_scale_val(int64_t n, int ns, const ScaleArg &c, const cx<T> *x, cx<T> *y,
+                                            hipStream_t st);
+// y[s] = x[s] / sqrt(Re d[s * dstride]) (zero where that is zero): scaling
+// by a squared norm that stays on the device
+template <typename T> void launch_scale_rnorm(int64_t n, int ns, const c128 *d, int dstride, const cx<T> *x,
+                                              cx<T> *y, hipStream_t st);
 // y[i] = d[i] * x[i] with per-element complex d (range [i0, i1), zero elsewhere if zero_out)
 template <typename T> void launch_diag_mul(int64_t n, const c128 *d, const cx<T> *x, cx<T> *y, hipStream_t st);
 constexpr int DOT_BLOCKS = 256;

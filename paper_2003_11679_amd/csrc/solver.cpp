@@ -81,10 +81,14 @@ struct Gmres {
     int m = 0;                      // restart length
     int dblk = 1;                   // dot-product blocks per system
     DBuf<cx<T>> V, Zb, w, r;        // V: (m+1) x [nb][n], Zb: m x [nb][n], w, r: [nb][n]
-    DBuf<c128> part, hd, cd;
-    PinnedC128 hh;                  // 3 slots of [nb][m + 1] dot results
-    PinnedC128 hc;                  // [nb] scaling coefficients
+    DBuf<c128> part, hd, cd;        // hd: 4 slots of [nb][m + 1] dot results
+    PinnedC128 hh;                  // host copy of the 4 slots of hd
+    PinnedC128 hc;                  // [nb] scaling coefficients (batches wider than kScaleArg)
+    PinnedC128 hy;                  // [nb][m + 1] least-squares solutions
     hipEvent_t hc_done = nullptr;   // last copy out of hc
+    hipEvent_t hy_done = nullptr;   // last copy out of hy
+    hipEvent_t sync_ev = nullptr;   // host waits
+    std::vector<c128> H;            // [nb][m + 1][m] Hessenberg matrices, kept between solves
     using Op = std::function<void(const cx<T> *, cx<T> *)>;
     const char *tag = "gmres";
     // Stagnation window: a system that gains under 1 % over this many
@@ -92,8 +96,10 @@ struct Gmres {
     // correction); 0 disables it.
     int stag_window = 25;
 
+    size_t slot() const { return (size_t)nb * (m + 1); }
     void init(int64_t n_, int nb_, int m_) {
         if (n == n_ && nb == nb_ && m == m_) return;
+        if (hy_done) SIE_HIP(hipEventSynchronize(hy_done));   // hy is reallocated below
         n = n_; nb = nb_; m = m_;
         const size_t blk = (size_t)nb * n;
         V.alloc((size_t)(m + 1) * blk);
@@ -102,33 +108,48 @@ struct Gmres {
         r.alloc(blk);
         dblk = (int)std::min<int64_t>(DOT_BLOCKS, std::max<int64_t>(4, (n + 4095) / 4096));
         part.alloc((size_t)nb * (m + 1) * dblk);
-        hd.alloc((size_t)nb * (m + 1));
+        hd.alloc(4 * slot());
         cd.alloc(nb);
-        hh.alloc(3 * (size_t)nb * (m + 1));
+        hh.alloc(4 * slot());
+        hy.alloc(slot());
         hc.alloc(nb);
         if (!hc_done) SIE_HIP(hipEventCreateWithFlags(&hc_done, hipEventDisableTiming));
+        if (!hy_done) SIE_HIP(hipEventCreateWithFlags(&hy_done, hipEventDisableTiming));
+        if (!sync_ev) SIE_HIP(hipEventCreateWithFlags(&sync_ev, hipEventDisableTiming));
+        const size_t need = (size_t)nb * (m + 1) * m;
+        if (H.size() < need) H.resize(need);
     }
     Gmres() = default;
     Gmres(const Gmres &) = delete;
     Gmres &operator=(const Gmres &) = delete;
     ~Gmres() {
-        if (hc_done) (void)hipEventDestroy(hc_done);
+        if (hy_done) (void)hipEventSynchronize(hy_done);   // hy is freed with the object
+        for (hipEvent_t e : {hc_done, hy_done, sync_ev})
+            if (e) (void)hipEventDestroy(e);
     }
-    // Launches h[s][j] = V_j[s]^H x[s], j < J, and its copy into host slot
-    // `slot`; readable after the next synchronisation of st.
-    const c128 *dots_async(int J, const cx<T> *Vp, const cx<T> *x, int slot, hipStream_t st) {
-        launch_dots_sys<T>(n, J, Vp, (int64_t)nb * n, nb, x, part.p, dblk, hd.p, m + 1, st);
-        c128 *h = hh.p + (size_t)slot * nb * (m + 1);
-        SIE_HIP(hipMemcpyAsync(h, hd.p, (size_t)nb * (m + 1) * sizeof(c128), hipMemcpyDeviceToHost, st));
+    // Host wait for the work queued on st so far.  It polls an event: a
+    // blocking synchronisation sleeps and adds a wake-up latency to every
+    // Arnoldi step.
+    void wait(hipStream_t st) {
+        SIE_HIP(hipEventRecord(sync_ev, st));
+        hipError_t e;
+        while ((e = hipEventQuery(sync_ev)) == hipErrorNotReady)
+            for (int i = 0; i < 32; ++i) __builtin_ia32_pause();
+        SIE_HIP(e);
+    }
+    // Device slot sl of hd receives h[s][j] = V_j[s]^H x[s], j < J
+    // (V_j at Vp + j * nb * n); returns it.
+    c128 *dots_dev(int J, const cx<T> *Vp, const cx<T> *x, int sl, hipStream_t st) {
+        c128 *h = hd.p + (size_t)sl * slot();
+        launch_dots_sys<T>(n, J, Vp, (int64_t)nb * n, nb, x, part.p, dblk, h, m + 1, st);
         return h;
     }
-    // h[s][j] = V_j[s]^H x[s], j < J (V_j at Vp + j * nb * n)
+    // h[s][j] = V_j[s]^H x[s], j < J
     std::vector<c128> dots(int J, const cx<T> *Vp, const cx<T> *x, hipStream_t st) {
-        launch_dots_sys<T>(n, J, Vp, (int64_t)nb * n, nb, x, part.p, dblk, hd.p, m + 1, st);
-        std::vector<c128> h((size_t)nb * (m + 1));
-        SIE_HIP(hipMemcpyAsync(h.data(), hd.p, h.size() * sizeof(c128), hipMemcpyDeviceToHost, st));
-        SIE_HIP(hipStreamSynchronize(st));
-        return h;
+        const c128 *h = dots_dev(J, Vp, x, 0, st);
+        SIE_HIP(hipMemcpyAsync(hh.p, h, slot() * sizeof(c128), hipMemcpyDeviceToHost, st));
+        wait(st);
+        return std::vector<c128>(hh.p, hh.p + slot());
     }
     std::vector<double> norms(const cx<T> *x, hipStream_t st) {
         std::vector<c128> h = dots(1, x, x, st);
@@ -137,6 +158,12 @@ struct Gmres {
         return out;
     }
     void scale(const std::vector<c128> &c, const cx<T> *x, cx<T> *y, hipStream_t st) {
+        if (nb <= kScaleArg) {
+            ScaleArg a;
+            for (int k = 0; k < nb; ++k) a.v[k] = c[k];
+            launch_scale_val<T>(n, nb, a, x, y, st);
+            return;
+        }
         SIE_HIP(hipEventSynchronize(hc_done));     // hc no longer being copied
         std::copy(c.begin(), c.end(), hc.p);
         SIE_HIP(hipMemcpyAsync(cd.p, hc.p, nb * sizeof(c128), hipMemcpyHostToDevice, st));
@@ -147,62 +174,77 @@ struct Gmres {
     // Solves A x = b for the nb systems (x holds the initial guesses), each
     // to its own relative tolerance tol[k].  Returns the iterations of the
     // longest system; relres[k] receives the final relative residuals.
-    // x_zero: the guesses are zero (the first residual is b, no product).
+    // x_zero: the guesses are zero (the first residual is b, no product; its
+    // norms are applied on the device and read with the first Arnoldi step).
     // trust_estimate: return when every system's Arnoldi residual estimate
     // meets its tolerance (or it stagnated) instead of confirming it with a
     // true residual; for solves inside an outer iteration whose own residual
-    // is checked.
+    // is checked.  The host then returns without waiting for the device.
     int solve(const Op &A, const Op &M, const cx<T> *b, cx<T> *x, const std::vector<double> &tol, int maxit,
               std::vector<double> *relres, hipStream_t st, int *napply = nullptr, bool x_zero = false,
               bool trust_estimate = false) {
         static const bool trace = std::getenv("SIE_TRACE") != nullptr;
-        const std::vector<double> bn = norms(b, st);
+        const size_t ld = (size_t)m + 1, sl = slot(), mm = ld * m;
+        const bool defer = x_zero && maxit > 0;
         std::vector<char> fin(nb, 0);
-        std::vector<double> res(nb, 0.0);
-        std::vector<c128> zero(nb, c128());
-        for (int k = 0; k < nb; ++k)
-            if (bn[k] == 0.0) fin[k] = 1;
-        {   // systems with a zero right-hand side: x = 0
-            std::vector<c128> keep(nb);
-            for (int k = 0; k < nb; ++k) keep[k] = c128(fin[k] ? 0.0 : 1.0);
-            scale(keep, x, x, st);
+        std::vector<double> res(nb, 0.0), bn(nb, 0.0);
+        if (!defer) {
+            bn = norms(b, st);
+            bool any_zero = false;
+            for (int k = 0; k < nb; ++k)
+                if (bn[k] == 0.0) fin[k] = 1, any_zero = true;
+            if (any_zero) {   // systems with a zero right-hand side: x = 0
+                std::vector<c128> keep(nb);
+                for (int k = 0; k < nb; ++k) keep[k] = c128(fin[k] ? 0.0 : 1.0);
+                scale(keep, x, x, st);
+            }
         }
-        const size_t mm = (size_t)(m + 1) * m;
-        std::vector<c128> H((size_t)nb * mm), g((size_t)nb * (m + 1)), sn((size_t)nb * m);
+        std::vector<c128> g((size_t)nb * ld), sn((size_t)nb * m);
         std::vector<double> cs((size_t)nb * m);
         std::vector<std::vector<double>> hist(nb);
         std::vector<char> stag(nb, 0);
         int it = 0;
         bool first = true;
         while (true) {
-            // r = b - A x
-            if (first && x_zero) {
-                SIE_HIP(hipMemcpyAsync(r.p, b, (size_t)nb * n * sizeof(cx<T>), hipMemcpyDeviceToDevice, st));
-            } else {
-                A(x, r.p);
-                if (napply) ++*napply;
-                launch_axpby<T>((int64_t)nb * n, c128(1.0), b, c128(-1.0), r.p, st);
-            }
-            first = false;
-            const std::vector<double> beta = norms(r.p, st);
-            bool all = true;
-            for (int k = 0; k < nb; ++k) {
-                if (bn[k] > 0.0) res[k] = beta[k] / bn[k];
-                if (!fin[k] && (res[k] <= tol[k] || stag[k])) fin[k] = 1;
-                all = all && fin[k];
-            }
-            if (trace) std::fprintf(stderr, "[%s] restart at it %d true res %.3e\n", tag, it, res[0]);
-            if (all || it >= maxit) break;
-            std::vector<c128> c0(nb);
+            std::vector<double> beta(nb, 0.0);
             std::vector<char> act(nb, 0);
             std::vector<int> kb(nb, 0);
-            for (int k = 0; k < nb; ++k) {
-                act[k] = !fin[k];
-                c0[k] = act[k] ? c128(1.0 / beta[k]) : c128();
-                std::fill(g.begin() + (size_t)k * (m + 1), g.begin() + (size_t)(k + 1) * (m + 1), c128());
-                g[(size_t)k * (m + 1)] = c128(beta[k]);
+            const bool pending = first && defer;   // ||b|| still on the device
+            if (pending) {
+                // V_0 = b / ||b|| on the device; the host reads ||b|| with
+                // the first Arnoldi step
+                const c128 *nd = dots_dev(1, b, b, 3, st);
+                launch_scale_rnorm<T>(n, nb, nd, m + 1, b, V.p, st);
+                std::fill(g.begin(), g.end(), c128());
+                std::fill(act.begin(), act.end(), 1);
+            } else {
+                // r = b - A x
+                if (first && x_zero) {
+                    SIE_HIP(hipMemcpyAsync(r.p, b, (size_t)nb * n * sizeof(cx<T>), hipMemcpyDeviceToDevice, st));
+                } else {
+                    A(x, r.p);
+                    if (napply) ++*napply;
+                    launch_axpby<T>((int64_t)nb * n, c128(1.0), b, c128(-1.0), r.p, st);
+                }
+                beta = norms(r.p, st);
+                bool all = true;
+                for (int k = 0; k < nb; ++k) {
+                    if (bn[k] > 0.0) res[k] = beta[k] / bn[k];
+                    if (!fin[k] && (res[k] <= tol[k] || stag[k])) fin[k] = 1;
+                    all = all && fin[k];
+                }
+                if (trace) std::fprintf(stderr, "[%s] restart at it %d true res %.3e\n", tag, it, res[0]);
+                if (all || it >= maxit) break;
+                std::vector<c128> c0(nb);
+                for (int k = 0; k < nb; ++k) {
+                    act[k] = !fin[k];
+                    c0[k] = act[k] ? c128(1.0 / beta[k]) : c128();
+                    std::fill(g.begin() + (size_t)k * ld, g.begin() + (size_t)(k + 1) * ld, c128());
+                    g[(size_t)k * ld] = c128(beta[k]);
+                }
+                scale(c0, r.p, V.p, st);
             }
-            scale(c0, r.p, V.p, st);
+            first = false;
             const int64_t blk = (int64_t)nb * n;
             int j = 0;
             for (; j < m && it < maxit; ++j, ++it) {
@@ -212,25 +254,37 @@ struct Gmres {
                 if (napply) ++*napply;
                 // classical Gram-Schmidt, twice (the projections use the
                 // device copies of the coefficients; the host reads all
-                // three results after one synchronisation)
-                const c128 *hp1 = dots_async(j + 1, V.p, w.p, 0, st);
-                launch_gemv_sys<T>(n, j + 1, V.p, blk, nb, hd.p, m + 1, w.p, false, st);
-                const c128 *hp2 = dots_async(j + 1, V.p, w.p, 1, st);
-                launch_gemv_sys<T>(n, j + 1, V.p, blk, nb, hd.p, m + 1, w.p, false, st);
-                const c128 *hp3 = dots_async(1, w.p, w.p, 2, st);
-                SIE_HIP(hipStreamSynchronize(st));
-                std::vector<c128> h(hp1, hp1 + (size_t)nb * (m + 1));
-                const c128 *h2 = hp2;
+                // results after one copy and one wait)
+                const c128 *d1 = dots_dev(j + 1, V.p, w.p, 0, st);
+                launch_gemv_sys<T>(n, j + 1, V.p, blk, nb, d1, m + 1, w.p, false, st);
+                const c128 *d2 = dots_dev(j + 1, V.p, w.p, 1, st);
+                launch_gemv_sys<T>(n, j + 1, V.p, blk, nb, d2, m + 1, w.p, false, st);
+                dots_dev(1, w.p, w.p, 2, st);
+                const bool read_b = pending && j == 0;
+                SIE_HIP(hipMemcpyAsync(hh.p, hd.p, (read_b ? 4 : 3) * sl * sizeof(c128), hipMemcpyDeviceToHost,
+                                       st));
+                wait(st);
+                c128 *h1 = hh.p;
+                const c128 *h2 = hh.p + sl, *h3 = hh.p + 2 * sl;
+                if (read_b) {
+                    for (int k = 0; k < nb; ++k) {
+                        bn[k] = std::sqrt(std::max(0.0, hh.p[3 * sl + (size_t)k * ld].re));
+                        beta[k] = bn[k];
+                        res[k] = 1.0;
+                        if (bn[k] == 0.0) { fin[k] = 1; act[k] = 0; res[k] = 0.0; }   // x stays zero
+                        else g[(size_t)k * ld] = c128(beta[k]);
+                    }
+                }
                 std::vector<double> hn(nb);
-                for (int k = 0; k < nb; ++k) hn[k] = std::sqrt(std::max(0.0, hp3[(size_t)k * (m + 1)].re));
+                for (int k = 0; k < nb; ++k) hn[k] = std::sqrt(std::max(0.0, h3[(size_t)k * ld].re));
                 std::vector<c128> cn(nb);
                 bool any = false;
                 for (int k = 0; k < nb; ++k) {
                     if (!act[k]) continue;
-                    c128 *hk = h.data() + (size_t)k * (m + 1);
-                    const c128 *h2k = h2 + (size_t)k * (m + 1);
+                    c128 *hk = h1 + (size_t)k * ld;
+                    const c128 *h2k = h2 + (size_t)k * ld;
                     for (int i = 0; i <= j; ++i) hk[i] += h2k[i];
-                    c128 *gk = g.data() + (size_t)k * (m + 1);
+                    c128 *gk = g.data() + (size_t)k * ld;
                     double *csk = cs.data() + (size_t)k * m;
                     c128 *snk = sn.data() + (size_t)k * m;
                     for (int i = 0; i < j; ++i) {
@@ -266,36 +320,36 @@ struct Gmres {
                     any = any || act[k];
                 }
                 if (trace) std::fprintf(stderr, "[%s] it %d res %.3e\n", tag, it + 1, res[0]);
-                scale(cn, w.p, V.p + (size_t)(j + 1) * blk, st);
                 if (!any) { ++j; ++it; break; }
+                scale(cn, w.p, V.p + (size_t)(j + 1) * blk, st);
             }
             // y_k = H_k^-1 g_k ; x_k += Zb_k y_k
-            std::vector<c128> y((size_t)nb * (m + 1));
             int kmax = 0;
-            for (int k = 0; k < nb; ++k) {
-                const int kk = kb[k];
-                kmax = std::max(kmax, kk);
-                const c128 *Hk = H.data() + (size_t)k * mm;
-                const c128 *gk = g.data() + (size_t)k * (m + 1);
-                c128 *yk = y.data() + (size_t)k * (m + 1);
-                for (int i = kk - 1; i >= 0; --i) {
-                    c128 sacc = gk[i];
-                    for (int l = i + 1; l < kk; ++l) sacc -= Hk[(size_t)i * m + l] * yk[l];
-                    yk[i] = cdiv(sacc, Hk[(size_t)i * m + i]);
-                }
-            }
+            for (int k = 0; k < nb; ++k) kmax = std::max(kmax, kb[k]);
             if (kmax > 0) {
-                SIE_HIP(hipMemcpyAsync(hd.p, y.data(), y.size() * sizeof(c128), hipMemcpyHostToDevice, st));
+                SIE_HIP(hipEventSynchronize(hy_done));   // hy no longer being copied
+                c128 *y = hy.p;
+                for (int k = 0; k < nb; ++k) {
+                    const int kk = kb[k];
+                    const c128 *Hk = H.data() + (size_t)k * mm;
+                    const c128 *gk = g.data() + (size_t)k * ld;
+                    c128 *yk = y + (size_t)k * ld;
+                    std::fill(yk + kk, yk + kmax, c128());
+                    for (int i = kk - 1; i >= 0; --i) {
+                        c128 sacc = gk[i];
+                        for (int l = i + 1; l < kk; ++l) sacc -= Hk[(size_t)i * m + l] * yk[l];
+                        yk[i] = cdiv(sacc, Hk[(size_t)i * m + i]);
+                    }
+                }
+                SIE_HIP(hipMemcpyAsync(hd.p, y, sl * sizeof(c128), hipMemcpyHostToDevice, st));
+                SIE_HIP(hipEventRecord(hy_done, st));
                 launch_gemv_sys<T>(n, kmax, Zb.p, blk, nb, hd.p, m + 1, x, true, st);
             }
             if (trust_estimate) {
                 bool done = true;
                 for (int k = 0; k < nb; ++k)
                     if (!fin[k] && !(res[k] <= tol[k] || stag[k])) done = false;
-                if (done || it >= maxit) {
-                    SIE_HIP(hipStreamSynchronize(st));   // y is host memory
-                    break;
-                }
+                if (done || it >= maxit) break;
             }
         }
         if (relres) *relres = res;

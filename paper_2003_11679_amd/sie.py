@@ -318,7 +318,8 @@ class Problem:
     STAGES = ("project", "fft", "interp", "spmv", "product", "spmv64")
 
     def set_timing(self, on=True):
-        _check(lib().sie_set_timing(self.h, 1 if on else 0))
+        """True/1: time every stage; 2: the near-field CSR product alone; False/0: off."""
+        _check(lib().sie_set_timing(self.h, int(on)))
 
     def stage_times(self):
         """{stage: (launches, total_ms)} of the stage timers."""
