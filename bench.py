@@ -9,7 +9,9 @@ near lists, FP64 near-field integrals with precorrection, Green's spectra,
 plane-wave excitation, the nested GIBC solve (FP32 interior stages inside
 FP64 refinement to the relative FP64 block residual given by --tol, default
 1e-7; the nested solves preconditioned by the near-region operator in
-restricted additive Schwarz form, outer restart 1000) and the far field.
+restricted additive Schwarz form and run, inside each FP32 correction, to a
+tolerance relaxed with the outer residual (--inner-relax 0.1); outer restart
+1000) and the far field.
 The FP32 currents are compared with an FP64 solve of the same request during
 warmup (relative error gate 1e-3).  The synthetic
 mesh is generated on the host before the timed region.
@@ -61,6 +63,9 @@ def parse():
     ap.add_argument("--restart", type=int, default=None,
                     help="outer GMRES restart length; default 1000 for the bar (its low-frequency EFIE "
                          "converges in a staircase that restarts would lengthen), 200 for the batch workload")
+    ap.add_argument("--inner-relax", type=float, default=0.1,
+                    help="relaxed nested tolerance inside the FP32 correction solves: nested solve j runs to "
+                         "this x (correction target) / (outer residual estimate); 0: fixed tolerance")
     ap.add_argument("--precond", type=int, default=4,
                     help="preconditioner bit mask: 1 nested block-Jacobi, 2 outer block-Jacobi, 4 nested "
                          "near-region preconditioner in Schwarz form (conductive media)")
@@ -398,7 +403,7 @@ def main():
     cfg = bar_cfg()
     mesh = (cfg.objects[0].xyz, cfg.objects[0].tri)
     prec = 1 if args.precision == "fp32" else 0
-    SOLVE_OPTS.update(restart=args.restart, precond=args.precond)
+    SOLVE_OPTS.update(restart=args.restart, precond=args.precond, inner_relax=args.inner_relax)
     print(f"[bench] workload bar {len(mesh[1])} triangles, precision {args.precision}, "
           f"warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
     ref = None

@@ -104,6 +104,14 @@ typedef struct {
                             region (five skin depths within R grid spacings)
                             get it, the others run unpreconditioned.  1 and 4
                             exclude each other (SIE_EINVAL); 0 none (default) */
+    double inner_relax;  /* SIE_FP32 only: relaxed nested tolerance inside each
+                            FP32 correction solve (inexact Krylov relaxation,
+                            Simoncini and Szyld): nested solve j runs to
+                            inner_relax x (correction target) / (current
+                            outer residual estimate), clamped to
+                            [max(inner_tol, 1e-5), 1e-2]; 0 keeps the fixed
+                            tolerance (default).  The FP64 block residual of
+                            every refinement sweep still decides convergence. */
 } sie_solver_opts;
 
 typedef struct {

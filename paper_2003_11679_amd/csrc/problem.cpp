@@ -18,6 +18,10 @@
 #include <cmath>
 #include <numeric>
 
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+
 #include "problem.h"
 
 namespace sie {
@@ -75,6 +79,18 @@ static void build_grid_geometry(sie_problem *p, Grid &g, const GridReq &req, dou
 
 // Stencil centres, live box, local (cell-sorted) triangle order, moments,
 // projection lists, near pairs and the RWG near pattern of one grid.
+// Setup phase timing on stderr when SIE_TRACE is set (waits for the device at
+// every mark; silent and free otherwise).
+static void setup_mark(const char *what) {
+    static const bool trace = std::getenv("SIE_TRACE") != nullptr;
+    if (!trace) return;
+    static auto last = std::chrono::steady_clock::now();
+    SIE_HIP(hipDeviceSynchronize());
+    const auto now = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "[setup] %-28s %8.1f ms\n", what, std::chrono::duration<double, std::milli>(now - last).count());
+    last = now;
+}
+
 static void build_grid(sie_problem *p, Grid &g) {
     const Mesh &m = p->mesh;
     const int64_t ntg = (int64_t)g.tris.size();
@@ -171,6 +187,7 @@ static void build_grid(sie_problem *p, Grid &g) {
         }
     }
     g.d_rwgloc.upload(rwgloc);
+    setup_mark("grid: stencils, near pairs");
     // 6. moments
     {
         Rule r = rule_collapsed(5);   // exact to degree 8 (integrands of degree 7)
@@ -205,6 +222,7 @@ static void build_grid(sie_problem *p, Grid &g) {
         g.d_node_ptr.upload(nptr);
         g.d_node_ent.upload(ent);
     }
+    setup_mark("grid: moments, gather lists");
     // 8. RWG near pattern
     {
         DBuf<int64_t> d_len(nrow), d_rp(nrow + 1);
@@ -286,6 +304,7 @@ static void build_medium(sie_problem *p, Medium &md) {
     d_gl.upload(gl);
     const int polar = std::fabs(md.k.im) >= 0.38 * std::hypot(md.k.re, md.k.im) ? 1 : 0;
 
+    setup_mark("medium: rules, tables");
     md.d_nL64.alloc(std::max<int64_t>(g.nnz, 1));
     md.d_nK64.alloc(std::max<int64_t>(g.nnz, 1));
     md.d_nLd64.alloc(std::max<int64_t>(g.nnz, 1));
@@ -293,13 +312,15 @@ static void build_medium(sie_problem *p, Medium &md) {
     SIE_HIP(hipMemset(md.d_nK64.p, 0, md.d_nK64.bytes()));
     SIE_HIP(hipMemset(md.d_nLd64.p, 0, md.d_nLd64.bytes()));
     // process row triangles in chunks to bound the pair-block buffer
+    setup_mark("medium: alloc + clear");
     std::vector<int64_t> pptr = g.d_pair_ptr.download();
+    std::vector<int32_t> rwgloc = g.d_rwgloc.download();
+    setup_mark("fill: downloads");
     const int64_t max_chunk = 30000000;  // pair blocks of one chunk: 13 GB of HBM at most
     DBuf<c128> blocks;
     DBuf<int64_t> d_pp;
     DBuf<int32_t> d_rwgloc_chunk;
     const int64_t nrow = g.rwg1 - g.rwg0;
-    std::vector<int32_t> rwgloc = g.d_rwgloc.download();
     int64_t t0 = 0;
     while (t0 < ntg) {
         int64_t t1 = t0 + 1;
@@ -310,6 +331,7 @@ static void build_medium(sie_problem *p, Medium &md) {
         for (int64_t i = 0; i <= ntg; ++i) cp[i] = std::min(std::max(pptr[i], pptr[t0]), pptr[t1]) - pptr[t0];
         d_pp.upload(cp);
         blocks.alloc(std::max<int64_t>(np, 1) * 27);
+        setup_mark("fill: chunk buffers");
         NearFillArgs a;
         a.xyz = p->d_xyz.p; a.tri = p->d_tri.p; a.tris = g.d_tris.p; a.centre = g.d_centre.p;
         a.centroid = p->d_centroid.p; a.tri_coef = g.d_tri64.p; a.mom = g.d_mom64.p;
@@ -320,17 +342,20 @@ static void build_medium(sie_problem *p, Medium &md) {
         a.polar = polar;
         a.polar_gl = d_gl.p;
         launch_near_fill(a, np, 0);
+        setup_mark("fill: pair blocks");
         launch_near_gather(nrow, g.rwg0, g.max_row, g.d_row_ptr.p, g.d_cols.p, g.d_rwgloc.p, g.d_glob2loc.p,
                            p->d_tpm.p, p->d_epm.p, d_pp.p, g.d_pair_s.p + pptr[t0], blocks.p, md.d_nL64.p,
                            md.d_nK64.p, md.d_nLd64.p, 0);
         SIE_HIP(hipStreamSynchronize(0));
         t0 = t1;
     }
+    setup_mark("medium: near fill");
     md.d_nL32.alloc(std::max<int64_t>(g.nnz, 1));
     md.d_nK32.alloc(std::max<int64_t>(g.nnz, 1));
     launch_convert<double, float>(md.d_nL64.p, md.d_nL32.p, g.nnz, 0);
     launch_convert<double, float>(md.d_nK64.p, md.d_nK32.p, g.nnz, 0);
     // spectra of G, dG/dx, dG/dy, dG/dz, folded to the octant, 1/(mx my mz) folded in
+    setup_mark("medium: FP32 copies");
     const int64_t vol = g.mvol();
     DBuf<c128> d_vol(vol), d_tmp(vol);
     md.d_spec64.alloc(4 * g.oct());
@@ -342,6 +367,7 @@ static void build_medium(sie_problem *p, Medium &md) {
         launch_fold_octant(d_vol.p, g.m, kind, scale, md.d_spec64.p, md.d_spec32.p, 0);
     }
     SIE_HIP(hipStreamSynchronize(0));
+    setup_mark("medium: spectra");
 }
 
 static void build_x(sie_problem *p) {
@@ -572,7 +598,9 @@ void problem_setup(sie_problem *p) {
         for (int32_t v : o.tri) SIE_CHECK(v >= 0 && v < (int32_t)(o.xyz.size() / 3), SIE_EMESH, "vertex index out of range");
     }
     m.nobj = (int)p->objs.size();
+    setup_mark("start");
     build_topology(m);
+    setup_mark("topology");
     // quadrature defaults
     sie_quad_params &q = p->quad;
     if (q.touch_out <= 0) q.touch_out = 6;
@@ -594,6 +622,7 @@ void problem_setup(sie_problem *p) {
     p->d_area.upload(m.area);
     p->d_tri_sign.upload(m.tri_sign);
     build_x(p);
+    setup_mark("mesh upload, X");
     // media
     p->w = 2.0 * 3.14159265358979323846 * p->freq;
     const double w = p->w;
@@ -620,6 +649,7 @@ void problem_setup(sie_problem *p) {
         for (int i = 0; i < m.nobj; ++i) g->objs.push_back(i);
         build_grid_geometry(p, *g, p->ext_req, lam0);
         build_grid(p, *g);
+        setup_mark("exterior grid");
         p->ext.grid = g.get();
         p->grids.push_back(std::move(g));
     }

@@ -89,6 +89,7 @@ struct Gmres {
     hipEvent_t hy_done = nullptr;   // last copy out of hy
     hipEvent_t sync_ev = nullptr;   // host waits
     std::vector<c128> H;            // [nb][m + 1][m] Hessenberg matrices, kept between solves
+    std::vector<double> live;       // [nb] residual estimate of the running solve, per step
     using Op = std::function<void(const cx<T> *, cx<T> *)>;
     const char *tag = "gmres";
     // Stagnation window: a system that gains under 1 % over this many
@@ -118,6 +119,7 @@ struct Gmres {
         if (!sync_ev) SIE_HIP(hipEventCreateWithFlags(&sync_ev, hipEventDisableTiming));
         const size_t need = (size_t)nb * (m + 1) * m;
         if (H.size() < need) H.resize(need);
+        live.assign(nb, 1.0);
     }
     Gmres() = default;
     Gmres(const Gmres &) = delete;
@@ -217,6 +219,7 @@ struct Gmres {
                 launch_scale_rnorm<T>(n, nb, nd, m + 1, b, V.p, st);
                 std::fill(g.begin(), g.end(), c128());
                 std::fill(act.begin(), act.end(), 1);
+                std::fill(live.begin(), live.end(), 1.0);
             } else {
                 // r = b - A x
                 if (first && x_zero) {
@@ -233,6 +236,7 @@ struct Gmres {
                     if (!fin[k] && (res[k] <= tol[k] || stag[k])) fin[k] = 1;
                     all = all && fin[k];
                 }
+                live = res;
                 if (trace) std::fprintf(stderr, "[%s] restart at it %d true res %.3e\n", tag, it, res[0]);
                 if (all || it >= maxit) break;
                 std::vector<c128> c0(nb);
@@ -309,6 +313,7 @@ struct Gmres {
                     c128 *Hk = H.data() + (size_t)k * mm;
                     for (int i = 0; i <= j; ++i) Hk[(size_t)i * m + j] = hk[i];
                     res[k] = std::sqrt(norm2(gk[j + 1])) / bn[k];
+                    live[k] = res[k];
                     kb[k] = j + 1;
                     auto &hs = hist[k];
                     hs.push_back(res[k]);
@@ -687,12 +692,21 @@ struct Ops {
     Ops<float> *lo = nullptr;
     // v = Lhat^-1 a (nested solve, eq. nest2)
     void inner_solve(const cx<T> *a, cx<T> *v);
+    // Relaxed nested tolerance (inexact Krylov): while relax_res points at
+    // the enclosing solve's residual estimates, nested solve k runs to
+    // relax_eps[k] / (*relax_res)[k] within [inner_tol, kRelaxCap].
+    static constexpr double kRelaxCap = 1e-2;
+    const std::vector<double> *relax_res = nullptr;
+    std::vector<double> relax_eps;
     void inner_solve_native(const cx<T> *a, cx<T> *v) {
         SIE_HIP(hipMemsetAsync(v, 0, NE * sizeof(cx<T>), st));
+        std::vector<double> tol(nb, inner_tol);
+        if (relax_res)
+            for (int k = 0; k < nb; ++k)
+                tol[k] = std::min(kRelaxCap, std::max(inner_tol, relax_eps[k] / std::max((*relax_res)[k], 1e-300)));
         int it = inner_of<T>(s).solve([&](const cx<T> *x, cx<T> *y) { Lhat(x, y); },
-                                      [&](const cx<T> *x, cx<T> *y) { prec_inner(x, y); }, a, v,
-                                      std::vector<double>(nb, inner_tol), inner_max_iter, nullptr, st, nullptr,
-                                      true, true);
+                                      [&](const cx<T> *x, cx<T> *y) { prec_inner(x, y); }, a, v, tol,
+                                      inner_max_iter, nullptr, st, nullptr, true, true);
         s.inner_iters += it;
         s.inner_max = std::max(s.inner_max, it);
     }
@@ -790,8 +804,12 @@ static void build_preconditioners(sie_problem *p, SolveState &s, int precond) {
         s.pre_built = true;
     }
     if ((precond & 4) && !s.sin_built) {
+        const auto t0 = std::chrono::steady_clock::now();
         schwarz_build(p, s.sin, mi, ri, si);
         s.sin_built = true;
+        if (std::getenv("SIE_TRACE"))
+            std::fprintf(stderr, "[setup] %-28s %8.1f ms\n", "Schwarz clusters",
+                         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
     }
 }
 
@@ -876,9 +894,15 @@ static void solve_all(sie_problem *p, sie_precision prec, const sie_solver_opts 
                 const double need = res[k] > 0.0 ? o.tol / res[k] : 1.0;
                 stol[k] = prec == SIE_FP32 ? std::max(need, 1e-3) : need;
             }
+            if (o32 && o.inner_relax > 0.0) {
+                o32->relax_eps.resize(cnt);
+                for (int k = 0; k < cnt; ++k) o32->relax_eps[k] = o.inner_relax * stol[k];
+                o32->relax_res = &g.live;
+            }
             outer_total += g.solve([&](const c128 *x, c128 *y) { o64.gibc(x, y); },
                                    [&](const c128 *x, c128 *y) { o64.prec_outer(x, y); }, r1.p, du.p, stol,
                                    o.max_iter, nullptr, st, nullptr, true);
+            if (o32) o32->relax_res = nullptr;
             // dv = Lhat^-1 (r2 + (K_i + X/2) du)
             o64.KpX(true, +1.0, du.p, o64.t[3]);
             launch_axpby<double>(NE, c128(1.0), r2.p, c128(1.0), o64.t[3], st);
@@ -989,7 +1013,7 @@ void solve_entry(sie_problem *p, sie_precision prec, const sie_solver_opts *opts
     SIE_CHECK(p && p->is_setup, SIE_ESTATE, "problem not set up");
     SIE_CHECK(p->solve && p->solve->nrhs > 0, SIE_ESTATE, "no plane waves set");
     SIE_CHECK(prec == SIE_FP64 || prec == SIE_FP32, SIE_EINVAL, "unknown precision");
-    sie_solver_opts o{1e-6, 1e-8, 100, 800, 800, 10, 0};
+    sie_solver_opts o{1e-6, 1e-8, 100, 800, 800, 10, 0, 0.0};
     if (opts) {
         if (opts->tol > 0) o.tol = opts->tol;
         if (opts->inner_tol > 0) o.inner_tol = opts->inner_tol;
@@ -998,6 +1022,8 @@ void solve_entry(sie_problem *p, sie_precision prec, const sie_solver_opts *opts
         if (opts->inner_max_iter > 0) o.inner_max_iter = opts->inner_max_iter;
         if (opts->max_refine > 0) o.max_refine = opts->max_refine;
         o.precond = opts->precond;
+        SIE_CHECK(opts->inner_relax >= 0.0, SIE_EINVAL, "inner_relax must be non-negative");
+        o.inner_relax = opts->inner_relax;
     }
     SIE_CHECK(o.precond >= 0 && o.precond <= 7, SIE_EINVAL, "unknown preconditioner");
     SIE_CHECK((o.precond & 5) != 5, SIE_EINVAL, "nested block-Jacobi (1) and nested Schwarz clusters (4) exclude each other");

@@ -39,7 +39,7 @@ class QuadParams(ctypes.Structure):
 class SolverOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("inner_tol", ctypes.c_double), ("restart", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("inner_max_iter", ctypes.c_int32),
-                ("max_refine", ctypes.c_int32), ("precond", ctypes.c_int32)]
+                ("max_refine", ctypes.c_int32), ("precond", ctypes.c_int32), ("inner_relax", ctypes.c_double)]
 
 
 class Report(ctypes.Structure):

@@ -142,3 +142,25 @@ def test_rcs_against_mie(solved):
         mr = mie.bistatic_rcs(k0, 1.0, eps_r, th, phi + 0 * th)
         err2 += np.sum((r - mr) ** 2); ref2 += np.sum(mr ** 2)
     assert np.sqrt(err2 / ref2) < 0.10
+
+
+def test_relaxed_nested_tolerance(solved):
+    """FP32 with the nested tolerance relaxed along the outer residual
+    (inexact Krylov): same convergence test in FP64, same agreement with the
+    FP64 solution as the fixed tolerance, no more nested iterations; a
+    negative relaxation factor is rejected.  Runs last: it replaces the
+    problems' solutions."""
+    from paper_2003_11679_amd import SieError
+    for name, s in solved.items():
+        p = s["p"]
+        r = p.solve(1, inner_relax=0.1)
+        u, v = p.currents()
+        print(f"{name}: relaxed {r} fixed {s['r32']}", flush=True)
+        assert r["converged"] and r["residual"] <= 1e-5, (name, r)
+        assert r["inner_iters"] <= s["r32"]["inner_iters"] + 5, (name, r, s["r32"])
+        tol = 1e-3 if name == "box_cond" else 2e-5
+        for a, b in ((u, s["u64"]), (v, s["v64"])):
+            err = np.linalg.norm(a - b) / np.linalg.norm(b)
+            assert err <= tol, (name, err)
+    with pytest.raises(SieError):
+        solved["sphere2"]["p"].solve(1, inner_relax=-1.0)
