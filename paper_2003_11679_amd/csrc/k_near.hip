@@ -381,11 +381,12 @@ __device__ inline int classify(const NearFillArgs &a, int64_t tg, int64_t sg, in
 }
 
 // Direct integrals of pair (tl, sl) minus its grid contribution; writes the
-// L, K and direct-L 3x3 blocks of pair slot p.  mt: moments of tl (LDS or
-// global); gr: radial tables in LDS, gr[2 q] = G(h sqrt(q)), gr[2 q + 1] =
-// -(1 + j k r) exp(-j k r)/(4 pi r^3) at r = h sqrt(q), q = |d|^2 (0 at q = 0).
+// L, K and direct-L 3x3 blocks of pair slot p.  The grid contribution reads
+// the test-node sums of tl from a.ptab (k_precorr_table); gr: radial tables
+// in LDS, gr[2 q] = G(h sqrt(q)), gr[2 q + 1] = -(1 + j k r) exp(-j k r)/(4 pi
+// r^3) at r = h sqrt(q), q = |d|^2 (0 at q = 0).
 __device__ void fill_pair(const NearFillArgs &a, int64_t tl, int64_t sl, int64_t p, int kind, int loc,
-                          const double *mt, const c128 *gr) {
+                          const c128 *gr) {
     const int64_t tg = a.tris[tl], sg = a.tris[sl];
     const V3 o = {a.centroid[3 * tg], a.centroid[3 * tg + 1], a.centroid[3 * tg + 2]};
     V3 pt[3], ps[3];
@@ -473,33 +474,26 @@ __device__ void fill_pair(const NearFillArgs &a, int64_t tl, int64_t sl, int64_t
     const int dx0 = a.centre[3 * tl] - a.centre[3 * sl];
     const int dy0 = a.centre[3 * tl + 1] - a.centre[3 * sl + 1];
     const int dz0 = a.centre[3 * tl + 2] - a.centre[3 * sl + 2];
-    const double h = a.h;
     c128 S00, S11, C11;
     CV3 S10 = {}, S01 = {}, Vs = {}, Vt = {}, U = {};
     // The sums over node pairs factor through the source node b: for each b
-    // the test-node sums Gb0 = sum_a m0t G, Gb1 = sum_a m1t G,
-    // gb0 = sum_a m0t g and gb1x = sum_a g x m1t, then
+    // the test-node sums at offset e = (c_t - c_s) - o_b (from the row's
+    // table) Gb0 = sum_a m0t G, Gb1 = sum_a m1t G, gb0 = sum_a m0t g and
+    // gb1x = sum_a g x m1t, then
     //   S00 += m0s Gb0, S01 += m1s Gb0, S10 += m0s Gb1, S11 += m1s . Gb1,
     //   U += m0s gb0, Vs += gb0 x m1s, Vt -= m0s gb1x, C11 -= m1s . gb1x
     // (g . (m1s x m1t) = -m1s . (g x m1t)).
+    const int W = a.tab_w, S = 2 * W + 1;
+    const c128 *tt = a.ptab + (tl - a.tab_row0) * (int64_t)(S * S * S) * 10;
     const double *ms = a.mom + sl * 27 * 4;
     for (int ib = 0; ib < 27; ++ib) {
         const int bx = ib % 3 - 1, by = (ib / 3) % 3 - 1, bz = ib / 9 - 1;
-        c128 Gb0;
-        CV3 Gb1 = {}, gb0 = {}, gb1x = {};
-        for (int ia = 0; ia < 27; ++ia) {
-            const int ddx = dx0 + ia % 3 - 1 - bx, ddy = dy0 + (ia / 3) % 3 - 1 - by, ddz = dz0 + ia / 9 - 1 - bz;
-            const int q = ddx * ddx + ddy * ddy + ddz * ddz;
-            const c128 G = gr[2 * q];
-            const c128 sr = gr[2 * q + 1];
-            const CV3 g = {(h * ddx) * sr, (h * ddy) * sr, (h * ddz) * sr};
-            const double m0t = mt[4 * ia];
-            const V3 m1t = {mt[4 * ia + 1], mt[4 * ia + 2], mt[4 * ia + 3]};
-            Gb0 += m0t * G;
-            cadd(Gb1, cscale(G, m1t));
-            cadd(gb0, CV3{m0t * g.x, m0t * g.y, m0t * g.z});
-            cadd(gb1x, ccross_cv(g, m1t));
-        }
+        // near pairs lie within the near radius per axis, so |e| <= W; the
+        // clamps only keep the read inside the table
+        const int ex = min(max(dx0 - bx, -W), W), ey = min(max(dy0 - by, -W), W), ez = min(max(dz0 - bz, -W), W);
+        const c128 *te = tt + ((int64_t)((ez + W) * S + (ey + W)) * S + (ex + W)) * 10;
+        const c128 Gb0 = te[0];
+        const CV3 Gb1 = {te[1], te[2], te[3]}, gb0 = {te[4], te[5], te[6]}, gb1x = {te[7], te[8], te[9]};
         const double m0s = ms[4 * ib];
         const V3 m1s = {ms[4 * ib + 1], ms[4 * ib + 2], ms[4 * ib + 3]};
         S00 += m0s * Gb0;
@@ -572,23 +566,69 @@ __global__ void k_near_classify(NearFillArgs a, int64_t ntg, int pass, unsigned 
     }
 }
 
-// Far pairs: one workgroup per row triangle; its moments and the radial
-// tables live in LDS.
-__global__ void __launch_bounds__(128) k_near_fill_far(NearFillArgs a, int64_t ntg) {
+// Test-node sums of the precorrection (eq. LinNRP / KinNRP) for row triangle
+// row0 + blockIdx.x and every offset e in [-W, W]^3 between its stencil centre
+// and a source stencil node (W = near radius + 1): with G and g the Green's
+// function and its gradient at the node offset e + o_a,
+//   [0] sum_a m0t G, [1..3] sum_a G m1t, [4..6] sum_a m0t g, [7..9] sum_a g x m1t
+// over the 27 test nodes a.  Every source triangle of the row with the same
+// offset reuses them.
+__global__ void __launch_bounds__(256) k_precorr_table(NearFillArgs a, int64_t row0, c128 *tab) {
     extern __shared__ unsigned char smem[];
     c128 *gr = reinterpret_cast<c128 *>(smem);
     double *mt = reinterpret_cast<double *>(gr + 2 * a.nq);
+    const int64_t tl = row0 + blockIdx.x;
+    load_radial(a.gradial, a.nq, gr);
+    for (int i = threadIdx.x; i < 108; i += blockDim.x) mt[i] = a.mom[tl * 108 + i];
+    __syncthreads();
+    const int W = a.tab_w, S = 2 * W + 1, NT = S * S * S;
+    const double h = a.h;
+    for (int idx = threadIdx.x; idx < NT; idx += blockDim.x) {
+        const int ex = idx % S - W, ey = (idx / S) % S - W, ez = idx / (S * S) - W;
+        c128 Gb0;
+        CV3 Gb1 = {}, gb0 = {}, gb1x = {};
+        for (int ia = 0; ia < 27; ++ia) {
+            const int ddx = ex + ia % 3 - 1, ddy = ey + (ia / 3) % 3 - 1, ddz = ez + ia / 9 - 1;
+            const int q = ddx * ddx + ddy * ddy + ddz * ddz;
+            const c128 G = gr[2 * q];
+            const c128 sr = gr[2 * q + 1];
+            const CV3 g = {(h * ddx) * sr, (h * ddy) * sr, (h * ddz) * sr};
+            const double m0t = mt[4 * ia];
+            const V3 m1t = {mt[4 * ia + 1], mt[4 * ia + 2], mt[4 * ia + 3]};
+            Gb0 += m0t * G;
+            cadd(Gb1, cscale(G, m1t));
+            cadd(gb0, CV3{m0t * g.x, m0t * g.y, m0t * g.z});
+            cadd(gb1x, ccross_cv(g, m1t));
+        }
+        c128 *o = tab + ((int64_t)blockIdx.x * NT + idx) * 10;
+        o[0] = Gb0;
+        o[1] = Gb1.x; o[2] = Gb1.y; o[3] = Gb1.z;
+        o[4] = gb0.x; o[5] = gb0.y; o[6] = gb0.z;
+        o[7] = gb1x.x; o[8] = gb1x.y; o[9] = gb1x.z;
+    }
+}
+
+void launch_precorr_table(const NearFillArgs &a, int64_t row0, int64_t nrows, c128 *tab, hipStream_t st) {
+    if (nrows <= 0) return;
+    const size_t sh = 2 * (size_t)a.nq * sizeof(c128) + 108 * sizeof(double);
+    hipLaunchKernelGGL(k_precorr_table, dim3((unsigned)nrows), dim3(256), sh, st, a, row0, tab);
+    SIE_HIP(hipGetLastError());
+}
+
+// Far pairs: one workgroup per row triangle; the radial tables live in LDS.
+__global__ void __launch_bounds__(128) k_near_fill_far(NearFillArgs a, int64_t ntg) {
+    extern __shared__ unsigned char smem[];
+    c128 *gr = reinterpret_cast<c128 *>(smem);
     const int64_t tl = blockIdx.x;
     if (tl >= ntg) return;
     load_radial(a.gradial, a.nq, gr);
-    for (int i = threadIdx.x; i < 108; i += blockDim.x) mt[i] = a.mom[tl * 108 + i];
     __syncthreads();
     const int64_t tg = a.tris[tl];
     for (int64_t p = a.pair_ptr[tl] + threadIdx.x; p < a.pair_ptr[tl + 1]; p += blockDim.x) {
         const int64_t sl = a.pair_s[p];
         int loc;
         if (classify(a, tg, a.tris[sl], loc) != KIND_FAR) continue;
-        fill_pair(a, tl, sl, p, KIND_FAR, 0, mt, gr);
+        fill_pair(a, tl, sl, p, KIND_FAR, 0, gr);
     }
 }
 
@@ -609,7 +649,7 @@ __global__ void __launch_bounds__(128) k_near_fill_list(NearFillArgs a, int64_t 
         const int64_t mid = (lo + hi) >> 1;
         if (a.pair_ptr[mid] <= p) lo = mid; else hi = mid;
     }
-    fill_pair(a, lo, a.pair_s[p], p, kind, loc, a.mom + lo * 108, gr);
+    fill_pair(a, lo, a.pair_s[p], p, kind, loc, gr);
 }
 
 void launch_green_radial(c128 k, double h, int nq, c128 *gr, hipStream_t st) {
@@ -637,7 +677,7 @@ void launch_near_fill(const NearFillArgs &a, int64_t npairs, hipStream_t st) {
                        lists[1].p, lists[2].p, lists[3].p);
     SIE_HIP(hipGetLastError());
     // far pairs per row triangle
-    hipLaunchKernelGGL(k_near_fill_far, dim3((unsigned)ntg), dim3(128), sh_rad + 108 * sizeof(double), st, a, ntg);
+    hipLaunchKernelGGL(k_near_fill_far, dim3((unsigned)ntg), dim3(128), sh_rad, st, a, ntg);
     SIE_HIP(hipGetLastError());
     for (int kd = 0; kd < 4; ++kd) {
         if (!cnt[kd]) continue;

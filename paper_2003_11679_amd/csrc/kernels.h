@@ -64,7 +64,12 @@ struct NearFillArgs {
     c128 *blocks;                    // [npairs][3][3][3]: L, K (precorrected), L direct
     int polar;                       // medium lossy enough for the strong-loss inner scheme
     const double *polar_gl;          // its Gauss-Legendre nodes [8] and weights [8] on [-1, 1]
+    // precorrection test-node sums of rows [tab_row0, tab_row0 + rows):
+    // [row][(2 tab_w + 1)^3 offsets][10], tab_w = near radius + 1
+    const c128 *ptab; int64_t tab_row0; int tab_w;
 };
+// Fills ptab's rows (the test-node sums every pair of those rows reads).
+void launch_precorr_table(const NearFillArgs &a, int64_t row0, int64_t nrows, c128 *tab, hipStream_t st);
 void launch_near_fill(const NearFillArgs &a, int64_t npairs, hipStream_t st);
 void launch_near_gather(int64_t nrow, int64_t rwg0, int64_t max_row, const int64_t *row_ptr, const int32_t *cols,
                         const int32_t *rwg_loc, const int32_t *glob2loc, const int32_t *tpm, const int32_t *epm,

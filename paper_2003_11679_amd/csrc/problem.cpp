@@ -314,17 +314,19 @@ static void build_medium(sie_problem *p, Medium &md) {
     // process row triangles in chunks to bound the pair-block buffer
     setup_mark("medium: alloc + clear");
     std::vector<int64_t> pptr = g.d_pair_ptr.download();
-    std::vector<int32_t> rwgloc = g.d_rwgloc.download();
-    setup_mark("fill: downloads");
     const int64_t max_chunk = 30000000;  // pair blocks of one chunk: 13 GB of HBM at most
-    DBuf<c128> blocks;
+    DBuf<c128> blocks, ptab;
     DBuf<int64_t> d_pp;
-    DBuf<int32_t> d_rwgloc_chunk;
     const int64_t nrow = g.rwg1 - g.rwg0;
+    // precorrection tables: (2 (R + 1) + 1)^3 offsets x 10 sums per row, rows
+    // of one chunk within 4 GB
+    const int tab_w = g.near_radius + 1;
+    const int64_t tab_row = (int64_t)(2 * tab_w + 1) * (2 * tab_w + 1) * (2 * tab_w + 1) * 10;
+    const int64_t max_rows = std::max<int64_t>(1, (int64_t)(4e9 / (double)(tab_row * sizeof(c128))));
     int64_t t0 = 0;
     while (t0 < ntg) {
         int64_t t1 = t0 + 1;
-        while (t1 < ntg && pptr[t1 + 1] - pptr[t0] <= max_chunk) ++t1;
+        while (t1 < ntg && pptr[t1 + 1] - pptr[t0] <= max_chunk && t1 - t0 < max_rows) ++t1;
         const int64_t np = pptr[t1] - pptr[t0];
         // chunk-relative pair pointers over all rows (rows outside the chunk empty)
         std::vector<int64_t> cp(ntg + 1);
@@ -341,6 +343,10 @@ static void build_medium(sie_problem *p, Medium &md) {
         a.blocks = blocks.p;
         a.polar = polar;
         a.polar_gl = d_gl.p;
+        ptab.alloc((t1 - t0) * tab_row);
+        a.ptab = ptab.p; a.tab_row0 = t0; a.tab_w = tab_w;
+        launch_precorr_table(a, t0, t1 - t0, ptab.p, 0);
+        setup_mark("fill: precorrection tables");
         launch_near_fill(a, np, 0);
         setup_mark("fill: pair blocks");
         launch_near_gather(nrow, g.rwg0, g.max_row, g.d_row_ptr.p, g.d_cols.p, g.d_rwgloc.p, g.d_glob2loc.p,
