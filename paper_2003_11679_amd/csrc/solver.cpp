@@ -887,12 +887,15 @@ static void solve_all(sie_problem *p, sie_precision prec, const sie_solver_opts 
             // hand back when a correction stalls for longer than a plateau
             g.stag_window = prec == SIE_FP32 ? 100 : 0;
             // relative tolerance of each correction solve: what is left to the
-            // target, but at most three digits per FP32 sweep (its interior
-            // products carry FP32 rounding)
+            // target, but in FP32 (its interior products carry FP32 rounding)
+            // no tighter than 0.63 sqrt(tol), so that two sweeps reach tol
+            // with a margin of 2.5, clamped to [2e-4, 1e-3] (tighter FP32
+            // corrections of the low-frequency EFIE stall and cost a sweep)
+            const double floor32 = std::min(1e-3, std::max(2e-4, 0.63 * std::sqrt(o.tol)));
             std::vector<double> stol(cnt);
             for (int k = 0; k < cnt; ++k) {
                 const double need = res[k] > 0.0 ? o.tol / res[k] : 1.0;
-                stol[k] = prec == SIE_FP32 ? std::max(need, 1e-3) : need;
+                stol[k] = prec == SIE_FP32 ? std::max(need, floor32) : need;
             }
             if (o32 && o.inner_relax > 0.0) {
                 o32->relax_eps.resize(cnt);
