@@ -288,78 +288,133 @@ __global__ __launch_bounds__(512) void k_ras_gather(int c0, const int64_t *__res
     }
 }
 
-__global__ __launch_bounds__(1024) void k_ras_invert(int c0, const int64_t *__restrict__ ext_off,
-                                                    const int32_t *__restrict__ own_off,
-                                                    const int64_t *__restrict__ ws_off,
-                                                    const int64_t *__restrict__ m_off, c128 *__restrict__ ws,
-                                                    c128 *__restrict__ m64, c64 *__restrict__ m32,
-                                                    int *__restrict__ fail) {
-    __shared__ __align__(16) double lds[2 * (3 * kRasMax + 1)];
-    c128 *prow = reinterpret_cast<c128 *>(lds);          // [2 kRasMax] scaled pivot row
-    c128 *fcol = prow + 2 * kRasMax;                     // [kRasMax] column k
-    c128 *pinv = fcol + kRasMax;                         // 1 / pivot
+// Blocked Gauss-Jordan with partial pivoting.  Panels of bw pivot columns
+// are factored in LDS: row swaps, the scaled pivot rows and, in place, the
+// multiplier of every other row at each step.  Then the thread that owns a
+// trailing column brings it up to date in one pass: the swaps in order, the
+// bw scaled pivot rows R in registers, every other row minus its multipliers
+// times R.  The subtractions per element come in the same order as pivot by
+// pivot elimination, but the matrix streams once per panel instead of once
+// per pivot.
+constexpr int kPanelElems = 4096;   // n x bw complex128 panel: 64 KB of LDS
+constexpr int kPanelMax = 16;
+
+__global__ __launch_bounds__(512) void k_ras_invert(int c0, const int64_t *__restrict__ ext_off,
+                                                   const int32_t *__restrict__ own_off,
+                                                   const int64_t *__restrict__ ws_off,
+                                                   const int64_t *__restrict__ m_off, c128 *__restrict__ ws,
+                                                   c128 *__restrict__ m64, c64 *__restrict__ m32,
+                                                   int *__restrict__ fail) {
+    __shared__ __align__(16) double lds[2 * (kPanelElems + kPanelMax)];
+    c128 *P = reinterpret_cast<c128 *>(lds);      // [n][bw] panel
+    c128 *sinv = P + kPanelElems;                 // [bw] 1 / pivot
+    __shared__ int swp[kPanelMax];
     __shared__ double rv[16];
     __shared__ int ri[16];
-    __shared__ int piv;
     const int c = c0 + blockIdx.x;
     const int n = (int)(ext_off[c + 1] - ext_off[c]);
     const int no = own_off[c + 1] - own_off[c];
     const int W = n + no;
     c128 *B = ws + (ws_off[c] - ws_off[c0]);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
-    for (int k = 0; k < n; ++k) {
-        // pivot: largest |B[i][k]|, i >= k (lowest index among equals)
-        double best = -1.0;
-        int bi = n;
-        for (int i = k + tid; i < n; i += blockDim.x) {
-            const double v = norm2(B[(int64_t)i * W + k]);
-            if (v > best) { best = v; bi = i; }
-        }
-        for (int off = 32; off > 0; off >>= 1) {
-            const double ov = __shfl_down(best, off);
-            const int oi = __shfl_down(bi, off);
-            if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
-        }
-        if (lane == 0) { rv[wv] = best; ri[wv] = bi; }
-        __syncthreads();
-        if (tid == 0) {
-            double b = rv[0];
-            int p = ri[0];
-            for (int w = 1; w < nw; ++w)
-                if (rv[w] > b || (rv[w] == b && ri[w] < p)) { b = rv[w]; p = ri[w]; }
-            piv = p;
-            if (!(b > 0.0)) *fail = 1;
+    int bwmax = kPanelMax;                  // n <= kRasMax = 2048: width 2 always fits
+    while (bwmax > 2 && n * bwmax > kPanelElems) bwmax >>= 1;
+    for (int kb = 0; kb < n; kb += bwmax) {
+        const int bw = min(bwmax, n - kb);
+        for (int t = tid; t < n * bw; t += blockDim.x) {
+            const int i = t / bw, jj = t - i * bw;
+            P[t] = B[(int64_t)i * W + kb + jj];
         }
         __syncthreads();
-        const int pr = piv;
-        if (pr != k)
-            for (int j = k + tid; j < W; j += blockDim.x) {
-                const c128 t = B[(int64_t)k * W + j];
-                B[(int64_t)k * W + j] = B[(int64_t)pr * W + j];
-                B[(int64_t)pr * W + j] = t;
+        for (int jj = 0; jj < bw; ++jj) {
+            const int k = kb + jj;
+            // pivot: largest |P[i][jj]|, i >= k (lowest index among equals)
+            double best = -1.0;
+            int bi = n;
+            for (int i = k + tid; i < n; i += blockDim.x) {
+                const double v = norm2(P[i * bw + jj]);
+                if (v > best) { best = v; bi = i; }
             }
-        __syncthreads();
-        if (tid == 0) {
-            const c128 d = B[(int64_t)k * W + k];
-            *pinv = norm2(d) > 0.0 ? cdiv(c128(1.0), d) : c128();
+            for (int off = 32; off > 0; off >>= 1) {
+                const double ov = __shfl_down(best, off);
+                const int oi = __shfl_down(bi, off);
+                if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+            }
+            if (lane == 0) { rv[wv] = best; ri[wv] = bi; }
+            __syncthreads();
+            if (tid == 0) {
+                double bb = rv[0];
+                int pp = ri[0];
+                for (int w = 1; w < nw; ++w)
+                    if (rv[w] > bb || (rv[w] == bb && ri[w] < pp)) { bb = rv[w]; pp = ri[w]; }
+                swp[jj] = pp;
+                if (!(bb > 0.0)) *fail = 1;
+            }
+            __syncthreads();
+            const int pr = swp[jj];
+            if (pr != k && tid < bw) {   // whole panel rows, multipliers included
+                const c128 t = P[k * bw + tid];
+                P[k * bw + tid] = P[pr * bw + tid];
+                P[pr * bw + tid] = t;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                const c128 d = P[k * bw + jj];
+                sinv[jj] = norm2(d) > 0.0 ? cdiv(c128(1.0), d) : c128();
+            }
+            __syncthreads();
+            if (tid > jj && tid < bw) P[k * bw + tid] = sinv[jj] * P[k * bw + tid];
+            __syncthreads();
+            // other rows, remaining panel columns; P[i][jj] keeps the multiplier
+            const int rem = bw - jj - 1;
+            if (rem > 0)
+                for (int t = tid; t < n * rem; t += blockDim.x) {
+                    const int i = t / rem, j2 = jj + 1 + (t - i * rem);
+                    if (i != k) P[i * bw + j2] -= P[i * bw + jj] * P[k * bw + j2];
+                }
+            __syncthreads();
         }
-        __syncthreads();
-        const c128 s = *pinv;
-        for (int j = k + 1 + tid; j < W; j += blockDim.x) {
-            const c128 v = s * B[(int64_t)k * W + j];
-            prow[j] = v;
-            B[(int64_t)k * W + j] = v;
+        // trailing columns
+        for (int j = kb + bw + tid; j < W; j += blockDim.x) {
+            for (int jj = 0; jj < bw; ++jj) {
+                const int pr = swp[jj];
+                if (pr != kb + jj) {
+                    const c128 t = B[(int64_t)(kb + jj) * W + j];
+                    B[(int64_t)(kb + jj) * W + j] = B[(int64_t)pr * W + j];
+                    B[(int64_t)pr * W + j] = t;
+                }
+            }
+            c128 R[kPanelMax];
+#pragma unroll
+            for (int jj = 0; jj < kPanelMax; ++jj) {
+                if (jj < bw) {
+                    c128 x = B[(int64_t)(kb + jj) * W + j];
+#pragma unroll
+                    for (int q = 0; q < kPanelMax; ++q)
+                        if (q < jj) x -= P[(kb + jj) * bw + q] * R[q];
+                    R[jj] = sinv[jj] * x;
+                }
+            }
+            for (int i = 0; i < n; ++i) {
+                if (i >= kb && i < kb + bw) continue;
+                c128 acc = B[(int64_t)i * W + j];
+#pragma unroll
+                for (int q = 0; q < kPanelMax; ++q)
+                    if (q < bw) acc -= P[i * bw + q] * R[q];
+                B[(int64_t)i * W + j] = acc;
+            }
+#pragma unroll
+            for (int jj = 0; jj < kPanelMax; ++jj) {
+                if (jj < bw) {
+                    c128 x = R[jj];
+#pragma unroll
+                    for (int q = 0; q < kPanelMax; ++q)
+                        if (q > jj && q < bw) x -= P[(kb + jj) * bw + q] * R[q];
+                    B[(int64_t)(kb + jj) * W + j] = x;
+                }
+            }
         }
-        for (int i = tid; i < n; i += blockDim.x) fcol[i] = i == k ? c128() : B[(int64_t)i * W + k];
-        __syncthreads();
-        // eliminate column k from every other row: one wave per row segment
-        for (int i = wv; i < n; i += nw) {
-            if (i == k) continue;
-            const c128 f = fcol[i];
-            c128 *row = B + (int64_t)i * W;
-            for (int j = k + 1 + lane; j < W; j += 64) row[j] -= f * prow[j];
-        }
-        __syncthreads();
+        __syncthreads();   // trailing columns complete before the next panel load
     }
     // Y = right block (n x no); row q of the kept inverse is column q of Y
     const int64_t mo = m_off[c];
@@ -379,7 +434,7 @@ void launch_ras_setup(int c0, int cnt, const int64_t *ext_off, const int32_t *ex
     hipLaunchKernelGGL(k_ras_gather, dim3(cnt), dim3(512), 0, st, c0, ext_off, ext, own_off, own_pos, ws_off, rwg0,
                        row_ptr, cols, vals, scale, ws);
     SIE_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_ras_invert, dim3(cnt), dim3(1024), 0, st, c0, ext_off, own_off, ws_off, m_off, ws, m64, m32,
+    hipLaunchKernelGGL(k_ras_invert, dim3(cnt), dim3(512), 0, st, c0, ext_off, own_off, ws_off, m_off, ws, m64, m32,
                        fail);
     SIE_HIP(hipGetLastError());
 }
