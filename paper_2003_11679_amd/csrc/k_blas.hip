@@ -99,30 +99,41 @@ void launch_dots(int64_t n, int J, const cx<T> *V, int64_t ldv, const cx<T> *w, 
     launch_dots_sys<T>(n, J, V, ldv, 1, w, part, nb, h, J, st);
 }
 
-// w[s] += SGN sum_j V_j[s] h[s * hstride + j]
+// w[s] += SGN sum_j V_j[s] h[s * hstride + j].  A workgroup covers 64
+// elements; its 4 waves take every fourth j (FP64 partial sums), and wave 0
+// adds the 4 partials in a fixed order.
 template <typename T, int SGN>
-__global__ void k_gemv(int64_t n, int J, const cx<T> *__restrict__ V, int64_t ldv, const c128 *__restrict__ h,
-                       int hstride, cx<T> *__restrict__ w) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
+__global__ __launch_bounds__(256) void k_gemv(int64_t n, int J, const cx<T> *__restrict__ V, int64_t ldv,
+                                              const c128 *__restrict__ h, int hstride, cx<T> *__restrict__ w) {
+    __shared__ double pre[4][64], pim[4][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t i = blockIdx.x * (int64_t)64 + lane;
     const int s = blockIdx.y;
     V += s * n;
     h += (int64_t)s * hstride;
     w += s * n;
     double re = 0, im = 0;
-    for (int j = 0; j < J; ++j) {
-        const cx<T> v = V[j * ldv + i];
-        const c128 c = h[j];
-        re += v.re * c.re - v.im * c.im;
-        im += v.re * c.im + v.im * c.re;
+    if (i < n)
+        for (int j = wv; j < J; j += 4) {
+            const cx<T> v = V[j * ldv + i];
+            const c128 c = h[j];
+            re += v.re * c.re - v.im * c.im;
+            im += v.re * c.im + v.im * c.re;
+        }
+    pre[wv][lane] = re;
+    pim[wv][lane] = im;
+    __syncthreads();
+    if (wv == 0 && i < n) {
+        const double sr = ((pre[0][lane] + pre[1][lane]) + pre[2][lane]) + pre[3][lane];
+        const double si = ((pim[0][lane] + pim[1][lane]) + pim[2][lane]) + pim[3][lane];
+        w[i] = cx<T>((T)(w[i].re + SGN * sr), (T)(w[i].im + SGN * si));
     }
-    w[i] = cx<T>((T)(w[i].re + SGN * re), (T)(w[i].im + SGN * im));
 }
 template <typename T>
 void launch_gemv_sys(int64_t n, int J, const cx<T> *V, int64_t ldv, int ns, const c128 *h, int hstride, cx<T> *w,
                      bool add, hipStream_t st) {
     if (J <= 0 || n <= 0 || ns <= 0) return;
-    const dim3 grid((unsigned)((n + 255) / 256), (unsigned)ns);
+    const dim3 grid((unsigned)((n + 63) / 64), (unsigned)ns);
     if (add) hipLaunchKernelGGL((k_gemv<T, 1>), grid, dim3(256), 0, st, n, J, V, ldv, h, hstride, w);
     else hipLaunchKernelGGL((k_gemv<T, -1>), grid, dim3(256), 0, st, n, J, V, ldv, h, hstride, w);
     SIE_HIP(hipGetLastError());
