@@ -181,6 +181,9 @@ struct Grid {
     DBuf<int64_t> d_pair_ptr;  // [ntg + 1]
     DBuf<int32_t> d_pair_s;    // [npairs]
     int64_t npairs = 0;
+    // kind | loc << 4 of every near pair (geometry only: built once, with
+    // the first medium, and shared by the others)
+    DBuf<uint8_t> d_pair_kind; // [npairs]
     // RWG near pattern (global RWG rows of the grid's objects)
     int64_t rwg0 = 0, rwg1 = 0; // RWG range [rwg0, rwg1)
     DBuf<int64_t> d_row_ptr;   // [nrow + 1] (row r = RWG rwg0 + r)

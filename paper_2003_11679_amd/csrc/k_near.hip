@@ -548,20 +548,53 @@ __device__ inline void load_radial(const c128 *g, int nq, c128 *lds) {
     for (int i = threadIdx.x; i < 2 * nq; i += blockDim.x) lds[i] = g[i];
 }
 
-// Pass 0 counts, pass 1 appends, the non-far pairs of each kind (lists[kind]).
-__global__ void k_near_classify(NearFillArgs a, int64_t ntg, int pass, unsigned long long *counts,
-                                int64_t *lists0, int64_t *lists1, int64_t *lists2, int64_t *lists3) {
+// kinds[p] = kind | loc << 4 of every pair of row triangle blockIdx.x.
+__global__ void k_pair_kinds(NearFillArgs a, int64_t ntg, uint8_t *kinds) {
     const int64_t tl = blockIdx.x;
     if (tl >= ntg) return;
     const int64_t tg = a.tris[tl];
     for (int64_t p = a.pair_ptr[tl] + threadIdx.x; p < a.pair_ptr[tl + 1]; p += blockDim.x) {
         int loc;
         const int kind = classify(a, tg, a.tris[a.pair_s[p]], loc);
-        if (kind == KIND_FAR) continue;
-        const unsigned long long i = atomicAdd(&counts[kind], 1ull);
-        if (pass == 1) {
-            int64_t *L = kind == 0 ? lists0 : (kind == 1 ? lists1 : (kind == 2 ? lists2 : lists3));
-            L[i] = (p << 2) | loc;
+        kinds[p] = (uint8_t)(kind | (loc << 4));
+    }
+}
+
+void launch_pair_kinds(const NearFillArgs &a, uint8_t *kinds, hipStream_t st) {
+    if (a.ntg <= 0) return;
+    hipLaunchKernelGGL(k_pair_kinds, dim3((unsigned)a.ntg), dim3(128), 0, st, a, a.ntg, kinds);
+    SIE_HIP(hipGetLastError());
+}
+
+// Pass 0 counts, pass 1 appends, the non-far pairs of each kind (lists[kind]).
+// One atomic per wave and kind: the lanes of a kind take consecutive slots
+// after the wave's base (ballot and population count).
+__global__ void k_near_classify(NearFillArgs a, int64_t ntg, int pass, unsigned long long *counts,
+                                int64_t *lists0, int64_t *lists1, int64_t *lists2, int64_t *lists3) {
+    const int64_t tl = blockIdx.x;
+    if (tl >= ntg) return;
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const int64_t p0 = a.pair_ptr[tl], p1 = a.pair_ptr[tl + 1];
+    for (int64_t base = p0; base < p1; base += blockDim.x) {   // same trip count for every lane
+        const int64_t p = base + threadIdx.x;
+        int kind = KIND_FAR, loc = 0;
+        if (p < p1) {
+            const int b = a.pkind[p];
+            kind = b & 15;
+            loc = b >> 4;
+        }
+        for (int kd = 0; kd < 4; ++kd) {
+            const unsigned long long m = __ballot(kind == kd);
+            if (!m) continue;
+            const int leader = __ffsll((long long)m) - 1;
+            unsigned long long off = 0;
+            if (lane == leader) off = atomicAdd(&counts[kd], (unsigned long long)__popcll(m));
+            off = __shfl(off, leader);
+            if (pass == 1 && kind == kd) {
+                int64_t *L = kd == 0 ? lists0 : (kd == 1 ? lists1 : (kd == 2 ? lists2 : lists3));
+                L[off + __popcll(m & below)] = (p << 2) | loc;
+            }
         }
     }
 }
@@ -623,11 +656,9 @@ __global__ void __launch_bounds__(128) k_near_fill_far(NearFillArgs a, int64_t n
     if (tl >= ntg) return;
     load_radial(a.gradial, a.nq, gr);
     __syncthreads();
-    const int64_t tg = a.tris[tl];
     for (int64_t p = a.pair_ptr[tl] + threadIdx.x; p < a.pair_ptr[tl + 1]; p += blockDim.x) {
         const int64_t sl = a.pair_s[p];
-        int loc;
-        if (classify(a, tg, a.tris[sl], loc) != KIND_FAR) continue;
+        if ((a.pkind[p] & 15) != KIND_FAR) continue;
         fill_pair(a, tl, sl, p, KIND_FAR, 0, gr);
     }
 }

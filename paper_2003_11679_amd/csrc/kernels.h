@@ -67,7 +67,10 @@ struct NearFillArgs {
     // precorrection test-node sums of rows [tab_row0, tab_row0 + rows):
     // [row][(2 tab_w + 1)^3 offsets][10], tab_w = near radius + 1
     const c128 *ptab; int64_t tab_row0; int tab_w;
+    const uint8_t *pkind;            // kind | loc << 4 of pair slot p (same offset as pair_s)
 };
+// kinds[p] = kind | loc << 4 for every pair slot of a.pair_ptr / a.pair_s.
+void launch_pair_kinds(const NearFillArgs &a, uint8_t *kinds, hipStream_t st);
 // Fills ptab's rows (the test-node sums every pair of those rows reads).
 void launch_precorr_table(const NearFillArgs &a, int64_t row0, int64_t nrows, c128 *tab, hipStream_t st);
 void launch_near_fill(const NearFillArgs &a, int64_t npairs, hipStream_t st);

@@ -323,6 +323,14 @@ static void build_medium(sie_problem *p, Medium &md) {
     const int tab_w = g.near_radius + 1;
     const int64_t tab_row = (int64_t)(2 * tab_w + 1) * (2 * tab_w + 1) * (2 * tab_w + 1) * 10;
     const int64_t max_rows = std::max<int64_t>(1, (int64_t)(4e9 / (double)(tab_row * sizeof(c128))));
+    if (g.d_pair_kind.n != (size_t)std::max<int64_t>(g.npairs, 1)) {   // pair kinds: once per grid
+        g.d_pair_kind.alloc(std::max<int64_t>(g.npairs, 1));
+        NearFillArgs a{};
+        a.xyz = p->d_xyz.p; a.tri = p->d_tri.p; a.tris = g.d_tris.p; a.centroid = p->d_centroid.p;
+        a.pair_ptr = g.d_pair_ptr.p; a.pair_s = g.d_pair_s.p; a.ntg = ntg;
+        launch_pair_kinds(a, g.d_pair_kind.p, 0);
+        setup_mark("fill: pair kinds");
+    }
     int64_t t0 = 0;
     while (t0 < ntg) {
         int64_t t1 = t0 + 1;
@@ -345,6 +353,7 @@ static void build_medium(sie_problem *p, Medium &md) {
         a.polar_gl = d_gl.p;
         ptab.alloc((t1 - t0) * tab_row);
         a.ptab = ptab.p; a.tab_row0 = t0; a.tab_w = tab_w;
+        a.pkind = g.d_pair_kind.p + pptr[t0];
         launch_precorr_table(a, t0, t1 - t0, ptab.p, 0);
         setup_mark("fill: precorrection tables");
         launch_near_fill(a, np, 0);
