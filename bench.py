@@ -220,7 +220,7 @@ def batch_workload(args):
     xyz, tri = box_mesh((100e-6, 10e-6, 5e-6), (90, 9, 4))
     waves = multi_rhs_waves()[:args.nrhs]
     prec = 1 if args.precision == "fp32" else 0
-    opts = dict(tol=args.tol, restart=args.restart, precond=args.precond)
+    opts = dict(tol=args.tol, restart=args.restart, precond=args.precond, inner_relax=args.inner_relax)
 
     def one(timing=False):
         p = Problem(10e9)
@@ -293,7 +293,7 @@ def serve_workload(args):
         p.set_grid(-1, n=n, near_radius=3)
         tickets.append(srv.submit(p, (0.0, 0.0, -1.0), (1.0, 0.0, 0.0), prec, tol=args.tol, restart=100,
                                   precond=args.precond, max_iter=args.max_iter,
-                                  inner_max_iter=args.inner_max_iter))
+                                  inner_max_iter=args.inner_max_iter, inner_relax=args.inner_relax))
     # requests are reported as they start and as they finish (completion order)
     infos = [None] * len(tickets)
     started = [False] * len(tickets)
