@@ -296,7 +296,7 @@ __global__ __launch_bounds__(512) void k_ras_gather(int c0, const int64_t *__res
 // times R.  The subtractions per element come in the same order as pivot by
 // pivot elimination, but the matrix streams once per panel instead of once
 // per pivot.
-constexpr int kPanelElems = 4096;   // n x bw complex128 panel: 64 KB of LDS
+constexpr int kPanelElems = 8192;   // n x bw complex128 panel: 128 KB of LDS
 constexpr int kPanelMax = 16;
 
 __global__ __launch_bounds__(512) void k_ras_invert(int c0, const int64_t *__restrict__ ext_off,
