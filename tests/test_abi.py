@@ -53,3 +53,32 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     monkeypatch.setattr(S, "LIB_PATH", str(tmp_path / "absent.so"))
     with pytest.raises(RuntimeError):
         S.lib()
+
+
+def test_binding_structs_match_header_layout(tmp_path):
+    """Every struct the binding passes by pointer has the header's size and
+    field offsets (a small C program built with gcc against include/sie.h
+    prints them)."""
+    import shutil
+    import subprocess
+    from paper_2003_11679_amd import sie
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    structs = {"sie_c128": sie.c128, "sie_quad_params": sie.QuadParams, "sie_solver_opts": sie.SolverOpts,
+               "sie_report": sie.Report, "sie_job_info": sie.JobInfo}
+    lines = ['#include <stdio.h>', '#include "sie.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'    printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'    printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
