@@ -274,8 +274,10 @@ typedef struct {
 } sie_job_info;
 
 /* Device-memory estimate (bytes) of a problem's setup and solve: near-field
- * CSR values of every medium (FP64 and FP32), grid buffers and spectra, and
- * the Krylov bases of the default solver options; available before setup. */
+ * CSR values of every medium (FP64 and FP32), grid buffers and spectra, the
+ * largest near-field fill transient (pair blocks and precorrection tables of
+ * one chunk), and the Krylov bases of the default solver options; available
+ * before setup. */
 sie_status sie_problem_footprint(const sie_problem *p, size_t *device_bytes);
 /* hbm_budget_bytes 0: 80 % of the device memory free at creation;
  * max_slots: concurrent requests (worker threads), 1..64. */

@@ -61,11 +61,23 @@ size_t estimate_footprint(const sie_problem *p, int restart, int inner_max_iter)
         const double fft = 3.0 * m * m * m * 16.0;        // buffers + spectra (octants, both precisions)
         return near + fft;
     };
+    // near-field fill transients of one medium at a time (freed before the
+    // next): pair blocks of a chunk (at most 30M pairs x 27 complex128) and
+    // the precorrection tables of its rows (at most 4 GB)
+    auto fill_bytes = [&](int R, double tris) {
+        const int Rr = R > 0 ? R : 5;
+        const double pairs = tris * std::min(tris, 27.0 * (2 * Rr + 1) * (2 * Rr + 1));
+        const double tab = tris * std::pow(2.0 * Rr + 3.0, 3) * 10.0 * 16.0;
+        return std::min(pairs, 30e6) * 27.0 * 16.0 + std::min(tab, 4e9);
+    };
     double b = grid_bytes(p->ext_req.n, p->ext_req.R, E);
+    double transient = fill_bytes(p->ext_req.R, (double)T);
     for (size_t i = 0; i < p->obj_req.size(); ++i) {
         const double rows = p->objs.empty() ? 0.0 : 1.5 * (double)p->objs[i].tri.size() / 3.0;
         b += grid_bytes(p->obj_req[i].n, p->obj_req[i].R, rows);
+        if (!p->objs.empty()) transient = std::max(transient, fill_bytes(p->obj_req[i].R, (double)p->objs[i].tri.size() / 3.0));
     }
+    b += transient;
     const int mi = std::max(restart, std::min(inner_max_iter, 300));
     b += E * ((2.0 * restart + 1.0) + (2.0 * mi + 1.0)) * (16.0 + 8.0);   // outer and nested bases, FP64 + FP32
     b += E * 64.0 * 16.0;                                     // vectors of the solve
