@@ -385,6 +385,7 @@ __device__ inline int classify(const NearFillArgs &a, int64_t tg, int64_t sg, in
 // the test-node sums of tl from a.ptab (k_precorr_table); gr: radial tables
 // in LDS, gr[2 q] = G(h sqrt(q)), gr[2 q + 1] = -(1 + j k r) exp(-j k r)/(4 pi
 // r^3) at r = h sqrt(q), q = |d|^2 (0 at q = 0).
+template <bool POLAR>
 __device__ void fill_pair(const NearFillArgs &a, int64_t tl, int64_t sl, int64_t p, int kind, int loc,
                           const c128 *gr) {
     const int64_t tg = a.tris[tl], sg = a.tris[sl];
@@ -420,7 +421,7 @@ __device__ void fill_pair(const NearFillArgs &a, int64_t tl, int64_t sl, int64_t
     const int no = a.rule_n[ro], ni = a.rule_n[ri];
     double lmax = 0.0;
     for (int i = 0; i < 3; ++i) lmax = fmax(lmax, len(ps[(i + 1) % 3] - ps[i]));
-    const bool polar = a.polar && fabs(k.im) * lmax > kPolarKL;
+    const bool polar = POLAR && a.polar && fabs(k.im) * lmax > kPolarKL;
 
     c128 aRV, aS;
     CV3 aV = {}, aSR = {}, aGR = {}, aG = {};
@@ -649,7 +650,10 @@ void launch_precorr_table(const NearFillArgs &a, int64_t row0, int64_t nrows, c1
 }
 
 // Far pairs: one workgroup per row triangle; the radial tables live in LDS.
-__global__ void __launch_bounds__(128) k_near_fill_far(NearFillArgs a, int64_t ntg) {
+// POLAR: the strong-loss scheme may apply (its code is left out otherwise,
+// which frees registers and scratch for the common case).
+template <bool POLAR>
+__global__ void __launch_bounds__(128, 2) k_near_fill_far(NearFillArgs a, int64_t ntg) {
     extern __shared__ unsigned char smem[];
     c128 *gr = reinterpret_cast<c128 *>(smem);
     const int64_t tl = blockIdx.x;
@@ -659,11 +663,12 @@ __global__ void __launch_bounds__(128) k_near_fill_far(NearFillArgs a, int64_t n
     for (int64_t p = a.pair_ptr[tl] + threadIdx.x; p < a.pair_ptr[tl + 1]; p += blockDim.x) {
         const int64_t sl = a.pair_s[p];
         if ((a.pkind[p] & 15) != KIND_FAR) continue;
-        fill_pair(a, tl, sl, p, KIND_FAR, 0, gr);
+        fill_pair<POLAR>(a, tl, sl, p, KIND_FAR, 0, gr);
     }
 }
 
 // Listed (touching / close) pairs of one kind: one thread per pair.
+template <bool POLAR>
 __global__ void __launch_bounds__(128) k_near_fill_list(NearFillArgs a, int64_t ntg, const int64_t *list, int64_t n,
                                                         int kind) {
     extern __shared__ unsigned char smem[];
@@ -680,7 +685,7 @@ __global__ void __launch_bounds__(128) k_near_fill_list(NearFillArgs a, int64_t 
         const int64_t mid = (lo + hi) >> 1;
         if (a.pair_ptr[mid] <= p) lo = mid; else hi = mid;
     }
-    fill_pair(a, lo, a.pair_s[p], p, kind, loc, gr);
+    fill_pair<POLAR>(a, lo, a.pair_s[p], p, kind, loc, gr);
 }
 
 void launch_green_radial(c128 k, double h, int nq, c128 *gr, hipStream_t st) {
@@ -708,12 +713,18 @@ void launch_near_fill(const NearFillArgs &a, int64_t npairs, hipStream_t st) {
                        lists[1].p, lists[2].p, lists[3].p);
     SIE_HIP(hipGetLastError());
     // far pairs per row triangle
-    hipLaunchKernelGGL(k_near_fill_far, dim3((unsigned)ntg), dim3(128), sh_rad, st, a, ntg);
+    if (a.polar) hipLaunchKernelGGL(k_near_fill_far<true>, dim3((unsigned)ntg), dim3(128), sh_rad, st, a, ntg);
+    else hipLaunchKernelGGL(k_near_fill_far<false>, dim3((unsigned)ntg), dim3(128), sh_rad, st, a, ntg);
     SIE_HIP(hipGetLastError());
     for (int kd = 0; kd < 4; ++kd) {
         if (!cnt[kd]) continue;
-        hipLaunchKernelGGL(k_near_fill_list, dim3((unsigned)((cnt[kd] + 127) / 128)), dim3(128), sh_rad, st, a, ntg,
-                           lists[kd].p, (int64_t)cnt[kd], kd);
+        const dim3 grid((unsigned)((cnt[kd] + 127) / 128));
+        if (a.polar)
+            hipLaunchKernelGGL(k_near_fill_list<true>, grid, dim3(128), sh_rad, st, a, ntg, lists[kd].p,
+                               (int64_t)cnt[kd], kd);
+        else
+            hipLaunchKernelGGL(k_near_fill_list<false>, grid, dim3(128), sh_rad, st, a, ntg, lists[kd].p,
+                               (int64_t)cnt[kd], kd);
         SIE_HIP(hipGetLastError());
     }
     SIE_HIP(hipStreamSynchronize(st));

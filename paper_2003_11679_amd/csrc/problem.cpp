@@ -302,7 +302,21 @@ static void build_medium(sie_problem *p, Medium &md) {
     for (double w : glw) gl.push_back(2.0 * w);
     DBuf<double> d_gl;
     d_gl.upload(gl);
-    const int polar = std::fabs(md.k.im) >= 0.38 * std::hypot(md.k.re, md.k.im) ? 1 : 0;
+    // strong-loss scheme: lossy enough a medium (|Im k| >= 0.38 |k|) and, for
+    // some source triangle, |Im k| times its longest edge above 2 (the
+    // per-pair test on the device; 1 % margin here so none is missed)
+    double lmax_grid = 0.0;
+    for (int32_t t : g.tris)
+        for (int e = 0; e < 3; ++e) {
+            const double *u = &p->mesh.xyz[3 * (int64_t)p->mesh.tri[3 * (int64_t)t + e]];
+            const double *v = &p->mesh.xyz[3 * (int64_t)p->mesh.tri[3 * (int64_t)t + (e + 1) % 3]];
+            lmax_grid = std::max(lmax_grid, std::sqrt((u[0] - v[0]) * (u[0] - v[0]) + (u[1] - v[1]) * (u[1] - v[1]) +
+                                                      (u[2] - v[2]) * (u[2] - v[2])));
+        }
+    const int polar = std::fabs(md.k.im) >= 0.38 * std::hypot(md.k.re, md.k.im) &&
+                              std::fabs(md.k.im) * lmax_grid > 0.99 * 2.0
+                          ? 1
+                          : 0;
 
     setup_mark("medium: rules, tables");
     md.d_nL64.alloc(std::max<int64_t>(g.nnz, 1));
