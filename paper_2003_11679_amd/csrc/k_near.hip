@@ -732,48 +732,63 @@ void launch_near_fill(const NearFillArgs &a, int64_t npairs, hipStream_t st) {
 
 // Deterministic CSR assembly: entry (m, n) sums the blocks of the (at most 4)
 // near triangle pairs (T+-(m), T+-(n)).
-__device__ inline int64_t find_pair(const int64_t *pair_ptr, const int32_t *pair_s, int64_t tl, int32_t sl) {
-    int64_t lo = pair_ptr[tl], hi = pair_ptr[tl + 1];
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        const int32_t v = pair_s[mid];
-        if (v == sl) return mid;
-        if (v < sl) lo = mid + 1; else hi = mid;
-    }
-    return -1;
-}
+// One workgroup per RWG row: the pair lists of its two triangles (this
+// chunk's) are staged in LDS when they fit and searched there; a row whose
+// triangles have no pairs in the chunk returns at once.
+constexpr int kGatherLds = 4096;
 
-__global__ void k_near_gather(int64_t nrow, int64_t rwg0, const int64_t *__restrict__ row_ptr,
-                              const int32_t *__restrict__ cols, const int32_t *__restrict__ rwg_loc,
-                              const int32_t *__restrict__ glob2loc, const int32_t *__restrict__ tpm,
-                              const int32_t *__restrict__ epm, const int64_t *__restrict__ pair_ptr,
-                              const int32_t *__restrict__ pair_s, const c128 *__restrict__ blocks,
-                              c128 *__restrict__ nL64, c128 *__restrict__ nK64, c128 *__restrict__ nLd64) {
-    const int64_t r = blockIdx.y;
+__global__ __launch_bounds__(256) void k_near_gather(int64_t nrow, int64_t rwg0, const int64_t *__restrict__ row_ptr,
+                                                     const int32_t *__restrict__ cols, const int32_t *__restrict__ rwg_loc,
+                                                     const int32_t *__restrict__ glob2loc, const int32_t *__restrict__ tpm,
+                                                     const int32_t *__restrict__ epm, const int64_t *__restrict__ pair_ptr,
+                                                     const int32_t *__restrict__ pair_s, const c128 *__restrict__ blocks,
+                                                     c128 *__restrict__ nL64, c128 *__restrict__ nK64,
+                                                     c128 *__restrict__ nLd64) {
+    __shared__ int32_t ls[2][kGatherLds];
+    const int64_t r = blockIdx.x;
     if (r >= nrow) return;
-    const int64_t j = row_ptr[r] + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (j >= row_ptr[r + 1]) return;
-    const int32_t n = cols[j];
-    c128 L, K, Ld;
+    int64_t b0[2], nn[2];
+    int ea[2];
     for (int sa = 0; sa < 2; ++sa) {
         const int32_t lc = rwg_loc[2 * r + sa];
         const int64_t tl = lc >> 2;
-        const int ea = lc & 3;
-        for (int sb = 0; sb < 2; ++sb) {
-            const int32_t sl = glob2loc[tpm[2 * (int64_t)n + sb]];
-            if (sl < 0) continue;
-            const int eb = epm[2 * (int64_t)n + sb];
-            const int64_t q = find_pair(pair_ptr, pair_s, tl, sl);
-            if (q < 0) continue;
-            L += blocks[q * 27 + ea * 3 + eb];
-            K += blocks[q * 27 + 9 + ea * 3 + eb];
-            Ld += blocks[q * 27 + 18 + ea * 3 + eb];
-        }
+        ea[sa] = lc & 3;
+        b0[sa] = pair_ptr[tl];
+        nn[sa] = pair_ptr[tl + 1] - b0[sa];
     }
-    // row-triangle chunks are processed one after the other: accumulate
-    nL64[j] += L;
-    nK64[j] += K;
-    nLd64[j] += Ld;
+    if (nn[0] == 0 && nn[1] == 0) return;   // uniform over the workgroup
+    for (int sa = 0; sa < 2; ++sa)
+        if (nn[sa] <= kGatherLds)
+            for (int64_t i = threadIdx.x; i < nn[sa]; i += blockDim.x) ls[sa][i] = pair_s[b0[sa] + i];
+    __syncthreads();
+    for (int64_t j = row_ptr[r] + threadIdx.x; j < row_ptr[r + 1]; j += blockDim.x) {
+        const int32_t n = cols[j];
+        c128 L, K, Ld;
+        for (int sa = 0; sa < 2; ++sa) {
+            if (nn[sa] == 0) continue;
+            const bool inl = nn[sa] <= kGatherLds;
+            for (int sb = 0; sb < 2; ++sb) {
+                const int32_t sl = glob2loc[tpm[2 * (int64_t)n + sb]];
+                if (sl < 0) continue;
+                const int eb = epm[2 * (int64_t)n + sb];
+                int64_t lo = 0, hi = nn[sa], q = -1;
+                while (lo < hi) {
+                    const int64_t mid = (lo + hi) >> 1;
+                    const int32_t v = inl ? ls[sa][mid] : pair_s[b0[sa] + mid];
+                    if (v == sl) { q = b0[sa] + mid; break; }
+                    if (v < sl) lo = mid + 1; else hi = mid;
+                }
+                if (q < 0) continue;
+                L += blocks[q * 27 + ea[sa] * 3 + eb];
+                K += blocks[q * 27 + 9 + ea[sa] * 3 + eb];
+                Ld += blocks[q * 27 + 18 + ea[sa] * 3 + eb];
+            }
+        }
+        // row-triangle chunks are processed one after the other: accumulate
+        nL64[j] += L;
+        nK64[j] += K;
+        nLd64[j] += Ld;
+    }
 }
 
 void launch_near_gather(int64_t nrow, int64_t rwg0, int64_t max_row, const int64_t *row_ptr, const int32_t *cols,
@@ -781,14 +796,10 @@ void launch_near_gather(int64_t nrow, int64_t rwg0, int64_t max_row, const int64
                          const int64_t *pair_ptr, const int32_t *pair_s, const c128 *blocks, c128 *nL64,
                          c128 *nK64, c128 *nLd64, hipStream_t st) {
     if (!nrow || !max_row) return;
-    SIE_CHECK(nrow < 65536LL * 1024, SIE_EINVAL, "too many rows");
-    for (int64_t r0 = 0; r0 < nrow; r0 += 65535) {
-        const int64_t nr = std::min<int64_t>(65535, nrow - r0);
-        dim3 grid((unsigned)((max_row + 255) / 256), (unsigned)nr);
-        hipLaunchKernelGGL(k_near_gather, grid, dim3(256), 0, st, nr, rwg0, row_ptr + r0, cols,
-                           rwg_loc + 2 * r0, glob2loc, tpm, epm, pair_ptr, pair_s, blocks, nL64, nK64, nLd64);
-        SIE_HIP(hipGetLastError());
-    }
+    SIE_CHECK(nrow < (1LL << 31), SIE_EINVAL, "too many rows");
+    hipLaunchKernelGGL(k_near_gather, dim3((unsigned)nrow), dim3(256), 0, st, nrow, rwg0, row_ptr, cols, rwg_loc,
+                       glob2loc, tpm, epm, pair_ptr, pair_s, blocks, nL64, nK64, nLd64);
+    SIE_HIP(hipGetLastError());
 }
 
 // ----------------------------------------------------------------- Green's function tables
