@@ -146,3 +146,29 @@ def test_x_operator(case):
     got = p.matvec(-1, 2, _dev(x)).cpu().numpy()
     ref = x_matrix(m) @ x
     assert _rel(got, ref) < 1e-13
+
+
+def test_stage_timer_modes(case):
+    """Timing mode 1 times every stage of a product, mode 2 the near-field CSR
+    product alone, 0 nothing (each call clears the totals); an unknown mode is
+    rejected; timing leaves the product unchanged."""
+    from paper_2003_11679_amd import SieError
+    name, p = case
+    x = _dev(vec(p.num_rwg, 34))
+    y0 = p.matvec(-1, 0, x).cpu().numpy()
+    p.set_timing(1)
+    y1 = p.matvec(-1, 0, x).cpu().numpy()
+    st = p.stage_times()
+    for k in ("project", "fft", "interp", "spmv", "product", "spmv64"):
+        assert st[k][0] == 1 and st[k][1] > 0.0, (k, st)
+    p.set_timing(2)
+    p.matvec(-1, 0, x)
+    st = p.stage_times()
+    assert st["spmv"][0] == 1 and st["spmv64"][0] == 1, st
+    assert all(st[k][0] == 0 for k in ("project", "fft", "interp", "product")), st
+    p.set_timing(0)
+    p.matvec(-1, 0, x)
+    assert all(v[0] == 0 for v in p.stage_times().values())
+    with pytest.raises(SieError):
+        p.set_timing(3)
+    assert np.array_equal(y0, y1)
