@@ -653,7 +653,7 @@ void launch_precorr_table(const NearFillArgs &a, int64_t row0, int64_t nrows, c1
 // POLAR: the strong-loss scheme may apply (its code is left out otherwise,
 // which frees registers and scratch for the common case).
 template <bool POLAR>
-__global__ void __launch_bounds__(128, 2) k_near_fill_far(NearFillArgs a, int64_t ntg) {
+__global__ void __launch_bounds__(128, POLAR ? 1 : 2) k_near_fill_far(NearFillArgs a, int64_t ntg) {
     extern __shared__ unsigned char smem[];
     c128 *gr = reinterpret_cast<c128 *>(smem);
     const int64_t tl = blockIdx.x;
@@ -669,7 +669,7 @@ __global__ void __launch_bounds__(128, 2) k_near_fill_far(NearFillArgs a, int64_
 
 // Listed (touching / close) pairs of one kind: one thread per pair.
 template <bool POLAR>
-__global__ void __launch_bounds__(128) k_near_fill_list(NearFillArgs a, int64_t ntg, const int64_t *list, int64_t n,
+__global__ void __launch_bounds__(128, POLAR ? 1 : 2) k_near_fill_list(NearFillArgs a, int64_t ntg, const int64_t *list, int64_t n,
                                                         int kind) {
     extern __shared__ unsigned char smem[];
     c128 *gr = reinterpret_cast<c128 *>(smem);
