@@ -1,9 +1,12 @@
 """Triangle quadrature for the oracle: collapsed (Duffy) Gauss-Legendre rules.
 
 An n x n rule maps the unit square to the triangle by x = u, y = v (1 - u);
-it integrates polynomials of total degree <= 2n - 2 exactly.  The oracle uses
-its own rules; the library uses a different (symmetric) rule, so the two agree
-only where both are exact or converged.
+it integrates polynomials of total degree <= 2n - 2 exactly.  The library
+builds the same families of rules (collapsed Gauss-Legendre; corner, edge and
+self rules for touching pairs) from its own code, with the same orders in the
+parity tests: near-value parity between the two therefore checks that both
+evaluate the same quadrature, while the correctness of that quadrature rests
+on the closed-form, convergence and Mie pins of the oracle tests.
 """
 import numpy as np
 
