@@ -119,9 +119,14 @@ typedef struct {
     int32_t inner_iters;     /* total nested GMRES iterations */
     int32_t inner_iters_max; /* largest nested count in one outer iteration */
     int32_t refine_sweeps;
-    int32_t matvecs;         /* operator applications in SIE-matvec units */
+    int64_t matvecs;         /* L-type AIM products (eq. AIM_Lin): one per medium
+                                and right-hand side, FP32 and FP64 together */
+    int64_t k_matvecs;       /* K-type AIM products (eq. AIM_Kin), counted alike */
     double residual;         /* final relative residual of the FP64 GIBC system */
+    double t_setup_s;        /* duration of the problem's sie_problem_setup */
     double t_solve_s;
+    size_t device_bytes;     /* the problem's device-memory estimate
+                                (sie_problem_footprint with the solve's options) */
 } sie_report;
 
 /* ---- context --------------------------------------------------------- */
@@ -150,7 +155,61 @@ sie_status sie_problem_add_object(sie_problem *p, const double *xyz, int64_t nv,
  * interiors share the exterior grid when there is one object. */
 sie_status sie_problem_set_grid(sie_problem *p, int32_t medium, int32_t n, int32_t near_radius,
                                 int32_t share);
+
+/* Grid parameters of one medium (Sec. III-D-1 grid, Sec. IV spacing).  As
+ * input to sie_problem_set_grid_params: h > 0 and n > 0 fix the spacing and
+ * the points per axis, with origin[] the grid's first node (zero h or n: the
+ * rule below; an origin of NaN centres the grid on the medium's objects);
+ * order is the stencil order (points per axis - 1; only 2 is built, anything
+ * else is SIE_EINVAL; 0 means 2); near_radius the Chebyshev near radius in
+ * cells (0 = 5, a near region 11 points across, Sec. IV-A).  As output of
+ * sie_grid_choose every field is set. */
+typedef struct {
+    double h;
+    int32_t n;
+    double origin[3];
+    int32_t order;
+    int32_t near_radius;
+    double loss_ratio;   /* out: worst Delta G_n / Delta G_n,lossless beyond the near region */
+    double lambda_r;     /* out: 2 pi / k_r, the medium's wavelength without losses */
+} sie_grid_params;
+
+/* Grid rule of Sec. IV for a medium (eps_r, mu_r, sigma) at freq_hz, objects
+ * of largest bounding-box extent `extent` and mean mesh edge `mean_edge`:
+ * spacing lambda_r / 20 with lambda_r = 2 pi / (k0 sqrt(eps_r mu_r)) (the
+ * lossy error bound of eq. LboundsD2 stays within ~1.5 of the lossless one
+ * for one grid, so losses do not refine it), with strict != 0 further refined
+ * by the (order+1)-th root of the worst lossy/lossless bound ratio (eq. Ddef)
+ * beyond the near region, and never coarser than the mean edge (a stencil
+ * spans a triangle); n = ceil(extent / h) + 3 points (one spare node a side),
+ * clamped to [5, 1024], and h = extent / (n - 3).  Host-only; needs no device.
+ * The library applies this rule to every grid whose n is 0, taking the finest
+ * spacing over the media that share the grid. */
+sie_status sie_grid_choose(double freq_hz, double eps_r, double mu_r, double sigma, double extent,
+                           double mean_edge, int32_t near_radius, int32_t strict, sie_grid_params *out);
+/* Grid of a medium from explicit parameters (see sie_grid_params); the
+ * interior of a single object shares the exterior grid unless share == 0. */
+sie_status sie_problem_set_grid_params(sie_problem *p, int32_t medium, const sie_grid_params *g,
+                                       int32_t share);
 sie_status sie_problem_set_quadrature(sie_problem *p, const sie_quad_params *q);
+/* Skin-depth cutoff of the interior problem (Sec. V: interactions of
+ * triangles more than `skin_depths` skin depths apart are ignored; the paper
+ * uses 5; 0 turns it off, the default).  Two triangles are apart when their
+ * centroids are farther than the cutoff plus both bounding radii about the
+ * centroids (touching triangles never are).  The cutoff applies to an
+ * interior medium whose cutoff lies within its near region (every far pair
+ * beyond it): the medium then has no grid part, its near list keeps the pairs
+ * within the cutoff and its operator is the direct near-region one
+ * (Sec. III-D-2 item a); an interior that would share the exterior grid gets
+ * the exterior grid's geometry with a near list of its own.  Elsewhere the
+ * AIM operator is kept unchanged.  Independently of the cutoff, a medium
+ * whose grid has every pair near (objects within the near region,
+ * Sec. III-D-2 item b) also runs without grid part: the grid part would
+ * equal its precorrection. */
+sie_status sie_problem_set_skin_cutoff(sie_problem *p, double skin_depths);
+/* 1 if the medium runs without grid part (see sie_problem_set_skin_cutoff),
+ * 0 if it has one, negative sie_status on error. */
+int32_t sie_medium_is_local(const sie_problem *p, int32_t medium);
 /* Builds RWG topology, grids, stencils and projection moments, near lists,
  * precorrected near-field matrices (FP64 direct integrals on the device) and
  * Green's spectra for every medium.  Synchronous. */
@@ -188,7 +247,11 @@ sie_status sie_get_wavenumber(const sie_problem *p, int32_t medium, sie_c128 *k)
  * (E = sie_problem_num_rwg), complex64 for SIE_FP32 and complex128 for
  * SIE_FP64.  Op = L or K: AIM product near + W G P (eq. AIM_Lin / AIM_Kin);
  * rows and columns outside the medium's objects are zero.  Op = X: medium
- * ignored. */
+ * ignored.  medium = SIE_INTERIORS: every object's interior operator on its
+ * own rows (the block-diagonal operator whose blocks eq. nest2 inverts,
+ * without its -j w eps_i factors), computed the way the solver does: the
+ * objects whose grids share a shape in one launch per stage. */
+#define SIE_INTERIORS (-2)
 sie_status sie_matvec(sie_problem *p, int32_t medium, sie_op op, sie_precision prec, int32_t nrhs,
                       const void *x_dev, void *y_dev, void *stream);
 /* The stages of one AIM product, exposed for stage-level checks: grid
@@ -224,7 +287,10 @@ int32_t sie_nested_precond_clusters(const sie_problem *p, int64_t *owned);
  * instead of ten), 0 stops; each call clears the totals.  Stages:
  * 0 projection, 1 FFT convolution, 2 interpolation, 3 near-field CSR product
  * (the k_spmv_far kernel alone), 4 whole operator product, 5 the FP64
- * near-field CSR products alone (also counted in 3).  Query returns the
+ * near-field CSR products alone (also counted in 3), 6 and 7 the near-field
+ * CSR products of the interior media inside solves (the nested operator of
+ * eq. nest2, one launch per group of media) in FP32 and FP64 (also counted
+ * in 3, and 7 in 5).  Query returns the
  * number of timed launches and their summed duration (synchronises). */
 sie_status sie_set_timing(sie_problem *p, int32_t on);
 sie_status sie_get_stage_time(sie_problem *p, int32_t stage, int64_t *launches, double *total_ms);

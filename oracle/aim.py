@@ -19,6 +19,19 @@ Readings taken where the paper only cites the construction:
   pairs and precorrected away).
 * Near region: triangles t, s are near iff max_axis |i_t - i_s| <= R (R = 5:
   a diameter of 11 grid points); corrections are per triangle pair.
+* Skin-depth cutoff (Sec. V: interactions farther apart than five skin depths
+  are ignored), for a medium given the cutoff distance d_c: two triangles are
+  "apart" when the distance of their centroids exceeds d_c + rho_t + rho_s,
+  rho being a triangle's largest vertex distance from its centroid (so that
+  touching triangles, whose minimum distance is zero, are never dropped).
+  Applied where it removes the grid part: every far pair (centroids at least
+  R h apart along some axis) is then beyond the cutoff, i.e. when
+  d_c <= R h - 2 max(rho).  The operator is then the direct near-region one
+  on the pairs within the cutoff (Sec. III-D-2 item a: L_NR = L once the skin
+  depth is within the near region).
+* Small objects (Sec. III-D-2 item b): when every pair of the grid is near
+  (stencil centres within R of each other on every axis) the grid part equals
+  the precorrection exactly, and the operator is the direct one.
 """
 import numpy as np
 import scipy.sparse as sp
@@ -115,12 +128,23 @@ def grad_green_grid(k, h, d):
 class AIMOperator:
     """AIM approximations of A, Phi and K at one wavenumber on one grid."""
 
-    def __init__(self, mesh, grid, k, near_radius=5, tris=None, rules=None, g0=0.0, near=True):
+    def __init__(self, mesh, grid, k, near_radius=5, tris=None, rules=None, g0=0.0, near=True, cutoff=None,
+                 bypass=True):
         self.mesh, self.grid, self.k, self.R = mesh, grid, complex(k), int(near_radius)
         self.g0 = g0                      # grid G at zero offset (result must not depend on it)
         T = len(mesh.tri)
         self.tris = np.arange(T) if tris is None else np.asarray(tris)
         self.centres = stencil_centres(grid, mesh.centroid)
+        # local operator: no grid part (cutoff within the near region, or
+        # every pair near)
+        c = self.centres[self.tris]
+        self.all_near = bypass and bool(np.all(c.max(axis=0) - c.min(axis=0) <= self.R))
+        d = mesh.verts - mesh.centroid[:, None, :]
+        self.rho = np.sqrt(np.max(np.sum(d * d, axis=2), axis=1))       # [T]
+        self.cutoff = None if cutoff is None else float(cutoff)
+        self.cut_local = self.cutoff is not None and \
+            self.cutoff <= self.R * grid.h - 2.0 * float(self.rho[self.tris].max())
+        self.local = self.all_near or self.cut_local
         self.M0, self.M1 = triangle_moments(mesh, grid, self.centres)
         self.Pv, self.Ps = rwg_weights(mesh, grid, self.centres, self.M0, self.M1)
         self.nodes = node_index(grid, self.centres)
@@ -136,7 +160,17 @@ class AIMOperator:
         c = self.centres[self.tris]
         d = np.abs(c[:, None, :] - c[None, :, :]).max(axis=2)
         ti, si = np.nonzero(d <= self.R)
-        return self.tris[ti], self.tris[si]
+        tl, sl = self.tris[ti], self.tris[si]
+        if self.cut_local:
+            keep = self.within_cutoff(tl, sl)
+            tl, sl = tl[keep], sl[keep]
+        return tl, sl
+
+    def within_cutoff(self, tl, sl):
+        """Pairs not farther apart than the cutoff (bounding spheres)."""
+        dc = self.mesh.centroid[tl] - self.mesh.centroid[sl]
+        lim = self.cutoff + self.rho[tl] + self.rho[sl]
+        return np.sum(dc * dc, axis=1) <= lim * lim
 
     def near_rows(self, rows):
         """Precorrected near-region L and K (and direct L) of the given RWG rows
@@ -153,11 +187,15 @@ class AIMOperator:
             ss = self.tris[d <= self.R]
             tl.append(np.full(len(ss), t)); sl.append(ss)
         tl = np.concatenate(tl); sl = np.concatenate(sl)
+        if self.cut_local:
+            keep = self.within_cutoff(tl, sl)
+            tl, sl = tl[keep], sl[keep]
         Ad, Pd, Kd = pair_blocks(m, self.k, tl, sl, self.rules)
-        Ag = np.empty_like(Ad); Pg = np.empty_like(Pd); Kg = np.empty_like(Kd)
-        for c0 in range(0, len(tl), 2000):
-            Ag[c0:c0 + 2000], Pg[c0:c0 + 2000], Kg[c0:c0 + 2000] = self.grid_blocks(tl[c0:c0 + 2000],
-                                                                                 sl[c0:c0 + 2000])
+        Ag = np.zeros_like(Ad); Pg = np.zeros_like(Pd); Kg = np.zeros_like(Kd)
+        if not self.local:
+            for c0 in range(0, len(tl), 2000):
+                Ag[c0:c0 + 2000], Pg[c0:c0 + 2000], Kg[c0:c0 + 2000] = self.grid_blocks(tl[c0:c0 + 2000],
+                                                                                     sl[c0:c0 + 2000])
         Lp = (Ad - Ag) - (Pd - Pg) / k2
         Kp = Kd - Kg
         Ld = Ad - Pd / k2
@@ -210,7 +248,10 @@ class AIMOperator:
         for c0 in range(0, len(self.near_t), chunk):
             tl = self.near_t[c0:c0 + chunk]; sl = self.near_s[c0:c0 + chunk]
             Ad, Pd, Kd = pair_blocks(self.mesh, self.k, tl, sl, rules)
-            Ag, Pg, Kg = self.grid_blocks(tl, sl)
+            if self.local:            # no grid part: nothing to precorrect
+                Ag, Pg, Kg = np.zeros_like(Ad), np.zeros_like(Pd), np.zeros_like(Kd)
+            else:
+                Ag, Pg, Kg = self.grid_blocks(tl, sl)
             rm = self.mesh.tri_rwg[tl]; rn = self.mesh.tri_rwg[sl]
             rows.append(np.broadcast_to(rm[:, :, None], (len(tl), 3, 3)).ravel())
             cols.append(np.broadcast_to(rn[:, None, :], (len(tl), 3, 3)).ravel())
@@ -300,6 +341,8 @@ class AIMOperator:
         return (g @ src.ravel()).reshape(src.shape)
 
     def far_part(self, x, op, conv=None):
+        if self.local:
+            return np.zeros(self.mesh.nrwg, np.complex128)
         conv = conv or self.convolve_fft
         J, Q = self.project(x)
         if op == "A":

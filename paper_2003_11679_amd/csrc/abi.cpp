@@ -1,4 +1,5 @@
 // C ABI (include/sie.h): argument checking, error capture, dispatch.
+#include <chrono>
 #include <cmath>
 #include <cstring>
 
@@ -106,6 +107,36 @@ sie_status sie_problem_set_grid(sie_problem *p, int32_t medium, int32_t n, int32
     });
 }
 
+sie_status sie_grid_choose(double freq_hz, double eps_r, double mu_r, double sigma, double extent, double mean_edge,
+                           int32_t near_radius, int32_t strict, sie_grid_params *out) {
+    return guard([&] {
+        SIE_CHECK(out, SIE_EINVAL, "out is NULL");
+        choose_grid(freq_hz, eps_r, mu_r, sigma, extent, mean_edge, near_radius, strict, out);
+    });
+}
+
+sie_status sie_problem_set_grid_params(sie_problem *p, int32_t medium, const sie_grid_params *g, int32_t share) {
+    return guard([&] {
+        SIE_CHECK(p && g, SIE_EINVAL, "NULL argument");
+        SIE_CHECK(!p->is_setup, SIE_ESTATE, "problem already set up");
+        SIE_CHECK(g->order == 0 || g->order == 2, SIE_EINVAL, "only stencil order 2 (3 points per axis) is built");
+        const int R = g->near_radius == 0 ? 5 : g->near_radius;
+        SIE_CHECK(R >= 1 && R <= 12, SIE_EINVAL, "near radius must be in [1, 12]");
+        SIE_CHECK(g->n == 0 || (g->n >= 5 && g->n <= 1024), SIE_EINVAL, "grid points per axis must be 0 or in [5, 1024]");
+        SIE_CHECK(g->h >= 0 && std::isfinite(g->h), SIE_EINVAL, "grid spacing must be finite and non-negative");
+        GridReq r;
+        r.n = g->n;
+        r.R = R;
+        r.h = g->n > 0 ? g->h : 0.0;
+        r.has_origin = std::isfinite(g->origin[0]) && std::isfinite(g->origin[1]) && std::isfinite(g->origin[2]);
+        for (int c = 0; c < 3; ++c) r.origin[c] = g->origin[c];
+        r.share = share ? 1 : 0;
+        if (medium == -1) { r.share = -1; p->ext_req = r; return; }
+        SIE_CHECK(medium >= 0 && medium < (int)p->objs.size(), SIE_EINVAL, "medium out of range");
+        p->obj_req[medium] = r;
+    });
+}
+
 sie_status sie_problem_set_quadrature(sie_problem *p, const sie_quad_params *q) {
     return guard([&] {
         SIE_CHECK(p && q, SIE_EINVAL, "NULL argument");
@@ -114,12 +145,32 @@ sie_status sie_problem_set_quadrature(sie_problem *p, const sie_quad_params *q) 
     });
 }
 
+sie_status sie_problem_set_skin_cutoff(sie_problem *p, double skin_depths) {
+    return guard([&] {
+        SIE_CHECK(p, SIE_EINVAL, "NULL problem");
+        SIE_CHECK(!p->is_setup, SIE_ESTATE, "problem already set up");
+        SIE_CHECK(skin_depths >= 0.0 && std::isfinite(skin_depths), SIE_EINVAL, "cutoff must be finite and >= 0");
+        p->cutoff_factor = skin_depths;
+    });
+}
+
+int32_t sie_medium_is_local(const sie_problem *p, int32_t medium) {
+    int32_t out = SIE_EINVAL;
+    const sie_status st = guard([&] {
+        SIE_CHECK(p && p->is_setup, SIE_ESTATE, "problem not set up");
+        out = p->medium(medium).local ? 1 : 0;
+    });
+    return st == SIE_OK ? out : st;
+}
+
 sie_status sie_problem_setup(sie_problem *p) {
     return guard([&] {
         SIE_CHECK(p, SIE_EINVAL, "NULL problem");
         SIE_CHECK(!p->is_setup, SIE_ESTATE, "problem already set up");
         after_caller_work();
+        const auto t0 = std::chrono::steady_clock::now();
         problem_setup(p);
+        p->t_setup_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     });
 }
 
@@ -218,8 +269,18 @@ sie_status sie_matvec(sie_problem *p, int32_t medium, sie_op op, sie_precision p
         SIE_CHECK(x_dev && y_dev && nrhs >= 1, SIE_EINVAL, "bad vectors");
         SIE_CHECK(x_dev != y_dev, SIE_EINVAL, "x and y must not alias");
         SIE_CHECK(op == SIE_OP_L || op == SIE_OP_K || op == SIE_OP_X, SIE_EINVAL, "unknown operator");
-        Medium &md = p->medium(op == SIE_OP_X ? -1 : medium);
         hipStream_t st = user_stream(stream);
+        if (medium == SIE_INTERIORS && op != SIE_OP_X) {
+            SIE_CHECK(prec == SIE_FP64 || prec == SIE_FP32, SIE_EINVAL, "unknown precision");
+            for (auto &gp : p->groups) {
+                if (prec == SIE_FP64)
+                    group_product<double>(p, *gp, op, false, nrhs, (const c128 *)x_dev, (c128 *)y_dev, st);
+                else
+                    group_product<float>(p, *gp, op, false, nrhs, (const c64 *)x_dev, (c64 *)y_dev, st);
+            }
+            return;
+        }
+        Medium &md = p->medium(op == SIE_OP_X ? -1 : medium);
         if (prec == SIE_FP64)
             matvec<double>(p, md, op, nrhs, (const c128 *)x_dev, (c128 *)y_dev, st);
         else if (prec == SIE_FP32)

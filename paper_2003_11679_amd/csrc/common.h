@@ -61,20 +61,27 @@ struct Error : std::runtime_error {
     } while (0)
 
 // ---------------------------------------------------------------- device buffer
+// Owns its device memory, or (view) refers to a slice of another DBuf's.
 template <typename T>
 struct DBuf {
     T *p = nullptr;
     size_t n = 0;
+    bool own = true;
     DBuf() = default;
     explicit DBuf(size_t count) { alloc(count); }
     DBuf(const DBuf &) = delete;
     DBuf &operator=(const DBuf &) = delete;
-    DBuf(DBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DBuf(DBuf &&o) noexcept : p(o.p), n(o.n), own(o.own) { o.p = nullptr; o.n = 0; o.own = true; }
     DBuf &operator=(DBuf &&o) noexcept {
-        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        if (this != &o) { release(); p = o.p; n = o.n; own = o.own; o.p = nullptr; o.n = 0; o.own = true; }
         return *this;
     }
     ~DBuf() { release(); }
+    // Refer to count elements at q (owned elsewhere; never freed here).
+    void view(T *q, size_t count) {
+        release();
+        p = q; n = count; own = false;
+    }
     void alloc(size_t count) {
         release();
         n = count;
@@ -87,8 +94,8 @@ struct DBuf {
         }
     }
     void release() {
-        if (p) (void)hipFree(p);
-        p = nullptr; n = 0;
+        if (p && own) (void)hipFree(p);
+        p = nullptr; n = 0; own = true;
     }
     void upload(const T *h, size_t count) {
         if (count > n) alloc(count);
@@ -164,6 +171,8 @@ struct Grid {
     int nl[3] = {0, 0, 0};     // live box extent
     int m[3] = {0, 0, 0};      // FFT lengths (powers of two >= 2 nl - 1)
     int near_radius = 5;
+    double cutoff = 0;         // skin-depth cutoff of the near list (0: none)
+    bool all_near = false;     // every pair of the grid's triangles is near
     std::vector<int32_t> tris; // triangles (global ids) on this grid, ascending
     std::vector<int32_t> objs; // objects covered
     std::vector<int32_t> centre;  // [ntg][3] stencil centres (host copy)
@@ -211,6 +220,49 @@ struct Grid {
 struct Medium;
 template <typename T> Work<T> &work_of(Grid &g);
 
+// What one launch of the grid stages and the near-field product reads: one
+// grid, or several grids of one live-box shape laid side by side ("slots",
+// one object each).  Slot s owns live nodes [s nlive, (s + 1) nlive) of the
+// node range, its triangles' centres are relative to its own live box, and
+// grid fields are stored [rhs][slot][F][nl_z][nl_y][nl_x].  The near-field
+// product covers the RWG rows [rwg0, rwg1) (the slots' objects, contiguous).
+struct GridView {
+    int nslot = 1;
+    int64_t ntg = 0;                 // triangles of all slots
+    int64_t nlive = 0;               // live nodes of one slot
+    int nl[3] = {0, 0, 0}, m[3] = {0, 0, 0}, lo[3] = {0, 0, 0};
+    int64_t rwg0 = 0, rwg1 = 0;
+    const int32_t *centre = nullptr;     // [ntg][3], minus lo = live-box index
+    const int32_t *tri_slot = nullptr;   // [ntg] slot of each triangle (null: one slot)
+    const int32_t *node_ptr = nullptr;   // [nslot nlive + 1]
+    const int32_t *node_ent = nullptr;   // (triangle << 5) | stencil slot
+    const int32_t *trirwg = nullptr;     // [ntg][3] global RWG of each triangle edge
+    const int32_t *rwgloc = nullptr;     // [nrow][2] (triangle << 2) | local edge
+    const double *mom64 = nullptr, *coef64 = nullptr;
+    const float *mom32 = nullptr, *coef32 = nullptr;
+    const int64_t *row_ptr = nullptr;    // [nrow + 1]
+    const int32_t *cols = nullptr;
+    const uint16_t *cols16 = nullptr;
+    const int32_t *row_base = nullptr;
+    bool c16 = false;
+    int64_t nrow() const { return rwg1 - rwg0; }
+    int64_t nnodes() const { return nlive * nslot; }
+};
+GridView view_of(const Grid &g);
+
+// Medium-dependent arrays of one launch, per slot: spectra ([slot][4][oct]),
+// near values (CSR of the view), -2 k^-2 of the scalar term of L, and an
+// optional per-slot factor on the whole result.
+template <typename T>
+struct MediaView {
+    bool far = true;                     // grid part present
+    const cx<T> *spec = nullptr;
+    int64_t spec_stride = 0;
+    const cx<T> *nL = nullptr, *nK = nullptr;
+    const cx<T> *kscal = nullptr;        // [nslot]
+    const cx<T> *alpha = nullptr;        // [nslot] or null (factor 1)
+};
+
 struct Medium {
     int id = -1;               // -1 exterior, else object index
     Grid *grid = nullptr;
@@ -223,6 +275,35 @@ struct Medium {
     DBuf<c128> d_nL64, d_nK64;
     DBuf<c64> d_nL32, d_nK32;
     DBuf<c128> d_nLd64;        // direct near-region L (no precorrection): preconditioner source
+    DBuf<c128> d_ks64, d_alpha64;   // [1]: -2 k^-2 and -j w eps~ (nested operator factor)
+    DBuf<c64> d_ks32, d_alpha32;
+    int group = -1;            // interior media: the product group it belongs to
+    // no grid part (Sec. III-D-2 items a and b): the skin-depth cutoff lies
+    // within the near region, or every pair of the grid is near; the
+    // operator is then the direct near-region one
+    bool local = false;
+};
+
+// Interior media whose grids share one live-box shape, batched into one
+// launch per stage (Sec. III-D-1: one grid per object; the objects'
+// products are independent and run side by side).  A group of one medium
+// refers to that medium's own grid arrays; a larger one owns merged copies,
+// and its media's near values are views into the group's arrays.
+struct Group {
+    std::vector<int> media;    // object ids, consecutive
+    GridView view;
+    const Grid *grid0 = nullptr;   // the grid of a one-medium group
+    int64_t nnz = 0;
+    // merged arrays (several slots)
+    DBuf<int32_t> d_centre, d_tri_slot, d_node_ptr, d_node_ent, d_trirwg, d_rwgloc, d_cols, d_row_base;
+    DBuf<uint16_t> d_cols16;
+    DBuf<int64_t> d_row_ptr;
+    DBuf<double> d_mom64, d_coef64;
+    DBuf<float> d_mom32, d_coef32;
+    DBuf<c128> d_spec64, d_ks64, d_alpha64, d_nL64, d_nK64;
+    DBuf<c64> d_spec32, d_ks32, d_alpha32, d_nL32, d_nK32;
+    Work<double> w64;
+    Work<float> w32;
 };
 
 }  // namespace sie

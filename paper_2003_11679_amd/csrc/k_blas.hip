@@ -41,6 +41,18 @@ template <typename T> void launch_scale_into(int64_t n, c128 a, const cx<T> *x, 
     SIE_HIP(hipGetLastError());
 }
 
+// y = 0 (a fill kernel, so the call also works where memset nodes are unwanted)
+template <typename T>
+__global__ void k_zero(int64_t n, cx<T> *__restrict__ y) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) y[i] = cx<T>();
+}
+template <typename T> void launch_zero(int64_t n, cx<T> *y, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_zero<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, y);
+    SIE_HIP(hipGetLastError());
+}
+
 // Batched dot products of ns systems stored [ns][n] inside every vector:
 // h[s * hstride + j] = sum_i conj(V_j[s][i]) w[s][i], j < J, where V_j starts
 // at V + j * ldv.  Partial sums per block (b, j, s), then a final reduction;
@@ -219,6 +231,7 @@ template void launch_convert<double, float>(const c128 *, c64 *, int64_t, hipStr
 template void launch_convert<float, double>(const c64 *, c128 *, int64_t, hipStream_t);
 template void launch_convert<double, double>(const c128 *, c128 *, int64_t, hipStream_t);
 #define SIE_INST_B(T)                                                                                          \
+    template void launch_zero<T>(int64_t, cx<T> *, hipStream_t);                                               \
     template void launch_axpby<T>(int64_t, c128, const cx<T> *, c128, cx<T> *, hipStream_t);                  \
     template void launch_scale_into<T>(int64_t, c128, const cx<T> *, cx<T> *, hipStream_t);                   \
     template void launch_dots<T>(int64_t, int, const cx<T> *, int64_t, const cx<T> *, c128 *, int, c128 *,     \

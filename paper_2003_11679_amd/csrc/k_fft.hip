@@ -346,9 +346,14 @@ __global__ void __launch_bounds__(NT, MINW) k_fft_pass(const cx<T> *__restrict__
 // along every axis, dG/dx_a odd along axis a (kinds 1..3).
 constexpr int kZFields = 4;   // fields per G z-pass block
 
+// Fields come in runs of fps consecutive fields that share one spectrum:
+// run j (of this launch) uses spectrum (run0 + j) mod nspec, spec_stride
+// elements apart.  MODE 0: block z index = (run, chunk of kZFields fields of
+// the run); MODE 1: block z index = triple, fps a multiple of 3.
 template <typename T, int NT, int VPT, int LGL, int MODE, int MINW>
 __global__ void __launch_bounds__(NT, MINW) k_fft_zpass(cx<T> *__restrict__ buf, const cx<T> *__restrict__ spec,
-                                                        int mx, int my, int nz, int nf) {
+                                                        int mx, int my, int nz, int fps, int run0, int nspec,
+                                                        long spec_stride) {
     using TS = Tile<T, NT, VPT, LGL>;
     constexpr int mz = 1 << LGL, PITCH = TS::PITCH, tx = TS::TX, lgtx = TS::LGTX;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -412,10 +417,13 @@ __global__ void __launch_bounds__(NT, MINW) k_fft_zpass(cx<T> *__restrict__ buf,
     };
 
     if constexpr (MODE == 0) {
+        const int cpr = (fps + kZFields - 1) / kZFields;   // chunks per run
+        const int run = blockIdx.z / cpr, ch = blockIdx.z - run * cpr;
+        spec += (long)((run0 + run) % nspec) * spec_stride;
         cx<T> g[VPT];
 #pragma unroll
         for (int q = 0; q < VPT; ++q) g[q] = spec_q(0, q);
-        const int fb = blockIdx.z * kZFields, nfb = min(kZFields, nf - fb);
+        const int fb = run * fps + ch * kZFields, nfb = min(kZFields, fps - ch * kZFields);
         for (int t = 0; t < nrows * nfb; ++t) {
             const int row = t / nfb, f = fb + t - row * nfb;
             load_field(f, row);
@@ -430,6 +438,7 @@ __global__ void __launch_bounds__(NT, MINW) k_fft_zpass(cx<T> *__restrict__ buf,
     } else {
         cx<T> J[3][VPT];
         const int f0 = 3 * blockIdx.z;            // the block's (J_x, J_y, J_z) triple
+        spec += (long)((run0 + f0 / fps) % nspec) * spec_stride;
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
             load_field(f0 + f, 0);
@@ -565,12 +574,14 @@ static void pass(const cx<T> *in, cx<T> *out, int L, int n_in, int n_out, long s
 }
 
 template <typename T, int LGL = kMinLg>
-static void zpass_lg(int lg, const Grid &g, const cx<T> *spec, int nf, int mode, cx<T> *bufB, hipStream_t st) {
+static void zpass_lg(int lg, const GridView &g, const cx<T> *spec, long spec_stride, int fps, int run0, int nspec,
+                     int nf, int mode, cx<T> *bufB, hipStream_t st) {
     if constexpr (LGL <= kMaxLg) {
         if (lg != LGL) {
-            zpass_lg<T, LGL + 1>(lg, g, spec, nf, mode, bufB, st);
+            zpass_lg<T, LGL + 1>(lg, g, spec, spec_stride, fps, run0, nspec, nf, mode, bufB, st);
             return;
         }
+        SIE_CHECK(fps >= 1 && nf % fps == 0 && nspec >= 1, SIE_EINVAL, "fields must form whole spectrum runs");
         constexpr int mz = 1 << LGL;
         const int mx = g.m[0], my = g.m[1], nz = g.nl[2];
         check_span((long)nz * my * mx);
@@ -579,16 +590,18 @@ static void zpass_lg(int lg, const Grid &g, const cx<T> *spec, int nf, int mode,
             constexpr int NT = FftShape<T>::nt, V = FftShape<T>::vpt, W = FftShape<T>::minw;
             using TS = Tile<T, NT, V, LGL>;
             check_tile<TS>();
-            dim3 grid((mx + TS::TX - 1) / TS::TX, my / 2 + 1, (nf + kZFields - 1) / kZFields);
+            const int cpr = (fps + kZFields - 1) / kZFields;
+            dim3 grid((mx + TS::TX - 1) / TS::TX, my / 2 + 1, (nf / fps) * cpr);
             hipLaunchKernelGGL((k_fft_zpass<T, NT, V, LGL, 0, W>), grid, dim3(NT), TS::BYTES, st, bufB, spec, mx, my,
-                               nz, nf);
+                               nz, fps, run0, nspec, spec_stride);
         } else {
             constexpr int NT = FftShape<T>::grad_nt, V = FftShape<T>::grad_vpt, W = FftShape<T>::grad_minw;
             using TS = Tile<T, NT, V, LGL>;
             check_tile<TS>();
+            SIE_CHECK(fps % 3 == 0, SIE_EINVAL, "grad-G spectrum runs must hold whole field triples");
             dim3 grid((mx + TS::TX - 1) / TS::TX, my, nf / 3);
             hipLaunchKernelGGL((k_fft_zpass<T, NT, V, LGL, 1, W>), grid, dim3(NT), TS::BYTES, st, bufB, spec, mx, my,
-                               nz, nf);
+                               nz, fps, run0, nspec, spec_stride);
         }
         SIE_HIP(hipGetLastError());
     } else {
@@ -598,8 +611,8 @@ static void zpass_lg(int lg, const Grid &g, const cx<T> *spec, int nf, int mode,
 
 // One chunk of fields through the five passes (nf * nz <= 65535).
 template <typename T>
-static void convolve_chunk(const Grid &g, const cx<T> *spec, int nf, int mode, const cx<T> *in, cx<T> *out,
-                           cx<T> *bufA, cx<T> *bufB, hipStream_t st) {
+static void convolve_chunk(const GridView &g, const cx<T> *spec, long spec_stride, int fps, int run0, int nspec,
+                           int nf, int mode, const cx<T> *in, cx<T> *out, cx<T> *bufA, cx<T> *bufB, hipStream_t st) {
     const int nx = g.nl[0], ny = g.nl[1], nz = g.nl[2];
     const int mx = g.m[0], my = g.m[1], mz = g.m[2];
     // x forward: lines (f, z, y) contiguous; batch b = f*nz + z, j = y
@@ -609,7 +622,7 @@ static void convolve_chunk(const Grid &g, const cx<T> *spec, int nf, int mode, c
             st);
     // z fused
     SIE_CHECK((mz & (mz - 1)) == 0, SIE_EGRID, "FFT length must be a power of two");
-    zpass_lg<T>(ilog2(mz), g, spec, nf, mode, bufB, st);
+    zpass_lg<T>(ilog2(mz), g, spec, spec_stride, fps, run0, nspec, nf, mode, bufB, st);
     // y inverse: keep ny
     pass<T>(bufB, bufA, my, my, ny, mx, mx, 1, 1, (long)my * mx, (long)ny * mx, mx, (long)nf * nz, false, true, st);
     // x inverse: keep nx
@@ -620,18 +633,22 @@ static void convolve_chunk(const Grid &g, const cx<T> *spec, int nf, int mode, c
 // mode 1 consecutive triples (J_x, J_y, J_z) to grad G x J (nf % 3 == 0).
 // bufA / bufB hold nf fields of their pass layouts.
 template <typename T>
-void fft_convolve(const Grid &g, const cx<T> *spec, int nf, int mode, const cx<T> *in, cx<T> *out,
-                  cx<T> *bufA, cx<T> *bufB, hipStream_t st) {
+void fft_convolve(const GridView &g, const cx<T> *spec, int64_t spec_stride, int fps, int nspec, int nf, int mode,
+                  const cx<T> *in, cx<T> *out, cx<T> *bufA, cx<T> *bufB, hipStream_t st) {
     SIE_CHECK(nf >= 1 && (mode == 0 || nf % 3 == 0), SIE_EINVAL, "grad-G convolution needs field triples");
+    const bool single = fps >= nf || nspec <= 1;      // one spectrum for every field
+    SIE_CHECK(single || (fps >= 1 && nf % fps == 0 && (mode == 0 || fps % 3 == 0)), SIE_EINVAL,
+              "fields must form whole spectrum runs");
     const int nx = g.nl[0], ny = g.nl[1], nz = g.nl[2];
     const int mx = g.m[0], my = g.m[1];
-    const int group = mode == 1 ? 3 : 1;
-    const int chunk = std::max(group, (65535 / nz) / group * group);
+    const int unit = single ? (mode == 1 ? 3 : 1) : fps;   // chunks hold whole runs
+    const int chunk = std::max(unit, (65535 / nz) / unit * unit);
     SIE_CHECK((long)chunk * nz <= 65535, SIE_EGRID, "live box too deep for one FFT batch");
     const long flive = (long)nx * ny * nz, fa = (long)nz * ny * mx, fb = (long)nz * my * mx;
     for (int f0 = 0; f0 < nf; f0 += chunk) {
         const int c = std::min(chunk, nf - f0);
-        convolve_chunk<T>(g, spec, c, mode, in + f0 * flive, out + f0 * flive, bufA + f0 * fa, bufB + f0 * fb, st);
+        convolve_chunk<T>(g, spec, (long)spec_stride, single ? c : fps, single ? 0 : f0 / fps, single ? 1 : nspec, c,
+                          mode, in + f0 * flive, out + f0 * flive, bufA + f0 * fa, bufB + f0 * fb, st);
     }
 }
 
@@ -649,7 +666,9 @@ void fft3d_full_fwd(c128 *vol, c128 *tmp, int mx, int my, int mz, hipStream_t st
     SIE_HIP(hipMemcpyAsync(vol, tmp, sizeof(c128) * (size_t)mx * my * mz, hipMemcpyDeviceToDevice, st));
 }
 
-template void fft_convolve<float>(const Grid &, const c64 *, int, int, const c64 *, c64 *, c64 *, c64 *, hipStream_t);
-template void fft_convolve<double>(const Grid &, const c128 *, int, int, const c128 *, c128 *, c128 *, c128 *, hipStream_t);
+template void fft_convolve<float>(const GridView &, const c64 *, int64_t, int, int, int, int, const c64 *, c64 *,
+                                  c64 *, c64 *, hipStream_t);
+template void fft_convolve<double>(const GridView &, const c128 *, int64_t, int, int, int, int, const c128 *, c128 *,
+                                   c128 *, c128 *, hipStream_t);
 
 }  // namespace sie

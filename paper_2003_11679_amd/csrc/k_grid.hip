@@ -118,9 +118,10 @@ __global__ void k_tri_sources(int64_t ntg, const int32_t *__restrict__ tri_rwg, 
 }
 
 template <typename T>
-void launch_tri_sources(const Grid &g, const int32_t *tri_rwg_loc, const T *tri_coef, const cx<T> *x,
-                        int64_t ldx, int nrhs, cx<T> *trisrc, hipStream_t st) {
-    int64_t ntg = (int64_t)g.tris.size();
+void launch_tri_sources(const GridView &g, const T *tri_coef, const cx<T> *x, int64_t ldx, int nrhs, cx<T> *trisrc,
+                        hipStream_t st) {
+    const int32_t *tri_rwg_loc = g.trirwg;
+    const int64_t ntg = g.ntg;
     if (!ntg || nrhs < 1) return;
     SIE_CHECK(nrhs <= 65535, SIE_EINVAL, "too many right-hand sides");
     hipLaunchKernelGGL(k_tri_sources<T>, dim3((unsigned)((ntg + 255) / 256), (unsigned)nrhs), dim3(256), 0, st, ntg,
@@ -138,17 +139,17 @@ __device__ inline T seg_sum(T v, int lpn) {
 }
 
 template <typename T>
-__global__ void k_project(int64_t nlive, const int32_t *__restrict__ node_ptr, const int32_t *__restrict__ ent,
-                          const T *__restrict__ mom, const cx<T> *__restrict__ src, cx<T> *__restrict__ grid,
-                          int nf, int lpn, int64_t ntg) {
+__global__ void k_project(int64_t nnodes, int64_t nlive, const int32_t *__restrict__ node_ptr,
+                          const int32_t *__restrict__ ent, const T *__restrict__ mom, const cx<T> *__restrict__ src,
+                          cx<T> *__restrict__ grid, int nf, int lpn, int64_t ntg) {
     const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t v = gid / lpn;
     src += blockIdx.y * 4 * ntg;           // right-hand side blockIdx.y
-    grid += blockIdx.y * nf * nlive;
+    grid += blockIdx.y * nf * nnodes;
     const int sub = (int)(gid % lpn);
     // every lane of a wave takes part in the shuffles; out-of-range nodes add zeros
     T s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (v < nlive) {
+    if (v < nnodes) {
         for (int k = node_ptr[v] + sub; k < node_ptr[v + 1]; k += lpn) {
             const int32_t e = ent[k];
             const int64_t t = e >> 5;
@@ -162,40 +163,43 @@ __global__ void k_project(int64_t nlive, const int32_t *__restrict__ node_ptr, c
         }
     }
     for (int i = 0; i < 8; ++i) s[i] = seg_sum(s[i], lpn);
-    if (v < nlive && sub == 0) {
-        grid[v] = cx<T>(s[0], s[1]);
-        grid[nlive + v] = cx<T>(s[2], s[3]);
-        grid[2 * nlive + v] = cx<T>(s[4], s[5]);
-        if (nf == 4) grid[3 * nlive + v] = cx<T>(T(2) * s[6], T(2) * s[7]);
+    if (v < nnodes && sub == 0) {
+        // node v of slot v / nlive: fields of a slot are nf consecutive blocks
+        const int64_t slot = v / nlive;
+        cx<T> *o = grid + slot * (nf - 1) * nlive + v;
+        o[0] = cx<T>(s[0], s[1]);
+        o[nlive] = cx<T>(s[2], s[3]);
+        o[2 * nlive] = cx<T>(s[4], s[5]);
+        if (nf == 4) o[3 * nlive] = cx<T>(T(2) * s[6], T(2) * s[7]);
     }
 }
 
 template <typename T>
-void launch_project(const Grid &g, const T *mom, const cx<T> *trisrc, cx<T> *grid, int nfields, int nrhs,
+void launch_project(const GridView &g, const T *mom, const cx<T> *trisrc, cx<T> *grid, int nfields, int nrhs,
                     hipStream_t st) {
-    const int64_t nlive = g.nlive();
+    const int64_t nnodes = g.nnodes();
     if (nrhs < 1) return;
     SIE_CHECK(nrhs <= 65535, SIE_EINVAL, "too many right-hand sides");
     // lanes per node: about two entries per lane on average
-    const double avg = 27.0 * (double)g.tris.size() / (double)std::max<int64_t>(nlive, 1);
+    const double avg = 27.0 * (double)g.ntg / (double)std::max<int64_t>(nnodes, 1);
     int lpn = 1;
     while (lpn < 64 && lpn * 2 <= avg / 2.0) lpn *= 2;
-    const int64_t threads = nlive * lpn;
+    const int64_t threads = nnodes * lpn;
     hipLaunchKernelGGL(k_project<T>, dim3((unsigned)((threads + 255) / 256), (unsigned)nrhs), dim3(256), 0, st,
-                       nlive, g.d_node_ptr.p, g.d_node_ent.p, mom, trisrc, grid, nfields, lpn,
-                       (int64_t)g.tris.size());
+                       nnodes, g.nlive, g.node_ptr, g.node_ent, mom, trisrc, grid, nfields, lpn, g.ntg);
     SIE_HIP(hipGetLastError());
 }
 
 // Interpolation partials per triangle: psi = sum_a M1[a] . F_vec(a),
 // chi = sum_a M0[a] F_vec(a), zeta = sum_a M0[a] F_scal(a) (F == 4).
 template <typename T>
-__global__ void k_interp(int64_t ntg, const int32_t *__restrict__ centre, int lox, int loy, int loz, int nlx,
-                         int nly, int64_t nlive, const T *__restrict__ mom, const cx<T> *__restrict__ pot, int nf,
-                         cx<T> *__restrict__ out) {
+__global__ void k_interp(int64_t ntg, const int32_t *__restrict__ centre, const int32_t *__restrict__ tri_slot,
+                         int lox, int loy, int loz, int nlx, int nly, int64_t nlive, int64_t nnodes,
+                         const T *__restrict__ mom, const cx<T> *__restrict__ pot, int nf, cx<T> *__restrict__ out) {
     int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= ntg) return;
-    pot += blockIdx.y * nf * nlive;        // right-hand side blockIdx.y
+    pot += blockIdx.y * nf * nnodes;       // right-hand side blockIdx.y
+    if (tri_slot) pot += (int64_t)tri_slot[t] * nf * nlive;
     out += blockIdx.y * 5 * ntg;
     const int cxi = centre[3 * t] - lox, cyi = centre[3 * t + 1] - loy, czi = centre[3 * t + 2] - loz;
     cx<T> psi, chx, chy, chz, zeta;
@@ -215,14 +219,14 @@ __global__ void k_interp(int64_t ntg, const int32_t *__restrict__ centre, int lo
 }
 
 template <typename T>
-void launch_interp(const Grid &g, const T *mom, const cx<T> *pot, int nfields, int nrhs, cx<T> *tripot,
+void launch_interp(const GridView &g, const T *mom, const cx<T> *pot, int nfields, int nrhs, cx<T> *tripot,
                    hipStream_t st) {
-    int64_t ntg = (int64_t)g.tris.size();
+    const int64_t ntg = g.ntg;
     if (!ntg || nrhs < 1) return;
     SIE_CHECK(nrhs <= 65535, SIE_EINVAL, "too many right-hand sides");
     hipLaunchKernelGGL(k_interp<T>, dim3((unsigned)((ntg + 255) / 256), (unsigned)nrhs), dim3(256), 0, st, ntg,
-                       g.d_centre.p,
-                       g.lo[0], g.lo[1], g.lo[2], g.nl[0], g.nl[1], g.nlive(), mom, pot, nfields, tripot);
+                       g.centre, g.tri_slot, g.lo[0], g.lo[1], g.lo[2], g.nl[0], g.nl[1], g.nlive, g.nnodes(), mom,
+                       pot, nfields, tripot);
     SIE_HIP(hipGetLastError());
 }
 
@@ -261,21 +265,22 @@ void launch_cols16(int64_t nrow, const int64_t *row_ptr, const int32_t *cols, in
     SIE_HIP(hipGetLastError());
 }
 
+// Rows rwg0 + r, r < nrow (the rows of the view; others are not touched).
+// The far part's scalar weight kscal (-2 k^-2 for L, none for K) and the
+// optional factor alpha on the row's result are taken per slot, the slot
+// being that of the row's triangles.
 template <typename T, bool C16>
-__global__ void k_spmv_far(int64_t E, int64_t rwg0, int64_t rwg1, const int64_t *__restrict__ row_ptr,
+__global__ void k_spmv_far(int64_t nrow, int64_t rwg0, const int64_t *__restrict__ row_ptr,
                            const int32_t *__restrict__ cols, const uint16_t *__restrict__ cols16,
                            const int32_t *__restrict__ row_base, const cx<T> *__restrict__ vals,
                            const int32_t *__restrict__ rwg_loc, const T *__restrict__ coef,
-                           const cx<T> *__restrict__ tripot, cx<T> kscal, const cx<T> *__restrict__ x,
-                           cx<T> *__restrict__ y, int use_far) {
+                           const cx<T> *__restrict__ tripot, const int32_t *__restrict__ tri_slot,
+                           const cx<T> *__restrict__ kscal, const cx<T> *__restrict__ alpha,
+                           const cx<T> *__restrict__ x, cx<T> *__restrict__ y, int use_far) {
     const int lane = threadIdx.x & 63;
-    const int64_t row = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (row >= E) return;
-    if (row < rwg0 || row >= rwg1) {
-        if (lane == 0) y[row] = cx<T>();
-        return;
-    }
-    const int64_t r = row - rwg0;
+    const int64_t r = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (r >= nrow) return;
+    const int64_t row = rwg0 + r;
     cx<T> acc;
     if (vals) {
         const int64_t b = row_ptr[r], e = row_ptr[r + 1];
@@ -309,7 +314,9 @@ __global__ void k_spmv_far(int64_t E, int64_t rwg0, int64_t rwg1, const int64_t 
         acc = wave_sum(acc);
     }
     if (lane == 0) {
+        const int slot = tri_slot ? tri_slot[rwg_loc[2 * r] >> 2] : 0;
         if (use_far) {
+            const cx<T> ks = kscal ? kscal[slot] : cx<T>();
             for (int s = 0; s < 2; ++s) {
                 const int32_t lc = rwg_loc[2 * r + s];
                 const int64_t t = lc >> 2;
@@ -317,27 +324,29 @@ __global__ void k_spmv_far(int64_t E, int64_t rwg0, int64_t rwg1, const int64_t 
                 const T *c = coef + (t * 3 + ed) * 4;
                 const cx<T> *p = tripot + 5 * t;
                 cx<T> v = p[0] - (c[1] * p[1] + c[2] * p[2] + c[3] * p[3]);
-                v += kscal * p[4];
+                v += ks * p[4];
                 acc += c[0] * v;
             }
         }
+        if (alpha) acc = alpha[slot] * acc;
         y[row] = acc;
     }
 }
 
 template <typename T>
-void launch_spmv_far(const Grid &g, int64_t E, const int32_t *rwg_loc, const T *tri_coef, const cx<T> *tripot,
-                     cx<T> kscal, const cx<T> *vals, const cx<T> *x, cx<T> *y, bool use_far, hipStream_t st) {
-    if (E == 0) return;
+void launch_spmv_far(const GridView &g, const T *tri_coef, const cx<T> *tripot, const cx<T> *kscal,
+                     const cx<T> *alpha, const cx<T> *vals, const cx<T> *x, cx<T> *y, bool use_far, hipStream_t st) {
+    const int64_t nrow = g.nrow();
+    if (nrow <= 0) return;
     const int rows_per_block = 4;
-    const dim3 grid((unsigned)((E + rows_per_block - 1) / rows_per_block));
-    if (g.cols16)
-        hipLaunchKernelGGL((k_spmv_far<T, true>), grid, dim3(256), 0, st, E, g.rwg0, g.rwg1, g.d_row_ptr.p, g.d_cols.p,
-                           g.d_cols16.p, g.d_row_base.p, vals, rwg_loc, tri_coef, tripot, kscal, x, y,
+    const dim3 grid((unsigned)((nrow + rows_per_block - 1) / rows_per_block));
+    if (g.c16)
+        hipLaunchKernelGGL((k_spmv_far<T, true>), grid, dim3(256), 0, st, nrow, g.rwg0, g.row_ptr, g.cols, g.cols16,
+                           g.row_base, vals, g.rwgloc, tri_coef, tripot, g.tri_slot, kscal, alpha, x, y,
                            use_far ? 1 : 0);
     else
-        hipLaunchKernelGGL((k_spmv_far<T, false>), grid, dim3(256), 0, st, E, g.rwg0, g.rwg1, g.d_row_ptr.p,
-                           g.d_cols.p, g.d_cols16.p, g.d_row_base.p, vals, rwg_loc, tri_coef, tripot, kscal, x, y,
+        hipLaunchKernelGGL((k_spmv_far<T, false>), grid, dim3(256), 0, st, nrow, g.rwg0, g.row_ptr, g.cols, g.cols16,
+                           g.row_base, vals, g.rwgloc, tri_coef, tripot, g.tri_slot, kscal, alpha, x, y,
                            use_far ? 1 : 0);
     SIE_HIP(hipGetLastError());
 }
@@ -376,24 +385,21 @@ __global__ void k_rhs_transpose(int64_t E, int nrhs, const cx<T> *__restrict__ x
 // nrhs is; the groups are summed with lane shuffles at the end.  The x
 // values of one column are one contiguous row of xt.
 template <typename T, int RPW, bool C16>
-__global__ void __launch_bounds__(64) k_spmm_far(int64_t E, int64_t rwg0, int64_t rwg1, int nrhs,
+__global__ void __launch_bounds__(64) k_spmm_far(int64_t E, int64_t rwg0, int nrhs,
                                                  const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ cols,
                                                  const uint16_t *__restrict__ cols16,
                                                  const int32_t *__restrict__ row_base,
                                                  const cx<T> *__restrict__ vals, const int32_t *__restrict__ rwg_loc,
                                                  const T *__restrict__ coef, const cx<T> *__restrict__ tripot,
-                                                 int64_t ntg, cx<T> kscal, const cx<T> *__restrict__ xt,
-                                                 cx<T> *__restrict__ y) {
+                                                 int64_t ntg, const int32_t *__restrict__ tri_slot,
+                                                 const cx<T> *__restrict__ kscal, const cx<T> *__restrict__ alpha,
+                                                 const cx<T> *__restrict__ xt, cx<T> *__restrict__ y) {
     constexpr int SLOTS = 64 / RPW;
-    const int64_t row = blockIdx.x;
+    const int64_t rr = blockIdx.x;         // row rwg0 + rr of the view
+    const int64_t row = rwg0 + rr;
     const int slot = threadIdx.x / RPW, q = threadIdx.x % RPW;
     const int r = blockIdx.y * RPW + q;
     const bool act = r < nrhs;
-    if (row < rwg0 || row >= rwg1) {
-        if (act && slot == 0) y[r * E + row] = cx<T>();
-        return;
-    }
-    const int64_t rr = row - rwg0;
     cx<T> acc;
     if (vals) {
         const int64_t b = row_ptr[rr], e = row_ptr[rr + 1];
@@ -421,7 +427,9 @@ __global__ void __launch_bounds__(64) k_spmm_far(int64_t E, int64_t rwg0, int64_
         }
     }
     if (!act || slot != 0) return;
+    const int sl = tri_slot ? tri_slot[rwg_loc[2 * rr] >> 2] : 0;
     if (tripot) {
+        const cx<T> ks = kscal ? kscal[sl] : cx<T>();
         const cx<T> *tp = tripot + (int64_t)r * 5 * ntg;
         for (int s2 = 0; s2 < 2; ++s2) {
             const int32_t lc = rwg_loc[2 * rr + s2];
@@ -430,19 +438,20 @@ __global__ void __launch_bounds__(64) k_spmm_far(int64_t E, int64_t rwg0, int64_
             const T *c = coef + (t * 3 + ed) * 4;
             const cx<T> *qq = tp + 5 * t;
             cx<T> v = qq[0] - (c[1] * qq[1] + c[2] * qq[2] + c[3] * qq[3]);
-            v += kscal * qq[4];
+            v += ks * qq[4];
             acc += c[0] * v;
         }
     }
+    if (alpha) acc = alpha[sl] * acc;
     y[r * E + row] = acc;
 }
 
-// xt: scratch of E * nrhs values; x, y: [nrhs][E].
+// xt: scratch of E * nrhs values; x, y: [nrhs][E]; rows of the view only.
 template <typename T>
-void launch_spmm_far(const Grid &g, int64_t E, int nrhs, const int32_t *rwg_loc, const T *tri_coef,
-                     const cx<T> *tripot, cx<T> kscal, const cx<T> *vals, const cx<T> *x, cx<T> *xt, cx<T> *y,
+void launch_spmm_far(const GridView &g, int64_t E, int nrhs, const T *tri_coef, const cx<T> *tripot,
+                     const cx<T> *kscal, const cx<T> *alpha, const cx<T> *vals, const cx<T> *x, cx<T> *xt, cx<T> *y,
                      hipStream_t st) {
-    if (E == 0 || nrhs < 1) return;
+    if (E == 0 || nrhs < 1 || g.nrow() <= 0) return;
     SIE_CHECK(nrhs <= 65535 * 64, SIE_EINVAL, "too many right-hand sides");
     SIE_CHECK(E <= 0x7fffffffLL, SIE_EINVAL, "too many RWG functions for one launch");
     if (vals) {
@@ -452,17 +461,17 @@ void launch_spmm_far(const Grid &g, int64_t E, int nrhs, const int32_t *rwg_loc,
     }
     int rpw = 1;
     while (rpw < nrhs && rpw < 64) rpw *= 2;
-    const dim3 grid((unsigned)E, (unsigned)((nrhs + rpw - 1) / rpw));
-    const int64_t ntg = (int64_t)g.tris.size();
+    const dim3 grid((unsigned)g.nrow(), (unsigned)((nrhs + rpw - 1) / rpw));
+    const int64_t ntg = g.ntg;
 #define SIE_SPMM(R)                                                                                              \
-    if (g.cols16)                                                                                                \
-        hipLaunchKernelGGL((k_spmm_far<T, R, true>), grid, dim3(64), 0, st, E, g.rwg0, g.rwg1, nrhs,             \
-                           g.d_row_ptr.p, g.d_cols.p, g.d_cols16.p, g.d_row_base.p, vals, rwg_loc, tri_coef,     \
-                           tripot, ntg, kscal, xt, y);                                                           \
+    if (g.c16)                                                                                                   \
+        hipLaunchKernelGGL((k_spmm_far<T, R, true>), grid, dim3(64), 0, st, E, g.rwg0, nrhs, g.row_ptr, g.cols,  \
+                           g.cols16, g.row_base, vals, g.rwgloc, tri_coef, tripot, ntg, g.tri_slot, kscal, alpha,\
+                           xt, y);                                                                               \
     else                                                                                                         \
-        hipLaunchKernelGGL((k_spmm_far<T, R, false>), grid, dim3(64), 0, st, E, g.rwg0, g.rwg1, nrhs,            \
-                           g.d_row_ptr.p, g.d_cols.p, g.d_cols16.p, g.d_row_base.p, vals, rwg_loc, tri_coef,     \
-                           tripot, ntg, kscal, xt, y)
+        hipLaunchKernelGGL((k_spmm_far<T, R, false>), grid, dim3(64), 0, st, E, g.rwg0, nrhs, g.row_ptr, g.cols, \
+                           g.cols16, g.row_base, vals, g.rwgloc, tri_coef, tripot, ntg, g.tri_slot, kscal, alpha,\
+                           xt, y)
     switch (rpw) {
     case 1: SIE_SPMM(1); break;
     case 2: SIE_SPMM(2); break;
@@ -496,13 +505,13 @@ void launch_x_apply(int64_t E, const int32_t *xptr, const int32_t *xcol, const T
 }
 
 #define SIE_INST(T)                                                                                           \
-    template void launch_tri_sources<T>(const Grid &, const int32_t *, const T *, const cx<T> *, int64_t, int,  \
-                                        cx<T> *, hipStream_t);                                                 \
-    template void launch_project<T>(const Grid &, const T *, const cx<T> *, cx<T> *, int, int, hipStream_t);    \
-    template void launch_interp<T>(const Grid &, const T *, const cx<T> *, int, int, cx<T> *, hipStream_t);     \
-    template void launch_spmm_far<T>(const Grid &, int64_t, int, const int32_t *, const T *, const cx<T> *,     \
-                                     cx<T>, const cx<T> *, const cx<T> *, cx<T> *, cx<T> *, hipStream_t);       \
-    template void launch_spmv_far<T>(const Grid &, int64_t, const int32_t *, const T *, const cx<T> *, cx<T>,   \
+    template void launch_tri_sources<T>(const GridView &, const T *, const cx<T> *, int64_t, int, cx<T> *,      \
+                                        hipStream_t);                                                          \
+    template void launch_project<T>(const GridView &, const T *, const cx<T> *, cx<T> *, int, int, hipStream_t);\
+    template void launch_interp<T>(const GridView &, const T *, const cx<T> *, int, int, cx<T> *, hipStream_t); \
+    template void launch_spmm_far<T>(const GridView &, int64_t, int, const T *, const cx<T> *, const cx<T> *,   \
+                                     const cx<T> *, const cx<T> *, const cx<T> *, cx<T> *, cx<T> *, hipStream_t); \
+    template void launch_spmv_far<T>(const GridView &, const T *, const cx<T> *, const cx<T> *, const cx<T> *,  \
                                      const cx<T> *, const cx<T> *, cx<T> *, bool, hipStream_t);                 \
     template void launch_x_apply<T>(int64_t, const int32_t *, const int32_t *, const T *, const cx<T> *, cx<T> *, \
                                     hipStream_t);

@@ -22,8 +22,23 @@
 namespace sie {
 
 // ----------------------------------------------------------------- near pairs
+// Skin-depth cutoff (Sec. V): with dc > 0 a pair is kept only if its
+// centroids are at most dc + rho_t + rho_s apart (rho: a triangle's bounding
+// radius about its centroid), the squares compared without contraction so
+// that the decision does not depend on fused rounding.
+__device__ __forceinline__ bool within_cutoff(const NearCut &c, int64_t t, int64_t s) {
+    if (!(c.dc > 0.0)) return true;
+    const int64_t gt = c.tris[t], gs = c.tris[s];
+    const double dx = __dsub_rn(c.centroid[3 * gt], c.centroid[3 * gs]);
+    const double dy = __dsub_rn(c.centroid[3 * gt + 1], c.centroid[3 * gs + 1]);
+    const double dz = __dsub_rn(c.centroid[3 * gt + 2], c.centroid[3 * gs + 2]);
+    const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+    const double lim = __dadd_rn(__dadd_rn(c.dc, c.rho[gt]), c.rho[gs]);
+    return d2 <= __dmul_rn(lim, lim);
+}
+
 __global__ void k_near_count(const int32_t *__restrict__ centre, int64_t ntg, const int32_t *__restrict__ cell_ptr,
-                             int lox, int loy, int loz, int nlx, int nly, int nlz, int R,
+                             int lox, int loy, int loz, int nlx, int nly, int nlz, int R, NearCut cut,
                              int64_t *__restrict__ count) {
     int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= ntg) return;
@@ -33,13 +48,17 @@ __global__ void k_near_count(const int32_t *__restrict__ centre, int64_t ntg, co
     for (int z = max(cz - R, 0); z <= min(cz + R, nlz - 1); ++z)
         for (int y = max(cy - R, 0); y <= min(cy + R, nly - 1); ++y) {
             const int64_t base = ((int64_t)z * nly + y) * nlx;
-            n += cell_ptr[base + x1 + 1] - cell_ptr[base + x0];
+            if (cut.dc > 0.0) {
+                for (int32_t s = cell_ptr[base + x0]; s < cell_ptr[base + x1 + 1]; ++s) n += within_cutoff(cut, t, s);
+            } else {
+                n += cell_ptr[base + x1 + 1] - cell_ptr[base + x0];
+            }
         }
     count[t] = n;
 }
 
 __global__ void k_near_emit(const int32_t *__restrict__ centre, int64_t ntg, const int32_t *__restrict__ cell_ptr,
-                            int lox, int loy, int loz, int nlx, int nly, int nlz, int R,
+                            int lox, int loy, int loz, int nlx, int nly, int nlz, int R, NearCut cut,
                             const int64_t *__restrict__ pair_ptr, int32_t *__restrict__ pair_s) {
     int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= ntg) return;
@@ -49,24 +68,25 @@ __global__ void k_near_emit(const int32_t *__restrict__ centre, int64_t ntg, con
     for (int z = max(cz - R, 0); z <= min(cz + R, nlz - 1); ++z)
         for (int y = max(cy - R, 0); y <= min(cy + R, nly - 1); ++y) {
             const int64_t base = ((int64_t)z * nly + y) * nlx;
-            for (int32_t s = cell_ptr[base + x0]; s < cell_ptr[base + x1 + 1]; ++s) pair_s[o++] = s;
+            for (int32_t s = cell_ptr[base + x0]; s < cell_ptr[base + x1 + 1]; ++s)
+                if (within_cutoff(cut, t, s)) pair_s[o++] = s;
         }
 }
 
-void launch_near_count(const int32_t *centre, int64_t ntg, const int32_t *cell_ptr, const int32_t *,
+void launch_near_count(const int32_t *centre, int64_t ntg, const int32_t *cell_ptr, const NearCut &cut,
                        const int lo[3], const int nl[3], int R, int64_t *count, hipStream_t st) {
     if (!ntg) return;
     hipLaunchKernelGGL(k_near_count, dim3((unsigned)((ntg + 255) / 256)), dim3(256), 0, st, centre, ntg, cell_ptr,
-                       lo[0], lo[1], lo[2], nl[0], nl[1], nl[2], R, count);
+                       lo[0], lo[1], lo[2], nl[0], nl[1], nl[2], R, cut, count);
     SIE_HIP(hipGetLastError());
 }
 
-void launch_near_emit(const int32_t *centre, int64_t ntg, const int32_t *cell_ptr, const int32_t *,
+void launch_near_emit(const int32_t *centre, int64_t ntg, const int32_t *cell_ptr, const NearCut &cut,
                       const int lo[3], const int nl[3], int R, const int64_t *pair_ptr, int32_t *pair_s,
                       hipStream_t st) {
     if (!ntg) return;
     hipLaunchKernelGGL(k_near_emit, dim3((unsigned)((ntg + 255) / 256)), dim3(256), 0, st, centre, ntg, cell_ptr,
-                       lo[0], lo[1], lo[2], nl[0], nl[1], nl[2], R, pair_ptr, pair_s);
+                       lo[0], lo[1], lo[2], nl[0], nl[1], nl[2], R, cut, pair_ptr, pair_s);
     SIE_HIP(hipGetLastError());
 }
 
@@ -471,12 +491,14 @@ __device__ void fill_pair(const NearFillArgs &a, int64_t tl, int64_t sl, int64_t
     }
 
     // precorrection: grid contribution of the pair over the 27 x 27 stencil
-    // node pairs, offsets d = (c_t + o_a) - (c_s + o_b)
+    // node pairs, offsets d = (c_t + o_a) - (c_s + o_b); none for a medium
+    // without grid part (its near values are the direct integrals)
+    c128 S00, S11, C11;
+    CV3 S10 = {}, S01 = {}, Vs = {}, Vt = {}, U = {};
+    if (!a.no_grid) {
     const int dx0 = a.centre[3 * tl] - a.centre[3 * sl];
     const int dy0 = a.centre[3 * tl + 1] - a.centre[3 * sl + 1];
     const int dz0 = a.centre[3 * tl + 2] - a.centre[3 * sl + 2];
-    c128 S00, S11, C11;
-    CV3 S10 = {}, S01 = {}, Vs = {}, Vt = {}, U = {};
     // The sums over node pairs factor through the source node b: for each b
     // the test-node sums at offset e = (c_t - c_s) - o_b (from the row's
     // table) Gb0 = sum_a m0t G, Gb1 = sum_a m1t G, gb0 = sum_a m0t g and
@@ -505,6 +527,7 @@ __device__ void fill_pair(const NearFillArgs &a, int64_t tl, int64_t sl, int64_t
         cadd(Vs, ccross_cv(gb0, m1s));
         cadd(Vt, CV3{-m0s * gb1x.x, -m0s * gb1x.y, -m0s * gb1x.z});
         C11 += -cdot(m1s, gb1x);
+    }
     }
     const c128 ik2 = cdiv(c128(1.0), k * k);
     const double *ct = a.tri_coef + tl * 12;

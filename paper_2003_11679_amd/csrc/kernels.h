@@ -5,9 +5,14 @@
 namespace sie {
 
 // ---- k_fft.hip
+// nf fields [nf][nl_z][nl_y][nl_x] of the view's live-box shape.  The fields
+// form runs of `fps` consecutive fields that share one spectrum; run j uses
+// spec + ((j mod nspec) * spec_stride) (one spectrum for all: fps = nf,
+// nspec = 1).  mode 0: each field times G; mode 1: triples (J_x, J_y, J_z) to
+// grad G x J (fps and nf multiples of 3).
 template <typename T>
-void fft_convolve(const Grid &g, const cx<T> *spec, int nf, int mode, const cx<T> *in, cx<T> *out,
-                  cx<T> *bufA, cx<T> *bufB, hipStream_t st);
+void fft_convolve(const GridView &g, const cx<T> *spec, int64_t spec_stride, int fps, int nspec, int nf, int mode,
+                  const cx<T> *in, cx<T> *out, cx<T> *bufA, cx<T> *bufB, hipStream_t st);
 void fft3d_full_fwd(c128 *vol, c128 *tmp, int mx, int my, int mz, hipStream_t st);
 
 // ---- k_grid.hip
@@ -17,33 +22,41 @@ void launch_moments(const double *xyz, const int32_t *tri, const int32_t *tris, 
                     int64_t ntg, const double origin[3], double h, const double *rule, int nq,
                     double *mom64, float *mom32, hipStream_t st);
 template <typename T>
-void launch_tri_sources(const Grid &g, const int32_t *tri_rwg_loc, const T *tri_coef, const cx<T> *x,
-                        int64_t ldx, int nrhs, cx<T> *trisrc, hipStream_t st);
+void launch_tri_sources(const GridView &g, const T *tri_coef, const cx<T> *x, int64_t ldx, int nrhs,
+                        cx<T> *trisrc, hipStream_t st);
 template <typename T>
-void launch_project(const Grid &g, const T *mom, const cx<T> *trisrc, cx<T> *grid, int nfields, int nrhs,
+void launch_project(const GridView &g, const T *mom, const cx<T> *trisrc, cx<T> *grid, int nfields, int nrhs,
                     hipStream_t st);
 template <typename T>
-void launch_interp(const Grid &g, const T *mom, const cx<T> *pot, int nfields, int nrhs, cx<T> *tripot,
+void launch_interp(const GridView &g, const T *mom, const cx<T> *pot, int nfields, int nrhs, cx<T> *tripot,
                    hipStream_t st);
 // y[r] = sum_j N[r,j] x[j] + sum over the row's triangles of the far part,
-// for rows r in [rwg0, rwg1); rows outside are zeroed.  kscal = -2 k^-2
-// (scalar part weight; 0 for K-type).  N may be null (far part only).
+// times alpha[slot] (alpha null: 1), for the view's rows r in [rwg0, rwg1);
+// other rows are not written.  kscal[slot] = -2 k^-2 (scalar part weight;
+// null for K-type).  N may be null (far part only).
 template <typename T>
-void launch_spmv_far(const Grid &g, int64_t E, const int32_t *rwg_loc, const T *tri_coef,
-                     const cx<T> *tripot, cx<T> kscal, const cx<T> *vals, const cx<T> *x, cx<T> *y,
-                     bool use_far, hipStream_t st);
+void launch_spmv_far(const GridView &g, const T *tri_coef, const cx<T> *tripot, const cx<T> *kscal,
+                     const cx<T> *alpha, const cx<T> *vals, const cx<T> *x, cx<T> *y, bool use_far, hipStream_t st);
 template <typename T>
-void launch_spmm_far(const Grid &g, int64_t E, int nrhs, const int32_t *rwg_loc, const T *tri_coef,
-                     const cx<T> *tripot, cx<T> kscal, const cx<T> *vals, const cx<T> *x, cx<T> *xt, cx<T> *y,
+void launch_spmm_far(const GridView &g, int64_t E, int nrhs, const T *tri_coef, const cx<T> *tripot,
+                     const cx<T> *kscal, const cx<T> *alpha, const cx<T> *vals, const cx<T> *x, cx<T> *xt, cx<T> *y,
                      hipStream_t st);
 template <typename T>
 void launch_x_apply(int64_t E, const int32_t *xptr, const int32_t *xcol, const T *xval, const cx<T> *x,
                     cx<T> *y, hipStream_t st);
 
 // ---- k_near.hip
-void launch_near_count(const int32_t *centre, int64_t ntg, const int32_t *cell_ptr, const int32_t *cell_tri,
+// Skin-depth cutoff of a near search: dc > 0 keeps the pairs whose centroids
+// (global arrays, triangle tris[local]) are at most dc + rho_t + rho_s apart.
+struct NearCut {
+    double dc = 0.0;
+    const double *centroid = nullptr;
+    const double *rho = nullptr;
+    const int32_t *tris = nullptr;
+};
+void launch_near_count(const int32_t *centre, int64_t ntg, const int32_t *cell_ptr, const NearCut &cut,
                        const int lo[3], const int nl[3], int R, int64_t *count, hipStream_t st);
-void launch_near_emit(const int32_t *centre, int64_t ntg, const int32_t *cell_ptr, const int32_t *cell_tri,
+void launch_near_emit(const int32_t *centre, int64_t ntg, const int32_t *cell_ptr, const NearCut &cut,
                       const int lo[3], const int nl[3], int R, const int64_t *pair_ptr, int32_t *pair_s,
                       hipStream_t st);
 // 16-bit column offsets from each row's first column; *wide is set when a
@@ -68,6 +81,7 @@ struct NearFillArgs {
     // [row][(2 tab_w + 1)^3 offsets][10], tab_w = near radius + 1
     const c128 *ptab; int64_t tab_row0; int tab_w;
     const uint8_t *pkind;            // kind | loc << 4 of pair slot p (same offset as pair_s)
+    int no_grid;                     // medium without grid part: direct values, no precorrection
 };
 // kinds[p] = kind | loc << 4 for every pair slot of a.pair_ptr / a.pair_s.
 void launch_pair_kinds(const NearFillArgs &a, uint8_t *kinds, hipStream_t st);

@@ -46,7 +46,35 @@ static int next_pow2(int v) {
     return m;
 }
 
-static void build_grid_geometry(sie_problem *p, Grid &g, const GridReq &req, double lambda_r) {
+// Largest vertex distance of every triangle from its centroid, in the
+// arithmetic the near-list cutoff is compared with (no contraction).
+static std::vector<double> bounding_radii(const Mesh &m) {
+#pragma clang fp contract(off)
+    const int64_t T = m.nt();
+    std::vector<double> r(T);
+    for (int64_t t = 0; t < T; ++t) {
+        double best = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            const double *v = &m.xyz[3 * (int64_t)m.tri[3 * t + k]];
+            const double *c = &m.centroid[3 * t];
+            const double dx = v[0] - c[0], dy = v[1] - c[1], dz = v[2] - c[2];
+            const double d2 = (dx * dx + dy * dy) + dz * dz;
+            best = std::max(best, d2);
+        }
+        r[t] = std::sqrt(best);
+    }
+    return r;
+}
+
+// Grid geometry: explicit (h, n, origin) when given; otherwise n points per
+// axis (n from the Sec. IV rule when 0: the finest spacing over the media
+// that use the grid, at most 256 points per axis) over the largest
+// bounding-box extent with one spare node a side, h = extent / (n - 3),
+// centred on the bounding box.
+struct MediumProps {
+    double eps_r, mu_r, sigma;
+};
+static void build_grid_geometry(sie_problem *p, Grid &g, const GridReq &req, const std::vector<MediumProps> &media) {
     const Mesh &m = p->mesh;
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
     double esum = 0;
@@ -58,15 +86,27 @@ static void build_grid_geometry(sie_problem *p, Grid &g, const GridReq &req, dou
             const int e = m.tri_rwg[3 * (int64_t)t + k];
             esum += m.len[e]; ecnt++;
         }
-    double ext = std::max(hi[0] - lo[0], std::max(hi[1] - lo[1], hi[2] - lo[2]));
+    const double ext = std::max(hi[0] - lo[0], std::max(hi[1] - lo[1], hi[2] - lo[2]));
+    g.near_radius = req.R;
+    if (req.h > 0 && req.n > 0) {
+        g.h = req.h;
+        for (int c = 0; c < 3; ++c) {
+            g.n[c] = req.n;
+            g.origin[c] = req.has_origin ? req.origin[c] : 0.5 * (lo[c] + hi[c]) - g.h * (req.n - 1) / 2.0;
+        }
+        return;
+    }
     int n = req.n;
     if (n <= 0) {
-        // lambda_r / 20 (Sec. IV), no finer than the mean edge length
         const double mean_edge = esum / std::max<int64_t>(ecnt, 1);
-        const double hr = std::max(lambda_r / 20.0, mean_edge);
-        const double htarget = std::min(hr, std::max(mean_edge, 1e-300));
-        n = (int)std::ceil(ext / htarget) + 3;
-        n = std::max(5, std::min(n, 256));
+        n = 5;
+        for (const MediumProps &md : media) {
+            sie_grid_params gp;
+            choose_grid(p->freq, md.eps_r, md.mu_r, md.sigma, std::max(ext, 1e-300), std::max(mean_edge, 1e-300),
+                        req.R, 0, &gp);
+            n = std::max(n, gp.n);
+        }
+        n = std::min(n, 256);
     }
     SIE_CHECK(n >= 4, SIE_EGRID, "grid needs at least 4 points per axis");
     g.h = ext / (n - 3);
@@ -74,7 +114,6 @@ static void build_grid_geometry(sie_problem *p, Grid &g, const GridReq &req, dou
         g.n[c] = n;
         g.origin[c] = 0.5 * (lo[c] + hi[c]) - g.h * (n - 1) / 2.0;
     }
-    g.near_radius = req.R;
 }
 
 // Stencil centres, live box, local (cell-sorted) triangle order, moments,
@@ -112,6 +151,9 @@ static void build_grid(sie_problem *p, Grid &g) {
             g.nl[k] = hi[k] - lo[k] + 3;
             g.m[k] = std::max(2, next_pow2(2 * g.nl[k] - 1));
         }
+        // every pair near: stencil centres within R of each other on every axis
+        g.all_near = hi[0] - lo[0] <= g.near_radius && hi[1] - lo[1] <= g.near_radius &&
+                     hi[2] - lo[2] <= g.near_radius;
         // 3. local order: sorted by live-box cell (z, y, x), then global id
         std::vector<int64_t> key(ntg);
         for (int64_t i = 0; i < ntg; ++i)
@@ -138,14 +180,19 @@ static void build_grid(sie_problem *p, Grid &g) {
         DBuf<int32_t> d_cell(nlive + 1);
         d_cell.upload(cell_ptr);
         DBuf<int64_t> d_cnt(ntg);
-        launch_near_count(g.d_centre.p, ntg, d_cell.p, nullptr, g.lo, g.nl, g.near_radius, d_cnt.p, 0);
+        NearCut cut;
+        cut.dc = g.cutoff;
+        cut.centroid = p->d_centroid.p;
+        cut.rho = p->d_rho.p;
+        cut.tris = g.d_tris.p;
+        launch_near_count(g.d_centre.p, ntg, d_cell.p, cut, g.lo, g.nl, g.near_radius, d_cnt.p, 0);
         std::vector<int64_t> cnt = d_cnt.download();
         std::vector<int64_t> pptr(ntg + 1, 0);
         for (int64_t i = 0; i < ntg; ++i) pptr[i + 1] = pptr[i] + cnt[i];
         g.npairs = pptr[ntg];
         g.d_pair_ptr.upload(pptr);
         g.d_pair_s.alloc(std::max<int64_t>(g.npairs, 1));
-        launch_near_emit(g.d_centre.p, ntg, d_cell.p, nullptr, g.lo, g.nl, g.near_radius, g.d_pair_ptr.p,
+        launch_near_emit(g.d_centre.p, ntg, d_cell.p, cut, g.lo, g.nl, g.near_radius, g.d_pair_ptr.p,
                          g.d_pair_s.p, 0);
     }
     // 5. per-triangle coefficients and maps
@@ -263,6 +310,14 @@ static std::vector<double> pack_rule(const Rule &r) {
     return v;
 }
 
+// A buffer that is already a large enough view into a group's array stays
+// one; otherwise it gets memory of its own.
+template <typename T>
+static void keep_or_alloc(DBuf<T> &b, size_t n) {
+    if (b.p && !b.own && b.n >= n) return;
+    b.alloc(n);
+}
+
 // Precorrected near values and Green's spectra of one medium on its grid.
 static void build_medium(sie_problem *p, Medium &md) {
     Grid &g = *md.grid;
@@ -319,8 +374,8 @@ static void build_medium(sie_problem *p, Medium &md) {
                           : 0;
 
     setup_mark("medium: rules, tables");
-    md.d_nL64.alloc(std::max<int64_t>(g.nnz, 1));
-    md.d_nK64.alloc(std::max<int64_t>(g.nnz, 1));
+    keep_or_alloc(md.d_nL64, std::max<int64_t>(g.nnz, 1));
+    keep_or_alloc(md.d_nK64, std::max<int64_t>(g.nnz, 1));
     md.d_nLd64.alloc(std::max<int64_t>(g.nnz, 1));
     SIE_HIP(hipMemset(md.d_nL64.p, 0, md.d_nL64.bytes()));
     SIE_HIP(hipMemset(md.d_nK64.p, 0, md.d_nK64.bytes()));
@@ -365,10 +420,16 @@ static void build_medium(sie_problem *p, Medium &md) {
         a.blocks = blocks.p;
         a.polar = polar;
         a.polar_gl = d_gl.p;
-        ptab.alloc((t1 - t0) * tab_row);
-        a.ptab = ptab.p; a.tab_row0 = t0; a.tab_w = tab_w;
+        a.tab_row0 = t0; a.tab_w = tab_w;
         a.pkind = g.d_pair_kind.p + pptr[t0];
-        launch_precorr_table(a, t0, t1 - t0, ptab.p, 0);
+        a.no_grid = md.local ? 1 : 0;
+        if (!md.local) {
+            ptab.alloc((t1 - t0) * tab_row);
+            a.ptab = ptab.p;
+            launch_precorr_table(a, t0, t1 - t0, ptab.p, 0);
+        } else {
+            a.ptab = nullptr;
+        }
         setup_mark("fill: precorrection tables");
         launch_near_fill(a, np, 0);
         setup_mark("fill: pair blocks");
@@ -379,24 +440,211 @@ static void build_medium(sie_problem *p, Medium &md) {
         t0 = t1;
     }
     setup_mark("medium: near fill");
-    md.d_nL32.alloc(std::max<int64_t>(g.nnz, 1));
-    md.d_nK32.alloc(std::max<int64_t>(g.nnz, 1));
+    keep_or_alloc(md.d_nL32, std::max<int64_t>(g.nnz, 1));
+    keep_or_alloc(md.d_nK32, std::max<int64_t>(g.nnz, 1));
     launch_convert<double, float>(md.d_nL64.p, md.d_nL32.p, g.nnz, 0);
     launch_convert<double, float>(md.d_nK64.p, md.d_nK32.p, g.nnz, 0);
     // spectra of G, dG/dx, dG/dy, dG/dz, folded to the octant, 1/(mx my mz) folded in
     setup_mark("medium: FP32 copies");
-    const int64_t vol = g.mvol();
-    DBuf<c128> d_vol(vol), d_tmp(vol);
-    md.d_spec64.alloc(4 * g.oct());
-    md.d_spec32.alloc(4 * g.oct());
-    const double scale = 1.0 / (double)vol;
-    for (int kind = 0; kind < 4; ++kind) {
-        launch_green_sample(md.k, g.h, g.nl, g.m, kind, d_vol.p, 0);
-        fft3d_full_fwd(d_vol.p, d_tmp.p, g.m[0], g.m[1], g.m[2], 0);
-        launch_fold_octant(d_vol.p, g.m, kind, scale, md.d_spec64.p, md.d_spec32.p, 0);
+    if (!md.local) {   // a medium without grid part needs no spectra
+        const int64_t vol = g.mvol();
+        DBuf<c128> d_vol(vol), d_tmp(vol);
+        md.d_spec64.alloc(4 * g.oct());
+        md.d_spec32.alloc(4 * g.oct());
+        const double scale = 1.0 / (double)vol;
+        for (int kind = 0; kind < 4; ++kind) {
+            launch_green_sample(md.k, g.h, g.nl, g.m, kind, d_vol.p, 0);
+            fft3d_full_fwd(d_vol.p, d_tmp.p, g.m[0], g.m[1], g.m[2], 0);
+            launch_fold_octant(d_vol.p, g.m, kind, scale, md.d_spec64.p, md.d_spec32.p, 0);
+        }
     }
     SIE_HIP(hipStreamSynchronize(0));
     setup_mark("medium: spectra");
+    // per-medium scalars of the products: -2 k^-2 (scalar term of L) and the
+    // nested operator's factor -j w eps~
+    const c128 ks = cdiv(c128(-2.0), md.k * md.k);
+    const c128 al = c128(0.0, -p->w) * md.eps;
+    md.d_ks64.upload(std::vector<c128>{ks});
+    md.d_ks32.upload(std::vector<c64>{c64((float)ks.re, (float)ks.im)});
+    md.d_alpha64.upload(std::vector<c128>{al});
+    md.d_alpha32.upload(std::vector<c64>{c64((float)al.re, (float)al.im)});
+}
+
+// Groups of interior media for batched products: consecutive objects whose
+// own grids share the live-box and FFT shapes (at most kGroupMax per
+// group); a medium on the exterior grid, or of a shape of its own, forms a
+// group of one.  Media of larger groups get their near values as views into
+// the group's arrays (filled in place by the near-field setup).
+constexpr int kGroupMax = 4096;
+
+static bool same_shape(const Grid &a, const Grid &b) {
+    for (int c = 0; c < 3; ++c)
+        if (a.nl[c] != b.nl[c] || a.m[c] != b.m[c]) return false;
+    return true;
+}
+
+static void form_groups(sie_problem *p) {
+    p->groups.clear();
+    for (int i = 0; i < (int)p->ints.size(); ++i) {
+        Medium &md = p->ints[i];
+        const bool own = md.grid != p->ext.grid;
+        if (own && !p->groups.empty()) {
+            Group &last = *p->groups.back();
+            const Medium &prev = p->ints[last.media.back()];
+            if (prev.grid != p->ext.grid && last.media.back() == i - 1 && same_shape(*prev.grid, *md.grid) &&
+                prev.local == md.local && (int)last.media.size() < kGroupMax) {
+                last.media.push_back(i);
+                md.group = (int)p->groups.size() - 1;
+                continue;
+            }
+        }
+        auto g = std::make_unique<Group>();
+        g->media.push_back(i);
+        md.group = (int)p->groups.size();
+        p->groups.push_back(std::move(g));
+    }
+    for (auto &gp : p->groups) {
+        Group &gr = *gp;
+        if (gr.media.size() < 2) continue;
+        int64_t nnz = 0;
+        for (int i : gr.media) nnz += p->ints[i].grid->nnz;
+        gr.nnz = nnz;
+        gr.d_nL64.alloc(std::max<int64_t>(nnz, 1));
+        gr.d_nK64.alloc(std::max<int64_t>(nnz, 1));
+        gr.d_nL32.alloc(std::max<int64_t>(nnz, 1));
+        gr.d_nK32.alloc(std::max<int64_t>(nnz, 1));
+        int64_t off = 0;
+        for (int i : gr.media) {
+            Medium &md = p->ints[i];
+            const int64_t n = std::max<int64_t>(md.grid->nnz, 1);
+            md.d_nL64.view(gr.d_nL64.p + off, n);
+            md.d_nK64.view(gr.d_nK64.p + off, n);
+            md.d_nL32.view(gr.d_nL32.p + off, n);
+            md.d_nK32.view(gr.d_nK32.p + off, n);
+            off += md.grid->nnz;
+        }
+    }
+}
+
+template <typename T>
+static void d2d(T *dst, const T *src, size_t n) {
+    if (n) SIE_HIP(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyDeviceToDevice, 0));
+}
+
+// Merged per-triangle, per-node and per-row arrays of the groups of several
+// media, in slot order (slot s = the group's s-th medium); triangle, entry,
+// row and nonzero indices offset by those of the earlier slots.
+static void finalize_groups(sie_problem *p) {
+    for (auto &gp : p->groups) {
+        Group &gr = *gp;
+        if (gr.media.size() < 2) {
+            gr.grid0 = p->ints[gr.media[0]].grid;
+            gr.view = view_of(*gr.grid0);
+            continue;
+        }
+        const int S = (int)gr.media.size();
+        const Grid &g0 = *p->ints[gr.media[0]].grid;
+        int64_t ntg = 0, nrow = 0;
+        bool c16 = true;
+        for (int i : gr.media) {
+            const Grid &g = *p->ints[i].grid;
+            ntg += (int64_t)g.tris.size();
+            nrow += g.rwg1 - g.rwg0;
+            c16 = c16 && g.cols16;
+        }
+        const int64_t nlive = g0.nlive(), oct = g0.oct();
+        std::vector<int32_t> centre(3 * ntg), slot(ntg), nptr((size_t)S * nlive + 1, 0), ent, rwgloc(2 * nrow);
+        std::vector<int64_t> rptr(nrow + 1, 0);
+        ent.reserve(27 * ntg);
+        gr.d_trirwg.alloc(3 * ntg);
+        gr.d_mom64.alloc(27 * 4 * ntg);
+        gr.d_mom32.alloc(27 * 4 * ntg);
+        gr.d_coef64.alloc(12 * ntg);
+        gr.d_coef32.alloc(12 * ntg);
+        gr.d_cols.alloc(std::max<int64_t>(gr.nnz, 1));
+        if (c16) {
+            gr.d_cols16.alloc(std::max<int64_t>(gr.nnz, 1));
+            gr.d_row_base.alloc(std::max<int64_t>(nrow, 1));
+        }
+        const bool local = p->ints[gr.media[0]].local;
+        if (!local) {
+            gr.d_spec64.alloc((size_t)S * 4 * oct);
+            gr.d_spec32.alloc((size_t)S * 4 * oct);
+        }
+        std::vector<c128> ks(S), al(S);
+        int64_t toff = 0, roff = 0, zoff = 0, eoff = 0;
+        for (int s = 0; s < S; ++s) {
+            const Medium &md = p->ints[gr.media[s]];
+            const Grid &g = *md.grid;
+            const int64_t nt = (int64_t)g.tris.size(), nr = g.rwg1 - g.rwg0;
+            for (int64_t t = 0; t < nt; ++t) {
+                for (int c = 0; c < 3; ++c) centre[3 * (toff + t) + c] = g.centre[3 * t + c] - g.lo[c];
+                slot[toff + t] = s;
+            }
+            const std::vector<int32_t> np = g.d_node_ptr.download(nlive + 1);
+            for (int64_t v = 0; v < nlive; ++v) nptr[(size_t)s * nlive + v + 1] = (int32_t)(eoff + np[v + 1]);
+            for (int32_t e : g.d_node_ent.download(np[nlive])) ent.push_back((int32_t)(((e >> 5) + toff) << 5 | (e & 31)));
+            eoff += np[nlive];
+            const std::vector<int32_t> rl = g.d_rwgloc.download(2 * nr);
+            for (int64_t k = 0; k < 2 * nr; ++k) rwgloc[2 * roff + k] = (int32_t)((((rl[k] >> 2) + toff) << 2) | (rl[k] & 3));
+            const std::vector<int64_t> rp = g.d_row_ptr.download(nr + 1);
+            for (int64_t r = 0; r < nr; ++r) rptr[roff + r + 1] = zoff + rp[r + 1];
+            d2d(gr.d_trirwg.p + 3 * toff, g.d_trirwg.p, 3 * nt);
+            d2d(gr.d_mom64.p + 108 * toff, g.d_mom64.p, 108 * nt);
+            d2d(gr.d_mom32.p + 108 * toff, g.d_mom32.p, 108 * nt);
+            d2d(gr.d_coef64.p + 12 * toff, g.d_tri64.p, 12 * nt);
+            d2d(gr.d_coef32.p + 12 * toff, g.d_tri32.p, 12 * nt);
+            d2d(gr.d_cols.p + zoff, g.d_cols.p, g.nnz);
+            if (c16) {
+                d2d(gr.d_cols16.p + zoff, g.d_cols16.p, g.nnz);
+                d2d(gr.d_row_base.p + roff, g.d_row_base.p, nr);
+            }
+            if (!local) {
+                d2d(gr.d_spec64.p + (size_t)s * 4 * oct, md.d_spec64.p, 4 * oct);
+                d2d(gr.d_spec32.p + (size_t)s * 4 * oct, md.d_spec32.p, 4 * oct);
+            }
+            ks[s] = cdiv(c128(-2.0), md.k * md.k);
+            al[s] = c128(0.0, -p->w) * md.eps;
+            toff += nt; roff += nr; zoff += g.nnz;
+        }
+        gr.d_centre.upload(centre);
+        gr.d_tri_slot.upload(slot);
+        gr.d_node_ptr.upload(nptr);
+        gr.d_node_ent.upload(ent);
+        gr.d_rwgloc.upload(rwgloc);
+        gr.d_row_ptr.upload(rptr);
+        gr.d_ks64.upload(ks);
+        gr.d_alpha64.upload(al);
+        std::vector<c64> ks32(S), al32(S);
+        for (int s = 0; s < S; ++s) {
+            ks32[s] = c64((float)ks[s].re, (float)ks[s].im);
+            al32[s] = c64((float)al[s].re, (float)al[s].im);
+        }
+        gr.d_ks32.upload(ks32);
+        gr.d_alpha32.upload(al32);
+        SIE_HIP(hipStreamSynchronize(0));
+        GridView v;
+        v.nslot = S;
+        v.ntg = ntg;
+        v.nlive = nlive;
+        for (int c = 0; c < 3; ++c) { v.nl[c] = g0.nl[c]; v.m[c] = g0.m[c]; v.lo[c] = 0; }
+        v.rwg0 = g0.rwg0;
+        v.rwg1 = g0.rwg0 + nrow;
+        v.centre = gr.d_centre.p;
+        v.tri_slot = gr.d_tri_slot.p;
+        v.node_ptr = gr.d_node_ptr.p;
+        v.node_ent = gr.d_node_ent.p;
+        v.trirwg = gr.d_trirwg.p;
+        v.rwgloc = gr.d_rwgloc.p;
+        v.mom64 = gr.d_mom64.p; v.mom32 = gr.d_mom32.p;
+        v.coef64 = gr.d_coef64.p; v.coef32 = gr.d_coef32.p;
+        v.row_ptr = gr.d_row_ptr.p;
+        v.cols = gr.d_cols.p;
+        v.cols16 = c16 ? gr.d_cols16.p : nullptr;
+        v.row_base = c16 ? gr.d_row_base.p : nullptr;
+        v.c16 = c16;
+        gr.view = v;
+    }
 }
 
 static void build_x(sie_problem *p) {
@@ -440,43 +688,103 @@ static void build_x(sie_problem *p) {
     p->d_xval32.upload(val32);
 }
 
-// Scratch for products of up to nrhs right-hand sides (grown on demand; E is
-// the number of RWG functions, for the transposed right-hand sides).
+GridView view_of(const Grid &g) {
+    GridView v;
+    v.nslot = 1;
+    v.ntg = (int64_t)g.tris.size();
+    v.nlive = g.nlive();
+    for (int c = 0; c < 3; ++c) { v.nl[c] = g.nl[c]; v.m[c] = g.m[c]; v.lo[c] = g.lo[c]; }
+    v.rwg0 = g.rwg0;
+    v.rwg1 = g.rwg1;
+    v.centre = g.d_centre.p;
+    v.tri_slot = nullptr;
+    v.node_ptr = g.d_node_ptr.p;
+    v.node_ent = g.d_node_ent.p;
+    v.trirwg = g.d_trirwg.p;
+    v.rwgloc = g.d_rwgloc.p;
+    v.mom64 = g.d_mom64.p; v.mom32 = g.d_mom32.p;
+    v.coef64 = g.d_tri64.p; v.coef32 = g.d_tri32.p;
+    v.row_ptr = g.d_row_ptr.p;
+    v.cols = g.d_cols.p;
+    v.cols16 = g.d_cols16.p;
+    v.row_base = g.d_row_base.p;
+    v.c16 = g.cols16;
+    return v;
+}
+
+// Scratch for products of up to nrhs right-hand sides over a view (grown on
+// demand; E is the number of RWG functions, for the transposed right-hand
+// sides of a batched product).
 template <typename T>
-static void ensure_work(Grid &g, Work<T> &w, int nrhs, int64_t E) {
+static void ensure_work(const GridView &v, Work<T> &w, int nrhs, int64_t E) {
     if (w.cap_rhs < nrhs) {
-        const size_t F = 4, R = (size_t)nrhs;
-        w.grid.alloc(R * F * g.nlive());
-        w.bufA.alloc(R * F * g.nl[2] * g.nl[1] * g.m[0]);
-        w.bufB.alloc(R * F * g.nl[2] * g.m[1] * g.m[0]);
-        w.trisrc.alloc(R * 4 * g.tris.size());
-        w.tripot.alloc(R * 5 * g.tris.size());
+        const size_t F = 4, R = (size_t)nrhs, S = (size_t)v.nslot;
+        w.grid.alloc(R * F * v.nnodes());
+        w.bufA.alloc(R * F * S * v.nl[2] * v.nl[1] * v.m[0]);
+        w.bufB.alloc(R * F * S * v.nl[2] * v.m[1] * v.m[0]);
+        w.trisrc.alloc(R * 4 * v.ntg);
+        w.tripot.alloc(R * 5 * v.ntg);
         w.cap_rhs = nrhs;
     }
     if (nrhs > 1 && w.xt.n < (size_t)nrhs * E) w.xt.alloc((size_t)nrhs * E);
 }
 
-template <> Work<double> &work_of<double>(Grid &g) { ensure_work(g, g.w64, 1, 0); return g.w64; }
-template <> Work<float> &work_of<float>(Grid &g) { ensure_work(g, g.w32, 1, 0); return g.w32; }
-template <typename T> static Work<T> &work_rhs(Grid &g, int nrhs, int64_t E);
-template <> Work<double> &work_rhs<double>(Grid &g, int nrhs, int64_t E) { ensure_work(g, g.w64, nrhs, E); return g.w64; }
-template <> Work<float> &work_rhs<float>(Grid &g, int nrhs, int64_t E) { ensure_work(g, g.w32, nrhs, E); return g.w32; }
+template <> Work<double> &work_of<double>(Grid &g) { ensure_work(view_of(g), g.w64, 1, 0); return g.w64; }
+template <> Work<float> &work_of<float>(Grid &g) { ensure_work(view_of(g), g.w32, 1, 0); return g.w32; }
+template <typename T> static Work<T> &work_sel(Grid &g);
+template <> Work<double> &work_sel<double>(Grid &g) { return g.w64; }
+template <> Work<float> &work_sel<float>(Grid &g) { return g.w32; }
+template <typename T> static Work<T> &work_sel(Group &g);
+template <> Work<double> &work_sel<double>(Group &g) { return g.w64; }
+template <> Work<float> &work_sel<float>(Group &g) { return g.w32; }
 
-template <typename T> static const T *mom_of(Grid &g);
-template <> const double *mom_of<double>(Grid &g) { return g.d_mom64.p; }
-template <> const float *mom_of<float>(Grid &g) { return g.d_mom32.p; }
-template <typename T> static const T *coef_of(Grid &g);
-template <> const double *coef_of<double>(Grid &g) { return g.d_tri64.p; }
-template <> const float *coef_of<float>(Grid &g) { return g.d_tri32.p; }
-template <typename T> static const cx<T> *spec_of(Medium &m);
-template <> const c128 *spec_of<double>(Medium &m) { return m.d_spec64.p; }
-template <> const c64 *spec_of<float>(Medium &m) { return m.d_spec32.p; }
-template <typename T> static const cx<T> *near_of(Medium &m, sie_op op);
-template <> const c128 *near_of<double>(Medium &m, sie_op op) { return op == SIE_OP_L ? m.d_nL64.p : m.d_nK64.p; }
-template <> const c64 *near_of<float>(Medium &m, sie_op op) { return op == SIE_OP_L ? m.d_nL32.p : m.d_nK32.p; }
+template <typename T> static const T *mom_v(const GridView &v);
+template <> const double *mom_v<double>(const GridView &v) { return v.mom64; }
+template <> const float *mom_v<float>(const GridView &v) { return v.mom32; }
+template <typename T> static const T *coef_v(const GridView &v);
+template <> const double *coef_v<double>(const GridView &v) { return v.coef64; }
+template <> const float *coef_v<float>(const GridView &v) { return v.coef32; }
+template <typename T> static const cx<T> *spec_of(const Medium &m);
+template <> const c128 *spec_of<double>(const Medium &m) { return m.d_spec64.p; }
+template <> const c64 *spec_of<float>(const Medium &m) { return m.d_spec32.p; }
 template <typename T> static const T *xval_of(sie_problem *p);
 template <> const double *xval_of<double>(sie_problem *p) { return p->d_xval64.p; }
 template <> const float *xval_of<float>(sie_problem *p) { return p->d_xval32.p; }
+
+// Medium-dependent arrays of a product of one medium on its own grid.
+template <typename T> static MediaView<T> media_of(const Medium &m, bool scaled);
+template <> MediaView<double> media_of<double>(const Medium &m, bool scaled) {
+    MediaView<double> v;
+    v.far = !m.local;
+    v.spec = m.d_spec64.p; v.nL = m.d_nL64.p; v.nK = m.d_nK64.p; v.kscal = m.d_ks64.p;
+    v.alpha = scaled ? m.d_alpha64.p : nullptr;
+    return v;
+}
+template <> MediaView<float> media_of<float>(const Medium &m, bool scaled) {
+    MediaView<float> v;
+    v.far = !m.local;
+    v.spec = m.d_spec32.p; v.nL = m.d_nL32.p; v.nK = m.d_nK32.p; v.kscal = m.d_ks32.p;
+    v.alpha = scaled ? m.d_alpha32.p : nullptr;
+    return v;
+}
+// ... and of a merged group (spectra [slot][4][oct]).
+template <typename T> static MediaView<T> media_of(const Group &g, bool scaled);
+template <> MediaView<double> media_of<double>(const Group &g, bool scaled) {
+    MediaView<double> v;
+    v.far = g.d_spec64.p != nullptr;
+    v.spec = g.d_spec64.p; v.spec_stride = (int64_t)(g.d_spec64.n / g.view.nslot);
+    v.nL = g.d_nL64.p; v.nK = g.d_nK64.p; v.kscal = g.d_ks64.p;
+    v.alpha = scaled ? g.d_alpha64.p : nullptr;
+    return v;
+}
+template <> MediaView<float> media_of<float>(const Group &g, bool scaled) {
+    MediaView<float> v;
+    v.far = g.d_spec32.p != nullptr;
+    v.spec = g.d_spec32.p; v.spec_stride = (int64_t)(g.d_spec32.n / g.view.nslot);
+    v.nL = g.d_nL32.p; v.nK = g.d_nK32.p; v.kscal = g.d_ks32.p;
+    v.alpha = scaled ? g.d_alpha32.p : nullptr;
+    return v;
+}
 
 // ---- stage timers
 hipEvent_t StageTimer::get() {
@@ -493,10 +801,10 @@ void StageTimer::begin(int, hipStream_t st, hipEvent_t &a) {
     a = get();
     SIE_HIP(hipEventRecord(a, st));
 }
-void StageTimer::end(int stage, hipStream_t st, hipEvent_t a, int extra) {
+void StageTimer::end(int stage, hipStream_t st, hipEvent_t a, int extra, int extra2) {
     hipEvent_t b = get();
     SIE_HIP(hipEventRecord(b, st));
-    pending.push_back({stage, extra, a, b});
+    pending.push_back({stage, extra, extra2, a, b});
     if (pending.size() >= 4096) flush();
 }
 void StageTimer::flush() {
@@ -506,10 +814,11 @@ void StageTimer::flush() {
         SIE_HIP(hipEventElapsedTime(&ms, r.a, r.b));
         total_ms[r.stage] += ms;
         count[r.stage] += 1;
-        if (r.extra >= 0) {
-            total_ms[r.extra] += ms;
-            count[r.extra] += 1;
-        }
+        for (int x : {r.extra, r.extra2})
+            if (x >= 0) {
+                total_ms[x] += ms;
+                count[x] += 1;
+            }
         pool.push_back(r.a);
         pool.push_back(r.b);
     }
@@ -524,6 +833,61 @@ StageTimer::~StageTimer() {
     for (auto e : pool) (void)hipEventDestroy(e);
 }
 
+// One AIM product over a view for nrhs right-hand sides [nrhs][E]: the rows
+// of the view are written, others are not touched.  Every stage takes all
+// right-hand sides and slots at once; with several right-hand sides the
+// near-field values are streamed once for the whole batch.
+template <typename T>
+static void run_product(sie_problem *p, const GridView &v, const MediaView<T> &mv, sie_op op, int nrhs,
+                        const cx<T> *x, cx<T> *y, const ProductBufs<T> &b, cx<T> *xt, StageTimer *tm,
+                        hipStream_t st, bool interior = false) {
+    const int x64 = sizeof(T) == 8 ? ST_SPMV64 : -1;
+    const int xint = interior ? (sizeof(T) == 8 ? ST_INT64 : ST_INT32) : -1;
+    const int64_t E = p->mesh.nrwg;
+    const int F = op == SIE_OP_L ? 4 : 3;
+    const int nf = F * v.nslot * nrhs;
+    const bool all = tm && tm->on == 1;   // every stage; otherwise the near-field CSR product only
+    const bool csr = tm && tm->on;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const cx<T> *vals = op == SIE_OP_L ? mv.nL : mv.nK;
+    if (!mv.far) {
+        // local operator: the direct near-region values alone
+        if (all) tm->begin(ST_PRODUCT, st, e0);
+        if (csr) tm->begin(ST_SPMV, st, e1);
+        if (nrhs == 1)
+            launch_spmv_far<T>(v, coef_v<T>(v), (const cx<T> *)nullptr, (const cx<T> *)nullptr, mv.alpha, vals, x, y,
+                               false, st);
+        else
+            launch_spmm_far<T>(v, E, nrhs, coef_v<T>(v), (const cx<T> *)nullptr, (const cx<T> *)nullptr, mv.alpha,
+                               vals, x, xt, y, st);
+        if (csr) tm->end(ST_SPMV, st, e1, x64, xint);
+        if (all) tm->end(ST_PRODUCT, st, e0);
+        return;
+    }
+    if (all) { tm->begin(ST_PRODUCT, st, e0); tm->begin(ST_PROJECT, st, e1); }
+    launch_tri_sources<T>(v, coef_v<T>(v), x, E, nrhs, b.trisrc, st);
+    launch_project<T>(v, mom_v<T>(v), b.trisrc, b.grid, F, nrhs, st);
+    if (all) { tm->end(ST_PROJECT, st, e1); tm->begin(ST_FFT, st, e1); }
+    fft_convolve<T>(v, mv.spec, mv.spec_stride, v.nslot > 1 ? F : nf, v.nslot, nf, op == SIE_OP_L ? 0 : 1, b.grid,
+                    b.grid, b.bufA, b.bufB, st);
+    if (all) { tm->end(ST_FFT, st, e1); tm->begin(ST_INTERP, st, e1); }
+    launch_interp<T>(v, mom_v<T>(v), b.grid, F, nrhs, b.tripot, st);
+    if (all) tm->end(ST_INTERP, st, e1);
+    if (csr) tm->begin(ST_SPMV, st, e1);
+    const cx<T> *ks = op == SIE_OP_L ? mv.kscal : nullptr;
+    if (nrhs == 1)
+        launch_spmv_far<T>(v, coef_v<T>(v), b.tripot, ks, mv.alpha, vals, x, y, true, st);
+    else
+        launch_spmm_far<T>(v, E, nrhs, coef_v<T>(v), b.tripot, ks, mv.alpha, vals, x, xt, y, st);
+    if (csr) tm->end(ST_SPMV, st, e1, x64, xint);
+    if (all) tm->end(ST_PRODUCT, st, e0);
+}
+
+template <typename T>
+static ProductBufs<T> bufs_of(Work<T> &w) {
+    return ProductBufs<T>{w.grid.p, w.bufA.p, w.bufB.p, w.trisrc.p, w.tripot.p};
+}
+
 template <typename T>
 void matvec(sie_problem *p, Medium &md, sie_op op, int nrhs, const cx<T> *x, cx<T> *y, hipStream_t st) {
     const int64_t E = p->mesh.nrwg;
@@ -533,80 +897,88 @@ void matvec(sie_problem *p, Medium &md, sie_op op, int nrhs, const cx<T> *x, cx<
         return;
     }
     Grid &g = *md.grid;
-    Work<T> &w = work_of<T>(g);
-    const int F = op == SIE_OP_L ? 4 : 3;
-    const c128 k2 = md.k * md.k;
-    const c128 ks = op == SIE_OP_L ? cdiv(c128(-2.0), k2) : c128();
-    const cx<T> kscal((T)ks.re, (T)ks.im);
-    StageTimer &tm = p->timer;
-    const bool all = tm.on == 1;   // every stage; otherwise the near-field CSR product only
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (nrhs > 1) {
-        // batched: every stage takes all right-hand sides at once; the
-        // near-field values are streamed once for the whole batch
-        Work<T> &wb = work_rhs<T>(g, nrhs, E);
-        if (all) { tm.begin(ST_PRODUCT, st, e0); tm.begin(ST_PROJECT, st, e1); }
-        launch_tri_sources<T>(g, g.d_trirwg.p, coef_of<T>(g), x, E, nrhs, wb.trisrc.p, st);
-        launch_project<T>(g, mom_of<T>(g), wb.trisrc.p, wb.grid.p, F, nrhs, st);
-        if (all) { tm.end(ST_PROJECT, st, e1); tm.begin(ST_FFT, st, e1); }
-        fft_convolve<T>(g, spec_of<T>(md), F * nrhs, op == SIE_OP_L ? 0 : 1, wb.grid.p, wb.grid.p, wb.bufA.p,
-                        wb.bufB.p, st);
-        if (all) { tm.end(ST_FFT, st, e1); tm.begin(ST_INTERP, st, e1); }
-        launch_interp<T>(g, mom_of<T>(g), wb.grid.p, F, nrhs, wb.tripot.p, st);
-        if (all) tm.end(ST_INTERP, st, e1);
-        if (tm.on) tm.begin(ST_SPMV, st, e1);
-        launch_spmm_far<T>(g, E, nrhs, g.d_rwgloc.p, coef_of<T>(g), wb.tripot.p, kscal, near_of<T>(md, op), x,
-                           wb.xt.p, y, st);
-        if (tm.on) tm.end(ST_SPMV, st, e1, sizeof(T) == 8 ? ST_SPMV64 : -1);
-        if (all) tm.end(ST_PRODUCT, st, e0);
+    const GridView v = view_of(g);
+    Work<T> &w = work_sel<T>(g);
+    ensure_work(v, w, nrhs, E);
+    // rows outside the medium's objects are zero
+    if (v.rwg0 > 0 || v.rwg1 < E) launch_zero<T>((int64_t)nrhs * E, y, st);
+    run_product<T>(p, v, media_of<T>(md, false), op, nrhs, x, y, bufs_of(w), w.xt.p, &p->timer, st);
+}
+
+template <typename T>
+void group_product(sie_problem *p, Group &gr, sie_op op, bool scaled, int nrhs, const cx<T> *x, cx<T> *y,
+                   hipStream_t st) {
+    const int64_t E = p->mesh.nrwg;
+    if (gr.media.size() == 1) {
+        Medium &md = p->ints[gr.media[0]];
+        Grid &g = *md.grid;
+        const GridView v = view_of(g);
+        Work<T> &w = work_sel<T>(g);
+        ensure_work(v, w, nrhs, E);
+        run_product<T>(p, v, media_of<T>(md, scaled), op, nrhs, x, y, bufs_of(w), w.xt.p, &p->timer, st, true);
         return;
     }
-    for (int r = 0; r < nrhs; ++r) {
-        if (all) { tm.begin(ST_PRODUCT, st, e0); tm.begin(ST_PROJECT, st, e1); }
-        launch_tri_sources<T>(g, g.d_trirwg.p, coef_of<T>(g), x + r * E, E, 1, w.trisrc.p, st);
-        launch_project<T>(g, mom_of<T>(g), w.trisrc.p, w.grid.p, F, 1, st);
-        if (all) { tm.end(ST_PROJECT, st, e1); tm.begin(ST_FFT, st, e1); }
-        fft_convolve<T>(g, spec_of<T>(md), F, op == SIE_OP_L ? 0 : 1, w.grid.p, w.grid.p, w.bufA.p, w.bufB.p, st);
-        if (all) { tm.end(ST_FFT, st, e1); tm.begin(ST_INTERP, st, e1); }
-        launch_interp<T>(g, mom_of<T>(g), w.grid.p, F, 1, w.tripot.p, st);
-        if (all) tm.end(ST_INTERP, st, e1);
-        if (tm.on) tm.begin(ST_SPMV, st, e1);
-        launch_spmv_far<T>(g, E, g.d_rwgloc.p, coef_of<T>(g), w.tripot.p, kscal, near_of<T>(md, op), x + r * E,
-                           y + r * E, true, st);
-        if (tm.on) tm.end(ST_SPMV, st, e1, sizeof(T) == 8 ? ST_SPMV64 : -1);
-        if (all) tm.end(ST_PRODUCT, st, e0);
-    }
+    Work<T> &w = work_sel<T>(gr);
+    ensure_work(gr.view, w, nrhs, E);
+    run_product<T>(p, gr.view, media_of<T>(gr, scaled), op, nrhs, x, y, bufs_of(w), w.xt.p, &p->timer, st, true);
+}
+
+template <typename T>
+void product_one(sie_problem *p, Medium &md, sie_op op, const cx<T> *x, cx<T> *y, const ProductBufs<T> &b,
+                 StageTimer *tm, hipStream_t st) {
+    const GridView v = view_of(*md.grid);
+    const int64_t E = p->mesh.nrwg;
+    if (v.rwg0 > 0 || v.rwg1 < E) launch_zero<T>(E, y, st);
+    run_product<T>(p, v, media_of<T>(md, false), op, 1, x, y, b, nullptr, tm, st);
+}
+
+// Elements of cx<T> each buffer of one single-right-hand-side product needs
+// (L-type, four fields; a K-type product uses the first three).
+ProductSizes product_sizes(const Grid &g) {
+    const int64_t F = 4;
+    const int64_t ntg = (int64_t)g.tris.size();
+    return {F * g.nlive(), F * g.nl[2] * g.nl[1] * g.m[0], F * g.nl[2] * g.m[1] * g.m[0], 4 * ntg, 5 * ntg};
 }
 
 template <typename T>
 void stage_project(sie_problem *p, Medium &md, const cx<T> *x, cx<T> *grid, hipStream_t st) {
     Grid &g = *md.grid;
+    const GridView v = view_of(g);
     Work<T> &w = work_of<T>(g);
-    launch_tri_sources<T>(g, g.d_trirwg.p, coef_of<T>(g), x, p->mesh.nrwg, 1, w.trisrc.p, st);
-    launch_project<T>(g, mom_of<T>(g), w.trisrc.p, grid, 4, 1, st);
+    launch_tri_sources<T>(v, coef_v<T>(v), x, p->mesh.nrwg, 1, w.trisrc.p, st);
+    launch_project<T>(v, mom_v<T>(v), w.trisrc.p, grid, 4, 1, st);
 }
 
 template <typename T>
 void stage_convolve(sie_problem *p, Medium &md, sie_op op, int nf, const cx<T> *in, cx<T> *out, hipStream_t st) {
     Grid &g = *md.grid;
     Work<T> &w = work_of<T>(g);
+    SIE_CHECK(!md.local, SIE_ESTATE, "the medium has no grid part (skin-depth cutoff or every pair near)");
     if (op == SIE_OP_K) SIE_CHECK(nf == 3, SIE_EINVAL, "the grad-G convolution takes 3 fields");
     else SIE_CHECK(nf >= 1 && nf <= 4, SIE_EINVAL, "nfields must be 1..4");
-    fft_convolve<T>(g, spec_of<T>(md), nf, op == SIE_OP_K ? 1 : 0, in, out, w.bufA.p, w.bufB.p, st);
+    fft_convolve<T>(view_of(g), spec_of<T>(md), 0, nf, 1, nf, op == SIE_OP_K ? 1 : 0, in, out, w.bufA.p, w.bufB.p,
+                    st);
 }
 
 template <typename T>
 void stage_interpolate(sie_problem *p, Medium &md, const cx<T> *grid, cx<T> *y, hipStream_t st) {
     Grid &g = *md.grid;
+    const GridView v = view_of(g);
     Work<T> &w = work_of<T>(g);
-    const c128 ks = cdiv(c128(-2.0), md.k * md.k);
-    launch_interp<T>(g, mom_of<T>(g), grid, 4, 1, w.tripot.p, st);
-    launch_spmv_far<T>(g, p->mesh.nrwg, g.d_rwgloc.p, coef_of<T>(g), w.tripot.p, cx<T>((T)ks.re, (T)ks.im),
-                       (const cx<T> *)nullptr, (const cx<T> *)nullptr, y, true, st);
+    const int64_t E = p->mesh.nrwg;
+    launch_interp<T>(v, mom_v<T>(v), grid, 4, 1, w.tripot.p, st);
+    if (v.rwg0 > 0 || v.rwg1 < E) launch_zero<T>(E, y, st);
+    const MediaView<T> mv = media_of<T>(md, false);
+    launch_spmv_far<T>(v, coef_v<T>(v), w.tripot.p, mv.kscal, (const cx<T> *)nullptr, (const cx<T> *)nullptr,
+                       (const cx<T> *)nullptr, y, true, st);
 }
 
 #define SIE_INST_MV(T)                                                                                     \
     template void matvec<T>(sie_problem *, Medium &, sie_op, int, const cx<T> *, cx<T> *, hipStream_t);    \
+    template void group_product<T>(sie_problem *, Group &, sie_op, bool, int, const cx<T> *, cx<T> *,       \
+                                   hipStream_t);                                                           \
+    template void product_one<T>(sie_problem *, Medium &, sie_op, const cx<T> *, cx<T> *, const ProductBufs<T> &, \
+                                 StageTimer *, hipStream_t);                                               \
     template void stage_project<T>(sie_problem *, Medium &, const cx<T> *, cx<T> *, hipStream_t);          \
     template void stage_convolve<T>(sie_problem *, Medium &, sie_op, int, const cx<T> *, cx<T> *, hipStream_t); \
     template void stage_interpolate<T>(sie_problem *, Medium &, const cx<T> *, cx<T> *, hipStream_t);
@@ -669,40 +1041,85 @@ void problem_setup(sie_problem *p) {
         md.eps = c128(EPS0 * p->objs[i].eps_r, -p->objs[i].sigma / w);
         md.mu = c128(MU0 * p->objs[i].mu_r);
     }
+    // per-triangle bounding radius about the centroid, for the skin-depth
+    // cutoff of the near lists
+    p->rho = bounding_radii(m);
+    p->d_rho.upload(p->rho);
+    // cutoff distance of an interior medium (0: none): the chosen number of
+    // skin depths, delta = -1 / Im k_i (Sec. V)
+    auto cutoff_of = [&](int i) {
+        const double ki = p->ints[i].k.im;
+        return p->cutoff_factor > 0.0 && ki < 0.0 ? p->cutoff_factor / -ki : 0.0;
+    };
+    auto rho_max = [&](int obj) {
+        double r = 0.0;
+        for (int64_t t = 0; t < m.nt(); ++t)
+            if (obj < 0 || m.tri_obj[t] == obj) r = std::max(r, p->rho[t]);
+        return r;
+    };
+    // the cutoff removes the grid part when every far pair (centroids at
+    // least R h apart along an axis) lies beyond it
+    auto cut_local = [&](int i, double h, int R) {
+        const double dc = cutoff_of(i);
+        return dc > 0.0 && dc <= R * h - 2.0 * rho_max(i);
+    };
     // grids
     p->grids.clear();
-    const double lam0 = 2.0 * 3.14159265358979323846 / p->ext.k.re;
+    auto shares = [&](int i) {
+        const GridReq &rq = p->obj_req[i];
+        return rq.share == 1 || (rq.share == -1 && m.nobj == 1);
+    };
+    std::vector<char> unshare(m.nobj, 0);   // local under the cutoff: a near list of its own
     {
         auto g = std::make_unique<Grid>();
         for (int64_t t = 0; t < m.nt(); ++t) g->tris.push_back((int32_t)t);
         for (int i = 0; i < m.nobj; ++i) g->objs.push_back(i);
-        build_grid_geometry(p, *g, p->ext_req, lam0);
+        std::vector<MediumProps> users{{p->bg_eps_r, p->bg_mu_r, 0.0}};
+        for (int i = 0; i < m.nobj; ++i)
+            if (shares(i)) users.push_back({p->objs[i].eps_r, p->objs[i].mu_r, p->objs[i].sigma});
+        build_grid_geometry(p, *g, p->ext_req, users);
+        for (int i = 0; i < m.nobj; ++i)
+            if (shares(i) && cut_local(i, g->h, p->obj_req[i].R)) unshare[i] = 1;
         build_grid(p, *g);
         setup_mark("exterior grid");
         p->ext.grid = g.get();
+        p->ext.local = g->all_near;
         p->grids.push_back(std::move(g));
     }
     for (int i = 0; i < m.nobj; ++i) {
-        const GridReq &rq = p->obj_req[i];
-        const bool share = rq.share == 1 || (rq.share == -1 && m.nobj == 1);
-        if (share) {
+        GridReq rq = p->obj_req[i];
+        Medium &md = p->ints[i];
+        if (shares(i) && !unshare[i]) {
             SIE_CHECK(m.nobj == 1, SIE_EINVAL, "interior grids can share the exterior grid only for one object");
-            p->ints[i].grid = p->ext.grid;
+            md.grid = p->ext.grid;
+            md.local = p->ext.grid->all_near;
             continue;
         }
         auto g = std::make_unique<Grid>();
         for (int64_t t = 0; t < m.nt(); ++t)
             if (m.tri_obj[t] == i) g->tris.push_back((int32_t)t);
         g->objs.push_back(i);
-        const double lam_r = 2.0 * 3.14159265358979323846 /
-                             (p->ext.k.re * std::sqrt(p->objs[i].eps_r * p->objs[i].mu_r));
-        build_grid_geometry(p, *g, rq, lam_r);
+        if (unshare[i]) {
+            // the exterior grid's geometry, the medium's own (cut) near list
+            const Grid &ge = *p->ext.grid;
+            rq.h = ge.h;
+            rq.n = ge.n[0];
+            rq.has_origin = true;
+            for (int c = 0; c < 3; ++c) rq.origin[c] = ge.origin[c];
+        }
+        build_grid_geometry(p, *g, rq, {{p->objs[i].eps_r, p->objs[i].mu_r, p->objs[i].sigma}});
+        const bool cut = cut_local(i, g->h, g->near_radius);
+        if (cut) g->cutoff = cutoff_of(i);
         build_grid(p, *g);
-        p->ints[i].grid = g.get();
+        md.local = cut || g->all_near;
+        md.grid = g.get();
         p->grids.push_back(std::move(g));
     }
+    form_groups(p);
     build_medium(p, p->ext);
     for (int i = 0; i < m.nobj; ++i) build_medium(p, p->ints[i]);
+    finalize_groups(p);
+    setup_mark("groups");
     p->is_setup = true;
 }
 

@@ -19,24 +19,36 @@ struct GridReq {
     int n = 0;         // 0 = rule
     int R = 5;
     int share = -1;    // -1 default, 0 own grid, 1 share exterior grid
+    double h = 0;      // > 0 with n > 0: explicit spacing
+    double origin[3] = {0, 0, 0};
+    bool has_origin = false;
 };
+// host_grid.cpp: grid rule of Sec. IV (eq. LboundsD2, Ddef)
+double loss_ratio(int n, double theta0, double s);
+void choose_grid(double freq, double eps_r, double mu_r, double sigma, double extent, double mean_edge,
+                 int near_radius, int strict, sie_grid_params *out);
 
 struct SolveState;     // solver.cpp
 
 // HIP-event timers of the operator stages (enabled per problem).
 // ST_SPMV64 counts the FP64 near-field products a second time (they are in
 // ST_SPMV as well).
-enum Stage { ST_PROJECT = 0, ST_FFT = 1, ST_INTERP = 2, ST_SPMV = 3, ST_PRODUCT = 4, ST_SPMV64 = 5, NSTAGE = 6 };
+// ST_INT32 / ST_INT64 count the interior media's near-field products (the
+// nested operator's, through the product groups) once more, per precision.
+enum Stage {
+    ST_PROJECT = 0, ST_FFT = 1, ST_INTERP = 2, ST_SPMV = 3, ST_PRODUCT = 4, ST_SPMV64 = 5, ST_INT32 = 6,
+    ST_INT64 = 7, NSTAGE = 8
+};
 struct StageTimer {
     int on = 0;   // 0 off, 1 every stage, 2 the near-field CSR product alone
-    struct Rec { int stage, extra; hipEvent_t a, b; };
+    struct Rec { int stage, extra, extra2; hipEvent_t a, b; };
     std::vector<Rec> pending;
     std::vector<hipEvent_t> pool;
-    double total_ms[NSTAGE] = {0, 0, 0, 0, 0, 0};
-    int64_t count[NSTAGE] = {0, 0, 0, 0, 0, 0};
+    double total_ms[NSTAGE] = {};
+    int64_t count[NSTAGE] = {};
     hipEvent_t get();
     void begin(int stage, hipStream_t st, hipEvent_t &a);
-    void end(int stage, hipStream_t st, hipEvent_t a, int extra = -1);
+    void end(int stage, hipStream_t st, hipEvent_t a, int extra = -1, int extra2 = -1);
     void flush();
     void reset();
     ~StageTimer();
@@ -52,15 +64,20 @@ struct sie_problem {
     std::vector<sie::GridReq> obj_req;
     sie_quad_params quad{0, 0, 0, 0, 0, 0};
     bool is_setup = false;
+    double t_setup_s = 0;
+    double cutoff_factor = 0;       // skin-depth cutoff in skin depths (0: off)
 
     sie::Mesh mesh;
     std::vector<std::unique_ptr<sie::Grid>> grids;
     sie::Medium ext;
     std::vector<sie::Medium> ints;
+    std::vector<std::unique_ptr<sie::Group>> groups;   // interior media batched by grid shape
     // device mesh arrays
     sie::DBuf<double> d_xyz, d_centroid;
     sie::DBuf<int32_t> d_tri, d_tri_rwg, d_tpm, d_epm;
     sie::DBuf<double> d_len, d_area, d_tri_sign;
+    sie::DBuf<double> d_rho;           // [nt] largest vertex distance from the centroid
+    std::vector<double> rho;
     // X operator (CSR, real)
     sie::DBuf<int32_t> d_xptr, d_xcol;
     sie::DBuf<double> d_xval64;
@@ -80,6 +97,28 @@ namespace sie {
 void problem_setup(sie_problem *p);
 template <typename T>
 void matvec(sie_problem *p, Medium &md, sie_op op, int nrhs, const cx<T> *x, cx<T> *y, hipStream_t st);
+// The product of every medium of a group on the group's rows (others not
+// written), times -j w eps~_i per medium when `scaled` (the nested
+// operator of eq. nest2).
+template <typename T>
+void group_product(sie_problem *p, Group &gr, sie_op op, bool scaled, int nrhs, const cx<T> *x, cx<T> *y,
+                   hipStream_t st);
+// Stage intermediates of one single-right-hand-side product: grid sources
+// and potentials [F][nlive], the FFT pass buffers, per-triangle projection
+// coefficients [ntg][4] and interpolation partials [ntg][5].
+template <typename T>
+struct ProductBufs {
+    cx<T> *grid, *bufA, *bufB, *trisrc, *tripot;
+};
+struct ProductSizes {
+    int64_t grid, bufA, bufB, trisrc, tripot;   // elements
+};
+ProductSizes product_sizes(const Grid &g);
+// One AIM product y = Op_medium x (one right-hand side) in the given
+// buffers; tm (nullable) records stage timings.  Allocates nothing.
+template <typename T>
+void product_one(sie_problem *p, Medium &md, sie_op op, const cx<T> *x, cx<T> *y, const ProductBufs<T> &b,
+                 StageTimer *tm, hipStream_t st);
 template <typename T>
 void stage_project(sie_problem *p, Medium &md, const cx<T> *x, cx<T> *grid, hipStream_t st);
 template <typename T>
@@ -87,6 +126,8 @@ void stage_convolve(sie_problem *p, Medium &md, sie_op op, int nf, const cx<T> *
 template <typename T>
 void stage_interpolate(sie_problem *p, Medium &md, const cx<T> *grid, cx<T> *y, hipStream_t st);
 void solver_destroy(SolveState *s);
+// server.cpp: device bytes of a problem, estimated from its description
+size_t estimate_footprint(const sie_problem *p, int restart, int inner_max_iter);
 void planewaves_entry(sie_problem *p, int32_t nrhs, const double *khat, const sie_c128 *e0);
 void solve_entry(sie_problem *p, sie_precision prec, const sie_solver_opts *opts, sie_report *rep);
 void nested_precond_entry(sie_problem *p, int precond, sie_precision prec, int nrhs, const void *x, void *y,
@@ -98,6 +139,7 @@ void set_last_error(const std::string &m);
 void farfield_entry(const sie_problem *p, int32_t rhs, int64_t ndir, const double *rhat, sie_c128 *F);
 
 // ---- k_blas.hip
+template <typename T> void launch_zero(int64_t n, cx<T> *y, hipStream_t st);
 template <typename Ti, typename To> void launch_convert(const cx<Ti> *in, cx<To> *out, int64_t n, hipStream_t st);
 template <typename T> void launch_axpby(int64_t n, c128 a, const cx<T> *x, c128 b, cx<T> *y, hipStream_t st);
 template <typename T> void launch_scale_into(int64_t n, c128 a, const cx<T> *x, cx<T> *y, hipStream_t st);

@@ -40,12 +40,14 @@ double now_s(std::chrono::steady_clock::time_point t0) {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
+}  // namespace
+
 // Device bytes of one problem, estimated from its description: near-field
 // CSR of every medium (FP64 L, K and direct L, FP32 L and K, column index;
 // rows times an estimate of the RWG functions within the near region),
 // grid buffers and spectra, and the Krylov bases of the solve (outer
 // dimension `restart`, nested max(restart, min(inner_max_iter, 300))).
-size_t estimate_footprint(const sie_problem *p, int restart, int inner_max_iter) {
+size_t sie::estimate_footprint(const sie_problem *p, int restart, int inner_max_iter) {
     int64_t T = 0;
     for (const auto &o : p->objs) T += (int64_t)o.tri.size() / 3;
     const double E = 1.5 * (double)T;
@@ -83,8 +85,6 @@ size_t estimate_footprint(const sie_problem *p, int restart, int inner_max_iter)
     b += E * 64.0 * 16.0;                                     // vectors of the solve
     return (size_t)b;
 }
-
-}  // namespace
 
 struct sie_server {
     sie_ctx *ctx = nullptr;

@@ -584,7 +584,8 @@ struct SolveState {
     Gmres<float> go32, gi32;
     DBuf<c128> t64[6];
     DBuf<c64> t32[6];
-    int matvecs = 0, inner_iters = 0, inner_max = 0;
+    int64_t matvecs = 0, kmatvecs = 0;   // L-type / K-type products, one per medium and right-hand side
+    int inner_iters = 0, inner_max = 0;
 };
 
 void solver_destroy(SolveState *s) { delete s; }
@@ -620,6 +621,11 @@ struct Ops {
     int inner_max_iter;
     int restart;
 
+    // Nested systems per right-hand side: one per object when the objects
+    // have equal RWG counts (their block-diagonal systems then iterate side
+    // by side in lock step, each with its own Krylov basis, tolerance and
+    // convergence), else one for all of them.
+    int nsys = 1;
     Ops(sie_problem *p_, SolveState &s_, hipStream_t st_, double itol, int imax, int rs, int nb_)
         : p(p_), s(s_), st(st_), E(p_->mesh.nrwg), nb(nb_), NE((int64_t)nb_ * p_->mesh.nrwg), inner_tol(itol),
           inner_max_iter(imax), restart(rs) {
@@ -628,40 +634,39 @@ struct Ops {
             if (tb[i].n != (size_t)NE) tb[i].alloc(NE);
             t[i] = tb[i].p;
         }
-        inner_of<T>(s).init(E, nb, nested_dim(restart, imax));
+        const std::vector<int64_t> &o0 = p->mesh.obj_rwg0;
+        const int nobj = (int)o0.size() - 1;
+        bool equal = nobj > 1;
+        for (int i = 1; i < nobj && equal; ++i) equal = o0[i + 1] - o0[i] == o0[1] - o0[0];
+        nsys = equal ? nobj : 1;
+        inner_of<T>(s).init(E / nsys, nb * nsys, nested_dim(restart, imax));
         outer_of<T>(s).init(E, nb, restart);
         inner_of<T>(s).tag = sizeof(T) == 8 ? "inner64" : "inner32";
         outer_of<T>(s).tag = sizeof(T) == 8 ? "outer64" : "outer32";
     }
 
+    void count(sie_op op, int64_t n) {
+        if (op == SIE_OP_L) s.matvecs += n;
+        else if (op == SIE_OP_K) s.kmatvecs += n;
+    }
     void mv(Medium &md, sie_op op, const cx<T> *x, cx<T> *y) {
         matvec<T>(p, md, op, nb, x, y, st);
-        if (op != SIE_OP_X) s.matvecs += nb;
+        count(op, nb);
     }
-    // y = sum_i (-j w eps~_i) L_i x   (block diagonal over objects)
-    void Lhat(const cx<T> *x, cx<T> *y) {
-        for (size_t i = 0; i < p->ints.size(); ++i) {
-            Medium &md = p->ints[i];
-            const c128 sc = c128(0.0, -p->w) * md.eps;
-            if (i == 0) {
-                mv(md, SIE_OP_L, x, y);
-                launch_scale_into<T>(NE, sc, y, y, st);
-            } else {
-                mv(md, SIE_OP_L, x, t[5]);
-                launch_axpby<T>(NE, sc, t[5], c128(1.0), y, st);
-            }
+    // Product of every interior medium on its own rows, one launch per stage
+    // and group of media (the groups' rows cover all RWG functions).
+    void interior(sie_op op, bool scaled, const cx<T> *x, cx<T> *y) {
+        for (auto &gp : p->groups) {
+            group_product<T>(p, *gp, op, scaled, nb, x, y, st);
+            count(op, (int64_t)nb * (int64_t)gp->media.size());
         }
     }
+    // y = sum_i (-j w eps~_i) L_i x   (block diagonal over objects)
+    void Lhat(const cx<T> *x, cx<T> *y) { interior(SIE_OP_L, true, x, y); }
     // y = sum_i K_i x + sgn X x / 2
-    void KpX(bool interior, double sgn, const cx<T> *x, cx<T> *y) {
-        if (interior) {
-            for (size_t i = 0; i < p->ints.size(); ++i) {
-                if (i == 0) mv(p->ints[i], SIE_OP_K, x, y);
-                else {
-                    mv(p->ints[i], SIE_OP_K, x, t[5]);
-                    launch_axpby<T>(NE, c128(1.0), t[5], c128(1.0), y, st);
-                }
-            }
+    void KpX(bool interior_side, double sgn, const cx<T> *x, cx<T> *y) {
+        if (interior_side) {
+            interior(SIE_OP_K, false, x, y);
         } else {
             mv(p->ext, SIE_OP_K, x, y);
         }
@@ -700,10 +705,13 @@ struct Ops {
     std::vector<double> relax_eps;
     void inner_solve_native(const cx<T> *a, cx<T> *v) {
         SIE_HIP(hipMemsetAsync(v, 0, NE * sizeof(cx<T>), st));
-        std::vector<double> tol(nb, inner_tol);
+        // system k of the nested solver: right-hand side k / nsys, object k mod nsys
+        std::vector<double> tol((size_t)nb * nsys, inner_tol);
         if (relax_res)
-            for (int k = 0; k < nb; ++k)
-                tol[k] = std::min(kRelaxCap, std::max(inner_tol, relax_eps[k] / std::max((*relax_res)[k], 1e-300)));
+            for (int k = 0; k < nb * nsys; ++k) {
+                const int r = k / nsys;
+                tol[k] = std::min(kRelaxCap, std::max(inner_tol, relax_eps[r] / std::max((*relax_res)[r], 1e-300)));
+            }
         int it = inner_of<T>(s).solve([&](const cx<T> *x, cx<T> *y) { Lhat(x, y); },
                                       [&](const cx<T> *x, cx<T> *y) { prec_inner(x, y); }, a, v, tol,
                                       inner_max_iter, nullptr, st, nullptr, true, true);
@@ -822,7 +830,8 @@ static void solve_all(sie_problem *p, sie_precision prec, const sie_solver_opts 
     const int64_t E = s.E;
     hipStream_t st = 0;
     if (o.precond != 0) build_preconditioners(p, s, o.precond);
-    s.matvecs = s.inner_iters = s.inner_max = 0;
+    s.matvecs = s.kmatvecs = 0;
+    s.inner_iters = s.inner_max = 0;
     int outer_total = 0, sweeps_total = 0;
     double worst = 0.0;
     bool all_conv = true;
@@ -928,6 +937,9 @@ static void solve_all(sie_problem *p, sie_precision prec, const sie_solver_opts 
         rep->inner_iters_max = s.inner_max;
         rep->refine_sweeps = sweeps_total;
         rep->matvecs = s.matvecs;
+        rep->k_matvecs = s.kmatvecs;
+        rep->t_setup_s = p->t_setup_s;
+        rep->device_bytes = estimate_footprint(p, o.restart, o.inner_max_iter);
         rep->residual = worst;
         rep->t_solve_s = dt;
     }

@@ -16,6 +16,7 @@ SIE_OK, SIE_EINVAL, SIE_ENOMEM, SIE_EMESH, SIE_EGRID, SIE_ENOCONV, SIE_EDEVICE, 
 FP64, FP32 = 0, 1
 OP_L, OP_K, OP_X = 0, 1, 2
 EXTERIOR = -1
+INTERIORS = -2
 
 _STATUS = {SIE_EINVAL: "EINVAL", SIE_ENOMEM: "ENOMEM", SIE_EMESH: "EMESH", SIE_EGRID: "EGRID",
            SIE_ENOCONV: "ENOCONV", SIE_EDEVICE: "EDEVICE", SIE_ESTATE: "ESTATE"}
@@ -36,6 +37,17 @@ class QuadParams(ctypes.Structure):
                 ("touch_out", "touch_in", "close_out", "close_in", "far_out", "far_in")]
 
 
+class GridParams(ctypes.Structure):
+    _fields_ = [("h", ctypes.c_double), ("n", ctypes.c_int32), ("origin", ctypes.c_double * 3),
+                ("order", ctypes.c_int32), ("near_radius", ctypes.c_int32), ("loss_ratio", ctypes.c_double),
+                ("lambda_r", ctypes.c_double)]
+
+    def as_dict(self):
+        d = {n: getattr(self, n) for n, _ in self._fields_ if n != "origin"}
+        d["origin"] = tuple(self.origin)
+        return d
+
+
 class SolverOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("inner_tol", ctypes.c_double), ("restart", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("inner_max_iter", ctypes.c_int32),
@@ -45,7 +57,8 @@ class SolverOpts(ctypes.Structure):
 class Report(ctypes.Structure):
     _fields_ = [("outer_iters", ctypes.c_int32), ("inner_iters", ctypes.c_int32),
                 ("inner_iters_max", ctypes.c_int32), ("refine_sweeps", ctypes.c_int32),
-                ("matvecs", ctypes.c_int32), ("residual", ctypes.c_double), ("t_solve_s", ctypes.c_double)]
+                ("matvecs", ctypes.c_int64), ("k_matvecs", ctypes.c_int64), ("residual", ctypes.c_double),
+                ("t_setup_s", ctypes.c_double), ("t_solve_s", ctypes.c_double), ("device_bytes", ctypes.c_size_t)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -81,7 +94,13 @@ SIGNATURES = [
                                               ctypes.c_double, ctypes.c_double, ctypes.c_double, _I32P]),
     ("sie_problem_set_grid", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                             ctypes.c_int32]),
+    ("sie_grid_choose", ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.POINTER(GridParams)]),
+    ("sie_problem_set_grid_params", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.POINTER(GridParams), ctypes.c_int32]),
     ("sie_problem_set_quadrature", ctypes.c_int, [_VP, ctypes.POINTER(QuadParams)]),
+    ("sie_problem_set_skin_cutoff", ctypes.c_int, [_VP, ctypes.c_double]),
+    ("sie_medium_is_local", ctypes.c_int32, [_VP, ctypes.c_int32]),
     ("sie_problem_setup", ctypes.c_int, [_VP]),
     ("sie_problem_destroy", None, [_VP]),
     ("sie_problem_num_rwg", ctypes.c_int64, [_VP]),
@@ -147,6 +166,15 @@ def _stream(stream):
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def grid_choose(freq, eps_r, mu_r, sigma, extent, mean_edge, near_radius=5, strict=False):
+    """Grid rule of Sec. IV (library side): dict of h, n, order, near radius,
+    worst lossy/lossless bound ratio and lambda_r.  Host-only."""
+    g = GridParams()
+    _check(lib().sie_grid_choose(float(freq), float(eps_r), float(mu_r), float(sigma), float(extent),
+                                 float(mean_edge), int(near_radius), int(bool(strict)), ctypes.byref(g)))
+    return g.as_dict()
+
+
 class Context:
     def __init__(self, device=0):
         h = _VP()
@@ -188,12 +216,33 @@ class Problem:
     def set_grid(self, medium, n=0, near_radius=5, share=0):
         _check(lib().sie_problem_set_grid(self.h, medium, n, near_radius, share))
 
+    def set_grid_params(self, medium, h=0.0, n=0, origin=None, order=2, near_radius=5, share=0):
+        """Grid of a medium from explicit spacing, points per axis and first
+        node (origin None: centred on the medium's objects)."""
+        g = GridParams()
+        g.h, g.n, g.order, g.near_radius = float(h), int(n), int(order), int(near_radius)
+        o = (float("nan"),) * 3 if origin is None else tuple(float(v) for v in origin)
+        for c in range(3):
+            g.origin[c] = o[c]
+        _check(lib().sie_problem_set_grid_params(self.h, medium, ctypes.byref(g), int(share)))
+
     def set_quadrature(self, **orders):
         q = QuadParams(**{k: int(v) for k, v in orders.items()})
         _check(lib().sie_problem_set_quadrature(self.h, ctypes.byref(q)))
 
+    def set_skin_cutoff(self, skin_depths=5.0):
+        _check(lib().sie_problem_set_skin_cutoff(self.h, float(skin_depths)))
+
     def setup(self):
         _check(lib().sie_problem_setup(self.h))
+
+    def is_local(self, medium):
+        """True if the medium runs without grid part (skin-depth cutoff within
+        the near region, or every pair near)."""
+        r = lib().sie_medium_is_local(self.h, medium)
+        if r < 0:
+            _check(r)
+        return bool(r)
 
     # -- queries --------------------------------------------------------------
     @property
@@ -315,7 +364,7 @@ class Problem:
                                      _VP(y.data_ptr()), _stream(stream)))
         return y
 
-    STAGES = ("project", "fft", "interp", "spmv", "product", "spmv64")
+    STAGES = ("project", "fft", "interp", "spmv", "product", "spmv64", "spmv_int32", "spmv_int64")
 
     def set_timing(self, on=True):
         """True/1: time every stage; 2: the near-field CSR product alone; False/0: off."""
