@@ -254,6 +254,22 @@ sie_status sie_get_wavenumber(const sie_problem *p, int32_t medium, sie_c128 *k)
 #define SIE_INTERIORS (-2)
 sie_status sie_matvec(sie_problem *p, int32_t medium, sie_op op, sie_precision prec, int32_t nrhs,
                       const void *x_dev, void *y_dev, void *stream);
+/* Allocation-free form of sie_matvec, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): one right-hand side [E], same operators and result as
+ * sie_matvec, but the stage intermediates (grid sources and potentials, FFT
+ * pass buffers, per-triangle partials) live in a library-owned device array of
+ * SIE_NOALLOC_SCRATCH_BYTES per device (held from the first sie_ctx_create on
+ * that device until the process ends) instead of buffers the problem
+ * allocates.  The call allocates and frees nothing and does not synchronise.
+ * SIE_EINVAL when the medium's intermediates exceed the array (about 64 MiB
+ * holds an L product on a live box of ~1.6e6 complex64 nodes per field, or
+ * half that in FP64); SIE_EDEVICE when the problem's device is not current.
+ * All calls on one device share the array: calls that overlap on a device
+ * (two streams, two threads) race and must be serialised by the caller. */
+#define SIE_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+sie_status sie_matvec_noalloc(sie_problem *p, int32_t medium, sie_op op, sie_precision prec,
+                              const void *x_dev, void *y_dev, void *stream);
 /* The stages of one AIM product, exposed for stage-level checks: grid
  * sources [4][nl_z][nl_y][nl_x] (J_x, J_y, J_z, charge; x fastest) from RWG
  * coefficients (projection P, P_phi); the zero-padded FFT convolution on the

@@ -53,6 +53,7 @@ sie_status sie_ctx_create(int device, sie_ctx **out) {
         SIE_HIP(hipGetDeviceCount(&n));
         SIE_CHECK(device >= 0 && device < n, SIE_EDEVICE, "no HIP device " + std::to_string(device));
         SIE_HIP(hipSetDevice(device));
+        noalloc_init(device);
         auto *c = new sie_ctx;
         c->device = device;
         *out = c;
@@ -287,6 +288,19 @@ sie_status sie_matvec(sie_problem *p, int32_t medium, sie_op op, sie_precision p
             matvec<float>(p, md, op, nrhs, (const c64 *)x_dev, (c64 *)y_dev, st);
         else
             throw Error(SIE_EINVAL, "unknown precision");
+    });
+}
+
+sie_status sie_matvec_noalloc(sie_problem *p, int32_t medium, sie_op op, sie_precision prec, const void *x_dev,
+                              void *y_dev, void *stream) {
+    return guard([&] {
+        SIE_CHECK(p && p->is_setup, SIE_ESTATE, "problem not set up");
+        SIE_CHECK(x_dev && y_dev, SIE_EINVAL, "bad vectors");
+        SIE_CHECK(x_dev != y_dev, SIE_EINVAL, "x and y must not alias");
+        SIE_CHECK(op == SIE_OP_L || op == SIE_OP_K || op == SIE_OP_X, SIE_EINVAL, "unknown operator");
+        SIE_CHECK(prec == SIE_FP64 || prec == SIE_FP32, SIE_EINVAL, "unknown precision");
+        Medium &md = p->medium(op == SIE_OP_X ? -1 : medium);
+        matvec_noalloc(p, md, op, prec, x_dev, y_dev, user_stream(stream));
     });
 }
 

@@ -128,6 +128,11 @@ void stage_interpolate(sie_problem *p, Medium &md, const cx<T> *grid, cx<T> *y, 
 void solver_destroy(SolveState *s);
 // server.cpp: device bytes of a problem, estimated from its description
 size_t estimate_footprint(const sie_problem *p, int restart, int inner_max_iter);
+// noalloc.hip: device address of the allocation-free product's scratch on
+// `device` (current), looked up once; the product itself.
+void noalloc_init(int device);
+void matvec_noalloc(sie_problem *p, Medium &md, sie_op op, sie_precision prec, const void *x, void *y,
+                    hipStream_t st);
 void planewaves_entry(sie_problem *p, int32_t nrhs, const double *khat, const sie_c128 *e0);
 void solve_entry(sie_problem *p, sie_precision prec, const sie_solver_opts *opts, sie_report *rep);
 void nested_precond_entry(sie_problem *p, int precond, sie_precision prec, int nrhs, const void *x, void *y,

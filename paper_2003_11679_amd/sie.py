@@ -112,6 +112,7 @@ SIGNATURES = [
     ("sie_get_near_values", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int, _CP]),
     ("sie_get_wavenumber", ctypes.c_int, [_VP, ctypes.c_int32, _CP]),
     ("sie_matvec", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int, ctypes.c_int, ctypes.c_int32, _VP, _VP, _VP]),
+    ("sie_matvec_noalloc", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int, ctypes.c_int, _VP, _VP, _VP]),
     ("sie_project", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int, _VP, _VP, _VP]),
     ("sie_convolve", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int, ctypes.c_int, ctypes.c_int32, _VP, _VP, _VP]),
     ("sie_interpolate", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int, _VP, _VP, _VP]),
@@ -314,6 +315,17 @@ class Problem:
         nrhs = 1 if x.dim() == 1 else x.shape[0]
         _check(lib().sie_matvec(self.h, medium, op, prec, nrhs, _VP(x.data_ptr()), _VP(y.data_ptr()),
                                 _stream(stream)))
+        return y
+
+    def matvec_noalloc(self, medium, op, x, y, stream=None):
+        """y = Op x for one right-hand side x [E] on the device, through the
+        allocation-free entry point (y must be preallocated)."""
+        prec = self._prec_of(x)
+        if not (x.is_contiguous() and y.is_contiguous() and x.dim() == 1 and y.shape == x.shape
+                and y.dtype == x.dtype):
+            raise ValueError("x and y must be contiguous vectors of one shape and dtype")
+        _check(lib().sie_matvec_noalloc(self.h, medium, op, prec, _VP(x.data_ptr()), _VP(y.data_ptr()),
+                                        _stream(stream)))
         return y
 
     def nested_precond(self, precond, x, y=None, stream=None):
