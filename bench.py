@@ -2,28 +2,29 @@
 """Benchmark: SIE matvecs/s and served solves/s of the GIBC/AIM solver on one
 MI355X.
 
-Default workload: the 8 x 8 array of lossy dielectric cubes (196,608
-triangles, 294,912 RWG functions; eps_r ~ U[2, 10], sigma ~ U[0, 10] S/m,
-1 GHz, cube edge 0.2 lambda0, pitch 0.4 lambda0; exterior grid 256^3 with FFT
-512 x 512 x 64 on its live box, one 16^3 grid per cube, near region 11
-points across).  One step is one complete solve request: mesh topology,
-grids and stencils, near lists, FP64 near-field integrals with
-precorrection, Green's spectra, the plane wave, the nested GIBC solve (FP32
-interior stages, the 64 cubes batched into one launch per stage and solved
-as 64 nested systems side by side, inside FP64 refinement to the relative
-FP64 block residual --tol) and the far field.  The FP32 currents of the
-first warmup request are compared with an FP64 solve of the same request
-(relative error gate 1e-3).  --workload bar and sphere run the copper bar
-and the dielectric sphere the same way.  The synthetic meshes are generated
-on the host before the timed region; one request's problem is released
-before the next one starts.
+Default workload: the copper bar (100 x 10 x 5 um, sigma 5.8e7 S/m, 20,088
+triangles / 30,132 RWG functions, 10 GHz, 64^3 grid, near region 11 points
+across, interior skin-depth cutoff of 5 skin depths).  One step is one
+complete solve request: mesh topology, grid and stencils, near lists, FP64
+near-field integrals with precorrection, Green's spectra, the plane wave,
+the nested GIBC solve (FP32 interior stages inside FP64 refinement to the
+relative FP64 block residual --tol, default 1e-7; outer restart 1000) and
+the far field.  The FP32 currents of the first warmup request are compared
+with an FP64 solve of the same request (relative error gate 1e-3).  After
+the timed steps one request of the 8 x 8 lossy cube array (196,608
+triangles, 64 interior grids batched into one launch per stage, FP32 +
+refinement to 1e-6) is measured the same way, with its own FP64 gate and
+kernel roofline (--no-cube-array skips it).  --workload cubes and sphere
+time those configurations instead.  The synthetic meshes are generated on
+the host before the timed region; one request's problem is released before
+the next one starts.
 
 value = SIE matvecs / s over the timed steps: one SIE matvec is one L-type
 AIM product (eq. AIM_Lin) of one medium for one right-hand side; K-type
 products are counted beside it.  Solves/s and p50/p99 request latency are
-reported too.  The roofline object covers the dominant kernel, the
-near-field CSR product of the interior media (the nested operator) in FP32,
-timed with HIP events the library records on the stream the kernel runs on.
+reported too.  The roofline object covers the near-field CSR launch class
+with the largest measured time (per medium class and precision), timed with
+HIP events the library records on the stream the kernel runs on.
 """
 import argparse
 import json
@@ -47,16 +48,16 @@ def parse():
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=64, help="rows of the oracle's dense matvec sample")
-    ap.add_argument("--workload", choices=["cubes", "bar", "sphere", "fft", "batch", "serve", "counters"],
-                    default="cubes",
-                    help="cubes (default), bar, sphere: solve requests on the cube array, copper bar or "
+    ap.add_argument("--workload", choices=["bar", "cubes", "sphere", "fft", "batch", "serve", "counters"],
+                    default="bar",
+                    help="bar (default), cubes, sphere: solve requests on the copper bar, cube array or "
                          "dielectric sphere; fft: 4-field 256^3 convolution microbenchmark; "
                          "batch: 64 plane waves solved together on a 4,824-triangle copper bar; "
                          "serve: a Poisson stream of solve requests on the library's server; "
                          "counters: launches for HBM counter runs (1 GiB copy + copper-bar near-field products)")
     ap.add_argument("--nrhs", type=int, default=64, help="batch workload: plane waves")
     ap.add_argument("--requests", type=int, default=8, help="serve workload: requests of the trace")
-    ap.add_argument("--max-tri", type=int, default=8000, help="serve workload: triangle cap per request")
+    ap.add_argument("--max-tri", type=int, default=20000, help="serve workload: triangle cap per request")
     ap.add_argument("--max-iter", type=int, default=400, help="serve workload: outer iteration cap per solve")
     ap.add_argument("--inner-max-iter", type=int, default=300, help="serve workload: nested iteration cap")
     ap.add_argument("--slots", type=int, default=4, help="serve workload: concurrent requests")
@@ -73,14 +74,19 @@ def parse():
                          "this x (correction target) / (outer residual estimate); 0: fixed tolerance")
     ap.add_argument("--skin-cutoff", type=float, default=5.0,
                     help="skin-depth cutoff of the interior problem in skin depths (Sec. V; 0 off)")
-    ap.add_argument("--precond", type=int, default=4,
+    ap.add_argument("--no-cube-array", action="store_true",
+                    help="bar workload: skip the single cube-array request measured after the timed steps")
+    ap.add_argument("--precond", type=int, default=None,
                     help="preconditioner bit mask: 1 nested block-Jacobi, 2 outer block-Jacobi, 4 nested "
-                         "near-region preconditioner in Schwarz form (conductive media)")
+                         "near-region preconditioner in Schwarz form (conductive media), 8 with 4: for every "
+                         "interior medium; default 12 for the cube array, 4 otherwise")
     a = ap.parse_args()
     if a.tol is None:
         a.tol = 1e-7 if a.workload == "bar" else 1e-6
     if a.restart is None:
-        a.restart = {"bar": 1000, "cubes": 300}.get(a.workload, 200)
+        a.restart = {"bar": 1000, "cubes": 1000}.get(a.workload, 200)
+    if a.precond is None:
+        a.precond = 12 if a.workload == "cubes" else 4
     return a
 
 
@@ -114,7 +120,7 @@ def build_problem(cfg):
     return p
 
 
-def run_request(cfg, prec, tol, timing=False):
+def run_request(cfg, prec, tol, timing=False, opts=None):
     """One solve request; returns (problem, report, setup_s, total_s)."""
     import torch
     t0 = time.perf_counter()
@@ -124,7 +130,7 @@ def run_request(cfg, prec, tol, timing=False):
         p.set_timing(2)   # the near-field CSR products alone: two events per product
     w = cfg.waves[0]
     p.set_planewaves(w.khat, w.e0)
-    rep = p.solve(prec, tol=tol, **SOLVE_OPTS)
+    rep = p.solve(prec, tol=tol, **(SOLVE_OPTS if opts is None else opts))
     th = np.linspace(0.0, np.pi, 91)
     rhat = np.stack([np.sin(th), 0 * th, np.cos(th)], axis=1)
     F = p.far_field(rhat)
@@ -283,64 +289,108 @@ def fft_micro(args):
 
 
 def batch_workload(args):
-    """64 plane waves (8 x 8 incidence grid, alternating polarisation) on the
-    4,824-triangle copper bar of the batching meshes (100 x 10 x 5 um, 90 x 9
-    x 4 divisions, sigma 5.8e7 S/m, 10 GHz, 32^3 grid, near radius 5): one
-    step is one solve of all waves together (lock-step GMRES over the
-    right-hand sides, batched products: the near-field values are streamed
-    once per batch)."""
+    """64 plane waves (8 x 8 incidence grid, polarisation alternating theta /
+    phi) at 4 frequencies on a copper bar of the batching meshes (100 x 10 x 5
+    um, 90 x 9 x 4 divisions = 4,824 triangles, sigma 5.8e7 S/m; 1, 3, 10 and
+    30 GHz; 32^3 grid, near radius 5, skin-depth cutoff): each frequency is
+    one request whose 64 right-hand sides are solved together (lock-step
+    GMRES, batched products: near-field values streamed once per batch), and
+    the four frequencies run concurrently on the library's server.  One step
+    is the whole 4 x 64 batch.  The FP32 far field of one wave at 10 GHz is
+    checked against an FP64 single-wave solve."""
     import torch
     from workloads import box_mesh
     from workloads.configs import multi_rhs_waves
-    from paper_2003_11679_amd import Problem
+    from paper_2003_11679_amd import Problem, Server
     xyz, tri = box_mesh((100e-6, 10e-6, 5e-6), (90, 9, 4))
     waves = multi_rhs_waves()[:args.nrhs]
+    freqs = (1e9, 3e9, 10e9, 30e9)
     prec = 1 if args.precision == "fp32" else 0
     opts = dict(tol=args.tol, restart=args.restart, precond=args.precond, inner_relax=args.inner_relax)
+    khat = [w.khat for w in waves]
+    e0 = [w.e0 for w in waves]
+    th = np.linspace(0.0, np.pi, 37)
+    rhat = np.stack([np.sin(th), 0 * th, np.cos(th)], axis=1)
 
-    def one(timing=False):
-        p = Problem(10e9)
+    def problem(f, ctx=None):
+        p = Problem(f, ctx=ctx)
         p.add_object(xyz, tri, eps_r=1.0, sigma=5.8e7)
         p.set_grid(-1, n=32, near_radius=5)
-        t0 = time.perf_counter()
-        p.setup()
-        if timing:
-            p.set_timing(True)
-        p.set_planewaves([w.khat for w in waves], [w.e0 for w in waves])
-        rep = p.solve(prec, **opts)
-        torch.cuda.synchronize()
-        return p, rep, time.perf_counter() - t0
+        p.set_skin_cutoff(args.skin_cutoff)
+        return p
 
+    def one(timing=False):
+        srv = Server(max_slots=len(freqs))
+        t0 = time.perf_counter()
+        ts = [srv.submit(problem(f, srv.ctx), khat, e0, prec, **opts) for f in freqs]
+        infos, probs = [], []
+        for t in ts:
+            while True:
+                i = srv.poll(t)
+                if i["done"]:
+                    break
+                time.sleep(0.002)
+            infos.append(i)
+            probs.append(srv.take(t))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        srv.close()
+        return probs, infos, dt
+
+    ref = None
     for i in range(args.warmup):
-        _, rep, dt = one()
-        print(f"[bench] batch warmup {i}: {dt:.2f}s {rep}", file=sys.stderr, flush=True)
+        probs, infos, dt = one()
+        print(f"[bench] batch warmup {i}: {dt:.2f}s {[x['report'] for x in infos]}", file=sys.stderr, flush=True)
+        if i == 0:
+            q = problem(10e9)
+            q.setup()
+            q.set_planewaves(khat[5], e0[5])
+            q.solve(0, **opts)
+            F64 = q.far_field(rhat)
+            F32 = probs[2].far_field(rhat, rhs=5)
+            ref = {"rel_err_far_field": float(np.abs(F32 - F64).max() / np.abs(F64).max()),
+                   "wave": 5, "freq_hz": 10e9}
+            print(f"[bench] fp64 single-wave reference: {ref}", file=sys.stderr, flush=True)
+            del q
+        del probs
     t0 = time.perf_counter()
-    matvecs, reps = 0, []
+    matvecs = kmatvecs = 0
+    reps = []
     for i in range(args.steps):
-        p, rep, dt = one(timing=True)
-        matvecs += rep["matvecs"]
-        reps.append(rep)
-        print(f"[bench] batch step {i}: {dt:.2f}s {rep}", file=sys.stderr, flush=True)
+        probs, infos, dt = one()
+        for x in infos:
+            matvecs += x["report"]["matvecs"]
+            kmatvecs += x["report"]["k_matvecs"]
+            reps.append(x)
+        print(f"[bench] batch step {i}: {dt:.2f}s {[x['report'] for x in infos]}", file=sys.stderr, flush=True)
+        del probs
     T = time.perf_counter() - t0
-    st = p.stage_times()
-    print(json.dumps({"metric": "RHS-matvecs/s of a batched multi-RHS solve", "value": matvecs / T,
+    nrhs = len(waves) * len(freqs)
+    print(json.dumps({"metric": "RHS-matvecs/s of batched multi-RHS, multi-frequency solves", "value": matvecs / T,
                       "unit": "RHS-matvecs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
                       "ms_per_step": T / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
                       "vs_baseline": None, "dtype": "c64+f64" if prec == 1 else "c128", "data": "synthetic",
                       "config": {"workload": f"{len(waves)} plane waves (8x8 incidence grid, alternating "
-                                             "polarisation), copper bar 100x10x5 um, 4824 triangles, 10 GHz, "
-                                             f"32^3 grid, near radius 5, solve to {args.tol:g}"},
-                      "solves_per_s": args.steps / T, "rhs_solves_per_s": args.steps * len(waves) / T,
-                      "converged": all(r["converged"] for r in reps), "residual_fp64_max":
-                      max(r["residual"] for r in reps), "outer_iters": reps[-1]["outer_iters"],
-                      "batched_product_ms": {k: v[1] / max(v[0], 1) for k, v in st.items()}}))
+                                             "polarisation) x 4 frequencies (1, 3, 10, 30 GHz), copper bar "
+                                             "100x10x5 um, 4824 triangles, 32^3 grid, near radius 5, skin-depth "
+                                             f"cutoff {args.skin_cutoff:g}, solve to {args.tol:g}; frequencies "
+                                             "run concurrently on the server, right-hand sides in lock step"},
+                      "k_matvecs_per_s": kmatvecs / T, "rhs_solves_per_s": args.steps * nrhs / T,
+                      "batches_per_s": args.steps / T,
+                      "converged": all(x["status"] == 0 for x in reps),
+                      "residual_fp64_max": max(x["report"]["residual"] for x in reps),
+                      "fp32_vs_fp64": ref,
+                      "per_frequency_s": [x["t_end_s"] - x["t_start_s"] for x in reps[-len(freqs):]]}))
 
 
 def serve_workload(args):
     """The seeded Poisson request stream (50 req/s): each request a sphere,
-    box or ellipsoid with its own material and frequency, submitted at its
-    arrival time to the library's server (FP32 + FP64 refinement); latency =
-    completion - arrival, queueing, setup and solve included."""
+    box or ellipsoid with its own material and frequency, on the grid of the
+    Sec. IV rule (near radius 3, skin-depth cutoff), submitted at its arrival
+    time to the library's server; latency = completion - arrival (queueing,
+    setup and solve).  The same requests run twice, FP32 + FP64 refinement
+    and plain FP64; the far fields of each request are compared between the
+    two."""
     import torch
     from workloads.configs import serving_trace, serving_mesh
     from paper_2003_11679_amd import Problem, Server
@@ -350,60 +400,75 @@ def serve_workload(args):
         r = dict(r)
         r["nt"] = min(r["nt"], args.max_tri)
         xyz, tri = serving_mesh(r)
-        ext = float(np.max(xyz.max(0) - xyz.min(0)))
-        edge = float(np.mean(np.linalg.norm(xyz[tri[:, 1]] - xyz[tri[:, 0]], axis=1)))
-        n = 8
-        while ext / (n - 3) > edge and n < 256:
-            n *= 2
-        reqs.append((r, xyz, tri, n))
+        reqs.append((r, xyz, tri))
+    th = np.linspace(0.0, np.pi, 37)
+    rhat = np.stack([np.sin(th), 0 * th, np.cos(th)], axis=1)
+
+    def run(prec):
+        srv = Server(max_slots=args.slots)
+        t0 = time.perf_counter()
+        tickets = []
+        for r, xyz, tri in reqs:
+            dt = r["t"] - trace[0]["t"] - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            p = Problem(r["freq"], ctx=srv.ctx)
+            p.add_object(xyz, tri, eps_r=r["eps_r"], sigma=r["sigma"])
+            p.set_grid(-1, n=0, near_radius=3)
+            p.set_skin_cutoff(args.skin_cutoff)
+            tickets.append(srv.submit(p, (0.0, 0.0, -1.0), (1.0, 0.0, 0.0), prec, tol=args.tol, restart=100,
+                                      precond=args.precond, max_iter=args.max_iter,
+                                      inner_max_iter=args.inner_max_iter,
+                                      inner_relax=args.inner_relax if prec == 1 else 0.0))
+        infos = [None] * len(tickets)
+        far = [None] * len(tickets)
+        started = [False] * len(tickets)
+        left = set(range(len(tickets)))
+        while left:
+            for q in sorted(left):
+                i = srv.poll(tickets[q])
+                if i["running"] and not started[q]:
+                    started[q] = True
+                    print(f"[bench] {'fp32' if prec else 'fp64'} request {q + 1}: started", file=sys.stderr,
+                          flush=True)
+                if i["done"]:
+                    infos[q] = i
+                    left.discard(q)
+                    pq = srv.take(tickets[q])
+                    far[q] = pq.far_field(rhat) if i["status"] in (0, -5) else None
+                    del pq
+                    print(f"[bench] {'fp32' if prec else 'fp64'} request {q + 1}: status {i['status']} latency "
+                          f"{i['t_end_s'] - i['t_submit_s']:.2f}s run {i['t_end_s'] - i['t_start_s']:.2f}s "
+                          f"{i['report']}", file=sys.stderr, flush=True)
+            time.sleep(0.005)
+        wall = time.perf_counter() - t0
+        srv.close()
+        lat = [i["t_end_s"] - i["t_submit_s"] for i in infos]
+        span = max(i["t_end_s"] for i in infos) - min(i["t_submit_s"] for i in infos)
+        return {"solves_per_s": len(infos) / span, "latency_p50_s": float(np.percentile(lat, 50)),
+                "latency_p99_s": float(np.percentile(lat, 99)), "converged": sum(i["status"] == 0 for i in infos),
+                "wall_s": wall, "busy_s": sum(i["t_end_s"] - i["t_start_s"] for i in infos)}, infos, far
+
     prec = 1 if args.precision == "fp32" else 0
-    srv = Server(max_slots=args.slots)
-    t0 = time.perf_counter()
-    tickets = []
-    for r, xyz, tri, n in reqs:
-        dt = r["t"] - trace[0]["t"] - (time.perf_counter() - t0)
-        if dt > 0:
-            time.sleep(dt)
-        p = Problem(r["freq"], ctx=srv.ctx)
-        p.add_object(xyz, tri, eps_r=r["eps_r"], sigma=r["sigma"])
-        p.set_grid(-1, n=n, near_radius=3)
-        tickets.append(srv.submit(p, (0.0, 0.0, -1.0), (1.0, 0.0, 0.0), prec, tol=args.tol, restart=100,
-                                  precond=args.precond, max_iter=args.max_iter,
-                                  inner_max_iter=args.inner_max_iter, inner_relax=args.inner_relax))
-    # requests are reported as they start and as they finish (completion order)
-    infos = [None] * len(tickets)
-    started = [False] * len(tickets)
-    left = set(range(len(tickets)))
-    while left:
-        for q in sorted(left):
-            i = srv.poll(tickets[q])
-            if i["running"] and not started[q]:
-                started[q] = True
-                print(f"[bench] request {q + 1}: started", file=sys.stderr, flush=True)
-            if i["done"]:
-                infos[q] = i
-                left.discard(q)
-                print(f"[bench] request {q + 1}: status {i['status']} latency "
-                      f"{i['t_end_s'] - i['t_submit_s']:.2f}s run {i['t_end_s'] - i['t_start_s']:.2f}s "
-                      f"{i['report']}", file=sys.stderr, flush=True)
-                srv.take(tickets[q])
-        time.sleep(0.005)
-    T = time.perf_counter() - t0
-    srv.close()
-    lat = [i["t_end_s"] - i["t_submit_s"] for i in infos]
-    conv = sum(1 for i in infos if i["status"] == 0)
-    span = max(i["t_end_s"] for i in infos) - min(i["t_submit_s"] for i in infos)
-    print(json.dumps({"metric": "served solves/s, p50/p99 latency", "value": len(infos) / span,
+    main, infos, far = run(prec)
+    ref = None
+    if prec == 1:
+        ref, infos64, far64 = run(0)
+        errs = [float(np.abs(a - b).max() / np.abs(b).max()) for a, b in zip(far, far64)
+                if a is not None and b is not None]
+        ref["far_field_rel_err_max"] = max(errs) if errs else None
+        ref["far_field_rel_err_median"] = float(np.median(errs)) if errs else None
+    tris = [len(t) for _, _, t in reqs]
+    print(json.dumps({"metric": "served solves/s, p50/p99 latency", "value": main["solves_per_s"],
                       "unit": "solves/s", "n_gpus": 1, "steps": len(infos), "warmup": 0,
-                      "ms_per_step": span / len(infos) * 1e3, "higher_is_better": True, "scaling": "weak",
+                      "ms_per_step": 1e3 / main["solves_per_s"], "higher_is_better": True, "scaling": "weak",
                       "vs_baseline": None, "dtype": "c64+f64" if prec == 1 else "c128", "data": "synthetic",
-                      "config": {"workload": f"first {len(infos)} requests of the seeded 50 req/s trace, "
-                                             f"triangles capped at {args.max_tri}, {args.slots} slots, near "
-                                             f"radius 3, solve to {args.tol:g} (caps {args.max_iter} outer / "
-                                             f"{args.inner_max_iter} nested iterations)"},
-                      "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
-                      "converged": conv, "requests": len(infos), "wall_s": T,
-                      "offered_rate": 50.0}))
+                      "config": {"workload": f"first {len(infos)} requests of the seeded 50 req/s trace "
+                                             f"({min(tris)}-{max(tris)} triangles, cap {args.max_tri}), "
+                                             f"{args.slots} slots, Sec. IV grid rule, near radius 3, skin-depth "
+                                             f"cutoff {args.skin_cutoff:g}, solve to {args.tol:g} (caps "
+                                             f"{args.max_iter} outer / {args.inner_max_iter} nested iterations)"},
+                      **main, "offered_rate": 50.0, "fp64_same_requests": ref}))
 
 
 def counters_workload(args):
@@ -475,6 +540,84 @@ def main():
     request_workload(args)
 
 
+def spmv_classes(p, ncfg_objects, prec):
+    """Byte models of the near-field CSR launch classes of a request."""
+    media = list(range(ncfg_objects))
+    return {"interior": spmv_model(p, media, prec), "interior64": spmv_model(p, media, 0),
+            "exterior64": spmv_model(p, [-1], 0), "exterior32": spmv_model(p, [-1], 1),
+            "local": [p.is_local(m) for m in media]}
+
+
+def dominant_kernel(tm, model, prec):
+    """The near-field CSR launch class with the largest measured time, with
+    its HIP-event average and algorithmic bytes."""
+    ext64 = (tm["spmv64"][0] - tm["spmv_int64"][0], tm["spmv64"][1] - tm["spmv_int64"][1])
+    ext32 = (tm["spmv"][0] - tm["spmv64"][0] - tm["spmv_int32"][0],
+             tm["spmv"][1] - tm["spmv64"][1] - tm["spmv_int32"][1])
+    cls = {"interior media": (tm["spmv_int32"] if prec == 1 else tm["spmv_int64"],
+                              model["interior"] if prec == 1 else model["interior64"], prec == 1),
+           "exterior medium": (ext64, model["exterior64"], False)}
+    if prec == 1:
+        cls["exterior medium, FP32"] = (ext32, model["exterior32"], True)
+    name = max(cls, key=lambda k: cls[k][0][1])
+    (n, ms), (nb, nnz), fp32 = cls[name]
+    avg = ms / max(n, 1)
+    ach = nb / (avg * 1e-3) / 1e9 if n else None
+    return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS if ach else None,
+            "kernel": ("k_spmv_far<float> " if fp32 else "k_spmv_far<double> ") + f"({name})",
+            "avg_launch_ms": avg, "launches": n, "bytes_per_launch": nb, "nnz": nnz,
+            "share_of_csr_time": ms / max(tm["spmv"][1], 1e-30)}
+
+
+def fp64_gate(p, tol, opts):
+    """FP64 solve of the same request; relative differences of the FP32
+    currents and far field from it."""
+    u32, v32 = p.currents()
+    th = np.linspace(0.0, np.pi, 91)
+    rhat = np.stack([np.sin(th), 0 * th, np.cos(th)], axis=1)
+    F32 = p.far_field(rhat)
+    r64 = p.solve(0, tol=tol, **opts)
+    u64, v64 = p.currents()
+    F64 = p.far_field(rhat)
+    return {"rel_err_u": float(np.linalg.norm(u32 - u64) / np.linalg.norm(u64)),
+            "rel_err_v": float(np.linalg.norm(v32 - v64) / np.linalg.norm(v64)),
+            "rel_err_far_field": float(np.abs(F32 - F64).max() / np.abs(F64).max()),
+            "fp64_solve": r64}
+
+
+NAMES = {"cubes": "8x8 array of lossy dielectric cubes (edge 0.2 lambda0, pitch 0.4 lambda0, eps_r ~ U[2,10], "
+                  "sigma ~ U[0,10] S/m, seed 11682), 196608 triangles (294912 RWG), 1 GHz, exterior grid 256^3 "
+                  "(FFT on the live box), one 16^3 grid per cube",
+         "bar": "copper bar 100x10x5 um, sigma 5.8e7 S/m, 20088 triangles (30132 RWG), 10 GHz, 64^3 grid",
+         "sphere": "dielectric sphere r = 1 m, eps_r 4, 1280 triangles (1920 RWG), 150 MHz, 44^3 grid "
+                   "(the lambda_r/20 rule of Sec. IV)"}
+
+
+def cube_array_request(args):
+    """One cube-array request after the timed steps (FP32 + refinement to
+    1e-6, nested near-region preconditioner for every cube, outer restart
+    1000), with the near-field kernel roofline and the FP64 gate."""
+    import torch
+    cfg = workload_cfg("cubes")
+    opts = dict(restart=1000, precond=12, inner_relax=args.inner_relax)
+    p, rep, su, tot = run_request(cfg, 1, 1e-6, timing=True, opts=opts)
+    st = p.stage_times()
+    model = spmv_classes(p, len(cfg.objects), 1)
+    tm = {k: st[k] for k in ("spmv", "spmv64", "spmv_int32", "spmv_int64")}
+    roof = dominant_kernel(tm, model, 1)
+    print(f"[bench] cube array: setup {su:.2f}s total {tot:.2f}s {rep}", file=sys.stderr, flush=True)
+    gate = fp64_gate(p, 1e-6, dict(opts, inner_relax=0.0))
+    print(f"[bench] cube array fp64 gate: {gate}", file=sys.stderr, flush=True)
+    del p
+    torch.cuda.synchronize()
+    return {"workload": NAMES["cubes"] + ", near radius 5, plane wave -z x-polarised, 1 RHS, FP32 + FP64 "
+                                        "refinement to 1e-6",
+            "request_s": tot, "setup_s": su, "matvecs_per_s": rep["matvecs"] / tot,
+            "k_matvecs_per_s": rep["k_matvecs"] / tot, "converged": rep["converged"], "report": rep,
+            "roofline": roof, "fp32_vs_fp64": gate}
+
+
 def request_workload(args):
     """Solve requests of one configuration (see the module docstring)."""
     import torch
@@ -490,24 +633,10 @@ def request_workload(args):
     for i in range(args.warmup):
         p, rep, su, tot = run_request(cfg, prec, args.tol)
         print(f"[bench] warmup {i}: setup {su:.2f}s total {tot:.2f}s {rep}", file=sys.stderr, flush=True)
-        if i == 0:
-            media = list(range(len(cfg.objects)))
-            model = {"int": spmv_model(p, media, prec), "ext64": spmv_model(p, [-1], 0),
-                     "int64": spmv_model(p, media, 0), "local": [p.is_local(m) for m in media],
-                     "E": p.num_rwg}
+        if model is None:
+            model = spmv_classes(p, len(cfg.objects), prec)
         if i == 0 and prec == 1:
-            # FP64 reference of the same request (accuracy of the FP32 path)
-            u32, v32 = p.currents()
-            th = np.linspace(0.0, np.pi, 91)
-            rhat = np.stack([np.sin(th), 0 * th, np.cos(th)], axis=1)
-            F32 = p.far_field(rhat)
-            r64 = p.solve(0, tol=args.tol, **SOLVE_OPTS)
-            u64, v64 = p.currents()
-            F64 = p.far_field(rhat)
-            ref = {"rel_err_u": float(np.linalg.norm(u32 - u64) / np.linalg.norm(u64)),
-                   "rel_err_v": float(np.linalg.norm(v32 - v64) / np.linalg.norm(v64)),
-                   "rel_err_far_field": float(np.abs(F32 - F64).max() / np.abs(F64).max()),
-                   "fp64_solve": r64}
+            ref = fp64_gate(p, args.tol, SOLVE_OPTS)
             print(f"[bench] fp64 reference: {ref}", file=sys.stderr, flush=True)
         del p
     torch.cuda.synchronize()
@@ -521,10 +650,7 @@ def request_workload(args):
             tm[k][0] += st[k][0]
             tm[k][1] += st[k][1]
         if model is None:
-            media = list(range(len(cfg.objects)))
-            model = {"int": spmv_model(p, media, prec), "ext64": spmv_model(p, [-1], 0),
-                     "int64": spmv_model(p, media, 0), "local": [p.is_local(m) for m in media],
-                     "E": p.num_rwg}
+            model = spmv_classes(p, len(cfg.objects), prec)
         del p            # release the request's device memory before the next one
         lat.append(tot); setups.append(su); reps.append(rep)
         matvecs += rep["matvecs"]
@@ -532,22 +658,8 @@ def request_workload(args):
         print(f"[bench] step {i}: setup {su:.2f}s total {tot:.2f}s {rep}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     Tt = time.perf_counter() - t0
-    # dominant kernel: the interior media's near-field product in the path's
-    # precision (one launch per group of media per nested product)
-    kn, kms = tm["spmv_int32"] if prec == 1 else tm["spmv_int64"]
-    nbytes, nnz = model["int"] if prec == 1 else model["int64"]
-    avg_ms = kms / max(kn, 1)
-    achieved = nbytes / (avg_ms * 1e-3) / 1e9 if kn else None
-    # exterior products: all launches minus the interior ones, per precision
-    e64n = tm["spmv64"][0] - tm["spmv_int64"][0]
-    e64ms = tm["spmv64"][1] - tm["spmv_int64"][1]
-    conv = all(r["converged"] for r in reps)
-    names = {"cubes": "8x8 array of lossy dielectric cubes (edge 0.2 lambda0, pitch 0.4 lambda0, eps_r ~ U[2,10], "
-                      "sigma ~ U[0,10] S/m, seed 11682), 196608 triangles (294912 RWG), 1 GHz, exterior grid "
-                      "256^3 (FFT on the live box), one 16^3 grid per cube",
-             "bar": "copper bar 100x10x5 um, sigma 5.8e7 S/m, 20088 triangles (30132 RWG), 10 GHz, 64^3 grid",
-             "sphere": "dielectric sphere r = 1 m, eps_r 4, 1280 triangles (1920 RWG), 150 MHz, 44^3 grid "
-                       "(the lambda_r/20 rule of Sec. IV)"}
+    roof = dominant_kernel({k: tuple(v) for k, v in tm.items()}, model, prec)
+    roof["traffic"] = spmv_traffic(args.workload) if roof["kernel"].endswith("(exterior medium)") else None
     out = {
         "metric": "SIE matvecs/s + served solves/s, p50/p99 latency at rel err <=1e-3 vs FP64",
         "value": matvecs / Tt,
@@ -557,32 +669,27 @@ def request_workload(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "c64+f64" if prec == 1 else "c128",
         "data": "synthetic",
-        "config": {"workload": names[args.workload] + f", near radius {cfg.near_radius}, plane wave -z "
+        "config": {"workload": NAMES[args.workload] + f", near radius {cfg.near_radius}, plane wave -z "
                                f"x-polarised, 1 RHS, GIBC solve to a relative FP64 residual of {args.tol:g}"
                                + (f", skin-depth cutoff {args.skin_cutoff:g}" if args.skin_cutoff else ""),
-                   "precision": args.precision, "nnz_near_interior": int(nnz),
+                   "precision": args.precision, "nnz_near_interior": int(model["interior"][1]),
+                   "nnz_near_exterior": int(model["exterior64"][1]),
                    "interior_media_without_grid_part": int(sum(model["local"]))},
         "k_matvecs_per_s": kmatvecs / Tt,
         "solves_per_s": args.steps / Tt,
         "latency_p50_s": float(np.percentile(lat, 50)),
         "latency_p99_s": float(np.percentile(lat, 99)),
         "setup_s_mean": float(np.mean(setups)),
-        "converged": conv,
+        "converged": all(r["converged"] for r in reps),
         "tol": args.tol,
         "fp32_vs_fp64": ref,
         "residual_fp64_max": max(r["residual"] for r in reps),
         "outer_iters": reps[-1]["outer_iters"], "inner_iters": reps[-1]["inner_iters"],
         "refine_sweeps": reps[-1]["refine_sweeps"],
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS if achieved else None,
-                     "traffic": spmv_traffic(args.workload) if prec == 1 else None,
-                     "kernel": "k_spmv_far<float> (interior media)" if prec == 1 else
-                               "k_spmv_far<double> (interior media)",
-                     "avg_launch_ms": avg_ms, "launches": kn, "bytes_per_launch": nbytes},
-        "spmv_exterior_fp64": {"avg_launch_ms": e64ms / max(e64n, 1), "launches": e64n,
-                               "bytes_per_launch": model["ext64"][0],
-                               "achieved_gbs": model["ext64"][0] / (e64ms / e64n * 1e-3) / 1e9 if e64n else None},
+        "roofline": roof,
     }
+    if args.workload == "bar" and not args.no_cube_array:
+        out["cube_array"] = cube_array_request(args)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle AIM product, bounded sample)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline_aim(cfg)

@@ -25,7 +25,8 @@
  *     stated.  Handles belong to the caller, who destroys them.
  *   - Errors: every call returns an sie_status; on failure nothing is thrown
  *     across the ABI, outputs are left unspecified and sie_last_error() holds a
- *     message (thread-local, valid until the next call on that thread).
+ *     message (thread-local, valid until the next call on that thread);
+ *     sie_ctx_last_error() keeps the last failure of a context.
  *   - Threads: one sie_problem is used by one host thread at a time.  Setup
  *     and solves run on the calling thread's default stream; a NULL stream
  *     passed to a hot-path call means the caller's legacy default stream.
@@ -102,8 +103,11 @@ typedef struct {
                             extended cluster would exceed 2048 functions);
                             only media whose field decays within the near
                             region (five skin depths within R grid spacings)
-                            get it, the others run unpreconditioned.  1 and 4
-                            exclude each other (SIE_EINVAL); 0 none (default) */
+                            get it, the others run unpreconditioned; with 8
+                            as well (12) every interior medium gets it, the
+                            others with clusters of 4^3 cells and two cells
+                            of overlap.  1 and 4 exclude each other, 8 needs 4
+                            (SIE_EINVAL); 0 none (default) */
     double inner_relax;  /* SIE_FP32 only: relaxed nested tolerance inside each
                             FP32 correction solve (inexact Krylov relaxation,
                             Simoncini and Szyld): nested solve j runs to
@@ -135,6 +139,10 @@ typedef struct {
 sie_status sie_ctx_create(int device, sie_ctx **out);
 void sie_ctx_destroy(sie_ctx *ctx);
 const char *sie_last_error(void);
+/* Message of the last failing call made with this context (through a
+ * problem or server created on it); "" if none.  Valid until the next
+ * failing call on the context. */
+const char *sie_ctx_last_error(const sie_ctx *ctx);
 
 /* ---- problem definition (Sec. II: objects with (eps_i, mu_i, sigma_i) in a
  * homogeneous background; Sec. III-A: triangle meshes) ------------------- */
@@ -230,6 +238,13 @@ sie_status sie_get_grid(const sie_problem *p, int32_t medium, double *origin, do
  * medium's grid, in the grid's triangle order (all triangles of the objects the
  * grid covers, ascending).  out: [nt_grid][3]; *nt_grid receives the count. */
 sie_status sie_get_stencils(const sie_problem *p, int32_t medium, int32_t *out, int64_t *nt_grid);
+/* Stencil assignment on the device (Sec. III-D-1, the integer grid index of
+ * each triangle's stencil centre: floor((c - origin) / h + 0.5) of the centroid
+ * c = ((v0 + v1) + v2) / 3, clamped to [1, n - 2]) for every triangle of the
+ * medium's grid, in ascending global triangle order, into centre_dev [nt][3]
+ * int32 (device memory of the caller, nt from sie_get_stencils) on the
+ * caller's stream; recomputes what setup assigned. */
+sie_status sie_stencil_assign(sie_problem *p, int32_t medium, int32_t *centre_dev, void *stream);
 /* Near-field CSR of a medium (RWG rows/cols of the medium's objects, global
  * numbering): row_ptr [E+1] int64, cols [nnz] int32.  With row_ptr == NULL
  * only *nnz is written. */
@@ -328,6 +343,12 @@ sie_status sie_get_currents(const sie_problem *p, int32_t rhs, sie_c128 *u, sie_
  * `rhs` in the directions rhat [ndir][3]: F [ndir][3] (host). */
 sie_status sie_far_field(const sie_problem *p, int32_t rhs, int64_t ndir, const double *rhat,
                          sie_c128 *F);
+/* The same in spherical components (Sec. V-A far field / RCS): directions
+ * (theta[i], phi[i]) in radians, e_theta[i] = F . theta-hat and
+ * e_phi[i] = F . phi-hat (host arrays [ndir]); the RCS of unit incidence is
+ * 4 pi (|e_theta|^2 + |e_phi|^2). */
+sie_status sie_far_field_angles(const sie_problem *p, int32_t rhs, int64_t ndir, const double *theta,
+                                const double *phi, sie_c128 *e_theta, sie_c128 *e_phi);
 
 /* ---- serving: continuous batching of independent solve requests
  *

@@ -1,4 +1,5 @@
 // C ABI (include/sie.h): argument checking, error capture, dispatch.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -33,18 +34,41 @@ static sie_status guard(F &&f) {
     }
 }
 
+// The same, also recording a failure's message on the context.
+template <typename F>
+static sie_status guard(sie_ctx *ctx, F &&f) {
+    const sie_status st = guard(std::forward<F>(f));
+    if (st != SIE_OK && ctx) ctx_set_error(ctx, g_err);
+    return st;
+}
+static sie_ctx *ctx_of(const sie_problem *p) { return p ? p->ctx : nullptr; }
+
 // The library runs its own work (setup, solves) on the calling thread's
 // default stream.  A null stream handed in by a caller means the caller's
 // legacy default stream, so hot-path calls order with the caller's work.
 static hipStream_t user_stream(void *stream) { return stream ? (hipStream_t)stream : hipStreamLegacy; }
 
 // Entry points that run on the thread's own stream first wait for work the
-// caller queued on the legacy default stream.
-static void after_caller_work() { SIE_HIP(hipStreamSynchronize(hipStreamLegacy)); }
+// caller queued on the legacy default stream; server workers have no such
+// caller (and the wait would order them behind every blocking stream).
+static thread_local bool g_worker = false;
+namespace sie {
+void mark_worker_thread() { g_worker = true; }
+}  // namespace sie
+static void after_caller_work() {
+    if (!g_worker) SIE_HIP(hipStreamSynchronize(hipStreamLegacy));
+}
 
 extern "C" {
 
 const char *sie_last_error(void) { return g_err.c_str(); }
+
+const char *sie_ctx_last_error(const sie_ctx *ctx) {
+    if (!ctx) return "";
+    sie_ctx *c = const_cast<sie_ctx *>(ctx);
+    std::lock_guard<std::mutex> lk(c->mu);
+    return c->err.c_str();
+}
 
 sie_status sie_ctx_create(int device, sie_ctx **out) {
     return guard([&] {
@@ -63,7 +87,7 @@ sie_status sie_ctx_create(int device, sie_ctx **out) {
 void sie_ctx_destroy(sie_ctx *ctx) { delete ctx; }
 
 sie_status sie_problem_create(sie_ctx *ctx, double freq_hz, double bg_eps_r, double bg_mu_r, sie_problem **out) {
-    return guard([&] {
+    return guard(ctx, [&] {
         SIE_CHECK(ctx && out, SIE_EINVAL, "NULL argument");
         SIE_CHECK(freq_hz > 0 && std::isfinite(freq_hz), SIE_EINVAL, "frequency must be positive");
         SIE_CHECK(bg_eps_r > 0 && bg_mu_r > 0, SIE_EINVAL, "background must be lossless with positive eps, mu");
@@ -78,7 +102,7 @@ sie_status sie_problem_create(sie_ctx *ctx, double freq_hz, double bg_eps_r, dou
 
 sie_status sie_problem_add_object(sie_problem *p, const double *xyz, int64_t nv, const int32_t *tri, int64_t nt,
                                   double eps_r, double mu_r, double sigma, int32_t *obj_id) {
-    return guard([&] {
+    return guard(ctx_of(p), [&] {
         SIE_CHECK(p && xyz && tri, SIE_EINVAL, "NULL argument");
         SIE_CHECK(!p->is_setup, SIE_ESTATE, "problem already set up");
         SIE_CHECK(nv >= 4 && nt >= 4, SIE_EMESH, "a closed surface needs at least 4 vertices and 4 triangles");
@@ -95,7 +119,7 @@ sie_status sie_problem_add_object(sie_problem *p, const double *xyz, int64_t nv,
 }
 
 sie_status sie_problem_set_grid(sie_problem *p, int32_t medium, int32_t n, int32_t near_radius, int32_t share) {
-    return guard([&] {
+    return guard(ctx_of(p), [&] {
         SIE_CHECK(p, SIE_EINVAL, "NULL problem");
         SIE_CHECK(!p->is_setup, SIE_ESTATE, "problem already set up");
         SIE_CHECK(n == 0 || (n >= 5 && n <= 1024), SIE_EINVAL, "grid points per axis must be 0 or in [5, 1024]");
@@ -117,7 +141,7 @@ sie_status sie_grid_choose(double freq_hz, double eps_r, double mu_r, double sig
 }
 
 sie_status sie_problem_set_grid_params(sie_problem *p, int32_t medium, const sie_grid_params *g, int32_t share) {
-    return guard([&] {
+    return guard(ctx_of(p), [&] {
         SIE_CHECK(p && g, SIE_EINVAL, "NULL argument");
         SIE_CHECK(!p->is_setup, SIE_ESTATE, "problem already set up");
         SIE_CHECK(g->order == 0 || g->order == 2, SIE_EINVAL, "only stencil order 2 (3 points per axis) is built");
@@ -139,7 +163,7 @@ sie_status sie_problem_set_grid_params(sie_problem *p, int32_t medium, const sie
 }
 
 sie_status sie_problem_set_quadrature(sie_problem *p, const sie_quad_params *q) {
-    return guard([&] {
+    return guard(ctx_of(p), [&] {
         SIE_CHECK(p && q, SIE_EINVAL, "NULL argument");
         SIE_CHECK(!p->is_setup, SIE_ESTATE, "problem already set up");
         p->quad = *q;
@@ -147,7 +171,7 @@ sie_status sie_problem_set_quadrature(sie_problem *p, const sie_quad_params *q) 
 }
 
 sie_status sie_problem_set_skin_cutoff(sie_problem *p, double skin_depths) {
-    return guard([&] {
+    return guard(ctx_of(p), [&] {
         SIE_CHECK(p, SIE_EINVAL, "NULL problem");
         SIE_CHECK(!p->is_setup, SIE_ESTATE, "problem already set up");
         SIE_CHECK(skin_depths >= 0.0 && std::isfinite(skin_depths), SIE_EINVAL, "cutoff must be finite and >= 0");
@@ -157,7 +181,7 @@ sie_status sie_problem_set_skin_cutoff(sie_problem *p, double skin_depths) {
 
 int32_t sie_medium_is_local(const sie_problem *p, int32_t medium) {
     int32_t out = SIE_EINVAL;
-    const sie_status st = guard([&] {
+    const sie_status st = guard(ctx_of(p), [&] {
         SIE_CHECK(p && p->is_setup, SIE_ESTATE, "problem not set up");
         out = p->medium(medium).local ? 1 : 0;
     });
@@ -165,7 +189,7 @@ int32_t sie_medium_is_local(const sie_problem *p, int32_t medium) {
 }
 
 sie_status sie_problem_setup(sie_problem *p) {
-    return guard([&] {
+    return guard(ctx_of(p), [&] {
         SIE_CHECK(p, SIE_EINVAL, "NULL problem");
         SIE_CHECK(!p->is_setup, SIE_ESTATE, "problem already set up");
         after_caller_work();
@@ -185,7 +209,7 @@ int64_t sie_problem_num_rwg(const sie_problem *p) { return p && p->is_setup ? p-
 int64_t sie_problem_num_tri(const sie_problem *p) { return p && p->is_setup ? p->mesh.nt() : -1; }
 
 sie_status sie_get_rwg(const sie_problem *p, int32_t *edge_v, int32_t *tpm) {
-    return guard([&] {
+    return guard(ctx_of(p), [&] {
         SIE_CHECK(p && p->is_setup, SIE_ESTATE, "problem not set up");
         if (edge_v) std::memcpy(edge_v, p->mesh.edge_v.data(), p->mesh.edge_v.size() * sizeof(int32_t));
         if (tpm) std::memcpy(tpm, p->mesh.tpm.data(), p->mesh.tpm.size() * sizeof(int32_t));
@@ -194,7 +218,7 @@ sie_status sie_get_rwg(const sie_problem *p, int32_t *edge_v, int32_t *tpm) {
 
 sie_status sie_get_grid(const sie_problem *p, int32_t medium, double *origin, double *h, int32_t *n, int32_t *lo,
                         int32_t *nl, int32_t *m) {
-    return guard([&] {
+    return guard(ctx_of(p), [&] {
         SIE_CHECK(p && p->is_setup, SIE_ESTATE, "problem not set up");
         const Grid &g = *p->medium(medium).grid;
         for (int c = 0; c < 3; ++c) {
@@ -209,7 +233,7 @@ sie_status sie_get_grid(const sie_problem *p, int32_t medium, double *origin, do
 }
 
 sie_status sie_get_stencils(const sie_problem *p, int32_t medium, int32_t *out, int64_t *nt_grid) {
-    return guard([&] {
+    return guard(ctx_of(p), [&] {
         SIE_CHECK(p && p->is_setup, SIE_ESTATE, "problem not set up");
         const Grid &g = *p->medium(medium).grid;
         const int64_t ntg = (int64_t)g.tris.size();
@@ -224,8 +248,21 @@ sie_status sie_get_stencils(const sie_problem *p, int32_t medium, int32_t *out, 
     });
 }
 
+sie_status sie_stencil_assign(sie_problem *p, int32_t medium, int32_t *centre_dev, void *stream) {
+    return guard(ctx_of(p), [&] {
+        SIE_CHECK(p && p->is_setup, SIE_ESTATE, "problem not set up");
+        SIE_CHECK(centre_dev, SIE_EINVAL, "NULL pointer");
+        const Grid &g = *p->medium(medium).grid;
+        // the grid covers whole objects, whose triangles are contiguous
+        const int64_t t0 = *std::min_element(g.tris.begin(), g.tris.end());
+        const int64_t ntg = (int64_t)g.tris.size();
+        launch_stencil_assign(p->d_centroid.p, nullptr, t0, ntg, g.origin, g.h, g.n, centre_dev, nullptr,
+                              user_stream(stream));
+    });
+}
+
 sie_status sie_get_near_pattern(const sie_problem *p, int32_t medium, int64_t *row_ptr, int32_t *cols, int64_t *nnz) {
-    return guard([&] {
+    return guard(ctx_of(p), [&] {
         SIE_CHECK(p && p->is_setup, SIE_ESTATE, "problem not set up");
         const Grid &g = *p->medium(medium).grid;
         if (nnz) *nnz = g.nnz;
@@ -245,7 +282,7 @@ sie_status sie_get_near_pattern(const sie_problem *p, int32_t medium, int64_t *r
 }
 
 sie_status sie_get_near_values(const sie_problem *p, int32_t medium, sie_op op, sie_c128 *out) {
-    return guard([&] {
+    return guard(ctx_of(p), [&] {
         SIE_CHECK(p && p->is_setup, SIE_ESTATE, "problem not set up");
         SIE_CHECK(op == SIE_OP_L || op == SIE_OP_K, SIE_EINVAL, "near values exist for L and K");
         const Medium &md = p->medium(medium);
@@ -256,7 +293,7 @@ sie_status sie_get_near_values(const sie_problem *p, int32_t medium, sie_op op, 
 }
 
 sie_status sie_get_wavenumber(const sie_problem *p, int32_t medium, sie_c128 *k) {
-    return guard([&] {
+    return guard(ctx_of(p), [&] {
         SIE_CHECK(p && p->is_setup && k, SIE_ESTATE, "problem not set up");
         const c128 v = p->medium(medium).k;
         k->re = v.re; k->im = v.im;
@@ -265,7 +302,7 @@ sie_status sie_get_wavenumber(const sie_problem *p, int32_t medium, sie_c128 *k)
 
 sie_status sie_matvec(sie_problem *p, int32_t medium, sie_op op, sie_precision prec, int32_t nrhs, const void *x_dev,
                       void *y_dev, void *stream) {
-    return guard([&] {
+    return guard(ctx_of(p), [&] {
         SIE_CHECK(p && p->is_setup, SIE_ESTATE, "problem not set up");
         SIE_CHECK(x_dev && y_dev && nrhs >= 1, SIE_EINVAL, "bad vectors");
         SIE_CHECK(x_dev != y_dev, SIE_EINVAL, "x and y must not alias");
@@ -293,7 +330,7 @@ sie_status sie_matvec(sie_problem *p, int32_t medium, sie_op op, sie_precision p
 
 sie_status sie_matvec_noalloc(sie_problem *p, int32_t medium, sie_op op, sie_precision prec, const void *x_dev,
                               void *y_dev, void *stream) {
-    return guard([&] {
+    return guard(ctx_of(p), [&] {
         SIE_CHECK(p && p->is_setup, SIE_ESTATE, "problem not set up");
         SIE_CHECK(x_dev && y_dev, SIE_EINVAL, "bad vectors");
         SIE_CHECK(x_dev != y_dev, SIE_EINVAL, "x and y must not alias");
@@ -306,7 +343,7 @@ sie_status sie_matvec_noalloc(sie_problem *p, int32_t medium, sie_op op, sie_pre
 
 sie_status sie_nested_precond(sie_problem *p, int32_t precond, sie_precision prec, int32_t nrhs, const void *x_dev,
                               void *y_dev, void *stream) {
-    return guard([&] {
+    return guard(ctx_of(p), [&] {
         SIE_CHECK(p, SIE_EINVAL, "NULL problem");
         nested_precond_entry(p, precond, prec, nrhs, x_dev, y_dev, user_stream(stream));
     });
@@ -319,7 +356,7 @@ int32_t sie_nested_precond_clusters(const sie_problem *p, int64_t *owned) {
 
 sie_status sie_project(sie_problem *p, int32_t medium, sie_precision prec, const void *x_dev, void *grid_dev,
                        void *stream) {
-    return guard([&] {
+    return guard(ctx_of(p), [&] {
         SIE_CHECK(p && p->is_setup, SIE_ESTATE, "problem not set up");
         SIE_CHECK(x_dev && grid_dev, SIE_EINVAL, "NULL pointer");
         Medium &md = p->medium(medium);
@@ -330,7 +367,7 @@ sie_status sie_project(sie_problem *p, int32_t medium, sie_precision prec, const
 
 sie_status sie_convolve(sie_problem *p, int32_t medium, sie_op op, sie_precision prec, int32_t nfields,
                         const void *in_dev, void *out_dev, void *stream) {
-    return guard([&] {
+    return guard(ctx_of(p), [&] {
         SIE_CHECK(p && p->is_setup, SIE_ESTATE, "problem not set up");
         SIE_CHECK(in_dev && out_dev, SIE_EINVAL, "NULL pointer");
         SIE_CHECK(op == SIE_OP_L || op == SIE_OP_K, SIE_EINVAL, "convolution op must be L (G) or K (grad G x)");
@@ -344,7 +381,7 @@ sie_status sie_convolve(sie_problem *p, int32_t medium, sie_op op, sie_precision
 
 sie_status sie_interpolate(sie_problem *p, int32_t medium, sie_precision prec, const void *grid_dev, void *y_dev,
                            void *stream) {
-    return guard([&] {
+    return guard(ctx_of(p), [&] {
         SIE_CHECK(p && p->is_setup, SIE_ESTATE, "problem not set up");
         SIE_CHECK(grid_dev && y_dev, SIE_EINVAL, "NULL pointer");
         Medium &md = p->medium(medium);
@@ -356,7 +393,7 @@ sie_status sie_interpolate(sie_problem *p, int32_t medium, sie_precision prec, c
 }
 
 sie_status sie_set_timing(sie_problem *p, int32_t on) {
-    return guard([&] {
+    return guard(ctx_of(p), [&] {
         SIE_CHECK(p, SIE_EINVAL, "NULL problem");
         SIE_CHECK(on >= 0 && on <= 2, SIE_EINVAL, "timing mode must be 0, 1 or 2");
         p->timer.reset();
@@ -365,7 +402,7 @@ sie_status sie_set_timing(sie_problem *p, int32_t on) {
 }
 
 sie_status sie_get_stage_time(sie_problem *p, int32_t stage, int64_t *launches, double *total_ms) {
-    return guard([&] {
+    return guard(ctx_of(p), [&] {
         SIE_CHECK(p, SIE_EINVAL, "NULL problem");
         SIE_CHECK(stage >= 0 && stage < NSTAGE, SIE_EINVAL, "stage out of range");
         p->timer.flush();
@@ -375,25 +412,51 @@ sie_status sie_get_stage_time(sie_problem *p, int32_t stage, int64_t *launches, 
 }
 
 sie_status sie_set_planewaves(sie_problem *p, int32_t nrhs, const double *khat, const sie_c128 *e0) {
-    return guard([&] {
+    return guard(ctx_of(p), [&] {
         after_caller_work();
         planewaves_entry(p, nrhs, khat, e0);
     });
 }
 
 sie_status sie_solve(sie_problem *p, sie_precision prec, const sie_solver_opts *opts, sie_report *report) {
-    return guard([&] {
+    return guard(ctx_of(p), [&] {
         after_caller_work();
         solve_entry(p, prec, opts, report);
     });
 }
 
 sie_status sie_get_currents(const sie_problem *p, int32_t rhs, sie_c128 *u, sie_c128 *v) {
-    return guard([&] { currents_entry(p, rhs, u, v); });
+    return guard(ctx_of(p), [&] { currents_entry(p, rhs, u, v); });
 }
 
 sie_status sie_far_field(const sie_problem *p, int32_t rhs, int64_t ndir, const double *rhat, sie_c128 *F) {
-    return guard([&] { farfield_entry(p, rhs, ndir, rhat, F); });
+    return guard(ctx_of(p), [&] { farfield_entry(p, rhs, ndir, rhat, F); });
+}
+
+sie_status sie_far_field_angles(const sie_problem *p, int32_t rhs, int64_t ndir, const double *theta,
+                                const double *phi, sie_c128 *e_theta, sie_c128 *e_phi) {
+    return guard(ctx_of(p), [&] {
+        SIE_CHECK(ndir >= 0 && (ndir == 0 || (theta && phi && e_theta && e_phi)), SIE_EINVAL, "bad directions");
+        if (ndir == 0) return;
+        std::vector<double> rhat(3 * ndir);
+        std::vector<sie_c128> F(3 * ndir);
+        for (int64_t i = 0; i < ndir; ++i) {
+            const double st = std::sin(theta[i]), ct = std::cos(theta[i]), sp = std::sin(phi[i]), cp = std::cos(phi[i]);
+            rhat[3 * i] = st * cp; rhat[3 * i + 1] = st * sp; rhat[3 * i + 2] = ct;
+        }
+        farfield_entry(p, rhs, ndir, rhat.data(), F.data());
+        for (int64_t i = 0; i < ndir; ++i) {
+            const double st = std::sin(theta[i]), ct = std::cos(theta[i]), sp = std::sin(phi[i]), cp = std::cos(phi[i]);
+            const double th[3] = {ct * cp, ct * sp, -st}, ph[3] = {-sp, cp, 0.0};
+            sie_c128 a{0, 0}, b{0, 0};
+            for (int c = 0; c < 3; ++c) {
+                a.re += th[c] * F[3 * i + c].re; a.im += th[c] * F[3 * i + c].im;
+                b.re += ph[c] * F[3 * i + c].re; b.im += ph[c] * F[3 * i + c].im;
+            }
+            e_theta[i] = a;
+            e_phi[i] = b;
+        }
+    });
 }
 
 }  // extern "C"

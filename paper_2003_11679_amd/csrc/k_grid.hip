@@ -15,12 +15,14 @@
 
 namespace sie {
 
+// Triangle i of the launch is tris[i], or t0 + i without a list; raw
+// (nullable) receives the unclamped index.
 __global__ void k_stencil_assign(const double *__restrict__ centroids, const int32_t *__restrict__ tris,
-                                 int64_t ntg, double ox, double oy, double oz, double h, int nx, int ny,
+                                 int64_t t0, int64_t ntg, double ox, double oy, double oz, double h, int nx, int ny,
                                  int nz, int32_t *__restrict__ centre, int32_t *__restrict__ raw) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= ntg) return;
-    const int64_t t = tris[i];
+    const int64_t t = tris ? tris[i] : t0 + i;
     const double o[3] = {ox, oy, oz};
     const int n[3] = {nx, ny, nz};
     for (int c = 0; c < 3; ++c) {
@@ -28,16 +30,17 @@ __global__ void k_stencil_assign(const double *__restrict__ centroids, const int
         double q = (centroids[3 * t + c] - o[c]) / h;
         double f = floor(q + 0.5);
         int v = (int)f;
-        raw[3 * i + c] = v;
+        if (raw) raw[3 * i + c] = v;
         centre[3 * i + c] = v < 1 ? 1 : (v > n[c] - 2 ? n[c] - 2 : v);
     }
 }
 
-void launch_stencil_assign(const double *centroids, const int32_t *tris, int64_t ntg, const double origin[3],
-                           double h, const int n[3], int32_t *centre_out, int32_t *raw_out, hipStream_t st) {
+void launch_stencil_assign(const double *centroids, const int32_t *tris, int64_t t0, int64_t ntg,
+                           const double origin[3], double h, const int n[3], int32_t *centre_out, int32_t *raw_out,
+                           hipStream_t st) {
     if (ntg == 0) return;
     hipLaunchKernelGGL(k_stencil_assign, dim3((unsigned)((ntg + 255) / 256)), dim3(256), 0, st, centroids, tris,
-                       ntg, origin[0], origin[1], origin[2], h, n[0], n[1], n[2], centre_out, raw_out);
+                       t0, ntg, origin[0], origin[1], origin[2], h, n[0], n[1], n[2], centre_out, raw_out);
     SIE_HIP(hipGetLastError());
 }
 
@@ -268,7 +271,9 @@ void launch_cols16(int64_t nrow, const int64_t *row_ptr, const int32_t *cols, in
 // Rows rwg0 + r, r < nrow (the rows of the view; others are not touched).
 // The far part's scalar weight kscal (-2 k^-2 for L, none for K) and the
 // optional factor alpha on the row's result are taken per slot, the slot
-// being that of the row's triangles.
+// being that of the row's triangles.  Lanes 0 and 1 load the far-part
+// operands of the row's two triangles before the near-field loop, so that
+// those loads overlap it, and their contributions join the lane sum.
 template <typename T, bool C16>
 __global__ void k_spmv_far(int64_t nrow, int64_t rwg0, const int64_t *__restrict__ row_ptr,
                            const int32_t *__restrict__ cols, const uint16_t *__restrict__ cols16,
@@ -282,6 +287,22 @@ __global__ void k_spmv_far(int64_t nrow, int64_t rwg0, const int64_t *__restrict
     if (r >= nrow) return;
     const int64_t row = rwg0 + r;
     cx<T> acc;
+    cx<T> al(T(1));
+    if (lane < 2 && (use_far || alpha)) {
+        const int32_t lc = rwg_loc[2 * r + lane];
+        const int64_t t = lc >> 2;
+        const int slot = tri_slot ? tri_slot[t] : 0;
+        if (use_far) {
+            const int ed = lc & 3;
+            const T *c = coef + (t * 3 + ed) * 4;
+            const cx<T> *p = tripot + 5 * t;
+            const cx<T> ks = kscal ? kscal[slot] : cx<T>();
+            cx<T> v = p[0] - (c[1] * p[1] + c[2] * p[2] + c[3] * p[3]);
+            v += ks * p[4];
+            acc = c[0] * v;
+        }
+        if (alpha) al = alpha[slot];
+    }
     if (vals) {
         const int64_t b = row_ptr[r], e = row_ptr[r + 1];
         // four independent gathers in flight per lane; values and column
@@ -311,26 +332,9 @@ __global__ void k_spmv_far(int64_t nrow, int64_t rwg0, const int64_t *__restrict
         }
         for (; j < e; j += 64) acc += vals[j] * x[col(j)];
         acc += (a1 + a2) + a3;
-        acc = wave_sum(acc);
     }
-    if (lane == 0) {
-        const int slot = tri_slot ? tri_slot[rwg_loc[2 * r] >> 2] : 0;
-        if (use_far) {
-            const cx<T> ks = kscal ? kscal[slot] : cx<T>();
-            for (int s = 0; s < 2; ++s) {
-                const int32_t lc = rwg_loc[2 * r + s];
-                const int64_t t = lc >> 2;
-                const int ed = lc & 3;
-                const T *c = coef + (t * 3 + ed) * 4;
-                const cx<T> *p = tripot + 5 * t;
-                cx<T> v = p[0] - (c[1] * p[1] + c[2] * p[2] + c[3] * p[3]);
-                v += ks * p[4];
-                acc += c[0] * v;
-            }
-        }
-        if (alpha) acc = alpha[slot] * acc;
-        y[row] = acc;
-    }
+    acc = wave_sum(acc);
+    if (lane == 0) y[row] = alpha ? al * acc : acc;
 }
 
 template <typename T>
@@ -400,7 +404,28 @@ __global__ void __launch_bounds__(64) k_spmm_far(int64_t E, int64_t rwg0, int nr
     const int slot = threadIdx.x / RPW, q = threadIdx.x % RPW;
     const int r = blockIdx.y * RPW + q;
     const bool act = r < nrhs;
+    // the far part of right-hand side r and the row's factor, loaded by the
+    // lanes of group 0 before the near loop (their sums join the reduction)
     cx<T> acc;
+    cx<T> al(T(1));
+    if (act && slot == 0) {
+        const int sl = tri_slot ? tri_slot[rwg_loc[2 * rr] >> 2] : 0;
+        if (tripot) {
+            const cx<T> ks = kscal ? kscal[sl] : cx<T>();
+            const cx<T> *tp = tripot + (int64_t)r * 5 * ntg;
+            for (int s2 = 0; s2 < 2; ++s2) {
+                const int32_t lc = rwg_loc[2 * rr + s2];
+                const int64_t t = lc >> 2;
+                const int ed = lc & 3;
+                const T *c = coef + (t * 3 + ed) * 4;
+                const cx<T> *qq = tp + 5 * t;
+                cx<T> v = qq[0] - (c[1] * qq[1] + c[2] * qq[2] + c[3] * qq[3]);
+                v += ks * qq[4];
+                acc += c[0] * v;
+            }
+        }
+        if (alpha) al = alpha[sl];
+    }
     if (vals) {
         const int64_t b = row_ptr[rr], e = row_ptr[rr + 1];
         const cx<T> *xr = xt + (act ? r : 0);
@@ -427,23 +452,7 @@ __global__ void __launch_bounds__(64) k_spmm_far(int64_t E, int64_t rwg0, int nr
         }
     }
     if (!act || slot != 0) return;
-    const int sl = tri_slot ? tri_slot[rwg_loc[2 * rr] >> 2] : 0;
-    if (tripot) {
-        const cx<T> ks = kscal ? kscal[sl] : cx<T>();
-        const cx<T> *tp = tripot + (int64_t)r * 5 * ntg;
-        for (int s2 = 0; s2 < 2; ++s2) {
-            const int32_t lc = rwg_loc[2 * rr + s2];
-            const int64_t t = lc >> 2;
-            const int ed = lc & 3;
-            const T *c = coef + (t * 3 + ed) * 4;
-            const cx<T> *qq = tp + 5 * t;
-            cx<T> v = qq[0] - (c[1] * qq[1] + c[2] * qq[2] + c[3] * qq[3]);
-            v += ks * qq[4];
-            acc += c[0] * v;
-        }
-    }
-    if (alpha) acc = alpha[sl] * acc;
-    y[r * E + row] = acc;
+    y[r * E + row] = alpha ? al * acc : acc;
 }
 
 // xt: scratch of E * nrhs values; x, y: [nrhs][E]; rows of the view only.

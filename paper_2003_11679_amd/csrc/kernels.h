@@ -16,8 +16,9 @@ void fft_convolve(const GridView &g, const cx<T> *spec, int64_t spec_stride, int
 void fft3d_full_fwd(c128 *vol, c128 *tmp, int mx, int my, int mz, hipStream_t st);
 
 // ---- k_grid.hip
-void launch_stencil_assign(const double *centroids, const int32_t *tris, int64_t ntg, const double origin[3],
-                           double h, const int n[3], int32_t *centre_out, int32_t *raw_out, hipStream_t st);
+void launch_stencil_assign(const double *centroids, const int32_t *tris, int64_t t0, int64_t ntg,
+                           const double origin[3], double h, const int n[3], int32_t *centre_out, int32_t *raw_out,
+                           hipStream_t st);
 void launch_moments(const double *xyz, const int32_t *tri, const int32_t *tris, const int32_t *centre,
                     int64_t ntg, const double origin[3], double h, const double *rule, int nq,
                     double *mom64, float *mom32, hipStream_t st);

@@ -138,7 +138,7 @@ static void build_grid(sie_problem *p, Grid &g) {
     {
         DBuf<int32_t> d_t(ntg), d_c(3 * ntg), d_raw(3 * ntg);
         d_t.upload(g.tris);
-        launch_stencil_assign(p->d_centroid.p, d_t.p, ntg, g.origin, g.h, g.n, d_c.p, d_raw.p, 0);
+        launch_stencil_assign(p->d_centroid.p, d_t.p, 0, ntg, g.origin, g.h, g.n, d_c.p, d_raw.p, 0);
         std::vector<int32_t> c = d_c.download(), raw = d_raw.download();
         for (int64_t i = 0; i < 3 * ntg; ++i)
             SIE_CHECK(raw[i] >= 0 && raw[i] <= g.n[i % 3] - 1, SIE_EGRID, "triangle outside its grid");

@@ -3,9 +3,17 @@
 #include "common.h"
 #include "kernels.h"
 
+#include <mutex>
+
 struct sie_ctx {
     int device = 0;
+    std::mutex mu;
+    std::string err;   // message of the last failing call on this context
 };
+inline void ctx_set_error(sie_ctx *c, const std::string &m) {
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->err = m;
+}
 
 namespace sie {
 
@@ -126,6 +134,8 @@ void stage_convolve(sie_problem *p, Medium &md, sie_op op, int nf, const cx<T> *
 template <typename T>
 void stage_interpolate(sie_problem *p, Medium &md, const cx<T> *grid, cx<T> *y, hipStream_t st);
 void solver_destroy(SolveState *s);
+// abi.cpp: the calling thread is a server worker (no caller work to wait for)
+void mark_worker_thread();
 // server.cpp: device bytes of a problem, estimated from its description
 size_t estimate_footprint(const sie_problem *p, int restart, int inner_max_iter);
 // noalloc.hip: device address of the allocation-free product's scratch on

@@ -103,6 +103,7 @@ struct sie_server {
 
     void work() {
         (void)hipSetDevice(ctx->device);
+        mark_worker_thread();
         while (true) {
             Job *j = nullptr;
             {
@@ -150,27 +151,29 @@ struct sie_server {
 };
 
 template <typename F>
-static sie_status sguard(F &&f) {
+static sie_status sguard(sie_ctx *ctx, F &&f) {
+    std::string msg;
+    sie_status st = SIE_OK;
     try {
         set_last_error("");
         f();
         return SIE_OK;
     } catch (const Error &e) {
-        set_last_error(e.what());
-        return e.code;
+        msg = e.what(); st = e.code;
     } catch (const std::bad_alloc &) {
-        set_last_error("host allocation failed");
-        return SIE_ENOMEM;
+        msg = "host allocation failed"; st = SIE_ENOMEM;
     } catch (const std::exception &e) {
-        set_last_error(e.what());
-        return SIE_EINVAL;
+        msg = e.what(); st = SIE_EINVAL;
     }
+    set_last_error(msg);
+    if (ctx) ctx_set_error(ctx, msg);
+    return st;
 }
 
 extern "C" {
 
 sie_status sie_problem_footprint(const sie_problem *p, size_t *device_bytes) {
-    return sguard([&] {
+    return sguard(p ? p->ctx : nullptr, [&] {
         SIE_CHECK(p && device_bytes, SIE_EINVAL, "NULL argument");
         SIE_CHECK(!p->objs.empty(), SIE_ESTATE, "no objects");
         *device_bytes = estimate_footprint(p, 100, 800);
@@ -178,7 +181,7 @@ sie_status sie_problem_footprint(const sie_problem *p, size_t *device_bytes) {
 }
 
 sie_status sie_server_create(sie_ctx *ctx, size_t hbm_budget_bytes, int32_t max_slots, sie_server **out) {
-    return sguard([&] {
+    return sguard(ctx, [&] {
         SIE_CHECK(ctx && out, SIE_EINVAL, "NULL argument");
         SIE_CHECK(max_slots >= 1 && max_slots <= 64, SIE_EINVAL, "max_slots must be 1..64");
         SIE_HIP(hipSetDevice(ctx->device));
@@ -199,7 +202,7 @@ sie_status sie_server_create(sie_ctx *ctx, size_t hbm_budget_bytes, int32_t max_
 
 sie_status sie_server_submit(sie_server *s, sie_problem *p, int32_t nrhs, const double *khat, const sie_c128 *e0,
                              sie_precision prec, const sie_solver_opts *opts, uint64_t *ticket) {
-    return sguard([&] {
+    return sguard(s ? s->ctx : nullptr, [&] {
         SIE_CHECK(s && p && khat && e0 && ticket, SIE_EINVAL, "NULL argument");
         SIE_CHECK(nrhs >= 1, SIE_EINVAL, "need at least one plane wave");
         SIE_CHECK(prec == SIE_FP64 || prec == SIE_FP32, SIE_EINVAL, "unknown precision");
@@ -227,7 +230,7 @@ sie_status sie_server_submit(sie_server *s, sie_problem *p, int32_t nrhs, const 
 }
 
 sie_status sie_server_poll(sie_server *s, uint64_t ticket, sie_job_info *info) {
-    return sguard([&] {
+    return sguard(s ? s->ctx : nullptr, [&] {
         SIE_CHECK(s && info, SIE_EINVAL, "NULL argument");
         std::lock_guard<std::mutex> lk(s->mu);
         auto it = s->jobs.find(ticket);
@@ -237,7 +240,7 @@ sie_status sie_server_poll(sie_server *s, uint64_t ticket, sie_job_info *info) {
 }
 
 sie_status sie_server_take(sie_server *s, uint64_t ticket, sie_problem **out) {
-    return sguard([&] {
+    return sguard(s ? s->ctx : nullptr, [&] {
         SIE_CHECK(s && out, SIE_EINVAL, "NULL argument");
         std::unique_lock<std::mutex> lk(s->mu);
         auto it = s->jobs.find(ticket);

@@ -500,8 +500,14 @@ static bool cluster_medium(sie_problem *p, const Medium &md, int64_t r0, int64_t
     return true;
 }
 
+// all_media: also the media whose field does not decay within the near
+// region (dielectrics, weak conductors), with clusters of 4^3 cells and two
+// cells of overlap (or smaller where an extended cluster would be too large);
+// there the near-region operator still carries the strong (hypersingular)
+// part of the interior EFIE that makes the nested solve slow.
 static void schwarz_build(sie_problem *p, Schwarz &sw, const std::vector<Medium *> &media,
-                          const std::vector<std::pair<int64_t, int64_t>> &ranges, const std::vector<c128> &scales) {
+                          const std::vector<std::pair<int64_t, int64_t>> &ranges, const std::vector<c128> &scales,
+                          bool all_media) {
     ClusterLists L;
     std::vector<int> first, used;
     int64_t total = 0;
@@ -509,12 +515,13 @@ static void schwarz_build(sie_problem *p, Schwarz &sw, const std::vector<Medium 
         total += ranges[i].second - ranges[i].first;
         first.push_back((int)L.own_off.size() - 1);
         used.push_back(0);
-        if (!near_region_dominates(*media[i])) continue;
+        const bool dominated = near_region_dominates(*media[i]);
+        if (!dominated && !all_media) continue;
         const int64_t r0 = ranges[i].first, r1 = ranges[i].second;
         double l = 0.0;
         for (int64_t r = r0; r < r1; ++r) l += p->mesh.len[r];
         l /= (double)std::max<int64_t>(r1 - r0, 1);
-        const int O0 = std::max(1, (int)std::lround(3.0 * l / media[i]->grid->h));
+        const int O0 = dominated ? std::max(1, (int)std::lround(3.0 * l / media[i]->grid->h)) : 2;
         for (int O = O0; O >= 1 && !used.back(); --O)
             for (int C = 2 * O; C >= 1 && !used.back(); --C)
                 if (cluster_medium(p, *media[i], r0, r1, C, O, L)) used.back() = 1;
@@ -813,7 +820,7 @@ static void build_preconditioners(sie_problem *p, SolveState &s, int precond) {
     }
     if ((precond & 4) && !s.sin_built) {
         const auto t0 = std::chrono::steady_clock::now();
-        schwarz_build(p, s.sin, mi, ri, si);
+        schwarz_build(p, s.sin, mi, ri, si, (precond & 8) != 0);
         s.sin_built = true;
         if (std::getenv("SIE_TRACE"))
             std::fprintf(stderr, "[setup] %-28s %8.1f ms\n", "Schwarz clusters",
@@ -953,7 +960,7 @@ template <typename T>
 static void nested_precond_apply(sie_problem *p, SolveState &s, int precond, int nrhs, const cx<T> *x, cx<T> *y,
                                  hipStream_t st) {
     const int64_t E = p->mesh.nrwg;
-    if (precond == 4) {
+    if (precond & 4) {
         const Schwarz &w = s.sin;
         if (!w.covers_all)
             SIE_HIP(hipMemcpyAsync(y, x, (size_t)nrhs * E * sizeof(cx<T>), hipMemcpyDeviceToDevice, st));
@@ -968,8 +975,8 @@ static void nested_precond_apply(sie_problem *p, SolveState &s, int precond, int
 void nested_precond_entry(sie_problem *p, int precond, sie_precision prec, int nrhs, const void *x, void *y,
                           hipStream_t st) {
     SIE_CHECK(p && p->is_setup, SIE_ESTATE, "problem not set up");
-    SIE_CHECK(precond == 1 || precond == 4, SIE_EINVAL,
-              "nested preconditioner must be 1 (block-Jacobi) or 4 (Schwarz clusters)");
+    SIE_CHECK(precond == 1 || precond == 4 || precond == 12, SIE_EINVAL,
+              "nested preconditioner must be 1 (block-Jacobi), 4 or 12 (Schwarz clusters)");
     SIE_CHECK(x && y && nrhs >= 1, SIE_EINVAL, "bad vectors");
     SIE_CHECK(x != y, SIE_EINVAL, "x and y must not alias");
     SIE_CHECK(prec == SIE_FP64 || prec == SIE_FP32, SIE_EINVAL, "unknown precision");
@@ -1040,7 +1047,8 @@ void solve_entry(sie_problem *p, sie_precision prec, const sie_solver_opts *opts
         SIE_CHECK(opts->inner_relax >= 0.0, SIE_EINVAL, "inner_relax must be non-negative");
         o.inner_relax = opts->inner_relax;
     }
-    SIE_CHECK(o.precond >= 0 && o.precond <= 7, SIE_EINVAL, "unknown preconditioner");
+    SIE_CHECK(o.precond >= 0 && o.precond <= 15, SIE_EINVAL, "unknown preconditioner");
+    SIE_CHECK(!(o.precond & 8) || (o.precond & 4), SIE_EINVAL, "preconditioner bit 8 extends bit 4");
     SIE_CHECK((o.precond & 5) != 5, SIE_EINVAL, "nested block-Jacobi (1) and nested Schwarz clusters (4) exclude each other");
     SIE_CHECK(o.restart <= 1000, SIE_EINVAL, "restart above 1000");
     solve_all(p, prec, o, rep);

@@ -108,6 +108,9 @@ SIGNATURES = [
     ("sie_get_rwg", ctypes.c_int, [_VP, _I32P, _I32P]),
     ("sie_get_grid", ctypes.c_int, [_VP, ctypes.c_int32, _DP, _DP, _I32P, _I32P, _I32P, _I32P]),
     ("sie_get_stencils", ctypes.c_int, [_VP, ctypes.c_int32, _I32P, _I64P]),
+    ("sie_ctx_last_error", ctypes.c_char_p, [_VP]),
+    ("sie_stencil_assign", ctypes.c_int, [_VP, ctypes.c_int32, _VP, _VP]),
+    ("sie_far_field_angles", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int64, _DP, _DP, _CP, _CP]),
     ("sie_get_near_pattern", ctypes.c_int, [_VP, ctypes.c_int32, _I64P, _I32P, _I64P]),
     ("sie_get_near_values", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int, _CP]),
     ("sie_get_wavenumber", ctypes.c_int, [_VP, ctypes.c_int32, _CP]),
@@ -237,6 +240,12 @@ class Problem:
     def setup(self):
         _check(lib().sie_problem_setup(self.h))
 
+    def footprint(self):
+        """Device-memory estimate (bytes) the server admits the problem with."""
+        b = ctypes.c_size_t()
+        _check(lib().sie_problem_footprint(self.h, ctypes.byref(b)))
+        return b.value
+
     def is_local(self, medium):
         """True if the medium runs without grid part (skin-depth cutoff within
         the near region, or every pair near)."""
@@ -274,6 +283,18 @@ class Problem:
         out = np.empty((cnt.value, 3), np.int32)
         _check(lib().sie_get_stencils(self.h, medium, _ptr(out, ctypes.c_int32), ctypes.byref(cnt)))
         return out
+
+    def stencil_assign(self, medium=EXTERIOR, stream=None):
+        """Stencil centres recomputed on the device: int32 tensor [nt][3]."""
+        import torch
+        nt = len(self.stencils(medium))
+        out = torch.empty((nt, 3), dtype=torch.int32, device="cuda")
+        _check(lib().sie_stencil_assign(self.h, medium, _VP(out.data_ptr()), _stream(stream)))
+        return out
+
+    def last_error(self):
+        """Message of the last failing call on this problem's context."""
+        return lib().sie_ctx_last_error(self.ctx.h).decode()
 
     def near_pattern(self, medium=EXTERIOR):
         nnz = ctypes.c_int64()
@@ -413,6 +434,17 @@ class Problem:
         u = np.empty((E, 2)); v = np.empty((E, 2))
         _check(lib().sie_get_currents(self.h, rhs, u.ctypes.data_as(_CP), v.ctypes.data_as(_CP)))
         return u[:, 0] + 1j * u[:, 1], v[:, 0] + 1j * v[:, 1]
+
+    def far_field_angles(self, theta, phi, rhs=0):
+        """(E_theta, E_phi) far-field amplitudes at the directions (theta, phi)."""
+        th = np.ascontiguousarray(np.atleast_1d(theta), dtype=np.float64)
+        ph = np.ascontiguousarray(np.atleast_1d(phi), dtype=np.float64)
+        if th.shape != ph.shape:
+            raise ValueError("theta and phi must have one shape")
+        a = np.empty((len(th), 2)); b = np.empty((len(th), 2))
+        _check(lib().sie_far_field_angles(self.h, rhs, len(th), _ptr(th, ctypes.c_double),
+                                          _ptr(ph, ctypes.c_double), a.ctypes.data_as(_CP), b.ctypes.data_as(_CP)))
+        return a[:, 0] + 1j * a[:, 1], b[:, 0] + 1j * b[:, 1]
 
     def far_field(self, rhat, rhs=0):
         rhat = np.ascontiguousarray(np.atleast_2d(rhat), dtype=np.float64)

@@ -91,3 +91,39 @@ def test_server_errors():
     with pytest.raises(SieError):
         srv.poll(12345)
     srv.close()
+
+
+def test_binding_memory_budget_serialises_and_is_never_exceeded():
+    """A budget that holds one request's footprint estimate (plus a margin
+    below a second one) admits one request at a time although four slots
+    are free; the admitted footprints never sum above the budget."""
+    from paper_2003_11679_amd import Server, FP32
+    probe = _problem("sphere2")
+    fp = probe.footprint()
+    budget = int(1.5 * fp)
+    srv = Server(hbm_budget_bytes=budget, max_slots=4)
+    ts = [srv.submit(_problem(nm, ctx=srv.ctx), KHAT, E0, FP32, tol=1e-6)
+          for nm in ("sphere2",) * 4]
+    import time
+    done = []
+    for t in ts:
+        while True:
+            i = srv.poll(t)
+            if i["done"]:
+                break
+            time.sleep(0.01)
+        done.append(i)
+        srv.take(t)
+    srv.close()
+    assert all(i["status"] == 0 for i in done), done
+    ev = sorted([(i["t_start_s"], i["footprint"]) for i in done] + [(i["t_end_s"], -i["footprint"]) for i in done])
+    use = peak = 0
+    live = peak_live = 0
+    for _, f in ev:
+        use += f
+        live += 1 if f > 0 else -1
+        peak = max(peak, use)
+        peak_live = max(peak_live, live)
+    assert all(i["footprint"] <= budget for i in done)
+    assert peak <= budget, (peak, budget)
+    assert peak_live == 1, peak_live

@@ -8,13 +8,14 @@ from here, so that the two sides see identical meshes and vectors while sharing
 no computation.
 """
 from .meshes import (icosphere, geodesic_sphere, box_mesh, cube_array, ellipsoid,
-                     mesh_stats)
+                     mesh_stats, voxel_mesh, split_ring)
 from .configs import (Problem, ObjectSpec, PlaneWave, sphere_cfg, bar_cfg, bar_small_cfg,
                       cube_array_cfg, batching_meshes, serving_trace, random_vector,
                       C0_NOMINAL)
 
 __all__ = [
-    "icosphere", "geodesic_sphere", "box_mesh", "cube_array", "ellipsoid", "mesh_stats",
+    "icosphere", "geodesic_sphere", "box_mesh", "cube_array", "ellipsoid", "mesh_stats", "voxel_mesh",
+    "split_ring",
     "Problem", "ObjectSpec", "PlaneWave", "sphere_cfg", "bar_cfg", "bar_small_cfg",
     "cube_array_cfg", "batching_meshes", "serving_trace", "random_vector", "C0_NOMINAL",
 ]

@@ -142,6 +142,66 @@ def cube_array(nx, ny, edge, pitch, cells, z=0.0):
     return out
 
 
+def voxel_mesh(mask, cell, center=(0.0, 0.0, 0.0)):
+    """Closed surface of a set of boxes: ``mask`` [nx, ny, nz] bool, cubic or
+    rectangular cells of size ``cell`` = (dx, dy, dz); every face between a
+    filled cell and an empty one becomes two triangles, outward oriented.
+    The filled cells must form a solid whose cells touch through faces only
+    (no two cells sharing just an edge or a corner)."""
+    m = np.asarray(mask, dtype=bool)
+    d = np.asarray(cell, dtype=np.float64)
+    pad = np.zeros(tuple(n + 2 for n in m.shape), dtype=bool)
+    pad[1:-1, 1:-1, 1:-1] = m
+    keys, pts, tris = {}, [], []
+
+    def vid(ijk):
+        if ijk not in keys:
+            keys[ijk] = len(pts)
+            pts.append([ijk[a] * d[a] for a in range(3)])
+        return keys[ijk]
+
+    for ax in range(3):
+        u, v = (ax + 1) % 3, (ax + 2) % 3          # (u, v, ax) right-handed
+        for idx in np.argwhere(m):
+            for sgn in (-1, 1):
+                nb = idx + 1
+                nb[ax] += sgn
+                if pad[tuple(nb)]:
+                    continue
+                face = idx[ax] + (1 if sgn > 0 else 0)
+
+                def node(di, dj):
+                    ijk = [0, 0, 0]
+                    ijk[ax] = face
+                    ijk[u] = idx[u] + di
+                    ijk[v] = idx[v] + dj
+                    return vid(tuple(int(q) for q in ijk))
+                a, b, c, e = node(0, 0), node(1, 0), node(1, 1), node(0, 1)
+                if sgn > 0:
+                    tris += [(a, b, c), (a, c, e)]
+                else:
+                    tris += [(a, c, b), (a, e, c)]
+    xyz = np.asarray(pts)
+    xyz = xyz - 0.5 * (xyz.min(axis=0) + xyz.max(axis=0)) + np.asarray(center, dtype=np.float64)
+    return xyz, np.asarray(tris, dtype=np.int32)
+
+
+def split_ring(side=2e-6, width=0.375e-6, gap=0.25e-6, thickness=0.1e-6, cells=16):
+    """Square split-ring resonator: a square ring of outer side ``side`` and
+    trace ``width`` with a ``gap`` cut through one side, ``thickness`` thick,
+    meshed on a ``cells`` x ``cells`` in-plane raster (one cell through the
+    thickness).  Defaults give 812 triangles."""
+    h = side / cells
+    w = max(1, int(round(width / h)))
+    g = max(1, int(round(gap / h)))
+    m = np.zeros((cells, cells, 1), dtype=bool)
+    m[:w, :, 0] = m[-w:, :, 0] = True
+    m[:, :w, 0] = m[:, -w:, 0] = True
+    c0 = (cells - g) // 2
+    m[c0:c0 + g, :w, 0] = False                    # the gap, through the side y = 0
+    return voxel_mesh(m, (h, h, thickness))
+
+
 def mesh_stats(xyz, tri):
     """Counts and signed enclosed volume (positive for outward orientation)."""
     a, b, c = xyz[tri[:, 0]], xyz[tri[:, 1]], xyz[tri[:, 2]]
