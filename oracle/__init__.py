@@ -22,4 +22,6 @@ follows):
 * ``aim``       - AIM reference: grid, stencils, projection, convolution,
                   near list, precorrection (Sec. III-D-1, eq. AIM_Lin/AIM_Kin)
 * ``bound``     - Lagrange interpolation error bound (Sec. IV, eq. Ddef)
+* ``aefie``     - augmented EFIE and constraint preconditioner (Sec. III-E,
+                  eq. sys)
 """

@@ -1,0 +1,146 @@
+"""Oracle pins for the augmented EFIE and its constraint preconditioner
+(Sec. III-E, eq. sys): the scalar potential factors through the pulse
+integrals, eliminating the charge reproduces the GIBC solution, the pulse
+integrals agree with plain quadrature of G, and the Schur-complement
+application of the preconditioner is its inverse."""
+import numpy as np
+import pytest
+
+from workloads import icosphere, box_mesh
+from oracle.rwg import RWGMesh
+from oracle.quad import collapsed_gauss, points_on
+from oracle.aefie import AugmentedProblem, equilibrated_solve
+
+
+@pytest.fixture(scope="module")
+def sphere_lf():
+    """Lossy dielectric sphere of radius 0.5 m at 30 MHz: k0 h ~ 0.1 on the
+    80-triangle icosphere (the low-frequency regime of eq. sys)."""
+    m = RWGMesh([icosphere(1, 0.5)])
+    return AugmentedProblem(m, 30e6, [(4.0, 1.0, 0.05)])
+
+
+@pytest.fixture(scope="module")
+def bar_lf():
+    """Copper box 10 x 2 x 1 um at 10 GHz (k0 h ~ 4e-5, skin depth 0.66 um)."""
+    xyz, tri = box_mesh((10e-6, 2e-6, 1e-6), (10, 2, 1))
+    m = RWGMesh([(xyz, tri)])
+    return AugmentedProblem(m, 10e9, [(1.0, 1.0, 5.8e7)])
+
+
+def test_divergence_matrix_is_rwg_divergence(sphere_lf):
+    """Every RWG function has zero net charge: sum_t A_t Dv[t, n] = 0, with
+    one positive and one negative triangle."""
+    dp = sphere_lf
+    Dv = dp.Dv
+    assert np.abs(dp.mesh.area @ Dv).max() < 1e-12 * np.abs(Dv).max()
+    assert np.all((Dv != 0).sum(axis=0) == 2)
+    assert np.all((Dv > 0).sum(axis=0) == 1)
+
+
+def test_scalar_potential_factors_through_pulses(sphere_lf):
+    """Phi0 = Dv^T Gam Dv (eq. opL with the divergence constant per triangle)."""
+    dp = sphere_lf
+    ref = dp.P0
+    assert np.abs(dp.Dv.T @ dp.Gam0 @ dp.Dv - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+def test_pulse_integrals_match_plain_quadrature(sphere_lf):
+    """Well-separated pairs: Gam[t, s] against a 12 x 12 collapsed Gauss rule
+    on both triangles applied to G = exp(-j k0 R) / (4 pi R) directly."""
+    dp = sphere_lf
+    m = dp.mesh
+    bary, w = collapsed_gauss(12)
+    pts = points_on(m.verts, bary)
+    c = m.centroid
+    d = np.linalg.norm(c[:, None, :] - c[None, :, :], axis=2)
+    hmax = m.length.max()
+    pairs = np.argwhere(d > 3.0 * hmax)[:200]
+    assert len(pairs) >= 100
+    k0 = dp.k0
+    for t, s in pairs:
+        R = np.linalg.norm(pts[t][:, None, :] - pts[s][None, :, :], axis=2)
+        ref = m.area[t] * m.area[s] * np.einsum("q,p,qp->", w, w, np.exp(-1j * k0 * R) / (4 * np.pi * R))
+        assert abs(dp.Gam0[t, s] - ref) < 1e-9 * abs(ref), (t, s)
+
+
+def test_pulse_integrals_reciprocal(sphere_lf):
+    g = sphere_lf.Gam0
+    assert np.abs(g - g.T).max() < 1e-6 * np.abs(g).max()
+
+
+@pytest.mark.parametrize("which,tol", [("sphere_lf", 1e-9), ("bar_lf", 1e-6)])
+def test_eliminating_charge_gives_gibc_solution(which, tol, request):
+    """P13: u of eq. sys equals u of the GIBC system (eq. GIBCsys); the charge
+    satisfies continuity, sigma = -Dv u / (j k0).  On the bar (k0 h ~ 4e-5)
+    the GIBC system's conditioning, ~(k0 h)^-2, amplifies FP64 rounding to
+    ~1e-7 in its own solution, hence the looser bound there."""
+    dp = request.getfixturevalue(which)
+    e = dp.rhs((0.0, 0.0, -1.0), (1.0, 0.0, 0.0))
+    u_ref = equilibrated_solve(dp.gibc_matrix(), e)
+    u, sg, v = dp.solve_aug(e)
+    assert np.linalg.norm(u - u_ref) < tol * np.linalg.norm(u_ref)
+    s_ref = -dp.Dv @ u / (1j * dp.k0)
+    assert np.linalg.norm(sg - s_ref) < 1e-9 * np.linalg.norm(s_ref)
+
+
+def test_unnested_block_form_has_the_same_solution(sphere_lf):
+    dp = sphere_lf
+    E, T = dp.mesh.nrwg, dp.T
+    e = dp.rhs((0.0, 0.0, -1.0), (1.0, 0.0, 0.0))
+    u, sg, v = dp.solve_aug(e)
+    b = np.concatenate([dp.aug_rhs(e), np.zeros(E, np.complex128)])
+    x = equilibrated_solve(dp.aug_block_matrix(), b)
+    assert np.linalg.norm(x[:E] - u) < 1e-9 * np.linalg.norm(u)
+    assert np.linalg.norm(x[E + T:] - v) < 1e-8 * np.linalg.norm(v)
+
+
+@pytest.mark.parametrize("which", ["sphere_lf", "bar_lf"])
+def test_schur_application_inverts_the_preconditioner(which, request):
+    """apply_preconditioner (block elimination through S) equals the
+    equilibrated dense solve with P."""
+    dp = request.getfixturevalue(which)
+    rng = np.random.default_rng(3)
+    n = dp.mesh.nrwg + dp.T
+    r = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    got = dp.apply_preconditioner(r)
+    ref = equilibrated_solve(dp.constraint_preconditioner(), r)
+    assert np.linalg.norm(got - ref) < 1e-8 * np.linalg.norm(ref)
+
+
+def test_schur_pattern_is_triangle_adjacency(sphere_lf):
+    dp = sphere_lf
+    S = dp.schur()
+    adj = (np.abs(dp.Dv) @ np.abs(dp.Dv).T) > 0
+    assert np.all((np.abs(S) > 0) == adj)
+
+
+def test_constraint_preconditioner_cuts_iterations(bar_lf):
+    """Right-preconditioned GMRES on eq. sys converges in far fewer iterations
+    with P than the GIBC system without it."""
+    dp = bar_lf
+    e = dp.rhs((0.0, 0.0, -1.0), (1.0, 0.0, 0.0))
+
+    def gmres(apply, b, prec=None, tol=1e-6, m=400):
+        beta = np.linalg.norm(b)
+        V = [b / beta]
+        H = np.zeros((m + 1, m), complex)
+        for j in range(m):
+            w = apply(prec(V[j]) if prec else V[j])
+            for i in range(j + 1):
+                H[i, j] = np.vdot(V[i], w); w = w - H[i, j] * V[i]
+            for i in range(j + 1):
+                c = np.vdot(V[i], w); H[i, j] += c; w = w - c * V[i]
+            H[j + 1, j] = np.linalg.norm(w)
+            V.append(w / H[j + 1, j])
+            g = np.zeros(j + 2, complex); g[0] = beta
+            y = np.linalg.lstsq(H[:j + 2, :j + 1], g, rcond=None)[0]
+            if np.linalg.norm(H[:j + 2, :j + 1] @ y - g) < tol * beta:
+                return j + 1
+        return m
+
+    G = dp.gibc_matrix() / dp.eta0
+    A = dp.aug_matrix()
+    n_gibc = gmres(lambda x: G @ x, e / dp.eta0)
+    n_cp = gmres(lambda x: A @ x, dp.aug_rhs(e), prec=dp.apply_preconditioner)
+    assert n_cp < 0.5 * n_gibc, (n_cp, n_gibc)
