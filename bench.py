@@ -54,7 +54,8 @@ def parse():
                          "dielectric sphere; fft: 4-field 256^3 convolution microbenchmark; "
                          "batch: 64 plane waves solved together on a 4,824-triangle copper bar; "
                          "serve: a Poisson stream of solve requests on the library's server; "
-                         "counters: launches for HBM counter runs (1 GiB copy + copper-bar near-field products)")
+                         "counters: launches for HBM counter runs (1 GiB copy, copper-bar exterior and cube-array "
+                         "interior near-field products)")
     ap.add_argument("--nrhs", type=int, default=64, help="batch workload: plane waves")
     ap.add_argument("--requests", type=int, default=8, help="serve workload: requests of the trace")
     ap.add_argument("--max-tri", type=int, default=20000, help="serve workload: triangle cap per request")
@@ -66,9 +67,8 @@ def parse():
                          "conditioning turns a 1e-6 residual into ~1e-3 in the currents; 1e-7 keeps FP32 "
                          "within 1e-3 of FP64), 1e-6 otherwise")
     ap.add_argument("--restart", type=int, default=None,
-                    help="outer GMRES restart length; default 1000 for the bar (its low-frequency EFIE "
-                         "converges in a staircase that restarts would lengthen), 300 for the cubes, 200 "
-                         "otherwise")
+                    help="outer GMRES restart length; default 1000 for the bar and the cube array (their "
+                         "exterior EFIE converges in a staircase that restarts would lengthen), 200 otherwise")
     ap.add_argument("--inner-relax", type=float, default=0.1,
                     help="relaxed nested tolerance inside the FP32 correction solves: nested solve j runs to "
                          "this x (correction target) / (outer residual estimate); 0: fixed tolerance")
@@ -172,6 +172,14 @@ def spmv_model(p, media, prec):
     return b, nnz
 
 
+def oracle_threads():
+    """Threads the oracle's OpenMP pair integrals run on (numpy's FFTs run
+    on one of them)."""
+    n = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    return min(n, int(env)) if env.isdigit() and int(env) > 0 else n
+
+
 def cpu_baseline_aim(cfg, rows=24):
     """The oracle's AIM product (O-aim, same approximation as the GPU) of one
     medium for one right-hand side, timed on a bounded sample: the grid part
@@ -200,7 +208,7 @@ def cpu_baseline_aim(cfg, rows=24):
     _ = op.near_rows(sample)
     t2 = time.perf_counter()
     per = (t1 - t0) + (t2 - t1) * m.nrwg / len(sample)
-    return {"value": 1.0 / per, "unit": "SIE matvecs/s", "cores": os.cpu_count(), "kind": "oracle",
+    return {"value": 1.0 / per, "unit": "SIE matvecs/s", "cores": oracle_threads(), "kind": "oracle",
             "sample": f"oracle AIM L product of one medium (interior of object 0: {len(o.tri)} triangles, "
                       f"{m.nrwg} RWG, {n}^3 grid, near radius {cfg.near_radius}): moments and grid part "
                       f"of the whole medium {t1 - t0:.1f} s, precorrected near rows of {len(sample)} seeded "
@@ -231,7 +239,7 @@ def cpu_baseline(cfg, mesh, rows):
         _ = np.sum(vals * x[cols])
     dt = time.perf_counter() - t0
     rate = rows / dt / m.nrwg                        # matvecs/s
-    return {"value": rate, "unit": "SIE matvecs/s", "cores": os.cpu_count(), "kind": "oracle",
+    return {"value": rate, "unit": "SIE matvecs/s", "cores": oracle_threads(), "kind": "oracle",
             "sample": f"dense L-operator rows of the copper bar: {rows} seeded rows of {m.nrwg} "
                       f"(each row: its 2 triangles x all {T} triangles, oracle integration policy, "
                       f"C pair integrals with OpenMP), {dt:.1f} s, extrapolated to whole matvecs"}
@@ -472,10 +480,13 @@ def serve_workload(args):
 
 
 def counters_workload(args):
-    """Launches for `rocprofv3 --pmc FETCH_SIZE` / `WRITE_SIZE` runs: a plain
-    1 GiB device copy (calibration of the counters) and five FP32 products
-    of every interior medium of the cube array (SIE_INTERIORS: the nested
-    operator's k_spmv_far launch over all 64 cubes, the dominant kernel)."""
+    """Launches for `rocprofv3 --pmc FETCH_SIZE` / `WRITE_SIZE` runs, in this
+    order: a plain 1 GiB device copy three times (calibration of the
+    counters); five FP64 and five FP32 exterior L products of the copper bar
+    (its near-field launches are the bar requests' dominant class); five FP32
+    products of every interior medium of the cube array (SIE_INTERIORS: the
+    nested operator's k_spmv_far launch over all 64 cubes).  Prints the
+    algorithmic bytes of each class."""
     import torch
     from paper_2003_11679_amd import INTERIORS
     a = torch.empty(2 ** 28, dtype=torch.float32, device="cuda")
@@ -485,7 +496,20 @@ def counters_workload(args):
     for _ in range(3):
         b.copy_(a)
     torch.cuda.synchronize()
+    del a, b
     SETUP_OPTS["skin_cutoff"] = args.skin_cutoff
+    out = {"copy_bytes": 2 ** 30}
+    p = build_problem(workload_cfg("bar"))
+    for prec, dt in ((0, torch.complex128), (1, torch.complex64)):
+        X = torch.randn(p.num_rwg, dtype=dt, device="cuda")
+        Y = torch.empty_like(X)
+        for _ in range(5):
+            p.matvec(-1, 0, X, Y)
+        torch.cuda.synchronize()
+        nb, nnz = spmv_model(p, [-1], prec)
+        out[f"bar_exterior{64 if prec == 0 else 32}"] = {"bytes": nb, "nnz": nnz}
+    del p
+    torch.cuda.synchronize()
     cfg = workload_cfg("cubes")
     p = build_problem(cfg)
     X = torch.randn(p.num_rwg, dtype=torch.complex64, device="cuda")
@@ -494,25 +518,40 @@ def counters_workload(args):
         p.matvec(INTERIORS, 0, X, Y)
     torch.cuda.synchronize()
     nb, nnz = spmv_model(p, list(range(len(cfg.objects))), 1)
-    print(json.dumps({"copy_bytes": 2 ** 30, "k_spmv_far_algorithmic_bytes": nb, "nnz": nnz}))
+    out["cubes_interior32"] = {"bytes": nb, "nnz": nnz}
+    print(json.dumps(out))
 
 
-def spmv_traffic(workload):
-    """Measured HBM bytes per dominant k_spmv_far<float> launch of the
+TRAFFIC_FILES = {"bar": "copper_bar", "cubes": "cube_array"}
+
+
+def spmv_source_sha():
+    """SHA-256 of the k_spmv_far kernel and its launcher in k_grid.hip (the
+    code a stored counter measurement belongs to)."""
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_2003_11679_amd", "csrc", "k_grid.hip")).read()
+    a = src.index("__global__ void k_spmv_far")
+    b = src.index("// y[r][row] = sum_j N[row][j] xt[j][r]")
+    return hashlib.sha256(src[a:b].encode()).hexdigest()
+
+
+def spmv_traffic(workload, cls):
+    """Measured HBM bytes per launch of the near-field class `cls` of the
     workload from the committed counter summary, if the kernel source is
     the one measured (else None)."""
     import hashlib
     import re
-    prof = os.path.join(ROOT, "profiles", f"k_spmv_far__{workload}_traffic.md")
-    src = os.path.join(ROOT, "paper_2003_11679_amd", "csrc", "k_grid.hip")
+    if workload not in TRAFFIC_FILES:
+        return None
+    prof = os.path.join(ROOT, "profiles", f"k_spmv_far__{TRAFFIC_FILES[workload]}_traffic.md")
     if not os.path.exists(prof):
         return None
-    m = re.search(r"bench-traffic: bytes_per_launch=(\d+) k_grid_sha256=([0-9a-f]+)", open(prof).read())
-    if not m:
-        return None
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != m.group(2):
-        return None
-    return int(m.group(1))
+    sha = spmv_source_sha()
+    for m in re.finditer(r"bench-traffic: class=(\w+) bytes_per_launch=(\d+) k_spmv_far_sha256=([0-9a-f]+)",
+                         open(prof).read()):
+        if m.group(1) == cls and m.group(3) == sha:
+            return int(m.group(2))
+    return None
 
 
 def main():
@@ -566,6 +605,8 @@ def dominant_kernel(tm, model, prec):
     return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": ach / HBM_PEAK_GBS if ach else None,
             "kernel": ("k_spmv_far<float> " if fp32 else "k_spmv_far<double> ") + f"({name})",
+            "class": {"interior media": "interior32" if fp32 else "interior64",
+                      "exterior medium": "exterior64", "exterior medium, FP32": "exterior32"}[name],
             "avg_launch_ms": avg, "launches": n, "bytes_per_launch": nb, "nnz": nnz,
             "share_of_csr_time": ms / max(tm["spmv"][1], 1e-30)}
 
@@ -606,6 +647,7 @@ def cube_array_request(args):
     model = spmv_classes(p, len(cfg.objects), 1)
     tm = {k: st[k] for k in ("spmv", "spmv64", "spmv_int32", "spmv_int64")}
     roof = dominant_kernel(tm, model, 1)
+    roof["traffic"] = spmv_traffic("cubes", roof["class"])
     print(f"[bench] cube array: setup {su:.2f}s total {tot:.2f}s {rep}", file=sys.stderr, flush=True)
     gate = fp64_gate(p, 1e-6, dict(opts, inner_relax=0.0))
     print(f"[bench] cube array fp64 gate: {gate}", file=sys.stderr, flush=True)
@@ -659,7 +701,7 @@ def request_workload(args):
     torch.cuda.synchronize()
     Tt = time.perf_counter() - t0
     roof = dominant_kernel({k: tuple(v) for k, v in tm.items()}, model, prec)
-    roof["traffic"] = spmv_traffic(args.workload) if roof["kernel"].endswith("(exterior medium)") else None
+    roof["traffic"] = spmv_traffic(args.workload, roof["class"])
     out = {
         "metric": "SIE matvecs/s + served solves/s, p50/p99 latency at rel err <=1e-3 vs FP64",
         "value": matvecs / Tt,

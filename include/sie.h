@@ -70,7 +70,8 @@ typedef enum {
 typedef enum {
     SIE_OP_L = 0,
     SIE_OP_K = 1,
-    SIE_OP_X = 2
+    SIE_OP_X = 2,
+    SIE_OP_AUG = 3   /* exterior rows of the augmented EFIE (sie_problem_set_augmented) */
 } sie_op;
 
 /* Quadrature orders (points per axis of the product rules) used for the
@@ -138,6 +139,10 @@ typedef struct {
 /* Binds HIP device `device`.  Returns SIE_EDEVICE if it does not exist. */
 sie_status sie_ctx_create(int device, sie_ctx **out);
 void sie_ctx_destroy(sie_ctx *ctx);
+/* Frees the device memory the library keeps for reuse (see
+ * sie_problem_destroy) on the context's device, e.g. before the caller
+ * allocates much device memory of its own.  Kept blocks outlive contexts. */
+sie_status sie_ctx_trim(sie_ctx *ctx);
 const char *sie_last_error(void);
 /* Message of the last failing call made with this context (through a
  * problem or server created on it); "" if none.  Valid until the next
@@ -215,6 +220,28 @@ sie_status sie_problem_set_quadrature(sie_problem *p, const sie_quad_params *q);
  * Sec. III-D-2 item b) also runs without grid part: the grid part would
  * equal its precorrection. */
 sie_status sie_problem_set_skin_cutoff(sie_problem *p, double skin_depths);
+/* Augmented EFIE for the exterior problem (Sec. III-E, eq. sys), set before
+ * setup; on = 1 or 0 (default).  The surface charge becomes an unknown, one
+ * pulse per triangle: with sigma = c0 rho, Dv[t][n] = div f_n on triangle t
+ * (+-l_n / A_t) and Gam[t][s] = int_t int_s G0,
+ *   [ j k0 A0 - (K0 - X/2) Z / eta0 , -Dv^T Gam ] [ u     ]   [ e / eta0 ]
+ *   [ W Dv                          ,  j k0 W   ] [ sigma ] = [ 0        ]
+ * (A0 the vector-potential part of L0, Z the GIBC operator of eq. GIBCdef,
+ * W = diag(A_t / k0) weighting the continuity rows).  Eliminating sigma
+ * gives the GIBC system divided by eta0, so u is the same.  Setup then also
+ * keeps the precorrected A0 and pulse near values, and factors the Schur
+ * complement S = j k0 I + Dv diag(j k0 A0_nn)^-1 Dv^T diag(Gam_tt) of the
+ * constraint preconditioner (sparse LU, host, FP64; SIE_EINVAL from setup
+ * when a separator of its nested dissection exceeds 1024 triangles).  Solves
+ * then iterate on (u, sigma) with that preconditioner (the outer-solve
+ * preconditioner bit 2 is ignored), and their residual is that of the
+ * augmented block system. */
+sie_status sie_problem_set_augmented(sie_problem *p, int32_t on);
+/* After setup: *on (1 if set up augmented), stored off-diagonal entries of
+ * the Schur factors, levels of the dissection tree, host factorisation time.
+ * Any output may be NULL. */
+sie_status sie_problem_augmented_info(const sie_problem *p, int32_t *on, int64_t *factor_nnz, int32_t *levels,
+                                      double *t_factor_s);
 /* 1 if the medium runs without grid part (see sie_problem_set_skin_cutoff),
  * 0 if it has one, negative sie_status on error. */
 int32_t sie_medium_is_local(const sie_problem *p, int32_t medium);
@@ -222,6 +249,10 @@ int32_t sie_medium_is_local(const sie_problem *p, int32_t medium);
  * precorrected near-field matrices (FP64 direct integrals on the device) and
  * Green's spectra for every medium.  Synchronous. */
 sie_status sie_problem_setup(sie_problem *p);
+/* Synchronises the device; the problem's device memory stays with the
+ * library for reuse by later problems on the device (blocks beyond half of
+ * the device's memory are freed), so that a request that repeats an earlier
+ * one maps no new memory.  sie_ctx_trim frees what is kept. */
 void sie_problem_destroy(sie_problem *p);
 
 /* ---- queries --------------------------------------------------------- */
@@ -267,6 +298,11 @@ sie_status sie_get_wavenumber(const sie_problem *p, int32_t medium, sie_c128 *k)
  * without its -j w eps_i factors), computed the way the solver does: the
  * objects whose grids share a shape in one launch per stage. */
 #define SIE_INTERIORS (-2)
+/* Op = SIE_OP_AUG (medium -1, SIE_FP64, problem set up augmented): x and y
+ * are [nrhs][E + T] (T triangles), [u; sigma] in and
+ * [j k0 A0 u - Dv^T Gam sigma; W (Dv u + j k0 sigma)] out, the AIM product
+ * of the exterior rows of eq. sys without the GIBC term (the vector fields
+ * projected from u, the scalar field from the pulse charges). */
 sie_status sie_matvec(sie_problem *p, int32_t medium, sie_op op, sie_precision prec, int32_t nrhs,
                       const void *x_dev, void *y_dev, void *stream);
 /* Allocation-free form of sie_matvec, for callers that cannot allocate device
@@ -311,6 +347,15 @@ sie_status sie_nested_precond(sie_problem *p, int32_t precond, sie_precision pre
 /* Clusters of the built Schwarz preconditioner (-1 if not built); *owned
  * (nullable) receives the number of RWG rows they own. */
 int32_t sie_nested_precond_clusters(const sie_problem *p, int64_t *owned);
+
+/* Constraint preconditioner of the augmented EFIE (Sec. III-E), y = P^-1 x
+ * for nrhs vectors [nrhs][E + T] complex128 on the caller's stream, with
+ *   P = [ j k0 diag(A0_nn) , -Dv^T diag(Gam_tt) ]
+ *       [ W Dv             ,  j k0 W            ]
+ * applied by block elimination through the factored Schur complement (see
+ * sie_problem_set_augmented).  x and y must not alias.  SIE_ESTATE unless
+ * set up augmented. */
+sie_status sie_constraint_precond(sie_problem *p, int32_t nrhs, const void *x_dev, void *y_dev, void *stream);
 
 /* Stage timers (HIP events recorded on the stream of each product).
  * sie_set_timing(p, 1) starts recording every stage, sie_set_timing(p, 2)
@@ -382,7 +427,8 @@ typedef struct {
  * one chunk), and the Krylov bases of the default solver options; available
  * before setup. */
 sie_status sie_problem_footprint(const sie_problem *p, size_t *device_bytes);
-/* hbm_budget_bytes 0: 80 % of the device memory free at creation;
+/* hbm_budget_bytes 0: 80 % of the device memory free at creation (blocks
+ * the library keeps for reuse count as free);
  * max_slots: concurrent requests (worker threads), 1..64. */
 sie_status sie_server_create(sie_ctx *ctx, size_t hbm_budget_bytes, int32_t max_slots, sie_server **out);
 /* Queues a request; the server owns p until sie_server_take.  khat / e0 as

@@ -172,3 +172,62 @@ class AugmentedProblem(DenseProblem):
         k0 = self.k0
         w = 1.0 / (1j * k0 * np.diag(self.A0))
         return 1j * k0 * np.eye(self.T) + (self.Dv * w[None, :]) @ self.Dv.T * np.diag(self.Gam0)[None, :]
+
+
+class AugmentedAIM:
+    """AIM form of the exterior rows of eq. sys (the library's augmented
+    product): the vector potential A0 of an AIMOperator (its precorrected near
+    matrix NA plus grid part), and the pulse-charge potential Gam0 through the
+    same grid: pulse charges project with the triangle moments M0 (the scalar
+    stencil weights without the RWG divergence), the convolved potential is
+    tested with M0 per triangle, and the near pairs of the operator carry the
+    direct pulse integrals minus their grid part (eq. LinNRP applied to
+    pulses)."""
+
+    def __init__(self, op, rules=None):
+        self.op = op
+        mesh = op.mesh
+        self.mesh = mesh
+        self.k0 = op.k
+        self.T = len(mesh.tri)
+        self.Dv = divergence_matrix(mesh)
+        div0 = mesh.tri_sign[:, 0] * mesh.tri_len[:, 0] / mesh.area
+        tl, sl = op.near_t, op.near_s
+        G = np.zeros((self.T, self.T), np.complex128)
+        for c0 in range(0, len(tl), 20000):
+            a, b = tl[c0:c0 + 20000], sl[c0:c0 + 20000]
+            _, ph, _ = pair_blocks(mesh, op.k, a, b, rules)
+            direct = ph[:, 0, 0] / (div0[a] * div0[b])
+            if op.local:
+                grid = 0.0
+            else:
+                if not hasattr(op, "_Gt"):
+                    op._offset_tables()
+                dn = op.nodes[a][:, :, None, :] - op.nodes[b][:, None, :, :] + op._W
+                Gg = op._Gt[dn[..., 0], dn[..., 1], dn[..., 2]]                    # [P,27,27]
+                grid = np.einsum("pa,pab,pb->p", op.M0[a], Gg, op.M0[b])
+            G[a, b] += direct - grid
+        self.NG = G
+
+    def pulse_far(self, sg):
+        """Grid part of Gam0 sigma per triangle: project sigma_t M0_t, convolve
+        with G, test with M0_t."""
+        op = self.op
+        if op.local:
+            return np.zeros(self.T, np.complex128)
+        n = op.grid.n
+        Q = np.zeros((n[2], n[1], n[0]), np.complex128)
+        idx = op.nodes
+        np.add.at(Q, (idx[..., 2], idx[..., 1], idx[..., 0]), sg[:, None] * op.M0)
+        F = op.convolve_fft(Q, "G")
+        return np.einsum("ta,ta->t", op.M0, F[idx[..., 2], idx[..., 1], idx[..., 0]])
+
+    def matvec(self, x):
+        """[j k0 A0 u - Dv^T Gam0 sigma ; W (Dv u + j k0 sigma)] for x = [u; sigma]."""
+        E = self.mesh.nrwg
+        u, sg = x[:E], x[E:]
+        k0 = self.k0
+        yu = 1j * k0 * self.op.matvec(u, "A") - self.Dv.T @ (self.NG @ sg + self.pulse_far(sg))
+        W = self.mesh.area / k0.real
+        ys = W * (self.Dv @ u + 1j * k0 * sg)
+        return np.concatenate([yu, ys])

@@ -86,6 +86,13 @@ sie_status sie_ctx_create(int device, sie_ctx **out) {
 
 void sie_ctx_destroy(sie_ctx *ctx) { delete ctx; }
 
+sie_status sie_ctx_trim(sie_ctx *ctx) {
+    return guard(ctx, [&] {
+        SIE_CHECK(ctx, SIE_EINVAL, "NULL context");
+        pool_trim(ctx->device);
+    });
+}
+
 sie_status sie_problem_create(sie_ctx *ctx, double freq_hz, double bg_eps_r, double bg_mu_r, sie_problem **out) {
     return guard(ctx, [&] {
         SIE_CHECK(ctx && out, SIE_EINVAL, "NULL argument");
@@ -176,6 +183,37 @@ sie_status sie_problem_set_skin_cutoff(sie_problem *p, double skin_depths) {
         SIE_CHECK(!p->is_setup, SIE_ESTATE, "problem already set up");
         SIE_CHECK(skin_depths >= 0.0 && std::isfinite(skin_depths), SIE_EINVAL, "cutoff must be finite and >= 0");
         p->cutoff_factor = skin_depths;
+    });
+}
+
+sie_status sie_problem_set_augmented(sie_problem *p, int32_t on) {
+    return guard(ctx_of(p), [&] {
+        SIE_CHECK(p, SIE_EINVAL, "NULL problem");
+        SIE_CHECK(!p->is_setup, SIE_ESTATE, "problem already set up");
+        SIE_CHECK(on == 0 || on == 1, SIE_EINVAL, "augmented must be 0 or 1");
+        p->aug_mode = on;
+    });
+}
+
+sie_status sie_problem_augmented_info(const sie_problem *p, int32_t *on, int64_t *factor_nnz, int32_t *levels,
+                                      double *t_factor_s) {
+    return guard(ctx_of(p), [&] {
+        SIE_CHECK(p && p->is_setup, SIE_ESTATE, "problem not set up");
+        const bool a = (bool)p->aug;
+        if (on) *on = a ? 1 : 0;
+        if (factor_nnz) *factor_nnz = a ? p->aug->lu.nnz_factor : 0;
+        if (levels) *levels = a ? (int32_t)p->aug->lu.lev_ptr.size() - 1 : 0;
+        if (t_factor_s) *t_factor_s = a ? p->aug->t_factor_s : 0.0;
+    });
+}
+
+sie_status sie_constraint_precond(sie_problem *p, int32_t nrhs, const void *x_dev, void *y_dev, void *stream) {
+    return guard(ctx_of(p), [&] {
+        SIE_CHECK(p && p->is_setup, SIE_ESTATE, "problem not set up");
+        SIE_CHECK(p->aug, SIE_ESTATE, "problem not set up for the augmented EFIE");
+        SIE_CHECK(x_dev && y_dev && nrhs >= 1, SIE_EINVAL, "bad vectors");
+        SIE_CHECK(x_dev != y_dev, SIE_EINVAL, "x and y must not alias");
+        cp_apply(p, nrhs, (const c128 *)x_dev, (c128 *)y_dev, user_stream(stream));
     });
 }
 
@@ -306,8 +344,16 @@ sie_status sie_matvec(sie_problem *p, int32_t medium, sie_op op, sie_precision p
         SIE_CHECK(p && p->is_setup, SIE_ESTATE, "problem not set up");
         SIE_CHECK(x_dev && y_dev && nrhs >= 1, SIE_EINVAL, "bad vectors");
         SIE_CHECK(x_dev != y_dev, SIE_EINVAL, "x and y must not alias");
-        SIE_CHECK(op == SIE_OP_L || op == SIE_OP_K || op == SIE_OP_X, SIE_EINVAL, "unknown operator");
+        SIE_CHECK(op == SIE_OP_L || op == SIE_OP_K || op == SIE_OP_X || op == SIE_OP_AUG, SIE_EINVAL,
+                  "unknown operator");
         hipStream_t st = user_stream(stream);
+        if (op == SIE_OP_AUG) {
+            SIE_CHECK(medium == -1, SIE_EINVAL, "the augmented product belongs to the exterior medium (-1)");
+            SIE_CHECK(prec == SIE_FP64, SIE_EINVAL, "the augmented product runs in FP64");
+            SIE_CHECK(p->aug, SIE_ESTATE, "problem not set up for the augmented EFIE");
+            aug_product(p, nrhs, (const c128 *)x_dev, (c128 *)y_dev, st);
+            return;
+        }
         if (medium == SIE_INTERIORS && op != SIE_OP_X) {
             SIE_CHECK(prec == SIE_FP64 || prec == SIE_FP32, SIE_EINVAL, "unknown precision");
             for (auto &gp : p->groups) {

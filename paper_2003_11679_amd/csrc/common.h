@@ -60,6 +60,14 @@ struct Error : std::runtime_error {
         if (!(cond)) throw ::sie::Error(code, msg);                           \
     } while (0)
 
+// ---------------------------------------------------------------- device memory
+// Pool of device blocks (pool.cpp): pool_alloc throws SIE_ENOMEM; pool_free
+// synchronises the device and keeps the block for reuse.
+void *pool_alloc(size_t bytes);
+void pool_free(void *p);
+size_t pool_cached_bytes(int device);
+void pool_trim(int device);
+
 // ---------------------------------------------------------------- device buffer
 // Owns its device memory, or (view) refers to a slice of another DBuf's.
 template <typename T>
@@ -86,15 +94,16 @@ struct DBuf {
         release();
         n = count;
         if (count) {
-            hipError_t e = hipMalloc(&p, count * sizeof(T));
-            if (e != hipSuccess) {
+            try {
+                p = static_cast<T *>(pool_alloc(count * sizeof(T)));
+            } catch (...) {
                 p = nullptr; n = 0;
-                throw Error(SIE_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+                throw;
             }
         }
     }
     void release() {
-        if (p && own) (void)hipFree(p);
+        if (p && own) pool_free(p);
         p = nullptr; n = 0; own = true;
     }
     void upload(const T *h, size_t count) {

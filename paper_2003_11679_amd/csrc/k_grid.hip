@@ -134,7 +134,9 @@ void launch_tri_sources(const GridView &g, const T *tri_coef, const cx<T> *x, in
 
 // Gather projection: `lpn` lanes (a power of two <= 64) per live node share
 // its entry list and reduce with lane shuffles.  grid [F][nlive] with
-// J_c = sum (alpha M1_c - beta_c M0) and (F == 4) Q = sum 2 alpha M0.
+// J_c = sum (alpha M1_c - beta_c M0) and (F == 4) Q = sum 2 alpha M0, the
+// RWG divergences; with rho given (augmented EFIE, Sec. III-E), Q = sum
+// rho_t M0 of the pulse charges instead (rho [rhs][ntg], stride ldr).
 template <typename T>
 __device__ inline T seg_sum(T v, int lpn) {
     for (int off = lpn >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -144,11 +146,13 @@ __device__ inline T seg_sum(T v, int lpn) {
 template <typename T>
 __global__ void k_project(int64_t nnodes, int64_t nlive, const int32_t *__restrict__ node_ptr,
                           const int32_t *__restrict__ ent, const T *__restrict__ mom, const cx<T> *__restrict__ src,
-                          cx<T> *__restrict__ grid, int nf, int lpn, int64_t ntg) {
+                          cx<T> *__restrict__ grid, int nf, int lpn, int64_t ntg, const cx<T> *__restrict__ rho,
+                          int64_t ldr) {
     const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t v = gid / lpn;
     src += blockIdx.y * 4 * ntg;           // right-hand side blockIdx.y
     grid += blockIdx.y * nf * nnodes;
+    if (rho) rho += blockIdx.y * ldr;
     const int sub = (int)(gid % lpn);
     // every lane of a wave takes part in the shuffles; out-of-range nodes add zeros
     T s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -162,7 +166,12 @@ __global__ void k_project(int64_t nnodes, int64_t nlive, const int32_t *__restri
             s[0] += m[1] * al.re - m[0] * bx.re; s[1] += m[1] * al.im - m[0] * bx.im;
             s[2] += m[2] * al.re - m[0] * by.re; s[3] += m[2] * al.im - m[0] * by.im;
             s[4] += m[3] * al.re - m[0] * bz.re; s[5] += m[3] * al.im - m[0] * bz.im;
-            s[6] += m[0] * al.re; s[7] += m[0] * al.im;
+            if (rho) {
+                const cx<T> q = rho[t];
+                s[6] += m[0] * q.re; s[7] += m[0] * q.im;
+            } else {
+                s[6] += m[0] * al.re; s[7] += m[0] * al.im;
+            }
         }
     }
     for (int i = 0; i < 8; ++i) s[i] = seg_sum(s[i], lpn);
@@ -173,13 +182,13 @@ __global__ void k_project(int64_t nnodes, int64_t nlive, const int32_t *__restri
         o[0] = cx<T>(s[0], s[1]);
         o[nlive] = cx<T>(s[2], s[3]);
         o[2 * nlive] = cx<T>(s[4], s[5]);
-        if (nf == 4) o[3 * nlive] = cx<T>(T(2) * s[6], T(2) * s[7]);
+        if (nf == 4) o[3 * nlive] = rho ? cx<T>(s[6], s[7]) : cx<T>(T(2) * s[6], T(2) * s[7]);
     }
 }
 
 template <typename T>
 void launch_project(const GridView &g, const T *mom, const cx<T> *trisrc, cx<T> *grid, int nfields, int nrhs,
-                    hipStream_t st) {
+                    hipStream_t st, const cx<T> *rho, int64_t ldr) {
     const int64_t nnodes = g.nnodes();
     if (nrhs < 1) return;
     SIE_CHECK(nrhs <= 65535, SIE_EINVAL, "too many right-hand sides");
@@ -189,7 +198,7 @@ void launch_project(const GridView &g, const T *mom, const cx<T> *trisrc, cx<T> 
     while (lpn < 64 && lpn * 2 <= avg / 2.0) lpn *= 2;
     const int64_t threads = nnodes * lpn;
     hipLaunchKernelGGL(k_project<T>, dim3((unsigned)((threads + 255) / 256), (unsigned)nrhs), dim3(256), 0, st,
-                       nnodes, g.nlive, g.node_ptr, g.node_ent, mom, trisrc, grid, nfields, lpn, g.ntg);
+                       nnodes, g.nlive, g.node_ptr, g.node_ent, mom, trisrc, grid, nfields, lpn, g.ntg, rho, ldr);
     SIE_HIP(hipGetLastError());
 }
 
@@ -516,7 +525,8 @@ void launch_x_apply(int64_t E, const int32_t *xptr, const int32_t *xcol, const T
 #define SIE_INST(T)                                                                                           \
     template void launch_tri_sources<T>(const GridView &, const T *, const cx<T> *, int64_t, int, cx<T> *,      \
                                         hipStream_t);                                                          \
-    template void launch_project<T>(const GridView &, const T *, const cx<T> *, cx<T> *, int, int, hipStream_t);\
+    template void launch_project<T>(const GridView &, const T *, const cx<T> *, cx<T> *, int, int, hipStream_t, \
+                                    const cx<T> *, int64_t);                                                     \
     template void launch_interp<T>(const GridView &, const T *, const cx<T> *, int, int, cx<T> *, hipStream_t); \
     template void launch_spmm_far<T>(const GridView &, int64_t, int, const T *, const cx<T> *, const cx<T> *,   \
                                      const cx<T> *, const cx<T> *, const cx<T> *, cx<T> *, cx<T> *, hipStream_t); \

@@ -532,7 +532,8 @@ __device__ void fill_pair(const NearFillArgs &a, int64_t tl, int64_t sl, int64_t
     const c128 ik2 = cdiv(c128(1.0), k * k);
     const double *ct = a.tri_coef + tl * 12;
     const double *cs = a.tri_coef + sl * 12;
-    c128 *out = a.blocks + p * 27;
+    c128 *out = a.blocks + p * a.bstride;
+    const bool aug = a.bstride > 27;
     for (int e = 0; e < 3; ++e) {
         const double ce = ct[4 * e];
         const V3 qe = {ct[4 * e + 1], ct[4 * e + 2], ct[4 * e + 3]};
@@ -551,7 +552,15 @@ __device__ void fill_pair(const NearFillArgs &a, int64_t tl, int64_t sl, int64_t
             out[e * 3 + f] = (Ad - Ag) - ik2 * (Pd - Pg);
             out[9 + e * 3 + f] = Kd - Kg;
             out[18 + e * 3 + f] = Ad - ik2 * Pd;     // direct (unprecorrected) L
+            if (aug) {
+                out[27 + e * 3 + f] = Ad - Ag;       // precorrected vector potential
+                out[36 + e * 3 + f] = Ad;            // direct vector potential
+            }
         }
+    }
+    if (aug) {
+        a.gam[p] = aS - S00;                         // pulse integral minus its grid part
+        if (tl == sl) a.gself[tg] = aS;
     }
 }
 
@@ -765,8 +774,9 @@ __global__ __launch_bounds__(256) void k_near_gather(int64_t nrow, int64_t rwg0,
                                                      const int32_t *__restrict__ glob2loc, const int32_t *__restrict__ tpm,
                                                      const int32_t *__restrict__ epm, const int64_t *__restrict__ pair_ptr,
                                                      const int32_t *__restrict__ pair_s, const c128 *__restrict__ blocks,
-                                                     c128 *__restrict__ nL64, c128 *__restrict__ nK64,
-                                                     c128 *__restrict__ nLd64) {
+                                                     int bstride, c128 *__restrict__ nL64, c128 *__restrict__ nK64,
+                                                     c128 *__restrict__ nLd64, c128 *__restrict__ nA64,
+                                                     c128 *__restrict__ adiag) {
     __shared__ int32_t ls[2][kGatherLds];
     const int64_t r = blockIdx.x;
     if (r >= nrow) return;
@@ -786,7 +796,7 @@ __global__ __launch_bounds__(256) void k_near_gather(int64_t nrow, int64_t rwg0,
     __syncthreads();
     for (int64_t j = row_ptr[r] + threadIdx.x; j < row_ptr[r + 1]; j += blockDim.x) {
         const int32_t n = cols[j];
-        c128 L, K, Ld;
+        c128 L, K, Ld, A, Ad;
         for (int sa = 0; sa < 2; ++sa) {
             if (nn[sa] == 0) continue;
             const bool inl = nn[sa] <= kGatherLds;
@@ -802,26 +812,37 @@ __global__ __launch_bounds__(256) void k_near_gather(int64_t nrow, int64_t rwg0,
                     if (v < sl) lo = mid + 1; else hi = mid;
                 }
                 if (q < 0) continue;
-                L += blocks[q * 27 + ea[sa] * 3 + eb];
-                K += blocks[q * 27 + 9 + ea[sa] * 3 + eb];
-                Ld += blocks[q * 27 + 18 + ea[sa] * 3 + eb];
+                const c128 *bq = blocks + q * bstride + ea[sa] * 3 + eb;
+                L += bq[0];
+                K += bq[9];
+                Ld += bq[18];
+                if (nA64) {
+                    A += bq[27];
+                    Ad += bq[36];
+                }
             }
         }
         // row-triangle chunks are processed one after the other: accumulate
         nL64[j] += L;
         nK64[j] += K;
         nLd64[j] += Ld;
+        if (nA64) {
+            nA64[j] += A;
+            if (n == rwg0 + r) adiag[r] += Ad;   // one column of the row is its diagonal
+        }
     }
 }
 
 void launch_near_gather(int64_t nrow, int64_t rwg0, int64_t max_row, const int64_t *row_ptr, const int32_t *cols,
                          const int32_t *rwg_loc, const int32_t *glob2loc, const int32_t *tpm, const int32_t *epm,
-                         const int64_t *pair_ptr, const int32_t *pair_s, const c128 *blocks, c128 *nL64,
-                         c128 *nK64, c128 *nLd64, hipStream_t st) {
+                         const int64_t *pair_ptr, const int32_t *pair_s, const c128 *blocks, int bstride,
+                         c128 *nL64, c128 *nK64, c128 *nLd64, c128 *nA64, c128 *adiag, hipStream_t st) {
     if (!nrow || !max_row) return;
     SIE_CHECK(nrow < (1LL << 31), SIE_EINVAL, "too many rows");
+    SIE_CHECK(bstride == 27 || (bstride == 45 && nA64 && adiag), SIE_EINVAL, "bad pair block layout");
     hipLaunchKernelGGL(k_near_gather, dim3((unsigned)nrow), dim3(256), 0, st, nrow, rwg0, row_ptr, cols, rwg_loc,
-                       glob2loc, tpm, epm, pair_ptr, pair_s, blocks, nL64, nK64, nLd64);
+                       glob2loc, tpm, epm, pair_ptr, pair_s, blocks, bstride, nL64, nK64, nLd64,
+                       bstride == 45 ? nA64 : nullptr, adiag);
     SIE_HIP(hipGetLastError());
 }
 

@@ -27,7 +27,7 @@ void launch_tri_sources(const GridView &g, const T *tri_coef, const cx<T> *x, in
                         cx<T> *trisrc, hipStream_t st);
 template <typename T>
 void launch_project(const GridView &g, const T *mom, const cx<T> *trisrc, cx<T> *grid, int nfields, int nrhs,
-                    hipStream_t st);
+                    hipStream_t st, const cx<T> *rho = nullptr, int64_t ldr = 0);
 template <typename T>
 void launch_interp(const GridView &g, const T *mom, const cx<T> *pot, int nfields, int nrhs, cx<T> *tripot,
                    hipStream_t st);
@@ -45,6 +45,22 @@ void launch_spmm_far(const GridView &g, int64_t E, int nrhs, const T *tri_coef, 
 template <typename T>
 void launch_x_apply(int64_t E, const int32_t *xptr, const int32_t *xcol, const T *xval, const cx<T> *x,
                     cx<T> *y, hipStream_t st);
+
+// ---- k_aug.hip (augmented EFIE, Sec. III-E; FP64)
+// tripot[r][t][4] += sum over the near pairs (t, s) of gam[p] rho[r][s].
+void launch_tri_near(int64_t ntg, const int64_t *pair_ptr, const int32_t *pair_s, const c128 *gam, const c128 *rho,
+                     int64_t ldr, int nrhs, c128 *tripot, hipStream_t st);
+// y[r][t] = sum_e sl[t][e] u[r][n_e] / k0 + j A_t sigma[r][t] (weighted continuity rows).
+void launch_continuity(int64_t nt, const int32_t *tri_rwg, const double *sl, const double *area, double k0,
+                       const c128 *u, int64_t ldu, const c128 *sg, int64_t lds, c128 *y, int64_t ldy, int nrhs,
+                       hipStream_t st);
+// Constraint preconditioner around the Schur solve (xnd [nrhs][nt] in the
+// solver's position order).
+void launch_cp_pre(int64_t nt, const int32_t *tri_rwg, const double *sl, const double *area, double k0, const c128 *ad,
+                   const int32_t *iperm, const c128 *r, int64_t ldr, int64_t E, c128 *xnd, int nrhs, hipStream_t st);
+void launch_cp_post(int64_t E, int64_t nt, const int32_t *tpm, const int32_t *epm, const double *sl, const double *area,
+                    const c128 *gself, const c128 *ad, const int32_t *iperm, const c128 *xnd, const c128 *r,
+                    int64_t ldr, c128 *y, int64_t ldy, int nrhs, hipStream_t st);
 
 // ---- k_near.hip
 // Skin-depth cutoff of a near search: dc > 0 keeps the pairs whose centroids
@@ -83,6 +99,13 @@ struct NearFillArgs {
     const c128 *ptab; int64_t tab_row0; int tab_w;
     const uint8_t *pkind;            // kind | loc << 4 of pair slot p (same offset as pair_s)
     int no_grid;                     // medium without grid part: direct values, no precorrection
+    // augmented EFIE (exterior medium, Sec. III-E): blocks of bstride = 45
+    // values per pair also hold the precorrected and the direct vector
+    // potential blocks; gam[p] receives the pair's precorrected pulse integral
+    // int_t int_s G, gself[t] the direct self integral of global triangle t
+    int bstride = 27;
+    c128 *gam = nullptr;
+    c128 *gself = nullptr;
 };
 // kinds[p] = kind | loc << 4 for every pair slot of a.pair_ptr / a.pair_s.
 void launch_pair_kinds(const NearFillArgs &a, uint8_t *kinds, hipStream_t st);
@@ -91,8 +114,8 @@ void launch_precorr_table(const NearFillArgs &a, int64_t row0, int64_t nrows, c1
 void launch_near_fill(const NearFillArgs &a, int64_t npairs, hipStream_t st);
 void launch_near_gather(int64_t nrow, int64_t rwg0, int64_t max_row, const int64_t *row_ptr, const int32_t *cols,
                         const int32_t *rwg_loc, const int32_t *glob2loc, const int32_t *tpm, const int32_t *epm,
-                        const int64_t *pair_ptr, const int32_t *pair_s, const c128 *blocks, c128 *nL64,
-                        c128 *nK64, c128 *nLd64, hipStream_t st);
+                        const int64_t *pair_ptr, const int32_t *pair_s, const c128 *blocks, int bstride,
+                        c128 *nL64, c128 *nK64, c128 *nLd64, c128 *nA64, c128 *adiag, hipStream_t st);
 void launch_green_radial(c128 k, double h, int nq, c128 *gr, hipStream_t st);
 void launch_green_sample(c128 k, double h, const int nl[3], const int m[3], int kind, c128 *vol, hipStream_t st);
 void launch_fold_octant(const c128 *vol, const int m[3], int kind, double scale, c128 *spec64, c64 *spec32,

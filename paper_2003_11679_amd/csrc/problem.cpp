@@ -374,6 +374,21 @@ static void build_medium(sie_problem *p, Medium &md) {
                           : 0;
 
     setup_mark("medium: rules, tables");
+    // augmented EFIE: the exterior medium also yields the vector-potential
+    // values, the pulse integrals and the preconditioner's diagonals
+    const bool aug = p->aug && &md == &p->ext;
+    if (aug) {
+        AugState &A = *p->aug;
+        SIE_CHECK(ntg == p->mesh.nt(), SIE_EINVAL, "augmented EFIE: exterior grid must hold every triangle");
+        A.nA64.alloc(std::max<int64_t>(g.nnz, 1));
+        A.gam64.alloc(std::max<int64_t>(g.npairs, 1));
+        A.adiag.alloc(std::max<int64_t>(g.rwg1 - g.rwg0, 1));
+        A.gself.alloc(std::max<int64_t>(ntg, 1));
+        SIE_HIP(hipMemset(A.nA64.p, 0, A.nA64.bytes()));
+        SIE_HIP(hipMemset(A.adiag.p, 0, A.adiag.bytes()));
+        SIE_HIP(hipMemset(A.gself.p, 0, A.gself.bytes()));
+    }
+    const int bstride = aug ? 45 : 27;
     keep_or_alloc(md.d_nL64, std::max<int64_t>(g.nnz, 1));
     keep_or_alloc(md.d_nK64, std::max<int64_t>(g.nnz, 1));
     md.d_nLd64.alloc(std::max<int64_t>(g.nnz, 1));
@@ -383,7 +398,7 @@ static void build_medium(sie_problem *p, Medium &md) {
     // process row triangles in chunks to bound the pair-block buffer
     setup_mark("medium: alloc + clear");
     std::vector<int64_t> pptr = g.d_pair_ptr.download();
-    const int64_t max_chunk = 30000000;  // pair blocks of one chunk: 13 GB of HBM at most
+    const int64_t max_chunk = 30000000 * 27 / bstride;  // pair blocks of one chunk: 13 GB of HBM at most
     DBuf<c128> blocks, ptab;
     DBuf<int64_t> d_pp;
     const int64_t nrow = g.rwg1 - g.rwg0;
@@ -409,7 +424,7 @@ static void build_medium(sie_problem *p, Medium &md) {
         std::vector<int64_t> cp(ntg + 1);
         for (int64_t i = 0; i <= ntg; ++i) cp[i] = std::min(std::max(pptr[i], pptr[t0]), pptr[t1]) - pptr[t0];
         d_pp.upload(cp);
-        blocks.alloc(std::max<int64_t>(np, 1) * 27);
+        blocks.alloc(std::max<int64_t>(np, 1) * bstride);
         setup_mark("fill: chunk buffers");
         NearFillArgs a;
         a.xyz = p->d_xyz.p; a.tri = p->d_tri.p; a.tris = g.d_tris.p; a.centre = g.d_centre.p;
@@ -423,6 +438,9 @@ static void build_medium(sie_problem *p, Medium &md) {
         a.tab_row0 = t0; a.tab_w = tab_w;
         a.pkind = g.d_pair_kind.p + pptr[t0];
         a.no_grid = md.local ? 1 : 0;
+        a.bstride = bstride;
+        a.gam = aug ? p->aug->gam64.p + pptr[t0] : nullptr;
+        a.gself = aug ? p->aug->gself.p : nullptr;
         if (!md.local) {
             ptab.alloc((t1 - t0) * tab_row);
             a.ptab = ptab.p;
@@ -434,8 +452,9 @@ static void build_medium(sie_problem *p, Medium &md) {
         launch_near_fill(a, np, 0);
         setup_mark("fill: pair blocks");
         launch_near_gather(nrow, g.rwg0, g.max_row, g.d_row_ptr.p, g.d_cols.p, g.d_rwgloc.p, g.d_glob2loc.p,
-                           p->d_tpm.p, p->d_epm.p, d_pp.p, g.d_pair_s.p + pptr[t0], blocks.p, md.d_nL64.p,
-                           md.d_nK64.p, md.d_nLd64.p, 0);
+                           p->d_tpm.p, p->d_epm.p, d_pp.p, g.d_pair_s.p + pptr[t0], blocks.p, bstride,
+                           md.d_nL64.p, md.d_nK64.p, md.d_nLd64.p, aug ? p->aug->nA64.p : nullptr,
+                           aug ? p->aug->adiag.p : nullptr, 0);
         SIE_HIP(hipStreamSynchronize(0));
         t0 = t1;
     }
@@ -985,6 +1004,125 @@ void stage_interpolate(sie_problem *p, Medium &md, const cx<T> *grid, cx<T> *y, 
 SIE_INST_MV(float)
 SIE_INST_MV(double)
 
+// Constants of the augmented product and the factors of the constraint
+// preconditioner's Schur complement (Sec. III-E).
+static void aug_setup(sie_problem *p) {
+    AugState &A = *p->aug;
+    const Mesh &m = p->mesh;
+    const int64_t E = m.nrwg, T = m.nt();
+    const double k0 = p->ext.k.re;
+    std::vector<double> sl(3 * T);
+    for (int64_t i = 0; i < 3 * T; ++i) sl[i] = m.tri_sign[i] * m.len[m.tri_rwg[i]];
+    A.sl.upload(sl);
+    A.ks.upload(std::vector<c128>{c128(0.0, 2.0 / k0)});
+    A.alpha.upload(std::vector<c128>{c128(0.0, k0)});
+    const std::vector<c128> adiag = A.adiag.download(E), gself = A.gself.download(T);
+    std::vector<c128> ad(E);
+    for (int64_t n = 0; n < E; ++n) ad[n] = c128(0.0, k0) * adiag[n];
+    A.ad.upload(ad);
+    // S = j k0 I + Dv diag(ad)^-1 Dv^T diag(gself): the RWG function n couples
+    // its two triangles
+    std::vector<std::vector<std::pair<int32_t, c128>>> rows(T);
+    for (int64_t t = 0; t < T; ++t) rows[t].push_back({(int32_t)t, c128(0.0, k0)});
+    for (int64_t n = 0; n < E; ++n) {
+        int32_t ts[2];
+        double dv[2];
+        for (int s = 0; s < 2; ++s) {
+            ts[s] = m.tpm[2 * n + s];
+            dv[s] = sl[3 * (int64_t)ts[s] + m.epm[2 * n + s]] / m.area[ts[s]];
+        }
+        const c128 w = cdiv(c128(1.0), ad[n]);
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) rows[ts[a]].push_back({ts[b], (dv[a] * dv[b]) * (w * gself[ts[b]])});
+    }
+    std::vector<int64_t> rp(T + 1, 0);
+    std::vector<int32_t> ci;
+    std::vector<c128> val;
+    for (int64_t t = 0; t < T; ++t) {
+        auto &r = rows[t];
+        std::sort(r.begin(), r.end(), [](const std::pair<int32_t, c128> &a, const std::pair<int32_t, c128> &b) {
+            return a.first < b.first;
+        });
+        for (size_t i = 0; i < r.size(); ++i) {
+            if (!ci.empty() && (int64_t)ci.size() > rp[t] && ci.back() == r[i].first) val.back() += r[i].second;
+            else { ci.push_back(r[i].first); val.push_back(r[i].second); }
+        }
+        rp[t + 1] = (int64_t)ci.size();
+        std::vector<std::pair<int32_t, c128>>().swap(r);
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    SparseLUHost h;
+    lu_factor_host(h, T, rp, ci, val, m.centroid);
+    lu_upload(h, A.lu);
+    A.t_factor_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    setup_mark("augmented EFIE: Schur factors");
+}
+
+void aug_product(sie_problem *p, int nb, const c128 *x, c128 *y, hipStream_t st) {
+    SIE_CHECK(p->aug, SIE_ESTATE, "problem not set up for the augmented EFIE");
+    AugState &A = *p->aug;
+    Medium &md = p->ext;
+    Grid &g = *md.grid;
+    const GridView v = view_of(g);
+    const int64_t E = p->mesh.nrwg, T = p->mesh.nt(), ld = E + T;
+    const double k0 = md.k.re;
+    Work<double> &w = work_sel<double>(g);
+    ensure_work(v, w, nb, E);
+    const c128 *u = x;
+    c128 *yu = y;
+    if (nb > 1) {
+        if (A.u.n < (size_t)nb * E) { A.u.alloc((size_t)nb * E); A.yu.alloc((size_t)nb * E); }
+        SIE_HIP(hipMemcpy2DAsync(A.u.p, E * sizeof(c128), x, ld * sizeof(c128), E * sizeof(c128), nb,
+                                 hipMemcpyDeviceToDevice, st));
+        u = A.u.p;
+        yu = A.yu.p;
+    }
+    StageTimer *tm = &p->timer;
+    const bool all = tm->on == 1, csr = tm->on != 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (all) tm->begin(ST_PRODUCT, st, e0);
+    const MediaView<double> mv = media_of<double>(md, false);
+    if (mv.far) {
+        // vector fields from u, the scalar field from the pulse charges
+        if (all) tm->begin(ST_PROJECT, st, e1);
+        launch_tri_sources<double>(v, v.coef64, u, E, nb, w.trisrc.p, st);
+        launch_project<double>(v, v.mom64, w.trisrc.p, w.grid.p, 4, nb, st, x + E, ld);
+        if (all) { tm->end(ST_PROJECT, st, e1); tm->begin(ST_FFT, st, e1); }
+        fft_convolve<double>(v, mv.spec, mv.spec_stride, 4 * nb, 1, 4 * nb, 0, w.grid.p, w.grid.p, w.bufA.p, w.bufB.p,
+                             st);
+        if (all) { tm->end(ST_FFT, st, e1); tm->begin(ST_INTERP, st, e1); }
+        launch_interp<double>(v, v.mom64, w.grid.p, 4, nb, w.tripot.p, st);
+        if (all) tm->end(ST_INTERP, st, e1);
+    } else {
+        launch_zero<double>((int64_t)nb * 5 * v.ntg, w.tripot.p, st);
+    }
+    // near part of the pulse potential joins the interpolated one per triangle
+    launch_tri_near(v.ntg, g.d_pair_ptr.p, g.d_pair_s.p, A.gam64.p, x + E, ld, nb, w.tripot.p, st);
+    if (csr) tm->begin(ST_SPMV, st, e1);
+    if (nb == 1)
+        launch_spmv_far<double>(v, v.coef64, w.tripot.p, A.ks.p, A.alpha.p, A.nA64.p, u, yu, true, st);
+    else
+        launch_spmm_far<double>(v, E, nb, v.coef64, w.tripot.p, A.ks.p, A.alpha.p, A.nA64.p, u, w.xt.p, yu, st);
+    if (csr) tm->end(ST_SPMV, st, e1, ST_SPMV64);
+    launch_continuity(T, p->d_tri_rwg.p, A.sl.p, p->d_area.p, k0, u, E, x + E, ld, y + E, ld, nb, st);
+    if (nb > 1)
+        SIE_HIP(hipMemcpy2DAsync(y, ld * sizeof(c128), yu, E * sizeof(c128), E * sizeof(c128), nb,
+                                 hipMemcpyDeviceToDevice, st));
+    if (all) tm->end(ST_PRODUCT, st, e0);
+}
+
+void cp_apply(sie_problem *p, int nb, const c128 *x, c128 *y, hipStream_t st) {
+    SIE_CHECK(p->aug, SIE_ESTATE, "problem not set up for the augmented EFIE");
+    AugState &A = *p->aug;
+    const int64_t E = p->mesh.nrwg, T = p->mesh.nt(), ld = E + T;
+    const double k0 = p->ext.k.re;
+    if (A.xnd.n < (size_t)nb * T) A.xnd.alloc((size_t)nb * T);
+    launch_cp_pre(T, p->d_tri_rwg.p, A.sl.p, p->d_area.p, k0, A.ad.p, A.lu.iperm.p, x, ld, E, A.xnd.p, nb, st);
+    lu_solve(A.lu, nb, A.xnd.p, st);
+    launch_cp_post(E, T, p->d_tpm.p, p->d_epm.p, A.sl.p, p->d_area.p, A.gself.p, A.ad.p, A.lu.iperm.p, A.xnd.p, x,
+                   ld, y, ld, nb, st);
+}
+
 void problem_setup(sie_problem *p) {
     SIE_CHECK(!p->objs.empty(), SIE_ESTATE, "no objects");
     SIE_HIP(hipSetDevice(p->ctx->device));
@@ -1116,7 +1254,10 @@ void problem_setup(sie_problem *p) {
         p->grids.push_back(std::move(g));
     }
     form_groups(p);
+    if (p->aug_mode == 1) p->aug.reset(new AugState);
+    else p->aug.reset();
     build_medium(p, p->ext);
+    if (p->aug) aug_setup(p);
     for (int i = 0; i < m.nobj; ++i) build_medium(p, p->ints[i]);
     finalize_groups(p);
     setup_mark("groups");

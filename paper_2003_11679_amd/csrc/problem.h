@@ -2,6 +2,7 @@
 #pragma once
 #include "common.h"
 #include "kernels.h"
+#include "sparse_lu.h"
 
 #include <mutex>
 
@@ -62,6 +63,24 @@ struct StageTimer {
     ~StageTimer();
 };
 
+// Augmented EFIE of the exterior medium (Sec. III-E, eq. sys): unknowns
+// [u (E); sigma = c0 rho (T, one pulse per triangle)], continuity rows
+// weighted by A_t / k0, and the constraint preconditioner
+// [j k0 diag(A0), -Dv^T diag(Gam); W Dv, j k0 W] applied through the exact
+// Schur complement S = j k0 I + Dv diag(j k0 A0)^-1 Dv^T diag(Gam).
+struct AugState {
+    DBuf<c128> nA64;     // precorrected vector-potential near values (exterior CSR)
+    DBuf<c128> gam64;    // precorrected pulse integrals per exterior near pair
+    DBuf<c128> adiag;    // direct A0_nn
+    DBuf<c128> gself;    // direct int_t int_t G0 of every triangle
+    DBuf<c128> ad;       // j k0 A0_nn
+    DBuf<c128> ks, alpha;   // [1]: the far part's scalar weight 2 j / k0 and the row factor j k0
+    DBuf<double> sl;     // [T][3] +-l of each triangle edge's RWG function
+    SparseLU lu;         // factors of S
+    DBuf<c128> xnd, u, yu;   // workspaces: Schur right-hand sides, u and y_u of nb > 1 products
+    double t_factor_s = 0.0;
+};
+
 }  // namespace sie
 
 struct sie_problem {
@@ -74,6 +93,8 @@ struct sie_problem {
     bool is_setup = false;
     double t_setup_s = 0;
     double cutoff_factor = 0;       // skin-depth cutoff in skin depths (0: off)
+    int aug_mode = 0;               // augmented EFIE: 1 on, 0 off
+    std::unique_ptr<sie::AugState> aug;   // set up when aug_mode is 1
 
     sie::Mesh mesh;
     std::vector<std::unique_ptr<sie::Grid>> grids;
@@ -103,6 +124,11 @@ struct sie_problem {
 namespace sie {
 
 void problem_setup(sie_problem *p);
+// Augmented exterior product (eq. sys without the GIBC term), x and y
+// [nb][E + T]: y_u = j k0 A0 u - Dv^T Gam0 sigma, y_s = W (Dv u + j k0 sigma).
+void aug_product(sie_problem *p, int nb, const c128 *x, c128 *y, hipStream_t st);
+// Constraint preconditioner y = P^-1 x, x and y [nb][E + T], not aliased.
+void cp_apply(sie_problem *p, int nb, const c128 *x, c128 *y, hipStream_t st);
 template <typename T>
 void matvec(sie_problem *p, Medium &md, sie_op op, int nrhs, const cx<T> *x, cx<T> *y, hipStream_t st);
 // The product of every medium of a group on the group's rows (others not

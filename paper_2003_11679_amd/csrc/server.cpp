@@ -80,6 +80,13 @@ size_t sie::estimate_footprint(const sie_problem *p, int restart, int inner_max_
         if (!p->objs.empty()) transient = std::max(transient, fill_bytes(p->obj_req[i].R, (double)p->objs[i].tri.size() / 3.0));
     }
     b += transient;
+    if (p->aug_mode == 1) {
+        // augmented EFIE: the exterior A0 near values, the pulse integrals per
+        // near pair, the charge unknowns in the outer basis, the Schur factors
+        const double cols = std::min(E, 40.0 * 121.0);
+        b += E * cols * 16.0 + (double)T * std::min((double)T, 27.0 * 121.0) * 16.0;
+        b += (double)T * (2.0 * restart + 1.0) * 16.0 + (double)T * 200.0 * 16.0;
+    }
     const int mi = std::max(restart, std::min(inner_max_iter, 300));
     b += E * ((2.0 * restart + 1.0) + (2.0 * mi + 1.0)) * (16.0 + 8.0);   // outer and nested bases, FP64 + FP32
     b += E * 64.0 * 16.0;                                     // vectors of the solve
@@ -189,7 +196,9 @@ sie_status sie_server_create(sie_ctx *ctx, size_t hbm_budget_bytes, int32_t max_
         if (budget == 0) {
             size_t fr = 0, tot = 0;
             SIE_HIP(hipMemGetInfo(&fr, &tot));
-            budget = (size_t)(0.8 * (double)fr);
+            int dev = 0;
+            SIE_HIP(hipGetDevice(&dev));
+            budget = (size_t)(0.8 * (double)(fr + pool_cached_bytes(dev)));   // cached blocks are free to reuse
         }
         auto *s = new sie_server;
         s->ctx = ctx;

@@ -589,6 +589,8 @@ struct SolveState {
     bool sin_built = false;
     Gmres<double> go64, gi64;
     Gmres<float> go32, gi32;
+    Gmres<double> goa;             // outer solve of the augmented EFIE (unknowns [u; sigma])
+    DBuf<c128> sg;                 // [nrhs][T] charge unknowns sigma = c0 rho of the augmented EFIE
     DBuf<c128> t64[6];
     DBuf<c64> t32[6];
     int64_t matvecs = 0, kmatvecs = 0;   // L-type / K-type products, one per medium and right-hand side
@@ -633,7 +635,7 @@ struct Ops {
     // by side in lock step, each with its own Krylov basis, tolerance and
     // convergence), else one for all of them.
     int nsys = 1;
-    Ops(sie_problem *p_, SolveState &s_, hipStream_t st_, double itol, int imax, int rs, int nb_)
+    Ops(sie_problem *p_, SolveState &s_, hipStream_t st_, double itol, int imax, int rs, int nb_, bool outer = true)
         : p(p_), s(s_), st(st_), E(p_->mesh.nrwg), nb(nb_), NE((int64_t)nb_ * p_->mesh.nrwg), inner_tol(itol),
           inner_max_iter(imax), restart(rs) {
         DBuf<cx<T>> *tb = tmp_of<T>(s);
@@ -647,7 +649,7 @@ struct Ops {
         for (int i = 1; i < nobj && equal; ++i) equal = o0[i + 1] - o0[i] == o0[1] - o0[0];
         nsys = equal ? nobj : 1;
         inner_of<T>(s).init(E / nsys, nb * nsys, nested_dim(restart, imax));
-        outer_of<T>(s).init(E, nb, restart);
+        if (outer) outer_of<T>(s).init(E, nb, restart);
         inner_of<T>(s).tag = sizeof(T) == 8 ? "inner64" : "inner32";
         outer_of<T>(s).tag = sizeof(T) == 8 ? "outer64" : "outer32";
     }
@@ -802,6 +804,66 @@ static std::vector<double> block_residual(Ops<double> &o, const c128 *e, const c
     return out;
 }
 
+// ---------------------------------------------------------------- augmented EFIE
+// Outer operator of eq. sys for x = [u; sigma] per right-hand side (stride
+// E + T): the augmented exterior product minus (K0 - X/2) Z u / eta0 on the
+// first E rows.  With an FP32 operator set, Z u and (K0 - X/2) Z u run in
+// FP32 (as in the GIBC system); the augmented product stays FP64.
+static double eta0_of(const sie_problem *p) { return std::sqrt(p->ext.mu.re / p->ext.eps.re); }
+
+static const c128 *aug_u(Ops<double> &o, const c128 *x, c128 *tmp) {
+    if (o.nb == 1) return x;
+    const int64_t ld = o.E + o.p->mesh.nt();
+    SIE_HIP(hipMemcpy2DAsync(tmp, o.E * sizeof(c128), x, ld * sizeof(c128), o.E * sizeof(c128), o.nb,
+                             hipMemcpyDeviceToDevice, o.st));
+    return tmp;
+}
+
+static void gibc_aug(Ops<double> &o, const c128 *x, c128 *y) {
+    sie_problem *p = o.p;
+    const int64_t E = o.E, ld = E + p->mesh.nt();
+    aug_product(p, o.nb, x, y, o.st);
+    o.count(SIE_OP_L, o.nb);
+    const c128 *u = aug_u(o, x, o.t[5]);
+    if (o.lo) {
+        Ops<float> &l = *o.lo;
+        launch_convert<double, float>(u, l.t[1], o.NE, o.st);
+        l.Z_native(l.t[1], l.t[2]);
+        l.KpX(false, -1.0, l.t[2], l.t[3]);
+        launch_convert<float, double>(l.t[3], o.t[2], o.NE, o.st);
+    } else {
+        o.Z(u, o.t[1]);
+        o.KpX(false, -1.0, o.t[1], o.t[2]);
+    }
+    const c128 a(-1.0 / eta0_of(p));
+    for (int k = 0; k < o.nb; ++k) launch_axpby<double>(E, a, o.t[2] + k * E, c128(1.0), y + k * ld, o.st);
+}
+
+// FP64 residual of the augmented block equations (eq. sys with v kept, and
+// the interior rows of eq. MFIE1dis): r1 [nb][E + T] = ea - [aug(u, sigma) -
+// (K0 - X/2) v / eta0 on the first E rows], r2 = (K_i + X/2) u - Lhat v;
+// returns sqrt(|r1|^2 + |r2|^2) / |ea| per system.
+static std::vector<double> block_residual_aug(Ops<double> &o, Gmres<double> &ga, const c128 *ea, const c128 *xa,
+                                              const c128 *v, c128 *r1, c128 *r2) {
+    sie_problem *p = o.p;
+    const int64_t E = o.E, ld = E + p->mesh.nt();
+    hipStream_t st = o.st;
+    aug_product(p, o.nb, xa, r1, st);
+    o.count(SIE_OP_L, o.nb);
+    o.KpX(false, -1.0, v, o.t[2]);
+    const c128 a(-1.0 / eta0_of(p));
+    for (int k = 0; k < o.nb; ++k) launch_axpby<double>(E, a, o.t[2] + k * E, c128(1.0), r1 + k * ld, st);
+    launch_axpby<double>((int64_t)o.nb * ld, c128(1.0), ea, c128(-1.0), r1, st);
+    const c128 *u = aug_u(o, xa, o.t[5]);
+    o.KpX(true, +1.0, u, r2);
+    o.Lhat(v, o.t[3]);
+    launch_axpby<double>(o.NE, c128(-1.0), o.t[3], c128(1.0), r2, st);
+    const std::vector<double> n1 = ga.norms(r1, st), n2 = o.s.go64.norms(r2, st), ne = ga.norms(ea, st);
+    std::vector<double> out(o.nb);
+    for (int k = 0; k < o.nb; ++k) out[k] = ne[k] > 0.0 ? std::sqrt(n1[k] * n1[k] + n2[k] * n2[k]) / ne[k] : 0.0;
+    return out;
+}
+
 // precond bits: 1 block-Jacobi in the nested solves, 2 block-Jacobi in the
 // outer solve, 4 near-region Schwarz clusters in the nested solves.
 static void build_preconditioners(sie_problem *p, SolveState &s, int precond) {
@@ -828,6 +890,79 @@ static void build_preconditioners(sie_problem *p, SolveState &s, int precond) {
     }
 }
 
+// Refinement sweeps of the augmented EFIE for one batch: the residual of the
+// augmented block equations in FP64, the correction [du; dsigma] from eq. sys
+// (right-preconditioned with the constraint preconditioner) around nested
+// solves as in the GIBC system.  u, v [cnt][E] and sg [cnt][T] receive the
+// solution; res the final relative residuals.
+static void refine_aug(sie_problem *p, SolveState &s, Ops<double> &o64, Ops<float> *o32, sie_precision prec,
+                       const sie_solver_opts &o, const c128 *e, c128 *u, c128 *v, c128 *sg, int cnt,
+                       std::vector<double> &res, int &outer_total, int &sweeps_total) {
+    const int64_t E = o64.E, T = p->mesh.nt(), ld = E + T, NE = o64.NE, NA = (int64_t)cnt * ld;
+    hipStream_t st = o64.st;
+    Gmres<double> &ga = s.goa;
+    ga.init(ld, cnt, o.restart);
+    ga.tag = "outer_aug";
+    s.go64.init(E, cnt, 1);   // norms and scaling of the interior rows
+    DBuf<c128> ea(NA), xa(NA), r1(NA), dx(NA), r2(NE), dv(NE), sv(NE), du(NE);
+    const double ie = 1.0 / eta0_of(p);
+    launch_zero<double>(NA, ea.p, st);
+    for (int k = 0; k < cnt; ++k) launch_axpby<double>(E, c128(ie), e + k * E, c128(0.0), ea.p + k * ld, st);
+    launch_zero<double>(NA, xa.p, st);
+    launch_zero<double>(NE, v, st);
+    std::vector<double> prev(cnt, 2.0);
+    std::vector<char> done(cnt, 0);
+    for (int sw = 0; sw <= o.max_refine; ++sw) {
+        res = block_residual_aug(o64, ga, ea.p, xa.p, v, r1.p, r2.p);
+        bool all = true;
+        std::vector<c128> keep(cnt);
+        for (int k = 0; k < cnt; ++k) {
+            if (!done[k] && (res[k] <= o.tol || sw == o.max_refine || res[k] > 0.5 * prev[k])) done[k] = 1;
+            prev[k] = res[k];
+            keep[k] = c128(done[k] ? 0.0 : 1.0);
+            all = all && done[k];
+        }
+        if (all) break;
+        ++sweeps_total;
+        ga.scale(keep, r1.p, r1.p, st);
+        s.go64.scale(keep, r2.p, r2.p, st);
+        // sv = Lhat^-1 r2 ; the exterior rows take (K0 - X/2) sv / eta0
+        o64.inner_solve(r2.p, sv.p);
+        o64.KpX(false, -1.0, sv.p, o64.t[3]);
+        for (int k = 0; k < cnt; ++k)
+            launch_axpby<double>(E, c128(ie), o64.t[3] + k * E, c128(1.0), r1.p + k * ld, st);
+        launch_zero<double>(NA, dx.p, st);
+        ga.stag_window = prec == SIE_FP32 ? 100 : 0;
+        const double floor32 = std::min(1e-3, std::max(2e-4, 0.63 * std::sqrt(o.tol)));
+        std::vector<double> stol(cnt);
+        for (int k = 0; k < cnt; ++k) {
+            const double need = res[k] > 0.0 ? o.tol / res[k] : 1.0;
+            stol[k] = prec == SIE_FP32 ? std::max(need, floor32) : need;
+        }
+        if (o32 && o.inner_relax > 0.0) {
+            o32->relax_eps.resize(cnt);
+            for (int k = 0; k < cnt; ++k) o32->relax_eps[k] = o.inner_relax * stol[k];
+            o32->relax_res = &ga.live;
+        }
+        outer_total += ga.solve([&](const c128 *x, c128 *y) { gibc_aug(o64, x, y); },
+                                [&](const c128 *x, c128 *y) { cp_apply(p, cnt, x, y, st); }, r1.p, dx.p, stol,
+                                o.max_iter, nullptr, st, nullptr, true);
+        if (o32) o32->relax_res = nullptr;
+        // dv = Lhat^-1 (r2 + (K_i + X/2) du)
+        const c128 *dup = aug_u(o64, dx.p, du.p);
+        o64.KpX(true, +1.0, dup, o64.t[3]);
+        launch_axpby<double>(NE, c128(1.0), r2.p, c128(1.0), o64.t[3], st);
+        o64.inner_solve(o64.t[3], dv.p);
+        launch_axpby<double>(NA, c128(1.0), dx.p, c128(1.0), xa.p, st);
+        launch_axpby<double>(NE, c128(1.0), dv.p, c128(1.0), v, st);
+    }
+    SIE_HIP(hipMemcpy2DAsync(u, E * sizeof(c128), xa.p, ld * sizeof(c128), E * sizeof(c128), cnt,
+                             hipMemcpyDeviceToDevice, st));
+    SIE_HIP(hipMemcpy2DAsync(sg, T * sizeof(c128), xa.p + E, ld * sizeof(c128), T * sizeof(c128), cnt,
+                             hipMemcpyDeviceToDevice, st));
+    SIE_HIP(hipStreamSynchronize(st));   // the batch's buffers are released on return
+}
+
 // Krylov storage of one batch of right-hand sides is kept within this many
 // bytes (outer and nested bases, FP64 plus the FP32 nested copy).
 constexpr double kKrylovBudget = 24e9;
@@ -847,11 +982,16 @@ static void solve_all(sie_problem *p, sie_precision prec, const sie_solver_opts 
     // (2 m + 1 vectors per level: FP64 and FP32 outer with m = restart, FP64
     // and FP32 nested with the nested dimension) would exceed the budget
     const int mi = nested_dim(o.restart, o.inner_max_iter);
-    const double per_rhs = (double)E * ((2.0 * o.restart + 1.0) * (16.0 + 8.0) + (2.0 * mi + 1.0) * (16.0 + 8.0));
+    const bool augm = (bool)p->aug;
+    const int64_t T = p->mesh.nt();
+    const double Eo = augm ? (double)(E + T) : (double)E;   // outer unknowns per right-hand side
+    const double per_rhs = Eo * (2.0 * o.restart + 1.0) * (augm ? 16.0 : 16.0 + 8.0) +
+                           (double)E * (2.0 * mi + 1.0) * (16.0 + 8.0);
+    if (augm && s.sg.n < (size_t)s.nrhs * T) s.sg.alloc((size_t)s.nrhs * T);
     const int nb = (int)std::max(1.0, std::min((double)s.nrhs, std::floor(kKrylovBudget / per_rhs)));
     for (int r0 = 0; r0 < s.nrhs; r0 += nb) {
         const int cnt = std::min(nb, s.nrhs - r0);
-        Ops<double> o64(p, s, st, o.inner_tol, o.inner_max_iter, o.restart, cnt);
+        Ops<double> o64(p, s, st, o.inner_tol, o.inner_max_iter, o.restart, cnt, !augm);
         o64.use_bj_in = (o.precond & 1) != 0;
         o64.use_bj_out = (o.precond & 2) != 0;
         o64.use_ras_in = (o.precond & 4) != 0 && s.sin.nc > 0;
@@ -864,7 +1004,8 @@ static void solve_all(sie_problem *p, sie_precision prec, const sie_solver_opts 
         // below its scalar potential and does not survive FP32).
         std::unique_ptr<Ops<float>> o32;
         if (prec == SIE_FP32) {
-            o32.reset(new Ops<float>(p, s, st, std::max(o.inner_tol, 1e-5), o.inner_max_iter, o.restart, cnt));
+            o32.reset(new Ops<float>(p, s, st, std::max(o.inner_tol, 1e-5), o.inner_max_iter, o.restart, cnt,
+                                     !augm));
             o32->use_bj_in = o64.use_bj_in;
             o32->use_bj_out = o64.use_bj_out;
             o32->use_ras_in = o64.use_ras_in;
@@ -872,8 +1013,13 @@ static void solve_all(sie_problem *p, sie_precision prec, const sie_solver_opts 
         }
         SIE_HIP(hipMemsetAsync(u, 0, NE * sizeof(c128), st));
         SIE_HIP(hipMemsetAsync(v, 0, NE * sizeof(c128), st));
+        std::vector<double> res(cnt, 1.0);
+        if (augm) {
+            refine_aug(p, s, o64, o32.get(), prec, o, e, u, v, s.sg.p + (int64_t)r0 * T, cnt, res, outer_total,
+                       sweeps_total);
+        } else {
         DBuf<c128> r1(NE), r2(NE), du(NE), dv(NE), sv(NE);
-        std::vector<double> prev(cnt, 2.0), res(cnt, 1.0);
+        std::vector<double> prev(cnt, 2.0);
         std::vector<char> done(cnt, 0);
         for (int sw = 0; sw <= o.max_refine; ++sw) {
             res = block_residual(o64, e, u, v, r1.p, r2.p);
@@ -928,6 +1074,7 @@ static void solve_all(sie_problem *p, sie_precision prec, const sie_solver_opts 
             o64.inner_solve(o64.t[3], dv.p);
             launch_axpby<double>(NE, c128(1.0), du.p, c128(1.0), u, st);
             launch_axpby<double>(NE, c128(1.0), dv.p, c128(1.0), v, st);
+        }
         }
         o64.lo = nullptr;
         for (int k = 0; k < cnt; ++k) {

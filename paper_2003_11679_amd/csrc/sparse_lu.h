@@ -1,0 +1,55 @@
+// Exact sparse solver for the Schur complement of the constraint
+// preconditioner: LU factorisation without pivoting, built on the host in
+// FP64 (multifrontal, nested-dissection order), applied on the device level
+// by level of the dissection tree.
+#pragma once
+
+#include "common.h"
+
+namespace sie {
+
+struct SparseLU {
+    int64_t n = 0;                     // unknowns
+    int nsn = 0;                       // supernodes (leaves and separators)
+    int max_sn = 0;                    // largest supernode
+    std::vector<int> lev_ptr;          // supernodes of level l: lev_sn[lev_ptr[l] .. lev_ptr[l + 1])
+    DBuf<int32_t> lev_sn;              // supernode ids grouped by level (leaves first)
+    DBuf<int32_t> sn_p0, sn_n;         // first position and size of each supernode
+    DBuf<int64_t> inv_off;             // offset of a supernode's n x n inverse blocks
+    DBuf<c128> linv, uinv;             // inverses of its unit-lower and upper diagonal blocks
+    DBuf<int64_t> lrow_ptr, urow_ptr;  // off-block entries per position (row) of L and U
+    DBuf<int32_t> lcol, ucol;
+    DBuf<c128> lval, uval;
+    DBuf<int32_t> perm, iperm;         // position -> unknown, unknown -> position
+    int64_t nnz_factor = 0;            // stored off-block entries of L and U
+    double t_factor_s = 0.0;
+};
+
+// The factors on the host (the device copy is SparseLU).
+struct SparseLUHost {
+    int64_t n = 0;
+    std::vector<int> lev_ptr;
+    std::vector<int32_t> lev_sn, sn_p0, sn_n, lcol, ucol, perm, iperm;
+    std::vector<int64_t> inv_off, lrow_ptr, urow_ptr;
+    std::vector<c128> linv, uinv, lval, uval;
+};
+
+// Factor the n x n matrix in CSR (rp, ci sorted per row, val); its pattern
+// must be structurally symmetric.  coords [n][3] place the unknowns in space
+// for the dissection.  Throws SIE_EINVAL when a separator exceeds
+// kLUMaxSupernode unknowns or a pivot vanishes.
+constexpr int kLUMaxSupernode = 1024;
+void lu_factor_host(SparseLUHost &h, int64_t n, const std::vector<int64_t> &rp, const std::vector<int32_t> &ci,
+                    const std::vector<c128> &val, const std::vector<double> &coords);
+void lu_upload(const SparseLUHost &h, SparseLU &f);
+// The device solve's steps on the host, for checking the factors: x [n] in
+// the original numbering, overwritten by the solution.
+void lu_solve_host(const SparseLUHost &h, c128 *x);
+
+// x [nrhs][n] in position order: overwritten by the solution of (LU) x = b.
+void lu_solve(const SparseLU &f, int nrhs, c128 *x, hipStream_t st);
+
+// Device side (k_lu.hip): one workgroup per supernode of a level.
+void launch_lu_level(const SparseLU &f, int level, bool forward, int nrhs, c128 *x, hipStream_t st);
+
+}  // namespace sie

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(_HERE, "libsie.so")
 
 SIE_OK, SIE_EINVAL, SIE_ENOMEM, SIE_EMESH, SIE_EGRID, SIE_ENOCONV, SIE_EDEVICE, SIE_ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, FP32 = 0, 1
-OP_L, OP_K, OP_X = 0, 1, 2
+OP_L, OP_K, OP_X, OP_AUG = 0, 1, 2, 3
 EXTERIOR = -1
 INTERIORS = -2
 
@@ -87,6 +87,7 @@ _CP = ctypes.POINTER(c128)
 SIGNATURES = [
     ("sie_ctx_create", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_VP)]),
     ("sie_ctx_destroy", None, [_VP]),
+    ("sie_ctx_trim", ctypes.c_int, [_VP]),
     ("sie_last_error", ctypes.c_char_p, []),
     ("sie_problem_create", ctypes.c_int, [_VP, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                           ctypes.POINTER(_VP)]),
@@ -101,6 +102,9 @@ SIGNATURES = [
     ("sie_problem_set_quadrature", ctypes.c_int, [_VP, ctypes.POINTER(QuadParams)]),
     ("sie_problem_set_skin_cutoff", ctypes.c_int, [_VP, ctypes.c_double]),
     ("sie_medium_is_local", ctypes.c_int32, [_VP, ctypes.c_int32]),
+    ("sie_problem_set_augmented", ctypes.c_int, [_VP, ctypes.c_int32]),
+    ("sie_problem_augmented_info", ctypes.c_int, [_VP, _I32P, _I64P, _I32P, _DP]),
+    ("sie_constraint_precond", ctypes.c_int, [_VP, ctypes.c_int32, _VP, _VP, _VP]),
     ("sie_problem_setup", ctypes.c_int, [_VP]),
     ("sie_problem_destroy", None, [_VP]),
     ("sie_problem_num_rwg", ctypes.c_int64, [_VP]),
@@ -186,6 +190,10 @@ class Context:
         self.h = h
         self.device = device
 
+    def trim(self):
+        """Free the device memory the library keeps for reuse on this device."""
+        _check(lib().sie_ctx_trim(self.h))
+
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
             _lib.sie_ctx_destroy(self.h)
@@ -236,6 +244,18 @@ class Problem:
 
     def set_skin_cutoff(self, skin_depths=5.0):
         _check(lib().sie_problem_set_skin_cutoff(self.h, float(skin_depths)))
+
+    def set_augmented(self, on=True):
+        """Augmented EFIE for the exterior problem (Sec. III-E), before setup."""
+        _check(lib().sie_problem_set_augmented(self.h, int(bool(on))))
+
+    def augmented_info(self):
+        """(on, Schur factor entries, dissection levels, factorisation seconds)."""
+        on = ctypes.c_int32(); nnz = ctypes.c_int64(); lev = ctypes.c_int32(); t = ctypes.c_double()
+        _check(lib().sie_problem_augmented_info(self.h, ctypes.byref(on), ctypes.byref(nnz), ctypes.byref(lev),
+                                                ctypes.byref(t)))
+        return {"on": bool(on.value), "factor_nnz": int(nnz.value), "levels": int(lev.value),
+                "t_factor_s": float(t.value)}
 
     def setup(self):
         _check(lib().sie_problem_setup(self.h))
@@ -347,6 +367,33 @@ class Problem:
             raise ValueError("x and y must be contiguous vectors of one shape and dtype")
         _check(lib().sie_matvec_noalloc(self.h, medium, op, prec, _VP(x.data_ptr()), _VP(y.data_ptr()),
                                         _stream(stream)))
+        return y
+
+    def aug_matvec(self, x, y=None, stream=None):
+        """Exterior rows of the augmented EFIE (SIE_OP_AUG, FP64) for x of
+        shape [E + T] or [nrhs, E + T] on the device."""
+        import torch
+        x = x.contiguous()
+        if x.dtype != torch.complex128:
+            raise ValueError("the augmented product takes complex128")
+        if y is None:
+            y = torch.empty_like(x)
+        nrhs = 1 if x.dim() == 1 else x.shape[0]
+        _check(lib().sie_matvec(self.h, -1, OP_AUG, FP64, nrhs, _VP(x.data_ptr()), _VP(y.data_ptr()),
+                                _stream(stream)))
+        return y
+
+    def constraint_precond(self, x, y=None, stream=None):
+        """Constraint preconditioner of the augmented EFIE, y = P^-1 x for x of
+        shape [E + T] or [nrhs, E + T] (complex128) on the device."""
+        import torch
+        x = x.contiguous()
+        if x.dtype != torch.complex128:
+            raise ValueError("the constraint preconditioner takes complex128")
+        if y is None:
+            y = torch.empty_like(x)
+        nrhs = 1 if x.dim() == 1 else x.shape[0]
+        _check(lib().sie_constraint_precond(self.h, nrhs, _VP(x.data_ptr()), _VP(y.data_ptr()), _stream(stream)))
         return y
 
     def nested_precond(self, precond, x, y=None, stream=None):

@@ -9,7 +9,8 @@ import pytest
 from workloads import icosphere, box_mesh
 from oracle.rwg import RWGMesh
 from oracle.quad import collapsed_gauss, points_on
-from oracle.aefie import AugmentedProblem, equilibrated_solve
+from oracle.aefie import AugmentedProblem, AugmentedAIM, equilibrated_solve
+from oracle.aim import AIMOperator, Grid
 
 
 @pytest.fixture(scope="module")
@@ -144,3 +145,24 @@ def test_constraint_preconditioner_cuts_iterations(bar_lf):
     n_gibc = gmres(lambda x: G @ x, e / dp.eta0)
     n_cp = gmres(lambda x: A @ x, dp.aug_rhs(e), prec=dp.apply_preconditioner)
     assert n_cp < 0.5 * n_gibc, (n_cp, n_gibc)
+
+
+def test_aim_form_approximates_the_dense_augmented_rows():
+    """AugmentedAIM (near pairs precorrected, pulses through the grid with the
+    triangle moments) against the dense blocks of eq. sys: within the AIM
+    error of a 3-cell near radius; the continuity rows are exact."""
+    xyz, tri = box_mesh((20e-6, 4e-6, 2e-6), (20, 4, 2))
+    m = RWGMesh([(xyz, tri)])
+    dp = AugmentedProblem(m, 10e9, [(1.0, 1.0, 5.8e7)])
+    op = AIMOperator(m, Grid.enclosing(m.xyz, 24), dp.k0, near_radius=3)
+    assert not op.local
+    aa = AugmentedAIM(op)
+    rng = np.random.default_rng(4)
+    E, T = m.nrwg, len(m.tri)
+    x = rng.standard_normal(E + T) + 1j * rng.standard_normal(E + T)
+    got, ref = aa.matvec(x), dp.aug_operator() @ x
+    assert np.linalg.norm(got[:E] - ref[:E]) < 5e-3 * np.linalg.norm(ref[:E])
+    assert np.linalg.norm(got[E:] - ref[E:]) < 1e-14 * np.linalg.norm(ref[E:])
+    s = x[E:]
+    g_aim = aa.NG @ s + aa.pulse_far(s)
+    assert np.linalg.norm(g_aim - dp.Gam0 @ s) < 2e-3 * np.linalg.norm(dp.Gam0 @ s)
