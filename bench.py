@@ -2,29 +2,35 @@
 """Benchmark: SIE matvecs/s and served solves/s of the GIBC/AIM solver on one
 MI355X.
 
-Default workload: the copper bar (100 x 10 x 5 um, sigma 5.8e7 S/m, 20,088
-triangles / 30,132 RWG functions, 10 GHz, 64^3 grid, near region 11 points
-across, interior skin-depth cutoff of 5 skin depths).  One step is one
-complete solve request: mesh topology, grid and stencils, near lists, FP64
-near-field integrals with precorrection, Green's spectra, the plane wave,
-the nested GIBC solve (FP32 interior stages inside FP64 refinement to the
-relative FP64 block residual --tol, default 1e-7; outer restart 1000) and
-the far field.  The FP32 currents of the first warmup request are compared
-with an FP64 solve of the same request (relative error gate 1e-3).  After
-the timed steps one request of the 8 x 8 lossy cube array (196,608
-triangles, 64 interior grids batched into one launch per stage, FP32 +
-refinement to 1e-6) is measured the same way, with its own FP64 gate and
-kernel roofline (--no-cube-array skips it).  --workload cubes and sphere
-time those configurations instead.  The synthetic meshes are generated on
-the host before the timed region; one request's problem is released before
-the next one starts.
+Default workload: the 8 x 8 array of lossy dielectric cubes (edge 0.2
+lambda0, pitch 0.4 lambda0, eps_r ~ U[2,10], sigma ~ U[0,10] S/m; 196,608
+triangles / 294,912 RWG functions, 1 GHz, exterior grid 256^3 with the FFT on
+the live box, one 16^3 grid per cube, near region 11 points across).  One
+step is one complete solve request: mesh topology, grids and stencils, near
+lists, FP64 near-field integrals with precorrection, Green's spectra, the
+factors of the constraint preconditioner, the plane wave, the solve of the
+augmented EFIE (Sec. III-E, eq. sys) with nested GIBC interiors (FP32
+interior stages inside FP64 refinement to the relative FP64 block residual
+--tol, default 1e-6; the 64 interior grids batched into one launch per stage)
+and the far field.  The FP32 currents of the first warmup request are
+compared with an FP64 solve of the same request (relative error gate 1e-3).
+After the timed steps five requests of the copper bar (100 x 10 x 5 um,
+sigma 5.8e7 S/m, 20,088 triangles, 10 GHz, 64^3 grid, interior skin-depth
+cutoff of 5 skin depths, residual 1e-7) are measured the same way, with
+their own FP64 gate and kernel roofline (--no-secondary skips them).
+--workload bar and sphere time those configurations instead (a bar run
+measures one cube-array request after its steps).  The synthetic meshes are
+generated on the host before the timed region; one request's problem is
+released before the next one starts (its device memory stays with the
+library's pool for the next request).
 
 value = SIE matvecs / s over the timed steps: one SIE matvec is one L-type
-AIM product (eq. AIM_Lin) of one medium for one right-hand side; K-type
-products are counted beside it.  Solves/s and p50/p99 request latency are
-reported too.  The roofline object covers the near-field CSR launch class
-with the largest measured time (per medium class and precision), timed with
-HIP events the library records on the stream the kernel runs on.
+AIM product (eq. AIM_Lin) of one medium for one right-hand side (the
+augmented exterior product counts as one); K-type products are counted
+beside it.  Solves/s and p50/p99 request latency are reported too.  The
+roofline object covers the near-field CSR launch class with the largest
+measured time (per medium class and precision), timed with HIP events the
+library records on the stream the kernel runs on.
 """
 import argparse
 import json
@@ -49,8 +55,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=64, help="rows of the oracle's dense matvec sample")
     ap.add_argument("--workload", choices=["bar", "cubes", "sphere", "fft", "batch", "serve", "counters"],
-                    default="bar",
-                    help="bar (default), cubes, sphere: solve requests on the copper bar, cube array or "
+                    default="cubes",
+                    help="cubes (default), bar, sphere: solve requests on the cube array, copper bar or "
                          "dielectric sphere; fft: 4-field 256^3 convolution microbenchmark; "
                          "batch: 64 plane waves solved together on a 4,824-triangle copper bar; "
                          "serve: a Poisson stream of solve requests on the library's server; "
@@ -74,24 +80,35 @@ def parse():
                          "this x (correction target) / (outer residual estimate); 0: fixed tolerance")
     ap.add_argument("--skin-cutoff", type=float, default=5.0,
                     help="skin-depth cutoff of the interior problem in skin depths (Sec. V; 0 off)")
-    ap.add_argument("--no-cube-array", action="store_true",
-                    help="bar workload: skip the single cube-array request measured after the timed steps")
+    ap.add_argument("--augmented", type=int, default=1,
+                    help="request workloads: 1 (default) exterior problem as the augmented EFIE with the "
+                         "constraint preconditioner (Sec. III-E, eq. sys); 0 the GIBC system of the EFIE")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the other configuration measured after the timed steps (bar requests after "
+                         "the cube array, one cube-array request after the bar)")
     ap.add_argument("--precond", type=int, default=None,
                     help="preconditioner bit mask: 1 nested block-Jacobi, 2 outer block-Jacobi, 4 nested "
                          "near-region preconditioner in Schwarz form (conductive media), 8 with 4: for every "
                          "interior medium; default 12 for the cube array, 4 otherwise")
     a = ap.parse_args()
     if a.tol is None:
-        a.tol = 1e-7 if a.workload == "bar" else 1e-6
+        a.tol = DEFAULT_TOL.get(a.workload, 1e-6)
     if a.restart is None:
         a.restart = {"bar": 1000, "cubes": 1000}.get(a.workload, 200)
     if a.precond is None:
-        a.precond = 12 if a.workload == "cubes" else 4
+        a.precond = DEFAULT_PRECOND.get(a.workload, 4)
     return a
 
 
+# per workload: relative FP64 block residual of the solves (the bar's EFIE
+# conditioning turns a 1e-6 residual into ~1e-3 in the currents) and the
+# preconditioner bits (Schwarz clusters for every interior of the cube array)
+DEFAULT_TOL = {"bar": 1e-7, "cubes": 1e-6}
+DEFAULT_PRECOND = {"bar": 4, "cubes": 12}
+
+
 SOLVE_OPTS = {}
-SETUP_OPTS = {"skin_cutoff": 0.0}
+SETUP_OPTS = {"skin_cutoff": 0.0, "augmented": False}
 
 
 def workload_cfg(name):
@@ -116,6 +133,7 @@ def build_problem(cfg):
         for i, o in enumerate(cfg.objects):
             p.set_grid(i, n=o.grid_n or 0, near_radius=cfg.near_radius, share=0)
     p.set_skin_cutoff(SETUP_OPTS["skin_cutoff"])
+    p.set_augmented(SETUP_OPTS["augmented"])
     p.setup()
     return p
 
@@ -325,6 +343,7 @@ def batch_workload(args):
         p.add_object(xyz, tri, eps_r=1.0, sigma=5.8e7)
         p.set_grid(-1, n=32, near_radius=5)
         p.set_skin_cutoff(args.skin_cutoff)
+        p.set_augmented(bool(args.augmented))
         return p
 
     def one(timing=False):
@@ -424,6 +443,7 @@ def serve_workload(args):
             p.add_object(xyz, tri, eps_r=r["eps_r"], sigma=r["sigma"])
             p.set_grid(-1, n=0, near_radius=3)
             p.set_skin_cutoff(args.skin_cutoff)
+            p.set_augmented(bool(args.augmented))
             tickets.append(srv.submit(p, (0.0, 0.0, -1.0), (1.0, 0.0, 0.0), prec, tol=args.tol, restart=100,
                                       precond=args.precond, max_iter=args.max_iter,
                                       inner_max_iter=args.inner_max_iter,
@@ -635,28 +655,41 @@ NAMES = {"cubes": "8x8 array of lossy dielectric cubes (edge 0.2 lambda0, pitch 
                    "(the lambda_r/20 rule of Sec. IV)"}
 
 
-def cube_array_request(args):
-    """One cube-array request after the timed steps (FP32 + refinement to
-    1e-6, nested near-region preconditioner for every cube, outer restart
-    1000), with the near-field kernel roofline and the FP64 gate."""
+def secondary_request(args, name, nreq):
+    """`nreq` requests of another configuration after the timed steps (its
+    default options, FP32 + refinement), with the near-field kernel roofline
+    and the FP64 gate of the first one."""
     import torch
-    cfg = workload_cfg("cubes")
-    opts = dict(restart=1000, precond=12, inner_relax=args.inner_relax)
-    p, rep, su, tot = run_request(cfg, 1, 1e-6, timing=True, opts=opts)
-    st = p.stage_times()
-    model = spmv_classes(p, len(cfg.objects), 1)
-    tm = {k: st[k] for k in ("spmv", "spmv64", "spmv_int32", "spmv_int64")}
-    roof = dominant_kernel(tm, model, 1)
-    roof["traffic"] = spmv_traffic("cubes", roof["class"])
-    print(f"[bench] cube array: setup {su:.2f}s total {tot:.2f}s {rep}", file=sys.stderr, flush=True)
-    gate = fp64_gate(p, 1e-6, dict(opts, inner_relax=0.0))
-    print(f"[bench] cube array fp64 gate: {gate}", file=sys.stderr, flush=True)
-    del p
-    torch.cuda.synchronize()
-    return {"workload": NAMES["cubes"] + ", near radius 5, plane wave -z x-polarised, 1 RHS, FP32 + FP64 "
-                                        "refinement to 1e-6",
-            "request_s": tot, "setup_s": su, "matvecs_per_s": rep["matvecs"] / tot,
-            "k_matvecs_per_s": rep["k_matvecs"] / tot, "converged": rep["converged"], "report": rep,
+    cfg = workload_cfg(name)
+    opts = dict(restart=1000, precond=DEFAULT_PRECOND.get(name, 4), inner_relax=args.inner_relax)
+    tol = DEFAULT_TOL.get(name, 1e-6)
+    tm = {k: [0, 0.0] for k in ("spmv", "spmv64", "spmv_int32", "spmv_int64")}
+    lat, reps, setups, gate, model = [], [], [], None, None
+    for i in range(nreq):
+        p, rep, su, tot = run_request(cfg, 1, tol, timing=True, opts=opts)
+        st = p.stage_times()
+        for k in tm:
+            tm[k][0] += st[k][0]
+            tm[k][1] += st[k][1]
+        if model is None:
+            model = spmv_classes(p, len(cfg.objects), 1)
+        print(f"[bench] {name} request {i}: setup {su:.2f}s total {tot:.2f}s {rep}", file=sys.stderr, flush=True)
+        if i == 0:
+            gate = fp64_gate(p, tol, opts)
+            print(f"[bench] {name} fp64 gate: {gate}", file=sys.stderr, flush=True)
+        del p
+        torch.cuda.synchronize()
+        lat.append(tot); reps.append(rep); setups.append(su)
+    roof = dominant_kernel({k: tuple(v) for k, v in tm.items()}, model, 1)
+    roof["traffic"] = spmv_traffic(name, roof["class"])
+    return {"workload": NAMES[name] + f", near radius {cfg.near_radius}, plane wave -z x-polarised, 1 RHS, "
+                                      f"FP32 + FP64 refinement to {tol:g}"
+                                      + (", augmented EFIE" if SETUP_OPTS["augmented"] else ""),
+            "requests": nreq, "request_s_mean": float(np.mean(lat)), "latency_p50_s": float(np.percentile(lat, 50)),
+            "latency_p99_s": float(np.percentile(lat, 99)), "setup_s_mean": float(np.mean(setups)),
+            "matvecs_per_s": sum(r["matvecs"] for r in reps) / sum(lat),
+            "k_matvecs_per_s": sum(r["k_matvecs"] for r in reps) / sum(lat),
+            "converged": all(r["converged"] for r in reps), "report": reps[-1],
             "roofline": roof, "fp32_vs_fp64": gate}
 
 
@@ -667,6 +700,7 @@ def request_workload(args):
     prec = 1 if args.precision == "fp32" else 0
     SOLVE_OPTS.update(restart=args.restart, precond=args.precond, inner_relax=args.inner_relax)
     SETUP_OPTS["skin_cutoff"] = args.skin_cutoff
+    SETUP_OPTS["augmented"] = bool(args.augmented)
     T = sum(len(o.tri) for o in cfg.objects)
     print(f"[bench] workload {args.workload}: {len(cfg.objects)} objects, {T} triangles, precision "
           f"{args.precision}, warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
@@ -712,7 +746,10 @@ def request_workload(args):
         "dtype": "c64+f64" if prec == 1 else "c128",
         "data": "synthetic",
         "config": {"workload": NAMES[args.workload] + f", near radius {cfg.near_radius}, plane wave -z "
-                               f"x-polarised, 1 RHS, GIBC solve to a relative FP64 residual of {args.tol:g}"
+                               f"x-polarised, 1 RHS, "
+                               + ("augmented EFIE (eq. sys) with nested GIBC interiors" if args.augmented
+                                  else "GIBC system of the EFIE")
+                               + f" solved to a relative FP64 residual of {args.tol:g}"
                                + (f", skin-depth cutoff {args.skin_cutoff:g}" if args.skin_cutoff else ""),
                    "precision": args.precision, "nnz_near_interior": int(model["interior"][1]),
                    "nnz_near_exterior": int(model["exterior64"][1]),
@@ -730,8 +767,11 @@ def request_workload(args):
         "refine_sweeps": reps[-1]["refine_sweeps"],
         "roofline": roof,
     }
-    if args.workload == "bar" and not args.no_cube_array:
-        out["cube_array"] = cube_array_request(args)
+    if not args.no_secondary:
+        if args.workload == "cubes":
+            out["copper_bar"] = secondary_request(args, "bar", 5)
+        elif args.workload == "bar":
+            out["cube_array"] = secondary_request(args, "cubes", 1)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle AIM product, bounded sample)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline_aim(cfg)

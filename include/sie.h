@@ -384,6 +384,10 @@ sie_status sie_solve(sie_problem *p, sie_precision prec, const sie_solver_opts *
                      sie_report *report);
 /* Currents of right-hand side `rhs` (host arrays [E]). */
 sie_status sie_get_currents(const sie_problem *p, int32_t rhs, sie_c128 *u, sie_c128 *v);
+/* Charge unknowns sigma = c0 rho (one pulse per triangle, host array [T]) of
+ * right-hand side `rhs` of an augmented solve (Sec. III-E); SIE_ESTATE if the
+ * problem is not set up augmented or not solved. */
+sie_status sie_get_charges(const sie_problem *p, int32_t rhs, sie_c128 *sigma);
 /* Scattered far-field amplitude F (E_s ~ F exp(-j k0 r)/r) of right-hand side
  * `rhs` in the directions rhat [ndir][3]: F [ndir][3] (host). */
 sie_status sie_far_field(const sie_problem *p, int32_t rhs, int64_t ndir, const double *rhat,

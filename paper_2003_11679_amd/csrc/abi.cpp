@@ -475,6 +475,10 @@ sie_status sie_get_currents(const sie_problem *p, int32_t rhs, sie_c128 *u, sie_
     return guard(ctx_of(p), [&] { currents_entry(p, rhs, u, v); });
 }
 
+sie_status sie_get_charges(const sie_problem *p, int32_t rhs, sie_c128 *sigma) {
+    return guard(ctx_of(p), [&] { charges_entry(p, rhs, sigma); });
+}
+
 sie_status sie_far_field(const sie_problem *p, int32_t rhs, int64_t ndir, const double *rhat, sie_c128 *F) {
     return guard(ctx_of(p), [&] { farfield_entry(p, rhs, ndir, rhat, F); });
 }

@@ -19,28 +19,29 @@ __device__ inline c128 wsum64(c128 v) {
 }
 
 // zeta slot of the interpolation partials: tripot[r][t][4] += sum over the
-// near pairs (t, s) of gam[p] rho[r][s] (precorrected pulse integrals).
-// One wavefront per triangle.
+// near pairs (t, s) of gam[p] rho[r][tris[s]] (precorrected pulse integrals;
+// t, s the grid's own triangle order, rho in the global numbering).  One
+// wavefront per triangle.
 __global__ void k_tri_near(int64_t ntg, const int64_t *__restrict__ pair_ptr, const int32_t *__restrict__ pair_s,
-                           const c128 *__restrict__ gam, const c128 *__restrict__ rho, int64_t ldr,
-                           c128 *__restrict__ tripot) {
+                           const int32_t *__restrict__ tris, const c128 *__restrict__ gam,
+                           const c128 *__restrict__ rho, int64_t ldr, c128 *__restrict__ tripot) {
     const int lane = threadIdx.x & 63;
     const int64_t t = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
     if (t >= ntg) return;
     rho += blockIdx.y * ldr;
     tripot += blockIdx.y * 5 * ntg;
     c128 acc;
-    for (int64_t p = pair_ptr[t] + lane; p < pair_ptr[t + 1]; p += 64) acc += gam[p] * rho[pair_s[p]];
+    for (int64_t p = pair_ptr[t] + lane; p < pair_ptr[t + 1]; p += 64) acc += gam[p] * rho[tris[pair_s[p]]];
     acc = wsum64(acc);
     if (lane == 0) tripot[5 * t + 4] += acc;
 }
 
-void launch_tri_near(int64_t ntg, const int64_t *pair_ptr, const int32_t *pair_s, const c128 *gam, const c128 *rho,
-                     int64_t ldr, int nrhs, c128 *tripot, hipStream_t st) {
+void launch_tri_near(int64_t ntg, const int64_t *pair_ptr, const int32_t *pair_s, const int32_t *tris,
+                     const c128 *gam, const c128 *rho, int64_t ldr, int nrhs, c128 *tripot, hipStream_t st) {
     if (ntg <= 0 || nrhs < 1) return;
     SIE_CHECK(nrhs <= 65535, SIE_EINVAL, "too many right-hand sides");
     hipLaunchKernelGGL(k_tri_near, dim3((unsigned)((ntg + 3) / 4), (unsigned)nrhs), dim3(256), 0, st, ntg, pair_ptr,
-                       pair_s, gam, rho, ldr, tripot);
+                       pair_s, tris, gam, rho, ldr, tripot);
     SIE_HIP(hipGetLastError());
 }
 

@@ -136,7 +136,8 @@ void launch_tri_sources(const GridView &g, const T *tri_coef, const cx<T> *x, in
 // its entry list and reduce with lane shuffles.  grid [F][nlive] with
 // J_c = sum (alpha M1_c - beta_c M0) and (F == 4) Q = sum 2 alpha M0, the
 // RWG divergences; with rho given (augmented EFIE, Sec. III-E), Q = sum
-// rho_t M0 of the pulse charges instead (rho [rhs][ntg], stride ldr).
+// rho_t M0 of the pulse charges instead (rho [rhs][T] in the global triangle
+// numbering, stride ldr; rho_tris maps the view's triangles to it).
 template <typename T>
 __device__ inline T seg_sum(T v, int lpn) {
     for (int off = lpn >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -147,7 +148,7 @@ template <typename T>
 __global__ void k_project(int64_t nnodes, int64_t nlive, const int32_t *__restrict__ node_ptr,
                           const int32_t *__restrict__ ent, const T *__restrict__ mom, const cx<T> *__restrict__ src,
                           cx<T> *__restrict__ grid, int nf, int lpn, int64_t ntg, const cx<T> *__restrict__ rho,
-                          int64_t ldr) {
+                          int64_t ldr, const int32_t *__restrict__ rho_tris) {
     const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t v = gid / lpn;
     src += blockIdx.y * 4 * ntg;           // right-hand side blockIdx.y
@@ -167,7 +168,7 @@ __global__ void k_project(int64_t nnodes, int64_t nlive, const int32_t *__restri
             s[2] += m[2] * al.re - m[0] * by.re; s[3] += m[2] * al.im - m[0] * by.im;
             s[4] += m[3] * al.re - m[0] * bz.re; s[5] += m[3] * al.im - m[0] * bz.im;
             if (rho) {
-                const cx<T> q = rho[t];
+                const cx<T> q = rho[rho_tris[t]];
                 s[6] += m[0] * q.re; s[7] += m[0] * q.im;
             } else {
                 s[6] += m[0] * al.re; s[7] += m[0] * al.im;
@@ -188,7 +189,8 @@ __global__ void k_project(int64_t nnodes, int64_t nlive, const int32_t *__restri
 
 template <typename T>
 void launch_project(const GridView &g, const T *mom, const cx<T> *trisrc, cx<T> *grid, int nfields, int nrhs,
-                    hipStream_t st, const cx<T> *rho, int64_t ldr) {
+                    hipStream_t st, const cx<T> *rho, int64_t ldr, const int32_t *rho_tris) {
+    SIE_CHECK(!rho || rho_tris, SIE_EINVAL, "pulse charges need the view's triangle numbers");
     const int64_t nnodes = g.nnodes();
     if (nrhs < 1) return;
     SIE_CHECK(nrhs <= 65535, SIE_EINVAL, "too many right-hand sides");
@@ -198,7 +200,8 @@ void launch_project(const GridView &g, const T *mom, const cx<T> *trisrc, cx<T> 
     while (lpn < 64 && lpn * 2 <= avg / 2.0) lpn *= 2;
     const int64_t threads = nnodes * lpn;
     hipLaunchKernelGGL(k_project<T>, dim3((unsigned)((threads + 255) / 256), (unsigned)nrhs), dim3(256), 0, st,
-                       nnodes, g.nlive, g.node_ptr, g.node_ent, mom, trisrc, grid, nfields, lpn, g.ntg, rho, ldr);
+                       nnodes, g.nlive, g.node_ptr, g.node_ent, mom, trisrc, grid, nfields, lpn, g.ntg, rho, ldr,
+                       rho_tris);
     SIE_HIP(hipGetLastError());
 }
 
@@ -526,7 +529,7 @@ void launch_x_apply(int64_t E, const int32_t *xptr, const int32_t *xcol, const T
     template void launch_tri_sources<T>(const GridView &, const T *, const cx<T> *, int64_t, int, cx<T> *,      \
                                         hipStream_t);                                                          \
     template void launch_project<T>(const GridView &, const T *, const cx<T> *, cx<T> *, int, int, hipStream_t, \
-                                    const cx<T> *, int64_t);                                                     \
+                                    const cx<T> *, int64_t, const int32_t *);                                    \
     template void launch_interp<T>(const GridView &, const T *, const cx<T> *, int, int, cx<T> *, hipStream_t); \
     template void launch_spmm_far<T>(const GridView &, int64_t, int, const T *, const cx<T> *, const cx<T> *,   \
                                      const cx<T> *, const cx<T> *, const cx<T> *, cx<T> *, cx<T> *, hipStream_t); \

@@ -27,7 +27,7 @@ void launch_tri_sources(const GridView &g, const T *tri_coef, const cx<T> *x, in
                         cx<T> *trisrc, hipStream_t st);
 template <typename T>
 void launch_project(const GridView &g, const T *mom, const cx<T> *trisrc, cx<T> *grid, int nfields, int nrhs,
-                    hipStream_t st, const cx<T> *rho = nullptr, int64_t ldr = 0);
+                    hipStream_t st, const cx<T> *rho = nullptr, int64_t ldr = 0, const int32_t *rho_tris = nullptr);
 template <typename T>
 void launch_interp(const GridView &g, const T *mom, const cx<T> *pot, int nfields, int nrhs, cx<T> *tripot,
                    hipStream_t st);
@@ -47,9 +47,10 @@ void launch_x_apply(int64_t E, const int32_t *xptr, const int32_t *xcol, const T
                     cx<T> *y, hipStream_t st);
 
 // ---- k_aug.hip (augmented EFIE, Sec. III-E; FP64)
-// tripot[r][t][4] += sum over the near pairs (t, s) of gam[p] rho[r][s].
-void launch_tri_near(int64_t ntg, const int64_t *pair_ptr, const int32_t *pair_s, const c128 *gam, const c128 *rho,
-                     int64_t ldr, int nrhs, c128 *tripot, hipStream_t st);
+// tripot[r][t][4] += sum over the near pairs (t, s) of gam[p] rho[r][tris[s]]
+// (t, s the grid's triangles, tris their global numbers).
+void launch_tri_near(int64_t ntg, const int64_t *pair_ptr, const int32_t *pair_s, const int32_t *tris,
+                     const c128 *gam, const c128 *rho, int64_t ldr, int nrhs, c128 *tripot, hipStream_t st);
 // y[r][t] = sum_e sl[t][e] u[r][n_e] / k0 + j A_t sigma[r][t] (weighted continuity rows).
 void launch_continuity(int64_t nt, const int32_t *tri_rwg, const double *sl, const double *area, double k0,
                        const c128 *u, int64_t ldu, const c128 *sg, int64_t lds, c128 *y, int64_t ldy, int nrhs,

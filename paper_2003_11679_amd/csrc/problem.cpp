@@ -1086,7 +1086,7 @@ void aug_product(sie_problem *p, int nb, const c128 *x, c128 *y, hipStream_t st)
         // vector fields from u, the scalar field from the pulse charges
         if (all) tm->begin(ST_PROJECT, st, e1);
         launch_tri_sources<double>(v, v.coef64, u, E, nb, w.trisrc.p, st);
-        launch_project<double>(v, v.mom64, w.trisrc.p, w.grid.p, 4, nb, st, x + E, ld);
+        launch_project<double>(v, v.mom64, w.trisrc.p, w.grid.p, 4, nb, st, x + E, ld, g.d_tris.p);
         if (all) { tm->end(ST_PROJECT, st, e1); tm->begin(ST_FFT, st, e1); }
         fft_convolve<double>(v, mv.spec, mv.spec_stride, 4 * nb, 1, 4 * nb, 0, w.grid.p, w.grid.p, w.bufA.p, w.bufB.p,
                              st);
@@ -1097,7 +1097,7 @@ void aug_product(sie_problem *p, int nb, const c128 *x, c128 *y, hipStream_t st)
         launch_zero<double>((int64_t)nb * 5 * v.ntg, w.tripot.p, st);
     }
     // near part of the pulse potential joins the interpolated one per triangle
-    launch_tri_near(v.ntg, g.d_pair_ptr.p, g.d_pair_s.p, A.gam64.p, x + E, ld, nb, w.tripot.p, st);
+    launch_tri_near(v.ntg, g.d_pair_ptr.p, g.d_pair_s.p, g.d_tris.p, A.gam64.p, x + E, ld, nb, w.tripot.p, st);
     if (csr) tm->begin(ST_SPMV, st, e1);
     if (nb == 1)
         launch_spmv_far<double>(v, v.coef64, w.tripot.p, A.ks.p, A.alpha.p, A.nA64.p, u, yu, true, st);

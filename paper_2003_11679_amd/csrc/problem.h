@@ -175,6 +175,7 @@ void nested_precond_entry(sie_problem *p, int precond, sie_precision prec, int n
                           hipStream_t st);
 int nested_precond_clusters(const sie_problem *p, int64_t *owned);
 void currents_entry(const sie_problem *p, int32_t rhs, sie_c128 *u, sie_c128 *v);
+void charges_entry(const sie_problem *p, int32_t rhs, sie_c128 *sg);
 // Message returned by sie_last_error() on this thread.
 void set_last_error(const std::string &m);
 void farfield_entry(const sie_problem *p, int32_t rhs, int64_t ndir, const double *rhat, sie_c128 *F);

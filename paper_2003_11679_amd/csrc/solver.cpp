@@ -1209,6 +1209,15 @@ void currents_entry(const sie_problem *p, int32_t rhs, sie_c128 *u, sie_c128 *v)
     if (v) SIE_HIP(hipMemcpy(v, p->solve->v.p + rhs * E, E * sizeof(c128), hipMemcpyDeviceToHost));
 }
 
+void charges_entry(const sie_problem *p, int32_t rhs, sie_c128 *sg) {
+    SIE_CHECK(p && p->solve && p->solve->solved, SIE_ESTATE, "no solution");
+    SIE_CHECK(p->aug, SIE_ESTATE, "problem not set up for the augmented EFIE");
+    SIE_CHECK(rhs >= 0 && rhs < p->solve->nrhs, SIE_EINVAL, "rhs out of range");
+    SIE_CHECK(sg, SIE_EINVAL, "NULL output");
+    const int64_t T = p->mesh.nt();
+    SIE_HIP(hipMemcpy(sg, p->solve->sg.p + rhs * T, T * sizeof(c128), hipMemcpyDeviceToHost));
+}
+
 void farfield_entry(const sie_problem *cp, int32_t rhs, int64_t ndir, const double *rhat, sie_c128 *F) {
     sie_problem *p = const_cast<sie_problem *>(cp);
     SIE_CHECK(p && p->solve && p->solve->solved, SIE_ESTATE, "no solution");

@@ -105,6 +105,7 @@ SIGNATURES = [
     ("sie_problem_set_augmented", ctypes.c_int, [_VP, ctypes.c_int32]),
     ("sie_problem_augmented_info", ctypes.c_int, [_VP, _I32P, _I64P, _I32P, _DP]),
     ("sie_constraint_precond", ctypes.c_int, [_VP, ctypes.c_int32, _VP, _VP, _VP]),
+    ("sie_get_charges", ctypes.c_int, [_VP, ctypes.c_int32, _CP]),
     ("sie_problem_setup", ctypes.c_int, [_VP]),
     ("sie_problem_destroy", None, [_VP]),
     ("sie_problem_num_rwg", ctypes.c_int64, [_VP]),
@@ -481,6 +482,13 @@ class Problem:
         u = np.empty((E, 2)); v = np.empty((E, 2))
         _check(lib().sie_get_currents(self.h, rhs, u.ctypes.data_as(_CP), v.ctypes.data_as(_CP)))
         return u[:, 0] + 1j * u[:, 1], v[:, 0] + 1j * v[:, 1]
+
+    def charges(self, rhs=0):
+        """sigma = c0 rho per triangle of an augmented solve."""
+        T = self.num_tri
+        sg = np.empty((T, 2))
+        _check(lib().sie_get_charges(self.h, rhs, sg.ctypes.data_as(_CP)))
+        return sg[:, 0] + 1j * sg[:, 1]
 
     def far_field_angles(self, theta, phi, rhs=0):
         """(E_theta, E_phi) far-field amplitudes at the directions (theta, phi)."""
