@@ -447,7 +447,7 @@ def serve_workload(args):
             tickets.append(srv.submit(p, (0.0, 0.0, -1.0), (1.0, 0.0, 0.0), prec, tol=args.tol, restart=100,
                                       precond=args.precond, max_iter=args.max_iter,
                                       inner_max_iter=args.inner_max_iter,
-                                      inner_relax=args.inner_relax if prec == 1 else 0.0))
+                                      inner_relax=args.inner_relax))
         infos = [None] * len(tickets)
         far = [None] * len(tickets)
         started = [False] * len(tickets)

@@ -109,14 +109,15 @@ typedef struct {
                             others with clusters of 4^3 cells and two cells
                             of overlap.  1 and 4 exclude each other, 8 needs 4
                             (SIE_EINVAL); 0 none (default) */
-    double inner_relax;  /* SIE_FP32 only: relaxed nested tolerance inside each
-                            FP32 correction solve (inexact Krylov relaxation,
-                            Simoncini and Szyld): nested solve j runs to
-                            inner_relax x (correction target) / (current
-                            outer residual estimate), clamped to
-                            [max(inner_tol, 1e-5), 1e-2]; 0 keeps the fixed
-                            tolerance (default).  The FP64 block residual of
-                            every refinement sweep still decides convergence. */
+    double inner_relax;  /* relaxed nested tolerance inside each correction
+                            solve (inexact Krylov relaxation, Simoncini and
+                            Szyld): nested solve j runs to inner_relax x
+                            (correction target) / (current outer residual
+                            estimate), clamped to [t, 1e-2] with t the nested
+                            tolerance (SIE_FP32: max(inner_tol, 1e-5)); 0 keeps
+                            the fixed tolerance (default).  The FP64 block
+                            residual of every refinement sweep still decides
+                            convergence. */
 } sie_solver_opts;
 
 typedef struct {

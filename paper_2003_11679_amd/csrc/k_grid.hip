@@ -286,7 +286,31 @@ void launch_cols16(int64_t nrow, const int64_t *row_ptr, const int32_t *cols, in
 // being that of the row's triangles.  Lanes 0 and 1 load the far-part
 // operands of the row's two triangles before the near-field loop, so that
 // those loads overlap it, and their contributions join the lane sum.
-template <typename T, bool C16>
+typedef float spmv_f4 __attribute__((ext_vector_type(4)));
+typedef int spmv_i2 __attribute__((ext_vector_type(2)));
+
+// Two consecutive FP32 nonzeros from position j (even, counted from arrays
+// whose starts are aligned): both values in one 16-byte load and both column
+// indices in one 4-byte (16-bit offsets) or 8-byte load, so that the lanes of
+// a wave read one contiguous stretch per load; streamed once (non-temporal).
+template <bool C16>
+__device__ inline void load2(const c64 *__restrict__ vals, const int32_t *__restrict__ cols,
+                             const uint16_t *__restrict__ cols16, int32_t base, int64_t j, c64 v[2], int32_t c[2]) {
+    if constexpr (C16) {
+        const unsigned w = __builtin_nontemporal_load(reinterpret_cast<const unsigned *>(cols16 + j));
+        c[0] = base + (int32_t)(w & 0xffffu);
+        c[1] = base + (int32_t)(w >> 16);
+    } else {
+        const spmv_i2 w = __builtin_nontemporal_load(reinterpret_cast<const spmv_i2 *>(cols + j));
+        c[0] = w.x;
+        c[1] = w.y;
+    }
+    const spmv_f4 a = __builtin_nontemporal_load(reinterpret_cast<const spmv_f4 *>(vals + j));
+    v[0] = c64(a.x, a.y);
+    v[1] = c64(a.z, a.w);
+}
+
+template <typename T, bool C16, bool VEC>
 __global__ void k_spmv_far(int64_t nrow, int64_t rwg0, const int64_t *__restrict__ row_ptr,
                            const int32_t *__restrict__ cols, const uint16_t *__restrict__ cols16,
                            const int32_t *__restrict__ row_base, const cx<T> *__restrict__ vals,
@@ -326,6 +350,33 @@ __global__ void k_spmv_far(int64_t nrow, int64_t rwg0, const int64_t *__restrict
             else return __builtin_nontemporal_load(cols + jj);
         };
         cx<T> a1, a2, a3;
+        if constexpr (VEC && sizeof(T) == 4) {
+            // VEC (FP32, aligned array starts): lane l takes the pair of
+            // nonzeros 2 l, 2 l + 1 of each stretch of 128; an odd first or
+            // last nonzero is taken alone
+            const int64_t jb = min(e, (b + 1) & ~(int64_t)1);
+            const int64_t je = max(jb, e & ~(int64_t)1);
+            if (lane == 0 && b < jb) acc += vals[b] * x[col(b)];
+            if (lane == 1 && je < e) a1 += vals[je] * x[col(je)];
+            int64_t j = jb + 2 * lane;
+            for (; j + 128 < je; j += 256) {
+                c64 v[4];
+                int32_t c[4];
+                load2<C16>(reinterpret_cast<const c64 *>(vals), cols, cols16, base, j, v, c);
+                load2<C16>(reinterpret_cast<const c64 *>(vals), cols, cols16, base, j + 128, v + 2, c + 2);
+                acc += v[0] * x[c[0]];
+                a1 += v[1] * x[c[1]];
+                a2 += v[2] * x[c[2]];
+                a3 += v[3] * x[c[3]];
+            }
+            if (j < je) {
+                c64 v[2];
+                int32_t c[2];
+                load2<C16>(reinterpret_cast<const c64 *>(vals), cols, cols16, base, j, v, c);
+                acc += v[0] * x[c[0]];
+                a1 += v[1] * x[c[1]];
+            }
+        } else {
         int64_t j = b + lane;
         for (; j + 192 < e; j += 256) {
             const int32_t c0 = col(j);
@@ -343,6 +394,7 @@ __global__ void k_spmv_far(int64_t nrow, int64_t rwg0, const int64_t *__restrict
             a3 += v3 * x[c3];
         }
         for (; j < e; j += 64) acc += vals[j] * x[col(j)];
+        }
         acc += (a1 + a2) + a3;
     }
     acc = wave_sum(acc);
@@ -356,14 +408,27 @@ void launch_spmv_far(const GridView &g, const T *tri_coef, const cx<T> *tripot, 
     if (nrow <= 0) return;
     const int rows_per_block = 4;
     const dim3 grid((unsigned)((nrow + rows_per_block - 1) / rows_per_block));
-    if (g.c16)
-        hipLaunchKernelGGL((k_spmv_far<T, true>), grid, dim3(256), 0, st, nrow, g.rwg0, g.row_ptr, g.cols, g.cols16,
-                           g.row_base, vals, g.rwgloc, tri_coef, tripot, g.tri_slot, kscal, alpha, x, y,
-                           use_far ? 1 : 0);
-    else
-        hipLaunchKernelGGL((k_spmv_far<T, false>), grid, dim3(256), 0, st, nrow, g.rwg0, g.row_ptr, g.cols, g.cols16,
-                           g.row_base, vals, g.rwgloc, tri_coef, tripot, g.tri_slot, kscal, alpha, x, y,
-                           use_far ? 1 : 0);
+    // paired loads: FP32 values, value and index arrays that start aligned
+    // (a medium's values viewed inside a group's array may not)
+    const bool vec = sizeof(T) == 4 && ((uintptr_t)vals % 16 == 0) &&
+                     (g.c16 ? (uintptr_t)g.cols16 % 4 == 0 : (uintptr_t)g.cols % 8 == 0);
+#define SIE_SPMV(C, V)                                                                                              \
+    hipLaunchKernelGGL((k_spmv_far<T, C, V>), grid, dim3(256), 0, st, nrow, g.rwg0, g.row_ptr, g.cols, g.cols16,     \
+                       g.row_base, vals, g.rwgloc, tri_coef, tripot, g.tri_slot, kscal, alpha, x, y, use_far ? 1 : 0)
+    if constexpr (sizeof(T) == 4) {
+        if (g.c16) {
+            if (vec) SIE_SPMV(true, true);
+            else SIE_SPMV(true, false);
+        } else {
+            if (vec) SIE_SPMV(false, true);
+            else SIE_SPMV(false, false);
+        }
+    } else {
+        (void)vec;
+        if (g.c16) SIE_SPMV(true, false);
+        else SIE_SPMV(false, false);
+    }
+#undef SIE_SPMV
     SIE_HIP(hipGetLastError());
 }
 

@@ -890,6 +890,22 @@ static void build_preconditioners(sie_problem *p, SolveState &s, int precond) {
     }
 }
 
+// Relaxed nested tolerances inside one correction solve (res: the outer
+// solve's residual estimates; null ends the relaxation).  The nested solves
+// run in the FP32 operator set when there is one, else in the FP64 one.
+static void set_relax(Ops<double> &o64, Ops<float> *o32, double relax, const std::vector<double> &stol,
+                      const std::vector<double> *res) {
+    std::vector<double> eps(stol.size());
+    for (size_t k = 0; k < stol.size(); ++k) eps[k] = relax * stol[k];
+    if (o32) {
+        o32->relax_eps = eps;
+        o32->relax_res = res;
+    } else {
+        o64.relax_eps = eps;
+        o64.relax_res = res;
+    }
+}
+
 // Refinement sweeps of the augmented EFIE for one batch: the residual of the
 // augmented block equations in FP64, the correction [du; dsigma] from eq. sys
 // (right-preconditioned with the constraint preconditioner) around nested
@@ -939,15 +955,11 @@ static void refine_aug(sie_problem *p, SolveState &s, Ops<double> &o64, Ops<floa
             const double need = res[k] > 0.0 ? o.tol / res[k] : 1.0;
             stol[k] = prec == SIE_FP32 ? std::max(need, floor32) : need;
         }
-        if (o32 && o.inner_relax > 0.0) {
-            o32->relax_eps.resize(cnt);
-            for (int k = 0; k < cnt; ++k) o32->relax_eps[k] = o.inner_relax * stol[k];
-            o32->relax_res = &ga.live;
-        }
+        if (o.inner_relax > 0.0) set_relax(o64, o32, o.inner_relax, stol, &ga.live);
         outer_total += ga.solve([&](const c128 *x, c128 *y) { gibc_aug(o64, x, y); },
                                 [&](const c128 *x, c128 *y) { cp_apply(p, cnt, x, y, st); }, r1.p, dx.p, stol,
                                 o.max_iter, nullptr, st, nullptr, true);
-        if (o32) o32->relax_res = nullptr;
+        set_relax(o64, o32, 0.0, stol, nullptr);
         // dv = Lhat^-1 (r2 + (K_i + X/2) du)
         const c128 *dup = aug_u(o64, dx.p, du.p);
         o64.KpX(true, +1.0, dup, o64.t[3]);
@@ -1059,15 +1071,11 @@ static void solve_all(sie_problem *p, sie_precision prec, const sie_solver_opts 
                 const double need = res[k] > 0.0 ? o.tol / res[k] : 1.0;
                 stol[k] = prec == SIE_FP32 ? std::max(need, floor32) : need;
             }
-            if (o32 && o.inner_relax > 0.0) {
-                o32->relax_eps.resize(cnt);
-                for (int k = 0; k < cnt; ++k) o32->relax_eps[k] = o.inner_relax * stol[k];
-                o32->relax_res = &g.live;
-            }
+            if (o.inner_relax > 0.0) set_relax(o64, o32.get(), o.inner_relax, stol, &g.live);
             outer_total += g.solve([&](const c128 *x, c128 *y) { o64.gibc(x, y); },
                                    [&](const c128 *x, c128 *y) { o64.prec_outer(x, y); }, r1.p, du.p, stol,
                                    o.max_iter, nullptr, st, nullptr, true);
-            if (o32) o32->relax_res = nullptr;
+            set_relax(o64, o32.get(), 0.0, stol, nullptr);
             // dv = Lhat^-1 (r2 + (K_i + X/2) du)
             o64.KpX(true, +1.0, du.p, o64.t[3]);
             launch_axpby<double>(NE, c128(1.0), r2.p, c128(1.0), o64.t[3], st);
