@@ -265,8 +265,10 @@ struct Gmres {
                 launch_gemv_sys<T>(n, j + 1, V.p, blk, nb, d2, m + 1, w.p, false, st);
                 dots_dev(1, w.p, w.p, 2, st);
                 const bool read_b = pending && j == 0;
-                SIE_HIP(hipMemcpyAsync(hh.p, hd.p, (read_b ? 4 : 3) * sl * sizeof(c128), hipMemcpyDeviceToHost,
-                                       st));
+                // the first j + 1 entries of each system's rows of the slots
+                // (all the host reads), not the whole [nb][m + 1] slots
+                SIE_HIP(hipMemcpy2DAsync(hh.p, ld * sizeof(c128), hd.p, ld * sizeof(c128), (j + 1) * sizeof(c128),
+                                         (size_t)(read_b ? 4 : 3) * nb, hipMemcpyDeviceToHost, st));
                 wait(st);
                 c128 *h1 = hh.p;
                 const c128 *h2 = hh.p + sl, *h3 = hh.p + 2 * sl;
@@ -346,7 +348,8 @@ struct Gmres {
                         yk[i] = cdiv(sacc, Hk[(size_t)i * m + i]);
                     }
                 }
-                SIE_HIP(hipMemcpyAsync(hd.p, y, sl * sizeof(c128), hipMemcpyHostToDevice, st));
+                SIE_HIP(hipMemcpy2DAsync(hd.p, ld * sizeof(c128), y, ld * sizeof(c128), kmax * sizeof(c128), nb,
+                                         hipMemcpyHostToDevice, st));
                 SIE_HIP(hipEventRecord(hy_done, st));
                 launch_gemv_sys<T>(n, kmax, Zb.p, blk, nb, hd.p, m + 1, x, true, st);
             }
