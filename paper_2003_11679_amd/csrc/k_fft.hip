@@ -478,6 +478,9 @@ template <typename T> struct FftShape {
     static constexpr int nt = 512;
     static constexpr int vpt = sizeof(T) == 4 ? 16 : 8;
     static constexpr int minw = 4;
+    static constexpr int z_nt = 256;
+    static constexpr int z_vpt = sizeof(T) == 4 ? 16 : 8;
+    static constexpr int z_minw = 4;
     static constexpr int grad_nt = 256;
     static constexpr int grad_vpt = 8;
     static constexpr int grad_minw = sizeof(T) == 4 ? 2 : 1;
@@ -587,7 +590,7 @@ static void zpass_lg(int lg, const GridView &g, const cx<T> *spec, long spec_str
         check_span((long)nz * my * mx);
         SIE_CHECK(nz <= mz / 2, SIE_EGRID, "z live extent above half the FFT length");
         if (mode == 0) {
-            constexpr int NT = FftShape<T>::nt, V = FftShape<T>::vpt, W = FftShape<T>::minw;
+            constexpr int NT = FftShape<T>::z_nt, V = FftShape<T>::z_vpt, W = FftShape<T>::z_minw;
             using TS = Tile<T, NT, V, LGL>;
             check_tile<TS>();
             const int cpr = (fps + kZFields - 1) / kZFields;
