@@ -67,6 +67,15 @@ void *pool_alloc(size_t bytes);
 void pool_free(void *p);
 size_t pool_cached_bytes(int device);
 void pool_trim(int device);
+// While one is alive, pool_free on this host thread skips its device-wide
+// synchronisation: the caller has completed every piece of work that used
+// the blocks it frees.
+struct PoolSyncedFree {
+    PoolSyncedFree();
+    ~PoolSyncedFree();
+    PoolSyncedFree(const PoolSyncedFree &) = delete;
+    PoolSyncedFree &operator=(const PoolSyncedFree &) = delete;
+};
 
 // ---------------------------------------------------------------- device buffer
 // Owns its device memory, or (view) refers to a slice of another DBuf's.
@@ -111,6 +120,13 @@ struct DBuf {
         if (count) SIE_HIP(hipMemcpy(p, h, count * sizeof(T), hipMemcpyHostToDevice));
     }
     void upload(const std::vector<T> &v) { upload(v.data(), v.size()); }
+    // Ordered on stream st; returns once the copy is complete.
+    void upload(const std::vector<T> &v, hipStream_t st) {
+        if (v.size() > n) alloc(v.size());
+        if (v.empty()) return;
+        SIE_HIP(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+        SIE_HIP(hipStreamSynchronize(st));
+    }
     std::vector<T> download(size_t count) const {
         std::vector<T> h(count);
         if (count) SIE_HIP(hipMemcpy(h.data(), p, count * sizeof(T), hipMemcpyDeviceToHost));

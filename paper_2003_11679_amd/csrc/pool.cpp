@@ -53,7 +53,12 @@ void release_cached(Pool &P, int dev) {
     P.cached_bytes[dev] = 0;
 }
 
+thread_local int t_synced = 0;
+
 }  // namespace
+
+PoolSyncedFree::PoolSyncedFree() { ++t_synced; }
+PoolSyncedFree::~PoolSyncedFree() { --t_synced; }
 
 void *pool_alloc(size_t bytes) {
     if (!bytes) return nullptr;
@@ -102,8 +107,8 @@ void pool_free(void *q) {
     (void)hipGetDevice(&cur);
     if (cur != b.device) (void)hipSetDevice(b.device);
     // as hipFree does: work of any stream that may still use the block ends
-    // before it can be handed out again
-    (void)hipDeviceSynchronize();
+    // before it can be handed out again (unless the caller has completed it)
+    if (!t_synced) (void)hipDeviceSynchronize();
     std::lock_guard<std::mutex> lk(P.mu);
     if (!P.cap.count(b.device)) {
         size_t fr = 0, tot = 0;

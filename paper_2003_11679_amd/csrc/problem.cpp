@@ -18,7 +18,11 @@
 #include <cmath>
 #include <numeric>
 
+#include <atomic>
 #include <chrono>
+#include <exception>
+#include <mutex>
+#include <thread>
 #include <cstdio>
 #include <cstdlib>
 
@@ -123,6 +127,8 @@ static void build_grid_geometry(sie_problem *p, Grid &g, const GridReq &req, con
 static void setup_mark(const char *what) {
     static const bool trace = std::getenv("SIE_TRACE") != nullptr;
     if (!trace) return;
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lk(mu);
     static auto last = std::chrono::steady_clock::now();
     SIE_HIP(hipDeviceSynchronize());
     const auto now = std::chrono::steady_clock::now();
@@ -319,7 +325,7 @@ static void keep_or_alloc(DBuf<T> &b, size_t n) {
 }
 
 // Precorrected near values and Green's spectra of one medium on its grid.
-static void build_medium(sie_problem *p, Medium &md) {
+static void build_medium(sie_problem *p, Medium &md, hipStream_t st) {
     Grid &g = *md.grid;
     const int64_t ntg = (int64_t)g.tris.size();
     // rules: 0 self, 1..3 edge, 4..6 vertex, 7 close, 8 far, 9 touch inner, 10 close inner, 11 far inner
@@ -341,22 +347,22 @@ static void build_medium(sie_problem *p, Medium &md) {
         auto v = pack_rule(r);
         packed.insert(packed.end(), v.begin(), v.end());
     }
-    DBuf<double> d_rules; d_rules.upload(packed);
-    DBuf<int> d_off; d_off.upload(off);
-    DBuf<int> d_num; d_num.upload(num);
+    DBuf<double> d_rules; d_rules.upload(packed, st);
+    DBuf<int> d_off; d_off.upload(off, st);
+    DBuf<int> d_num; d_num.upload(num, st);
     // radial Green's tables over squared node offsets of near pairs:
     // |d| <= R + 2 per axis
     const int W = g.near_radius + 2;
     const int nq = 3 * W * W + 1;
     DBuf<c128> d_grad(2 * nq);
-    launch_green_radial(md.k, g.h, nq, d_grad.p, 0);
+    launch_green_radial(md.k, g.h, nq, d_grad.p, st);
     // strong-loss inner scheme: 8-point Gauss-Legendre on [-1, 1]
     std::vector<double> glx, glw, gl;
     gauss_legendre01(8, glx, glw);
     for (double x : glx) gl.push_back(2.0 * x - 1.0);
     for (double w : glw) gl.push_back(2.0 * w);
     DBuf<double> d_gl;
-    d_gl.upload(gl);
+    d_gl.upload(gl, st);
     // strong-loss scheme: lossy enough a medium (|Im k| >= 0.38 |k|) and, for
     // some source triangle, |Im k| times its longest edge above 2 (the
     // per-pair test on the device; 1 % margin here so none is missed)
@@ -384,17 +390,17 @@ static void build_medium(sie_problem *p, Medium &md) {
         A.gam64.alloc(std::max<int64_t>(g.npairs, 1));
         A.adiag.alloc(std::max<int64_t>(g.rwg1 - g.rwg0, 1));
         A.gself.alloc(std::max<int64_t>(ntg, 1));
-        SIE_HIP(hipMemset(A.nA64.p, 0, A.nA64.bytes()));
-        SIE_HIP(hipMemset(A.adiag.p, 0, A.adiag.bytes()));
-        SIE_HIP(hipMemset(A.gself.p, 0, A.gself.bytes()));
+        SIE_HIP(hipMemsetAsync(A.nA64.p, 0, A.nA64.bytes(), st));
+        SIE_HIP(hipMemsetAsync(A.adiag.p, 0, A.adiag.bytes(), st));
+        SIE_HIP(hipMemsetAsync(A.gself.p, 0, A.gself.bytes(), st));
     }
     const int bstride = aug ? 45 : 27;
     keep_or_alloc(md.d_nL64, std::max<int64_t>(g.nnz, 1));
     keep_or_alloc(md.d_nK64, std::max<int64_t>(g.nnz, 1));
     md.d_nLd64.alloc(std::max<int64_t>(g.nnz, 1));
-    SIE_HIP(hipMemset(md.d_nL64.p, 0, md.d_nL64.bytes()));
-    SIE_HIP(hipMemset(md.d_nK64.p, 0, md.d_nK64.bytes()));
-    SIE_HIP(hipMemset(md.d_nLd64.p, 0, md.d_nLd64.bytes()));
+    SIE_HIP(hipMemsetAsync(md.d_nL64.p, 0, md.d_nL64.bytes(), st));
+    SIE_HIP(hipMemsetAsync(md.d_nK64.p, 0, md.d_nK64.bytes(), st));
+    SIE_HIP(hipMemsetAsync(md.d_nLd64.p, 0, md.d_nLd64.bytes(), st));
     // process row triangles in chunks to bound the pair-block buffer
     setup_mark("medium: alloc + clear");
     std::vector<int64_t> pptr = g.d_pair_ptr.download();
@@ -412,7 +418,7 @@ static void build_medium(sie_problem *p, Medium &md) {
         NearFillArgs a{};
         a.xyz = p->d_xyz.p; a.tri = p->d_tri.p; a.tris = g.d_tris.p; a.centroid = p->d_centroid.p;
         a.pair_ptr = g.d_pair_ptr.p; a.pair_s = g.d_pair_s.p; a.ntg = ntg;
-        launch_pair_kinds(a, g.d_pair_kind.p, 0);
+        launch_pair_kinds(a, g.d_pair_kind.p, st);
         setup_mark("fill: pair kinds");
     }
     int64_t t0 = 0;
@@ -423,7 +429,7 @@ static void build_medium(sie_problem *p, Medium &md) {
         // chunk-relative pair pointers over all rows (rows outside the chunk empty)
         std::vector<int64_t> cp(ntg + 1);
         for (int64_t i = 0; i <= ntg; ++i) cp[i] = std::min(std::max(pptr[i], pptr[t0]), pptr[t1]) - pptr[t0];
-        d_pp.upload(cp);
+        d_pp.upload(cp, st);
         blocks.alloc(std::max<int64_t>(np, 1) * bstride);
         setup_mark("fill: chunk buffers");
         NearFillArgs a;
@@ -444,49 +450,55 @@ static void build_medium(sie_problem *p, Medium &md) {
         if (!md.local) {
             ptab.alloc((t1 - t0) * tab_row);
             a.ptab = ptab.p;
-            launch_precorr_table(a, t0, t1 - t0, ptab.p, 0);
+            launch_precorr_table(a, t0, t1 - t0, ptab.p, st);
         } else {
             a.ptab = nullptr;
         }
         setup_mark("fill: precorrection tables");
-        launch_near_fill(a, np, 0);
+        launch_near_fill(a, np, st);
         setup_mark("fill: pair blocks");
         launch_near_gather(nrow, g.rwg0, g.max_row, g.d_row_ptr.p, g.d_cols.p, g.d_rwgloc.p, g.d_glob2loc.p,
                            p->d_tpm.p, p->d_epm.p, d_pp.p, g.d_pair_s.p + pptr[t0], blocks.p, bstride,
                            md.d_nL64.p, md.d_nK64.p, md.d_nLd64.p, aug ? p->aug->nA64.p : nullptr,
-                           aug ? p->aug->adiag.p : nullptr, 0);
-        SIE_HIP(hipStreamSynchronize(0));
+                           aug ? p->aug->adiag.p : nullptr, st);
+        SIE_HIP(hipStreamSynchronize(st));
         t0 = t1;
     }
     setup_mark("medium: near fill");
     keep_or_alloc(md.d_nL32, std::max<int64_t>(g.nnz, 1));
     keep_or_alloc(md.d_nK32, std::max<int64_t>(g.nnz, 1));
-    launch_convert<double, float>(md.d_nL64.p, md.d_nL32.p, g.nnz, 0);
-    launch_convert<double, float>(md.d_nK64.p, md.d_nK32.p, g.nnz, 0);
+    launch_convert<double, float>(md.d_nL64.p, md.d_nL32.p, g.nnz, st);
+    launch_convert<double, float>(md.d_nK64.p, md.d_nK32.p, g.nnz, st);
     // spectra of G, dG/dx, dG/dy, dG/dz, folded to the octant, 1/(mx my mz) folded in
     setup_mark("medium: FP32 copies");
+    DBuf<c128> d_vol, d_tmp;
     if (!md.local) {   // a medium without grid part needs no spectra
         const int64_t vol = g.mvol();
-        DBuf<c128> d_vol(vol), d_tmp(vol);
+        d_vol.alloc(vol);
+        d_tmp.alloc(vol);
         md.d_spec64.alloc(4 * g.oct());
         md.d_spec32.alloc(4 * g.oct());
         const double scale = 1.0 / (double)vol;
         for (int kind = 0; kind < 4; ++kind) {
-            launch_green_sample(md.k, g.h, g.nl, g.m, kind, d_vol.p, 0);
-            fft3d_full_fwd(d_vol.p, d_tmp.p, g.m[0], g.m[1], g.m[2], 0);
-            launch_fold_octant(d_vol.p, g.m, kind, scale, md.d_spec64.p, md.d_spec32.p, 0);
+            launch_green_sample(md.k, g.h, g.nl, g.m, kind, d_vol.p, st);
+            fft3d_full_fwd(d_vol.p, d_tmp.p, g.m[0], g.m[1], g.m[2], st);
+            launch_fold_octant(d_vol.p, g.m, kind, scale, md.d_spec64.p, md.d_spec32.p, st);
         }
     }
-    SIE_HIP(hipStreamSynchronize(0));
+    SIE_HIP(hipStreamSynchronize(st));
     setup_mark("medium: spectra");
     // per-medium scalars of the products: -2 k^-2 (scalar term of L) and the
     // nested operator's factor -j w eps~
     const c128 ks = cdiv(c128(-2.0), md.k * md.k);
     const c128 al = c128(0.0, -p->w) * md.eps;
-    md.d_ks64.upload(std::vector<c128>{ks});
-    md.d_ks32.upload(std::vector<c64>{c64((float)ks.re, (float)ks.im)});
-    md.d_alpha64.upload(std::vector<c128>{al});
-    md.d_alpha32.upload(std::vector<c64>{c64((float)al.re, (float)al.im)});
+    md.d_ks64.upload(std::vector<c128>{ks}, st);
+    md.d_ks32.upload(std::vector<c64>{c64((float)ks.re, (float)ks.im)}, st);
+    md.d_alpha64.upload(std::vector<c128>{al}, st);
+    md.d_alpha32.upload(std::vector<c64>{c64((float)al.re, (float)al.im)}, st);
+    // every launch that used the temporaries has completed on st
+    PoolSyncedFree synced;
+    d_rules.release(); d_off.release(); d_num.release(); d_grad.release(); d_gl.release();
+    blocks.release(); ptab.release(); d_pp.release(); d_vol.release(); d_tmp.release();
 }
 
 // Groups of interior media for batched products: consecutive objects whose
@@ -1123,6 +1135,9 @@ void cp_apply(sie_problem *p, int nb, const c128 *x, c128 *y, hipStream_t st) {
                    ld, y, ld, nb, st);
 }
 
+// Host threads that build interior media concurrently.
+constexpr int kBuildThreads = 8;
+
 void problem_setup(sie_problem *p) {
     SIE_CHECK(!p->objs.empty(), SIE_ESTATE, "no objects");
     SIE_HIP(hipSetDevice(p->ctx->device));
@@ -1256,9 +1271,40 @@ void problem_setup(sie_problem *p) {
     form_groups(p);
     if (p->aug_mode == 1) p->aug.reset(new AugState);
     else p->aug.reset();
-    build_medium(p, p->ext);
+    build_medium(p, p->ext, 0);
     if (p->aug) aug_setup(p);
-    for (int i = 0; i < m.nobj; ++i) build_medium(p, p->ints[i]);
+    // interior media are independent: several host threads build them, each
+    // on a stream of its own, so that their fills (many small launches per
+    // medium) overlap on the device
+    SIE_HIP(hipDeviceSynchronize());
+    {
+        const int nthr = std::max(1, std::min(kBuildThreads, m.nobj));
+        std::atomic<int> next{0};
+        std::exception_ptr err;
+        std::mutex emu;
+        auto work = [&]() {
+            hipStream_t st = nullptr;
+            try {
+                SIE_HIP(hipSetDevice(p->ctx->device));
+                SIE_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+                for (int i = next.fetch_add(1); i < m.nobj; i = next.fetch_add(1)) build_medium(p, p->ints[i], st);
+                SIE_HIP(hipStreamSynchronize(st));
+            } catch (...) {
+                std::lock_guard<std::mutex> lk(emu);
+                if (!err) err = std::current_exception();
+                next.store(m.nobj);
+            }
+            if (st) {
+                (void)hipStreamSynchronize(st);
+                (void)hipStreamDestroy(st);
+            }
+        };
+        std::vector<std::thread> th;
+        for (int t = 1; t < nthr; ++t) th.emplace_back(work);
+        work();
+        for (auto &t : th) t.join();
+        if (err) std::rethrow_exception(err);
+    }
     finalize_groups(p);
     setup_mark("groups");
     p->is_setup = true;
