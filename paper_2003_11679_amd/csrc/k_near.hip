@@ -405,9 +405,25 @@ __device__ inline int classify(const NearFillArgs &a, int64_t tg, int64_t sg, in
 // the test-node sums of tl from a.ptab (k_precorr_table); gr: radial tables
 // in LDS, gr[2 q] = G(h sqrt(q)), gr[2 q + 1] = -(1 + j k r) exp(-j k r)/(4 pi
 // r^3) at r = h sqrt(q), q = |d|^2 (0 at q = 0).
-template <bool POLAR>
+// G > 1: G consecutive lanes (aligned, in one wavefront, all active) share
+// the pair; lane sub of the group takes the outer points sub, sub + G, ...,
+// the group's partial sums are added by butterfly exchanges, and lane 0
+// finishes the pair alone.
+__device__ inline void group_sum(c128 &v, int G) {
+    for (int off = G >> 1; off > 0; off >>= 1) {
+        v.re += __shfl_xor(v.re, off, 64);
+        v.im += __shfl_xor(v.im, off, 64);
+    }
+}
+__device__ inline void group_sum(CV3 &v, int G) {
+    group_sum(v.x, G);
+    group_sum(v.y, G);
+    group_sum(v.z, G);
+}
+
+template <bool POLAR, int G = 1>
 __device__ void fill_pair(const NearFillArgs &a, int64_t tl, int64_t sl, int64_t p, int kind, int loc,
-                          const c128 *gr) {
+                          const c128 *gr, int sub = 0) {
     const int64_t tg = a.tris[tl], sg = a.tris[sl];
     const V3 o = {a.centroid[3 * tg], a.centroid[3 * tg + 1], a.centroid[3 * tg + 2]};
     V3 pt[3], ps[3];
@@ -445,7 +461,7 @@ __device__ void fill_pair(const NearFillArgs &a, int64_t tl, int64_t sl, int64_t
 
     c128 aRV, aS;
     CV3 aV = {}, aSR = {}, aGR = {}, aG = {};
-    for (int qo = 0; qo < no; ++qo) {
+    for (int qo = sub; qo < no; qo += G) {
         const V3 r = Ro[4 * qo] * pt[0] + Ro[4 * qo + 1] * pt[1] + Ro[4 * qo + 2] * pt[2];
         const double W = Ro[4 * qo + 3] * At;
         c128 S;
@@ -488,6 +504,15 @@ __device__ void fill_pair(const NearFillArgs &a, int64_t tl, int64_t sl, int64_t
         const CV3 gxr = ccross_cv(Gv, r);   // Gv x r
         cadd(aGR, CV3{W * gxr.x, W * gxr.y, W * gxr.z});
         cadd(aG, CV3{W * Gv.x, W * Gv.y, W * Gv.z});
+    }
+    if (G > 1) {
+        group_sum(aRV, G);
+        group_sum(aS, G);
+        group_sum(aV, G);
+        group_sum(aSR, G);
+        group_sum(aGR, G);
+        group_sum(aG, G);
+        if (sub != 0) return;
     }
 
     // precorrection: grid contribution of the pair over the 27 x 27 stencil
@@ -699,16 +724,18 @@ __global__ void __launch_bounds__(128, POLAR ? 1 : 2) k_near_fill_far(NearFillAr
     }
 }
 
-// Listed (touching / close) pairs of one kind: one thread per pair.
-template <bool POLAR>
+// Listed (touching / close) pairs of one kind: G consecutive threads per
+// pair (G = 1, 2, 4, 8 or 16).
+template <bool POLAR, int G>
 __global__ void __launch_bounds__(128, POLAR ? 1 : 2) k_near_fill_list(NearFillArgs a, int64_t ntg, const int64_t *list, int64_t n,
                                                         int kind) {
     extern __shared__ unsigned char smem[];
     c128 *gr = reinterpret_cast<c128 *>(smem);
     load_radial(a.gradial, a.nq, gr);
     __syncthreads();
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
+    const int sub = (int)(threadIdx.x % G);
+    if (i >= n) return;   // uniform over each group
     const int64_t e = list[i];
     const int64_t p = e >> 2;
     const int loc = (int)(e & 3);
@@ -717,7 +744,31 @@ __global__ void __launch_bounds__(128, POLAR ? 1 : 2) k_near_fill_list(NearFillA
         const int64_t mid = (lo + hi) >> 1;
         if (a.pair_ptr[mid] <= p) lo = mid; else hi = mid;
     }
-    fill_pair<POLAR>(a, lo, a.pair_s[p], p, kind, loc, gr);
+    fill_pair<POLAR, G>(a, lo, a.pair_s[p], p, kind, loc, gr, sub);
+}
+
+template <bool POLAR, int G>
+static void launch_fill_list(const NearFillArgs &a, int64_t ntg, const int64_t *list, int64_t n, int kind,
+                             size_t sh, hipStream_t st) {
+    const dim3 grid((unsigned)((n * G + 127) / 128));
+    hipLaunchKernelGGL((k_near_fill_list<POLAR, G>), grid, dim3(128), sh, st, a, ntg, list, n, kind);
+    SIE_HIP(hipGetLastError());
+}
+
+// Threads per listed pair: enough for about 64 K threads in the launch, at
+// most 16 (the smallest outer rules have 25 points).
+template <bool POLAR>
+static void launch_fill_list(const NearFillArgs &a, int64_t ntg, const int64_t *list, int64_t n, int kind,
+                             size_t sh, hipStream_t st) {
+    int G = 1;
+    while (G < 16 && n * G < 65536) G <<= 1;
+    switch (G) {
+        case 1: launch_fill_list<POLAR, 1>(a, ntg, list, n, kind, sh, st); break;
+        case 2: launch_fill_list<POLAR, 2>(a, ntg, list, n, kind, sh, st); break;
+        case 4: launch_fill_list<POLAR, 4>(a, ntg, list, n, kind, sh, st); break;
+        case 8: launch_fill_list<POLAR, 8>(a, ntg, list, n, kind, sh, st); break;
+        default: launch_fill_list<POLAR, 16>(a, ntg, list, n, kind, sh, st); break;
+    }
 }
 
 void launch_green_radial(c128 k, double h, int nq, c128 *gr, hipStream_t st) {
@@ -750,14 +801,8 @@ void launch_near_fill(const NearFillArgs &a, int64_t npairs, hipStream_t st) {
     SIE_HIP(hipGetLastError());
     for (int kd = 0; kd < 4; ++kd) {
         if (!cnt[kd]) continue;
-        const dim3 grid((unsigned)((cnt[kd] + 127) / 128));
-        if (a.polar)
-            hipLaunchKernelGGL(k_near_fill_list<true>, grid, dim3(128), sh_rad, st, a, ntg, lists[kd].p,
-                               (int64_t)cnt[kd], kd);
-        else
-            hipLaunchKernelGGL(k_near_fill_list<false>, grid, dim3(128), sh_rad, st, a, ntg, lists[kd].p,
-                               (int64_t)cnt[kd], kd);
-        SIE_HIP(hipGetLastError());
+        if (a.polar) launch_fill_list<true>(a, ntg, lists[kd].p, (int64_t)cnt[kd], kd, sh_rad, st);
+        else launch_fill_list<false>(a, ntg, lists[kd].p, (int64_t)cnt[kd], kd, sh_rad, st);
     }
     SIE_HIP(hipStreamSynchronize(st));
 }

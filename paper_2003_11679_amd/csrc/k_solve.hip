@@ -254,12 +254,17 @@ __global__ __launch_bounds__(512) void k_ras_gather(int c0, const int64_t *__res
                                                     const int32_t *__restrict__ ext,
                                                     const int32_t *__restrict__ own_off,
                                                     const int32_t *__restrict__ own_pos,
-                                                    const int64_t *__restrict__ ws_off, int64_t rwg0,
-                                                    const int64_t *__restrict__ row_ptr,
-                                                    const int32_t *__restrict__ cols, const c128 *__restrict__ vals,
-                                                    c128 scale, c128 *__restrict__ ws) {
+                                                    const int64_t *__restrict__ ws_off,
+                                                    const int32_t *__restrict__ cmed,
+                                                    const RasSource *__restrict__ src, c128 *__restrict__ ws) {
     __shared__ int32_t xs[kRasMax];
     const int c = c0 + blockIdx.x;
+    const RasSource s = src[cmed[c]];
+    const int64_t rwg0 = s.rwg0;
+    const int64_t *__restrict__ row_ptr = s.row_ptr;
+    const int32_t *__restrict__ cols = s.cols;
+    const c128 *__restrict__ vals = s.vals;
+    const c128 scale = s.scale;
     const int64_t e0 = ext_off[c];
     const int n = (int)(ext_off[c + 1] - e0);
     const int o0 = own_off[c];
@@ -427,12 +432,11 @@ __global__ __launch_bounds__(512) void k_ras_invert(int c0, const int64_t *__res
 }
 
 void launch_ras_setup(int c0, int cnt, const int64_t *ext_off, const int32_t *ext, const int32_t *own_off,
-                      const int32_t *own_pos, const int64_t *ws_off, const int64_t *m_off, int64_t rwg0,
-                      const int64_t *row_ptr, const int32_t *cols, const c128 *vals, c128 scale, c128 *ws,
-                      c128 *m64, c64 *m32, int *fail, hipStream_t st) {
+                      const int32_t *own_pos, const int64_t *ws_off, const int64_t *m_off, const int32_t *cmed,
+                      const RasSource *src, c128 *ws, c128 *m64, c64 *m32, int *fail, hipStream_t st) {
     if (cnt <= 0) return;
-    hipLaunchKernelGGL(k_ras_gather, dim3(cnt), dim3(512), 0, st, c0, ext_off, ext, own_off, own_pos, ws_off, rwg0,
-                       row_ptr, cols, vals, scale, ws);
+    hipLaunchKernelGGL(k_ras_gather, dim3(cnt), dim3(512), 0, st, c0, ext_off, ext, own_off, own_pos, ws_off, cmed,
+                       src, ws);
     SIE_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_ras_invert, dim3(cnt), dim3(512), 0, st, c0, ext_off, own_off, ws_off, m_off, ws, m64, m32,
                        fail);

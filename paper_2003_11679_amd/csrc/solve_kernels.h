@@ -14,10 +14,20 @@ void launch_bj_apply(int nb, int B, const int32_t *perm, const cx<T> *inv, const
 // Schwarz clusters of the near-region preconditioner: largest extended
 // cluster (RWG functions) the kernels take.
 constexpr int kRasMax = 2048;
+// Near-field rows of one medium that its clusters' matrices come from:
+// scale * vals of the CSR rows (RWG rwg0 + r).
+struct RasSource {
+    int64_t rwg0;
+    const int64_t *row_ptr;
+    const int32_t *cols;
+    const c128 *vals;
+    c128 scale;
+};
+// Clusters c0 .. c0 + cnt - 1 (cluster c's rows from src[cmed[c]]); their
+// workspaces start at ws + ws_off[c] - ws_off[c0].
 void launch_ras_setup(int c0, int cnt, const int64_t *ext_off, const int32_t *ext, const int32_t *own_off,
-                      const int32_t *own_pos, const int64_t *ws_off, const int64_t *m_off, int64_t rwg0,
-                      const int64_t *row_ptr, const int32_t *cols, const c128 *vals, c128 scale, c128 *ws,
-                      c128 *m64, c64 *m32, int *fail, hipStream_t st);
+                      const int32_t *own_pos, const int64_t *ws_off, const int64_t *m_off, const int32_t *cmed,
+                      const RasSource *src, c128 *ws, c128 *m64, c64 *m32, int *fail, hipStream_t st);
 template <typename T>
 void launch_ras_apply(int nc, int max_own, const int64_t *ext_off, const int32_t *ext, const int32_t *own_off,
                       const int32_t *own, const int64_t *m_off, const cx<T> *M, const cx<T> *x, cx<T> *y, int64_t ld,

@@ -442,8 +442,11 @@ struct Schwarz {
     DBuf<c64> m32;
 };
 
-// Setup workspace (augmented cluster matrices in FP64) per launch.
-constexpr double kSchwarzWorkspace = 2e9;
+// Setup workspace (augmented cluster matrices in FP64) per launch: at most
+// a quarter of the free device memory, between 2 and 12 GB.  One launch
+// then holds the clusters of many small media (one workgroup per cluster,
+// 128 KB of LDS each: the chip fills with 256 or more).
+constexpr double kSchwarzWorkspaceMin = 2e9, kSchwarzWorkspaceMax = 12e9;
 
 // The near-region operator carries the interior medium's interaction when
 // the field decays within the near region: five skin depths fit within
@@ -546,30 +549,38 @@ static void schwarz_build(sie_problem *p, Schwarz &sw, const std::vector<Medium 
     own_pos.upload(L.own_pos);
     DBuf<int64_t> ws_off;
     ws_off.upload(L.ws_off);
-    // batches of clusters within the workspace budget (at least one cluster)
+    // the rows each cluster's matrix comes from
+    std::vector<RasSource> src(media.size());
+    std::vector<int32_t> cmed(sw.nc);
+    for (size_t i = 0; i < media.size(); ++i) {
+        const Grid &g = *media[i]->grid;
+        src[i] = RasSource{g.rwg0, g.d_row_ptr.p, g.d_cols.p, media[i]->d_nLd64.p, scales[i]};
+        for (int c = first[i]; c < first[i + 1]; ++c) cmed[c] = (int32_t)i;
+    }
+    DBuf<RasSource> d_src;
+    d_src.upload(src);
+    DBuf<int32_t> d_cmed;
+    d_cmed.upload(cmed);
+    // batches of consecutive clusters (of any media) within the workspace
+    // budget, at least one cluster each
+    size_t fr = 0, tot = 0;
+    SIE_HIP(hipMemGetInfo(&fr, &tot));
+    const double budget = std::min(kSchwarzWorkspaceMax, std::max(kSchwarzWorkspaceMin, 0.25 * (double)fr));
     std::vector<std::pair<int, int>> batches;
     size_t ws_max = 0;
-    for (size_t i = 0; i < media.size(); ++i) {
-        for (int a = first[i]; a < first[i + 1];) {
-            int b = a + 1;
-            while (b < first[i + 1] && (double)(L.ws_off[b + 1] - L.ws_off[a]) * sizeof(c128) <= kSchwarzWorkspace) ++b;
-            batches.push_back({a, b});
-            ws_max = std::max(ws_max, (size_t)(L.ws_off[b] - L.ws_off[a]));
-            a = b;
-        }
+    for (int a = 0; a < sw.nc;) {
+        int b = a + 1;
+        while (b < sw.nc && (double)(L.ws_off[b + 1] - L.ws_off[a]) * sizeof(c128) <= budget) ++b;
+        batches.push_back({a, b});
+        ws_max = std::max(ws_max, (size_t)(L.ws_off[b] - L.ws_off[a]));
+        a = b;
     }
     DBuf<c128> ws(ws_max);
     DBuf<int> fail(1);
     SIE_HIP(hipMemsetAsync(fail.p, 0, sizeof(int), 0));
-    for (size_t i = 0; i < media.size(); ++i) {
-        const Grid &g = *media[i]->grid;
-        for (const auto &bt : batches) {
-            if (bt.first < first[i] || bt.first >= first[i + 1]) continue;
-            launch_ras_setup(bt.first, bt.second - bt.first, sw.ext_off.p, sw.ext.p, sw.own_off.p, own_pos.p,
-                             ws_off.p, sw.m_off.p, g.rwg0, g.d_row_ptr.p, g.d_cols.p, media[i]->d_nLd64.p,
-                             scales[i], ws.p, sw.m64.p, sw.m32.p, fail.p, 0);
-        }
-    }
+    for (const auto &bt : batches)
+        launch_ras_setup(bt.first, bt.second - bt.first, sw.ext_off.p, sw.ext.p, sw.own_off.p, own_pos.p, ws_off.p,
+                         sw.m_off.p, d_cmed.p, d_src.p, ws.p, sw.m64.p, sw.m32.p, fail.p, 0);
     int bad = 0;
     SIE_HIP(hipMemcpyAsync(&bad, fail.p, sizeof(int), hipMemcpyDeviceToHost, 0));
     SIE_HIP(hipStreamSynchronize(0));
