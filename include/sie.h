@@ -145,6 +145,34 @@ void sie_ctx_destroy(sie_ctx *ctx);
  * allocates much device memory of its own.  Kept blocks outlive contexts. */
 sie_status sie_ctx_trim(sie_ctx *ctx);
 const char *sie_last_error(void);
+
+/* ---- launch-shape tuning (process-wide) ------------------------------ */
+/* The grid stages of the AIM product (Sec. III-D-1: projection, the five
+ * passes of the zero-padded FFT convolution, interpolation) run with launch
+ * shapes chosen per problem shape: FFT tile shapes (threads and values per
+ * thread of a block, hence the lines per LDS tile) of the strided y passes
+ * and the fused z pass, and the block sizes of projection and
+ * interpolation.  All candidates of a stage compute identical values; only
+ * the time differs.  mode 1 (default): on the first product of a shape the
+ * candidates are timed on the caller's stream (a few launches each, on the
+ * product's own buffers before they hold data) and the fastest is kept per
+ * device for the rest of the process; not while the stream is being
+ * captured, not in sie_matvec_noalloc, and not while another thread tunes
+ * (that product uses the built-in shapes).  mode 0: built-in shapes only
+ * (choices already made are still used). */
+sie_status sie_set_tuning(int32_t mode);
+/* Testing: stage `family` (0 y forward, 1 y inverse, 2 z pass, 3
+ * projection, 4 interpolation) always uses candidate `candidate` (-1:
+ * choose as above).  SIE_EINVAL for an unknown family; a candidate beyond
+ * the stage's list fails the next product of that stage with SIE_EINVAL. */
+sie_status sie_tuning_force(int32_t family, int32_t candidate);
+/* The choices made so far, one text line per stage and shape (candidate
+ * times in microseconds, -1 where a candidate did not run).  Writes at most
+ * len bytes including the terminating NUL into buf (may be NULL with len 0);
+ * *needed (if not NULL) receives the full length including the NUL. */
+sie_status sie_tuning_report(char *buf, size_t len, size_t *needed);
+/* Forgets the choices made so far. */
+sie_status sie_tuning_clear(void);
 /* Message of the last failing call made with this context (through a
  * problem or server created on it); "" if none.  Valid until the next
  * failing call on the context. */

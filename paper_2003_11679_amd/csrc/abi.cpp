@@ -5,6 +5,7 @@
 #include <cstring>
 
 #include "problem.h"
+#include "tune.h"
 
 using namespace sie;
 
@@ -91,6 +92,31 @@ sie_status sie_ctx_trim(sie_ctx *ctx) {
         SIE_CHECK(ctx, SIE_EINVAL, "NULL context");
         pool_trim(ctx->device);
     });
+}
+
+sie_status sie_set_tuning(int32_t mode) {
+    return guard([&] { tune_set_mode(mode); });
+}
+
+sie_status sie_tuning_force(int32_t family, int32_t candidate) {
+    return guard([&] { tune_force(family, candidate); });
+}
+
+sie_status sie_tuning_report(char *buf, size_t len, size_t *needed) {
+    return guard([&] {
+        SIE_CHECK(buf || len == 0, SIE_EINVAL, "NULL buffer with nonzero length");
+        const std::string r = tune_report();
+        if (needed) *needed = r.size() + 1;
+        if (len) {
+            const size_t n = std::min(len - 1, r.size());
+            std::memcpy(buf, r.data(), n);
+            buf[n] = '\0';
+        }
+    });
+}
+
+sie_status sie_tuning_clear(void) {
+    return guard([&] { tune_clear(); });
 }
 
 sie_status sie_problem_create(sie_ctx *ctx, double freq_hz, double bg_eps_r, double bg_mu_r, sie_problem **out) {

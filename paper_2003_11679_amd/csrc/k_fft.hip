@@ -20,6 +20,7 @@
 // per-thread 32-bit offset plus a uniform step per register slot.
 #include "common.h"
 #include "kernels.h"
+#include "tune.h"
 
 #include <algorithm>
 #include <atomic>
@@ -486,6 +487,37 @@ template <typename T> struct FftShape {
     static constexpr int grad_minw = sizeof(T) == 4 ? 2 : 1;
 };
 
+// Tile shapes the launch-shape tuner chooses among for the strided y
+// passes and the G z pass (threads, values per thread; the first is the
+// built-in shape).  A shape only changes which thread runs which butterfly:
+// every candidate computes the same values.
+template <typename T> struct FftCands;
+template <> struct FftCands<float> {
+    static constexpr int ny = 3;
+    static constexpr int y_nt[ny] = {512, 256, 256};
+    static constexpr int y_vpt[ny] = {16, 16, 8};
+    static constexpr int nz = 5;
+    static constexpr int z_nt[nz] = {256, 512, 256, 128, 128};
+    static constexpr int z_vpt[nz] = {16, 16, 8, 16, 8};
+};
+template <> struct FftCands<double> {
+    static constexpr int ny = 2;
+    static constexpr int y_nt[ny] = {512, 256};
+    static constexpr int y_vpt[ny] = {8, 8};
+    static constexpr int nz = 3;
+    static constexpr int z_nt[nz] = {256, 512, 128};
+    static constexpr int z_vpt[nz] = {8, 8, 8};
+};
+static_assert(FftCands<float>::y_nt[0] == FftShape<float>::nt && FftCands<float>::y_vpt[0] == FftShape<float>::vpt,
+              "the first y candidate is the built-in shape");
+static_assert(FftCands<double>::y_nt[0] == FftShape<double>::nt && FftCands<double>::y_vpt[0] == FftShape<double>::vpt,
+              "the first y candidate is the built-in shape");
+static_assert(FftCands<float>::z_nt[0] == FftShape<float>::z_nt && FftCands<float>::z_vpt[0] == FftShape<float>::z_vpt,
+              "the first z candidate is the built-in shape");
+static_assert(FftCands<double>::z_nt[0] == FftShape<double>::z_nt &&
+                  FftCands<double>::z_vpt[0] == FftShape<double>::z_vpt,
+              "the first z candidate is the built-in shape");
+
 // Shortest and longest supported transform (2^3 .. 2^10).
 constexpr int kMinLg = 3, kMaxLg = 10;
 
@@ -522,10 +554,10 @@ static void check_tile() {
     SIE_CHECK((long)TS::BYTES <= lds_limit(), SIE_EDEVICE, "FFT tile needs more LDS than the device offers");
 }
 
-template <typename T, int LGL, bool INV, bool PRUNE>
+template <typename T, int LGL, bool INV, bool PRUNE, int NT = FftShape<T>::nt, int V = FftShape<T>::vpt>
 static void launch_pass(const cx<T> *in, cx<T> *out, int n_in, int n_out, long s_in, long s_out, long js_in,
                         long js_out, long bs_in, long bs_out, int nj, long nb, bool contiguous, hipStream_t st) {
-    constexpr int NT = FftShape<T>::nt, V = FftShape<T>::vpt, W = FftShape<T>::minw;
+    constexpr int W = FftShape<T>::minw;
     using TS = Tile<T, NT, V, LGL>;
     constexpr int L = 1 << LGL;
     check_tile<TS>();
@@ -533,12 +565,19 @@ static void launch_pass(const cx<T> *in, cx<T> *out, int n_in, int n_out, long s
     SIE_CHECK(n_in >= 0 && n_in <= L && n_out >= 0 && n_out <= L, SIE_EINVAL, "FFT line extents exceed the length");
     if (PRUNE) SIE_CHECK(INV ? n_out <= L / 2 : n_in <= L / 2, SIE_EINVAL, "pruned FFT needs a half-length live line");
     dim3 grid((nj + TS::TX - 1) / TS::TX, (unsigned)nb);
-    if (contiguous) {
-        SIE_CHECK(s_in == 1 && s_out == 1, SIE_EINVAL, "contiguous FFT pass needs unit element stride");
-        check_span((long)TS::TX * std::max(js_in, js_out) + L);
-        hipLaunchKernelGGL((k_fft_pass<T, NT, V, LGL, true, INV, PRUNE, W>), grid, dim3(NT), TS::BYTES, st, in, out,
-                           n_in, n_out, 1, 1, (int)js_in, (int)js_out, bs_in, bs_out, nj);
+    if constexpr (NT == FftShape<T>::nt && V == FftShape<T>::vpt) {
+        if (contiguous) {
+            SIE_CHECK(s_in == 1 && s_out == 1, SIE_EINVAL, "contiguous FFT pass needs unit element stride");
+            check_span((long)TS::TX * std::max(js_in, js_out) + L);
+            hipLaunchKernelGGL((k_fft_pass<T, NT, V, LGL, true, INV, PRUNE, W>), grid, dim3(NT), TS::BYTES, st, in,
+                               out, n_in, n_out, 1, 1, (int)js_in, (int)js_out, bs_in, bs_out, nj);
+            SIE_HIP(hipGetLastError());
+            return;
+        }
     } else {
+        SIE_CHECK(!contiguous, SIE_EINVAL, "contiguous FFT passes take the built-in shape");
+    }
+    {
         SIE_CHECK(js_in == 1 && js_out == 1, SIE_EINVAL, "strided FFT pass needs adjacent lines");
         check_span((long)L * std::max(s_in, s_out) + TS::TX);
         hipLaunchKernelGGL((k_fft_pass<T, NT, V, LGL, false, INV, PRUNE, W>), grid, dim3(NT), TS::BYTES, st, in,
@@ -547,16 +586,37 @@ static void launch_pass(const cx<T> *in, cx<T> *out, int n_in, int n_out, long s
     SIE_HIP(hipGetLastError());
 }
 
+// Strided pass with y candidate shape C (of FftCands<T>).
+template <typename T, int LGL, bool INV, bool PRUNE, int C = 0>
+static void launch_pass_shape(int shape, const cx<T> *in, cx<T> *out, int n_in, int n_out, long s_in, long s_out,
+                              long js_in, long js_out, long bs_in, long bs_out, int nj, long nb, bool contiguous,
+                              hipStream_t st) {
+    if constexpr (C < FftCands<T>::ny) {
+        if (shape == C)
+            launch_pass<T, LGL, INV, PRUNE, FftCands<T>::y_nt[C], FftCands<T>::y_vpt[C]>(
+                in, out, n_in, n_out, s_in, s_out, js_in, js_out, bs_in, bs_out, nj, nb, contiguous, st);
+        else
+            launch_pass_shape<T, LGL, INV, PRUNE, C + 1>(shape, in, out, n_in, n_out, s_in, s_out, js_in, js_out,
+                                                         bs_in, bs_out, nj, nb, contiguous, st);
+    } else {
+        SIE_CHECK(false, SIE_EINVAL, "FFT pass shape out of range");
+    }
+}
+
 template <typename T, bool INV, bool PRUNE, int LGL = kMinLg>
 static void pass_lg(int lg, const cx<T> *in, cx<T> *out, int n_in, int n_out, long s_in, long s_out, long js_in,
-                    long js_out, long bs_in, long bs_out, int nj, long nb, bool contiguous, hipStream_t st) {
+                    long js_out, long bs_in, long bs_out, int nj, long nb, bool contiguous, hipStream_t st,
+                    int shape = 0) {
     if constexpr (LGL <= kMaxLg) {
-        if (lg == LGL)
+        if (lg != LGL)
+            pass_lg<T, INV, PRUNE, LGL + 1>(lg, in, out, n_in, n_out, s_in, s_out, js_in, js_out, bs_in, bs_out,
+                                            nj, nb, contiguous, st, shape);
+        else if (contiguous || shape == 0)
             launch_pass<T, LGL, INV, PRUNE>(in, out, n_in, n_out, s_in, s_out, js_in, js_out, bs_in, bs_out, nj,
                                             nb, contiguous, st);
         else
-            pass_lg<T, INV, PRUNE, LGL + 1>(lg, in, out, n_in, n_out, s_in, s_out, js_in, js_out, bs_in, bs_out,
-                                            nj, nb, contiguous, st);
+            launch_pass_shape<T, LGL, INV, PRUNE>(shape, in, out, n_in, n_out, s_in, s_out, js_in, js_out, bs_in,
+                                                  bs_out, nj, nb, contiguous, st);
     } else {
         SIE_CHECK(false, SIE_EGRID, "FFT length must be a power of two between 8 and 1024");
     }
@@ -566,22 +626,44 @@ static void pass_lg(int lg, const cx<T> *in, cx<T> *out, int n_in, int n_out, lo
 // half-length live prefix, inverse passes keep one).
 template <typename T>
 static void pass(const cx<T> *in, cx<T> *out, int L, int n_in, int n_out, long s_in, long s_out, long js_in,
-                 long js_out, long bs_in, long bs_out, int nj, long nb, bool contiguous, bool inv, hipStream_t st) {
+                 long js_out, long bs_in, long bs_out, int nj, long nb, bool contiguous, bool inv, hipStream_t st,
+                 int shape = 0) {
     SIE_CHECK((L & (L - 1)) == 0, SIE_EGRID, "FFT length must be a power of two");
     if (inv)
         pass_lg<T, true, true>(ilog2(L), in, out, n_in, n_out, s_in, s_out, js_in, js_out, bs_in, bs_out, nj, nb,
-                               contiguous, st);
+                               contiguous, st, shape);
     else
         pass_lg<T, false, true>(ilog2(L), in, out, n_in, n_out, s_in, s_out, js_in, js_out, bs_in, bs_out, nj, nb,
-                                contiguous, st);
+                                contiguous, st, shape);
+}
+
+// G z pass with z candidate shape C (of FftCands<T>).
+template <typename T, int LGL, int C = 0>
+static void launch_zpass0(int shape, cx<T> *bufB, const cx<T> *spec, int mx, int my, int nz, int fps, int run0,
+                          int nspec, int nf, long spec_stride, hipStream_t st) {
+    if constexpr (C < FftCands<T>::nz) {
+        if (shape != C) {
+            launch_zpass0<T, LGL, C + 1>(shape, bufB, spec, mx, my, nz, fps, run0, nspec, nf, spec_stride, st);
+            return;
+        }
+        constexpr int NT = FftCands<T>::z_nt[C], V = FftCands<T>::z_vpt[C], W = FftShape<T>::z_minw;
+        using TS = Tile<T, NT, V, LGL>;
+        check_tile<TS>();
+        const int cpr = (fps + kZFields - 1) / kZFields;
+        dim3 grid((mx + TS::TX - 1) / TS::TX, my / 2 + 1, (nf / fps) * cpr);
+        hipLaunchKernelGGL((k_fft_zpass<T, NT, V, LGL, 0, W>), grid, dim3(NT), TS::BYTES, st, bufB, spec, mx, my, nz,
+                           fps, run0, nspec, spec_stride);
+    } else {
+        SIE_CHECK(false, SIE_EINVAL, "FFT z-pass shape out of range");
+    }
 }
 
 template <typename T, int LGL = kMinLg>
 static void zpass_lg(int lg, const GridView &g, const cx<T> *spec, long spec_stride, int fps, int run0, int nspec,
-                     int nf, int mode, cx<T> *bufB, hipStream_t st) {
+                     int nf, int mode, cx<T> *bufB, hipStream_t st, int shape = 0) {
     if constexpr (LGL <= kMaxLg) {
         if (lg != LGL) {
-            zpass_lg<T, LGL + 1>(lg, g, spec, spec_stride, fps, run0, nspec, nf, mode, bufB, st);
+            zpass_lg<T, LGL + 1>(lg, g, spec, spec_stride, fps, run0, nspec, nf, mode, bufB, st, shape);
             return;
         }
         SIE_CHECK(fps >= 1 && nf % fps == 0 && nspec >= 1, SIE_EINVAL, "fields must form whole spectrum runs");
@@ -590,13 +672,7 @@ static void zpass_lg(int lg, const GridView &g, const cx<T> *spec, long spec_str
         check_span((long)nz * my * mx);
         SIE_CHECK(nz <= mz / 2, SIE_EGRID, "z live extent above half the FFT length");
         if (mode == 0) {
-            constexpr int NT = FftShape<T>::z_nt, V = FftShape<T>::z_vpt, W = FftShape<T>::z_minw;
-            using TS = Tile<T, NT, V, LGL>;
-            check_tile<TS>();
-            const int cpr = (fps + kZFields - 1) / kZFields;
-            dim3 grid((mx + TS::TX - 1) / TS::TX, my / 2 + 1, (nf / fps) * cpr);
-            hipLaunchKernelGGL((k_fft_zpass<T, NT, V, LGL, 0, W>), grid, dim3(NT), TS::BYTES, st, bufB, spec, mx, my,
-                               nz, fps, run0, nspec, spec_stride);
+            launch_zpass0<T, LGL>(shape, bufB, spec, mx, my, nz, fps, run0, nspec, nf, spec_stride, st);
         } else {
             constexpr int NT = FftShape<T>::grad_nt, V = FftShape<T>::grad_vpt, W = FftShape<T>::grad_minw;
             using TS = Tile<T, NT, V, LGL>;
@@ -618,16 +694,38 @@ static void convolve_chunk(const GridView &g, const cx<T> *spec, long spec_strid
                            int nf, int mode, const cx<T> *in, cx<T> *out, cx<T> *bufA, cx<T> *bufB, hipStream_t st) {
     const int nx = g.nl[0], ny = g.nl[1], nz = g.nl[2];
     const int mx = g.m[0], my = g.m[1], mz = g.m[2];
+    SIE_CHECK((mz & (mz - 1)) == 0, SIE_EGRID, "FFT length must be a power of two");
+    auto yfwd = [&](int shape) {   // lines along y, j = x (adjacent), batch b = f*nz + z
+        pass<T>(bufA, bufB, my, ny, my, mx, mx, 1, 1, (long)ny * mx, (long)my * mx, mx, (long)nf * nz, false, false,
+                st, shape);
+        return true;
+    };
+    auto zfused = [&](int shape) {
+        zpass_lg<T>(ilog2(mz), g, spec, spec_stride, fps, run0, nspec, nf, mode, bufB, st, shape);
+        return true;
+    };
+    auto yinv = [&](int shape) {   // keep ny
+        pass<T>(bufB, bufA, my, my, ny, mx, mx, 1, 1, (long)my * mx, (long)ny * mx, mx, (long)nf * nz, false, true,
+                st, shape);
+        return true;
+    };
+    // tile shapes: on the first call for this shape the candidates run on
+    // bufA / bufB before they hold anything (the passes below overwrite
+    // both), so timing them disturbs no data
+    int dev = 0;
+    SIE_HIP(hipGetDevice(&dev));
+    const int prec = (int)sizeof(T);
+    const TuneKey kyf{dev, TUNE_FFT_YFWD, prec, {my, mx, ny, (int64_t)nf * nz, 0}};
+    const TuneKey kyi{dev, TUNE_FFT_YINV, prec, {my, mx, ny, (int64_t)nf * nz, 0}};
+    const TuneKey kz{dev, TUNE_FFT_Z, prec, {mz, mx, my, nz, (int64_t)nf * 65536 + fps}};
+    const int syf = tune_pick(kyf, FftCands<T>::ny, yfwd, st);
+    const int sz = mode == 0 ? tune_pick(kz, FftCands<T>::nz, zfused, st) : 0;
+    const int syi = tune_pick(kyi, FftCands<T>::ny, yinv, st);
     // x forward: lines (f, z, y) contiguous; batch b = f*nz + z, j = y
     pass<T>(in, bufA, mx, nx, mx, 1, 1, nx, mx, (long)ny * nx, (long)ny * mx, ny, (long)nf * nz, true, false, st);
-    // y forward: lines along y, j = x (adjacent), batch b = f*nz + z
-    pass<T>(bufA, bufB, my, ny, my, mx, mx, 1, 1, (long)ny * mx, (long)my * mx, mx, (long)nf * nz, false, false,
-            st);
-    // z fused
-    SIE_CHECK((mz & (mz - 1)) == 0, SIE_EGRID, "FFT length must be a power of two");
-    zpass_lg<T>(ilog2(mz), g, spec, spec_stride, fps, run0, nspec, nf, mode, bufB, st);
-    // y inverse: keep ny
-    pass<T>(bufB, bufA, my, my, ny, mx, mx, 1, 1, (long)my * mx, (long)ny * mx, mx, (long)nf * nz, false, true, st);
+    yfwd(syf);
+    zfused(sz);
+    yinv(syi);
     // x inverse: keep nx
     pass<T>(bufA, out, mx, mx, nx, 1, 1, mx, nx, (long)ny * mx, (long)ny * nx, ny, (long)nf * nz, true, true, st);
 }

@@ -12,6 +12,7 @@
 //   c_e = +-l/(2A),  q_e = (vertex opposite edge e) - r_c,  r_c = stencil centre.
 #include "common.h"
 #include "kernels.h"
+#include "tune.h"
 
 namespace sie {
 
@@ -132,6 +133,11 @@ void launch_tri_sources(const GridView &g, const T *tri_coef, const cx<T> *x, in
     SIE_HIP(hipGetLastError());
 }
 
+// Threads per block the tuner chooses among for projection and
+// interpolation (the first is the built-in size).
+constexpr int kNumStageBlocks = 4;
+constexpr int kStageBlocks[kNumStageBlocks] = {256, 128, 512, 64};
+
 // Gather projection: `lpn` lanes (a power of two <= 64) per live node share
 // its entry list and reduce with lane shuffles.  grid [F][nlive] with
 // J_c = sum (alpha M1_c - beta_c M0) and (F == 4) Q = sum 2 alpha M0, the
@@ -199,10 +205,20 @@ void launch_project(const GridView &g, const T *mom, const cx<T> *trisrc, cx<T> 
     int lpn = 1;
     while (lpn < 64 && lpn * 2 <= avg / 2.0) lpn *= 2;
     const int64_t threads = nnodes * lpn;
-    hipLaunchKernelGGL(k_project<T>, dim3((unsigned)((threads + 255) / 256), (unsigned)nrhs), dim3(256), 0, st,
-                       nnodes, g.nlive, g.node_ptr, g.node_ent, mom, trisrc, grid, nfields, lpn, g.ntg, rho, ldr,
-                       rho_tris);
-    SIE_HIP(hipGetLastError());
+    // block size: tuned among kStageBlocks (lpn divides each, so a node's
+    // lanes stay in one wavefront)
+    auto run = [&](int c) {
+        const int bs = kStageBlocks[c];
+        hipLaunchKernelGGL(k_project<T>, dim3((unsigned)((threads + bs - 1) / bs), (unsigned)nrhs), dim3(bs), 0, st,
+                           nnodes, g.nlive, g.node_ptr, g.node_ent, mom, trisrc, grid, nfields, lpn, g.ntg, rho, ldr,
+                           rho_tris);
+        SIE_HIP(hipGetLastError());
+        return true;
+    };
+    int dev = 0;
+    SIE_HIP(hipGetDevice(&dev));
+    const TuneKey key{dev, TUNE_PROJECT, (int)sizeof(T), {nnodes, g.ntg, nfields, nrhs, lpn + (rho ? 1000 : 0)}};
+    run(tune_pick(key, kNumStageBlocks, run, st));
 }
 
 // Interpolation partials per triangle: psi = sum_a M1[a] . F_vec(a),
@@ -239,10 +255,18 @@ void launch_interp(const GridView &g, const T *mom, const cx<T> *pot, int nfield
     const int64_t ntg = g.ntg;
     if (!ntg || nrhs < 1) return;
     SIE_CHECK(nrhs <= 65535, SIE_EINVAL, "too many right-hand sides");
-    hipLaunchKernelGGL(k_interp<T>, dim3((unsigned)((ntg + 255) / 256), (unsigned)nrhs), dim3(256), 0, st, ntg,
-                       g.centre, g.tri_slot, g.lo[0], g.lo[1], g.lo[2], g.nl[0], g.nl[1], g.nlive, g.nnodes(), mom,
-                       pot, nfields, tripot);
-    SIE_HIP(hipGetLastError());
+    auto run = [&](int c) {
+        const int bs = kStageBlocks[c];
+        hipLaunchKernelGGL(k_interp<T>, dim3((unsigned)((ntg + bs - 1) / bs), (unsigned)nrhs), dim3(bs), 0, st, ntg,
+                           g.centre, g.tri_slot, g.lo[0], g.lo[1], g.lo[2], g.nl[0], g.nl[1], g.nlive, g.nnodes(),
+                           mom, pot, nfields, tripot);
+        SIE_HIP(hipGetLastError());
+        return true;
+    };
+    int dev = 0;
+    SIE_HIP(hipGetDevice(&dev));
+    const TuneKey key{dev, TUNE_INTERP, (int)sizeof(T), {ntg, g.nnodes(), nfields, nrhs, 0}};
+    run(tune_pick(key, kNumStageBlocks, run, st));
 }
 
 template <typename T>

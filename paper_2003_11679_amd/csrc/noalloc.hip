@@ -12,6 +12,7 @@
 #include <mutex>
 
 #include "problem.h"
+#include "tune.h"
 
 namespace sie {
 
@@ -61,6 +62,9 @@ static void run(sie_problem *p, Medium &md, sie_op op, const cx<T> *x, cx<T> *y,
 
 void matvec_noalloc(sie_problem *p, Medium &md, sie_op op, sie_precision prec, const void *x, void *y,
                     hipStream_t st) {
+    // no launch-shape timing here (it creates events and synchronises):
+    // shapes already tuned are used, else the built-in ones
+    TuneSuspend no_tuning;
     int cur = -1;
     SIE_HIP(hipGetDevice(&cur));
     SIE_CHECK(cur == p->ctx->device, SIE_EDEVICE, "the problem's device must be current");

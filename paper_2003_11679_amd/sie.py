@@ -89,6 +89,10 @@ SIGNATURES = [
     ("sie_ctx_destroy", None, [_VP]),
     ("sie_ctx_trim", ctypes.c_int, [_VP]),
     ("sie_last_error", ctypes.c_char_p, []),
+    ("sie_set_tuning", ctypes.c_int, [ctypes.c_int32]),
+    ("sie_tuning_force", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32]),
+    ("sie_tuning_report", ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
+    ("sie_tuning_clear", ctypes.c_int, []),
     ("sie_problem_create", ctypes.c_int, [_VP, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                           ctypes.POINTER(_VP)]),
     ("sie_problem_add_object", ctypes.c_int, [_VP, _DP, ctypes.c_int64, _I32P, ctypes.c_int64,
@@ -182,6 +186,41 @@ def grid_choose(freq, eps_r, mu_r, sigma, extent, mean_edge, near_radius=5, stri
     _check(lib().sie_grid_choose(float(freq), float(eps_r), float(mu_r), float(sigma), float(extent),
                                  float(mean_edge), int(near_radius), int(bool(strict)), ctypes.byref(g)))
     return g.as_dict()
+
+
+# Stages whose launch shapes are tuned (sie_tuning_force families).
+TUNE_FAMILIES = {"fft_y_fwd": 0, "fft_y_inv": 1, "fft_z": 2, "project": 3, "interp": 4}
+
+
+def set_tuning(mode):
+    """Launch-shape tuning, process-wide: 1 tune on first use, 0 built-in shapes."""
+    _check(lib().sie_set_tuning(int(mode)))
+
+
+def tuning_force(family, candidate):
+    """Testing: stage `family` (name or number) always uses `candidate` (-1: tune)."""
+    f = TUNE_FAMILIES[family] if isinstance(family, str) else int(family)
+    _check(lib().sie_tuning_force(f, int(candidate)))
+
+
+def tuning_report():
+    """The tuner's choices so far: list of dicts (stage, precision, shape, times, choice)."""
+    n = ctypes.c_size_t(0)
+    _check(lib().sie_tuning_report(None, 0, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value)
+    _check(lib().sie_tuning_report(buf, n.value, None))
+    out = []
+    for line in buf.value.decode().splitlines():
+        f = line.split()
+        d = dict(kv.split("=", 1) for kv in f[1:] if "=" in kv)
+        out.append({"stage": f[0], "device": int(d["dev"]), "precision": f[2],
+                    "shape": [int(v) for v in d["shape"].split("x")],
+                    "us": [float(v) for v in d["us"].split(",")], "choice": int(d["choice"])})
+    return out
+
+
+def tuning_clear():
+    _check(lib().sie_tuning_clear())
 
 
 class Context:
