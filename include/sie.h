@@ -107,8 +107,18 @@ typedef struct {
                             get it, the others run unpreconditioned; with 8
                             as well (12) every interior medium gets it, the
                             others with clusters of 4^3 cells and two cells
-                            of overlap.  1 and 4 exclude each other, 8 needs 4
-                            (SIE_EINVAL); 0 none (default) */
+                            of overlap; 16 the same M_i factored exactly
+                            (sparse LU without pivoting over the object's RWG
+                            rows: host FP64 multifrontal factorisation in
+                            nested-dissection order, device triangular
+                            solves), for each medium whose M_i stays sparse
+                            (at most 1024 rows, or at most 200 nonzeros per
+                            row on average, and no separator above 1024
+                            unknowns, e.g. under the skin-depth cutoff); with 4 as well (20, or 28
+                            with 8) the media without a factorisation get
+                            Schwarz clusters.  1 and 4 exclude each other, 1
+                            and 16 too, 8 needs 4 (SIE_EINVAL); 0 none
+                            (default) */
     double inner_relax;  /* relaxed nested tolerance inside each correction
                             solve (inexact Krylov relaxation, Simoncini and
                             Szyld): nested solve j runs to inner_relax x
@@ -366,9 +376,10 @@ sie_status sie_interpolate(sie_problem *p, int32_t medium, sie_precision prec,
 
 /* Nested-solve preconditioner (eq. nest2pc, M_i = -j w eps_i L_i,NR of every
  * object's interior medium), applied to nrhs vectors [nrhs][E] on the
- * caller's stream: precond = 1 block-Jacobi, 4 restricted additive Schwarz
- * over grid-cell clusters (see sie_solver_opts.precond; rows of media
- * without clusters are copied).  Built on first use (host-synchronous); the
+ * caller's stream: precond = 1 block-Jacobi, 4 or 12 restricted additive
+ * Schwarz over grid-cell clusters, 16 the exact sparse LU of M_i, 20 or 28
+ * the LU where it applies and clusters elsewhere (see
+ * sie_solver_opts.precond; rows of media with neither are copied).  Built on first use (host-synchronous); the
  * same structure serves later solves.  x and y must not alias; complex64 for
  * SIE_FP32, complex128 for SIE_FP64.  SIE_ESTATE before setup. */
 sie_status sie_nested_precond(sie_problem *p, int32_t precond, sie_precision prec, int32_t nrhs,
@@ -376,6 +387,11 @@ sie_status sie_nested_precond(sie_problem *p, int32_t precond, sie_precision pre
 /* Clusters of the built Schwarz preconditioner (-1 if not built); *owned
  * (nullable) receives the number of RWG rows they own. */
 int32_t sie_nested_precond_clusters(const sie_problem *p, int64_t *owned);
+/* Interior media with an exact near-region factorisation (precond bit 16;
+ * -1 if not built); *factor_nnz (nullable) receives the stored off-block
+ * entries of their L and U factors, *t_factor_s (nullable) the host time of
+ * the factorisations. */
+int32_t sie_nested_precond_factored(const sie_problem *p, int64_t *factor_nnz, double *t_factor_s);
 
 /* Constraint preconditioner of the augmented EFIE (Sec. III-E), y = P^-1 x
  * for nrhs vectors [nrhs][E + T] complex128 on the caller's stream, with

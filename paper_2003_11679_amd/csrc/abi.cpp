@@ -421,6 +421,11 @@ sie_status sie_nested_precond(sie_problem *p, int32_t precond, sie_precision pre
     });
 }
 
+int32_t sie_nested_precond_factored(const sie_problem *p, int64_t *factor_nnz, double *t_factor_s) {
+    if (!p) return -1;
+    return nested_precond_factored(p, factor_nnz, t_factor_s);
+}
+
 int32_t sie_nested_precond_clusters(const sie_problem *p, int64_t *owned) {
     if (!p) return -1;
     return nested_precond_clusters(p, owned);

@@ -54,4 +54,51 @@ void launch_lu_level(const SparseLU &f, int level, bool forward, int nrhs, c128 
     SIE_HIP(hipGetLastError());
 }
 
+template <typename T>
+__global__ void k_lu_gather(int64_t n, int64_t r0, int64_t E, const int32_t *__restrict__ iperm,
+                            const cx<T> *__restrict__ x, c128 *__restrict__ xp) {
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const cx<T> v = x[blockIdx.y * E + r0 + j];
+    xp[blockIdx.y * n + iperm[j]] = c128((double)v.re, (double)v.im);
+}
+
+template <typename T>
+__global__ void k_lu_scatter(int64_t n, int64_t r0, int64_t E, const int32_t *__restrict__ iperm,
+                             const c128 *__restrict__ xp, cx<T> *__restrict__ y) {
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const c128 v = xp[blockIdx.y * n + iperm[j]];
+    y[blockIdx.y * E + r0 + j] = cx<T>((T)v.re, (T)v.im);
+}
+
+template <typename T>
+void launch_lu_gather(int64_t n, int64_t r0, int64_t E, int nrhs, const int32_t *iperm, const cx<T> *x, c128 *xp,
+                      hipStream_t st) {
+    if (n <= 0 || nrhs < 1) return;
+    SIE_CHECK(nrhs <= 65535, SIE_EINVAL, "too many right-hand sides");
+    hipLaunchKernelGGL(k_lu_gather<T>, dim3((unsigned)((n + 255) / 256), (unsigned)nrhs), dim3(256), 0, st, n, r0, E,
+                       iperm, x, xp);
+    SIE_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_lu_scatter(int64_t n, int64_t r0, int64_t E, int nrhs, const int32_t *iperm, const c128 *xp, cx<T> *y,
+                       hipStream_t st) {
+    if (n <= 0 || nrhs < 1) return;
+    SIE_CHECK(nrhs <= 65535, SIE_EINVAL, "too many right-hand sides");
+    hipLaunchKernelGGL(k_lu_scatter<T>, dim3((unsigned)((n + 255) / 256), (unsigned)nrhs), dim3(256), 0, st, n, r0,
+                       E, iperm, xp, y);
+    SIE_HIP(hipGetLastError());
+}
+
+template void launch_lu_gather<float>(int64_t, int64_t, int64_t, int, const int32_t *, const c64 *, c128 *,
+                                      hipStream_t);
+template void launch_lu_gather<double>(int64_t, int64_t, int64_t, int, const int32_t *, const c128 *, c128 *,
+                                       hipStream_t);
+template void launch_lu_scatter<float>(int64_t, int64_t, int64_t, int, const int32_t *, const c128 *, c64 *,
+                                       hipStream_t);
+template void launch_lu_scatter<double>(int64_t, int64_t, int64_t, int, const int32_t *, const c128 *, c128 *,
+                                        hipStream_t);
+
 }  // namespace sie

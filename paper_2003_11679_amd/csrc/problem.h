@@ -174,6 +174,7 @@ void solve_entry(sie_problem *p, sie_precision prec, const sie_solver_opts *opts
 void nested_precond_entry(sie_problem *p, int precond, sie_precision prec, int nrhs, const void *x, void *y,
                           hipStream_t st);
 int nested_precond_clusters(const sie_problem *p, int64_t *owned);
+int nested_precond_factored(const sie_problem *p, int64_t *factor_nnz, double *t_factor_s);
 void currents_entry(const sie_problem *p, int32_t rhs, sie_c128 *u, sie_c128 *v);
 void charges_entry(const sie_problem *p, int32_t rhs, sie_c128 *sg);
 // Message returned by sie_last_error() on this thread.

@@ -516,9 +516,7 @@ static void schwarz_build(sie_problem *p, Schwarz &sw, const std::vector<Medium 
                           bool all_media) {
     ClusterLists L;
     std::vector<int> first, used;
-    int64_t total = 0;
     for (size_t i = 0; i < media.size(); ++i) {
-        total += ranges[i].second - ranges[i].first;
         first.push_back((int)L.own_off.size() - 1);
         used.push_back(0);
         const bool dominated = near_region_dominates(*media[i]);
@@ -536,7 +534,7 @@ static void schwarz_build(sie_problem *p, Schwarz &sw, const std::vector<Medium 
     sw.nc = (int)L.own_off.size() - 1;
     sw.owned = (int64_t)L.own.size();
     for (int c = 0; c < sw.nc; ++c) sw.max_own = std::max(sw.max_own, L.own_off[c + 1] - L.own_off[c]);
-    sw.covers_all = sw.owned == total;
+    sw.covers_all = sw.owned == p->mesh.nrwg;
     if (sw.nc == 0) return;
     sw.ext_off.upload(L.ext_off);
     sw.ext.upload(L.ext);
@@ -591,6 +589,83 @@ template <typename T> static const cx<T> *ras_m(const Schwarz &w);
 template <> const c128 *ras_m<double>(const Schwarz &w) { return w.m64.p; }
 template <> const c64 *ras_m<float>(const Schwarz &w) { return w.m32.p; }
 
+// ---------------------------------------------------------------- exact near-region factorisation
+// The preconditioner of eq. nest2pc as the paper applies it: a sparse LU of
+// M_i = -j w eps_i L_i,NR over the object's RWG rows, factored on the host
+// (FP64, nested dissection, no pivoting) and applied with the device's
+// level-by-level triangular solves.  A medium whose near-region matrix is
+// too dense to factor as a sparse matrix (above the supernode limit in size
+// and more than kLUMeanRow nonzeros per row on average, or with a separator
+// above that limit) gets none.
+struct NearLU {
+    int medium = 0;
+    int64_t r0 = 0, n = 0;
+    SparseLU f;
+};
+constexpr double kLUMeanRow = 200.0;
+
+static bool near_lu_build(sie_problem *p, int medium, int64_t r0, int64_t r1, c128 scale, NearLU &out) {
+    const Medium &md = p->ints[medium];
+    const Grid &g = *md.grid;
+    const int64_t n = r1 - r0;
+    if (n <= 0) return false;
+    SIE_CHECK(r0 >= g.rwg0 && r1 <= g.rwg1, SIE_EINVAL, "object rows outside its grid's rows");
+    const std::vector<int64_t> rp_all = g.d_row_ptr.download();
+    const int64_t b = rp_all[r0 - g.rwg0], e = rp_all[r1 - g.rwg0];
+    if (n > kLUMaxSupernode && (double)(e - b) > kLUMeanRow * (double)n) return false;
+    std::vector<int32_t> cols(e - b);
+    std::vector<c128> vals(e - b);
+    if (e > b) {
+        SIE_HIP(hipMemcpy(cols.data(), g.d_cols.p + b, (e - b) * sizeof(int32_t), hipMemcpyDeviceToHost));
+        SIE_HIP(hipMemcpy(vals.data(), md.d_nLd64.p + b, (e - b) * sizeof(c128), hipMemcpyDeviceToHost));
+    }
+    // local rows and columns; the pattern made structurally symmetric
+    std::vector<std::vector<std::pair<int32_t, c128>>> rows(n);
+    for (int64_t i = 0; i < n; ++i) {
+        rows[i].push_back({(int32_t)i, c128()});
+        for (int64_t k = rp_all[r0 - g.rwg0 + i] - b; k < rp_all[r0 - g.rwg0 + i + 1] - b; ++k) {
+            const int64_t c = (int64_t)cols[k] - r0;
+            if (c < 0 || c >= n) continue;
+            rows[i].push_back({(int32_t)c, scale * vals[k]});
+            rows[c].push_back({(int32_t)i, c128()});
+        }
+    }
+    std::vector<int64_t> rp(n + 1, 0);
+    std::vector<int32_t> ci;
+    std::vector<c128> val;
+    for (int64_t i = 0; i < n; ++i) {
+        auto &r = rows[i];
+        std::sort(r.begin(), r.end(), [](const std::pair<int32_t, c128> &x, const std::pair<int32_t, c128> &y) {
+            return x.first < y.first;
+        });
+        for (const auto &kv : r) {
+            if ((int64_t)ci.size() > rp[i] && ci.back() == kv.first) val.back() += kv.second;
+            else { ci.push_back(kv.first); val.push_back(kv.second); }
+        }
+        rp[i + 1] = (int64_t)ci.size();
+        std::vector<std::pair<int32_t, c128>>().swap(r);
+    }
+    // RWG edge midpoints place the unknowns for the dissection
+    const Mesh &m = p->mesh;
+    std::vector<double> xyz(3 * n);
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t a = m.edge_v[2 * (r0 + i)], c = m.edge_v[2 * (r0 + i) + 1];
+        for (int d = 0; d < 3; ++d) xyz[3 * i + d] = 0.5 * (m.xyz[3 * a + d] + m.xyz[3 * c + d]);
+    }
+    SparseLUHost h;
+    try {
+        lu_factor_host(h, n, rp, ci, val, xyz);
+    } catch (const Error &er) {
+        if (er.code == SIE_EINVAL) return false;   // too dense, or a vanishing pivot
+        throw;
+    }
+    lu_upload(h, out.f);
+    out.medium = medium;
+    out.r0 = r0;
+    out.n = n;
+    return true;
+}
+
 // ---------------------------------------------------------------- solve state
 struct SolveState {
     int nrhs = 0;
@@ -601,6 +676,13 @@ struct SolveState {
     bool pre_built = false;
     Schwarz sin;                   // near-region Schwarz preconditioner of the nested solves
     bool sin_built = false;
+    int sin_bits = 0;              // preconditioner bits it was built for
+    std::vector<std::unique_ptr<NearLU>> nlu;   // exact near-region factorisations (one per factored medium)
+    bool nlu_built = false;
+    bool nlu_covers_all = false;   // every RWG row belongs to a factored medium
+    int64_t nlu_nnz = 0;
+    double nlu_factor_s = 0.0;
+    DBuf<c128> nlu_work;           // [nrhs][n] right-hand sides in position order
     Gmres<double> go64, gi64;
     Gmres<float> go32, gi32;
     Gmres<double> goa;             // outer solve of the augmented EFIE (unknowns [u; sigma])
@@ -631,6 +713,31 @@ static int nested_dim(int restart, int inner_max_iter) {
 }
 
 // Operator set for nb right-hand sides at once: every vector is [nb][E].
+// Nested-solve preconditioner on nrhs vectors [nrhs][E]: Schwarz clusters
+// (rows of media without clusters copied) and/or the exact factorisations
+// of the media that have one; x and y must not alias.
+template <typename T>
+static void nested_apply(sie_problem *p, SolveState &s, bool ras, bool lu, int nrhs, const cx<T> *x, cx<T> *y,
+                         hipStream_t st) {
+    const int64_t E = p->mesh.nrwg;
+    const bool covered = (ras && s.sin.covers_all) || (lu && s.nlu_covers_all);
+    if (!covered) SIE_HIP(hipMemcpyAsync(y, x, (size_t)nrhs * E * sizeof(cx<T>), hipMemcpyDeviceToDevice, st));
+    if (ras) {
+        const Schwarz &w = s.sin;
+        launch_ras_apply<T>(w.nc, w.max_own, w.ext_off.p, w.ext.p, w.own_off.p, w.own.p, w.m_off.p, ras_m<T>(w), x, y,
+                            E, nrhs, st);
+    }
+    if (lu) {
+        for (const auto &f : s.nlu) {
+            const size_t need = (size_t)nrhs * f->n;
+            if (s.nlu_work.n < need) s.nlu_work.alloc(need);
+            launch_lu_gather<T>(f->n, f->r0, E, nrhs, f->f.iperm.p, x, s.nlu_work.p, st);
+            lu_solve(f->f, nrhs, s.nlu_work.p, st);
+            launch_lu_scatter<T>(f->n, f->r0, E, nrhs, f->f.iperm.p, s.nlu_work.p, y, st);
+        }
+    }
+}
+
 template <typename T>
 struct Ops {
     sie_problem *p;
@@ -704,15 +811,13 @@ struct Ops {
         }
         for (int k = 0; k < nb; ++k) launch_bj_apply<T>(b.nb, b.B, b.perm.p, bj_inv<T>(b), x + k * E, y + k * E, st);
     }
-    bool use_ras_in = false;
+    bool use_ras_in = false, use_lu_in = false;
     void prec_inner(const cx<T> *x, cx<T> *y) {
-        if (!use_ras_in) {
+        if (!use_ras_in && !use_lu_in) {
             bj(use_bj_in, s.pin, x, y);
             return;
         }
-        const Schwarz &w = s.sin;
-        if (!w.covers_all) SIE_HIP(hipMemcpyAsync(y, x, NE * sizeof(cx<T>), hipMemcpyDeviceToDevice, st));
-        launch_ras_apply<T>(w.nc, w.max_own, w.ext_off.p, w.ext.p, w.own_off.p, w.own.p, w.m_off.p, ras_m<T>(w), x, y, E, nb, st);
+        nested_apply<T>(p, s, use_ras_in, use_lu_in, nb, x, y, st);
     }
     void prec_outer(const cx<T> *x, cx<T> *y) { bj(use_bj_out, s.pout, x, y); }
     // Mixed precision: an FP64 operator set may delegate the interior work
@@ -894,10 +999,41 @@ static void build_preconditioners(sie_problem *p, SolveState &s, int precond) {
         bj_build(p, s.pout, {&p->ext}, {{0, p->mesh.nrwg}}, {c128(0.0, p->w) * p->ext.mu});
         s.pre_built = true;
     }
-    if ((precond & 4) && !s.sin_built) {
+    std::vector<char> factored(mi.size(), 0);
+    if (precond & 16) {
+        if (!s.nlu_built) {
+            const auto t0 = std::chrono::steady_clock::now();
+            int64_t rows = 0;
+            for (size_t i = 0; i < mi.size(); ++i) {
+                std::unique_ptr<NearLU> f(new NearLU);
+                if (near_lu_build(p, (int)i, ri[i].first, ri[i].second, si[i], *f)) {
+                    rows += f->n;
+                    s.nlu_nnz += f->f.nnz_factor;
+                    s.nlu.push_back(std::move(f));
+                }
+            }
+            s.nlu_covers_all = rows == p->mesh.nrwg;
+            s.nlu_built = true;
+            s.nlu_factor_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            if (std::getenv("SIE_TRACE"))
+                std::fprintf(stderr, "[setup] %-28s %8.1f ms (%zu media)\n", "near-region LU", 1e3 * s.nlu_factor_s,
+                             s.nlu.size());
+        }
+        for (const auto &f : s.nlu) factored[f->medium] = 1;
+    }
+    const int sin_bits = precond & (4 | 8 | 16);
+    if ((precond & 4) && (!s.sin_built || s.sin_bits != sin_bits)) {
         const auto t0 = std::chrono::steady_clock::now();
-        schwarz_build(p, s.sin, mi, ri, si, (precond & 8) != 0);
+        // clusters for the media without an exact factorisation
+        std::vector<Medium *> mr;
+        std::vector<std::pair<int64_t, int64_t>> rr;
+        std::vector<c128> sr;
+        for (size_t i = 0; i < mi.size(); ++i)
+            if (!factored[i]) { mr.push_back(mi[i]); rr.push_back(ri[i]); sr.push_back(si[i]); }
+        s.sin = Schwarz();
+        schwarz_build(p, s.sin, mr, rr, sr, (precond & 8) != 0);
         s.sin_built = true;
+        s.sin_bits = sin_bits;
         if (std::getenv("SIE_TRACE"))
             std::fprintf(stderr, "[setup] %-28s %8.1f ms\n", "Schwarz clusters",
                          std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
@@ -1021,6 +1157,7 @@ static void solve_all(sie_problem *p, sie_precision prec, const sie_solver_opts 
         o64.use_bj_in = (o.precond & 1) != 0;
         o64.use_bj_out = (o.precond & 2) != 0;
         o64.use_ras_in = (o.precond & 4) != 0 && s.sin.nc > 0;
+        o64.use_lu_in = (o.precond & 16) != 0 && !s.nlu.empty();
         c128 *e = s.e.p + r0 * E, *u = s.u.p + r0 * E, *v = s.v.p + r0 * E;
         const int64_t NE = (int64_t)cnt * E;
         // Refinement sweeps: residual of the block equations in FP64, correction
@@ -1035,6 +1172,7 @@ static void solve_all(sie_problem *p, sie_precision prec, const sie_solver_opts 
             o32->use_bj_in = o64.use_bj_in;
             o32->use_bj_out = o64.use_bj_out;
             o32->use_ras_in = o64.use_ras_in;
+            o32->use_lu_in = o64.use_lu_in;
             o64.lo = o32.get();
         }
         SIE_HIP(hipMemsetAsync(u, 0, NE * sizeof(c128), st));
@@ -1129,12 +1267,8 @@ template <typename T>
 static void nested_precond_apply(sie_problem *p, SolveState &s, int precond, int nrhs, const cx<T> *x, cx<T> *y,
                                  hipStream_t st) {
     const int64_t E = p->mesh.nrwg;
-    if (precond & 4) {
-        const Schwarz &w = s.sin;
-        if (!w.covers_all)
-            SIE_HIP(hipMemcpyAsync(y, x, (size_t)nrhs * E * sizeof(cx<T>), hipMemcpyDeviceToDevice, st));
-        launch_ras_apply<T>(w.nc, w.max_own, w.ext_off.p, w.ext.p, w.own_off.p, w.own.p, w.m_off.p, ras_m<T>(w), x, y, E, nrhs,
-                            st);
+    if (precond & (4 | 16)) {
+        nested_apply<T>(p, s, (precond & 4) != 0, (precond & 16) != 0, nrhs, x, y, st);
     } else {
         for (int k = 0; k < nrhs; ++k)
             launch_bj_apply<T>(s.pin.nb, s.pin.B, s.pin.perm.p, bj_inv<T>(s.pin), x + k * E, y + k * E, st);
@@ -1144,8 +1278,10 @@ static void nested_precond_apply(sie_problem *p, SolveState &s, int precond, int
 void nested_precond_entry(sie_problem *p, int precond, sie_precision prec, int nrhs, const void *x, void *y,
                           hipStream_t st) {
     SIE_CHECK(p && p->is_setup, SIE_ESTATE, "problem not set up");
-    SIE_CHECK(precond == 1 || precond == 4 || precond == 12, SIE_EINVAL,
-              "nested preconditioner must be 1 (block-Jacobi), 4 or 12 (Schwarz clusters)");
+    SIE_CHECK(precond == 1 || precond == 4 || precond == 12 || precond == 16 || precond == 20 || precond == 28,
+              SIE_EINVAL,
+              "nested preconditioner must be 1 (block-Jacobi), 4 or 12 (Schwarz clusters), 16 (near-region LU), "
+              "20 or 28 (LU where it applies, Schwarz clusters elsewhere)");
     SIE_CHECK(x && y && nrhs >= 1, SIE_EINVAL, "bad vectors");
     SIE_CHECK(x != y, SIE_EINVAL, "x and y must not alias");
     SIE_CHECK(prec == SIE_FP64 || prec == SIE_FP32, SIE_EINVAL, "unknown precision");
@@ -1156,6 +1292,13 @@ void nested_precond_entry(sie_problem *p, int precond, sie_precision prec, int n
         nested_precond_apply<double>(p, s, precond, nrhs, (const c128 *)x, (c128 *)y, st);
     else
         nested_precond_apply<float>(p, s, precond, nrhs, (const c64 *)x, (c64 *)y, st);
+}
+
+int nested_precond_factored(const sie_problem *p, int64_t *factor_nnz, double *t_factor_s) {
+    if (!p->solve || !p->solve->nlu_built) return -1;
+    if (factor_nnz) *factor_nnz = p->solve->nlu_nnz;
+    if (t_factor_s) *t_factor_s = p->solve->nlu_factor_s;
+    return (int)p->solve->nlu.size();
 }
 
 int nested_precond_clusters(const sie_problem *p, int64_t *owned) {
@@ -1216,9 +1359,11 @@ void solve_entry(sie_problem *p, sie_precision prec, const sie_solver_opts *opts
         SIE_CHECK(opts->inner_relax >= 0.0, SIE_EINVAL, "inner_relax must be non-negative");
         o.inner_relax = opts->inner_relax;
     }
-    SIE_CHECK(o.precond >= 0 && o.precond <= 15, SIE_EINVAL, "unknown preconditioner");
     SIE_CHECK(!(o.precond & 8) || (o.precond & 4), SIE_EINVAL, "preconditioner bit 8 extends bit 4");
     SIE_CHECK((o.precond & 5) != 5, SIE_EINVAL, "nested block-Jacobi (1) and nested Schwarz clusters (4) exclude each other");
+    SIE_CHECK((o.precond & 17) != 17, SIE_EINVAL,
+              "nested block-Jacobi (1) and the near-region LU (16) exclude each other");
+    SIE_CHECK(o.precond >= 0 && o.precond < 32, SIE_EINVAL, "unknown preconditioner bits");
     SIE_CHECK(o.restart <= 1000, SIE_EINVAL, "restart above 1000");
     solve_all(p, prec, o, rep);
 }

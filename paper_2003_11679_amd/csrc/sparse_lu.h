@@ -49,6 +49,16 @@ void lu_solve_host(const SparseLUHost &h, c128 *x);
 // x [nrhs][n] in position order: overwritten by the solution of (LU) x = b.
 void lu_solve(const SparseLU &f, int nrhs, c128 *x, hipStream_t st);
 
+// xp[r][iperm[j]] = x[r * E + r0 + j] (widened to FP64), j < n: rows
+// [r0, r0 + n) of nrhs vectors into position order.
+template <typename T>
+void launch_lu_gather(int64_t n, int64_t r0, int64_t E, int nrhs, const int32_t *iperm, const cx<T> *x, c128 *xp,
+                      hipStream_t st);
+// y[r * E + r0 + j] = xp[r][iperm[j]] (rounded to T).
+template <typename T>
+void launch_lu_scatter(int64_t n, int64_t r0, int64_t E, int nrhs, const int32_t *iperm, const c128 *xp, cx<T> *y,
+                       hipStream_t st);
+
 // Device side (k_lu.hip): one workgroup per supernode of a level.
 void launch_lu_level(const SparseLU &f, int level, bool forward, int nrhs, c128 *x, hipStream_t st);
 

@@ -130,6 +130,7 @@ SIGNATURES = [
     ("sie_interpolate", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int, _VP, _VP, _VP]),
     ("sie_nested_precond", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int, ctypes.c_int32, _VP, _VP, _VP]),
     ("sie_nested_precond_clusters", ctypes.c_int32, [_VP, _I64P]),
+    ("sie_nested_precond_factored", ctypes.c_int32, [_VP, _I64P, _DP]),
     ("sie_set_timing", ctypes.c_int, [_VP, ctypes.c_int32]),
     ("sie_get_stage_time", ctypes.c_int, [_VP, ctypes.c_int32, _I64P, _DP]),
     ("sie_set_planewaves", ctypes.c_int, [_VP, ctypes.c_int32, _DP, _CP]),
@@ -437,8 +438,10 @@ class Problem:
         return y
 
     def nested_precond(self, precond, x, y=None, stream=None):
-        """y = nested-solve preconditioner (1 block-Jacobi, 4 Schwarz
-        clusters) applied to x of shape [E] or [nrhs, E] on the device."""
+        """y = nested-solve preconditioner (1 block-Jacobi, 4 / 12 Schwarz
+        clusters, 16 exact near-region LU, 20 / 28 LU where it applies and
+        clusters elsewhere) applied to x of shape [E] or [nrhs, E] on the
+        device."""
         import torch
         prec = self._prec_of(x)
         x = x.contiguous()
@@ -455,6 +458,14 @@ class Problem:
         owned = ctypes.c_int64(0)
         n = lib().sie_nested_precond_clusters(self.h, ctypes.byref(owned))
         return int(n), int(owned.value)
+
+    def nested_precond_factored(self):
+        """(media with an exact near-region LU, factor entries, factor
+        seconds); media -1 before it is built."""
+        nnz = ctypes.c_int64(0)
+        t = ctypes.c_double(0.0)
+        n = lib().sie_nested_precond_factored(self.h, ctypes.byref(nnz), ctypes.byref(t))
+        return int(n), int(nnz.value), float(t.value)
 
     def project(self, medium, x, stream=None):
         import torch

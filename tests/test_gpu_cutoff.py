@@ -123,3 +123,37 @@ def test_all_near_bypass_matches_oracle():
             y = p.matvec(medium, code, xd).cpu().numpy()
             assert _rel(y, loc.matvec(x, name)) < 1e-10, (medium, name)
             assert _rel(y, full.matvec(x, name)) < 1e-10, (medium, name)
+
+
+def test_near_lu_on_the_cut_interior(box):
+    """precond 16 factors M_i = -j w eps_i L_i,NR of the cut interior exactly
+    (eq. nest2pc): parity with scipy's sparse solve of the oracle's direct
+    near-region operator, and one nested iteration per solve, because the
+    local interior operator is M_i itself."""
+    from scipy.sparse.linalg import spsolve
+    from oracle import physics as ph
+    p, m, inner, outer = box
+    scale = -1j * ph.omega(FREQ) * ph.eps_tilde(FREQ, 1.0, SIGMA)
+    A = (scale * inner.NLd).tocsc()
+    X = np.stack([vec(p.num_rwg, 60 + r) for r in range(2)])
+    ref = np.stack([spsolve(A, x) for x in X])
+    got = p.nested_precond(16, torch.from_numpy(X).to("cuda", torch.complex128)).cpu().numpy()
+    assert _rel(got, ref) < 1e-9
+    one = p.nested_precond(16, torch.from_numpy(X[1]).to("cuda", torch.complex128)).cpu().numpy()
+    assert np.array_equal(one, got[1])
+    nm, nnz, t = p.nested_precond_factored()
+    assert nm == 1 and nnz > 0, (nm, nnz, t)
+    x32 = X[0].astype(np.complex64)
+    got32 = p.nested_precond(16, torch.from_numpy(x32).to("cuda")).cpu().numpy()
+    assert _rel(got32, spsolve(A, x32.astype(np.complex128))) < 1e-6
+    p.set_planewaves((0.0, 0.0, -1.0), (1.0, 0.0, 0.0))
+    r0 = p.solve(0, tol=1e-8, precond=0)
+    u0, v0 = p.currents()
+    for prec in (0, 1):
+        r16 = p.solve(prec, tol=1e-8, precond=16)
+        u16, v16 = p.currents()
+        print(f"  prec {prec}: none {r0}\n  near LU {r16}", flush=True)
+        assert r0["converged"] and r16["converged"]
+        assert r16["inner_iters_max"] == 1, r16
+        tol = 1e-6 if prec == 0 else 2e-5   # FP32 + refinement against the FP64 solve
+        assert _rel(u16, u0) < tol and _rel(v16, v0) < tol

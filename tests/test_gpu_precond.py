@@ -83,3 +83,47 @@ def test_solve_with_schwarz_matches_unpreconditioned(prec):
     assert r0["converged"] and r4["converged"]
     assert np.abs(f4 - f0).max() < 1e-5 * np.abs(f0).max()
     assert r4["inner_iters_max"] < r0["inner_iters_max"]
+
+
+def test_near_lu_matches_spsolve():
+    """precond 16 on the copper bar (full near list, 936 RWG functions: the
+    factorisation ends in one dense front): parity with scipy's sparse solve
+    of the oracle's direct near-region operator, and a solve that agrees
+    with the Schwarz one in at most as many nested iterations."""
+    from scipy.sparse.linalg import spsolve
+    print("[precond near-region LU bar_small]", flush=True)
+    p = gpu_problem("bar_small")
+    op = oracle_aim("bar_small", 0)
+    build, eps_r, sigma, freq, n, R = CASES["bar_small"]
+    scale = -1j * ph.omega(freq) * ph.eps_tilde(freq, eps_r, sigma)
+    A = (scale * op.NLd).tocsc()
+    X = np.stack([vec(p.num_rwg, 50 + r) for r in range(2)])
+    ref = np.stack([spsolve(A, x) for x in X])
+    got = p.nested_precond(16, torch.from_numpy(X).to("cuda", torch.complex128)).cpu().numpy()
+    assert np.linalg.norm(got - ref) < 1e-8 * np.linalg.norm(ref)
+    nm, nnz, t = p.nested_precond_factored()
+    assert nm == 1 and nnz > 0
+    p.set_planewaves((0.0, 0.0, -1.0), (1.0, 0.0, 0.0))
+    th = np.linspace(0.0, np.pi, 13)
+    rhat = np.stack([np.sin(th), 0 * th, np.cos(th)], axis=1)
+    r4 = p.solve(0, tol=1e-8, restart=200, precond=4)
+    f4 = p.far_field(rhat)
+    r16 = p.solve(0, tol=1e-8, restart=200, precond=16)
+    f16 = p.far_field(rhat)
+    print(f"  schwarz {r4}\n  near LU {r16}", flush=True)
+    assert r4["converged"] and r16["converged"]
+    assert np.abs(f16 - f4).max() < 1e-5 * np.abs(f4).max()
+    assert r16["inner_iters"] <= r4["inner_iters"]
+
+
+def test_near_lu_options_validated():
+    from paper_2003_11679_amd import SieError
+    p = gpu_problem("bar_small")
+    p.set_planewaves((0.0, 0.0, -1.0), (1.0, 0.0, 0.0))
+    with pytest.raises(SieError):
+        p.solve(0, tol=1e-6, precond=17)
+    with pytest.raises(SieError):
+        p.solve(0, tol=1e-6, precond=32)
+    x = torch.zeros(p.num_rwg, dtype=torch.complex128, device="cuda")
+    with pytest.raises(SieError):
+        p.nested_precond(24, x)
