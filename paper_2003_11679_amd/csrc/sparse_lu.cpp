@@ -342,6 +342,20 @@ void lu_upload(const SparseLUHost &h, SparseLU &f) {
     up(f.uval, h.uval, c128());
     up(f.perm, h.perm, int32_t(0));
     up(f.iperm, h.iperm, int32_t(0));
+    std::vector<int32_t> bsn, brow;
+    f.blk_ptr.assign(1, 0);
+    for (size_t l = 0; l + 1 < h.lev_ptr.size(); ++l) {
+        for (int q = h.lev_ptr[l]; q < h.lev_ptr[l + 1]; ++q) {
+            const int32_t sn = h.lev_sn[q];
+            for (int r = 0; r < h.sn_n[sn]; r += kLURowsPerBlock) {
+                bsn.push_back(sn);
+                brow.push_back(r);
+            }
+        }
+        f.blk_ptr.push_back((int)bsn.size());
+    }
+    up(f.blk_sn, bsn, int32_t(0));
+    up(f.blk_row0, brow, int32_t(0));
 }
 
 void lu_solve_host(const SparseLUHost &h, c128 *x) {
@@ -376,6 +390,7 @@ void lu_solve_host(const SparseLUHost &h, c128 *x) {
 }
 
 void lu_solve(const SparseLU &f, int nrhs, c128 *x, hipStream_t st) {
+    if (f.work.n < (size_t)nrhs * f.n) f.work.alloc((size_t)nrhs * f.n);
     const int H = (int)f.lev_ptr.size() - 1;
     for (int l = 0; l < H; ++l) launch_lu_level(f, l, true, nrhs, x, st);
     for (int l = H - 1; l >= 0; --l) launch_lu_level(f, l, false, nrhs, x, st);

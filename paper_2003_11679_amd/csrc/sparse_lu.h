@@ -23,7 +23,15 @@ struct SparseLU {
     DBuf<int32_t> perm, iperm;         // position -> unknown, unknown -> position
     int64_t nnz_factor = 0;            // stored off-block entries of L and U
     double t_factor_s = 0.0;
+    // row blocks of the device solve: block b of level l (blk_ptr[l] <= b <
+    // blk_ptr[l + 1]) takes rows blk_row0[b] .. + kLURowsPerBlock - 1 of
+    // supernode blk_sn[b]
+    std::vector<int> blk_ptr;
+    DBuf<int32_t> blk_sn, blk_row0;
+    mutable DBuf<c128> work;           // [nrhs][n] gathered right-hand sides of a level
 };
+// Rows of one supernode per workgroup of the device solve (one wavefront each).
+constexpr int kLURowsPerBlock = 4;
 
 // The factors on the host (the device copy is SparseLU).
 struct SparseLUHost {
@@ -59,7 +67,9 @@ template <typename T>
 void launch_lu_scatter(int64_t n, int64_t r0, int64_t E, int nrhs, const int32_t *iperm, const c128 *xp, cx<T> *y,
                        hipStream_t st);
 
-// Device side (k_lu.hip): one workgroup per supernode of a level.
+// Device side (k_lu.hip): one level of the forward or backward sweep, two
+// launches (gather the solved levels' contributions into f.work, then the
+// dense inverses of the diagonal blocks), rows spread over workgroups.
 void launch_lu_level(const SparseLU &f, int level, bool forward, int nrhs, c128 *x, hipStream_t st);
 
 }  // namespace sie
