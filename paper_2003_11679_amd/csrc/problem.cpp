@@ -1272,11 +1272,26 @@ void problem_setup(sie_problem *p) {
     if (p->aug_mode == 1) p->aug.reset(new AugState);
     else p->aug.reset();
     build_medium(p, p->ext, 0);
-    if (p->aug) aug_setup(p);
     // interior media are independent: several host threads build them, each
     // on a stream of its own, so that their fills (many small launches per
-    // medium) overlap on the device
+    // medium) overlap on the device; the host factorisation of the augmented
+    // EFIE's Schur complement runs beside them on a thread of its own
     SIE_HIP(hipDeviceSynchronize());
+    std::thread aug_thread;
+    std::exception_ptr aug_err;
+    if (p->aug)
+        aug_thread = std::thread([&]() {
+            try {
+                SIE_HIP(hipSetDevice(p->ctx->device));
+                aug_setup(p);
+            } catch (...) {
+                aug_err = std::current_exception();
+            }
+        });
+    struct JoinAug {
+        std::thread &t;
+        ~JoinAug() { if (t.joinable()) t.join(); }
+    } join_aug{aug_thread};
     {
         const int nthr = std::max(1, std::min(kBuildThreads, m.nobj));
         std::atomic<int> next{0};
@@ -1303,7 +1318,9 @@ void problem_setup(sie_problem *p) {
         for (int t = 1; t < nthr; ++t) th.emplace_back(work);
         work();
         for (auto &t : th) t.join();
+        if (aug_thread.joinable()) aug_thread.join();
         if (err) std::rethrow_exception(err);
+        if (aug_err) std::rethrow_exception(aug_err);
     }
     finalize_groups(p);
     setup_mark("groups");

@@ -27,6 +27,10 @@
 // (at low frequency the k0 operator's vector potential is ~(k0 h)^2 below its
 // scalar potential and does not survive FP32) around FP32 nested solves.
 #include <algorithm>
+#include <atomic>
+#include <exception>
+#include <mutex>
+#include <thread>
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
@@ -463,8 +467,9 @@ struct ClusterLists {
     std::vector<int32_t> ext, own_off{0}, own, own_pos;
 };
 
-// Clusters of one medium over its RWG rows [r0, r1); false if an extended
-// cluster would exceed kRasMax functions at this cluster size.
+// Clusters of one medium over its RWG rows [r0, r1), into L (lists of this
+// medium alone, offsets from zero); false if an extended cluster would exceed
+// kRasMax functions at this cluster size.
 static bool cluster_medium(sie_problem *p, const Medium &md, int64_t r0, int64_t r1, int C, int O,
                            ClusterLists &L) {
     const Grid &g = *md.grid;
@@ -477,7 +482,7 @@ static bool cluster_medium(sie_problem *p, const Medium &md, int64_t r0, int64_t
         bucket[lin(x, y, z)].push_back((int32_t)r);
         clusters[lin(x / C, y / C, z / C)].push_back((int32_t)r);
     }
-    ClusterLists M = L;
+    ClusterLists M;
     for (const auto &kv : clusters) {
         const std::vector<int32_t> &ow = kv.second;
         const int bx = cell(ow[0], 0) / C * C, by = cell(ow[0], 1) / C * C, bz = cell(ow[0], 2) / C * C;
@@ -514,21 +519,56 @@ static bool cluster_medium(sie_problem *p, const Medium &md, int64_t r0, int64_t
 static void schwarz_build(sie_problem *p, Schwarz &sw, const std::vector<Medium *> &media,
                           const std::vector<std::pair<int64_t, int64_t>> &ranges, const std::vector<c128> &scales,
                           bool all_media) {
+    // each medium's clusters on the host threads, then joined in medium order
+    std::vector<ClusterLists> per(media.size());
+    {
+        std::atomic<size_t> next{0};
+        std::exception_ptr err;
+        std::mutex emu;
+        auto work = [&]() {
+            for (size_t i = next.fetch_add(1); i < media.size(); i = next.fetch_add(1)) {
+                try {
+                    const bool dominated = near_region_dominates(*media[i]);
+                    if (!dominated && !all_media) continue;
+                    const int64_t r0 = ranges[i].first, r1 = ranges[i].second;
+                    double l = 0.0;
+                    for (int64_t r = r0; r < r1; ++r) l += p->mesh.len[r];
+                    l /= (double)std::max<int64_t>(r1 - r0, 1);
+                    const int O0 = dominated ? std::max(1, (int)std::lround(3.0 * l / media[i]->grid->h)) : 2;
+                    bool done = false;
+                    for (int O = O0; O >= 1 && !done; --O)
+                        for (int C = 2 * O; C >= 1 && !done; --C)
+                            done = cluster_medium(p, *media[i], r0, r1, C, O, per[i]);
+                } catch (...) {
+                    std::lock_guard<std::mutex> lk(emu);
+                    if (!err) err = std::current_exception();
+                }
+            }
+        };
+        const int nthr = (int)std::max<size_t>(1, std::min<size_t>(16, media.size()));
+        std::vector<std::thread> th;
+        for (int t = 1; t < nthr; ++t) th.emplace_back(work);
+        work();
+        for (auto &t : th) t.join();
+        if (err) std::rethrow_exception(err);
+    }
     ClusterLists L;
-    std::vector<int> first, used;
+    std::vector<int> first;
     for (size_t i = 0; i < media.size(); ++i) {
         first.push_back((int)L.own_off.size() - 1);
-        used.push_back(0);
-        const bool dominated = near_region_dominates(*media[i]);
-        if (!dominated && !all_media) continue;
-        const int64_t r0 = ranges[i].first, r1 = ranges[i].second;
-        double l = 0.0;
-        for (int64_t r = r0; r < r1; ++r) l += p->mesh.len[r];
-        l /= (double)std::max<int64_t>(r1 - r0, 1);
-        const int O0 = dominated ? std::max(1, (int)std::lround(3.0 * l / media[i]->grid->h)) : 2;
-        for (int O = O0; O >= 1 && !used.back(); --O)
-            for (int C = 2 * O; C >= 1 && !used.back(); --C)
-                if (cluster_medium(p, *media[i], r0, r1, C, O, L)) used.back() = 1;
+        const ClusterLists &M = per[i];
+        const int64_t e0 = (int64_t)L.ext.size(), m0 = L.m_off.back(), w0 = L.ws_off.back();
+        const int32_t o0 = (int32_t)L.own.size();
+        L.ext.insert(L.ext.end(), M.ext.begin(), M.ext.end());
+        L.own.insert(L.own.end(), M.own.begin(), M.own.end());
+        L.own_pos.insert(L.own_pos.end(), M.own_pos.begin(), M.own_pos.end());
+        for (size_t k = 1; k < M.ext_off.size(); ++k) {
+            L.ext_off.push_back(e0 + M.ext_off[k]);
+            L.own_off.push_back(o0 + M.own_off[k]);
+            L.m_off.push_back(m0 + M.m_off[k]);
+            L.ws_off.push_back(w0 + M.ws_off[k]);
+        }
+        ClusterLists().ext.swap(per[i].ext);
     }
     first.push_back((int)L.own_off.size() - 1);
     sw.nc = (int)L.own_off.size() - 1;
