@@ -79,7 +79,8 @@ __global__ void k_dots_part(int64_t n, const cx<T> *__restrict__ V, int64_t ldv,
     if (threadIdx.x == 0) part[((int64_t)s * J + j) * nb + blockIdx.x] = c128(sre[0], sim[0]);
 }
 
-__global__ void k_dots_final(int J, const c128 *__restrict__ part, int nb, c128 *__restrict__ h, int hstride) {
+__global__ void k_dots_final(int J, const c128 *__restrict__ part, int nb, c128 *__restrict__ h, int hstride,
+                             c128 *__restrict__ hmirror) {
     __shared__ double sre[256], sim[256];
     const int j = blockIdx.x, s = blockIdx.y;
     const c128 *ps = part + ((int64_t)s * J + j) * nb;
@@ -91,24 +92,28 @@ __global__ void k_dots_final(int J, const c128 *__restrict__ part, int nb, c128 
         if ((int)threadIdx.x < k) { sre[threadIdx.x] += sre[threadIdx.x + k]; sim[threadIdx.x] += sim[threadIdx.x + k]; }
         __syncthreads();
     }
-    if (threadIdx.x == 0) h[(int64_t)s * hstride + j] = c128(sre[0], sim[0]);
+    if (threadIdx.x == 0) {
+        const c128 v(sre[0], sim[0]);
+        h[(int64_t)s * hstride + j] = v;
+        if (hmirror) hmirror[(int64_t)s * hstride + j] = v;
+    }
 }
 
 // part holds ns * J * nb partial sums.
 template <typename T>
 void launch_dots_sys(int64_t n, int J, const cx<T> *V, int64_t ldv, int ns, const cx<T> *w, c128 *part, int nb,
-                     c128 *h, int hstride, hipStream_t st) {
+                     c128 *h, int hstride, hipStream_t st, c128 *hmirror) {
     if (J <= 0 || ns <= 0) return;
     hipLaunchKernelGGL(k_dots_part<T>, dim3(nb, J, ns), dim3(256), 0, st, n, V, ldv, w, part, nb);
     SIE_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_dots_final, dim3(J, ns), dim3(256), 0, st, J, part, nb, h, hstride);
+    hipLaunchKernelGGL(k_dots_final, dim3(J, ns), dim3(256), 0, st, J, part, nb, h, hstride, hmirror);
     SIE_HIP(hipGetLastError());
 }
 
 template <typename T>
 void launch_dots(int64_t n, int J, const cx<T> *V, int64_t ldv, const cx<T> *w, c128 *part, int nb, c128 *h,
                  hipStream_t st) {
-    launch_dots_sys<T>(n, J, V, ldv, 1, w, part, nb, h, J, st);
+    launch_dots_sys<T>(n, J, V, ldv, 1, w, part, nb, h, J, st, nullptr);
 }
 
 // w[s] += SGN sum_j V_j[s] h[s * hstride + j].  A workgroup covers 64
@@ -239,7 +244,7 @@ template void launch_convert<double, double>(const c128 *, c128 *, int64_t, hipS
     template void launch_gemv_sub<T>(int64_t, int, const cx<T> *, int64_t, const c128 *, cx<T> *, hipStream_t); \
     template void launch_gemv_add<T>(int64_t, int, const cx<T> *, int64_t, const c128 *, cx<T> *, hipStream_t); \
     template void launch_dots_sys<T>(int64_t, int, const cx<T> *, int64_t, int, const cx<T> *, c128 *, int, c128 *, \
-                                     int, hipStream_t);                                                       \
+                                     int, hipStream_t, c128 *);                                               \
     template void launch_gemv_sys<T>(int64_t, int, const cx<T> *, int64_t, int, const c128 *, int, cx<T> *, bool, \
                                      hipStream_t);                                                            \
     template void launch_scale_sys<T>(int64_t, int, const c128 *, const cx<T> *, cx<T> *, hipStream_t);       \

@@ -324,6 +324,16 @@ static void keep_or_alloc(DBuf<T> &b, size_t n) {
     b.alloc(n);
 }
 
+// Kind of every near pair of a grid (self, edge, vertex, close, far), shared
+// by the media on the grid.
+static void pair_kinds(sie_problem *p, Grid &g, hipStream_t st) {
+    g.d_pair_kind.alloc(std::max<int64_t>(g.npairs, 1));
+    NearFillArgs a{};
+    a.xyz = p->d_xyz.p; a.tri = p->d_tri.p; a.tris = g.d_tris.p; a.centroid = p->d_centroid.p;
+    a.pair_ptr = g.d_pair_ptr.p; a.pair_s = g.d_pair_s.p; a.ntg = (int64_t)g.tris.size();
+    launch_pair_kinds(a, g.d_pair_kind.p, st);
+}
+
 // Precorrected near values and Green's spectra of one medium on its grid.
 static void build_medium(sie_problem *p, Medium &md, hipStream_t st) {
     Grid &g = *md.grid;
@@ -413,14 +423,7 @@ static void build_medium(sie_problem *p, Medium &md, hipStream_t st) {
     const int tab_w = g.near_radius + 1;
     const int64_t tab_row = (int64_t)(2 * tab_w + 1) * (2 * tab_w + 1) * (2 * tab_w + 1) * 10;
     const int64_t max_rows = std::max<int64_t>(1, (int64_t)(4e9 / (double)(tab_row * sizeof(c128))));
-    if (g.d_pair_kind.n != (size_t)std::max<int64_t>(g.npairs, 1)) {   // pair kinds: once per grid
-        g.d_pair_kind.alloc(std::max<int64_t>(g.npairs, 1));
-        NearFillArgs a{};
-        a.xyz = p->d_xyz.p; a.tri = p->d_tri.p; a.tris = g.d_tris.p; a.centroid = p->d_centroid.p;
-        a.pair_ptr = g.d_pair_ptr.p; a.pair_s = g.d_pair_s.p; a.ntg = ntg;
-        launch_pair_kinds(a, g.d_pair_kind.p, st);
-        setup_mark("fill: pair kinds");
-    }
+    SIE_CHECK(g.d_pair_kind.n == (size_t)std::max<int64_t>(g.npairs, 1), SIE_ESTATE, "pair kinds not classified");
     int64_t t0 = 0;
     while (t0 < ntg) {
         int64_t t1 = t0 + 1;
@@ -1271,11 +1274,17 @@ void problem_setup(sie_problem *p) {
     form_groups(p);
     if (p->aug_mode == 1) p->aug.reset(new AugState);
     else p->aug.reset();
+    // the exterior medium first (its fill fills the device by itself); then
+    // the interior media, independent of each other, from several host
+    // threads, each on a stream of its own, so that their fills (many small
+    // launches per medium) overlap on the device, and beside them the host
+    // factorisation of the augmented EFIE's Schur complement on a thread of
+    // its own.  (Building the exterior medium beside the interior ones was
+    // slower: the factorisation, which needs the exterior values, then
+    // started later.)
+    for (auto &g : p->grids) pair_kinds(p, *g, 0);
+    setup_mark("pair kinds");
     build_medium(p, p->ext, 0);
-    // interior media are independent: several host threads build them, each
-    // on a stream of its own, so that their fills (many small launches per
-    // medium) overlap on the device; the host factorisation of the augmented
-    // EFIE's Schur complement runs beside them on a thread of its own
     SIE_HIP(hipDeviceSynchronize());
     std::thread aug_thread;
     std::exception_ptr aug_err;

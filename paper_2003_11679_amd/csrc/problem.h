@@ -196,10 +196,12 @@ template <typename T> void launch_gemv_sub(int64_t n, int J, const cx<T> *V, int
 template <typename T> void launch_gemv_add(int64_t n, int J, const cx<T> *V, int64_t ldv, const c128 *h, cx<T> *w,
                                            hipStream_t st);
 // Batched forms for ns systems stored [ns][n] inside every vector (Krylov
-// vector j at V + j * ldv): dots into h[s * hstride + j], w[s] -+= V[s] h[s],
-// y[s] = c[s] x[s].
+// vector j at V + j * ldv): dots into h[s * hstride + j] (and, when hmirror
+// is not null, the same entries of hmirror, e.g. mapped host memory),
+// w[s] -+= V[s] h[s], y[s] = c[s] x[s].
 template <typename T> void launch_dots_sys(int64_t n, int J, const cx<T> *V, int64_t ldv, int ns, const cx<T> *w,
-                                           c128 *part, int nb, c128 *h, int hstride, hipStream_t st);
+                                           c128 *part, int nb, c128 *h, int hstride, hipStream_t st,
+                                           c128 *hmirror = nullptr);
 template <typename T> void launch_gemv_sys(int64_t n, int J, const cx<T> *V, int64_t ldv, int ns, const c128 *h,
                                            int hstride, cx<T> *w, bool add, hipStream_t st);
 template <typename T> void launch_scale_sys(int64_t n, int ns, const c128 *c, const cx<T> *x, cx<T> *y,

@@ -60,16 +60,19 @@ static const double PI = 3.14159265358979323846;
 // synchronisation; host-to-device coefficients copied without staging).
 struct PinnedC128 {
     c128 *p = nullptr;
+    c128 *dev = nullptr;   // the device's address of the same memory
     size_t n = 0;
-    void alloc(size_t k) {
+    void alloc(size_t k, unsigned flags = hipHostMallocDefault) {
         if (k <= n) return;
         release();
-        SIE_HIP(hipHostMalloc((void **)&p, k * sizeof(c128), hipHostMallocDefault));
+        SIE_HIP(hipHostMalloc((void **)&p, k * sizeof(c128), flags));
         n = k;
+        SIE_HIP(hipHostGetDevicePointer((void **)&dev, p, 0));
     }
     void release() {
         if (p) (void)hipHostFree(p);
         p = nullptr;
+        dev = nullptr;
         n = 0;
     }
     PinnedC128() = default;
@@ -86,7 +89,7 @@ struct Gmres {
     int dblk = 1;                   // dot-product blocks per system
     DBuf<cx<T>> V, Zb, w, r;        // V: (m+1) x [nb][n], Zb: m x [nb][n], w, r: [nb][n]
     DBuf<c128> part, hd, cd;        // hd: 4 slots of [nb][m + 1] dot results
-    PinnedC128 hh;                  // host copy of the 4 slots of hd
+    PinnedC128 hh;                  // host copy of the 4 slots of hd (written by the dot kernels)
     PinnedC128 hc;                  // [nb] scaling coefficients (batches wider than kScaleArg)
     PinnedC128 hy;                  // [nb][m + 1] least-squares solutions
     hipEvent_t hc_done = nullptr;   // last copy out of hc
@@ -115,7 +118,7 @@ struct Gmres {
         part.alloc((size_t)nb * (m + 1) * dblk);
         hd.alloc(4 * slot());
         cd.alloc(nb);
-        hh.alloc(4 * slot());
+        hh.alloc(4 * slot(), hipHostMallocMapped | hipHostMallocCoherent);
         hy.alloc(slot());
         hc.alloc(nb);
         if (!hc_done) SIE_HIP(hipEventCreateWithFlags(&hc_done, hipEventDisableTiming));
@@ -144,18 +147,22 @@ struct Gmres {
         SIE_HIP(e);
     }
     // Device slot sl of hd receives h[s][j] = V_j[s]^H x[s], j < J
-    // (V_j at Vp + j * nb * n); returns it.
+    // (V_j at Vp + j * nb * n), and so does the same slot of the host's hh
+    // (the final dot kernel writes both: no copy launch); returns the device
+    // slot.
     c128 *dots_dev(int J, const cx<T> *Vp, const cx<T> *x, int sl, hipStream_t st) {
         c128 *h = hd.p + (size_t)sl * slot();
-        launch_dots_sys<T>(n, J, Vp, (int64_t)nb * n, nb, x, part.p, dblk, h, m + 1, st);
+        launch_dots_sys<T>(n, J, Vp, (int64_t)nb * n, nb, x, part.p, dblk, h, m + 1, st, hh.dev + (size_t)sl * slot());
         return h;
     }
     // h[s][j] = V_j[s]^H x[s], j < J
     std::vector<c128> dots(int J, const cx<T> *Vp, const cx<T> *x, hipStream_t st) {
-        const c128 *h = dots_dev(J, Vp, x, 0, st);
-        SIE_HIP(hipMemcpyAsync(hh.p, h, slot() * sizeof(c128), hipMemcpyDeviceToHost, st));
+        dots_dev(J, Vp, x, 0, st);
         wait(st);
-        return std::vector<c128>(hh.p, hh.p + slot());
+        std::vector<c128> out(slot(), c128());
+        for (int k = 0; k < nb; ++k)
+            std::copy(hh.p + (size_t)k * (m + 1), hh.p + (size_t)k * (m + 1) + J, out.begin() + (size_t)k * (m + 1));
+        return out;
     }
     std::vector<double> norms(const cx<T> *x, hipStream_t st) {
         std::vector<c128> h = dots(1, x, x, st);
@@ -269,10 +276,7 @@ struct Gmres {
                 launch_gemv_sys<T>(n, j + 1, V.p, blk, nb, d2, m + 1, w.p, false, st);
                 dots_dev(1, w.p, w.p, 2, st);
                 const bool read_b = pending && j == 0;
-                // the first j + 1 entries of each system's rows of the slots
-                // (all the host reads), not the whole [nb][m + 1] slots
-                SIE_HIP(hipMemcpy2DAsync(hh.p, ld * sizeof(c128), hd.p, ld * sizeof(c128), (j + 1) * sizeof(c128),
-                                         (size_t)(read_b ? 4 : 3) * nb, hipMemcpyDeviceToHost, st));
+                // the dot kernels have written the host's copies of the slots
                 wait(st);
                 c128 *h1 = hh.p;
                 const c128 *h2 = hh.p + sl, *h3 = hh.p + 2 * sl;
