@@ -625,8 +625,8 @@ def dominant_kernel(tm, model, prec):
     """The near-field CSR launch class with the largest measured time, with
     its HIP-event average and algorithmic bytes."""
     ext64 = (tm["spmv64"][0] - tm["spmv_int64"][0], tm["spmv64"][1] - tm["spmv_int64"][1])
-    ext32 = (tm["spmv"][0] - tm["spmv64"][0] - tm["spmv_int32"][0],
-             tm["spmv"][1] - tm["spmv64"][1] - tm["spmv_int32"][1])
+    ext32 = (tm["spmv"][0] - tm["spmv64"][0] - tm["spmv_int32"][0] - tm["spmv_skip"][0],
+             tm["spmv"][1] - tm["spmv64"][1] - tm["spmv_int32"][1] - tm["spmv_skip"][1])
     cls = {"interior media": (tm["spmv_int32"] if prec == 1 else tm["spmv_int64"],
                               model["interior"] if prec == 1 else model["interior64"], prec == 1),
            "exterior medium": (ext64, model["exterior64"], False)}
@@ -690,7 +690,7 @@ def secondary_request(args, name, nreq):
     cfg = workload_cfg(name)
     opts = dict(restart=1000, precond=DEFAULT_PRECOND.get(name, 4), inner_relax=args.inner_relax)
     tol = DEFAULT_TOL.get(name, 1e-6)
-    tm = {k: [0, 0.0] for k in ("spmv", "spmv64", "spmv_int32", "spmv_int64")}
+    tm = {k: [0, 0.0] for k in ("spmv", "spmv64", "spmv_int32", "spmv_int64", "spmv_skip")}
     lat, reps, setups, gate, model = [], [], [], None, None
     for i in range(nreq):
         p, rep, su, tot = run_request(cfg, 1, tol, timing=True, opts=opts)
@@ -744,7 +744,7 @@ def request_workload(args):
         del p
     torch.cuda.synchronize()
     lat, matvecs, kmatvecs, setups, reps = [], 0, 0, [], []
-    tm = {k: [0, 0.0] for k in ("spmv", "spmv64", "spmv_int32", "spmv_int64")}
+    tm = {k: [0, 0.0] for k in ("spmv", "spmv64", "spmv_int32", "spmv_int64", "spmv_skip")}
     t0 = time.perf_counter()
     for i in range(args.steps):
         p, rep, su, tot = run_request(cfg, prec, args.tol, timing=True)

@@ -128,6 +128,15 @@ typedef struct {
                             the fixed tolerance (default).  The FP64 block
                             residual of every refinement sweep still decides
                             convergence. */
+    int32_t keep_converged; /* nested solves with one system per object
+                            (objects of equal RWG counts) iterate the
+                            objects' systems side by side; once a system has
+                            converged its rows of the nested products are
+                            zero and are skipped (near-field product and
+                            Schwarz clusters write zeros without reading
+                            their values; such products are not counted in
+                            sie_report.matvecs).  1 keeps multiplying them
+                            (same results, more work); default 0 */
 } sie_solver_opts;
 
 typedef struct {
@@ -411,7 +420,9 @@ sie_status sie_constraint_precond(sie_problem *p, int32_t nrhs, const void *x_de
  * near-field CSR products alone (also counted in 3), 6 and 7 the near-field
  * CSR products of the interior media inside solves (the nested operator of
  * eq. nest2, one launch per group of media) in FP32 and FP64 (also counted
- * in 3, and 7 in 5).  Query returns the
+ * in 3, and 7 in 5), 8 the interior near-field products of nested solves
+ * that skip the rows of objects whose systems have converged (counted in 3
+ * only, not in 5, 6 or 7).  Query returns the
  * number of timed launches and their summed duration (synchronises). */
 sie_status sie_set_timing(sie_problem *p, int32_t on);
 sie_status sie_get_stage_time(sie_problem *p, int32_t stage, int64_t *launches, double *total_ms);

@@ -270,6 +270,11 @@ struct GridView {
     const uint16_t *cols16 = nullptr;
     const int32_t *row_base = nullptr;
     bool c16 = false;
+    // optional: the near-field product writes zero rows, without reading
+    // their values, for the slots s with !active[obj0 + s] (slot s holds
+    // object obj0 + s; one right-hand side)
+    const uint8_t *active = nullptr;
+    int obj0 = 0;
     int64_t nrow() const { return rwg1 - rwg0; }
     int64_t nnodes() const { return nlive * nslot; }
 };

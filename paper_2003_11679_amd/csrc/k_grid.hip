@@ -154,9 +154,13 @@ template <typename T>
 __global__ void k_project(int64_t nnodes, int64_t nlive, const int32_t *__restrict__ node_ptr,
                           const int32_t *__restrict__ ent, const T *__restrict__ mom, const cx<T> *__restrict__ src,
                           cx<T> *__restrict__ grid, int nf, int lpn, int64_t ntg, const cx<T> *__restrict__ rho,
-                          int64_t ldr, const int32_t *__restrict__ rho_tris) {
+                          int64_t ldr, const int32_t *__restrict__ rho_tris, const uint8_t *__restrict__ active,
+                          int obj0) {
     const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t v = gid / lpn;
+    // nodes of inactive slots are left as they are: nothing downstream
+    // reads them (uniform over the node's lanes)
+    if (active && v < nnodes && !active[obj0 + (int)(v / nlive)]) return;
     src += blockIdx.y * 4 * ntg;           // right-hand side blockIdx.y
     grid += blockIdx.y * nf * nnodes;
     if (rho) rho += blockIdx.y * ldr;
@@ -211,7 +215,7 @@ void launch_project(const GridView &g, const T *mom, const cx<T> *trisrc, cx<T> 
         const int bs = kStageBlocks[c];
         hipLaunchKernelGGL(k_project<T>, dim3((unsigned)((threads + bs - 1) / bs), (unsigned)nrhs), dim3(bs), 0, st,
                            nnodes, g.nlive, g.node_ptr, g.node_ent, mom, trisrc, grid, nfields, lpn, g.ntg, rho, ldr,
-                           rho_tris);
+                           rho_tris, nrhs == 1 ? g.active : nullptr, g.obj0);
         SIE_HIP(hipGetLastError());
         return true;
     };
@@ -226,9 +230,13 @@ void launch_project(const GridView &g, const T *mom, const cx<T> *trisrc, cx<T> 
 template <typename T>
 __global__ void k_interp(int64_t ntg, const int32_t *__restrict__ centre, const int32_t *__restrict__ tri_slot,
                          int lox, int loy, int loz, int nlx, int nly, int64_t nlive, int64_t nnodes,
-                         const T *__restrict__ mom, const cx<T> *__restrict__ pot, int nf, cx<T> *__restrict__ out) {
+                         const T *__restrict__ mom, const cx<T> *__restrict__ pot, int nf, cx<T> *__restrict__ out,
+                         const uint8_t *__restrict__ active, int obj0) {
     int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= ntg) return;
+    // triangles of inactive slots: their rows of the near-field product are
+    // zero and do not read these partials
+    if (active && !active[obj0 + (tri_slot ? tri_slot[t] : 0)]) return;
     pot += blockIdx.y * nf * nnodes;       // right-hand side blockIdx.y
     if (tri_slot) pot += (int64_t)tri_slot[t] * nf * nlive;
     out += blockIdx.y * 5 * ntg;
@@ -259,7 +267,7 @@ void launch_interp(const GridView &g, const T *mom, const cx<T> *pot, int nfield
         const int bs = kStageBlocks[c];
         hipLaunchKernelGGL(k_interp<T>, dim3((unsigned)((ntg + bs - 1) / bs), (unsigned)nrhs), dim3(bs), 0, st, ntg,
                            g.centre, g.tri_slot, g.lo[0], g.lo[1], g.lo[2], g.nl[0], g.nl[1], g.nlive, g.nnodes(),
-                           mom, pot, nfields, tripot);
+                           mom, pot, nfields, tripot, nrhs == 1 ? g.active : nullptr, g.obj0);
         SIE_HIP(hipGetLastError());
         return true;
     };
@@ -341,11 +349,19 @@ __global__ void k_spmv_far(int64_t nrow, int64_t rwg0, const int64_t *__restrict
                            const int32_t *__restrict__ rwg_loc, const T *__restrict__ coef,
                            const cx<T> *__restrict__ tripot, const int32_t *__restrict__ tri_slot,
                            const cx<T> *__restrict__ kscal, const cx<T> *__restrict__ alpha,
-                           const cx<T> *__restrict__ x, cx<T> *__restrict__ y, int use_far) {
+                           const cx<T> *__restrict__ x, cx<T> *__restrict__ y, int use_far,
+                           const uint8_t *__restrict__ active, int obj0) {
     const int lane = threadIdx.x & 63;
     const int64_t r = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
     if (r >= nrow) return;
     const int64_t row = rwg0 + r;
+    if (active) {   // a row of an inactive slot is zero (uniform over the wavefront)
+        const int slot = tri_slot ? tri_slot[rwg_loc[2 * r] >> 2] : 0;
+        if (!active[obj0 + slot]) {
+            if (lane == 0) y[row] = cx<T>();
+            return;
+        }
+    }
     cx<T> acc;
     cx<T> al(T(1));
     if (lane < 2 && (use_far || alpha)) {
@@ -438,7 +454,8 @@ void launch_spmv_far(const GridView &g, const T *tri_coef, const cx<T> *tripot, 
                      (g.c16 ? (uintptr_t)g.cols16 % 4 == 0 : (uintptr_t)g.cols % 8 == 0);
 #define SIE_SPMV(C, V)                                                                                              \
     hipLaunchKernelGGL((k_spmv_far<T, C, V>), grid, dim3(256), 0, st, nrow, g.rwg0, g.row_ptr, g.cols, g.cols16,     \
-                       g.row_base, vals, g.rwgloc, tri_coef, tripot, g.tri_slot, kscal, alpha, x, y, use_far ? 1 : 0)
+                       g.row_base, vals, g.rwgloc, tri_coef, tripot, g.tri_slot, kscal, alpha, x, y, use_far ? 1 : 0, \
+                       g.active, g.obj0)
     if constexpr (sizeof(T) == 4) {
         if (g.c16) {
             if (vec) SIE_SPMV(true, true);

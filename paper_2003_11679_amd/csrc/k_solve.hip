@@ -448,11 +448,15 @@ void launch_ras_setup(int c0, int cnt, const int64_t *ext_off, const int32_t *ex
 // staged in LDS, one wave per owned row (lanes over the extended set).
 constexpr int kRasRows = 16;
 
+// active (optional, [nrhs][nobj]): the owned rows of a cluster whose object
+// cobj[c] is inactive for the right-hand side are written zero.
 template <typename T>
 __global__ __launch_bounds__(256) void k_ras_apply(const int64_t *__restrict__ ext_off, const int32_t *__restrict__ ext,
                                                    const int32_t *__restrict__ own_off, const int32_t *__restrict__ own,
                                                    const int64_t *__restrict__ m_off, const cx<T> *__restrict__ M,
-                                                   const cx<T> *__restrict__ x, cx<T> *__restrict__ y, int64_t ld) {
+                                                   const cx<T> *__restrict__ x, cx<T> *__restrict__ y, int64_t ld,
+                                                   const uint8_t *__restrict__ active, int nobj,
+                                                   const int32_t *__restrict__ cobj) {
     __shared__ __align__(16) T lds[2 * kRasMax];
     cx<T> *xs = reinterpret_cast<cx<T> *>(lds);
     const int c = blockIdx.x;
@@ -462,6 +466,11 @@ __global__ __launch_bounds__(256) void k_ras_apply(const int64_t *__restrict__ e
     if (q0 >= no) return;                      // uniform over the workgroup
     x += blockIdx.z * ld;
     y += blockIdx.z * ld;
+    if (active && !active[(int64_t)blockIdx.z * nobj + cobj[c]]) {   // uniform over the workgroup
+        const int q1 = min(no, q0 + kRasRows);
+        for (int q = q0 + (int)threadIdx.x; q < q1; q += blockDim.x) y[own[o0 + q]] = cx<T>();
+        return;
+    }
     const int64_t e0 = ext_off[c];
     const int n = (int)(ext_off[c + 1] - e0);
     for (int i = threadIdx.x; i < n; i += blockDim.x) xs[i] = x[ext[e0 + i]];
@@ -498,19 +507,19 @@ __global__ __launch_bounds__(256) void k_ras_apply(const int64_t *__restrict__ e
 template <typename T>
 void launch_ras_apply(int nc, int max_own, const int64_t *ext_off, const int32_t *ext, const int32_t *own_off,
                       const int32_t *own, const int64_t *m_off, const cx<T> *M, const cx<T> *x, cx<T> *y, int64_t ld,
-                      int nrhs, hipStream_t st) {
+                      int nrhs, hipStream_t st, const uint8_t *active, int nobj, const int32_t *cobj) {
     if (nc <= 0 || nrhs <= 0 || max_own <= 0) return;
     SIE_CHECK(nrhs <= 65535, SIE_EINVAL, "too many right-hand sides for one preconditioner launch");
     const dim3 grid((unsigned)nc, (unsigned)((max_own + kRasRows - 1) / kRasRows), (unsigned)nrhs);
-    hipLaunchKernelGGL(k_ras_apply<T>, grid, dim3(256), 0, st, ext_off, ext, own_off, own, m_off, M, x, y, ld);
+    hipLaunchKernelGGL(k_ras_apply<T>, grid, dim3(256), 0, st, ext_off, ext, own_off, own, m_off, M, x, y, ld, active, nobj, cobj);
     SIE_HIP(hipGetLastError());
 }
 
 template void launch_ras_apply<float>(int, int, const int64_t *, const int32_t *, const int32_t *,
                                       const int32_t *, const int64_t *, const c64 *, const c64 *, c64 *, int64_t,
-                                      int, hipStream_t);
+                                      int, hipStream_t, const uint8_t *, int, const int32_t *);
 template void launch_ras_apply<double>(int, int, const int64_t *, const int32_t *, const int32_t *,
                                        const int32_t *, const int64_t *, const c128 *, const c128 *, c128 *,
-                                       int64_t, int, hipStream_t);
+                                       int64_t, int, hipStream_t, const uint8_t *, int, const int32_t *);
 
 }  // namespace sie

@@ -875,8 +875,9 @@ template <typename T>
 static void run_product(sie_problem *p, const GridView &v, const MediaView<T> &mv, sie_op op, int nrhs,
                         const cx<T> *x, cx<T> *y, const ProductBufs<T> &b, cx<T> *xt, StageTimer *tm,
                         hipStream_t st, bool interior = false) {
-    const int x64 = sizeof(T) == 8 ? ST_SPMV64 : -1;
-    const int xint = interior ? (sizeof(T) == 8 ? ST_INT64 : ST_INT32) : -1;
+    // launches that skip the rows of inactive objects go to their own class
+    const int x64 = v.active ? ST_SKIP : (sizeof(T) == 8 ? ST_SPMV64 : -1);
+    const int xint = interior && !v.active ? (sizeof(T) == 8 ? ST_INT64 : ST_INT32) : -1;
     const int64_t E = p->mesh.nrwg;
     const int F = op == SIE_OP_L ? 4 : 3;
     const int nf = F * v.nslot * nrhs;
@@ -941,12 +942,13 @@ void matvec(sie_problem *p, Medium &md, sie_op op, int nrhs, const cx<T> *x, cx<
 
 template <typename T>
 void group_product(sie_problem *p, Group &gr, sie_op op, bool scaled, int nrhs, const cx<T> *x, cx<T> *y,
-                   hipStream_t st) {
+                   hipStream_t st, const uint8_t *active) {
     const int64_t E = p->mesh.nrwg;
     if (gr.media.size() == 1) {
         Medium &md = p->ints[gr.media[0]];
         Grid &g = *md.grid;
-        const GridView v = view_of(g);
+        GridView v = view_of(g);
+        if (nrhs == 1 && active) { v.active = active; v.obj0 = gr.media[0]; }
         Work<T> &w = work_sel<T>(g);
         ensure_work(v, w, nrhs, E);
         run_product<T>(p, v, media_of<T>(md, scaled), op, nrhs, x, y, bufs_of(w), w.xt.p, &p->timer, st, true);
@@ -954,7 +956,9 @@ void group_product(sie_problem *p, Group &gr, sie_op op, bool scaled, int nrhs, 
     }
     Work<T> &w = work_sel<T>(gr);
     ensure_work(gr.view, w, nrhs, E);
-    run_product<T>(p, gr.view, media_of<T>(gr, scaled), op, nrhs, x, y, bufs_of(w), w.xt.p, &p->timer, st, true);
+    GridView v = gr.view;
+    if (nrhs == 1 && active) { v.active = active; v.obj0 = gr.media[0]; }
+    run_product<T>(p, v, media_of<T>(gr, scaled), op, nrhs, x, y, bufs_of(w), w.xt.p, &p->timer, st, true);
 }
 
 template <typename T>
@@ -1010,7 +1014,7 @@ void stage_interpolate(sie_problem *p, Medium &md, const cx<T> *grid, cx<T> *y, 
 #define SIE_INST_MV(T)                                                                                     \
     template void matvec<T>(sie_problem *, Medium &, sie_op, int, const cx<T> *, cx<T> *, hipStream_t);    \
     template void group_product<T>(sie_problem *, Group &, sie_op, bool, int, const cx<T> *, cx<T> *,       \
-                                   hipStream_t);                                                           \
+                                   hipStream_t, const uint8_t *);                                          \
     template void product_one<T>(sie_problem *, Medium &, sie_op, const cx<T> *, cx<T> *, const ProductBufs<T> &, \
                                  StageTimer *, hipStream_t);                                               \
     template void stage_project<T>(sie_problem *, Medium &, const cx<T> *, cx<T> *, hipStream_t);          \

@@ -44,9 +44,12 @@ struct SolveState;     // solver.cpp
 // ST_SPMV as well).
 // ST_INT32 / ST_INT64 count the interior media's near-field products (the
 // nested operator's, through the product groups) once more, per precision.
+// ST_SKIP counts, instead of ST_SPMV64 / ST_INT32 / ST_INT64, the interior
+// products that skip the rows of objects whose nested systems have
+// converged (in ST_SPMV as well).
 enum Stage {
     ST_PROJECT = 0, ST_FFT = 1, ST_INTERP = 2, ST_SPMV = 3, ST_PRODUCT = 4, ST_SPMV64 = 5, ST_INT32 = 6,
-    ST_INT64 = 7, NSTAGE = 8
+    ST_INT64 = 7, ST_SKIP = 8, NSTAGE = 9
 };
 struct StageTimer {
     int on = 0;   // 0 off, 1 every stage, 2 the near-field CSR product alone
@@ -133,10 +136,13 @@ template <typename T>
 void matvec(sie_problem *p, Medium &md, sie_op op, int nrhs, const cx<T> *x, cx<T> *y, hipStream_t st);
 // The product of every medium of a group on the group's rows (others not
 // written), times -j w eps~_i per medium when `scaled` (the nested
-// operator of eq. nest2).
+// operator of eq. nest2).  active (optional, one right-hand side, indexed
+// by object): the near-field product writes zero rows for the objects with
+// active[object] == 0, whose rows of x must be zero (their grid stages
+// still run, on zero sources).
 template <typename T>
 void group_product(sie_problem *p, Group &gr, sie_op op, bool scaled, int nrhs, const cx<T> *x, cx<T> *y,
-                   hipStream_t st);
+                   hipStream_t st, const uint8_t *active = nullptr);
 // Stage intermediates of one single-right-hand-side product: grid sources
 // and potentials [F][nlive], the FFT pass buffers, per-triangle projection
 // coefficients [ntg][4] and interpolation partials [ntg][5].

@@ -28,8 +28,11 @@ struct RasSource {
 void launch_ras_setup(int c0, int cnt, const int64_t *ext_off, const int32_t *ext, const int32_t *own_off,
                       const int32_t *own_pos, const int64_t *ws_off, const int64_t *m_off, const int32_t *cmed,
                       const RasSource *src, c128 *ws, c128 *m64, c64 *m32, int *fail, hipStream_t st);
+// active (optional, [nrhs][nobj]): clusters whose object cobj[c] is
+// inactive for a right-hand side write zeros to their owned rows.
 template <typename T>
 void launch_ras_apply(int nc, int max_own, const int64_t *ext_off, const int32_t *ext, const int32_t *own_off,
                       const int32_t *own, const int64_t *m_off, const cx<T> *M, const cx<T> *x, cx<T> *y, int64_t ld,
-                      int nrhs, hipStream_t st);
+                      int nrhs, hipStream_t st, const uint8_t *active = nullptr, int nobj = 0,
+                      const int32_t *cobj = nullptr);
 }  // namespace sie

@@ -98,6 +98,10 @@ struct Gmres {
     std::vector<c128> H;            // [nb][m + 1][m] Hessenberg matrices, kept between solves
     std::vector<double> live;       // [nb] residual estimate of the running solve, per step
     using Op = std::function<void(const cx<T> *, cx<T> *)>;
+    // Called before the products of every Arnoldi step with the systems
+    // still iterating (act[k] != 0); the others' basis vectors are zero, so
+    // the products may write zeros for them without computing.
+    std::function<void(const std::vector<char> &)> on_active;
     const char *tag = "gmres";
     // Stagnation window: a system that gains under 1 % over this many
     // iterations hands back to the caller (the precision floor of an FP32
@@ -197,6 +201,7 @@ struct Gmres {
               std::vector<double> *relres, hipStream_t st, int *napply = nullptr, bool x_zero = false,
               bool trust_estimate = false) {
         static const bool trace = std::getenv("SIE_TRACE") != nullptr;
+        static const bool trace_sys = std::getenv("SIE_TRACE_SYSTEMS") != nullptr;
         const size_t ld = (size_t)m + 1, sl = slot(), mm = ld * m;
         const bool defer = x_zero && maxit > 0;
         std::vector<char> fin(nb, 0);
@@ -236,6 +241,7 @@ struct Gmres {
                 if (first && x_zero) {
                     SIE_HIP(hipMemcpyAsync(r.p, b, (size_t)nb * n * sizeof(cx<T>), hipMemcpyDeviceToDevice, st));
                 } else {
+                    if (on_active) on_active(std::vector<char>(nb, 1));   // the product of every system
                     A(x, r.p);
                     if (napply) ++*napply;
                     launch_axpby<T>((int64_t)nb * n, c128(1.0), b, c128(-1.0), r.p, st);
@@ -264,6 +270,7 @@ struct Gmres {
             int j = 0;
             for (; j < m && it < maxit; ++j, ++it) {
                 cx<T> *vj = V.p + (size_t)j * blk, *zj = Zb.p + (size_t)j * blk;
+                if (on_active) on_active(act);
                 M(vj, zj);
                 A(zj, w.p);
                 if (napply) ++*napply;
@@ -370,7 +377,13 @@ struct Gmres {
         }
         if (relres) *relres = res;
         int itmax = 0;
-        for (int k = 0; k < nb; ++k) itmax = std::max(itmax, (int)hist[k].size());
+        int64_t itsum = 0;
+        for (int k = 0; k < nb; ++k) {
+            itmax = std::max(itmax, (int)hist[k].size());
+            itsum += (int64_t)hist[k].size();
+        }
+        if (trace_sys)
+            std::fprintf(stderr, "[%s] systems %d iterations max %d sum %lld\n", tag, nb, itmax, (long long)itsum);
         return itmax;
     }
 };
@@ -446,6 +459,7 @@ struct Schwarz {
     int64_t owned = 0;
     DBuf<int64_t> ext_off, m_off;  // [nc + 1]
     DBuf<int32_t> ext, own_off, own;
+    DBuf<int32_t> cobj;            // [nc] object of each cluster
     DBuf<c128> m64;
     DBuf<c64> m32;
 };
@@ -603,6 +617,9 @@ static void schwarz_build(sie_problem *p, Schwarz &sw, const std::vector<Medium 
     d_src.upload(src);
     DBuf<int32_t> d_cmed;
     d_cmed.upload(cmed);
+    std::vector<int32_t> cobj(sw.nc);
+    for (int c = 0; c < sw.nc; ++c) cobj[c] = (int32_t)media[cmed[c]]->id;
+    sw.cobj.upload(cobj);
     // batches of consecutive clusters (of any media) within the workspace
     // budget, at least one cluster each
     size_t fr = 0, tot = 0;
@@ -760,16 +777,18 @@ static int nested_dim(int restart, int inner_max_iter) {
 // Nested-solve preconditioner on nrhs vectors [nrhs][E]: Schwarz clusters
 // (rows of media without clusters copied) and/or the exact factorisations
 // of the media that have one; x and y must not alias.
+// active (optional, [nrhs][objects]): the Schwarz clusters of inactive
+// objects write zeros (their rows of x are zero).
 template <typename T>
 static void nested_apply(sie_problem *p, SolveState &s, bool ras, bool lu, int nrhs, const cx<T> *x, cx<T> *y,
-                         hipStream_t st) {
+                         hipStream_t st, const uint8_t *active = nullptr) {
     const int64_t E = p->mesh.nrwg;
     const bool covered = (ras && s.sin.covers_all) || (lu && s.nlu_covers_all);
     if (!covered) SIE_HIP(hipMemcpyAsync(y, x, (size_t)nrhs * E * sizeof(cx<T>), hipMemcpyDeviceToDevice, st));
     if (ras) {
         const Schwarz &w = s.sin;
         launch_ras_apply<T>(w.nc, w.max_own, w.ext_off.p, w.ext.p, w.own_off.p, w.own.p, w.m_off.p, ras_m<T>(w), x, y,
-                            E, nrhs, st);
+                            E, nrhs, st, active, (int)p->ints.size(), w.cobj.p);
     }
     if (lu) {
         for (const auto &f : s.nlu) {
@@ -829,14 +848,27 @@ struct Ops {
     }
     // Product of every interior medium on its own rows, one launch per stage
     // and group of media (the groups' rows cover all RWG functions).
-    void interior(sie_op op, bool scaled, const cx<T> *x, cx<T> *y) {
+    void interior(sie_op op, bool scaled, const cx<T> *x, cx<T> *y, const uint8_t *act = nullptr) {
         for (auto &gp : p->groups) {
-            group_product<T>(p, *gp, op, scaled, nb, x, y, st);
-            count(op, (int64_t)nb * (int64_t)gp->media.size());
+            group_product<T>(p, *gp, op, scaled, nb, x, y, st, act);
+            // products of objects that are skipped (zero rows) are not counted
+            int64_t n = (int64_t)gp->media.size();
+            if (act) {
+                n = 0;
+                for (int o : gp->media) n += act_last[o] ? 1 : 0;
+            }
+            count(op, (int64_t)nb * n);
         }
     }
+    // Objects whose nested systems still iterate ([nb][objects], device),
+    // while a nested solve with one system per object runs; null otherwise.
+    const uint8_t *active = nullptr;
+    bool skip_converged = true;
+    DBuf<uint8_t> act_dev;
+    PinnedC128 act_host;
+    std::vector<char> act_last;
     // y = sum_i (-j w eps~_i) L_i x   (block diagonal over objects)
-    void Lhat(const cx<T> *x, cx<T> *y) { interior(SIE_OP_L, true, x, y); }
+    void Lhat(const cx<T> *x, cx<T> *y) { interior(SIE_OP_L, true, x, y, active); }
     // y = sum_i K_i x + sgn X x / 2
     void KpX(bool interior_side, double sgn, const cx<T> *x, cx<T> *y) {
         if (interior_side) {
@@ -861,7 +893,7 @@ struct Ops {
             bj(use_bj_in, s.pin, x, y);
             return;
         }
-        nested_apply<T>(p, s, use_ras_in, use_lu_in, nb, x, y, st);
+        nested_apply<T>(p, s, use_ras_in, use_lu_in, nb, x, y, st, active);
     }
     void prec_outer(const cx<T> *x, cx<T> *y) { bj(use_bj_out, s.pout, x, y); }
     // Mixed precision: an FP64 operator set may delegate the interior work
@@ -884,9 +916,39 @@ struct Ops {
                 const int r = k / nsys;
                 tol[k] = std::min(kRelaxCap, std::max(inner_tol, relax_eps[r] / std::max((*relax_res)[r], 1e-300)));
             }
-        int it = inner_of<T>(s).solve([&](const cx<T> *x, cx<T> *y) { Lhat(x, y); },
-                                      [&](const cx<T> *x, cx<T> *y) { prec_inner(x, y); }, a, v, tol,
-                                      inner_max_iter, nullptr, st, nullptr, true, true);
+        // with one nested system per object, the products skip the objects
+        // whose systems have converged
+        Gmres<T> &g = inner_of<T>(s);
+        const int nobj = (int)p->ints.size();
+        if (skip_converged && nsys == nobj && nobj > 1 && nb == 1) {
+            if (act_dev.n < (size_t)nobj) {
+                act_dev.alloc(nobj);
+                act_host.alloc((nobj + 15) / 16);
+            }
+            act_last.assign(nobj, 2);
+            g.on_active = [&](const std::vector<char> &act) {
+                if (std::equal(act.begin(), act.end(), act_last.begin())) return;
+                act_last.assign(act.begin(), act.end());
+                if (std::find(act.begin(), act.end(), 0) == act.end()) {   // all iterate: no mask
+                    active = nullptr;
+                    return;
+                }
+                // the previous copy out of act_host ended before the last
+                // Arnoldi step's host wait
+                uint8_t *h = reinterpret_cast<uint8_t *>(act_host.p);
+                for (int k = 0; k < nobj; ++k) h[k] = act[k] ? 1 : 0;
+                SIE_HIP(hipMemcpyAsync(act_dev.p, h, nobj, hipMemcpyHostToDevice, st));
+                active = act_dev.p;
+            };
+        }
+        struct Reset {
+            Gmres<T> &g;
+            const uint8_t *&a;
+            ~Reset() { g.on_active = nullptr; a = nullptr; }
+        } reset{g, active};
+        int it = g.solve([&](const cx<T> *x, cx<T> *y) { Lhat(x, y); },
+                         [&](const cx<T> *x, cx<T> *y) { prec_inner(x, y); }, a, v, tol, inner_max_iter, nullptr, st,
+                         nullptr, true, true);
         s.inner_iters += it;
         s.inner_max = std::max(s.inner_max, it);
     }
@@ -1202,6 +1264,7 @@ static void solve_all(sie_problem *p, sie_precision prec, const sie_solver_opts 
         o64.use_bj_out = (o.precond & 2) != 0;
         o64.use_ras_in = (o.precond & 4) != 0 && s.sin.nc > 0;
         o64.use_lu_in = (o.precond & 16) != 0 && !s.nlu.empty();
+        o64.skip_converged = o.keep_converged == 0;
         c128 *e = s.e.p + r0 * E, *u = s.u.p + r0 * E, *v = s.v.p + r0 * E;
         const int64_t NE = (int64_t)cnt * E;
         // Refinement sweeps: residual of the block equations in FP64, correction
@@ -1217,6 +1280,7 @@ static void solve_all(sie_problem *p, sie_precision prec, const sie_solver_opts 
             o32->use_bj_out = o64.use_bj_out;
             o32->use_ras_in = o64.use_ras_in;
             o32->use_lu_in = o64.use_lu_in;
+            o32->skip_converged = o64.skip_converged;
             o64.lo = o32.get();
         }
         SIE_HIP(hipMemsetAsync(u, 0, NE * sizeof(c128), st));
@@ -1391,7 +1455,7 @@ void solve_entry(sie_problem *p, sie_precision prec, const sie_solver_opts *opts
     SIE_CHECK(p && p->is_setup, SIE_ESTATE, "problem not set up");
     SIE_CHECK(p->solve && p->solve->nrhs > 0, SIE_ESTATE, "no plane waves set");
     SIE_CHECK(prec == SIE_FP64 || prec == SIE_FP32, SIE_EINVAL, "unknown precision");
-    sie_solver_opts o{1e-6, 1e-8, 100, 800, 800, 10, 0, 0.0};
+    sie_solver_opts o{1e-6, 1e-8, 100, 800, 800, 10, 0, 0.0, 0};
     if (opts) {
         if (opts->tol > 0) o.tol = opts->tol;
         if (opts->inner_tol > 0) o.inner_tol = opts->inner_tol;
@@ -1402,6 +1466,8 @@ void solve_entry(sie_problem *p, sie_precision prec, const sie_solver_opts *opts
         o.precond = opts->precond;
         SIE_CHECK(opts->inner_relax >= 0.0, SIE_EINVAL, "inner_relax must be non-negative");
         o.inner_relax = opts->inner_relax;
+        SIE_CHECK(opts->keep_converged == 0 || opts->keep_converged == 1, SIE_EINVAL, "keep_converged must be 0 or 1");
+        o.keep_converged = opts->keep_converged;
     }
     SIE_CHECK(!(o.precond & 8) || (o.precond & 4), SIE_EINVAL, "preconditioner bit 8 extends bit 4");
     SIE_CHECK((o.precond & 5) != 5, SIE_EINVAL, "nested block-Jacobi (1) and nested Schwarz clusters (4) exclude each other");

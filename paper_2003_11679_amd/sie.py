@@ -51,7 +51,8 @@ class GridParams(ctypes.Structure):
 class SolverOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("inner_tol", ctypes.c_double), ("restart", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("inner_max_iter", ctypes.c_int32),
-                ("max_refine", ctypes.c_int32), ("precond", ctypes.c_int32), ("inner_relax", ctypes.c_double)]
+                ("max_refine", ctypes.c_int32), ("precond", ctypes.c_int32), ("inner_relax", ctypes.c_double),
+                ("keep_converged", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -495,7 +496,7 @@ class Problem:
                                      _VP(y.data_ptr()), _stream(stream)))
         return y
 
-    STAGES = ("project", "fft", "interp", "spmv", "product", "spmv64", "spmv_int32", "spmv_int64")
+    STAGES = ("project", "fft", "interp", "spmv", "product", "spmv64", "spmv_int32", "spmv_int64", "spmv_skip")
 
     def set_timing(self, on=True):
         """True/1: time every stage; 2: the near-field CSR product alone; False/0: off."""

@@ -108,3 +108,39 @@ def test_solve_satisfies_oracle_system(count, multi):
     assert np.linalg.norm(u32 - u64) < 1e-5 * np.linalg.norm(u64)
     assert np.linalg.norm(v32 - v64) < 1e-5 * np.linalg.norm(v64)
     assert r64["matvecs"] > 0 and r64["k_matvecs"] > 0
+
+
+def test_skipping_converged_objects_keeps_results():
+    """Equal objects (a 3 x 2 array of lossy cubes) iterate their nested
+    systems side by side; once an object's system has converged its rows of
+    the nested products are skipped.  The solve is the same, bit for bit in
+    FP64, as one that keeps multiplying every object, and counts fewer
+    L-type products."""
+    from paper_2003_11679_amd import Problem
+    from workloads import cube_array_cfg
+    print("[3 x 2 cube array: skipping converged nested systems]", flush=True)
+    cfg = cube_array_cfg(cells=4, ext_grid_n=48, int_grid_n=8, nx=3, ny=2)
+    p = Problem(cfg.freq)
+    for o in cfg.objects:
+        p.add_object(o.xyz, o.tri, eps_r=o.eps_r, mu_r=o.mu_r, sigma=o.sigma)
+    p.set_grid(-1, n=cfg.ext_grid_n, near_radius=3)
+    for i, o in enumerate(cfg.objects):
+        p.set_grid(i, n=o.grid_n, near_radius=3, share=0)
+    p.setup()
+    w = cfg.waves[0]
+    p.set_planewaves(w.khat, w.e0)
+    out = {}
+    for keep in (1, 0):
+        for prec in (0, 1):
+            r = p.solve(prec, tol=1e-8, restart=300, precond=12, keep_converged=keep)
+            print(f"  keep {keep} prec {prec}: {r}", flush=True)
+            assert r["converged"], r
+            out[keep, prec] = (r, p.currents())
+    for prec in (0, 1):
+        (rk, (uk, vk)), (rs, (us, vs)) = out[1, prec], out[0, prec]
+        assert rs["outer_iters"] == rk["outer_iters"] and rs["inner_iters"] == rk["inner_iters"], (rs, rk)
+        assert rs["matvecs"] < rk["matvecs"], (rs["matvecs"], rk["matvecs"])
+        if prec == 0:
+            assert np.array_equal(us, uk) and np.array_equal(vs, vk)
+        else:
+            assert np.linalg.norm(us - uk) <= 1e-12 * np.linalg.norm(uk)
