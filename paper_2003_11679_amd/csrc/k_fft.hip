@@ -260,6 +260,19 @@ struct Tile {
     static_assert(L <= NT * VPT, "line longer than the block's register slots");
 };
 
+// Fields the passes leave out: with active set, field fl of a launch (field
+// f0 + fl of the convolution, slot (f0 + fl) / fps, object obj0 + slot) is
+// skipped when its object is inactive; batches hold nzb lines per field.
+// Nothing reads a skipped field's output (one right-hand side).
+struct FieldMask {
+    const uint8_t *active = nullptr;
+    int obj0 = 0, fps = 1, nslot = 1;
+    long f0 = 0, nzb = 1;
+};
+__device__ __forceinline__ bool field_off(const FieldMask &m, long fl) {
+    return m.active && !m.active[m.obj0 + (int)(((m.f0 + fl) / m.fps) % m.nslot)];
+}
+
 // Generic pass: TX lines of length L = 2^LGL per block along one axis
 // (tile shape Tile<T, NT, VPT, LGL>).  Line (b, j) starts at
 // in + b*bs_in + j*js_in.
@@ -275,7 +288,8 @@ struct Tile {
 template <typename T, int NT, int VPT, int LGL, bool CONTIG, bool INV, bool PRUNE, int MINW>
 __global__ void __launch_bounds__(NT, MINW) k_fft_pass(const cx<T> *__restrict__ in, cx<T> *__restrict__ out,
                                                        int n_in, int n_out, int s_in, int s_out, int js_in,
-                                                       int js_out, long bs_in, long bs_out, int nj) {
+                                                       int js_out, long bs_in, long bs_out, int nj, FieldMask fm) {
+    if (field_off(fm, blockIdx.y / fm.nzb)) return;   // uniform over the block
     using TS = Tile<T, NT, VPT, LGL>;
     constexpr int L = 1 << LGL, PITCH = TS::PITCH, TX = TS::TX, LGTX = TS::LGTX;
     constexpr bool ZIN = PRUNE && !INV, ZOUT = PRUNE && INV;
@@ -354,7 +368,7 @@ constexpr int kZFields = 4;   // fields per G z-pass block
 template <typename T, int NT, int VPT, int LGL, int MODE, int MINW>
 __global__ void __launch_bounds__(NT, MINW) k_fft_zpass(cx<T> *__restrict__ buf, const cx<T> *__restrict__ spec,
                                                         int mx, int my, int nz, int fps, int run0, int nspec,
-                                                        long spec_stride) {
+                                                        long spec_stride, FieldMask fm) {
     using TS = Tile<T, NT, VPT, LGL>;
     constexpr int mz = 1 << LGL, PITCH = TS::PITCH, tx = TS::TX, lgtx = TS::LGTX;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -420,6 +434,7 @@ __global__ void __launch_bounds__(NT, MINW) k_fft_zpass(cx<T> *__restrict__ buf,
     if constexpr (MODE == 0) {
         const int cpr = (fps + kZFields - 1) / kZFields;   // chunks per run
         const int run = blockIdx.z / cpr, ch = blockIdx.z - run * cpr;
+        if (field_off(fm, (long)run * fps)) return;          // uniform over the block
         spec += (long)((run0 + run) % nspec) * spec_stride;
         cx<T> g[VPT];
 #pragma unroll
@@ -439,6 +454,7 @@ __global__ void __launch_bounds__(NT, MINW) k_fft_zpass(cx<T> *__restrict__ buf,
     } else {
         cx<T> J[3][VPT];
         const int f0 = 3 * blockIdx.z;            // the block's (J_x, J_y, J_z) triple
+        if (field_off(fm, f0)) return;            // uniform over the block
         spec += (long)((run0 + f0 / fps) % nspec) * spec_stride;
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
@@ -556,7 +572,8 @@ static void check_tile() {
 
 template <typename T, int LGL, bool INV, bool PRUNE, int NT = FftShape<T>::nt, int V = FftShape<T>::vpt>
 static void launch_pass(const cx<T> *in, cx<T> *out, int n_in, int n_out, long s_in, long s_out, long js_in,
-                        long js_out, long bs_in, long bs_out, int nj, long nb, bool contiguous, hipStream_t st) {
+                        long js_out, long bs_in, long bs_out, int nj, long nb, bool contiguous, hipStream_t st,
+                        const FieldMask &fm) {
     constexpr int W = FftShape<T>::minw;
     using TS = Tile<T, NT, V, LGL>;
     constexpr int L = 1 << LGL;
@@ -570,7 +587,7 @@ static void launch_pass(const cx<T> *in, cx<T> *out, int n_in, int n_out, long s
             SIE_CHECK(s_in == 1 && s_out == 1, SIE_EINVAL, "contiguous FFT pass needs unit element stride");
             check_span((long)TS::TX * std::max(js_in, js_out) + L);
             hipLaunchKernelGGL((k_fft_pass<T, NT, V, LGL, true, INV, PRUNE, W>), grid, dim3(NT), TS::BYTES, st, in,
-                               out, n_in, n_out, 1, 1, (int)js_in, (int)js_out, bs_in, bs_out, nj);
+                               out, n_in, n_out, 1, 1, (int)js_in, (int)js_out, bs_in, bs_out, nj, fm);
             SIE_HIP(hipGetLastError());
             return;
         }
@@ -581,7 +598,7 @@ static void launch_pass(const cx<T> *in, cx<T> *out, int n_in, int n_out, long s
         SIE_CHECK(js_in == 1 && js_out == 1, SIE_EINVAL, "strided FFT pass needs adjacent lines");
         check_span((long)L * std::max(s_in, s_out) + TS::TX);
         hipLaunchKernelGGL((k_fft_pass<T, NT, V, LGL, false, INV, PRUNE, W>), grid, dim3(NT), TS::BYTES, st, in,
-                           out, n_in, n_out, (int)s_in, (int)s_out, 1, 1, bs_in, bs_out, nj);
+                           out, n_in, n_out, (int)s_in, (int)s_out, 1, 1, bs_in, bs_out, nj, fm);
     }
     SIE_HIP(hipGetLastError());
 }
@@ -590,14 +607,14 @@ static void launch_pass(const cx<T> *in, cx<T> *out, int n_in, int n_out, long s
 template <typename T, int LGL, bool INV, bool PRUNE, int C = 0>
 static void launch_pass_shape(int shape, const cx<T> *in, cx<T> *out, int n_in, int n_out, long s_in, long s_out,
                               long js_in, long js_out, long bs_in, long bs_out, int nj, long nb, bool contiguous,
-                              hipStream_t st) {
+                              hipStream_t st, const FieldMask &fm) {
     if constexpr (C < FftCands<T>::ny) {
         if (shape == C)
             launch_pass<T, LGL, INV, PRUNE, FftCands<T>::y_nt[C], FftCands<T>::y_vpt[C]>(
-                in, out, n_in, n_out, s_in, s_out, js_in, js_out, bs_in, bs_out, nj, nb, contiguous, st);
+                in, out, n_in, n_out, s_in, s_out, js_in, js_out, bs_in, bs_out, nj, nb, contiguous, st, fm);
         else
             launch_pass_shape<T, LGL, INV, PRUNE, C + 1>(shape, in, out, n_in, n_out, s_in, s_out, js_in, js_out,
-                                                         bs_in, bs_out, nj, nb, contiguous, st);
+                                                         bs_in, bs_out, nj, nb, contiguous, st, fm);
     } else {
         SIE_CHECK(false, SIE_EINVAL, "FFT pass shape out of range");
     }
@@ -606,17 +623,17 @@ static void launch_pass_shape(int shape, const cx<T> *in, cx<T> *out, int n_in, 
 template <typename T, bool INV, bool PRUNE, int LGL = kMinLg>
 static void pass_lg(int lg, const cx<T> *in, cx<T> *out, int n_in, int n_out, long s_in, long s_out, long js_in,
                     long js_out, long bs_in, long bs_out, int nj, long nb, bool contiguous, hipStream_t st,
-                    int shape = 0) {
+                    int shape = 0, const FieldMask &fm = FieldMask()) {
     if constexpr (LGL <= kMaxLg) {
         if (lg != LGL)
             pass_lg<T, INV, PRUNE, LGL + 1>(lg, in, out, n_in, n_out, s_in, s_out, js_in, js_out, bs_in, bs_out,
-                                            nj, nb, contiguous, st, shape);
+                                            nj, nb, contiguous, st, shape, fm);
         else if (contiguous || shape == 0)
             launch_pass<T, LGL, INV, PRUNE>(in, out, n_in, n_out, s_in, s_out, js_in, js_out, bs_in, bs_out, nj,
-                                            nb, contiguous, st);
+                                            nb, contiguous, st, fm);
         else
             launch_pass_shape<T, LGL, INV, PRUNE>(shape, in, out, n_in, n_out, s_in, s_out, js_in, js_out, bs_in,
-                                                  bs_out, nj, nb, contiguous, st);
+                                                  bs_out, nj, nb, contiguous, st, fm);
     } else {
         SIE_CHECK(false, SIE_EGRID, "FFT length must be a power of two between 8 and 1024");
     }
@@ -627,23 +644,23 @@ static void pass_lg(int lg, const cx<T> *in, cx<T> *out, int n_in, int n_out, lo
 template <typename T>
 static void pass(const cx<T> *in, cx<T> *out, int L, int n_in, int n_out, long s_in, long s_out, long js_in,
                  long js_out, long bs_in, long bs_out, int nj, long nb, bool contiguous, bool inv, hipStream_t st,
-                 int shape = 0) {
+                 int shape = 0, const FieldMask &fm = FieldMask()) {
     SIE_CHECK((L & (L - 1)) == 0, SIE_EGRID, "FFT length must be a power of two");
     if (inv)
         pass_lg<T, true, true>(ilog2(L), in, out, n_in, n_out, s_in, s_out, js_in, js_out, bs_in, bs_out, nj, nb,
-                               contiguous, st, shape);
+                               contiguous, st, shape, fm);
     else
         pass_lg<T, false, true>(ilog2(L), in, out, n_in, n_out, s_in, s_out, js_in, js_out, bs_in, bs_out, nj, nb,
-                                contiguous, st, shape);
+                                contiguous, st, shape, fm);
 }
 
 // G z pass with z candidate shape C (of FftCands<T>).
 template <typename T, int LGL, int C = 0>
 static void launch_zpass0(int shape, cx<T> *bufB, const cx<T> *spec, int mx, int my, int nz, int fps, int run0,
-                          int nspec, int nf, long spec_stride, hipStream_t st) {
+                          int nspec, int nf, long spec_stride, hipStream_t st, const FieldMask &fm) {
     if constexpr (C < FftCands<T>::nz) {
         if (shape != C) {
-            launch_zpass0<T, LGL, C + 1>(shape, bufB, spec, mx, my, nz, fps, run0, nspec, nf, spec_stride, st);
+            launch_zpass0<T, LGL, C + 1>(shape, bufB, spec, mx, my, nz, fps, run0, nspec, nf, spec_stride, st, fm);
             return;
         }
         constexpr int NT = FftCands<T>::z_nt[C], V = FftCands<T>::z_vpt[C], W = FftShape<T>::z_minw;
@@ -652,7 +669,7 @@ static void launch_zpass0(int shape, cx<T> *bufB, const cx<T> *spec, int mx, int
         const int cpr = (fps + kZFields - 1) / kZFields;
         dim3 grid((mx + TS::TX - 1) / TS::TX, my / 2 + 1, (nf / fps) * cpr);
         hipLaunchKernelGGL((k_fft_zpass<T, NT, V, LGL, 0, W>), grid, dim3(NT), TS::BYTES, st, bufB, spec, mx, my, nz,
-                           fps, run0, nspec, spec_stride);
+                           fps, run0, nspec, spec_stride, fm);
     } else {
         SIE_CHECK(false, SIE_EINVAL, "FFT z-pass shape out of range");
     }
@@ -660,10 +677,11 @@ static void launch_zpass0(int shape, cx<T> *bufB, const cx<T> *spec, int mx, int
 
 template <typename T, int LGL = kMinLg>
 static void zpass_lg(int lg, const GridView &g, const cx<T> *spec, long spec_stride, int fps, int run0, int nspec,
-                     int nf, int mode, cx<T> *bufB, hipStream_t st, int shape = 0) {
+                     int nf, int mode, cx<T> *bufB, hipStream_t st, int shape = 0,
+                     const FieldMask &fm = FieldMask()) {
     if constexpr (LGL <= kMaxLg) {
         if (lg != LGL) {
-            zpass_lg<T, LGL + 1>(lg, g, spec, spec_stride, fps, run0, nspec, nf, mode, bufB, st, shape);
+            zpass_lg<T, LGL + 1>(lg, g, spec, spec_stride, fps, run0, nspec, nf, mode, bufB, st, shape, fm);
             return;
         }
         SIE_CHECK(fps >= 1 && nf % fps == 0 && nspec >= 1, SIE_EINVAL, "fields must form whole spectrum runs");
@@ -672,7 +690,7 @@ static void zpass_lg(int lg, const GridView &g, const cx<T> *spec, long spec_str
         check_span((long)nz * my * mx);
         SIE_CHECK(nz <= mz / 2, SIE_EGRID, "z live extent above half the FFT length");
         if (mode == 0) {
-            launch_zpass0<T, LGL>(shape, bufB, spec, mx, my, nz, fps, run0, nspec, nf, spec_stride, st);
+            launch_zpass0<T, LGL>(shape, bufB, spec, mx, my, nz, fps, run0, nspec, nf, spec_stride, st, fm);
         } else {
             constexpr int NT = FftShape<T>::grad_nt, V = FftShape<T>::grad_vpt, W = FftShape<T>::grad_minw;
             using TS = Tile<T, NT, V, LGL>;
@@ -680,7 +698,7 @@ static void zpass_lg(int lg, const GridView &g, const cx<T> *spec, long spec_str
             SIE_CHECK(fps % 3 == 0, SIE_EINVAL, "grad-G spectrum runs must hold whole field triples");
             dim3 grid((mx + TS::TX - 1) / TS::TX, my, nf / 3);
             hipLaunchKernelGGL((k_fft_zpass<T, NT, V, LGL, 1, W>), grid, dim3(NT), TS::BYTES, st, bufB, spec, mx, my,
-                               nz, fps, run0, nspec, spec_stride);
+                               nz, fps, run0, nspec, spec_stride, fm);
         }
         SIE_HIP(hipGetLastError());
     } else {
@@ -691,22 +709,25 @@ static void zpass_lg(int lg, const GridView &g, const cx<T> *spec, long spec_str
 // One chunk of fields through the five passes (nf * nz <= 65535).
 template <typename T>
 static void convolve_chunk(const GridView &g, const cx<T> *spec, long spec_stride, int fps, int run0, int nspec,
-                           int nf, int mode, const cx<T> *in, cx<T> *out, cx<T> *bufA, cx<T> *bufB, hipStream_t st) {
+                           int nf, int mode, const cx<T> *in, cx<T> *out, cx<T> *bufA, cx<T> *bufB, hipStream_t st,
+                           const FieldMask &fm) {
     const int nx = g.nl[0], ny = g.nl[1], nz = g.nl[2];
     const int mx = g.m[0], my = g.m[1], mz = g.m[2];
     SIE_CHECK((mz & (mz - 1)) == 0, SIE_EGRID, "FFT length must be a power of two");
-    auto yfwd = [&](int shape) {   // lines along y, j = x (adjacent), batch b = f*nz + z
+    // the timed candidates run without the field mask (whole passes)
+    const FieldMask none;
+    auto yfwd = [&](int shape, const FieldMask &m) {   // lines along y, j = x (adjacent), batch b = f*nz + z
         pass<T>(bufA, bufB, my, ny, my, mx, mx, 1, 1, (long)ny * mx, (long)my * mx, mx, (long)nf * nz, false, false,
-                st, shape);
+                st, shape, m);
         return true;
     };
-    auto zfused = [&](int shape) {
-        zpass_lg<T>(ilog2(mz), g, spec, spec_stride, fps, run0, nspec, nf, mode, bufB, st, shape);
+    auto zfused = [&](int shape, const FieldMask &m) {
+        zpass_lg<T>(ilog2(mz), g, spec, spec_stride, fps, run0, nspec, nf, mode, bufB, st, shape, m);
         return true;
     };
-    auto yinv = [&](int shape) {   // keep ny
+    auto yinv = [&](int shape, const FieldMask &m) {   // keep ny
         pass<T>(bufB, bufA, my, my, ny, mx, mx, 1, 1, (long)my * mx, (long)ny * mx, mx, (long)nf * nz, false, true,
-                st, shape);
+                st, shape, m);
         return true;
     };
     // tile shapes: on the first call for this shape the candidates run on
@@ -718,16 +739,18 @@ static void convolve_chunk(const GridView &g, const cx<T> *spec, long spec_strid
     const TuneKey kyf{dev, TUNE_FFT_YFWD, prec, {my, mx, ny, (int64_t)nf * nz, 0}};
     const TuneKey kyi{dev, TUNE_FFT_YINV, prec, {my, mx, ny, (int64_t)nf * nz, 0}};
     const TuneKey kz{dev, TUNE_FFT_Z, prec, {mz, mx, my, nz, (int64_t)nf * 65536 + fps}};
-    const int syf = tune_pick(kyf, FftCands<T>::ny, yfwd, st);
-    const int sz = mode == 0 ? tune_pick(kz, FftCands<T>::nz, zfused, st) : 0;
-    const int syi = tune_pick(kyi, FftCands<T>::ny, yinv, st);
+    const int syf = tune_pick(kyf, FftCands<T>::ny, [&](int c) { return yfwd(c, none); }, st);
+    const int sz = mode == 0 ? tune_pick(kz, FftCands<T>::nz, [&](int c) { return zfused(c, none); }, st) : 0;
+    const int syi = tune_pick(kyi, FftCands<T>::ny, [&](int c) { return yinv(c, none); }, st);
     // x forward: lines (f, z, y) contiguous; batch b = f*nz + z, j = y
-    pass<T>(in, bufA, mx, nx, mx, 1, 1, nx, mx, (long)ny * nx, (long)ny * mx, ny, (long)nf * nz, true, false, st);
-    yfwd(syf);
-    zfused(sz);
-    yinv(syi);
+    pass<T>(in, bufA, mx, nx, mx, 1, 1, nx, mx, (long)ny * nx, (long)ny * mx, ny, (long)nf * nz, true, false, st, 0,
+            fm);
+    yfwd(syf, fm);
+    zfused(sz, fm);
+    yinv(syi, fm);
     // x inverse: keep nx
-    pass<T>(bufA, out, mx, mx, nx, 1, 1, mx, nx, (long)ny * mx, (long)ny * nx, ny, (long)nf * nz, true, true, st);
+    pass<T>(bufA, out, mx, mx, nx, 1, 1, mx, nx, (long)ny * mx, (long)ny * nx, ny, (long)nf * nz, true, true, st, 0,
+            fm);
 }
 
 // out may alias in.  nf fields [nf][nl_z][nl_y][nl_x]: mode 0 each with G;
@@ -746,10 +769,20 @@ void fft_convolve(const GridView &g, const cx<T> *spec, int64_t spec_stride, int
     const int chunk = std::max(unit, (65535 / nz) / unit * unit);
     SIE_CHECK((long)chunk * nz <= 65535, SIE_EGRID, "live box too deep for one FFT batch");
     const long flive = (long)nx * ny * nz, fa = (long)nz * ny * mx, fb = (long)nz * my * mx;
+    // fields of inactive objects (one right-hand side) are left out
+    FieldMask fm;
+    if (g.active) {
+        fm.active = g.active;
+        fm.obj0 = g.obj0;
+        fm.fps = std::max(1, fps);
+        fm.nslot = std::max(1, g.nslot);
+        fm.nzb = nz;
+    }
     for (int f0 = 0; f0 < nf; f0 += chunk) {
         const int c = std::min(chunk, nf - f0);
+        fm.f0 = f0;
         convolve_chunk<T>(g, spec, (long)spec_stride, single ? c : fps, single ? 0 : f0 / fps, single ? 1 : nspec, c,
-                          mode, in + f0 * flive, out + f0 * flive, bufA + f0 * fa, bufB + f0 * fb, st);
+                          mode, in + f0 * flive, out + f0 * flive, bufA + f0 * fa, bufB + f0 * fb, st, fm);
     }
 }
 
