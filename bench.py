@@ -100,7 +100,9 @@ def parse():
     ap.add_argument("--precond", type=int, default=None,
                     help="preconditioner bit mask: 1 nested block-Jacobi, 2 outer block-Jacobi, 4 nested "
                          "near-region preconditioner in Schwarz form (conductive media), 8 with 4: for every "
-                         "interior medium; default 12 for the cube array, 4 otherwise")
+                         "interior medium, 16 the near-region preconditioner as an exact sparse LU where the "
+                         "medium's near-region matrix stays sparse (with 4: Schwarz for the others); default "
+                         "12 for the cube array, 28 for the serve trace, 4 otherwise")
     a = ap.parse_args()
     if a.tol is None:
         a.tol = DEFAULT_TOL.get(a.workload, 1e-6)
@@ -115,7 +117,7 @@ def parse():
 # conditioning turns a 1e-6 residual into ~1e-3 in the currents) and the
 # preconditioner bits (Schwarz clusters for every interior of the cube array)
 DEFAULT_TOL = {"bar": 1e-7, "cubes": 1e-6}
-DEFAULT_PRECOND = {"bar": 4, "cubes": 12}
+DEFAULT_PRECOND = {"bar": 4, "cubes": 12, "serve": 28}
 
 
 SOLVE_OPTS = {}
