@@ -1270,11 +1270,38 @@ void problem_setup(sie_problem *p) {
         build_grid_geometry(p, *g, rq, {{p->objs[i].eps_r, p->objs[i].mu_r, p->objs[i].sigma}});
         const bool cut = cut_local(i, g->h, g->near_radius);
         if (cut) g->cutoff = cutoff_of(i);
-        build_grid(p, *g);
-        md.local = cut || g->all_near;
+        md.local = cut;   // or'ed with the grid's all-near flag below
         md.grid = g.get();
         p->grids.push_back(std::move(g));
     }
+    // the interior grids (stencils, near lists, moments: host work with a
+    // few launches each) from several host threads, each on its own default
+    // stream
+    {
+        const int ng = (int)p->grids.size() - 1;   // [0]: the exterior grid, built above
+        const int nthr = std::max(1, std::min(kBuildThreads, ng));
+        std::atomic<int> next{0};
+        std::exception_ptr err;
+        std::mutex emu;
+        auto work = [&]() {
+            try {
+                SIE_HIP(hipSetDevice(p->ctx->device));
+                for (int k = next.fetch_add(1); k < ng; k = next.fetch_add(1)) build_grid(p, *p->grids[1 + k]);
+            } catch (...) {
+                std::lock_guard<std::mutex> lk(emu);
+                if (!err) err = std::current_exception();
+                next.store(ng);
+            }
+        };
+        std::vector<std::thread> th;
+        for (int t = 1; t < nthr; ++t) th.emplace_back(work);
+        work();
+        for (auto &t : th) t.join();
+        if (err) std::rethrow_exception(err);
+    }
+    for (int i = 0; i < m.nobj; ++i)
+        if (p->ints[i].grid != p->ext.grid) p->ints[i].local = p->ints[i].local || p->ints[i].grid->all_near;
+    setup_mark("interior grids");
     form_groups(p);
     if (p->aug_mode == 1) p->aug.reset(new AugState);
     else p->aug.reset();
