@@ -109,12 +109,14 @@ typedef struct {
                             others with clusters of 4^3 cells and two cells
                             of overlap; 16 the same M_i factored exactly
                             (sparse LU without pivoting over the object's RWG
-                            rows: host FP64 multifrontal factorisation in
-                            nested-dissection order, device triangular
-                            solves), for each medium whose M_i stays sparse
-                            (at most 1024 rows, or at most 200 nonzeros per
-                            row on average, and no separator above 1024
-                            unknowns, e.g. under the skin-depth cutoff); with 4 as well (20, or 28
+                            rows: FP64 multifrontal factorisation in
+                            nested-dissection order, the large fronts
+                            eliminated on the device, the small ones on the
+                            host; device triangular solves), for each medium
+                            whose M_i stays sparse enough (at most 4096 rows
+                            or at most 1500 nonzeros per row on average, no
+                            separator above 4096 unknowns, factors within
+                            8 GB and 5e12 flops); with 4 as well (20, or 28
                             with 8) the media without a factorisation get
                             Schwarz clusters.  1 and 4 exclude each other, 1
                             and 16 too, 8 needs 4 (SIE_EINVAL); 0 none
@@ -125,7 +127,9 @@ typedef struct {
                             (correction target) / (current outer residual
                             estimate), clamped to [t, 1e-2] with t the nested
                             tolerance (SIE_FP32: max(inner_tol, 1e-5)); 0 keeps
-                            the fixed tolerance (default).  The FP64 block
+                            the fixed tolerance (default), and so does a
+                            solve whose nested solves use the exact
+                            factorisation (precond 16).  The FP64 block
                             residual of every refinement sweep still decides
                             convergence. */
     int32_t keep_converged; /* nested solves with one system per object
@@ -279,8 +283,9 @@ sie_status sie_problem_set_skin_cutoff(sie_problem *p, double skin_depths);
  * gives the GIBC system divided by eta0, so u is the same.  Setup then also
  * keeps the precorrected A0 and pulse near values, and factors the Schur
  * complement S = j k0 I + Dv diag(j k0 A0_nn)^-1 Dv^T diag(Gam_tt) of the
- * constraint preconditioner (sparse LU, host, FP64; SIE_EINVAL from setup
- * when a separator of its nested dissection exceeds 1024 triangles).  Solves
+ * constraint preconditioner (sparse LU, FP64, host and device fronts;
+ * SIE_EINVAL from setup when a separator of its nested dissection exceeds
+ * 4096 triangles or the factors exceed 8 GB or 5e12 flops).  Solves
  * then iterate on (u, sigma) with that preconditioner (the outer-solve
  * preconditioner bit 2 is ignored), and their residual is that of the
  * augmented block system. */

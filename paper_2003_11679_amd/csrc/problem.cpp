@@ -1070,9 +1070,7 @@ static void aug_setup(sie_problem *p) {
         std::vector<std::pair<int32_t, c128>>().swap(r);
     }
     const auto t0 = std::chrono::steady_clock::now();
-    SparseLUHost h;
-    lu_factor_host(h, T, rp, ci, val, m.centroid);
-    lu_upload(h, A.lu);
+    lu_factor(A.lu, T, rp, ci, val, m.centroid, hipStreamPerThread);
     A.t_factor_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     setup_mark("augmented EFIE: Schur factors");
 }

@@ -652,18 +652,20 @@ template <> const c64 *ras_m<float>(const Schwarz &w) { return w.m32.p; }
 
 // ---------------------------------------------------------------- exact near-region factorisation
 // The preconditioner of eq. nest2pc as the paper applies it: a sparse LU of
-// M_i = -j w eps_i L_i,NR over the object's RWG rows, factored on the host
-// (FP64, nested dissection, no pivoting) and applied with the device's
+// M_i = -j w eps_i L_i,NR over the object's RWG rows, factored in FP64
+// (nested dissection and symbolic factorisation on the host, fronts
+// eliminated on the device, no pivoting) and applied with the device's
 // level-by-level triangular solves.  A medium whose near-region matrix is
-// too dense to factor as a sparse matrix (above the supernode limit in size
-// and more than kLUMeanRow nonzeros per row on average, or with a separator
-// above that limit) gets none.
+// too dense to factor as a sparse matrix (more than kLUMeanRow nonzeros per
+// row on average when above the supernode limit in size, a separator above
+// that limit, or factors beyond the size and arithmetic limits of the
+// sparse LU) gets none.
 struct NearLU {
     int medium = 0;
     int64_t r0 = 0, n = 0;
     SparseLU f;
 };
-constexpr double kLUMeanRow = 200.0;
+constexpr double kLUMeanRow = 1500.0;
 
 static bool near_lu_build(sie_problem *p, int medium, int64_t r0, int64_t r1, c128 scale, NearLU &out) {
     const Medium &md = p->ints[medium];
@@ -680,31 +682,25 @@ static bool near_lu_build(sie_problem *p, int medium, int64_t r0, int64_t r1, c1
         SIE_HIP(hipMemcpy(cols.data(), g.d_cols.p + b, (e - b) * sizeof(int32_t), hipMemcpyDeviceToHost));
         SIE_HIP(hipMemcpy(vals.data(), md.d_nLd64.p + b, (e - b) * sizeof(c128), hipMemcpyDeviceToHost));
     }
-    // local rows and columns; the pattern made structurally symmetric
-    std::vector<std::vector<std::pair<int32_t, c128>>> rows(n);
-    for (int64_t i = 0; i < n; ++i) {
-        rows[i].push_back({(int32_t)i, c128()});
-        for (int64_t k = rp_all[r0 - g.rwg0 + i] - b; k < rp_all[r0 - g.rwg0 + i + 1] - b; ++k) {
-            const int64_t c = (int64_t)cols[k] - r0;
-            if (c < 0 || c >= n) continue;
-            rows[i].push_back({(int32_t)c, scale * vals[k]});
-            rows[c].push_back({(int32_t)i, c128()});
-        }
-    }
+    // local rows and columns (the near pattern is symmetric, holds every
+    // diagonal and lists each row's columns in ascending order)
     std::vector<int64_t> rp(n + 1, 0);
     std::vector<int32_t> ci;
     std::vector<c128> val;
+    ci.reserve(e - b);
+    val.reserve(e - b);
     for (int64_t i = 0; i < n; ++i) {
-        auto &r = rows[i];
-        std::sort(r.begin(), r.end(), [](const std::pair<int32_t, c128> &x, const std::pair<int32_t, c128> &y) {
-            return x.first < y.first;
-        });
-        for (const auto &kv : r) {
-            if ((int64_t)ci.size() > rp[i] && ci.back() == kv.first) val.back() += kv.second;
-            else { ci.push_back(kv.first); val.push_back(kv.second); }
+        bool diag = false;
+        for (int64_t k = rp_all[r0 - g.rwg0 + i] - b; k < rp_all[r0 - g.rwg0 + i + 1] - b; ++k) {
+            const int64_t c = (int64_t)cols[k] - r0;
+            if (c < 0 || c >= n) continue;
+            SIE_CHECK((int64_t)ci.size() == rp[i] || ci.back() < c, SIE_EINVAL, "near pattern not ascending");
+            diag |= c == i;
+            ci.push_back((int32_t)c);
+            val.push_back(scale * vals[k]);
         }
+        SIE_CHECK(diag, SIE_EINVAL, "near pattern without its diagonal");
         rp[i + 1] = (int64_t)ci.size();
-        std::vector<std::pair<int32_t, c128>>().swap(r);
     }
     // RWG edge midpoints place the unknowns for the dissection
     const Mesh &m = p->mesh;
@@ -713,14 +709,12 @@ static bool near_lu_build(sie_problem *p, int medium, int64_t r0, int64_t r1, c1
         const int64_t a = m.edge_v[2 * (r0 + i)], c = m.edge_v[2 * (r0 + i) + 1];
         for (int d = 0; d < 3; ++d) xyz[3 * i + d] = 0.5 * (m.xyz[3 * a + d] + m.xyz[3 * c + d]);
     }
-    SparseLUHost h;
     try {
-        lu_factor_host(h, n, rp, ci, val, xyz);
+        lu_factor(out.f, n, rp, ci, val, xyz, hipStreamPerThread);
     } catch (const Error &er) {
         if (er.code == SIE_EINVAL) return false;   // too dense, or a vanishing pivot
         throw;
     }
-    lu_upload(h, out.f);
     out.medium = medium;
     out.r0 = r0;
     out.n = n;
@@ -1121,9 +1115,12 @@ static void build_preconditioners(sie_problem *p, SolveState &s, int precond) {
             s.nlu_covers_all = rows == p->mesh.nrwg;
             s.nlu_built = true;
             s.nlu_factor_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-            if (std::getenv("SIE_TRACE"))
-                std::fprintf(stderr, "[setup] %-28s %8.1f ms (%zu media)\n", "near-region LU", 1e3 * s.nlu_factor_s,
-                             s.nlu.size());
+            if (std::getenv("SIE_TRACE")) {
+                double fl = 0.0;
+                for (const auto &f : s.nlu) fl += f->f.est_flops;
+                std::fprintf(stderr, "[setup] %-28s %8.1f ms (%zu media, %.3g Tflop)\n", "near-region LU",
+                             1e3 * s.nlu_factor_s, s.nlu.size(), fl / 1e12);
+            }
         }
         for (const auto &f : s.nlu) factored[f->medium] = 1;
     }
@@ -1149,8 +1146,14 @@ static void build_preconditioners(sie_problem *p, SolveState &s, int precond) {
 // Relaxed nested tolerances inside one correction solve (res: the outer
 // solve's residual estimates; null ends the relaxation).  The nested solves
 // run in the FP32 operator set when there is one, else in the FP64 one.
+// Not with the exact near-region factorisation: its nested solves reach a
+// loose tolerance in one or two costly iterations, and the larger nested
+// errors then cost more outer iterations than the relaxation saves (on
+// dielectric requests 2-4 times the outer iterations and 1.3-4 times the
+// solve time of fixed tolerances).
 static void set_relax(Ops<double> &o64, Ops<float> *o32, double relax, const std::vector<double> &stol,
                       const std::vector<double> *res) {
+    if (o64.use_lu_in) res = nullptr;
     std::vector<double> eps(stol.size());
     for (size_t k = 0; k < stol.size(); ++k) eps[k] = relax * stol[k];
     if (o32) {

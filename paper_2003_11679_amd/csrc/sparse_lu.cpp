@@ -1,4 +1,6 @@
-// Multifrontal LU without pivoting in nested-dissection order (host, FP64).
+// Multifrontal LU without pivoting in nested-dissection order (FP64): the
+// ordering and the symbolic factorisation on the host, the numeric
+// factorisation on the device.
 //
 // Ordering: the unknowns are bisected recursively at the median of the
 // longest extent of their bounding box; the unknowns of the lower half with a
@@ -12,17 +14,25 @@
 // positions and its boundary B (later positions coupled to N directly or
 // through its descendants), eliminates its own positions (no pivoting: the
 // matrices factored here are shifted surface Laplacians, diagonally dominant
-// up to one eigenvalue per object that the shift moves off zero) and hands
-// the Schur complement on B to its parent.  Kept: the inverses of the
-// diagonal blocks L_NN (unit lower) and U_NN, and the blocks L_BN, U_NB,
-// stored by rows so that a device solve gathers what a row needs:
+// up to one eigenvalue per object that the shift moves off zero, and
+// near-region operators dominated by their self and neighbour terms) and
+// hands the Schur complement on B to its parent.  The symbolic pass finds
+// every B first, so that the size of the factors and the arithmetic are
+// known (and refused beyond the limits) before any front is factored, and
+// lays out where every result goes; the fronts then run on the device in
+// postorder (k_front.hip), their update matrices on a stack, or, when every
+// front is small, on the host (the supernodes of a level in parallel).  Kept: the
+// inverses of the diagonal blocks L_NN (unit lower) and U_NN, and the blocks
+// L_BN, U_NB, stored by rows so that a device solve gathers what a row
+// needs:
 //   forward  y_N = L_NN^-1 (b_N - sum_{descendants D} L_ND y_D)
 //   backward x_N = U_NN^-1 (y_N - U_NB x_B)
-// Supernodes of one level run concurrently on the host and on the device.
+// Supernodes of one level run concurrently in the device solve.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <exception>
 #include <limits>
 #include <mutex>
@@ -100,64 +110,35 @@ struct Dissection {
     }
 };
 
-struct Factor {
-    std::vector<int32_t> B;        // boundary positions (ascending)
-    std::vector<c128> upd;         // |B| x |B| Schur complement for the parent
-    std::vector<c128> linv, uinv;  // n x n
-    std::vector<c128> lb, ub;      // |B| x n and n x |B|
-};
-
-// Dense front of supernode `id`: assemble, eliminate its own positions.
-void factor_node(int id, const std::vector<Node> &nodes, std::vector<Factor> &fac, const std::vector<int32_t> &order,
-                 const std::vector<int32_t> &iperm, const std::vector<int64_t> &rp, const std::vector<int32_t> &ci,
-                 const std::vector<c128> &val) {
+// Boundary of supernode `id` (its children's already found): the later
+// positions coupled to its own directly or through a child's boundary.
+// mark [n] holds, per position, the last supernode that listed it.
+void front_boundary(int id, const std::vector<Node> &nodes, std::vector<std::vector<int32_t>> &Bs,
+                    const std::vector<int32_t> &order, const std::vector<int32_t> &iperm,
+                    const std::vector<int64_t> &rp, const std::vector<int32_t> &ci, std::vector<int32_t> &mark) {
     const Node &nd = nodes[id];
-    const int n = nd.n, p0 = nd.p0, p1 = p0 + n;
-    Factor &f = fac[id];
-    std::vector<int32_t> B;
-    for (int i = p0; i < p1; ++i) {
+    const int p1 = nd.p0 + nd.n;
+    std::vector<int32_t> &B = Bs[id];
+    B.clear();
+    auto add = [&](int32_t pos) {
+        if (pos >= p1 && mark[pos] != id) {
+            mark[pos] = id;
+            B.push_back(pos);
+        }
+    };
+    for (int i = nd.p0; i < p1; ++i) {
         const int32_t u = order[i];
-        for (int64_t k = rp[u]; k < rp[u + 1]; ++k)
-            if (iperm[ci[k]] >= p1) B.push_back(iperm[ci[k]]);
+        for (int64_t k = rp[u]; k < rp[u + 1]; ++k) add(iperm[ci[k]]);
     }
     for (int c : nd.children)
-        for (int32_t b : fac[c].B)
-            if (b >= p1) B.push_back(b);
+        for (int32_t b : Bs[c]) add(b);
     std::sort(B.begin(), B.end());
-    B.erase(std::unique(B.begin(), B.end()), B.end());
-    const int nb = (int)B.size(), m = n + nb;
-    auto loc = [&](int32_t pos) -> int {
-        if (pos < p1) return pos - p0;
-        return n + (int)(std::lower_bound(B.begin(), B.end(), pos) - B.begin());
-    };
-    std::vector<c128> F((size_t)m * m);
-    // original entries whose smaller position lies in N
-    for (int i = p0; i < p1; ++i) {
-        const int32_t u = order[i];
-        for (int64_t k = rp[u]; k < rp[u + 1]; ++k) {
-            const int32_t pj = iperm[ci[k]];
-            if (pj < p0) continue;
-            F[(size_t)loc(i) * m + loc(pj)] += val[k];
-            if (pj >= p1) {   // the transposed entry (row in B, column in N)
-                const int32_t w = ci[k];
-                const int32_t *b0 = ci.data() + rp[w], *b1 = ci.data() + rp[w + 1];
-                const int32_t *q = std::lower_bound(b0, b1, u);
-                SIE_CHECK(q != b1 && *q == u, SIE_EINVAL, "sparse LU: pattern not structurally symmetric");
-                F[(size_t)loc(pj) * m + loc(i)] += val[q - ci.data()];
-            }
-        }
-    }
-    // children's Schur complements
-    for (int c : nd.children) {
-        Factor &fc = fac[c];
-        const int bc = (int)fc.B.size();
-        std::vector<int> lc(bc);
-        for (int a = 0; a < bc; ++a) lc[a] = loc(fc.B[a]);
-        for (int a = 0; a < bc; ++a)
-            for (int b = 0; b < bc; ++b) F[(size_t)lc[a] * m + lc[b]] += fc.upd[(size_t)a * bc + b];
-        std::vector<c128>().swap(fc.upd);
-    }
-    // eliminate the n own positions
+}
+
+// Dense elimination of the first n positions of the m x m front F on the
+// host (the small fronts): the same results as the device's, multipliers of
+// zero skipped.
+void eliminate_host(c128 *F, int m, int n, c128 *linv, c128 *uinv) {
     for (int k = 0; k < n; ++k) {
         const c128 piv = F[(size_t)k * m + k];
         const double pa = std::hypot(piv.re, piv.im);
@@ -175,41 +156,31 @@ void factor_node(int id, const std::vector<Node> &nodes, std::vector<Factor> &fa
             }
         }
     }
-    // inverses of the diagonal blocks
-    f.linv.assign((size_t)n * n, c128());
-    f.uinv.assign((size_t)n * n, c128());
     for (int c = 0; c < n; ++c) {
-        f.linv[(size_t)c * n + c] = c128(1.0);
+        linv[(size_t)c * n + c] = c128(1.0);
         for (int i = c + 1; i < n; ++i) {
             c128 s;
-            for (int k = c; k < i; ++k) s += F[(size_t)i * m + k] * f.linv[(size_t)k * n + c];
-            f.linv[(size_t)i * n + c] = -s;
+            for (int k = c; k < i; ++k) s += F[(size_t)i * m + k] * linv[(size_t)k * n + c];
+            linv[(size_t)i * n + c] = -s;
         }
-        f.uinv[(size_t)c * n + c] = cdiv(c128(1.0), F[(size_t)c * m + c]);
+        uinv[(size_t)c * n + c] = cdiv(c128(1.0), F[(size_t)c * m + c]);
         for (int i = c - 1; i >= 0; --i) {
             c128 s;
-            for (int k = i + 1; k <= c; ++k) s += F[(size_t)i * m + k] * f.uinv[(size_t)k * n + c];
-            f.uinv[(size_t)i * n + c] = cdiv(-s, F[(size_t)i * m + i]);
+            for (int k = i + 1; k <= c; ++k) s += F[(size_t)i * m + k] * uinv[(size_t)k * n + c];
+            uinv[(size_t)i * n + c] = cdiv(-s, F[(size_t)i * m + i]);
         }
     }
-    f.lb.resize((size_t)nb * n);
-    f.ub.resize((size_t)n * nb);
-    for (int a = 0; a < nb; ++a)
-        for (int k = 0; k < n; ++k) f.lb[(size_t)a * n + k] = F[(size_t)(n + a) * m + k];
-    for (int k = 0; k < n; ++k)
-        for (int b = 0; b < nb; ++b) f.ub[(size_t)k * nb + b] = F[(size_t)k * m + n + b];
-    f.upd.resize((size_t)nb * nb);
-    for (int a = 0; a < nb; ++a)
-        for (int b = 0; b < nb; ++b) f.upd[(size_t)a * nb + b] = F[(size_t)(n + a) * m + n + b];
-    f.B = std::move(B);
 }
 
 }  // namespace
 
-void lu_factor_host(SparseLUHost &h, int64_t n, const std::vector<int64_t> &rp, const std::vector<int32_t> &ci,
-                    const std::vector<c128> &val, const std::vector<double> &coords) {
+void lu_factor(SparseLU &f, int64_t n, const std::vector<int64_t> &rp, const std::vector<int32_t> &ci,
+               const std::vector<c128> &val, const std::vector<double> &coords, hipStream_t st) {
     SIE_CHECK(n > 0 && n < (int64_t(1) << 31), SIE_EINVAL, "sparse LU: bad size");
     SIE_CHECK((int64_t)rp.size() == n + 1 && (int64_t)coords.size() == 3 * n, SIE_EINVAL, "sparse LU: bad input");
+    SIE_CHECK(rp[n] < (int64_t(1) << 31) && (int64_t)ci.size() == rp[n] && val.size() == ci.size(), SIE_EINVAL,
+              "sparse LU: bad input");
+    const auto t0 = std::chrono::steady_clock::now();
     Dissection nd(rp, ci, coords, n);
     {
         std::vector<int32_t> all(n);
@@ -220,134 +191,147 @@ void lu_factor_host(SparseLUHost &h, int64_t n, const std::vector<int64_t> &rp, 
     std::vector<int32_t> iperm(n);
     for (int64_t p = 0; p < n; ++p) iperm[nd.order[p]] = (int32_t)p;
     const int nn = (int)nd.nodes.size();
-    int H = 0;
-    for (const Node &x : nd.nodes) H = std::max(H, x.height + 1);
-    std::vector<std::vector<int>> by_level(H);
-    for (int i = 0; i < nn; ++i) by_level[nd.nodes[i].height].push_back(i);
-    // numeric factorisation, the supernodes of a level in parallel
-    std::vector<Factor> fac(nn);
-    const int nthr = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    for (int l = 0; l < H; ++l) {
-        const std::vector<int> &lv = by_level[l];
-        std::atomic<size_t> next{0};
-        std::exception_ptr err;
-        std::mutex emu;
-        auto work = [&]() {
-            for (;;) {
-                const size_t i = next.fetch_add(1);
-                if (i >= lv.size()) return;
-                try {
-                    factor_node(lv[i], nd.nodes, fac, nd.order, iperm, rp, ci, val);
-                } catch (...) {
-                    std::lock_guard<std::mutex> lk(emu);
-                    if (!err) err = std::current_exception();
-                }
-            }
-        };
-        const int nt = (int)std::min<size_t>(nthr, lv.size());
-        std::vector<std::thread> th;
-        for (int t = 1; t < nt; ++t) th.emplace_back(work);
-        work();
-        for (auto &t : th) t.join();
-        if (err) std::rethrow_exception(err);
+    const std::vector<Node> &nodes = nd.nodes;
+
+    // symbolic factorisation: every front's boundary, the factors' size and
+    // the arithmetic of the elimination (complex multiply-adds of 8 flops:
+    // n m^2 - n^2 m + n^3 / 3 for the front, n^3 / 3 for the two inverses)
+    std::vector<std::vector<int32_t>> Bs(nn);
+    double bytes = 0.0, flops = 0.0;
+    int64_t max_mm = 1;
+    std::vector<int32_t> mark(n, -1);
+    for (int id = 0; id < nn; ++id) {
+        front_boundary(id, nodes, Bs, nd.order, iperm, rp, ci, mark);
+        const double a = nodes[id].n, b = (double)Bs[id].size(), m = a + b;
+        bytes += 16.0 * (2.0 * a * a + 2.0 * a * b);
+        flops += 8.0 * (a * m * m - a * a * m + 2.0 * a * a * a / 3.0);
+        max_mm = std::max<int64_t>(max_mm, (int64_t)(a + b) * (int64_t)(a + b));
     }
-    // device layout
+    SIE_CHECK(bytes <= kLUMaxBytes && flops <= kLUMaxFlops, SIE_EINVAL,
+              "sparse LU: factors of " + std::to_string(bytes / 1e9) + " GB and " + std::to_string(flops / 1e12) +
+                  " Tflop exceed the limits");
+
+    // where each front's results go: rows of L gather the boundary rows of
+    // every descendant front, rows of U the boundary of their own front
     std::vector<int64_t> lcnt(n + 1, 0), ucnt(n + 1, 0);
     for (int id = 0; id < nn; ++id) {
-        const Node &x = nd.nodes[id];
-        for (int32_t b : fac[id].B) lcnt[b + 1] += x.n;
-        for (int k = 0; k < x.n; ++k) ucnt[x.p0 + k + 1] += (int64_t)fac[id].B.size();
+        for (int32_t b : Bs[id]) lcnt[b + 1] += nodes[id].n;
+        for (int k = 0; k < nodes[id].n; ++k) ucnt[nodes[id].p0 + k + 1] += (int64_t)Bs[id].size();
     }
     for (int64_t i = 0; i < n; ++i) { lcnt[i + 1] += lcnt[i]; ucnt[i + 1] += ucnt[i]; }
     std::vector<int32_t> lcol(lcnt[n]), ucol(ucnt[n]);
-    std::vector<c128> lval(lcnt[n]), uval(ucnt[n]);
-    std::vector<int64_t> lfill(lcnt.begin(), lcnt.end() - 1), ufill(ucnt.begin(), ucnt.end() - 1);
+    std::vector<int64_t> lfill(lcnt.begin(), lcnt.end() - 1);
+    std::vector<int64_t> loff;                     // per front and boundary row: first L entry
+    std::vector<int64_t> loff0(nn + 1, 0), inv_off(nn, 0), upd_off(nn, 0);
     std::vector<int32_t> sn_p0(nn), sn_n(nn);
-    std::vector<int64_t> inv_off(nn);
-    int64_t inv_total = 0;
-    int max_sn = 0;
+    int64_t inv_total = 0, top = 0, peak = 1;
     for (int id = 0; id < nn; ++id) {
-        const Node &x = nd.nodes[id];
-        const Factor &fc = fac[id];
-        const int nb = (int)fc.B.size();
-        for (int a = 0; a < nb; ++a)
-            for (int k = 0; k < x.n; ++k) {
-                const int64_t q = lfill[fc.B[a]]++;
-                lcol[q] = x.p0 + k;
-                lval[q] = fc.lb[(size_t)a * x.n + k];
-            }
+        const Node &x = nodes[id];
+        const std::vector<int32_t> &B = Bs[id];
+        const int nb = (int)B.size();
+        for (int a = 0; a < nb; ++a) {
+            const int64_t q = lfill[B[a]];
+            lfill[B[a]] += x.n;
+            loff.push_back(q);
+            for (int k = 0; k < x.n; ++k) lcol[q + k] = x.p0 + k;
+        }
+        loff0[id + 1] = (int64_t)loff.size();
         for (int k = 0; k < x.n; ++k)
-            for (int b = 0; b < nb; ++b) {
-                const int64_t q = ufill[x.p0 + k]++;
-                ucol[q] = fc.B[b];
-                uval[q] = fc.ub[(size_t)k * nb + b];
-            }
+            for (int b = 0; b < nb; ++b) ucol[ucnt[x.p0 + k] + b] = B[b];
         sn_p0[id] = x.p0;
         sn_n[id] = x.n;
         inv_off[id] = inv_total;
         inv_total += (int64_t)x.n * x.n;
-        max_sn = std::max(max_sn, x.n);
+        // update matrices on a stack: a front's children (consecutive
+        // subtrees just before it) left theirs on top; it pops them once
+        // assembled and pushes its own
+        if (!x.children.empty()) top = upd_off[x.children.front()];
+        upd_off[id] = top;
+        top += (int64_t)nb * nb;
+        peak = std::max(peak, top);
     }
-    std::vector<c128> linv(std::max<int64_t>(inv_total, 1)), uinv(std::max<int64_t>(inv_total, 1));
+    // assembly lists: original entries (front-local row, column, value
+    // index; every entry lands in exactly one front position) and the
+    // positions of each child's boundary in its parent's front
+    std::vector<int64_t> asm0(nn + 1, 0), map0(nn + 1, 0);
+    std::vector<int32_t> arow, acol, asrc, cmap;
+    arow.reserve(ci.size());
+    acol.reserve(ci.size());
+    asrc.reserve(ci.size());
     for (int id = 0; id < nn; ++id) {
-        std::copy(fac[id].linv.begin(), fac[id].linv.end(), linv.begin() + inv_off[id]);
-        std::copy(fac[id].uinv.begin(), fac[id].uinv.end(), uinv.begin() + inv_off[id]);
+        const Node &x = nodes[id];
+        const std::vector<int32_t> &B = Bs[id];
+        const int p0 = x.p0, p1 = p0 + x.n;
+        for (int a = 0; a < (int)B.size(); ++a) mark[B[a]] = x.n + a;   // front-local index of a boundary position
+        auto loc = [&](int32_t pos) -> int32_t { return pos < p1 ? pos - p0 : mark[pos]; };
+        for (int i = p0; i < p1; ++i) {
+            const int32_t u = nd.order[i];
+            for (int64_t k = rp[u]; k < rp[u + 1]; ++k) {
+                const int32_t pj = iperm[ci[k]];
+                if (pj < p0) continue;
+                arow.push_back(loc(i));
+                acol.push_back(loc(pj));
+                asrc.push_back((int32_t)k);
+                if (pj >= p1) {   // the transposed entry (row in B, column in N)
+                    const int32_t w = ci[k];
+                    const int32_t *b0 = ci.data() + rp[w], *b1 = ci.data() + rp[w + 1];
+                    const int32_t *q = std::lower_bound(b0, b1, u);
+                    SIE_CHECK(q != b1 && *q == u, SIE_EINVAL, "sparse LU: pattern not structurally symmetric");
+                    arow.push_back(loc(pj));
+                    acol.push_back(loc(i));
+                    asrc.push_back((int32_t)(q - ci.data()));
+                }
+            }
+        }
+        asm0[id + 1] = (int64_t)arow.size();
+        for (int c : x.children)
+            for (int32_t b : Bs[c]) {   // a child couples only to its ancestors' positions
+                SIE_CHECK(b >= p0, SIE_EINVAL, "sparse LU: child boundary outside its parent's front");
+                cmap.push_back(loc(b));
+            }
+        map0[id + 1] = (int64_t)cmap.size();
     }
-    h.lev_ptr.assign(1, 0);
-    h.lev_sn.clear();
-    for (int l = 0; l < H; ++l) {
-        for (int id : by_level[l])
-            if (nd.nodes[id].n > 0) h.lev_sn.push_back(id);
-        h.lev_ptr.push_back((int)h.lev_sn.size());
-    }
-    h.n = n;
-    h.sn_p0 = std::move(sn_p0);
-    h.sn_n = std::move(sn_n);
-    h.inv_off = std::move(inv_off);
-    h.linv = std::move(linv);
-    h.uinv = std::move(uinv);
-    h.lrow_ptr = std::move(lcnt);
-    h.urow_ptr = std::move(ucnt);
-    h.lcol = std::move(lcol);
-    h.ucol = std::move(ucol);
-    h.lval = std::move(lval);
-    h.uval = std::move(uval);
-    h.perm = std::move(nd.order);
-    h.iperm = std::move(iperm);
-    (void)max_sn;
-}
 
-void lu_upload(const SparseLUHost &h, SparseLU &f) {
+    const auto t1 = std::chrono::steady_clock::now();
+    // device layout of the factors (what the level-by-level solve reads)
     auto up = [](auto &d, const auto &v, auto zero) {
         if (v.empty()) d.upload(&zero, 1);
         else d.upload(v);
     };
-    f.n = h.n;
-    f.nsn = (int)h.sn_n.size();
+    f = SparseLU();
+    f.n = n;
+    f.nsn = nn;
     f.max_sn = 0;
-    for (int32_t x : h.sn_n) f.max_sn = std::max(f.max_sn, (int)x);
-    f.nnz_factor = (int64_t)h.lcol.size() + (int64_t)h.ucol.size();
-    f.lev_ptr = h.lev_ptr;
-    up(f.lev_sn, h.lev_sn, int32_t(0));
-    up(f.sn_p0, h.sn_p0, int32_t(0));
-    up(f.sn_n, h.sn_n, int32_t(0));
-    up(f.inv_off, h.inv_off, int64_t(0));
-    up(f.linv, h.linv, c128());
-    up(f.uinv, h.uinv, c128());
-    up(f.lrow_ptr, h.lrow_ptr, int64_t(0));
-    up(f.urow_ptr, h.urow_ptr, int64_t(0));
-    up(f.lcol, h.lcol, int32_t(0));
-    up(f.ucol, h.ucol, int32_t(0));
-    up(f.lval, h.lval, c128());
-    up(f.uval, h.uval, c128());
-    up(f.perm, h.perm, int32_t(0));
-    up(f.iperm, h.iperm, int32_t(0));
+    for (int32_t x : sn_n) f.max_sn = std::max(f.max_sn, (int)x);
+    f.nnz_factor = (int64_t)lcol.size() + (int64_t)ucol.size();
+    f.est_flops = flops;
+    int H = 0;
+    for (const Node &x : nodes) H = std::max(H, x.height + 1);
+    std::vector<std::vector<int>> by_level(H);
+    for (int i = 0; i < nn; ++i) by_level[nodes[i].height].push_back(i);
+    std::vector<int32_t> lev_sn;
+    f.lev_ptr.assign(1, 0);
+    for (int l = 0; l < H; ++l) {
+        for (int id : by_level[l])
+            if (nodes[id].n > 0) lev_sn.push_back(id);
+        f.lev_ptr.push_back((int)lev_sn.size());
+    }
+    up(f.lev_sn, lev_sn, int32_t(0));
+    up(f.sn_p0, sn_p0, int32_t(0));
+    up(f.sn_n, sn_n, int32_t(0));
+    up(f.inv_off, inv_off, int64_t(0));
+    up(f.lrow_ptr, lcnt, int64_t(0));
+    up(f.urow_ptr, ucnt, int64_t(0));
+    up(f.lcol, lcol, int32_t(0));
+    up(f.ucol, ucol, int32_t(0));
+    up(f.perm, nd.order, int32_t(0));
+    up(f.iperm, iperm, int32_t(0));
     std::vector<int32_t> bsn, brow;
     f.blk_ptr.assign(1, 0);
-    for (size_t l = 0; l + 1 < h.lev_ptr.size(); ++l) {
-        for (int q = h.lev_ptr[l]; q < h.lev_ptr[l + 1]; ++q) {
-            const int32_t sn = h.lev_sn[q];
-            for (int r = 0; r < h.sn_n[sn]; r += kLURowsPerBlock) {
+    for (size_t l = 0; l + 1 < f.lev_ptr.size(); ++l) {
+        for (int q = f.lev_ptr[l]; q < f.lev_ptr[l + 1]; ++q) {
+            const int32_t sn = lev_sn[q];
+            for (int r = 0; r < sn_n[sn]; r += kLURowsPerBlock) {
                 bsn.push_back(sn);
                 brow.push_back(r);
             }
@@ -356,37 +340,144 @@ void lu_upload(const SparseLUHost &h, SparseLU &f) {
     }
     up(f.blk_sn, bsn, int32_t(0));
     up(f.blk_row0, brow, int32_t(0));
-}
-
-void lu_solve_host(const SparseLUHost &h, c128 *x) {
-    const int64_t n = h.n;
-    std::vector<c128> y(n), t;
-    for (int64_t p = 0; p < n; ++p) y[p] = x[h.perm[p]];
-    const int H = (int)h.lev_ptr.size() - 1;
-    auto level = [&](int l, bool fwd) {
-        const std::vector<int64_t> &rp = fwd ? h.lrow_ptr : h.urow_ptr;
-        const std::vector<int32_t> &cc = fwd ? h.lcol : h.ucol;
-        const std::vector<c128> &vv = fwd ? h.lval : h.uval;
-        const std::vector<c128> &inv = fwd ? h.linv : h.uinv;
-        for (int q = h.lev_ptr[l]; q < h.lev_ptr[l + 1]; ++q) {
-            const int sn = h.lev_sn[q], p0 = h.sn_p0[sn], nn = h.sn_n[sn];
-            t.assign(nn, c128());
-            for (int i = 0; i < nn; ++i) {
-                c128 acc = y[p0 + i];
-                for (int64_t j = rp[p0 + i]; j < rp[p0 + i + 1]; ++j) acc -= vv[j] * y[cc[j]];
-                t[i] = acc;
+    const auto t2 = std::chrono::steady_clock::now();
+    int bad = 0;
+    const bool on_host = max_mm <= (int64_t)kLUHostFront * kLUHostFront;
+    if (on_host) {
+        // small fronts only: numeric factorisation on the host, the
+        // supernodes of a level in parallel, update matrices per supernode
+        std::vector<c128> lval(std::max<size_t>(lcol.size(), 1)), uval(std::max<size_t>(ucol.size(), 1));
+        std::vector<c128> linv((size_t)std::max<int64_t>(inv_total, 1)), uinv((size_t)std::max<int64_t>(inv_total, 1));
+        std::vector<std::vector<c128>> upd(nn);
+        auto front = [&](int id) {
+            const Node &x = nodes[id];
+            const int fn = x.n, nb = (int)Bs[id].size(), m = fn + nb;
+            if (m == 0) return;
+            std::vector<c128> F((size_t)m * m);
+            for (int64_t e = asm0[id]; e < asm0[id + 1]; ++e) F[(size_t)arow[e] * m + acol[e]] = val[asrc[e]];
+            int64_t mo = map0[id];
+            for (int c : x.children) {
+                const int bc = (int)Bs[c].size();
+                const int32_t *mp = cmap.data() + mo;
+                for (int a = 0; a < bc; ++a)
+                    for (int b = 0; b < bc; ++b) F[(size_t)mp[a] * m + mp[b]] += upd[c][(size_t)a * bc + b];
+                mo += bc;
+                std::vector<c128>().swap(upd[c]);
             }
-            const c128 *M = inv.data() + h.inv_off[sn];
-            for (int i = 0; i < nn; ++i) {
-                c128 s;
-                for (int k = fwd ? 0 : i; k < (fwd ? i + 1 : nn); ++k) s += M[(int64_t)i * nn + k] * t[k];
-                y[p0 + i] = s;
+            if (fn > 0) {
+                eliminate_host(F.data(), m, fn, linv.data() + inv_off[id], uinv.data() + inv_off[id]);
+                const int64_t *lo = loff.data() + loff0[id];
+                for (int a = 0; a < nb; ++a)
+                    for (int k = 0; k < fn; ++k) lval[lo[a] + k] = F[(size_t)(fn + a) * m + k];
+                for (int k = 0; k < fn; ++k)
+                    for (int b = 0; b < nb; ++b) uval[ucnt[x.p0 + k] + b] = F[(size_t)k * m + fn + b];
             }
+            upd[id].resize((size_t)nb * nb);
+            for (int a = 0; a < nb; ++a)
+                for (int b = 0; b < nb; ++b) upd[id][(size_t)a * nb + b] = F[(size_t)(fn + a) * m + fn + b];
+        };
+        const int nthr = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        for (int l = 0; l < H; ++l) {
+            const std::vector<int> &lv = by_level[l];
+            std::atomic<size_t> next{0};
+            std::exception_ptr err;
+            std::mutex emu;
+            auto work = [&]() {
+                for (;;) {
+                    const size_t i = next.fetch_add(1);
+                    if (i >= lv.size()) return;
+                    try {
+                        front(lv[i]);
+                    } catch (...) {
+                        std::lock_guard<std::mutex> lk(emu);
+                        if (!err) err = std::current_exception();
+                    }
+                }
+            };
+            const int nt = (int)std::min<size_t>(nthr, lv.size());
+            std::vector<std::thread> th;
+            for (int t = 1; t < nt; ++t) th.emplace_back(work);
+            work();
+            for (auto &t : th) t.join();
+            if (err) std::rethrow_exception(err);
         }
-    };
-    for (int l = 0; l < H; ++l) level(l, true);
-    for (int l = H - 1; l >= 0; --l) level(l, false);
-    for (int64_t p = 0; p < n; ++p) x[h.perm[p]] = y[p];
+        f.lval.upload(lval);
+        f.uval.upload(uval);
+        f.linv.upload(linv);
+        f.uinv.upload(uinv);
+    } else {
+        // numeric factorisation on the device, front by front in postorder
+        // on one stream (one front buffer reused; update matrices on the
+        // stack)
+        f.lval.alloc(std::max<size_t>(lcol.size(), 1));
+        f.uval.alloc(std::max<size_t>(ucol.size(), 1));
+        f.linv.alloc((size_t)std::max<int64_t>(inv_total, 1));
+        f.uinv.alloc((size_t)std::max<int64_t>(inv_total, 1));
+        PoolSyncedFree synced;   // the blocks below are freed after the stream is drained
+        DBuf<c128> dval, dF, dstack;
+        DBuf<int32_t> darow, dacol, dasrc, dmap;
+        DBuf<int64_t> dloff;
+        DBuf<int> dbad;
+        try {
+            dval.upload(val, st);
+            up(darow, arow, int32_t(0));
+            up(dacol, acol, int32_t(0));
+            up(dasrc, asrc, int32_t(0));
+            up(dmap, cmap, int32_t(0));
+            up(dloff, loff, int64_t(0));
+            dbad.upload(std::vector<int>(1, 0), st);
+            dF.alloc((size_t)max_mm);
+            dstack.alloc((size_t)peak);
+            for (int id = 0; id < nn; ++id) {
+                const Node &x = nodes[id];
+                const int nb = (int)Bs[id].size(), m = x.n + nb;
+                if (m == 0) continue;
+                FrontStep fs;
+                fs.F = dF.p;
+                fs.m = m;
+                fs.n = x.n;
+                fs.arow = darow.p + asm0[id];
+                fs.acol = dacol.p + asm0[id];
+                fs.asrc = dasrc.p + asm0[id];
+                fs.nasm = asm0[id + 1] - asm0[id];
+                fs.val = dval.p;
+                int64_t mo = map0[id];
+                for (int c : x.children) {
+                    const int bc = (int)Bs[c].size();
+                    if (bc == 0) continue;
+                    fs.child_upd.push_back(dstack.p + upd_off[c]);
+                    fs.child_nb.push_back(bc);
+                    fs.child_map.push_back(dmap.p + mo);
+                    mo += bc;
+                }
+                fs.linv = f.linv.p + inv_off[id];
+                fs.uinv = f.uinv.p + inv_off[id];
+                fs.lval = f.lval.p;
+                fs.loff = dloff.p + loff0[id];
+                fs.uval = f.uval.p;
+                fs.urow = f.urow_ptr.p + x.p0;
+                fs.upd = nb > 0 ? dstack.p + upd_off[id] : nullptr;
+                fs.bad = dbad.p;
+                launch_front_step(fs, st);
+            }
+            SIE_HIP(hipMemcpyAsync(&bad, dbad.p, sizeof(int), hipMemcpyDeviceToHost, st));
+            SIE_HIP(hipStreamSynchronize(st));
+        } catch (...) {
+            (void)hipStreamSynchronize(st);
+            throw;
+        }
+    }
+    SIE_CHECK(bad == 0, SIE_EINVAL, "sparse LU: zero pivot");
+    const auto t3 = std::chrono::steady_clock::now();
+    f.t_factor_s = std::chrono::duration<double>(t3 - t0).count();
+    if (std::getenv("SIE_TRACE")) {
+        auto ms = [](auto a, auto b) { return std::chrono::duration<double, std::milli>(b - a).count(); };
+        std::fprintf(stderr,
+                     "[setup]   sparse LU n=%lld: ordering + symbolic %.1f ms, layout upload %.1f ms, fronts %.1f ms "
+                     "(%d fronts, largest %lld, %.3g Tflop, factors %.3g GB)\n",
+                     (long long)n, ms(t0, t1), ms(t1, t2), ms(t2, t3), nn,
+                     (long long)std::llround(std::sqrt((double)max_mm)), flops / 1e12, bytes / 1e9);
+    }
 }
 
 void lu_solve(const SparseLU &f, int nrhs, c128 *x, hipStream_t st) {

@@ -23,6 +23,7 @@ struct SparseLU {
     DBuf<int32_t> perm, iperm;         // position -> unknown, unknown -> position
     int64_t nnz_factor = 0;            // stored off-block entries of L and U
     double t_factor_s = 0.0;
+    double est_flops = 0.0;            // arithmetic of the factorisation
     // row blocks of the device solve: block b of level l (blk_ptr[l] <= b <
     // blk_ptr[l + 1]) takes rows blk_row0[b] .. + kLURowsPerBlock - 1 of
     // supernode blk_sn[b]
@@ -33,26 +34,22 @@ struct SparseLU {
 // Rows of one supernode per workgroup of the device solve (one wavefront each).
 constexpr int kLURowsPerBlock = 4;
 
-// The factors on the host (the device copy is SparseLU).
-struct SparseLUHost {
-    int64_t n = 0;
-    std::vector<int> lev_ptr;
-    std::vector<int32_t> lev_sn, sn_p0, sn_n, lcol, ucol, perm, iperm;
-    std::vector<int64_t> inv_off, lrow_ptr, urow_ptr;
-    std::vector<c128> linv, uinv, lval, uval;
-};
-
 // Factor the n x n matrix in CSR (rp, ci sorted per row, val); its pattern
 // must be structurally symmetric.  coords [n][3] place the unknowns in space
-// for the dissection.  Throws SIE_EINVAL when a separator exceeds
-// kLUMaxSupernode unknowns or a pivot vanishes.
-constexpr int kLUMaxSupernode = 1024;
-void lu_factor_host(SparseLUHost &h, int64_t n, const std::vector<int64_t> &rp, const std::vector<int32_t> &ci,
-                    const std::vector<c128> &val, const std::vector<double> &coords);
-void lu_upload(const SparseLUHost &h, SparseLU &f);
-// The device solve's steps on the host, for checking the factors: x [n] in
-// the original numbering, overwritten by the solution.
-void lu_solve_host(const SparseLUHost &h, c128 *x);
+// for the dissection.  The ordering and the symbolic factorisation run on
+// the host, the numeric one on the device (stream st, synchronised before
+// returning) or, with small fronts only, on the host.  Throws SIE_EINVAL when a separator exceeds kLUMaxSupernode
+// unknowns, when the factors would exceed kLUMaxBytes of device memory or
+// kLUMaxFlops of arithmetic (estimated before any front is factored), or
+// when a pivot vanishes.
+constexpr int kLUMaxSupernode = 4096;
+constexpr double kLUMaxBytes = 8e9;
+constexpr double kLUMaxFlops = 5e12;
+// Factorisations whose fronts all have at most kLUHostFront rows run on the
+// host (launches would dominate their device time).
+constexpr int kLUHostFront = 512;
+void lu_factor(SparseLU &f, int64_t n, const std::vector<int64_t> &rp, const std::vector<int32_t> &ci,
+               const std::vector<c128> &val, const std::vector<double> &coords, hipStream_t st);
 
 // x [nrhs][n] in position order: overwritten by the solution of (LU) x = b.
 void lu_solve(const SparseLU &f, int nrhs, c128 *x, hipStream_t st);
@@ -66,6 +63,35 @@ void launch_lu_gather(int64_t n, int64_t r0, int64_t E, int nrhs, const int32_t 
 template <typename T>
 void launch_lu_scatter(int64_t n, int64_t r0, int64_t E, int nrhs, const int32_t *iperm, const c128 *xp, cx<T> *y,
                        hipStream_t st);
+
+// One front of the numeric factorisation (k_front.hip), in stream order:
+// F [m][m] (row-major, device) is cleared, receives its original entries
+// (F[arow[e]][acol[e]] = val[asrc[e]], e < nasm) and adds each child's update
+// matrix (child_upd [bc][bc], its rows and columns at child_map [bc] of F);
+// its first n positions are then eliminated without pivoting, linv and uinv
+// [n][n] receive the inverses of the unit-lower L_NN and the upper U_NN,
+// row a of L_BN goes to lval[loff[a] ..] and row k of U_NB to
+// uval[urow[k] ..], and the Schur complement on the boundary to upd
+// [nb][nb] (nb = m - n; none when nb = 0).  *bad is set non-zero on a pivot
+// that is zero or not finite.
+struct FrontStep {
+    c128 *F = nullptr;
+    int m = 0, n = 0;
+    const int32_t *arow = nullptr, *acol = nullptr, *asrc = nullptr;
+    int64_t nasm = 0;
+    const c128 *val = nullptr;
+    std::vector<const c128 *> child_upd;
+    std::vector<int> child_nb;
+    std::vector<const int32_t *> child_map;
+    c128 *linv = nullptr, *uinv = nullptr;
+    c128 *lval = nullptr;
+    const int64_t *loff = nullptr;
+    c128 *uval = nullptr;
+    const int64_t *urow = nullptr;
+    c128 *upd = nullptr;
+    int *bad = nullptr;
+};
+void launch_front_step(const FrontStep &s, hipStream_t st);
 
 // Device side (k_lu.hip): one level of the forward or backward sweep, two
 // launches (gather the solved levels' contributions into f.work, then the
