@@ -81,7 +81,9 @@ def parse():
                          "within 1e-3 of FP64), 1e-6 otherwise")
     ap.add_argument("--restart", type=int, default=None,
                     help="outer GMRES restart length; default 1000 for the bar and the cube array (their "
-                         "exterior EFIE converges in a staircase that restarts would lengthen), 200 otherwise")
+                         "exterior EFIE converges in a staircase that restarts would lengthen), 400 for the serve "
+                         "trace (its outer cap: shorter restarts stall on electrically large conductors), 200 "
+                         "otherwise")
     ap.add_argument("--inner-relax", type=float, default=0.1,
                     help="relaxed nested tolerance inside the FP32 correction solves: nested solve j runs to "
                          "this x (correction target) / (outer residual estimate); 0: fixed tolerance")
@@ -107,7 +109,7 @@ def parse():
     if a.tol is None:
         a.tol = DEFAULT_TOL.get(a.workload, 1e-6)
     if a.restart is None:
-        a.restart = {"bar": 1000, "cubes": 1000}.get(a.workload, 200)
+        a.restart = {"bar": 1000, "cubes": 1000, "serve": 400}.get(a.workload, 200)
     if a.precond is None:
         a.precond = DEFAULT_PRECOND.get(a.workload, 4)
     return a
@@ -471,7 +473,7 @@ def serve_workload(args):
             p.set_grid(-1, n=0, near_radius=3)
             p.set_skin_cutoff(args.skin_cutoff)
             p.set_augmented(bool(args.augmented))
-            tickets.append(srv.submit(p, (0.0, 0.0, -1.0), (1.0, 0.0, 0.0), prec, tol=args.tol, restart=100,
+            tickets.append(srv.submit(p, (0.0, 0.0, -1.0), (1.0, 0.0, 0.0), prec, tol=args.tol, restart=args.restart,
                                       precond=args.precond, max_iter=args.max_iter,
                                       inner_max_iter=args.inner_max_iter,
                                       inner_relax=args.inner_relax))
@@ -522,7 +524,8 @@ def serve_workload(args):
                                              f"({min(tris)}-{max(tris)} triangles, cap {args.max_tri}), "
                                              f"{args.slots} slots, Sec. IV grid rule, near radius 3, skin-depth "
                                              f"cutoff {args.skin_cutoff:g}, solve to {args.tol:g} (caps "
-                                             f"{args.max_iter} outer / {args.inner_max_iter} nested iterations)"},
+                                             f"{args.max_iter} outer / {args.inner_max_iter} nested iterations, "
+                                             f"outer restart {args.restart}, preconditioner {args.precond})"},
                       **main, "offered_rate": 50.0, "fp64_same_requests": ref}))
 
 

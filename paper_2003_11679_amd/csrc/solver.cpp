@@ -655,11 +655,12 @@ template <> const c64 *ras_m<float>(const Schwarz &w) { return w.m32.p; }
 // M_i = -j w eps_i L_i,NR over the object's RWG rows, factored in FP64
 // (nested dissection and symbolic factorisation on the host, fronts
 // eliminated on the device, no pivoting) and applied with the device's
-// level-by-level triangular solves.  A medium whose near-region matrix is
-// too dense to factor as a sparse matrix (more than kLUMeanRow nonzeros per
-// row on average when above the supernode limit in size, a separator above
-// that limit, or factors beyond the size and arithmetic limits of the
-// sparse LU) gets none.
+// level-by-level triangular solves (in FP32 with FP32 copies of the factors
+// for FP32 solves).  A medium whose near-region matrix is too dense to
+// factor as a sparse matrix (more than kLUMeanRow nonzeros per row on
+// average when above the supernode limit in size, a separator above that
+// limit, or factors beyond the size and arithmetic limits of the sparse LU)
+// gets none.
 struct NearLU {
     int medium = 0;
     int64_t r0 = 0, n = 0;
@@ -715,6 +716,7 @@ static bool near_lu_build(sie_problem *p, int medium, int64_t r0, int64_t r1, c1
         if (er.code == SIE_EINVAL) return false;   // too dense, or a vanishing pivot
         throw;
     }
+    lu_make_fp32(out.f, hipStreamPerThread);   // FP32 nested solves apply FP32 factors
     out.medium = medium;
     out.r0 = r0;
     out.n = n;
@@ -738,6 +740,7 @@ struct SolveState {
     int64_t nlu_nnz = 0;
     double nlu_factor_s = 0.0;
     DBuf<c128> nlu_work;           // [nrhs][n] right-hand sides in position order
+    DBuf<c64> nlu_work32;
     Gmres<double> go64, gi64;
     Gmres<float> go32, gi32;
     Gmres<double> goa;             // outer solve of the augmented EFIE (unknowns [u; sigma])
@@ -750,6 +753,9 @@ struct SolveState {
 
 void solver_destroy(SolveState *s) { delete s; }
 
+template <typename T> static DBuf<cx<T>> &nlu_work_of(SolveState &s);
+template <> DBuf<c128> &nlu_work_of<double>(SolveState &s) { return s.nlu_work; }
+template <> DBuf<c64> &nlu_work_of<float>(SolveState &s) { return s.nlu_work32; }
 template <typename T> static DBuf<cx<T>> *tmp_of(SolveState &s);
 template <> DBuf<c128> *tmp_of<double>(SolveState &s) { return s.t64; }
 template <> DBuf<c64> *tmp_of<float>(SolveState &s) { return s.t32; }
@@ -785,12 +791,13 @@ static void nested_apply(sie_problem *p, SolveState &s, bool ras, bool lu, int n
                             E, nrhs, st, active, (int)p->ints.size(), w.cobj.p);
     }
     if (lu) {
+        DBuf<cx<T>> &wk = nlu_work_of<T>(s);
         for (const auto &f : s.nlu) {
             const size_t need = (size_t)nrhs * f->n;
-            if (s.nlu_work.n < need) s.nlu_work.alloc(need);
-            launch_lu_gather<T>(f->n, f->r0, E, nrhs, f->f.iperm.p, x, s.nlu_work.p, st);
-            lu_solve(f->f, nrhs, s.nlu_work.p, st);
-            launch_lu_scatter<T>(f->n, f->r0, E, nrhs, f->f.iperm.p, s.nlu_work.p, y, st);
+            if (wk.n < need) wk.alloc(need);
+            launch_lu_gather<T>(f->n, f->r0, E, nrhs, f->f.iperm.p, x, wk.p, st);
+            lu_solve(f->f, nrhs, wk.p, st);
+            launch_lu_scatter<T>(f->n, f->r0, E, nrhs, f->f.iperm.p, wk.p, y, st);
         }
     }
 }

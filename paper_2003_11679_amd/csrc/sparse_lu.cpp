@@ -483,8 +483,16 @@ void lu_factor(SparseLU &f, int64_t n, const std::vector<int64_t> &rp, const std
 void lu_solve(const SparseLU &f, int nrhs, c128 *x, hipStream_t st) {
     if (f.work.n < (size_t)nrhs * f.n) f.work.alloc((size_t)nrhs * f.n);
     const int H = (int)f.lev_ptr.size() - 1;
-    for (int l = 0; l < H; ++l) launch_lu_level(f, l, true, nrhs, x, st);
-    for (int l = H - 1; l >= 0; --l) launch_lu_level(f, l, false, nrhs, x, st);
+    for (int l = 0; l < H; ++l) launch_lu_level<double>(f, l, true, nrhs, x, st);
+    for (int l = H - 1; l >= 0; --l) launch_lu_level<double>(f, l, false, nrhs, x, st);
+}
+
+void lu_solve(const SparseLU &f, int nrhs, c64 *x, hipStream_t st) {
+    SIE_CHECK(f.lval32.n == f.lval.n && f.linv32.n == f.linv.n, SIE_ESTATE, "sparse LU: no FP32 factors");
+    if (f.work32.n < (size_t)nrhs * f.n) f.work32.alloc((size_t)nrhs * f.n);
+    const int H = (int)f.lev_ptr.size() - 1;
+    for (int l = 0; l < H; ++l) launch_lu_level<float>(f, l, true, nrhs, x, st);
+    for (int l = H - 1; l >= 0; --l) launch_lu_level<float>(f, l, false, nrhs, x, st);
 }
 
 }  // namespace sie

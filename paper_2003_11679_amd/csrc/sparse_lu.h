@@ -30,6 +30,9 @@ struct SparseLU {
     std::vector<int> blk_ptr;
     DBuf<int32_t> blk_sn, blk_row0;
     mutable DBuf<c128> work;           // [nrhs][n] gathered right-hand sides of a level
+    // FP32 copies of the factors for FP32 solves (lu_make_fp32)
+    DBuf<c64> linv32, uinv32, lval32, uval32;
+    mutable DBuf<c64> work32;
 };
 // Rows of one supernode per workgroup of the device solve (one wavefront each).
 constexpr int kLURowsPerBlock = 4;
@@ -51,17 +54,22 @@ constexpr int kLUHostFront = 512;
 void lu_factor(SparseLU &f, int64_t n, const std::vector<int64_t> &rp, const std::vector<int32_t> &ci,
                const std::vector<c128> &val, const std::vector<double> &coords, hipStream_t st);
 
-// x [nrhs][n] in position order: overwritten by the solution of (LU) x = b.
-void lu_solve(const SparseLU &f, int nrhs, c128 *x, hipStream_t st);
+// Rounds the factors to FP32 copies (for lu_solve on complex64 vectors).
+void lu_make_fp32(SparseLU &f, hipStream_t st);
 
-// xp[r][iperm[j]] = x[r * E + r0 + j] (widened to FP64), j < n: rows
-// [r0, r0 + n) of nrhs vectors into position order.
+// x [nrhs][n] in position order: overwritten by the solution of (LU) x = b,
+// in FP64, or in FP32 with the FP32 copies of the factors.
+void lu_solve(const SparseLU &f, int nrhs, c128 *x, hipStream_t st);
+void lu_solve(const SparseLU &f, int nrhs, c64 *x, hipStream_t st);
+
+// xp[r][iperm[j]] = x[r * E + r0 + j], j < n: rows [r0, r0 + n) of nrhs
+// vectors into position order.
 template <typename T>
-void launch_lu_gather(int64_t n, int64_t r0, int64_t E, int nrhs, const int32_t *iperm, const cx<T> *x, c128 *xp,
+void launch_lu_gather(int64_t n, int64_t r0, int64_t E, int nrhs, const int32_t *iperm, const cx<T> *x, cx<T> *xp,
                       hipStream_t st);
-// y[r * E + r0 + j] = xp[r][iperm[j]] (rounded to T).
+// y[r * E + r0 + j] = xp[r][iperm[j]].
 template <typename T>
-void launch_lu_scatter(int64_t n, int64_t r0, int64_t E, int nrhs, const int32_t *iperm, const c128 *xp, cx<T> *y,
+void launch_lu_scatter(int64_t n, int64_t r0, int64_t E, int nrhs, const int32_t *iperm, const cx<T> *xp, cx<T> *y,
                        hipStream_t st);
 
 // One front of the numeric factorisation (k_front.hip), in stream order:
@@ -96,6 +104,8 @@ void launch_front_step(const FrontStep &s, hipStream_t st);
 // Device side (k_lu.hip): one level of the forward or backward sweep, two
 // launches (gather the solved levels' contributions into f.work, then the
 // dense inverses of the diagonal blocks), rows spread over workgroups.
-void launch_lu_level(const SparseLU &f, int level, bool forward, int nrhs, c128 *x, hipStream_t st);
+// T = float uses the FP32 copies of the factors.
+template <typename T>
+void launch_lu_level(const SparseLU &f, int level, bool forward, int nrhs, cx<T> *x, hipStream_t st);
 
 }  // namespace sie

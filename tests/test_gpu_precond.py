@@ -148,6 +148,13 @@ def test_near_lu_dense_fronts_match_dense_solve():
     print(f"  rel err {err:.2e}, factors {nnz} off-block entries, {t:.3f} s", flush=True)
     assert err < 1e-9
     assert nm == 1 and nnz > 0
+    # FP32 vectors are solved with FP32 copies of the factors
+    x32 = X[0].astype(np.complex64)
+    got32 = p.nested_precond(16, torch.from_numpy(x32).to("cuda")).cpu().numpy()
+    ref32 = np.linalg.solve(A, x32.astype(np.complex128))
+    err32 = np.linalg.norm(got32 - ref32) / np.linalg.norm(ref32)
+    print(f"  FP32 factors: rel err {err32:.2e}", flush=True)
+    assert err32 < 1e-6
     p.set_planewaves((0.0, 0.0, -1.0), (1.0, 0.0, 0.0))
     r = p.solve(0, tol=1e-8, restart=200, precond=16)
     print(f"  solve {r}", flush=True)
