@@ -37,7 +37,19 @@ __global__ void __launch_bounds__(64 * kLURowsPerBlock)
     const int64_t p = sn_p0[sn] + i;
     const cx<T> *xr = x + (int64_t)blockIdx.y * n;
     cx<T> acc;
-    for (int64_t j = row_ptr[p] + lane; j < row_ptr[p + 1]; j += 64) acc += vals[j] * xr[cols[j]];
+    // four entries per lane in flight (the same order of summation per lane)
+    int64_t j = row_ptr[p] + lane;
+    const int64_t e = row_ptr[p + 1];
+    for (; j + 192 < e; j += 256) {
+        const int32_t c0 = cols[j], c1 = cols[j + 64], c2 = cols[j + 128], c3 = cols[j + 192];
+        const cx<T> v0 = vals[j], v1 = vals[j + 64], v2 = vals[j + 128], v3 = vals[j + 192];
+        const cx<T> x0 = xr[c0], x1 = xr[c1], x2 = xr[c2], x3 = xr[c3];
+        acc += v0 * x0;
+        acc += v1 * x1;
+        acc += v2 * x2;
+        acc += v3 * x3;
+    }
+    for (; j < e; j += 64) acc += vals[j] * xr[cols[j]];
     acc = lu_wave_sum(acc);
     if (lane == 0) w[(int64_t)blockIdx.y * n + p] = xr[p] - acc;
 }
@@ -61,7 +73,16 @@ __global__ void __launch_bounds__(64 * kLURowsPerBlock)
     const cx<T> *wr = w + (int64_t)blockIdx.y * n + p0;
     const int k0 = FWD ? 0 : i, k1 = FWD ? i + 1 : nn;
     cx<T> acc;
-    for (int k = k0 + lane; k < k1; k += 64) acc += row[k] * wr[k];
+    int k = k0 + lane;
+    for (; k + 192 < k1; k += 256) {
+        const cx<T> a0 = row[k], a1 = row[k + 64], a2 = row[k + 128], a3 = row[k + 192];
+        const cx<T> b0 = wr[k], b1 = wr[k + 64], b2 = wr[k + 128], b3 = wr[k + 192];
+        acc += a0 * b0;
+        acc += a1 * b1;
+        acc += a2 * b2;
+        acc += a3 * b3;
+    }
+    for (; k < k1; k += 64) acc += row[k] * wr[k];
     acc = lu_wave_sum(acc);
     if (lane == 0) x[(int64_t)blockIdx.y * n + p0 + i] = acc;
 }
