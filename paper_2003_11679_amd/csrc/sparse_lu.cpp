@@ -43,7 +43,7 @@
 namespace sie {
 namespace {
 
-constexpr int kLeaf = 64;
+constexpr int kLeaf = 128;
 
 struct Node {
     int p0 = 0, n = 0, height = 0;
