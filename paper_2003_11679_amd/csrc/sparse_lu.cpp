@@ -135,6 +135,35 @@ void front_boundary(int id, const std::vector<Node> &nodes, std::vector<std::vec
     std::sort(B.begin(), B.end());
 }
 
+// f(i, t) for i in [0, count) on up to 16 host threads (t: the thread's
+// index); the first exception is rethrown once all have joined.
+template <typename F>
+void parallel_for(int64_t count, int nthr, F &&f) {
+    std::atomic<int64_t> next{0};
+    std::exception_ptr err;
+    std::mutex emu;
+    auto work = [&](int t) {
+        for (;;) {
+            const int64_t i = next.fetch_add(1);
+            if (i >= count) return;
+            try {
+                f(i, t);
+            } catch (...) {
+                std::lock_guard<std::mutex> lk(emu);
+                if (!err) err = std::current_exception();
+            }
+        }
+    };
+    const int nt = (int)std::max<int64_t>(1, std::min<int64_t>(nthr, count));
+    std::vector<std::thread> th;
+    for (int t = 1; t < nt; ++t) th.emplace_back(work, t);
+    work(0);
+    for (auto &t : th) t.join();
+    if (err) std::rethrow_exception(err);
+}
+
+int host_threads() { return (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency())); }
+
 // Dense elimination of the first n positions of the m x m front F on the
 // host (the small fronts): the same results as the device's, multipliers of
 // zero skipped.
@@ -230,14 +259,10 @@ void lu_factor(SparseLU &f, int64_t n, const std::vector<int64_t> &rp, const std
         const std::vector<int32_t> &B = Bs[id];
         const int nb = (int)B.size();
         for (int a = 0; a < nb; ++a) {
-            const int64_t q = lfill[B[a]];
+            loff.push_back(lfill[B[a]]);
             lfill[B[a]] += x.n;
-            loff.push_back(q);
-            for (int k = 0; k < x.n; ++k) lcol[q + k] = x.p0 + k;
         }
         loff0[id + 1] = (int64_t)loff.size();
-        for (int k = 0; k < x.n; ++k)
-            for (int b = 0; b < nb; ++b) ucol[ucnt[x.p0 + k] + b] = B[b];
         sn_p0[id] = x.p0;
         sn_n[id] = x.n;
         inv_off[id] = inv_total;
@@ -250,47 +275,78 @@ void lu_factor(SparseLU &f, int64_t n, const std::vector<int64_t> &rp, const std
         top += (int64_t)nb * nb;
         peak = std::max(peak, top);
     }
+    const int nthr = host_threads();
+    // column indices of the factors (each front fills its own ranges)
+    parallel_for(nn, nthr, [&](int64_t id, int) {
+        const Node &x = nodes[id];
+        const std::vector<int32_t> &B = Bs[id];
+        const int64_t *lo = loff.data() + loff0[id];
+        for (size_t a = 0; a < B.size(); ++a)
+            for (int k = 0; k < x.n; ++k) lcol[lo[a] + k] = x.p0 + k;
+        for (int k = 0; k < x.n; ++k) std::copy(B.begin(), B.end(), ucol.begin() + ucnt[x.p0 + k]);
+    });
     // assembly lists: original entries (front-local row, column, value
     // index; every entry lands in exactly one front position) and the
-    // positions of each child's boundary in its parent's front
+    // positions of each child's boundary in its parent's front; counted
+    // first, then filled per front
     std::vector<int64_t> asm0(nn + 1, 0), map0(nn + 1, 0);
-    std::vector<int32_t> arow, acol, asrc, cmap;
-    arow.reserve(ci.size());
-    acol.reserve(ci.size());
-    asrc.reserve(ci.size());
+    parallel_for(nn, nthr, [&](int64_t id, int) {
+        const Node &x = nodes[id];
+        const int p0 = x.p0, p1 = p0 + x.n;
+        int64_t cnt = 0;
+        for (int i = p0; i < p1; ++i) {
+            const int32_t u = nd.order[i];
+            for (int64_t k = rp[u]; k < rp[u + 1]; ++k) {
+                const int32_t pj = iperm[ci[k]];
+                if (pj >= p0) cnt += pj >= p1 ? 2 : 1;
+            }
+        }
+        asm0[id + 1] = cnt;
+        int64_t mc = 0;
+        for (int c : x.children) mc += (int64_t)Bs[c].size();
+        map0[id + 1] = mc;
+    });
     for (int id = 0; id < nn; ++id) {
+        asm0[id + 1] += asm0[id];
+        map0[id + 1] += map0[id];
+    }
+    std::vector<int32_t> arow(asm0[nn]), acol(asm0[nn]), asrc(asm0[nn]), cmap(map0[nn]);
+    std::vector<std::vector<int32_t>> lmap(nthr);   // per thread: front-local index of a boundary position
+    parallel_for(nn, nthr, [&](int64_t id, int t) {
         const Node &x = nodes[id];
         const std::vector<int32_t> &B = Bs[id];
         const int p0 = x.p0, p1 = p0 + x.n;
-        for (int a = 0; a < (int)B.size(); ++a) mark[B[a]] = x.n + a;   // front-local index of a boundary position
-        auto loc = [&](int32_t pos) -> int32_t { return pos < p1 ? pos - p0 : mark[pos]; };
+        std::vector<int32_t> &mk = lmap[t];
+        if (mk.size() != (size_t)n) mk.assign(n, -1);
+        for (int a = 0; a < (int)B.size(); ++a) mk[B[a]] = x.n + a;
+        auto loc = [&](int32_t pos) -> int32_t { return pos < p1 ? pos - p0 : mk[pos]; };
+        int64_t e = asm0[id];
         for (int i = p0; i < p1; ++i) {
             const int32_t u = nd.order[i];
             for (int64_t k = rp[u]; k < rp[u + 1]; ++k) {
                 const int32_t pj = iperm[ci[k]];
                 if (pj < p0) continue;
-                arow.push_back(loc(i));
-                acol.push_back(loc(pj));
-                asrc.push_back((int32_t)k);
+                arow[e] = loc(i);
+                acol[e] = loc(pj);
+                asrc[e++] = (int32_t)k;
                 if (pj >= p1) {   // the transposed entry (row in B, column in N)
                     const int32_t w = ci[k];
                     const int32_t *b0 = ci.data() + rp[w], *b1 = ci.data() + rp[w + 1];
                     const int32_t *q = std::lower_bound(b0, b1, u);
                     SIE_CHECK(q != b1 && *q == u, SIE_EINVAL, "sparse LU: pattern not structurally symmetric");
-                    arow.push_back(loc(pj));
-                    acol.push_back(loc(i));
-                    asrc.push_back((int32_t)(q - ci.data()));
+                    arow[e] = loc(pj);
+                    acol[e] = loc(i);
+                    asrc[e++] = (int32_t)(q - ci.data());
                 }
             }
         }
-        asm0[id + 1] = (int64_t)arow.size();
+        int64_t mo = map0[id];
         for (int c : x.children)
             for (int32_t b : Bs[c]) {   // a child couples only to its ancestors' positions
                 SIE_CHECK(b >= p0, SIE_EINVAL, "sparse LU: child boundary outside its parent's front");
-                cmap.push_back(loc(b));
+                cmap[mo++] = loc(b);
             }
-        map0[id + 1] = (int64_t)cmap.size();
-    }
+    });
 
     const auto t1 = std::chrono::steady_clock::now();
     // device layout of the factors (what the level-by-level solve reads)
@@ -376,30 +432,9 @@ void lu_factor(SparseLU &f, int64_t n, const std::vector<int64_t> &rp, const std
             for (int a = 0; a < nb; ++a)
                 for (int b = 0; b < nb; ++b) upd[id][(size_t)a * nb + b] = F[(size_t)(fn + a) * m + fn + b];
         };
-        const int nthr = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
         for (int l = 0; l < H; ++l) {
             const std::vector<int> &lv = by_level[l];
-            std::atomic<size_t> next{0};
-            std::exception_ptr err;
-            std::mutex emu;
-            auto work = [&]() {
-                for (;;) {
-                    const size_t i = next.fetch_add(1);
-                    if (i >= lv.size()) return;
-                    try {
-                        front(lv[i]);
-                    } catch (...) {
-                        std::lock_guard<std::mutex> lk(emu);
-                        if (!err) err = std::current_exception();
-                    }
-                }
-            };
-            const int nt = (int)std::min<size_t>(nthr, lv.size());
-            std::vector<std::thread> th;
-            for (int t = 1; t < nt; ++t) th.emplace_back(work);
-            work();
-            for (auto &t : th) t.join();
-            if (err) std::rethrow_exception(err);
+            parallel_for((int64_t)lv.size(), nthr, [&](int64_t i, int) { front(lv[i]); });
         }
         f.lval.upload(lval);
         f.uval.upload(uval);
