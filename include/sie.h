@@ -393,9 +393,11 @@ sie_status sie_interpolate(sie_problem *p, int32_t medium, sie_precision prec,
  * caller's stream: precond = 1 block-Jacobi, 4 or 12 restricted additive
  * Schwarz over grid-cell clusters, 16 the exact sparse LU of M_i, 20 or 28
  * the LU where it applies and clusters elsewhere (see
- * sie_solver_opts.precond; rows of media with neither are copied).  Built on first use (host-synchronous); the
- * same structure serves later solves.  x and y must not alias; complex64 for
- * SIE_FP32, complex128 for SIE_FP64.  SIE_ESTATE before setup. */
+ * sie_solver_opts.precond; rows of media with neither are copied).  Built
+ * on first use (host-synchronous); the same structure serves later solves.
+ * x and y must not alias; complex64 for SIE_FP32 (Schwarz inverses and LU
+ * factors in FP32 copies), complex128 for SIE_FP64.  SIE_ESTATE before
+ * setup. */
 sie_status sie_nested_precond(sie_problem *p, int32_t precond, sie_precision prec, int32_t nrhs,
                               const void *x_dev, void *y_dev, void *stream);
 /* Clusters of the built Schwarz preconditioner (-1 if not built); *owned
@@ -403,8 +405,9 @@ sie_status sie_nested_precond(sie_problem *p, int32_t precond, sie_precision pre
 int32_t sie_nested_precond_clusters(const sie_problem *p, int64_t *owned);
 /* Interior media with an exact near-region factorisation (precond bit 16;
  * -1 if not built); *factor_nnz (nullable) receives the stored off-block
- * entries of their L and U factors, *t_factor_s (nullable) the host time of
- * the factorisations. */
+ * entries of their L and U factors, *t_factor_s (nullable) the wall time of
+ * the factorisations (ordering and symbolic part on the host, fronts on the
+ * device or the host). */
 int32_t sie_nested_precond_factored(const sie_problem *p, int64_t *factor_nnz, double *t_factor_s);
 
 /* Constraint preconditioner of the augmented EFIE (Sec. III-E), y = P^-1 x
