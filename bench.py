@@ -288,9 +288,11 @@ def fft_bytes(nl, m, s, nf):
     return nf * per + octant
 
 
-def fft_micro(args):
+def fft_measure(steps, warmup, precision):
     """4 fields of a full-occupancy 256^3 live box (complex64), FFT 512^3,
-    times the Green's spectrum of k0 at 1 GHz with h = 3 lambda0 / 253."""
+    times the Green's spectrum of k0 at 1 GHz with h = 3 lambda0 / 253:
+    milliseconds per convolution with the built-in and the tuned tile
+    shapes, and the achieved fraction of the HBM peak."""
     import torch
     from workloads import geodesic_sphere, C0_NOMINAL
     from paper_2003_11679_amd import Problem
@@ -304,7 +306,7 @@ def fft_micro(args):
     g = p.grid(-1)
     nl = [int(v) for v in g["nl"]]
     m = [int(v) for v in g["m"]]
-    dt = torch.complex64 if args.precision == "fp32" else torch.complex128
+    dt = torch.complex64 if precision == "fp32" else torch.complex128
     s = 8 if dt == torch.complex64 else 16
     gen = torch.Generator(device="cuda").manual_seed(11685)
     src = torch.randn((4, nl[2], nl[1], nl[0]), dtype=dt, device="cuda", generator=gen)
@@ -315,16 +317,16 @@ def fft_micro(args):
     def timed(builtin):
         for f in fams:
             P.tuning_force(f, 0 if builtin else -1)
-        for _ in range(args.warmup + 1):   # the first convolution tunes the tile shapes
+        for _ in range(warmup + 1):   # the first convolution tunes the tile shapes
             p.convolve(-1, src, out)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        for _ in range(args.steps):
+        for _ in range(steps):
             p.convolve(-1, src, out)
         e1.record()
         torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / args.steps
+        return e0.elapsed_time(e1) / steps
 
     ms_builtin = timed(True)
     ms = timed(False)
@@ -334,13 +336,20 @@ def fft_micro(args):
              if r["stage"] in fams]
     nb = fft_bytes(nl, m, s, 4)
     ach = nb / (ms * 1e-3) / 1e9
-    print(json.dumps({"metric": "4-field zero-padded FFT convolution time", "value": ms, "unit": "ms",
+    del p, src, out
+    return {"ms": ms, "ms_builtin_shapes": ms_builtin, "tuning": tuned, "dtype": "c64" if s == 8 else "c128",
+            "workload": f"4 fields, live box {nl}, FFT {m}, G spectrum of k0 at 1 GHz",
+            "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": nb}}
+
+
+def fft_micro(args):
+    r = fft_measure(args.steps, args.warmup, args.precision)
+    print(json.dumps({"metric": "4-field zero-padded FFT convolution time", "value": r["ms"], "unit": "ms",
                       "higher_is_better": False, "steps": args.steps, "warmup": args.warmup,
-                      "dtype": "c64" if s == 8 else "c128", "data": "synthetic",
-                      "config": {"workload": f"4 fields, live box {nl}, FFT {m}, G spectrum of k0 at 1 GHz"},
-                      "ms_builtin_shapes": ms_builtin, "tuning": tuned,
-                      "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                   "frac": ach / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": nb}}))
+                      "dtype": r["dtype"], "data": "synthetic", "config": {"workload": r["workload"]},
+                      "ms_builtin_shapes": r["ms_builtin_shapes"], "tuning": r["tuning"],
+                      "roofline": r["roofline"]}))
 
 
 def batch_workload(args):
@@ -837,6 +846,8 @@ def request_workload(args):
         if args.workload == "cubes":
             out["other_nested_mode"] = nested_mode_comparison(args, cfg, prec, 3)
             out["copper_bar"] = secondary_request(args, "bar", 5)
+            print("[bench] FFT convolution (4 fields, 512^3)", file=sys.stderr, flush=True)
+            out["fft_convolution"] = fft_measure(10, 2, "fp32")
         elif args.workload == "bar":
             out["cube_array"] = secondary_request(args, "cubes", 1)
     if not args.no_cpu_baseline:
